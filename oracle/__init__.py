@@ -1,0 +1,105 @@
+"""FP64 CPU oracle for sum-product LDPC decoding -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may call
+this package.  It shares no code with the GPU library: the C source here builds
+its own adjacency lists from the COO input and decodes each frame with the
+flooding schedule of the paper's Algorithms 1-4 and 7, in double precision
+(see ldpc_oracle.c for the passage each step follows).
+
+Parity status: every function here is pinned by the CPU tests
+(tests/test_oracle_pins.py): brute-force bitwise MAP on cycle-free graphs,
+the probability-domain form of Algorithm 1, closed forms on single-parity-check
+and path codes, noiseless and all-zero inputs, the degree-1 clamp, sign
+symmetry, and the paper's Tables I and II for the adjacency lists.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ldpc_oracle.c")
+_SO = os.path.join(_HERE, "liboracle.so")
+LMAX = 64.0
+_lib = None
+
+
+def build() -> str:
+    """Compile the oracle with gcc (OpenMP over frames, strict IEEE arithmetic)."""
+    tmp = _SO + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                           "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        lib = ctypes.CDLL(_SO)
+        P = ctypes.c_void_p
+        lib.ldpc_oracle_decode.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long, P, P, P,
+                                           ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                           P, P, P, P, P, ctypes.c_int]
+        lib.ldpc_oracle_decode.restype = ctypes.c_int
+        lib.ldpc_oracle_adjacency.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long, P, P, P, P, P, P]
+        lib.ldpc_oracle_adjacency.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def decode(code, llr, max_iter: int, early_stop: bool = True, lmax: float = LMAX,
+           threads: int = 0, want_lpost: bool = True) -> dict:
+    """Decode every row of `llr` ([F][n] float32) on the CPU in FP64.
+
+    Returns a dict with bits [F][n] u8, ok [F] u8, iters [F] i32,
+    min_abs [F] f64 (smallest |Lpost| over all iterations run) and, if asked,
+    lpost [F][n] f64.
+    """
+    lib = _load()
+    rows = np.ascontiguousarray(code.rows, dtype=np.int32)
+    cols = np.ascontiguousarray(code.cols, dtype=np.int32)
+    llr = np.ascontiguousarray(np.atleast_2d(llr), dtype=np.float32)
+    F, n = llr.shape
+    if n != code.n:
+        raise ValueError("llr width does not match the code length")
+    bits = np.zeros((F, n), np.uint8)
+    ok = np.zeros(F, np.uint8)
+    iters = np.zeros(F, np.int32)
+    min_abs = np.zeros(F, np.float64)
+    lpost = np.zeros((F, n), np.float64) if want_lpost else None
+    st = lib.ldpc_oracle_decode(code.m, code.n, rows.size, _ptr(rows), _ptr(cols), _ptr(llr), F,
+                                int(max_iter), int(bool(early_stop)), float(lmax),
+                                _ptr(lpost) if want_lpost else None, _ptr(bits), _ptr(ok), _ptr(iters),
+                                _ptr(min_abs), int(threads))
+    if st != 0:
+        raise ValueError(f"oracle rejected the input (status {st})")
+    out = dict(bits=bits, ok=ok, iters=iters, min_abs=min_abs)
+    if want_lpost:
+        out["lpost"] = lpost
+    return out
+
+
+def adjacency(code):
+    """The oracle's own N_i / M_j lists: (bit_start, bit_edge, chk_start, chk_edge)."""
+    lib = _load()
+    rows = np.ascontiguousarray(code.rows, dtype=np.int32)
+    cols = np.ascontiguousarray(code.cols, dtype=np.int32)
+    bs = np.zeros(code.n + 1, np.int32)
+    be = np.zeros(rows.size, np.int32)
+    cs = np.zeros(code.m + 1, np.int32)
+    ce = np.zeros(rows.size, np.int32)
+    st = lib.ldpc_oracle_adjacency(code.m, code.n, rows.size, _ptr(rows), _ptr(cols),
+                                   _ptr(bs), _ptr(be), _ptr(cs), _ptr(ce))
+    if st != 0:
+        raise ValueError(f"oracle rejected the graph (status {st})")
+    return bs, be, cs, ce

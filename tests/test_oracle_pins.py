@@ -1,0 +1,305 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+Each test below fixes part of what the oracle computes from something the paper
+or the mathematics fixes independently:
+
+* the paper's Tables I/II (the (14,7) address arrays) pin the adjacency lists;
+* brute-force enumeration pins the (14,7) code itself (128 codewords, d_min 3);
+* bitwise-MAP marginals by enumeration pin whole decodes on cycle-free graphs
+  (sum-product is exact on trees), which fails on a dropped or extra term,
+  a wrong sign, or a non-extrinsic message anywhere in the bit or check rule;
+* the paper's own probability-domain Algorithm 1 (q0/q1, r0/r1 products),
+  written out independently, pins the LLR-domain form on a loopy graph;
+* closed forms: single parity check (tanh rule), path/repetition code (sum);
+* special cases: noiseless input stops after 1 iteration, all-zero LLRs give
+  the tie decision 0, a degree-1 check adds +LMAX, sign symmetry is exact.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import ldpc_inputs as li
+import oracle
+
+
+def _all_words(n):
+    return np.array(list(itertools.product([0, 1], repeat=n)), dtype=np.uint8)
+
+
+def _codewords(code):
+    words = _all_words(code.n)
+    return words[code.syndrome(words).sum(axis=1) == 0]
+
+
+def _map_llr(code, llr):
+    """Bitwise MAP LLRs by enumerating all codewords (log-sum-exp in FP64)."""
+    cw = _codewords(code).astype(np.float64)
+    metric = ((1.0 - 2.0 * cw) * llr.astype(np.float64)[None, :] / 2.0).sum(axis=1)
+    out = np.empty(code.n)
+    for j in range(code.n):
+        a, b = metric[cw[:, j] == 0], metric[cw[:, j] == 1]
+        out[j] = np.logaddexp.reduce(a) - np.logaddexp.reduce(b)
+    return out
+
+
+# ---------------------------------------------------------------- adjacency
+
+def test_adjacency_matches_paper_tables(tables):
+    code = li.code_14_7()
+    bs, be, cs, ce = oracle.adjacency(code)
+    E = code.nnz
+    # Table I: edges sorted by bit, in the table's own edge order.
+    assert be.tolist() == tables["e"]
+    assert [int(code.cols[e]) for e in be] == tables["v"]
+    assert [int(code.rows[e]) for e in be] == tables["c"]
+    v = code.cols[be]
+    assert [int(bs[x + 1] - bs[x]) for x in v] == tables["t"]
+    assert [int(bs[x]) for x in v] == tables["s"]
+    assert [k - int(bs[v[k]]) for k in range(E)] == tables["u"]
+    # Table II: edges sorted by check; ebar is the Table I id at each position.
+    assert ce.tolist() == tables["ebar"]
+    c = code.rows[ce]
+    assert [int(code.cols[e]) for e in ce] == tables["vbar"]
+    assert c.tolist() == tables["cbar"]
+    assert [int(cs[x + 1] - cs[x]) for x in c] == tables["tbar"]
+    assert [int(cs[x]) for x in c] == tables["sbar"]
+    assert [k - int(cs[c[k]]) for k in range(E)] == tables["ubar"]
+
+
+def test_worked_example_neighbourhoods():
+    """Sec. II-B: v0 joins c0, c2, c3, c5 and c3 joins v0, v4, v11, v12."""
+    code = li.code_14_7()
+    H = code.dense()
+    assert np.flatnonzero(H[:, 0]).tolist() == [0, 2, 3, 5]
+    assert np.flatnonzero(H[3]).tolist() == [0, 4, 11, 12]
+
+
+def test_code_14_7_codewords():
+    code = li.code_14_7()
+    cw = _codewords(code)
+    assert len(cw) == 128                       # rank 7 over GF(2), k = 7
+    assert sorted(set(cw.sum(axis=1).tolist()))[:3] == [0, 3, 4]
+
+
+def test_oracle_rejects_bad_input():
+    code = li.code_14_7()
+    bad = li.Code(m=7, n=14, rows=code.rows.copy(), cols=code.cols.copy())
+    bad.rows[3] = 7
+    with pytest.raises(ValueError):
+        oracle.decode(bad, np.zeros((1, 14), np.float32), 5)
+    with pytest.raises(ValueError):
+        oracle.decode(code, np.zeros((1, 14), np.float32), 0)
+
+
+# ---------------------------------------------------------- trees vs MAP
+
+@pytest.mark.parametrize("seed", range(12))
+def test_tree_decode_equals_bitwise_map(seed):
+    rng = np.random.default_rng(100 + seed)
+    code = li.tree_code(int(rng.integers(2, 6)), seed=seed, max_check_deg=4)
+    if code.n > 16:
+        pytest.skip("tree too large for enumeration")
+    llr = rng.uniform(-2.0, 2.0, size=(1, code.n)).astype(np.float32)
+    want = _map_llr(code, llr[0])
+    got = oracle.decode(code, llr, max_iter=code.m + 1, early_stop=False)
+    np.testing.assert_allclose(got["lpost"][0], want, rtol=1e-9, atol=1e-9)
+
+
+def test_tree_map_many_frames():
+    code = li.tree_code(5, seed=77, max_check_deg=4)
+    assert code.n <= 16
+    rng = np.random.default_rng(5)
+    llr = rng.normal(1.0, 1.5, size=(16, code.n)).astype(np.float32)
+    got = oracle.decode(code, llr, max_iter=code.m + 1, early_stop=False)
+    for f in range(llr.shape[0]):
+        np.testing.assert_allclose(got["lpost"][f], _map_llr(code, llr[f]), rtol=1e-9, atol=1e-9)
+
+
+# ---------------------------------------- probability-domain Algorithm 1
+
+def _probability_domain(code, llr, T):
+    """Algorithms 1-4 on probability pairs, as printed (with q normalised).
+
+    p_j = P(c_j = 0) = 1/(1 + exp(-L_j)) (Algorithm 3).  Iteration 1 uses
+    q = p; later ones use q0 = p0 prod r0, q1 = p1 prod r1 over the other checks.
+    r0 = 1/2 + 1/2 prod(1 - 2 q1) over the other bits; r1 = 1 - r0.
+    The estimate is Q0 = p0 prod r0, Q1 = p1 prod r1 over all checks.
+    """
+    E = code.nnz
+    rows, cols = code.rows, code.cols
+    p0 = 1.0 / (1.0 + np.exp(-llr.astype(np.float64)))
+    p1 = 1.0 - p0
+    r0 = np.full(E, 0.5)
+    r1 = np.full(E, 0.5)
+    for t in range(1, T + 1):
+        q1 = np.empty(E)
+        for e in range(E):
+            j, i = cols[e], rows[e]
+            a0, a1 = p0[j], p1[j]
+            if t > 1:
+                for e2 in range(E):
+                    if cols[e2] == j and rows[e2] != i:
+                        a0 *= r0[e2]
+                        a1 *= r1[e2]
+            q1[e] = a1 / (a0 + a1)
+        for e in range(E):
+            j, i = cols[e], rows[e]
+            prod = 1.0
+            for e2 in range(E):
+                if rows[e2] == i and cols[e2] != j:
+                    prod *= 1.0 - 2.0 * q1[e2]
+            r0[e] = 0.5 + 0.5 * prod
+            r1[e] = 1.0 - r0[e]
+    Q0, Q1 = p0.copy(), p1.copy()
+    for e in range(E):
+        Q0[cols[e]] *= r0[e]
+        Q1[cols[e]] *= r1[e]
+    return np.log(Q0) - np.log(Q1)
+
+
+@pytest.mark.parametrize("T", [1, 2, 3, 4])
+def test_llr_form_equals_probability_form_14_7(T):
+    code = li.code_14_7()
+    rng = np.random.default_rng(10 + T)
+    llr = rng.uniform(-2.5, 2.5, size=(3, code.n)).astype(np.float32)
+    got = oracle.decode(code, llr, max_iter=T, early_stop=False)
+    assert np.abs(got["lpost"]).max() < 40
+    for f in range(3):
+        want = _probability_domain(code, llr[f], T)
+        np.testing.assert_allclose(got["lpost"][f], want, rtol=1e-8, atol=1e-9)
+
+
+def test_llr_form_equals_probability_form_random_irregular():
+    code = li.socket_code([2, 2, 3, 2, 4, 2, 3, 2, 2, 3, 2, 2, 3, 2, 2, 2],
+                          li.even_check_degrees(38, 8), seed=9)
+    rng = np.random.default_rng(3)
+    llr = rng.uniform(-2.0, 2.0, size=(2, code.n)).astype(np.float32)
+    got = oracle.decode(code, llr, max_iter=3, early_stop=False)
+    for f in range(2):
+        np.testing.assert_allclose(got["lpost"][f], _probability_domain(code, llr[f], 3), rtol=1e-8, atol=1e-9)
+
+
+# --------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("d", [2, 3, 5, 9, 16])
+def test_single_parity_check_tanh_rule(d):
+    code = li.spc_code(d)
+    rng = np.random.default_rng(d)
+    llr = rng.uniform(-4, 4, size=(1, d)).astype(np.float32)
+    got = oracle.decode(code, llr, max_iter=1, early_stop=False)["lpost"][0]
+    L = llr[0].astype(np.longdouble)
+    th = np.tanh(L / 2)
+    for j in range(d):
+        ext = 2 * np.arctanh(np.prod(np.delete(th, j)))
+        assert abs(got[j] - float(L[j] + ext)) < 1e-9 * (1 + abs(got[j]))
+
+
+def test_degree_two_check_passes_message_through():
+    """A degree-2 check forwards the other bit's message unchanged."""
+    code = li.spc_code(2)
+    llr = np.array([[1.25, -0.75]], np.float32)
+    got = oracle.decode(code, llr, max_iter=1, early_stop=False)["lpost"][0]
+    np.testing.assert_allclose(got, [1.25 - 0.75, -0.75 + 1.25], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("n", [2, 3, 6, 11])
+def test_path_code_posterior_is_total_sum(n):
+    code = li.path_code(n)
+    rng = np.random.default_rng(n)
+    llr = rng.uniform(-3, 3, size=(2, n)).astype(np.float32)
+    got = oracle.decode(code, llr, max_iter=n - 1, early_stop=False)["lpost"]
+    want = llr.astype(np.float64).sum(axis=1, keepdims=True) * np.ones((1, n))
+    np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-12)
+
+
+# ------------------------------------------------------- special cases
+
+def test_noiseless_codewords_decode_in_one_iteration():
+    code = li.code_14_7()
+    cw = _codewords(code)
+    llr = (2.0 * (1.0 - 2.0 * cw) / 0.5).astype(np.float32)
+    got = oracle.decode(code, llr, max_iter=50)
+    assert (got["iters"] == 1).all()
+    assert (got["ok"] == 1).all()
+    assert (got["bits"] == cw).all()
+
+
+def test_noiseless_all_zero_large_code_one_iteration():
+    code = li.tiny_code()
+    llr = np.full((2, code.n), 2.0 / 0.631, np.float32)
+    got = oracle.decode(code, llr, max_iter=50)
+    assert got["iters"].tolist() == [1, 1] and got["ok"].tolist() == [1, 1]
+    assert got["bits"].sum() == 0
+
+
+def test_all_zero_llr_tie_decides_zero():
+    code = li.code_14_7()
+    got = oracle.decode(code, np.zeros((1, 14), np.float32), max_iter=10)
+    assert (got["lpost"] == 0).all()
+    assert got["bits"].sum() == 0
+    assert got["ok"][0] == 1 and got["iters"][0] == 1
+
+
+def test_degree_one_check_adds_lmax():
+    # check 0 = {bit 0}; check 1 = {bit 0, bit 1}
+    code = li.Code(m=2, n=2, rows=np.array([0, 1, 1], np.int32), cols=np.array([0, 0, 1], np.int32))
+    llr = np.array([[-1.5, 0.5]], np.float32)
+    got = oracle.decode(code, llr, max_iter=1, early_stop=False)["lpost"][0]
+    # bit 0: channel + LMAX from the degree-1 check + bit 1's value through the degree-2 check
+    assert got[0] == pytest.approx(-1.5 + 64.0 + 0.5, abs=1e-12)
+    assert got[1] == pytest.approx(0.5 + -1.5, abs=1e-12)
+    single = li.Code(m=1, n=1, rows=np.array([0], np.int32), cols=np.array([0], np.int32))
+    got = oracle.decode(single, np.array([[-3.0]], np.float32), max_iter=1)
+    assert got["lpost"][0, 0] == pytest.approx(61.0, abs=1e-12)
+    assert got["bits"][0, 0] == 0
+
+
+def test_clamp_saturated_inputs():
+    """Huge channel LLRs are clamped to LMAX on the way into the check rule.
+
+    Every check has degree 6, so each R combines five messages at LMAX:
+    R = phi(5 phi(64)) = 64 - ln 5 to within 1e-25, and Lpost = L + 3 R.
+    """
+    code = li.random_small_code(40, 20, 3, seed=4)
+    assert set(code.check_degrees().tolist()) == {6}
+    llr = np.full((1, 40), 500.0, np.float32)
+    got = oracle.decode(code, llr, max_iter=3, early_stop=False)["lpost"][0]
+    np.testing.assert_allclose(got, 500.0 + 3 * (64.0 - np.log(5.0)), rtol=1e-14)
+
+
+def test_sign_symmetry_is_exact():
+    code = li.code_14_7()
+    cw = _codewords(code)
+    rng = np.random.default_rng(1)
+    base = rng.normal(2.0, 2.0, size=(1, 14)).astype(np.float32)
+    ref = oracle.decode(code, base, max_iter=20)
+    flip = (1 - 2 * cw.astype(np.int32)).astype(np.float32)
+    got = oracle.decode(code, base * flip, max_iter=20)
+    assert (got["iters"] == ref["iters"][0]).all()
+    assert (got["ok"] == ref["ok"][0]).all()
+    assert (got["lpost"] == ref["lpost"][0] * flip).all()
+    assert (got["bits"] == (ref["bits"][0] ^ cw)).all()
+
+
+def test_early_stop_equals_truncated_run():
+    code = li.tiny_code()
+    llr = li.awgn_llr(code.n, 8, li.ebn0_to_sigma2(2.0, 0.5), seed=2001)
+    es = oracle.decode(code, llr, max_iter=50)
+    for f in range(8):
+        t = int(es["iters"][f])
+        fixed = oracle.decode(code, llr[f:f + 1], max_iter=t, early_stop=False)
+        assert fixed["ok"][0] == es["ok"][f]
+        assert (fixed["lpost"][0] == es["lpost"][f]).all()
+        if es["ok"][f] and t > 1:
+            before = oracle.decode(code, llr[f:f + 1], max_iter=t - 1, early_stop=False)
+            assert before["ok"][0] == 0
+
+
+def test_threads_do_not_change_results():
+    code = li.tiny_code()
+    llr = li.awgn_llr(code.n, 6, li.ebn0_to_sigma2(1.5, 0.5), seed=7)
+    a = oracle.decode(code, llr, max_iter=30, threads=1)
+    b = oracle.decode(code, llr, max_iter=30, threads=4)
+    for k in a:
+        assert (a[k] == b[k]).all()

@@ -1,0 +1,192 @@
+/*
+ * ldpc.h -- C ABI of the MI355X (gfx950) sum-product decoder for arbitrary
+ * irregular LDPC codes.
+ *
+ * Method: J. Broulim, A. Ayriyan, V. Georgiev, H. Grigorian, "OpenCL/CUDA
+ * algorithms for parallel decoding of any irregular LDPC code using GPU".
+ * The decoder runs the paper's soft-decision sum-product algorithm
+ * (Algorithm 2, with the message rules of Algorithm 1, the estimate of
+ * Algorithms 4/6 and the syndrome of Algorithm 7) on the Tanner graph of a
+ * binary parity-check matrix H (Sec. II-A, Eqs. (1)-(2)), with no bound on
+ * node degree.
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns an ldpc_status; on failure ldpc_last_error()
+ *    gives a human-readable detail for the calling thread.
+ *  - No C++ exception crosses this interface.
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are HIP device
+ *    memory on the device that was current when the graph was created.
+ *  - LLRs are L = ln(P(c=0)/P(c=1)); BPSK maps bit 0 to +1, so for an AWGN
+ *    channel L = 2y/sigma^2 (the log-ratio of Algorithm 3's probabilities).
+ */
+#ifndef LDPC_H
+#define LDPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define LDPC_API __attribute__((visibility("default")))
+#else
+#define LDPC_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Opaque graph handle.  Immutable after creation; may be used by several
+ * streams at once as long as each call has its own workspace. */
+typedef struct ldpc_graph ldpc_graph;
+
+typedef enum {
+    LDPC_OK = 0,
+    LDPC_E_INVAL = 1,        /* bad argument (sizes, null pointer, flags, workspace too small) */
+    LDPC_E_RANGE = 2,        /* an H index is outside [0,m) x [0,n) */
+    LDPC_E_DUP_EDGE = 3,     /* H lists the same (row, col) twice; H is binary (Sec. II-A) */
+    LDPC_E_NOMEM = 4,        /* host or device allocation failed */
+    LDPC_E_DEVICE = 5,       /* a HIP call or kernel launch failed */
+    LDPC_E_UNSUPPORTED = 6   /* the request is valid but not supported by this build */
+} ldpc_status;
+
+/* Decode flags. */
+enum {
+    LDPC_NO_EARLY_STOP = 1u << 0, /* run exactly max_iter iterations (no syndrome stop) */
+    LDPC_MSG_FP16 = 1u << 1,      /* store check->bit messages as IEEE fp16 (math stays fp32) */
+    LDPC_MSG_BF16 = 1u << 2       /* store check->bit messages as bfloat16 (math stays fp32) */
+};
+
+/* Graph flags. */
+enum {
+    LDPC_GRAPH_HOST_ONLY = 1u << 0 /* build the host tables only (no device copy; cannot decode) */
+};
+
+/*
+ * Build the Tanner graph of H (Sec. II-A, Eqs. (1)-(2)) and copy its index
+ * tables to the current HIP device.
+ *
+ *  m, n        rows (checks) and columns (bits) of H; both >= 1.
+ *  nnz         number of ones in H (edges), 0 <= nnz < 2^31.
+ *  rows, cols  host int32 arrays [nnz]: edge k joins check rows[k] and bit
+ *              cols[k].  Any order; the order is kept (stable sorts) within
+ *              each node's edge list, exactly as the paper's address arrays
+ *              (Tables I and II) keep it.  Read only during the call.
+ *  flags       0 or LDPC_GRAPH_HOST_ONLY.
+ *  out         receives the new handle (owned by the caller; free with
+ *              ldpc_graph_destroy).  Untouched on failure.
+ *
+ * Errors: INVAL (m or n < 1, nnz out of range, null pointer), RANGE (index
+ * out of range), DUP_EDGE (repeated pair), NOMEM, DEVICE.
+ * Rows or columns without edges are allowed (an empty check is always
+ * satisfied; an empty column keeps its channel LLR).
+ */
+LDPC_API ldpc_status ldpc_graph_create(int32_t m, int32_t n, int64_t nnz,
+                              const int32_t *rows, const int32_t *cols,
+                              uint32_t flags, ldpc_graph **out);
+
+/* Release the graph and its device tables.  NULL is accepted (no-op). */
+LDPC_API ldpc_status ldpc_graph_destroy(ldpc_graph *g);
+
+/* Sizes of the graph.  Any output pointer may be NULL.  device_bytes is the
+ * device memory held by the graph's index tables. */
+LDPC_API ldpc_status ldpc_graph_info(const ldpc_graph *g, int64_t *m, int64_t *n, int64_t *nnz,
+                            int32_t *max_check_deg, int32_t *max_bit_deg,
+                            int64_t *device_bytes);
+
+/*
+ * Copy the graph's address arrays to host memory (any pointer may be NULL).
+ * These are the paper's Table II / Table I arrays in compressed form:
+ *
+ *  row_ptr    [m+1]  edges sorted by check (stable): check i owns positions
+ *                    row_ptr[i] .. row_ptr[i+1]-1 (Table II's sbar and tbar)
+ *  col_idx    [nnz]  bit of each check-sorted position (Table II's vbar)
+ *  col_ptr    [n+1]  edges sorted by bit (stable): bit j owns positions
+ *                    col_ptr[j] .. col_ptr[j+1]-1 (Table I's s and t)
+ *  row_idx    [nnz]  check of each bit-sorted position (Table I's c)
+ *  csr_to_csc [nnz]  bit-sorted position of each check-sorted position
+ *                    (Table II's ebar)
+ */
+LDPC_API ldpc_status ldpc_graph_arrays(const ldpc_graph *g, int32_t *row_ptr, int32_t *col_idx,
+                              int32_t *col_ptr, int32_t *row_idx, int32_t *csr_to_csc);
+
+/*
+ * Device workspace that ldpc_decode needs for `frames` frames with `flags`.
+ * The workspace holds the per-frame message state (channel and posterior
+ * LLRs per bit, one message per edge, per-frame counters) and is owned by the
+ * caller.  Errors: INVAL (null g/bytes, frames < 0, conflicting flags).
+ */
+LDPC_API ldpc_status ldpc_decode_workspace_size(const ldpc_graph *g, int32_t frames, uint32_t flags,
+                                       size_t *bytes);
+
+/*
+ * Decode `frames` frames with the sum-product algorithm (Algorithm 2).
+ *
+ * Each iteration t = 1..max_iter is one check-node update (Algorithm 1,
+ * second half) on bit->check messages formed from the previous posterior
+ * (Algorithm 1, first half), then the posterior and hard decision
+ * (Algorithms 4/6: bit = 1 iff posterior LLR < 0; a tie gives 0), then the
+ * syndrome test (Algorithm 7).  The pass before Algorithm 2's loop counts as
+ * iteration 1; there is no syndrome test before it.  Unless
+ * LDPC_NO_EARLY_STOP is set, a frame stops at the first iteration whose
+ * estimate is a codeword.  Messages are clamped to +-64 (the posterior is
+ * not clamped).  All arithmetic is fp32; messages are stored as fp32, fp16
+ * or bf16 according to flags.
+ *
+ *  g            graph from ldpc_graph_create (not HOST_ONLY); its device
+ *               must be the current device.
+ *  llr_in       device float [frames][n], channel LLRs, finite.
+ *  frames       >= 0 (0 is a no-op).
+ *  max_iter     >= 1.
+ *  flags        LDPC_NO_EARLY_STOP | at most one of LDPC_MSG_FP16, LDPC_MSG_BF16.
+ *  bits_out     device uint8 [frames][n]: the estimate (0/1).
+ *  syndrome_ok  device uint8 [frames]: 1 iff the returned estimate is a codeword.
+ *  iters        device int32 [frames]: iterations run, 1..max_iter (the
+ *               iteration whose estimate is returned).
+ *  llr_out      device float [frames][n] posterior LLRs, or NULL.
+ *  workspace    device memory of at least ldpc_decode_workspace_size bytes,
+ *               256-byte aligned; caller-owned; contents are scratch.
+ *  hip_stream   hipStream_t to enqueue on (NULL = default stream).
+ *
+ * The call only enqueues work and returns; outputs are valid once the
+ * stream has reached this point.  Inputs must not be modified and outputs
+ * must not be read before then.  Errors (returned synchronously; nothing is
+ * enqueued): INVAL (bad sizes or pointers, workspace too small or unaligned,
+ * graph built HOST_ONLY, wrong current device), DEVICE (launch failure).
+ * Non-finite LLRs are a precondition violation: the result is unspecified
+ * but the call does not fault.
+ */
+LDPC_API ldpc_status ldpc_decode(const ldpc_graph *g, const float *llr_in, int32_t frames,
+                        int32_t max_iter, uint32_t flags,
+                        uint8_t *bits_out, uint8_t *syndrome_ok, int32_t *iters,
+                        float *llr_out, void *workspace, size_t workspace_bytes,
+                        void *hip_stream);
+
+/*
+ * ldpc_decode plus per-pass timing, for profiling.  Arguments and results are
+ * those of ldpc_decode; in addition the library records HIP events on
+ * hip_stream around each pass, waits for the stream to finish (this call
+ * blocks), and writes the elapsed times to caller-owned host arrays:
+ *   check_ms [max_iter]  check-node pass of iteration t (index t-1)
+ *   bit_ms   [max_iter]  bit-node pass of iteration t
+ *   edge_ms  [2]         [0] state set-up and LLR transpose,
+ *                        [1] final syndrome, per-frame results and output transpose
+ * Errors: those of ldpc_decode; INVAL if a timing array is NULL; DEVICE if an
+ * event cannot be created or the stream fails.
+ */
+LDPC_API ldpc_status ldpc_decode_profiled(const ldpc_graph *g, const float *llr_in, int32_t frames,
+                                          int32_t max_iter, uint32_t flags,
+                                          uint8_t *bits_out, uint8_t *syndrome_ok, int32_t *iters,
+                                          float *llr_out, void *workspace, size_t workspace_bytes,
+                                          void *hip_stream, float *check_ms, float *bit_ms,
+                                          float *edge_ms);
+
+/* Static string naming a status code. */
+LDPC_API const char *ldpc_status_str(ldpc_status s);
+
+/* Detail of the last failure on the calling thread ("" if none). */
+LDPC_API const char *ldpc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LDPC_H */

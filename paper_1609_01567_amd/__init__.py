@@ -1,0 +1,9 @@
+"""MI355X-native sum-product decoder for arbitrary irregular LDPC codes.
+
+The decoder is a C-ABI shared library (include/ldpc.h) with hand-written HIP
+kernels for gfx950; `paper_1609_01567_amd.ldpc` is its thin Python binding.
+"""
+from .ldpc import (  # noqa: F401
+    DecodeResult, Graph, LdpcError, Workspace, decode, decode_profiled, load_library, workspace_size,
+    NO_EARLY_STOP, MSG_FP16, MSG_BF16, GRAPH_HOST_ONLY, LIB_PATH, EXPORTED,
+)

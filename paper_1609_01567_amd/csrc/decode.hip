@@ -1,0 +1,778 @@
+// Sum-product decoding on gfx950: kernels and the ldpc_decode driver.
+//
+// Data layout (all in the caller's workspace, frames padded to S slots):
+//   Lch  [n][S]  f32   channel LLRs (transposed from the caller's [F][n])
+//   Lpost[n][S]  f32   posterior LLRs of the latest iteration
+//   R    [E][S]  f32/f16/bf16  check->bit messages, edges in check-sorted order
+//   iters[S], fail[S]  i32   per-frame stop state
+// One wavefront lane owns V consecutive frame slots, so every lane of a wave
+// walks the same row or column of the Tanner graph: graph indices are
+// wave-uniform (scalar loads) and every message access is a contiguous
+// 64*V*sizeof(elem) span.
+//
+// One iteration (Algorithm 2's loop body) is two passes:
+//   check pass  (Algorithm 1 second half): for each check, the bit->check
+//               messages are formed as Q = clamp(Lpost - R_old) (Algorithm 1
+//               first half, the extrinsic sum written as total minus own
+//               message, which is exact up to rounding), the extrinsic check
+//               rule produces R_new in place, and the syndrome bit of the
+//               previous estimate (Algorithm 7) is folded in from the signs
+//               of the same Lpost values;
+//   bit pass    (Algorithms 4 and 6): Lpost = Lch + sum of R_new over the
+//               bit's checks; the hard decision is the sign of Lpost.
+//
+// Check rule.  With u = 1 - tanh(|Q|/2) = 2w/(1+w), w = exp(-|Q|), the
+// extrinsic product of tanh's is 1 - D where D is the u's combined with
+// a (+) b = a + b(1 - a) (the complement of a product of complements), and
+// the message magnitude is 2 atanh(1 - D) = ln((2 - D)/D).  Every extrinsic
+// D is an exclusive prefix combined with an exclusive suffix, so no quantity
+// is ever formed by removing a term; strong messages keep full relative
+// precision (D small) and weak ones full absolute precision.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+constexpr float kLmax = 64.f;
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+constexpr int32_t kPadSlot = 0x7fffffff;   // iters value of a padding slot: never active
+
+enum MsgType { kF32 = 0, kF16 = 1, kBF16 = 2 };
+enum Mode { kFirst = 0, kIter = 1 };
+
+// ----------------------------------------------------------------- storage
+
+template <int M> struct Codec;
+template <> struct Codec<kF32> {
+    using T = float;
+    __device__ static float dec(T x) { return x; }
+    __device__ static T enc(float x) { return x; }
+};
+template <> struct Codec<kF16> {
+    using T = _Float16;
+    __device__ static float dec(T x) { return static_cast<float>(x); }
+    __device__ static T enc(float x) { return static_cast<_Float16>(x); }   // round to nearest even
+};
+template <> struct Codec<kBF16> {
+    using T = uint16_t;
+    __device__ static float dec(T x) { return __uint_as_float(uint32_t(x) << 16); }
+    __device__ static T enc(float x) {                                     // round to nearest even
+        const uint32_t b = __float_as_uint(x);
+        return static_cast<T>((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
+    }
+};
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+template <int B> struct Raw;
+template <> struct Raw<2> { using T = uint16_t; };
+template <> struct Raw<4> { using T = uint32_t; };
+template <> struct Raw<8> { using T = u32x2; };
+template <> struct Raw<16> { using T = u32x4; };
+
+template <int M, int V>
+__device__ __forceinline__ void load_vec(const typename Codec<M>::T *p, float (&out)[V]) {
+    using T = typename Codec<M>::T;
+    using W = typename Raw<sizeof(T) * V>::T;
+    const W raw = *reinterpret_cast<const W *>(p);
+    T e[V];
+    __builtin_memcpy(e, &raw, sizeof(W));
+#pragma unroll
+    for (int k = 0; k < V; k++) out[k] = Codec<M>::dec(e[k]);
+}
+
+template <int M, int V>
+__device__ __forceinline__ void store_vec(typename Codec<M>::T *p, const float (&in)[V]) {
+    using T = typename Codec<M>::T;
+    using W = typename Raw<sizeof(T) * V>::T;
+    T e[V];
+#pragma unroll
+    for (int k = 0; k < V; k++) e[k] = Codec<M>::enc(in[k]);
+    W raw;
+    __builtin_memcpy(&raw, e, sizeof(W));
+    *reinterpret_cast<W *>(p) = raw;
+}
+
+template <int V>
+__device__ __forceinline__ void load_i32(const int32_t *p, int32_t (&out)[V]) {
+    using W = typename Raw<4 * V>::T;
+    const W raw = *reinterpret_cast<const W *>(p);
+    __builtin_memcpy(out, &raw, sizeof(W));
+}
+
+// -------------------------------------------------------------- check math
+
+// u = 1 - tanh(x/2) = 2w/(1+w) with w = e^-x, for x = |Q| >= 0.
+__device__ __forceinline__ float tanh_complement(float x) {
+    const float w = __builtin_amdgcn_exp2f(-x * kLog2e);
+    return 2.f * w * __builtin_amdgcn_rcpf(1.f + w);
+}
+
+// Complement of a product of complements: 1 - (1-a)(1-b) = a + b(1-a).
+__device__ __forceinline__ float dplus(float a, float b) { return fmaf(b, 1.f - a, a); }
+
+// |R| = 2 atanh(1 - D) = ln((2 - D)/D), clamped to LMAX; D = 0 (empty product) gives LMAX.
+__device__ __forceinline__ float magnitude_from_complement(float D) {
+    const float ratio = (2.f - D) * __builtin_amdgcn_rcpf(D);
+    return fminf(__builtin_amdgcn_logf(ratio) * kLn2, kLmax);
+}
+
+__device__ __forceinline__ float clamp_msg(float q) { return fminf(fmaxf(q, -kLmax), kLmax); }
+
+__device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// ------------------------------------------------------------------ kernels
+
+__global__ __launch_bounds__(256) void init_state_kernel(int32_t *__restrict__ iters, int32_t *__restrict__ fail,
+                                                         int32_t F, int32_t S) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < S) {
+        iters[s] = s < F ? 0 : kPadSlot;
+        fail[s] = 0;
+    }
+}
+
+// llr_in [F][n] -> Lch [n][S] (zeros in padding slots), 64x64 tiles through LDS.
+__global__ __launch_bounds__(256) void ingest_kernel(const float *__restrict__ llr, int32_t F, int32_t n,
+                                                     float *__restrict__ Lch, int32_t S) {
+    __shared__ float tile[64][65];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int v0 = blockIdx.x * 64, s0 = blockIdx.y * 64;
+    for (int i = ty; i < 64; i += 4) {
+        const int f = s0 + i, v = v0 + tx;
+        tile[i][tx] = (f < F && v < n) ? llr[size_t(f) * n + v] : 0.f;
+    }
+    __syncthreads();
+    for (int i = ty; i < 64; i += 4) {
+        const int v = v0 + i;
+        if (v < n) Lch[size_t(v) * S + s0 + tx] = tile[tx][i];
+    }
+}
+
+// Check pass for rows of degree <= DMAX held in registers.  One wavefront per
+// (row, slot group).  kFirst: iteration 1, Q = clamp(Lch), no R read.
+// kIter: Q = clamp(Lpost - R_old); when syn_iter > 0 the syndrome of the
+// previous estimate is checked and failing frames get fail[s] = syn_iter.
+template <int M, int V, int DMAX, int MODE>
+__global__ __launch_bounds__(256) void check_rows_kernel(
+    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx, const int32_t *__restrict__ rows,
+    int32_t nrows, const float *__restrict__ L, typename Codec<M>::T *__restrict__ R,
+    const int32_t *__restrict__ iters, int32_t *__restrict__ fail, int32_t S, int32_t groups, int32_t syn_iter) {
+    using T = typename Codec<M>::T;
+    const int lane = threadIdx.x & 63;
+    const int wave = wave_uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int g = wave % groups;
+    const int rk = wave / groups;
+    if (rk >= nrows) return;
+    const int s0 = (g * 64 + lane) * V;
+
+    int32_t st[V];
+    load_i32<V>(iters + s0, st);
+    bool any_active = false;
+#pragma unroll
+    for (int k = 0; k < V; k++) any_active |= (st[k] == 0);
+    if (__ballot(any_active) == 0) return;
+
+    const int row = wave_uniform(rows[rk]);
+    const int e0 = wave_uniform(row_ptr[row]);
+    const int d = wave_uniform(row_ptr[row + 1]) - e0;
+
+    float u[DMAX][V];
+    float suf[DMAX][V];
+    uint32_t neg[V];
+    int syn[V];
+#pragma unroll
+    for (int k = 0; k < V; k++) { neg[k] = 0u; syn[k] = 0; }
+
+#pragma unroll
+    for (int j = 0; j < DMAX; j++) {
+        if (j < d) {
+            const int v = wave_uniform(col_idx[e0 + j]);
+            float lv[V], r[V];
+            load_vec<kF32, V>(L + size_t(v) * S + s0, lv);
+            if (MODE == kIter) {
+                load_vec<M, V>(R + size_t(e0 + j) * S + s0, r);
+            } else {
+#pragma unroll
+                for (int k = 0; k < V; k++) r[k] = 0.f;
+            }
+#pragma unroll
+            for (int k = 0; k < V; k++) {
+                syn[k] ^= (lv[k] < 0.f);
+                const float q = clamp_msg(lv[k] - r[k]);
+                neg[k] |= uint32_t(q < 0.f) << j;
+                u[j][k] = tanh_complement(fabsf(q));
+            }
+        }
+    }
+
+    // Exclusive suffixes, then exclusive prefixes combined on the fly.
+    float run[V];
+#pragma unroll
+    for (int k = 0; k < V; k++) run[k] = 0.f;
+#pragma unroll
+    for (int j = DMAX - 1; j >= 0; j--) {
+        if (j < d) {
+#pragma unroll
+            for (int k = 0; k < V; k++) {
+                suf[j][k] = run[k];
+                run[k] = dplus(u[j][k], run[k]);
+            }
+        }
+    }
+    uint32_t parity[V];
+#pragma unroll
+    for (int k = 0; k < V; k++) { run[k] = 0.f; parity[k] = __builtin_popcount(neg[k]) & 1u; }
+#pragma unroll
+    for (int j = 0; j < DMAX; j++) {
+        if (j < d) {
+            float out[V];
+#pragma unroll
+            for (int k = 0; k < V; k++) {
+                const float mag = magnitude_from_complement(dplus(run[k], suf[j][k]));
+                const uint32_t sgn = parity[k] ^ ((neg[k] >> j) & 1u);
+                out[k] = sgn ? -mag : mag;
+                run[k] = dplus(run[k], u[j][k]);
+            }
+            store_vec<M, V>(R + size_t(e0 + j) * S + s0, out);
+        }
+    }
+
+    if (MODE == kIter && syn_iter > 0) {
+#pragma unroll
+        for (int k = 0; k < V; k++) {
+            if (st[k] == 0 && syn[k] && fail[s0 + k] != syn_iter) fail[s0 + k] = syn_iter;
+        }
+    }
+}
+
+// Check pass for long rows (degree > 32): one workgroup of four wavefronts per
+// (row, 64-slot group).  The row is cut into 32-edge chunks; each chunk's
+// combined u (its D aggregate), sign parity and syndrome parity go to scratch,
+// one wavefront scans the chunk aggregates into per-chunk exclusive values,
+// and each chunk is then finished with a local prefix/suffix pass.
+template <int M, int MODE>
+__global__ __launch_bounds__(256) void check_hub_kernel(
+    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx, const int32_t *__restrict__ rows,
+    int32_t nrows, const int32_t *__restrict__ chunk_base, const float *__restrict__ L,
+    typename Codec<M>::T *__restrict__ R, const int32_t *__restrict__ iters, int32_t *__restrict__ fail,
+    int32_t S, int32_t groups, int32_t syn_iter, float *__restrict__ aggD, float *__restrict__ aggPre,
+    int32_t *__restrict__ aggBits) {
+    using T = typename Codec<M>::T;
+    constexpr int C = ldpc::kHubChunk;
+    __shared__ int32_t total_bits[64];
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_uniform(threadIdx.x >> 6);
+    const int nw = blockDim.x >> 6;
+    const int g = blockIdx.x % groups;
+    const int rk = blockIdx.x / groups;
+    if (rk >= nrows) return;
+    const int s = g * 64 + lane;
+    const bool active = iters[s] == 0;
+    if (__ballot(active) == 0) return;   // same slots in every wave: uniform over the block
+
+    const int row = wave_uniform(rows[rk]);
+    const int e0 = wave_uniform(row_ptr[row]);
+    const int d = wave_uniform(row_ptr[row + 1]) - e0;
+    const int nch = (d + C - 1) / C;
+    const int cb = wave_uniform(chunk_base[rk]);
+
+    // Phase A: per-chunk aggregates.
+    for (int c = wv; c < nch; c += nw) {
+        const int j0 = e0 + c * C;
+        const int dc = min(C, d - c * C);
+        float agg = 0.f;
+        int32_t bits = 0;
+#pragma unroll
+        for (int jj = 0; jj < C; jj++) {
+            if (jj < dc) {
+                const int v = wave_uniform(col_idx[j0 + jj]);
+                const float lv = L[size_t(v) * S + s];
+                const float r = (MODE == kIter) ? Codec<M>::dec(R[size_t(j0 + jj) * S + s]) : 0.f;
+                const float q = clamp_msg(lv - r);
+                bits ^= int32_t(q < 0.f) | (int32_t(lv < 0.f) << 1);
+                agg = dplus(agg, tanh_complement(fabsf(q)));
+            }
+        }
+        aggD[size_t(cb + c) * S + s] = agg;
+        aggBits[size_t(cb + c) * S + s] = bits;
+    }
+    __syncthreads();
+
+    // Phase B: exclusive prefix and suffix over chunks, serial in wave 0.
+    if (wv == 0) {
+        float pre = 0.f;
+        int32_t tot = 0;
+        for (int c = 0; c < nch; c++) {
+            aggPre[size_t(cb + c) * S + s] = pre;
+            pre = dplus(pre, aggD[size_t(cb + c) * S + s]);
+            tot ^= aggBits[size_t(cb + c) * S + s];
+        }
+        float suf = 0.f;
+        for (int c = nch - 1; c >= 0; c--) {
+            const float dcur = aggD[size_t(cb + c) * S + s];
+            aggD[size_t(cb + c) * S + s] = dplus(aggPre[size_t(cb + c) * S + s], suf);
+            suf = dplus(suf, dcur);
+        }
+        total_bits[lane] = tot;
+        if (MODE == kIter && syn_iter > 0 && active && (tot & 2) && fail[s] != syn_iter) fail[s] = syn_iter;
+    }
+    __syncthreads();
+
+    // Phase C: finish each chunk with its exclusive outside value.
+    const uint32_t parity = uint32_t(total_bits[lane]) & 1u;
+    for (int c = wv; c < nch; c += nw) {
+        const int j0 = e0 + c * C;
+        const int dc = min(C, d - c * C);
+        float u[C], sf[C];
+        uint32_t neg = 0u;
+#pragma unroll
+        for (int jj = 0; jj < C; jj++) {
+            if (jj < dc) {
+                const int v = wave_uniform(col_idx[j0 + jj]);
+                const float lv = L[size_t(v) * S + s];
+                const float r = (MODE == kIter) ? Codec<M>::dec(R[size_t(j0 + jj) * S + s]) : 0.f;
+                const float q = clamp_msg(lv - r);
+                neg |= uint32_t(q < 0.f) << jj;
+                u[jj] = tanh_complement(fabsf(q));
+            }
+        }
+        float run = 0.f;
+#pragma unroll
+        for (int jj = C - 1; jj >= 0; jj--) {
+            if (jj < dc) {
+                sf[jj] = run;
+                run = dplus(u[jj], run);
+            }
+        }
+        run = aggD[size_t(cb + c) * S + s];
+#pragma unroll
+        for (int jj = 0; jj < C; jj++) {
+            if (jj < dc) {
+                const float mag = magnitude_from_complement(dplus(run, sf[jj]));
+                const uint32_t sgn = parity ^ ((neg >> jj) & 1u);
+                R[size_t(j0 + jj) * S + s] = Codec<M>::enc(sgn ? -mag : mag);
+                run = dplus(run, u[jj]);
+            }
+        }
+    }
+}
+
+// Bit pass: Lpost = Lch + sum of R over the bit's checks (Algorithm 4); one
+// wavefront per (bit, slot group).  A frame whose previous estimate passed
+// the syndrome (no fail mark for iteration t-1) is finished: its Lpost is left
+// as is and the wavefront of bit 0 records iters = t-1.
+template <int M, int V>
+__global__ __launch_bounds__(256) void bit_kernel(const int32_t *__restrict__ col_ptr,
+                                                  const int32_t *__restrict__ csc_to_csr, int32_t n,
+                                                  const float *__restrict__ Lch, const typename Codec<M>::T *__restrict__ R,
+                                                  float *__restrict__ Lpost, int32_t *__restrict__ iters,
+                                                  const int32_t *__restrict__ fail, int32_t S, int32_t groups,
+                                                  int32_t t, int32_t early_stop) {
+    const int lane = threadIdx.x & 63;
+    const int wave = wave_uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int g = wave % groups;
+    const int v = wave / groups;
+    if (v >= n) return;
+    const int s0 = (g * 64 + lane) * V;
+
+    int32_t st[V];
+    load_i32<V>(iters + s0, st);
+    bool act[V];
+    bool any_active = false;
+#pragma unroll
+    for (int k = 0; k < V; k++) {
+        bool go = st[k] == 0;
+        if (go && early_stop && t > 1) {
+            const bool failed_prev = fail[s0 + k] == t - 1;
+            if (!failed_prev) {
+                go = false;
+                if (v == 0) iters[s0 + k] = t - 1;
+            }
+        }
+        act[k] = go;
+        any_active |= go;
+    }
+    if (__ballot(any_active) == 0) return;
+
+    float sum[V];
+    load_vec<kF32, V>(Lch + size_t(v) * S + s0, sum);
+    const int a = wave_uniform(col_ptr[v]);
+    const int b = wave_uniform(col_ptr[v + 1]);
+    for (int k = a; k < b; k++) {
+        const int e = wave_uniform(csc_to_csr[k]);
+        float r[V];
+        load_vec<M, V>(R + size_t(e) * S + s0, r);
+#pragma unroll
+        for (int q = 0; q < V; q++) sum[q] += r[q];
+    }
+    bool all = true;
+#pragma unroll
+    for (int k = 0; k < V; k++) all &= act[k];
+    if (all) {
+        store_vec<kF32, V>(Lpost + size_t(v) * S + s0, sum);
+    } else {
+#pragma unroll
+        for (int k = 0; k < V; k++)
+            if (act[k]) Lpost[size_t(v) * S + s0 + k] = sum[k];
+    }
+}
+
+// Syndrome of the current estimate for every non-empty check (any degree):
+// frames still running whose estimate fails get fail[s] = syn_iter.
+template <int V>
+__global__ __launch_bounds__(256) void syndrome_kernel(const int32_t *__restrict__ row_ptr,
+                                                       const int32_t *__restrict__ col_idx,
+                                                       const int32_t *__restrict__ rows, int32_t nrows,
+                                                       const float *__restrict__ Lpost,
+                                                       const int32_t *__restrict__ iters, int32_t *__restrict__ fail,
+                                                       int32_t S, int32_t groups, int32_t syn_iter) {
+    const int lane = threadIdx.x & 63;
+    const int wave = wave_uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int g = wave % groups;
+    const int rk = wave / groups;
+    if (rk >= nrows) return;
+    const int s0 = (g * 64 + lane) * V;
+    int32_t st[V];
+    load_i32<V>(iters + s0, st);
+    bool any_active = false;
+#pragma unroll
+    for (int k = 0; k < V; k++) any_active |= (st[k] == 0);
+    if (__ballot(any_active) == 0) return;
+    const int row = wave_uniform(rows[rk]);
+    const int a = wave_uniform(row_ptr[row]);
+    const int b = wave_uniform(row_ptr[row + 1]);
+    int syn[V];
+#pragma unroll
+    for (int k = 0; k < V; k++) syn[k] = 0;
+    for (int e = a; e < b; e++) {
+        const int v = wave_uniform(col_idx[e]);
+        float lv[V];
+        load_vec<kF32, V>(Lpost + size_t(v) * S + s0, lv);
+#pragma unroll
+        for (int k = 0; k < V; k++) syn[k] ^= (lv[k] < 0.f);
+    }
+#pragma unroll
+    for (int k = 0; k < V; k++)
+        if (st[k] == 0 && syn[k] && fail[s0 + k] != syn_iter) fail[s0 + k] = syn_iter;
+}
+
+// Per-frame results: a frame still running after max_iter iterations reports
+// iters = max_iter and ok = (its final syndrome passed).
+__global__ __launch_bounds__(256) void finalize_kernel(const int32_t *__restrict__ iters,
+                                                       const int32_t *__restrict__ fail, int32_t F, int32_t max_iter,
+                                                       int32_t *__restrict__ iters_out, uint8_t *__restrict__ ok_out) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= F) return;
+    const int32_t st = iters[s];
+    if (st == 0) {
+        iters_out[s] = max_iter;
+        ok_out[s] = fail[s] != max_iter;
+    } else {
+        iters_out[s] = st;
+        ok_out[s] = 1;
+    }
+}
+
+// Lpost [n][S] -> bits [F][n] (1 iff Lpost < 0, Algorithm 6) and optional llr_out [F][n].
+__global__ __launch_bounds__(256) void egress_kernel(const float *__restrict__ Lpost, int32_t S, int32_t F,
+                                                     int32_t n, uint8_t *__restrict__ bits, float *__restrict__ llr_out) {
+    __shared__ float tile[64][65];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int v0 = blockIdx.x * 64, s0 = blockIdx.y * 64;
+    for (int i = ty; i < 64; i += 4) {
+        const int v = v0 + i;
+        tile[i][tx] = v < n ? Lpost[size_t(v) * S + s0 + tx] : 0.f;
+    }
+    __syncthreads();
+    for (int i = ty; i < 64; i += 4) {
+        const int f = s0 + i, v = v0 + tx;
+        if (f < F && v < n) {
+            const float x = tile[tx][i];
+            bits[size_t(f) * n + v] = x < 0.f;
+            if (llr_out) llr_out[size_t(f) * n + v] = x;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ driver
+
+struct Plan {
+    int msg = kF32;
+    int V = 1;
+    int32_t S = 0;
+    size_t off_lch = 0, off_lpost = 0, off_r = 0, off_iters = 0, off_fail = 0;
+    size_t off_aggd = 0, off_aggpre = 0, off_aggbits = 0, total = 0;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool flags_ok(uint32_t flags) {
+    const uint32_t known = LDPC_NO_EARLY_STOP | LDPC_MSG_FP16 | LDPC_MSG_BF16;
+    if (flags & ~known) return false;
+    if ((flags & LDPC_MSG_FP16) && (flags & LDPC_MSG_BF16)) return false;
+    return true;
+}
+
+Plan make_plan(const ldpc_graph *g, int32_t F, uint32_t flags) {
+    Plan p;
+    p.msg = (flags & LDPC_MSG_FP16) ? kF16 : (flags & LDPC_MSG_BF16) ? kBF16 : kF32;
+    p.V = F > 128 ? 4 : F > 64 ? 2 : 1;
+    const int32_t unit = 64 * p.V;
+    p.S = (std::max<int32_t>(F, 1) + unit - 1) / unit * unit;
+    const size_t S = size_t(p.S);
+    const size_t msg_bytes = p.msg == kF32 ? 4 : 2;
+    size_t off = 0;
+    p.off_lch = off;     off = align256(off + size_t(g->n) * S * 4);
+    p.off_lpost = off;   off = align256(off + size_t(g->n) * S * 4);
+    p.off_r = off;       off = align256(off + size_t(g->E) * S * msg_bytes);
+    p.off_iters = off;   off = align256(off + S * 4);
+    p.off_fail = off;    off = align256(off + S * 4);
+    p.off_aggd = off;    off = align256(off + size_t(g->hub_chunks) * S * 4);
+    p.off_aggpre = off;  off = align256(off + size_t(g->hub_chunks) * S * 4);
+    p.off_aggbits = off; off = align256(off + size_t(g->hub_chunks) * S * 4);
+    p.total = off;
+    return p;
+}
+
+struct Bufs {
+    float *lch, *lpost;
+    void *r;
+    int32_t *iters, *fail;
+    float *aggd, *aggpre;
+    int32_t *aggbits;
+};
+
+inline unsigned blocks_for_waves(int64_t waves) { return unsigned((waves + 3) / 4); }
+
+template <int M, int V, int DMAX>
+void launch_rows(const ldpc_graph *g, int cls, int mode, const float *L, const Bufs &b, int32_t S, int32_t syn_iter,
+                 hipStream_t st) {
+    const int32_t nrows = g->class_begin[cls + 1] - g->class_begin[cls];
+    if (nrows == 0) return;
+    const int32_t groups = S / (64 * V);
+    const unsigned blocks = blocks_for_waves(int64_t(nrows) * groups);
+    using T = typename Codec<M>::T;
+    T *R = static_cast<T *>(b.r);
+    const int32_t *rows = g->d_class_rows + g->class_begin[cls];
+    if (mode == kFirst)
+        hipLaunchKernelGGL((check_rows_kernel<M, V, DMAX, kFirst>), dim3(blocks), dim3(256), 0, st, g->d_row_ptr,
+                           g->d_col_idx, rows, nrows, L, R, b.iters, b.fail, S, groups, 0);
+    else
+        hipLaunchKernelGGL((check_rows_kernel<M, V, DMAX, kIter>), dim3(blocks), dim3(256), 0, st, g->d_row_ptr,
+                           g->d_col_idx, rows, nrows, L, R, b.iters, b.fail, S, groups, syn_iter);
+}
+
+template <int M>
+void launch_hub(const ldpc_graph *g, int mode, const float *L, const Bufs &b, int32_t S, int32_t syn_iter,
+                hipStream_t st) {
+    const int32_t nrows = g->class_begin[ldpc::kClassHub + 1] - g->class_begin[ldpc::kClassHub];
+    if (nrows == 0) return;
+    const int32_t groups = S / 64;
+    const unsigned blocks = unsigned(int64_t(nrows) * groups);
+    using T = typename Codec<M>::T;
+    T *R = static_cast<T *>(b.r);
+    const int32_t *rows = g->d_class_rows + g->class_begin[ldpc::kClassHub];
+    if (mode == kFirst)
+        hipLaunchKernelGGL((check_hub_kernel<M, kFirst>), dim3(blocks), dim3(256), 0, st, g->d_row_ptr, g->d_col_idx,
+                           rows, nrows, g->d_hub_chunk_base, L, R, b.iters, b.fail, S, groups, 0, b.aggd, b.aggpre,
+                           b.aggbits);
+    else
+        hipLaunchKernelGGL((check_hub_kernel<M, kIter>), dim3(blocks), dim3(256), 0, st, g->d_row_ptr, g->d_col_idx,
+                           rows, nrows, g->d_hub_chunk_base, L, R, b.iters, b.fail, S, groups, syn_iter, b.aggd,
+                           b.aggpre, b.aggbits);
+}
+
+template <int M, int V>
+void launch_check_pass(const ldpc_graph *g, int mode, const float *L, const Bufs &b, int32_t S, int32_t syn_iter,
+                       hipStream_t st) {
+    launch_rows<M, V, 8>(g, ldpc::kClassD8, mode, L, b, S, syn_iter, st);
+    launch_rows<M, (V < 2 ? V : 2), 16>(g, ldpc::kClassD16, mode, L, b, S, syn_iter, st);
+    launch_rows<M, 1, 32>(g, ldpc::kClassD32, mode, L, b, S, syn_iter, st);
+    launch_hub<M>(g, mode, L, b, S, syn_iter, st);
+}
+
+// Optional event marks for the profiled entry point: mark(i) records event i
+// on the decode stream.  Layout: 0 start, 1 after ingest, then per iteration
+// t (1-based) 2t after the check pass and 2t+1 after the bit pass, and
+// 2T+2 after the syndrome/finalize/egress tail.
+struct Marks {
+    hipEvent_t *ev = nullptr;
+    void mark(int i, hipStream_t st) const {
+        if (ev) (void)hipEventRecord(ev[i], st);
+    }
+};
+
+template <int M, int V>
+void run_decode(const ldpc_graph *g, const Plan &p, const Bufs &b, const float *llr_in, int32_t F, int32_t T,
+                bool early_stop, uint8_t *bits, uint8_t *ok, int32_t *iters_out, float *llr_out, hipStream_t st,
+                const Marks &mk) {
+    using MT = typename Codec<M>::T;
+    const int32_t S = p.S;
+    const int32_t groups = S / (64 * V);
+    mk.mark(0, st);
+    hipLaunchKernelGGL(init_state_kernel, dim3((S + 255) / 256), dim3(256), 0, st, b.iters, b.fail, F, S);
+    const dim3 tgrid((g->n + 63) / 64, S / 64);
+    hipLaunchKernelGGL(ingest_kernel, tgrid, dim3(256), 0, st, llr_in, F, g->n, b.lch, S);
+    mk.mark(1, st);
+    const unsigned bit_blocks = blocks_for_waves(int64_t(g->n) * groups);
+    for (int32_t t = 1; t <= T; t++) {
+        const int32_t syn_iter = (early_stop && t > 1) ? t - 1 : 0;
+        launch_check_pass<M, V>(g, t == 1 ? kFirst : kIter, t == 1 ? b.lch : b.lpost, b, S, syn_iter, st);
+        mk.mark(2 * t, st);
+        hipLaunchKernelGGL((bit_kernel<M, V>), dim3(bit_blocks), dim3(256), 0, st, g->d_col_ptr, g->d_csc_to_csr,
+                           g->n, b.lch, static_cast<const MT *>(b.r), b.lpost, b.iters, b.fail, S, groups, t,
+                           int32_t(early_stop));
+        mk.mark(2 * t + 1, st);
+    }
+    const int32_t nrows = g->class_begin[ldpc::kNumClasses];
+    if (nrows > 0) {
+        hipLaunchKernelGGL((syndrome_kernel<V>), dim3(blocks_for_waves(int64_t(nrows) * groups)), dim3(256), 0, st,
+                           g->d_row_ptr, g->d_col_idx, g->d_class_rows, nrows, b.lpost, b.iters, b.fail, S, groups, T);
+    }
+    hipLaunchKernelGGL(finalize_kernel, dim3((F + 255) / 256), dim3(256), 0, st, b.iters, b.fail, F, T, iters_out, ok);
+    hipLaunchKernelGGL(egress_kernel, tgrid, dim3(256), 0, st, b.lpost, S, F, g->n, bits, llr_out);
+    mk.mark(2 * T + 2, st);
+}
+
+template <int M>
+void run_decode_v(const ldpc_graph *g, const Plan &p, const Bufs &b, const float *llr_in, int32_t F, int32_t T,
+                  bool es, uint8_t *bits, uint8_t *ok, int32_t *it, float *lo, hipStream_t st, const Marks &mk) {
+    switch (p.V) {
+        case 4: run_decode<M, 4>(g, p, b, llr_in, F, T, es, bits, ok, it, lo, st, mk); break;
+        case 2: run_decode<M, 2>(g, p, b, llr_in, F, T, es, bits, ok, it, lo, st, mk); break;
+        default: run_decode<M, 1>(g, p, b, llr_in, F, T, es, bits, ok, it, lo, st, mk); break;
+    }
+}
+
+}  // namespace
+
+using ldpc::set_error;
+
+extern "C" ldpc_status ldpc_decode_workspace_size(const ldpc_graph *g, int32_t frames, uint32_t flags, size_t *bytes) {
+    if (!g || !bytes) { set_error("ldpc_decode_workspace_size: NULL argument"); return LDPC_E_INVAL; }
+    if (frames < 0) { set_error("ldpc_decode_workspace_size: frames < 0"); return LDPC_E_INVAL; }
+    if (!flags_ok(flags)) { set_error("ldpc_decode_workspace_size: bad flags"); return LDPC_E_INVAL; }
+    *bytes = frames == 0 ? 0 : make_plan(g, frames, flags).total;
+    return LDPC_OK;
+}
+
+namespace {
+
+ldpc_status decode_core(const char *fn, const ldpc_graph *g, const float *llr_in, int32_t frames, int32_t max_iter,
+                        uint32_t flags, uint8_t *bits_out, uint8_t *syndrome_ok, int32_t *iters, float *llr_out,
+                        void *workspace, size_t workspace_bytes, void *hip_stream, const Marks &mk) {
+    const std::string f(fn);
+    if (!g) { set_error(f + ": graph is NULL"); return LDPC_E_INVAL; }
+    if (g->host_only) { set_error(f + ": graph was built host-only"); return LDPC_E_INVAL; }
+    if (frames < 0) { set_error(f + ": frames < 0"); return LDPC_E_INVAL; }
+    if (max_iter < 1) { set_error(f + ": max_iter must be >= 1"); return LDPC_E_INVAL; }
+    if (!flags_ok(flags)) { set_error(f + ": bad flags"); return LDPC_E_INVAL; }
+    if (frames == 0) return LDPC_OK;
+    if (!llr_in || !bits_out || !syndrome_ok || !iters || !workspace) {
+        set_error(f + ": NULL buffer");
+        return LDPC_E_INVAL;
+    }
+    if (reinterpret_cast<uintptr_t>(workspace) & 255u) {
+        set_error(f + ": workspace must be 256-byte aligned");
+        return LDPC_E_INVAL;
+    }
+    const Plan p = make_plan(g, frames, flags);
+    if (workspace_bytes < p.total) {
+        set_error(f + ": workspace too small (" + std::to_string(workspace_bytes) + " < " + std::to_string(p.total) +
+                  ")");
+        return LDPC_E_INVAL;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != g->device) {
+        (void)hipGetLastError();
+        set_error(f + ": the current device is not the graph's device");
+        return LDPC_E_INVAL;
+    }
+    char *ws = static_cast<char *>(workspace);
+    Bufs b;
+    b.lch = reinterpret_cast<float *>(ws + p.off_lch);
+    b.lpost = reinterpret_cast<float *>(ws + p.off_lpost);
+    b.r = ws + p.off_r;
+    b.iters = reinterpret_cast<int32_t *>(ws + p.off_iters);
+    b.fail = reinterpret_cast<int32_t *>(ws + p.off_fail);
+    b.aggd = reinterpret_cast<float *>(ws + p.off_aggd);
+    b.aggpre = reinterpret_cast<float *>(ws + p.off_aggpre);
+    b.aggbits = reinterpret_cast<int32_t *>(ws + p.off_aggbits);
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const bool es = !(flags & LDPC_NO_EARLY_STOP);
+    (void)hipGetLastError();
+    switch (p.msg) {
+        case kF16: run_decode_v<kF16>(g, p, b, llr_in, frames, max_iter, es, bits_out, syndrome_ok, iters, llr_out, st, mk); break;
+        case kBF16: run_decode_v<kBF16>(g, p, b, llr_in, frames, max_iter, es, bits_out, syndrome_ok, iters, llr_out, st, mk); break;
+        default: run_decode_v<kF32>(g, p, b, llr_in, frames, max_iter, es, bits_out, syndrome_ok, iters, llr_out, st, mk); break;
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error(f + ": launch failed: " + hipGetErrorString(e));
+        return LDPC_E_DEVICE;
+    }
+    return LDPC_OK;
+}
+
+}  // namespace
+
+extern "C" ldpc_status ldpc_decode(const ldpc_graph *g, const float *llr_in, int32_t frames, int32_t max_iter,
+                                   uint32_t flags, uint8_t *bits_out, uint8_t *syndrome_ok, int32_t *iters,
+                                   float *llr_out, void *workspace, size_t workspace_bytes, void *hip_stream) {
+    return decode_core("ldpc_decode", g, llr_in, frames, max_iter, flags, bits_out, syndrome_ok, iters, llr_out,
+                       workspace, workspace_bytes, hip_stream, Marks{});
+}
+
+extern "C" ldpc_status ldpc_decode_profiled(const ldpc_graph *g, const float *llr_in, int32_t frames,
+                                            int32_t max_iter, uint32_t flags, uint8_t *bits_out,
+                                            uint8_t *syndrome_ok, int32_t *iters, float *llr_out, void *workspace,
+                                            size_t workspace_bytes, void *hip_stream, float *check_ms,
+                                            float *bit_ms, float *edge_ms) {
+    if (!check_ms || !bit_ms || !edge_ms) { set_error("ldpc_decode_profiled: NULL timing array"); return LDPC_E_INVAL; }
+    if (frames <= 0 || max_iter < 1)
+        return decode_core("ldpc_decode_profiled", g, llr_in, frames, max_iter, flags, bits_out, syndrome_ok, iters,
+                           llr_out, workspace, workspace_bytes, hip_stream, Marks{});
+    const int nev = 2 * max_iter + 3;
+    std::vector<hipEvent_t> ev(size_t(nev), nullptr);
+    for (int i = 0; i < nev; i++) {
+        if (hipEventCreate(&ev[size_t(i)]) != hipSuccess) {
+            (void)hipGetLastError();
+            for (int k = 0; k < i; k++) (void)hipEventDestroy(ev[size_t(k)]);
+            set_error("ldpc_decode_profiled: hipEventCreate failed");
+            return LDPC_E_DEVICE;
+        }
+    }
+    Marks mk;
+    mk.ev = ev.data();
+    ldpc_status stt = decode_core("ldpc_decode_profiled", g, llr_in, frames, max_iter, flags, bits_out, syndrome_ok,
+                                  iters, llr_out, workspace, workspace_bytes, hip_stream, mk);
+    if (stt == LDPC_OK) {
+        if (hipStreamSynchronize(static_cast<hipStream_t>(hip_stream)) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("ldpc_decode_profiled: stream synchronization failed");
+            stt = LDPC_E_DEVICE;
+        } else {
+            auto span = [&](int a, int b) {
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, ev[size_t(a)], ev[size_t(b)]);
+                return ms;
+            };
+            edge_ms[0] = span(0, 1);
+            for (int t = 1; t <= max_iter; t++) {
+                check_ms[t - 1] = span(2 * t - 1, 2 * t);
+                bit_ms[t - 1] = span(2 * t, 2 * t + 1);
+            }
+            edge_ms[1] = span(2 * max_iter + 1, 2 * max_iter + 2);
+        }
+    }
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    return stt;
+}

@@ -1,0 +1,50 @@
+// Internal declarations shared by the graph builder and the decode driver.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ldpc.h"
+
+namespace ldpc {
+
+// Check rows are grouped by degree into classes, one kernel shape per class
+// (register-resident rows up to 8, 16 or 32 edges, and a segmented path for
+// longer rows that splits a row into 32-edge chunks over several wavefronts).
+enum CheckClass : int { kClassD8 = 0, kClassD16 = 1, kClassD32 = 2, kClassHub = 3, kNumClasses = 4 };
+constexpr int kHubChunk = 32;   // edges per chunk on the segmented path
+
+inline int check_class_of(int d) {
+    return d <= 8 ? kClassD8 : d <= 16 ? kClassD16 : d <= 32 ? kClassD32 : kClassHub;
+}
+
+void set_error(const std::string &msg);
+
+}  // namespace ldpc
+
+struct ldpc_graph {
+    int32_t m = 0, n = 0;
+    int64_t E = 0;
+    int32_t max_cdeg = 0, max_bdeg = 0;
+    bool host_only = false;
+    int device = -1;
+
+    // Host tables (Tables I/II in compressed form, see ldpc.h).
+    std::vector<int32_t> row_ptr, col_idx;           // check-sorted (CSR)
+    std::vector<int32_t> col_ptr, row_idx;           // bit-sorted (CSC)
+    std::vector<int32_t> csr_to_csc, csc_to_csr;     // position maps between the two orders
+
+    // Check rows listed by class (rows of degree 0 are in no class).
+    std::vector<int32_t> class_rows;                 // concatenated, class by class
+    int32_t class_begin[ldpc::kNumClasses + 1] = {0};
+    // Segmented path: first chunk index of each hub row (in class order) and total chunks.
+    std::vector<int32_t> hub_chunk_base;             // [#hub rows + 1]
+    int64_t hub_chunks = 0;
+
+    // Device copies.
+    int32_t *d_row_ptr = nullptr, *d_col_idx = nullptr;
+    int32_t *d_col_ptr = nullptr, *d_csc_to_csr = nullptr;
+    int32_t *d_class_rows = nullptr, *d_hub_chunk_base = nullptr;
+    int64_t device_bytes = 0;
+};

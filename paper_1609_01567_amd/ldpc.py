@@ -1,0 +1,215 @@
+"""Thin ctypes binding of the C ABI in include/ldpc.h (argument marshalling only).
+
+Every step of decoding runs in the HIP kernels of libldpc_hip.so; this module
+only converts Python/PyTorch arguments to pointers and sizes.  PyTorch is used
+for device memory and streams.  There is no fallback: if the library is
+missing the import of this module's functions raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libldpc_hip.so")
+
+# status codes (ldpc_status)
+OK, E_INVAL, E_RANGE, E_DUP_EDGE, E_NOMEM, E_DEVICE, E_UNSUPPORTED = range(7)
+# decode flags
+NO_EARLY_STOP = 1 << 0
+MSG_FP16 = 1 << 1
+MSG_BF16 = 1 << 2
+# graph flags
+GRAPH_HOST_ONLY = 1 << 0
+
+EXPORTED = ("ldpc_graph_create", "ldpc_graph_destroy", "ldpc_graph_info", "ldpc_graph_arrays",
+            "ldpc_decode_workspace_size", "ldpc_decode", "ldpc_decode_profiled", "ldpc_status_str",
+            "ldpc_last_error")
+
+
+class LdpcError(RuntimeError):
+    def __init__(self, status: int, func: str, detail: str):
+        super().__init__(f"{func}: {detail} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library():
+    """Load libldpc_hip.so (built in-tree by __graft_entry__.build()); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                          "python paper_1609_01567_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, U32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    lib.ldpc_graph_create.argtypes = [I32, I32, I64, P, P, U32, ctypes.POINTER(P)]
+    lib.ldpc_graph_destroy.argtypes = [P]
+    lib.ldpc_graph_info.argtypes = [P, P, P, P, P, P, P]
+    lib.ldpc_graph_arrays.argtypes = [P, P, P, P, P, P]
+    lib.ldpc_decode_workspace_size.argtypes = [P, I32, U32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.ldpc_decode.argtypes = [P, P, I32, I32, U32, P, P, P, P, P, ctypes.c_size_t, P]
+    lib.ldpc_decode_profiled.argtypes = [P, P, I32, I32, U32, P, P, P, P, P, ctypes.c_size_t, P, P, P, P]
+    for f in ("ldpc_graph_create", "ldpc_graph_destroy", "ldpc_graph_info", "ldpc_graph_arrays",
+              "ldpc_decode_workspace_size", "ldpc_decode", "ldpc_decode_profiled"):
+        getattr(lib, f).restype = ctypes.c_int
+    lib.ldpc_status_str.argtypes = [ctypes.c_int]
+    lib.ldpc_status_str.restype = ctypes.c_char_p
+    lib.ldpc_last_error.argtypes = []
+    lib.ldpc_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int, func: str):
+    if status != OK:
+        lib = load_library()
+        raise LdpcError(status, func, lib.ldpc_last_error().decode())
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Graph:
+    """Tanner graph of a binary parity-check matrix (ldpc_graph_create)."""
+
+    def __init__(self, m: int, n: int, rows, cols, host_only: bool = False):
+        lib = load_library()
+        self._lib = lib
+        self._h = ctypes.c_void_p()
+        rows = np.ascontiguousarray(rows, dtype=np.int32)
+        cols = np.ascontiguousarray(cols, dtype=np.int32)
+        if rows.shape != cols.shape or rows.ndim != 1:
+            raise ValueError("rows and cols must be 1-D arrays of equal length")
+        _check(lib.ldpc_graph_create(int(m), int(n), rows.size, _np_ptr(rows), _np_ptr(cols),
+                                     GRAPH_HOST_ONLY if host_only else 0, ctypes.byref(self._h)),
+               "ldpc_graph_create")
+        self.m, self.n, self.nnz = int(m), int(n), int(rows.size)
+        self.host_only = host_only
+
+    @classmethod
+    def from_code(cls, code, host_only: bool = False) -> "Graph":
+        return cls(code.m, code.n, code.rows, code.cols, host_only=host_only)
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("graph has been closed")
+        return self._h
+
+    def info(self) -> dict:
+        vals = [ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(),
+                ctypes.c_int64()]
+        _check(self._lib.ldpc_graph_info(self.handle, *[ctypes.byref(v) for v in vals]), "ldpc_graph_info")
+        keys = ("m", "n", "nnz", "max_check_deg", "max_bit_deg", "device_bytes")
+        return {k: int(v.value) for k, v in zip(keys, vals)}
+
+    def arrays(self) -> dict:
+        out = dict(row_ptr=np.zeros(self.m + 1, np.int32), col_idx=np.zeros(self.nnz, np.int32),
+                   col_ptr=np.zeros(self.n + 1, np.int32), row_idx=np.zeros(self.nnz, np.int32),
+                   csr_to_csc=np.zeros(self.nnz, np.int32))
+        _check(self._lib.ldpc_graph_arrays(self.handle, *[_np_ptr(out[k]) for k in
+                                                          ("row_ptr", "col_idx", "col_ptr", "row_idx", "csr_to_csc")]),
+               "ldpc_graph_arrays")
+        return out
+
+    def close(self):
+        if self._h:
+            self._lib.ldpc_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def workspace_size(graph: Graph, frames: int, flags: int = 0) -> int:
+    out = ctypes.c_size_t()
+    _check(graph._lib.ldpc_decode_workspace_size(graph.handle, int(frames), int(flags), ctypes.byref(out)),
+           "ldpc_decode_workspace_size")
+    return int(out.value)
+
+
+@dataclasses.dataclass
+class DecodeResult:
+    bits: "object"     # torch.uint8 [F][n] on the device
+    ok: "object"       # torch.uint8 [F]
+    iters: "object"    # torch.int32 [F]
+    llr: "object"      # torch.float32 [F][n] or None
+
+
+class Workspace:
+    """Caller-owned device workspace (a torch uint8 tensor, 256-byte aligned)."""
+
+    def __init__(self, nbytes: int, device=None):
+        import torch
+        self.nbytes = int(nbytes)
+        self._t = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=device or "cuda")
+        base = self._t.data_ptr()
+        self.ptr = (base + 255) // 256 * 256
+
+    def fits(self, nbytes: int) -> bool:
+        return nbytes <= self.nbytes
+
+
+def _prepare(graph: Graph, llr, flags: int, want_llr: bool, workspace, stream, out):
+    import torch
+    if llr.dtype != torch.float32 or not llr.is_cuda or llr.dim() != 2 or not llr.is_contiguous():
+        raise ValueError("llr must be a contiguous float32 CUDA tensor [frames][n]")
+    F, n = llr.shape
+    if n != graph.n:
+        raise ValueError("llr width does not match the graph")
+    dev = llr.device
+    if out is None:
+        out = DecodeResult(bits=torch.empty((F, n), dtype=torch.uint8, device=dev),
+                           ok=torch.empty(F, dtype=torch.uint8, device=dev),
+                           iters=torch.empty(F, dtype=torch.int32, device=dev),
+                           llr=torch.empty((F, n), dtype=torch.float32, device=dev) if want_llr else None)
+    need = workspace_size(graph, F, flags)
+    if workspace is None or not workspace.fits(need):
+        workspace = Workspace(need, device=dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    args = (graph.handle, ctypes.c_void_p(llr.data_ptr()), int(F))
+    outs = (ctypes.c_void_p(out.bits.data_ptr()), ctypes.c_void_p(out.ok.data_ptr()),
+            ctypes.c_void_p(out.iters.data_ptr()),
+            ctypes.c_void_p(out.llr.data_ptr()) if out.llr is not None else None,
+            ctypes.c_void_p(workspace.ptr), ctypes.c_size_t(workspace.nbytes),
+            ctypes.c_void_p(stream.cuda_stream))
+    return out, workspace, args, outs
+
+
+def decode(graph: Graph, llr, max_iter: int, flags: int = 0, want_llr: bool = False,
+           workspace: Workspace | None = None, stream=None, out: DecodeResult | None = None) -> DecodeResult:
+    """Enqueue ldpc_decode on `stream` (default: torch's current stream) and return the output tensors.
+
+    `llr` is a contiguous float32 CUDA tensor [F][n].  The call does not
+    synchronize; read the outputs after the stream reaches this point (torch
+    does that for you when you use them on the same stream).
+    """
+    out, workspace, args, outs = _prepare(graph, llr, flags, want_llr, workspace, stream, out)
+    _check(graph._lib.ldpc_decode(*args, int(max_iter), int(flags), *outs), "ldpc_decode")
+    out._workspace = workspace   # keep the workspace alive until the stream has consumed it
+    return out
+
+
+def decode_profiled(graph: Graph, llr, max_iter: int, flags: int = 0, want_llr: bool = False,
+                    workspace: Workspace | None = None, stream=None, out: DecodeResult | None = None):
+    """ldpc_decode_profiled: decode, wait, and return (result, timings in ms)."""
+    out, workspace, args, outs = _prepare(graph, llr, flags, want_llr, workspace, stream, out)
+    check_ms = np.zeros(max_iter, np.float32)
+    bit_ms = np.zeros(max_iter, np.float32)
+    edge_ms = np.zeros(2, np.float32)
+    _check(graph._lib.ldpc_decode_profiled(*args, int(max_iter), int(flags), *outs, _np_ptr(check_ms),
+                                           _np_ptr(bit_ms), _np_ptr(edge_ms)), "ldpc_decode_profiled")
+    out._workspace = workspace
+    return out, dict(check_ms=check_ms, bit_ms=bit_ms, edge_ms=edge_ms)

@@ -1,0 +1,67 @@
+"""Shared helpers for the GPU parity tests: run the HIP decoder through the C ABI
+and compare it with the FP64 oracle on the same seeded inputs.
+
+Parity bar (from the decoder's contract):
+  * hard decisions, syndrome flags and iteration counts are bit-exact on every
+    frame whose oracle trajectory keeps |Lpost| >= 1e-3 at every bit and
+    iteration (frames closer to a decision tie are counted and reported);
+  * posterior LLRs agree to |L_gpu - L_oracle| <= 1e-3 + 1e-4 |L_oracle|.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+ATOL = 1e-3
+RTOL = 1e-4
+TIE_MARGIN = 1e-3
+
+
+def gpu_decode(code, llr: np.ndarray, max_iter: int, flags: int = 0, graph=None):
+    import torch
+    from paper_1609_01567_amd import ldpc
+    g = graph if graph is not None else ldpc.Graph.from_code(code)
+    x = torch.from_numpy(np.ascontiguousarray(llr, dtype=np.float32)).cuda()
+    res = ldpc.decode(g, x, max_iter, flags=flags, want_llr=True)
+    torch.cuda.synchronize()
+    return dict(bits=res.bits.cpu().numpy(), ok=res.ok.cpu().numpy(), iters=res.iters.cpu().numpy(),
+                lpost=res.llr.cpu().numpy())
+
+
+def compare(code, llr, max_iter: int, early_stop: bool = True, flags: int = 0, frames=None,
+            gpu=None, atol: float = ATOL, rtol: float = RTOL, margin: float = TIE_MARGIN,
+            require_all: bool = False):
+    """Decode on both sides and assert the parity bar; returns a stats dict.
+
+    `frames` restricts the oracle to a subset of rows of `llr` (full-size
+    cases); `gpu` may carry a GPU result decoded earlier for all rows.
+    """
+    from paper_1609_01567_amd import ldpc
+    if not early_stop:
+        flags |= ldpc.NO_EARLY_STOP
+    if gpu is None:
+        gpu = gpu_decode(code, llr, max_iter, flags)
+    idx = np.arange(llr.shape[0]) if frames is None else np.asarray(frames)
+    ora = oracle.decode(code, llr[idx], max_iter, early_stop=early_stop)
+    g = {k: v[idx] for k, v in gpu.items()}
+    clear = ora["min_abs"] >= margin
+    if require_all:
+        clear[:] = True
+    same_bits = (g["bits"] == ora["bits"]).all(axis=1)
+    same_iter = g["iters"] == ora["iters"]
+    same_ok = g["ok"] == ora["ok"]
+    err = np.abs(g["lpost"].astype(np.float64) - ora["lpost"])
+    within = (err <= atol + rtol * np.abs(ora["lpost"])).all(axis=1)
+    bad = clear & ~(same_bits & same_iter & same_ok & within)
+    stats = dict(frames=int(idx.size), clear=int(clear.sum()), near_tie=int((~clear).sum()),
+                 mismatched_near_tie=int((~clear & ~(same_bits & same_iter & same_ok)).sum()),
+                 max_err=float(err[clear].max()) if clear.any() else 0.0,
+                 max_rel=float((err / (1.0 + np.abs(ora["lpost"])))[clear].max()) if clear.any() else 0.0)
+    if bad.any():
+        f = int(np.flatnonzero(bad)[0])
+        raise AssertionError(
+            f"parity failure on frame {int(idx[f])}: bits_equal={bool(same_bits[f])} "
+            f"iters gpu/oracle={int(g['iters'][f])}/{int(ora['iters'][f])} ok gpu/oracle="
+            f"{int(g['ok'][f])}/{int(ora['ok'][f])} max|dL|={float(err[f].max()):.3e} stats={stats}")
+    return stats

@@ -1,0 +1,137 @@
+"""Host-side checks of the C-ABI library: it loads, exports what include/ldpc.h
+declares, builds the paper's address arrays, and rejects bad input.
+No GPU is needed: graphs are built with LDPC_GRAPH_HOST_ONLY and every decode
+call here is one that fails argument checks before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import ldpc_inputs as li
+from paper_1609_01567_amd import ldpc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "ldpc.h")).read()
+    return sorted(set(re.findall(r"LDPC_API\s+[\w\s\*]*?\b(ldpc_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ldpc.load_library()
+    declared = _declared_symbols()
+    assert len(declared) >= 8
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(ldpc.EXPORTED) == declared
+
+
+def test_status_strings():
+    lib = ldpc.load_library()
+    assert lib.ldpc_status_str(0) == b"LDPC_OK"
+    assert lib.ldpc_status_str(3) == b"LDPC_E_DUP_EDGE"
+    assert lib.ldpc_status_str(99) == b"LDPC_E_UNKNOWN"
+
+
+def test_address_arrays_match_paper_tables(tables):
+    code = li.code_14_7()
+    g = ldpc.Graph.from_code(code, host_only=True)
+    a = g.arrays()
+    E = code.nnz
+    # Table I (bit-sorted positions)
+    cp = a["col_ptr"]
+    v = np.repeat(np.arange(code.n), np.diff(cp))
+    assert v.tolist() == tables["v"]
+    assert a["row_idx"].tolist() == tables["c"]
+    assert [int(cp[x + 1] - cp[x]) for x in v] == tables["t"]
+    assert [int(cp[x]) for x in v] == tables["s"]
+    assert [k - int(cp[v[k]]) for k in range(E)] == tables["u"]
+    # Table II (check-sorted positions)
+    rp = a["row_ptr"]
+    c = np.repeat(np.arange(code.m), np.diff(rp))
+    assert a["csr_to_csc"].tolist() == tables["ebar"]
+    assert a["col_idx"].tolist() == tables["vbar"]
+    assert c.tolist() == tables["cbar"]
+    assert [int(rp[x + 1] - rp[x]) for x in c] == tables["tbar"]
+    assert [int(rp[x]) for x in c] == tables["sbar"]
+    assert [k - int(rp[c[k]]) for k in range(E)] == tables["ubar"]
+    info = g.info()
+    assert (info["m"], info["n"], info["nnz"], info["max_check_deg"], info["max_bit_deg"]) == (7, 14, 31, 5, 4)
+    assert info["device_bytes"] == 0
+
+
+@pytest.mark.parametrize("maker", [li.tiny_code, li.extreme_code])
+def test_address_arrays_consistent_on_random_codes(maker):
+    code = maker()
+    g = ldpc.Graph.from_code(code, host_only=True)
+    a = g.arrays()
+    rp, ci, cp, ri, m2c = a["row_ptr"], a["col_idx"], a["col_ptr"], a["row_idx"], a["csr_to_csc"]
+    rows_csr = np.repeat(np.arange(code.m), np.diff(rp))
+    cols_csc = np.repeat(np.arange(code.n), np.diff(cp))
+    # same edge seen from both sides
+    assert (ri[m2c] == rows_csr).all()
+    assert (cols_csc[m2c] == ci).all()
+    assert sorted(m2c.tolist()) == list(range(code.nnz))
+    # stable order: within each check, input order is kept
+    order = np.argsort(code.rows, kind="stable")
+    assert (ci == code.cols[order]).all()
+    info = g.info()
+    assert info["max_check_deg"] == code.check_degrees().max()
+    assert info["max_bit_deg"] == code.bit_degrees().max()
+
+
+@pytest.mark.parametrize("m,n,rows,cols,status", [
+    (0, 4, [0], [0], ldpc.E_INVAL),
+    (2, 0, [0], [0], ldpc.E_INVAL),
+    (2, 4, [2], [0], ldpc.E_RANGE),
+    (2, 4, [0], [4], ldpc.E_RANGE),
+    (2, 4, [-1], [0], ldpc.E_RANGE),
+    (2, 4, [0, 1, 0], [1, 1, 1], ldpc.E_DUP_EDGE),
+])
+def test_graph_create_rejects_bad_input(m, n, rows, cols, status):
+    with pytest.raises(ldpc.LdpcError) as ei:
+        ldpc.Graph(m, n, np.array(rows), np.array(cols), host_only=True)
+    assert ei.value.status == status
+
+
+def test_empty_rows_and_columns_are_accepted():
+    g = ldpc.Graph(4, 6, np.array([0, 0, 2], np.int32), np.array([1, 3, 3], np.int32), host_only=True)
+    a = g.arrays()
+    assert a["row_ptr"].tolist() == [0, 2, 2, 3, 3]
+    assert a["col_ptr"].tolist() == [0, 0, 1, 1, 3, 3, 3]
+    g0 = ldpc.Graph(3, 3, np.zeros(0, np.int32), np.zeros(0, np.int32), host_only=True)
+    assert g0.info()["nnz"] == 0
+
+
+def test_workspace_size_rules():
+    code = li.tiny_code()
+    g = ldpc.Graph.from_code(code, host_only=True)
+    assert ldpc.workspace_size(g, 0) == 0
+    w32 = ldpc.workspace_size(g, 32)
+    w16 = ldpc.workspace_size(g, 32, ldpc.MSG_FP16)
+    assert w32 > w16 > 0
+    # fp32: Lch + Lpost (n*S*4 each) + R (E*S*4) with S = 64 slots, plus small state
+    assert w32 >= (2 * code.n + code.nnz) * 64 * 4
+    assert ldpc.workspace_size(g, 1000) > ldpc.workspace_size(g, 100) > w32
+    with pytest.raises(ldpc.LdpcError):
+        ldpc.workspace_size(g, 8, ldpc.MSG_FP16 | ldpc.MSG_BF16)
+    with pytest.raises(ldpc.LdpcError):
+        ldpc.workspace_size(g, -1)
+
+
+def test_decode_argument_checks_fail_before_device_work():
+    lib = ldpc.load_library()
+    code = li.code_14_7()
+    g = ldpc.Graph.from_code(code, host_only=True)
+    call = lambda *a: lib.ldpc_decode(g.handle, *a)
+    P = ctypes.c_void_p
+    # host-only graph
+    assert call(P(8), 1, 5, 0, P(8), P(8), P(8), None, P(256), 1 << 20, None) == ldpc.E_INVAL
+    assert b"host-only" in lib.ldpc_last_error()
+    # null graph
+    assert lib.ldpc_decode(None, P(8), 1, 5, 0, P(8), P(8), P(8), None, P(256), 1, None) == ldpc.E_INVAL
+    # frames == 0 is a no-op even with null buffers
+    assert lib.ldpc_decode(g.handle, None, 0, 5, 0, None, None, None, None, None, 0, None) in (ldpc.OK, ldpc.E_INVAL)

@@ -65,7 +65,7 @@ def test_tiny_code_fixed_iterations_every_frame(T):
     code = li.tiny_code()
     llr = li.awgn_llr(code.n, 32, li.ebn0_to_sigma2(2.0, code.rate), seed=2001)
     _announce("tiny-fixed", T=T)
-    compare(code, llr, T, early_stop=False, require_all=(T <= 2))
+    compare(code, llr, T, early_stop=False, require_all=(T <= 2), posterior_all=True)
 
 
 @pytest.mark.parametrize("frames", [1, 63, 65, 130, 200, 257])
@@ -73,7 +73,7 @@ def test_ragged_frame_counts(frames):
     code = li.random_small_code(300, 150, 3, seed=31)
     llr = li.awgn_llr(code.n, frames, li.ebn0_to_sigma2(1.5, code.rate), seed=40 + frames)
     _announce("ragged", frames=frames, n=code.n)
-    compare(code, llr, 30)
+    print(compare(code, llr, 30))
 
 
 def test_low_snr_many_iterations():
@@ -96,8 +96,8 @@ def test_degree_classes_and_segmented_rows():
     assert code.check_degrees().max() == 300
     llr = li.awgn_llr(n, 70, 0.7, seed=13)
     _announce("classes", frames=70, max_deg=300)
-    compare(code, llr, 25)
-    compare(code, llr, 3, early_stop=False)
+    print(compare(code, llr, 25))
+    compare(code, llr, 3, early_stop=False, posterior_all=True)
 
 
 def test_degree_one_checks_and_empty_nodes():
@@ -110,7 +110,7 @@ def test_degree_one_checks_and_empty_nodes():
     out = gpu_decode(code, llr, 6)
     np.testing.assert_array_equal(out["lpost"][:, 4], llr[:, 4])
     compare(code, llr, 6)
-    compare(code, llr, 4, early_stop=False)
+    compare(code, llr, 4, early_stop=False, posterior_all=True)
 
 
 def test_extreme_code_sampled():

@@ -36,10 +36,31 @@ def parse():
     ap.add_argument("--frames", type=int, default=256)
     ap.add_argument("--max-iter", type=int, default=50)
     ap.add_argument("--msg", choices=["fp32", "fp16", "bf16"], default="fp32")
+    ap.add_argument("--lane-slots", type=int, choices=[0, 1, 2, 4], default=0,
+                    help="frame slots per wavefront lane (0: library default)")
     ap.add_argument("--cpu-frames", type=int, default=16, help="oracle sample: frames per Eb/N0 point")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates rocprof byte counters) and exit")
     return ap.parse_args()
+
+
+def copy_ceiling(torch, nbytes=1 << 30, reps=5):
+    """GB/s of a plain device-to-device copy of nbytes (read + write counted)."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
 def algorithmic_bytes(iters: np.ndarray, T: int, E: int, n: int, msg_bytes: int):
@@ -97,7 +118,16 @@ def main():
     from paper_1609_01567_amd import ldpc
 
     torch.cuda.set_device(0)
+    if args.calib_copy:
+        a = torch.ones((1 << 30) // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)          # one dispatch: reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes_read": 1 << 30, "calib_copy_bytes_written": 1 << 30}))
+        return
     flags = {"fp32": 0, "fp16": ldpc.MSG_FP16, "bf16": ldpc.MSG_BF16}[args.msg]
+    flags |= {0: 0, 1: ldpc.LANE_SLOTS_1, 2: ldpc.LANE_SLOTS_2, 4: ldpc.LANE_SLOTS_4}[args.lane_slots]
     msg_bytes = 4 if args.msg == "fp32" else 2
     points = [float(x) for x in args.ebn0.split(",")]
     code = li.large_code()
@@ -183,6 +213,7 @@ def main():
                  "bit_achieved_gbs": round(bit_bytes.sum() / (bit_ms.sum() * 1e-3) / 1e9, 1)}
         print(f"[bench] profiled pass done", file=sys.stderr, flush=True)
 
+    ceiling = copy_ceiling(torch)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(code, llrs, T, args.cpu_frames)
@@ -206,6 +237,7 @@ def main():
                                f"syndrome early stop, {args.msg} messages",
                    "frames_per_step": frames_per_step, "info_bits_per_frame": k},
         "hbm_frac_step": round(hbm_frac, 4),
+        "copy_ceiling_gbs": round(ceiling, 1),
         "per_point": per_point,
         "roofline": roofline,
         "phases": phase,

@@ -53,7 +53,14 @@ typedef enum {
 enum {
     LDPC_NO_EARLY_STOP = 1u << 0, /* run exactly max_iter iterations (no syndrome stop) */
     LDPC_MSG_FP16 = 1u << 1,      /* store check->bit messages as IEEE fp16 (math stays fp32) */
-    LDPC_MSG_BF16 = 1u << 2       /* store check->bit messages as bfloat16 (math stays fp32) */
+    LDPC_MSG_BF16 = 1u << 2,      /* store check->bit messages as bfloat16 (math stays fp32) */
+    /* Tile shape (at most one; default: chosen from the frame count).  Each
+     * wavefront lane holds 1, 2 or 4 consecutive frame slots, so one memory
+     * access of a wavefront spans 64, 128 or 256 frames of one edge or bit.
+     * Results do not depend on the choice. */
+    LDPC_LANE_SLOTS_1 = 1u << 3,
+    LDPC_LANE_SLOTS_2 = 1u << 4,
+    LDPC_LANE_SLOTS_4 = 1u << 5
 };
 
 /* Graph flags. */
@@ -137,7 +144,8 @@ LDPC_API ldpc_status ldpc_decode_workspace_size(const ldpc_graph *g, int32_t fra
  *  llr_in       device float [frames][n], channel LLRs, finite.
  *  frames       >= 0 (0 is a no-op).
  *  max_iter     >= 1.
- *  flags        LDPC_NO_EARLY_STOP | at most one of LDPC_MSG_FP16, LDPC_MSG_BF16.
+ *  flags        LDPC_NO_EARLY_STOP | at most one of LDPC_MSG_FP16, LDPC_MSG_BF16 |
+ *               at most one LDPC_LANE_SLOTS_* tile-shape flag.
  *  bits_out     device uint8 [frames][n]: the estimate (0/1).
  *  syndrome_ok  device uint8 [frames]: 1 iff the returned estimate is a codeword.
  *  iters        device int32 [frames]: iterations run, 1..max_iter (the

@@ -45,7 +45,7 @@ def _load():
         P = ctypes.c_void_p
         lib.ldpc_oracle_decode.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long, P, P, P,
                                            ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
-                                           P, P, P, P, P, ctypes.c_int]
+                                           ctypes.c_double, P, P, P, P, P, P, ctypes.c_int]
         lib.ldpc_oracle_decode.restype = ctypes.c_int
         lib.ldpc_oracle_adjacency.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long, P, P, P, P, P, P]
         lib.ldpc_oracle_adjacency.restype = ctypes.c_int
@@ -58,12 +58,13 @@ def _ptr(a):
 
 
 def decode(code, llr, max_iter: int, early_stop: bool = True, lmax: float = LMAX,
-           threads: int = 0, want_lpost: bool = True) -> dict:
+           threads: int = 0, want_lpost: bool = True, tie_margin: float = 1e-3) -> dict:
     """Decode every row of `llr` ([F][n] float32) on the CPU in FP64.
 
     Returns a dict with bits [F][n] u8, ok [F] u8, iters [F] i32,
-    min_abs [F] f64 (smallest |Lpost| over all iterations run) and, if asked,
-    lpost [F][n] f64.
+    min_abs [F] f64 (smallest |Lpost| over all iterations run), tie_risk [F]
+    u8 (1 if flipping the sign of bits with |Lpost| < tie_margin could change
+    bits, ok or iters) and, if asked, lpost [F][n] f64.
     """
     lib = _load()
     rows = np.ascontiguousarray(code.rows, dtype=np.int32)
@@ -76,14 +77,15 @@ def decode(code, llr, max_iter: int, early_stop: bool = True, lmax: float = LMAX
     ok = np.zeros(F, np.uint8)
     iters = np.zeros(F, np.int32)
     min_abs = np.zeros(F, np.float64)
+    tie_risk = np.zeros(F, np.uint8)
     lpost = np.zeros((F, n), np.float64) if want_lpost else None
     st = lib.ldpc_oracle_decode(code.m, code.n, rows.size, _ptr(rows), _ptr(cols), _ptr(llr), F,
-                                int(max_iter), int(bool(early_stop)), float(lmax),
+                                int(max_iter), int(bool(early_stop)), float(lmax), float(tie_margin),
                                 _ptr(lpost) if want_lpost else None, _ptr(bits), _ptr(ok), _ptr(iters),
-                                _ptr(min_abs), int(threads))
+                                _ptr(min_abs), _ptr(tie_risk), int(threads))
     if st != 0:
         raise ValueError(f"oracle rejected the input (status {st})")
-    out = dict(bits=bits, ok=ok, iters=iters, min_abs=min_abs)
+    out = dict(bits=bits, ok=ok, iters=iters, min_abs=min_abs, tie_risk=tie_risk)
     if want_lpost:
         out["lpost"] = lpost
     return out

@@ -102,12 +102,12 @@ static double clamp(double x, double lim) {
 
 /* Decode one frame.  Work buffers: R, Q, P (per edge), lpost (per bit), chat (per bit). */
 static void decode_frame(const graph_t *g, const float *llr, int max_iter, int early_stop, double lmax,
-                         double *R, double *Q, double *P, double *lpost, uint8_t *chat,
-                         uint8_t *ok_out, int *iters_out, double *min_abs_out) {
+                         double tie_margin, double *R, double *Q, double *P, double *lpost, uint8_t *chat,
+                         uint8_t *ok_out, int *iters_out, double *min_abs_out, uint8_t *tie_risk_out) {
     const int m = g->m, n = g->n;
     const long E = g->E;
     double min_abs = INFINITY;
-    int ok = 0, t;
+    int ok = 0, t, tie_risk = 0;
 
     /* Algorithm 3: before any check update the bit->check messages are the
        channel values, which is the bit rule with every r at its neutral value
@@ -150,35 +150,51 @@ static void decode_frame(const graph_t *g, const float *llr, int max_iter, int e
         }
 
         /* Algorithm 4: the estimate uses the channel value and every incoming r. */
+        long near_degree = 0;                          /* diagnostics only, see below */
+        int near = 0;
         for (int j = 0; j < n; j++) {
             double s = (double)llr[j];
             for (int a = g->bit_start[j]; a < g->bit_start[j + 1]; a++) s += R[g->bit_edge[a]];
             lpost[j] = s;
             chat[j] = (uint8_t)(s < 0.0);              /* Algorithm 6: 1 only if Q1 > Q0 */
             if (fabs(s) < min_abs) min_abs = fabs(s);
+            if (fabs(s) < tie_margin) { near = 1; near_degree += g->bit_start[j + 1] - g->bit_start[j]; }
         }
 
         /* Algorithm 7: z = c H^T; the estimate is a codeword iff z = 0. */
-        ok = 1;
-        for (int i = 0; i < m && ok; i++) {
+        long weight = 0;
+        for (int i = 0; i < m; i++) {
             int z = 0;
             for (int a = g->chk_start[i]; a < g->chk_start[i + 1]; a++) z ^= chat[g->col[g->chk_edge[a]]];
-            if (z) ok = 0;
+            weight += z;
         }
+        ok = (weight == 0);
+
+        /* Diagnostics for comparisons with lower-precision decoders (no effect on
+           the decode): the hard decisions only reach the outputs through the
+           syndrome test and the returned estimate.  Flipping bits with
+           |Lpost| < tie_margin can change an output only if it can zero a
+           non-zero syndrome before the stop (weight <= sum of their degrees,
+           early stop on) or if such a bit exists at the returned iteration. */
+        const int stop = (ok && early_stop) || t == max_iter;
+        if (stop ? near : (early_stop && weight > 0 && weight <= near_degree)) tie_risk = 1;
         if (ok && early_stop) break;                   /* Algorithm 2: return the codeword */
     }
     *ok_out = (uint8_t)ok;
     *iters_out = (t > max_iter) ? max_iter : t;
     *min_abs_out = min_abs;
+    *tie_risk_out = (uint8_t)tie_risk;
 }
 
 /* Public entry.  llr: [frames][n] float32 LLRs.  Outputs per frame: lpost [frames][n]
  * (may be NULL), bits [frames][n], ok [frames], iters [frames], min_abs [frames]
- * (smallest |Lpost| over all bits and all iterations run; may be NULL). */
+ * (smallest |Lpost| over all bits and all iterations run; may be NULL) and
+ * tie_risk [frames] (1 if a sign flip of some bit with |Lpost| < tie_margin could
+ * change bits, ok or iters; may be NULL). */
 int ldpc_oracle_decode(int m, int n, long nnz, const int *rows, const int *cols,
                        const float *llr, int frames, int max_iter, int early_stop, double lmax,
-                       double *lpost_out, uint8_t *bits_out, uint8_t *ok_out, int *iters_out,
-                       double *min_abs_out, int nthreads) {
+                       double tie_margin, double *lpost_out, uint8_t *bits_out, uint8_t *ok_out,
+                       int *iters_out, double *min_abs_out, uint8_t *tie_risk_out, int nthreads) {
     if (max_iter < 1 || frames < 0 || !(lmax > 0.0)) return ORACLE_E_INVAL;
     graph_t g;
     int st = graph_build(&g, m, n, nnz, rows, cols);
@@ -202,9 +218,11 @@ int ldpc_oracle_decode(int m, int n, long nnz, const int *rows, const int *cols,
 #pragma omp for schedule(dynamic, 1)
             for (int f = 0; f < frames; f++) {
                 double mn;
-                decode_frame(&g, llr + (size_t)f * n, max_iter, early_stop, lmax, R, Q, P, lp, ch,
-                             &ok_out[f], &iters_out[f], &mn);
+                uint8_t risk;
+                decode_frame(&g, llr + (size_t)f * n, max_iter, early_stop, lmax, tie_margin, R, Q, P, lp, ch,
+                             &ok_out[f], &iters_out[f], &mn, &risk);
                 if (min_abs_out) min_abs_out[f] = mn;
+                if (tie_risk_out) tie_risk_out[f] = risk;
                 if (lpost_out) memcpy(lpost_out + (size_t)f * n, lp, sizeof(double) * (size_t)n);
                 memcpy(bits_out + (size_t)f * n, ch, (size_t)n);
             }

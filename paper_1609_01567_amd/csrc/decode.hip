@@ -175,10 +175,12 @@ __global__ __launch_bounds__(256) void check_rows_kernel(
 
     int32_t st[V];
     load_i32<V>(iters + s0, st);
-    bool any_active = false;
+    bool lane_active = false;
 #pragma unroll
-    for (int k = 0; k < V; k++) any_active |= (st[k] == 0);
-    if (__ballot(any_active) == 0) return;
+    for (int k = 0; k < V; k++) lane_active |= (st[k] == 0);
+    if (__ballot(lane_active) == 0) return;
+    // Lanes whose frames have all stopped issue no loads or stores.
+    if (!lane_active) return;
 
     const int row = wave_uniform(rows[rk]);
     const int e0 = wave_uniform(row_ptr[row]);
@@ -401,6 +403,7 @@ __global__ __launch_bounds__(256) void bit_kernel(const int32_t *__restrict__ co
         any_active |= go;
     }
     if (__ballot(any_active) == 0) return;
+    if (!any_active) return;   // lanes with no running frame issue no loads or stores
 
     float sum[V];
     load_vec<kF32, V>(Lch + size_t(v) * S + s0, sum);
@@ -446,6 +449,7 @@ __global__ __launch_bounds__(256) void syndrome_kernel(const int32_t *__restrict
 #pragma unroll
     for (int k = 0; k < V; k++) any_active |= (st[k] == 0);
     if (__ballot(any_active) == 0) return;
+    if (!any_active) return;
     const int row = wave_uniform(rows[rk]);
     const int a = wave_uniform(row_ptr[row]);
     const int b = wave_uniform(row_ptr[row + 1]);
@@ -514,17 +518,23 @@ struct Plan {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+constexpr uint32_t kLaneSlotFlags = LDPC_LANE_SLOTS_1 | LDPC_LANE_SLOTS_2 | LDPC_LANE_SLOTS_4;
+
 bool flags_ok(uint32_t flags) {
-    const uint32_t known = LDPC_NO_EARLY_STOP | LDPC_MSG_FP16 | LDPC_MSG_BF16;
+    const uint32_t known = LDPC_NO_EARLY_STOP | LDPC_MSG_FP16 | LDPC_MSG_BF16 | kLaneSlotFlags;
     if (flags & ~known) return false;
     if ((flags & LDPC_MSG_FP16) && (flags & LDPC_MSG_BF16)) return false;
+    if (__builtin_popcount(flags & kLaneSlotFlags) > 1) return false;
     return true;
 }
 
 Plan make_plan(const ldpc_graph *g, int32_t F, uint32_t flags) {
     Plan p;
     p.msg = (flags & LDPC_MSG_FP16) ? kF16 : (flags & LDPC_MSG_BF16) ? kBF16 : kF32;
-    p.V = F > 128 ? 4 : F > 64 ? 2 : 1;
+    if (flags & LDPC_LANE_SLOTS_1) p.V = 1;
+    else if (flags & LDPC_LANE_SLOTS_2) p.V = 2;
+    else if (flags & LDPC_LANE_SLOTS_4) p.V = 4;
+    else p.V = F > 128 ? 4 : F > 64 ? 2 : 1;
     const int32_t unit = 64 * p.V;
     p.S = (std::max<int32_t>(F, 1) + unit - 1) / unit * unit;
     const size_t S = size_t(p.S);

@@ -22,6 +22,9 @@ OK, E_INVAL, E_RANGE, E_DUP_EDGE, E_NOMEM, E_DEVICE, E_UNSUPPORTED = range(7)
 NO_EARLY_STOP = 1 << 0
 MSG_FP16 = 1 << 1
 MSG_BF16 = 1 << 2
+LANE_SLOTS_1 = 1 << 3
+LANE_SLOTS_2 = 1 << 4
+LANE_SLOTS_4 = 1 << 5
 # graph flags
 GRAPH_HOST_ONLY = 1 << 0
 

@@ -3,8 +3,13 @@ and compare it with the FP64 oracle on the same seeded inputs.
 
 Parity bar (from the decoder's contract):
   * hard decisions, syndrome flags and iteration counts are bit-exact on every
-    frame whose oracle trajectory keeps |Lpost| >= 1e-3 at every bit and
-    iteration (frames closer to a decision tie are counted and reported);
+    frame that is clear of decision ties.  The contract excludes frames whose
+    trajectory has any |Lpost| < 1e-3; at n = 64800 and tens of iterations
+    that excludes every frame, so the oracle instead flags a frame only when
+    flipping the bits with |Lpost| < 1e-3 could change an output (zero a
+    failing syndrome early, or touch the returned estimate).  Every frame the
+    contract keeps is also kept here (the test is stricter); tie-risk frames
+    are counted and their mismatches reported;
   * posterior LLRs agree to |L_gpu - L_oracle| <= 1e-3 + 1e-4 |L_oracle| on
     those frames when the oracle decodes them to a codeword, and on every
     frame in the fixed-iteration checks (posterior_all=True).  A frame that
@@ -49,9 +54,9 @@ def compare(code, llr, max_iter: int, early_stop: bool = True, flags: int = 0, f
     if gpu is None:
         gpu = gpu_decode(code, llr, max_iter, flags)
     idx = np.arange(llr.shape[0]) if frames is None else np.asarray(frames)
-    ora = oracle.decode(code, llr[idx], max_iter, early_stop=early_stop)
+    ora = oracle.decode(code, llr[idx], max_iter, early_stop=early_stop, tie_margin=margin)
     g = {k: v[idx] for k, v in gpu.items()}
-    clear = ora["min_abs"] >= margin
+    clear = ora["tie_risk"] == 0
     if require_all:
         clear[:] = True
     same_bits = (g["bits"] == ora["bits"]).all(axis=1)
@@ -64,6 +69,7 @@ def compare(code, llr, max_iter: int, early_stop: bool = True, flags: int = 0, f
     bad = (clear & ~(same_bits & same_iter & same_ok)) | (post & ~within)
     drift = clear & ~post
     stats = dict(frames=int(idx.size), clear=int(clear.sum()), near_tie=int((~clear).sum()),
+                 clear_by_min_abs=int((ora["min_abs"] >= margin).sum()),
                  mismatched_near_tie=int((~clear & ~(same_bits & same_iter & same_ok)).sum()),
                  posterior_checked=int(post.sum()),
                  max_err=float(err[post].max()) if post.any() else 0.0,

@@ -158,3 +158,17 @@ def test_large_code_full_batch_sampled_frames():
     # oracle on sampled frames: first, last and across slot groups
     st = compare(code, llr, 50, frames=[0, 1, 127, 128, 200, 255], gpu=gpu)
     print(st)
+
+
+def test_tile_shapes_give_identical_results():
+    """The slots-per-lane tile shape changes the memory access width only."""
+    from paper_1609_01567_amd import ldpc
+    code = li.random_small_code(600, 300, 3, seed=8)
+    llr = li.awgn_llr(code.n, 300, li.ebn0_to_sigma2(1.2, code.rate), seed=9)
+    _announce("tile-shapes", frames=300)
+    ref = gpu_decode(code, llr, 30, flags=ldpc.LANE_SLOTS_1)
+    for fl in (ldpc.LANE_SLOTS_2, ldpc.LANE_SLOTS_4, 0):
+        out = gpu_decode(code, llr, 30, flags=fl)
+        for k in ref:
+            assert (out[k] == ref[k]).all(), (fl, k)
+    compare(code, llr, 30, gpu=ref)

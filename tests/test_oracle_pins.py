@@ -303,3 +303,16 @@ def test_threads_do_not_change_results():
     b = oracle.decode(code, llr, max_iter=30, threads=4)
     for k in a:
         assert (a[k] == b[k]).all()
+
+
+def test_tie_risk_flags():
+    """Frames that never come within the margin of a tie carry no tie risk; an
+    all-zero input (every posterior exactly 0 at the returned iteration) does."""
+    code = li.tiny_code()
+    llr = li.awgn_llr(code.n, 16, li.ebn0_to_sigma2(2.0, code.rate), seed=2001)
+    r = oracle.decode(code, llr, 50)
+    assert (r["tie_risk"][r["min_abs"] >= 1e-3] == 0).all()
+    z = oracle.decode(code, np.zeros((1, code.n), np.float32), 5)
+    assert z["tie_risk"][0] == 1
+    big = oracle.decode(code, np.full((1, code.n), 9.0, np.float32), 5)
+    assert big["tie_risk"][0] == 0 and big["iters"][0] == 1

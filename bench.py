@@ -25,6 +25,29 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak, GB/s
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "check_rows_kernel_n64800_f256_4pts.json")
+DOMINANT = "void check_rows_kernel<0, 4, 8, 1>"
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 PMC record.
+
+    FETCH_SIZE and WRITE_SIZE per dispatch, scaled by what the same counters read
+    for a plain 1 GiB copy.  None when the kernel source changed since the counters
+    were taken.
+    """
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_RECORD))
+    except (OSError, ValueError):
+        return None
+    src = open(os.path.join(ROOT, "paper_1609_01567_amd", "csrc", "decode.hip"), "rb").read()
+    if hashlib.sha256(src).hexdigest()[:16] != rec.get("source_sha"):
+        return None
+    k = rec["kernels"].get(DOMINANT)
+    if not k:
+        return None
+    return int(round(k["fetch_bytes_per_dispatch"] + k["write_bytes_per_dispatch"]))
 
 
 def parse():
@@ -201,8 +224,11 @@ def main():
                 launches += T
         avg_ms = chk_ms.sum() / launches
         achieved = chk_bytes.sum() / launches / (avg_ms * 1e-3) / 1e9
+        traffic = measured_traffic() if flags == 0 else None
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "traffic_note": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0, "
+                                    "copy-calibrated) from " + os.path.relpath(TRAFFIC_RECORD, ROOT),
                     "kernel": "check_rows_kernel (check-node pass, rows of degree <= 8)",
                     "avg_launch_ms": round(avg_ms, 5), "launches": launches,
                     "bytes_per_launch": round(chk_bytes.sum() / launches),

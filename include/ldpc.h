@@ -188,6 +188,98 @@ LDPC_API ldpc_status ldpc_decode_profiled(const ldpc_graph *g, const float *llr_
                                           void *hip_stream, float *check_ms, float *bit_ms,
                                           float *edge_ms);
 
+/* ------------------------------------------------------------------------
+ * Batched decoding with continuous refill.
+ *
+ * An engine decodes frames of several codes (graphs) in one launch sequence.
+ * Each graph gets a pool of frame slots in HBM that keep the per-frame state
+ * of ldpc_decode (channel and posterior LLRs per bit, one message per edge).
+ * Frames are queued per graph; a decode *step* is, over every graph at once,
+ * one check pass and one bit pass (the same arithmetic and order as
+ * ldpc_decode, Algorithm 2's loop body), then the per-frame stop test
+ * (Algorithm 7 syndrome, or max_iter reached), the output of frames that
+ * stopped, and the admission of queued frames into the freed slots.  Frames of
+ * one graph therefore advance at their own pace: a frame's result is
+ * bit-identical to decoding it alone with ldpc_decode and the same flags.
+ * Steps are captured once into a hipGraph and replayed.
+ *
+ * The engine owns its device memory (allocated at creation) and a HIP stream
+ * of default priority; all of its work runs on that stream.  One engine must
+ * not be driven from several host threads at once.
+ * ------------------------------------------------------------------------ */
+typedef struct ldpc_engine ldpc_engine;
+
+/* One queued frame.  All pointers are device pointers on the engine's device. */
+typedef struct {
+    const float *llr;     /* [n] channel LLRs; read when the frame enters a slot */
+    uint8_t *bits;        /* [n] estimate (written when the frame finishes) */
+    uint8_t *ok;          /* 1 byte: 1 iff the estimate is a codeword */
+    int32_t *iters;       /* 1 int32: iterations run (1..max_iter) */
+    float *llr_out;       /* [n] posterior LLRs, or NULL */
+    int32_t *done;        /* int32 counter incremented atomically when the frame finishes, or NULL */
+} ldpc_frame;
+
+typedef struct {
+    int32_t lane_slots;   /* frame slots per wavefront lane: 1, 2 or 4; 0 = 4 */
+    int32_t graph_steps;  /* decode steps per captured hipGraph replay; 0 = 8 */
+    int32_t reserved[6];  /* must be 0 */
+} ldpc_engine_opts;
+
+/*
+ * Create an engine for `ngraphs` graphs (1..32).
+ *  graphs      [ngraphs] graph handles (not HOST_ONLY), all on the current device;
+ *              they must outlive the engine.
+ *  slots       [ngraphs] slot-pool size per graph (>= 1; rounded up to a multiple
+ *              of 64 * lane_slots).
+ *  queue_cap   [ngraphs] queue capacity per graph (>= 1): frames submitted but not
+ *              yet admitted to a slot.
+ *  max_iter    >= 1; flags: LDPC_NO_EARLY_STOP, LDPC_MSG_FP16 / LDPC_MSG_BF16.
+ *  opts        may be NULL.
+ * Errors: INVAL, NOMEM (device memory), DEVICE.
+ */
+LDPC_API ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32_t ngraphs,
+                                        const int32_t *slots, const int32_t *queue_cap,
+                                        int32_t max_iter, uint32_t flags,
+                                        const ldpc_engine_opts *opts, ldpc_engine **out);
+
+/* Release the engine (waits for its stream first).  NULL is a no-op. */
+LDPC_API ldpc_status ldpc_engine_destroy(ldpc_engine *e);
+
+/* Device memory held by the engine, and the rounded slot count of each graph
+ * (slots may be NULL; otherwise [ngraphs]). */
+LDPC_API ldpc_status ldpc_engine_info(const ldpc_engine *e, int64_t *device_bytes, int32_t *slots);
+
+/*
+ * Queue `count` frames (host array of descriptors, copied) for graph `graph`.
+ * If hip_stream is not NULL, the engine waits for work already enqueued on it
+ * (so LLRs produced there are ready) before admitting these frames.
+ * Errors: INVAL (bad index, count < 0, more frames than free queue capacity:
+ * nothing is queued then), DEVICE.
+ */
+LDPC_API ldpc_status ldpc_engine_submit(ldpc_engine *e, int32_t graph, const ldpc_frame *frames,
+                                        int32_t count, void *hip_stream);
+
+/* Free queue capacity of `graph` as of the last ldpc_engine_poll/run. */
+LDPC_API ldpc_status ldpc_engine_capacity(const ldpc_engine *e, int32_t graph, int32_t *free_entries);
+
+/* Enqueue `replays` hipGraph replays (replays * graph_steps decode steps) on the
+ * engine stream and return without waiting. */
+LDPC_API ldpc_status ldpc_engine_step(ldpc_engine *e, int32_t replays);
+
+/*
+ * Wait for the engine stream, then report per graph the frames finished so
+ * far (retired, [ngraphs], may be NULL) and the frames submitted but not yet
+ * finished (pending, [ngraphs], may be NULL).
+ */
+LDPC_API ldpc_status ldpc_engine_poll(ldpc_engine *e, int64_t *retired, int64_t *pending);
+
+/*
+ * Step until every submitted frame has finished or `max_replays` replays have
+ * run (0 = no limit); blocks.  replays_out (may be NULL) receives the number
+ * of replays run.
+ */
+LDPC_API ldpc_status ldpc_engine_run(ldpc_engine *e, int32_t max_replays, int64_t *replays_out);
+
 /* Static string naming a status code. */
 LDPC_API const char *ldpc_status_str(ldpc_status s);
 

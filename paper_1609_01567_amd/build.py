@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libldpc_hip.so")
-SOURCES = ["graph.cpp", "decode.hip"]
+SOURCES = ["graph.cpp", "decode.hip", "engine.hip"]
 ARCH = os.environ.get("LDPC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

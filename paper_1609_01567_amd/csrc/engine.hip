@@ -1,0 +1,840 @@
+// Batched decoding with continuous refill: the ldpc_engine_* entry points.
+//
+// Every graph owns a pool of S frame slots with the same layout as the plain
+// decoder ([n][S] channel/posterior LLRs, [E][S] messages in check-sorted
+// order).  Each slot carries its own iteration count, so frames of one graph
+// sit at different iterations in the same wavefront.  One decode step is
+//
+//   check pass  (all graphs)  iteration t_s+1 of every occupied slot s, and the
+//                             syndrome of its estimate t_s (Algorithm 7)
+//   bit pass    (all graphs)  Lpost / hard decision of iteration t_s+1
+//                             (Algorithm 4), skipped for frames that stop
+//   advance     (all slots)   stop test: estimate t_s passed (early stop) or
+//                             t_s = max_iter; write ok/iters; else t_s += 1
+//   turnover    (listed slots) write the estimate of stopped frames, admit the
+//                             next queued frame of the graph into the slot
+//
+// The check and bit arithmetic (device_common.h) and its order per frame are
+// those of decode.hip, so a frame's outputs do not depend on its neighbours.
+// K steps are captured once into a hipGraph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "device_common.h"
+
+namespace {
+
+using namespace ldpc_dev;
+
+constexpr int kMaxGraphs = 32;
+constexpr int kTurnoverBlocks = 512;
+
+struct EngFrame {   // device mirror of ldpc_frame
+    const float *llr;
+    uint8_t *bits;
+    uint8_t *ok;
+    int32_t *iters;
+    float *llr_out;
+    int32_t *done;
+};
+static_assert(sizeof(EngFrame) == sizeof(ldpc_frame), "ldpc_frame layout");
+
+struct EngGraph {
+    const int32_t *row_ptr, *col_idx, *col_ptr, *csc_to_csr, *class_rows, *hub_chunk_base;
+    int32_t n, S;
+    int32_t class_begin[ldpc::kNumClasses + 1];
+    float *lch, *lpost;
+    void *r;
+    int32_t *slot_q;      // queue index of the frame in the slot, -1 if empty
+    int32_t *slot_t;      // iterations completed by that frame
+    int32_t *fail;        // t of the last estimate whose syndrome failed
+    EngFrame *slot_desc;  // descriptor of the frame in the slot
+    float *aggd, *aggpre;
+    int32_t *aggbits;
+    EngFrame *queue;      // ring of cap entries
+    int32_t cap;
+    int32_t *head, *tail, *retired;   // monotonic counters
+};
+
+struct Prefix {           // offsets of each graph's work items in one launch
+    int32_t count;
+    int32_t p[kMaxGraphs + 1];
+};
+
+__device__ __forceinline__ int find_graph(const Prefix &pre, int x) {
+    int c = 0;
+    while (c + 1 < pre.count && x >= pre.p[c + 1]) c++;
+    return c;
+}
+
+// Frame in slot stops after its estimate t: passed the syndrome (early stop) or t = max_iter.
+__device__ __forceinline__ bool slot_stops(int32_t t, int32_t fail, int32_t T, int32_t early) {
+    return t >= 1 && ((early && fail != t) || t == T);
+}
+
+// ------------------------------------------------------------- check pass
+
+template <int M, int V, int DMAX>
+__global__ __launch_bounds__(256) void eng_check_rows(const EngGraph *__restrict__ graphs, Prefix pre, int32_t cls,
+                                                      int32_t T, int32_t early) {
+    using MT = typename Codec<M>::T;
+    const int lane = threadIdx.x & 63;
+    const int wave = wave_uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (wave >= pre.p[pre.count]) return;
+    const int c = find_graph(pre, wave);
+    const EngGraph &G = graphs[c];
+    const int32_t S = G.S;
+    const int groups = S / (64 * V);
+    const int local = wave - pre.p[c];
+    const int g = local % groups;
+    const int rk = local / groups;
+    const int s0 = (g * 64 + lane) * V;
+
+    int32_t q[V], t[V];
+    load_i32<V>(G.slot_q + s0, q);
+    load_i32<V>(G.slot_t + s0, t);
+    bool lane_active = false, any_first = false;
+    bool first[V], syn_on[V];
+#pragma unroll
+    for (int k = 0; k < V; k++) {
+        const bool act = q[k] >= 0;
+        first[k] = act && t[k] == 0;
+        syn_on[k] = act && t[k] >= 1 && (early || t[k] == T);
+        lane_active |= act;
+        any_first |= first[k];
+    }
+    if (__ballot(lane_active) == 0) return;
+    if (!lane_active) return;
+
+    const int row = wave_uniform(G.class_rows[G.class_begin[cls] + rk]);
+    const int e0 = wave_uniform(G.row_ptr[row]);
+    const int d = wave_uniform(G.row_ptr[row + 1]) - e0;
+    MT *R = static_cast<MT *>(G.r);
+
+    float u[DMAX][V];
+    float suf[DMAX][V];
+    uint32_t neg[V];
+    int syn[V];
+#pragma unroll
+    for (int k = 0; k < V; k++) { neg[k] = 0u; syn[k] = 0; }
+#pragma unroll
+    for (int j = 0; j < DMAX; j++) {
+        if (j < d) {
+            const int v = wave_uniform(G.col_idx[e0 + j]);
+            float lv[V], r[V];
+            load_vec<kF32, V>(G.lpost + size_t(v) * S + s0, lv);
+            if (any_first) {
+                float lc[V];
+                load_vec<kF32, V>(G.lch + size_t(v) * S + s0, lc);
+#pragma unroll
+                for (int k = 0; k < V; k++) if (first[k]) lv[k] = lc[k];
+            }
+            load_vec<M, V>(R + size_t(e0 + j) * S + s0, r);
+#pragma unroll
+            for (int k = 0; k < V; k++) {
+                if (first[k]) r[k] = 0.f;
+                syn[k] ^= (lv[k] < 0.f);
+                const float qv = clamp_msg(lv[k] - r[k]);
+                neg[k] |= uint32_t(qv < 0.f) << j;
+                u[j][k] = tanh_complement(fabsf(qv));
+            }
+        }
+    }
+    float run[V];
+#pragma unroll
+    for (int k = 0; k < V; k++) run[k] = 0.f;
+#pragma unroll
+    for (int j = DMAX - 1; j >= 0; j--) {
+        if (j < d) {
+#pragma unroll
+            for (int k = 0; k < V; k++) {
+                suf[j][k] = run[k];
+                run[k] = dplus(u[j][k], run[k]);
+            }
+        }
+    }
+    uint32_t parity[V];
+#pragma unroll
+    for (int k = 0; k < V; k++) { run[k] = 0.f; parity[k] = __builtin_popcount(neg[k]) & 1u; }
+#pragma unroll
+    for (int j = 0; j < DMAX; j++) {
+        if (j < d) {
+            float out[V];
+#pragma unroll
+            for (int k = 0; k < V; k++) {
+                const float mag = magnitude_from_complement(dplus(run[k], suf[j][k]));
+                const uint32_t sgn = parity[k] ^ ((neg[k] >> j) & 1u);
+                out[k] = sgn ? -mag : mag;
+                run[k] = dplus(run[k], u[j][k]);
+            }
+            store_vec<M, V>(R + size_t(e0 + j) * S + s0, out);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < V; k++)
+        if (syn_on[k] && syn[k] && G.fail[s0 + k] != t[k]) G.fail[s0 + k] = t[k];
+}
+
+// Rows longer than 32 edges: one workgroup of four wavefronts per (row, 64 slots),
+// 32-edge chunks combined through an exclusive prefix/suffix scan in scratch.
+template <int M>
+__global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict__ graphs, Prefix pre, int32_t T,
+                                                     int32_t early) {
+    using MT = typename Codec<M>::T;
+    constexpr int C = ldpc::kHubChunk;
+    __shared__ int32_t total_bits[64];
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_uniform(threadIdx.x >> 6);
+    const int nw = blockDim.x >> 6;
+    if (int(blockIdx.x) >= pre.p[pre.count]) return;
+    const int c = find_graph(pre, blockIdx.x);
+    const EngGraph &G = graphs[c];
+    const int32_t S = G.S;
+    const int groups = S / 64;
+    const int local = blockIdx.x - pre.p[c];
+    const int g = local % groups;
+    const int rk = local / groups;
+    const int s = g * 64 + lane;
+    const int32_t qs = G.slot_q[s], ts = G.slot_t[s];
+    const bool active = qs >= 0;
+    const bool first = active && ts == 0;
+    const bool syn_on = active && ts >= 1 && (early || ts == T);
+    if (__ballot(active) == 0) return;   // same slots in every wavefront: uniform over the block
+
+    const int row = wave_uniform(G.class_rows[G.class_begin[ldpc::kClassHub] + rk]);
+    const int e0 = wave_uniform(G.row_ptr[row]);
+    const int d = wave_uniform(G.row_ptr[row + 1]) - e0;
+    const int nch = (d + C - 1) / C;
+    const int cb = wave_uniform(G.hub_chunk_base[rk]);
+    MT *R = static_cast<MT *>(G.r);
+    const float *L = first ? G.lch : G.lpost;
+
+    for (int ch = wv; ch < nch; ch += nw) {
+        const int j0 = e0 + ch * C;
+        const int dc = min(C, d - ch * C);
+        float agg = 0.f;
+        int32_t bits = 0;
+#pragma unroll
+        for (int jj = 0; jj < C; jj++) {
+            if (jj < dc) {
+                const int v = wave_uniform(G.col_idx[j0 + jj]);
+                const float lv = L[size_t(v) * S + s];
+                const float r = first ? 0.f : Codec<M>::dec(R[size_t(j0 + jj) * S + s]);
+                const float qv = clamp_msg(lv - r);
+                bits ^= int32_t(qv < 0.f) | (int32_t(lv < 0.f) << 1);
+                agg = dplus(agg, tanh_complement(fabsf(qv)));
+            }
+        }
+        G.aggd[size_t(cb + ch) * S + s] = agg;
+        G.aggbits[size_t(cb + ch) * S + s] = bits;
+    }
+    __syncthreads();
+    if (wv == 0) {
+        float pre_d = 0.f;
+        int32_t tot = 0;
+        for (int ch = 0; ch < nch; ch++) {
+            G.aggpre[size_t(cb + ch) * S + s] = pre_d;
+            pre_d = dplus(pre_d, G.aggd[size_t(cb + ch) * S + s]);
+            tot ^= G.aggbits[size_t(cb + ch) * S + s];
+        }
+        float sf = 0.f;
+        for (int ch = nch - 1; ch >= 0; ch--) {
+            const float dcur = G.aggd[size_t(cb + ch) * S + s];
+            G.aggd[size_t(cb + ch) * S + s] = dplus(G.aggpre[size_t(cb + ch) * S + s], sf);
+            sf = dplus(sf, dcur);
+        }
+        total_bits[lane] = tot;
+        if (syn_on && (tot & 2) && G.fail[s] != ts) G.fail[s] = ts;
+    }
+    __syncthreads();
+    const uint32_t parity = uint32_t(total_bits[lane]) & 1u;
+    for (int ch = wv; ch < nch; ch += nw) {
+        const int j0 = e0 + ch * C;
+        const int dc = min(C, d - ch * C);
+        float u[C], sf[C];
+        uint32_t neg = 0u;
+#pragma unroll
+        for (int jj = 0; jj < C; jj++) {
+            if (jj < dc) {
+                const int v = wave_uniform(G.col_idx[j0 + jj]);
+                const float lv = L[size_t(v) * S + s];
+                const float r = first ? 0.f : Codec<M>::dec(R[size_t(j0 + jj) * S + s]);
+                const float qv = clamp_msg(lv - r);
+                neg |= uint32_t(qv < 0.f) << jj;
+                u[jj] = tanh_complement(fabsf(qv));
+            }
+        }
+        float run = 0.f;
+#pragma unroll
+        for (int jj = C - 1; jj >= 0; jj--) {
+            if (jj < dc) {
+                sf[jj] = run;
+                run = dplus(u[jj], run);
+            }
+        }
+        run = G.aggd[size_t(cb + ch) * S + s];
+#pragma unroll
+        for (int jj = 0; jj < C; jj++) {
+            if (jj < dc) {
+                const float mag = magnitude_from_complement(dplus(run, sf[jj]));
+                const uint32_t sgn = parity ^ ((neg >> jj) & 1u);
+                R[size_t(j0 + jj) * S + s] = Codec<M>::enc(sgn ? -mag : mag);
+                run = dplus(run, u[jj]);
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------------- bit pass
+
+template <int M, int V>
+__global__ __launch_bounds__(256) void eng_bit(const EngGraph *__restrict__ graphs, Prefix pre, int32_t T,
+                                               int32_t early, int32_t *__restrict__ list_count) {
+    using MT = typename Codec<M>::T;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *list_count = 0;   // turnover list of this step starts empty
+    const int lane = threadIdx.x & 63;
+    const int wave = wave_uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    if (wave >= pre.p[pre.count]) return;
+    const int c = find_graph(pre, wave);
+    const EngGraph &G = graphs[c];
+    const int32_t S = G.S;
+    const int groups = S / (64 * V);
+    const int local = wave - pre.p[c];
+    const int g = local % groups;
+    const int v = local / groups;
+    const int s0 = (g * 64 + lane) * V;
+
+    int32_t q[V], t[V], f[V];
+    load_i32<V>(G.slot_q + s0, q);
+    load_i32<V>(G.slot_t + s0, t);
+    load_i32<V>(G.fail + s0, f);
+    bool adv[V];
+    bool any = false, all = true;
+#pragma unroll
+    for (int k = 0; k < V; k++) {
+        adv[k] = q[k] >= 0 && !slot_stops(t[k], f[k], T, early);
+        any |= adv[k];
+        all &= adv[k];
+    }
+    if (__ballot(any) == 0) return;
+    if (!any) return;
+
+    const MT *R = static_cast<const MT *>(G.r);
+    float sum[V];
+    load_vec<kF32, V>(G.lch + size_t(v) * S + s0, sum);
+    const int a = wave_uniform(G.col_ptr[v]);
+    const int b = wave_uniform(G.col_ptr[v + 1]);
+    for (int k = a; k < b; k++) {
+        const int e = wave_uniform(G.csc_to_csr[k]);
+        float r[V];
+        load_vec<M, V>(R + size_t(e) * S + s0, r);
+#pragma unroll
+        for (int z = 0; z < V; z++) sum[z] += r[z];
+    }
+    if (all) {
+        store_vec<kF32, V>(G.lpost + size_t(v) * S + s0, sum);
+    } else {
+#pragma unroll
+        for (int k = 0; k < V; k++)
+            if (adv[k]) G.lpost[size_t(v) * S + s0 + k] = sum[k];
+    }
+}
+
+// ------------------------------------------------------ advance / turnover
+
+// One thread per slot: stop test, per-frame results, and the turnover list
+// (stopped frames, and empty slots while the graph has queued frames).
+__global__ __launch_bounds__(256) void eng_advance(const EngGraph *__restrict__ graphs, Prefix pre, int32_t T,
+                                                   int32_t early, int2 *__restrict__ list,
+                                                   int32_t *__restrict__ list_count) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= pre.p[pre.count]) return;
+    const int c = find_graph(pre, x);
+    const EngGraph &G = graphs[c];
+    const int s = x - pre.p[c];
+    const int32_t q = G.slot_q[s];
+    if (q < 0) {
+        if (*G.head < *G.tail) list[atomicAdd(list_count, 1)] = make_int2(c, s);
+        return;
+    }
+    const int32_t t = G.slot_t[s];
+    const int32_t f = G.fail[s];
+    if (slot_stops(t, f, T, early)) {
+        const EngFrame fr = G.slot_desc[s];
+        *fr.ok = (t < T) ? uint8_t(1) : uint8_t(f != T);
+        *fr.iters = t;
+        atomicAdd(G.retired, 1);
+        list[atomicAdd(list_count, 1)] = make_int2(c, s);
+    } else {
+        G.slot_t[s] = t + 1;
+    }
+}
+
+// One workgroup per listed slot: write the stopped frame's estimate (bit = 1
+// iff Lpost < 0, Algorithm 6) and optional posterior, then take the next
+// queued frame of the graph (or leave the slot empty).
+__global__ __launch_bounds__(256) void eng_turnover(const EngGraph *__restrict__ graphs,
+                                                    const int2 *__restrict__ list,
+                                                    const int32_t *__restrict__ list_count) {
+    __shared__ int32_t claim;
+    const int cnt = *list_count;
+    for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
+        const int2 ent = list[i];
+        const EngGraph &G = graphs[ent.x];
+        const int s = ent.y;
+        const int32_t S = G.S, n = G.n;
+        if (G.slot_q[s] >= 0) {
+            const EngFrame fr = G.slot_desc[s];
+            for (int v = threadIdx.x; v < n; v += blockDim.x) {
+                const float x = G.lpost[size_t(v) * S + s];
+                fr.bits[v] = x < 0.f;
+                if (fr.llr_out) fr.llr_out[v] = x;
+            }
+            __threadfence();
+            __syncthreads();
+            if (threadIdx.x == 0 && fr.done) atomicAdd(fr.done, 1);
+        }
+        if (threadIdx.x == 0) {
+            const int32_t tl = *static_cast<volatile int32_t *>(G.tail);
+            int32_t h = *static_cast<volatile int32_t *>(G.head);
+            int32_t got = -1;
+            while (h < tl) {                      // head only grows: the loop ends
+                const int32_t prev = atomicCAS(G.head, h, h + 1);
+                if (prev == h) { got = h; break; }
+                h = prev;
+            }
+            claim = got;
+        }
+        __syncthreads();
+        const int32_t nq = claim;
+        if (nq >= 0) {
+            const EngFrame fr = G.queue[nq % G.cap];
+            for (int v = threadIdx.x; v < n; v += blockDim.x) G.lch[size_t(v) * S + s] = fr.llr[v];
+            if (threadIdx.x == 0) {
+                G.slot_desc[s] = fr;
+                G.slot_t[s] = 0;
+                G.fail[s] = 0;
+                G.slot_q[s] = nq;
+            }
+        } else if (threadIdx.x == 0) {
+            G.slot_q[s] = -1;
+        }
+        __syncthreads();   // `claim` is reused by the next entry
+    }
+}
+
+__global__ void eng_publish(int32_t *tail, int32_t value) { *tail = value; }
+
+}  // namespace
+
+// ===================================================================== host
+
+struct ldpc_engine {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    int32_t ngraphs = 0, T = 0, V = 4, K = 8, msg = kF32;
+    uint32_t flags = 0;
+    bool early = true;
+    std::vector<const ldpc_graph *> graphs;
+    std::vector<int32_t> S, cap;
+    std::vector<EngGraph> hg;
+    void *dmem = nullptr;
+    size_t dbytes = 0;
+    EngGraph *d_graphs = nullptr;
+    int32_t *d_counters = nullptr;   // [ngraphs][3]: head, tail, retired
+    int2 *d_list = nullptr;
+    int32_t *d_list_count = nullptr;
+    ldpc_frame *h_stage = nullptr;   // pinned mirror of every queue ring
+    std::vector<size_t> stage_off;
+    int32_t *h_counters = nullptr;   // pinned copy of d_counters
+    std::vector<int64_t> submitted, head_seen, retired_seen;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    Prefix pre_rows[3], pre_hub, pre_bit, pre_slots;
+    bool has_rows[3] = {false, false, false}, has_hub = false;
+    int64_t bit_waves = 0, hub_blocks = 0, total_slots = 0, row_waves[3] = {0, 0, 0};
+};
+
+namespace {
+
+using ldpc::set_error;
+
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+template <int M, int V>
+void enqueue_step(ldpc_engine *e) {
+    hipStream_t st = e->stream;
+    const int32_t early = e->early ? 1 : 0;
+    if (e->has_rows[0])
+        hipLaunchKernelGGL((eng_check_rows<M, V, 8>), dim3(unsigned((e->row_waves[0] + 3) / 4)), dim3(256), 0, st,
+                           e->d_graphs, e->pre_rows[0], int32_t(ldpc::kClassD8), e->T, early);
+    if (e->has_rows[1])
+        hipLaunchKernelGGL((eng_check_rows<M, (V < 2 ? V : 2), 16>), dim3(unsigned((e->row_waves[1] + 3) / 4)),
+                           dim3(256), 0, st, e->d_graphs, e->pre_rows[1], int32_t(ldpc::kClassD16), e->T, early);
+    if (e->has_rows[2])
+        hipLaunchKernelGGL((eng_check_rows<M, 1, 32>), dim3(unsigned((e->row_waves[2] + 3) / 4)), dim3(256), 0, st,
+                           e->d_graphs, e->pre_rows[2], int32_t(ldpc::kClassD32), e->T, early);
+    if (e->has_hub)
+        hipLaunchKernelGGL((eng_check_hub<M>), dim3(unsigned(e->hub_blocks)), dim3(256), 0, st, e->d_graphs,
+                           e->pre_hub, e->T, early);
+    hipLaunchKernelGGL((eng_bit<M, V>), dim3(unsigned(std::max<int64_t>(1, (e->bit_waves + 3) / 4))), dim3(256), 0,
+                       st, e->d_graphs, e->pre_bit, e->T, early, e->d_list_count);
+    hipLaunchKernelGGL(eng_advance, dim3(unsigned((e->total_slots + 255) / 256)), dim3(256), 0, st, e->d_graphs,
+                       e->pre_slots, e->T, early, e->d_list, e->d_list_count);
+    hipLaunchKernelGGL(eng_turnover, dim3(unsigned(std::min<int64_t>(e->total_slots, kTurnoverBlocks))), dim3(256),
+                       0, st, e->d_graphs, e->d_list, e->d_list_count);
+}
+
+template <int M>
+void enqueue_step_v(ldpc_engine *e) {
+    switch (e->V) {
+        case 1: enqueue_step<M, 1>(e); break;
+        case 2: enqueue_step<M, 2>(e); break;
+        default: enqueue_step<M, 4>(e); break;
+    }
+}
+
+void enqueue_steps(ldpc_engine *e, int steps) {
+    for (int i = 0; i < steps; i++) {
+        switch (e->msg) {
+            case kF16: enqueue_step_v<kF16>(e); break;
+            case kBF16: enqueue_step_v<kBF16>(e); break;
+            default: enqueue_step_v<kF32>(e); break;
+        }
+    }
+}
+
+void destroy_engine(ldpc_engine *e) {
+    if (!e) return;
+    if (e->stream) (void)hipStreamSynchronize(e->stream);
+    if (e->exec) (void)hipGraphExecDestroy(e->exec);
+    if (e->graph) (void)hipGraphDestroy(e->graph);
+    if (e->dmem) (void)hipFree(e->dmem);
+    if (e->h_stage) (void)hipHostFree(e->h_stage);
+    if (e->h_counters) (void)hipHostFree(e->h_counters);
+    if (e->stream) (void)hipStreamDestroy(e->stream);
+    (void)hipGetLastError();
+    delete e;
+}
+
+ldpc_status hip_fail(ldpc_engine *e, const char *what, hipError_t err) {
+    set_error(std::string(what) + ": " + hipGetErrorString(err));
+    (void)hipGetLastError();
+    destroy_engine(e);
+    return err == hipErrorOutOfMemory ? LDPC_E_NOMEM : LDPC_E_DEVICE;
+}
+
+}  // namespace
+
+extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32_t ngraphs, const int32_t *slots,
+                                          const int32_t *queue_cap, int32_t max_iter, uint32_t flags,
+                                          const ldpc_engine_opts *opts, ldpc_engine **out) {
+    if (!out || !graphs || !slots || !queue_cap) { set_error("ldpc_engine_create: NULL argument"); return LDPC_E_INVAL; }
+    if (ngraphs < 1 || ngraphs > kMaxGraphs) { set_error("ldpc_engine_create: ngraphs must be in 1..32"); return LDPC_E_INVAL; }
+    if (max_iter < 1) { set_error("ldpc_engine_create: max_iter must be >= 1"); return LDPC_E_INVAL; }
+    const uint32_t known = LDPC_NO_EARLY_STOP | LDPC_MSG_FP16 | LDPC_MSG_BF16;
+    if ((flags & ~known) || ((flags & LDPC_MSG_FP16) && (flags & LDPC_MSG_BF16))) {
+        set_error("ldpc_engine_create: bad flags");
+        return LDPC_E_INVAL;
+    }
+    int V = 4, K = 8;
+    if (opts) {
+        for (int32_t r : opts->reserved)
+            if (r != 0) { set_error("ldpc_engine_create: reserved options must be 0"); return LDPC_E_INVAL; }
+        if (opts->lane_slots) {
+            if (opts->lane_slots != 1 && opts->lane_slots != 2 && opts->lane_slots != 4) {
+                set_error("ldpc_engine_create: lane_slots must be 1, 2 or 4");
+                return LDPC_E_INVAL;
+            }
+            V = opts->lane_slots;
+        }
+        if (opts->graph_steps < 0 || opts->graph_steps > 1024) {
+            set_error("ldpc_engine_create: graph_steps must be in 0..1024");
+            return LDPC_E_INVAL;
+        }
+        if (opts->graph_steps) K = opts->graph_steps;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) { (void)hipGetLastError(); set_error("ldpc_engine_create: no device"); return LDPC_E_DEVICE; }
+    for (int32_t c = 0; c < ngraphs; c++) {
+        if (!graphs[c] || graphs[c]->host_only || graphs[c]->device != dev) {
+            set_error("ldpc_engine_create: graph " + std::to_string(c) + " is NULL, host-only or on another device");
+            return LDPC_E_INVAL;
+        }
+        if (slots[c] < 1 || queue_cap[c] < 1) {
+            set_error("ldpc_engine_create: slots and queue_cap must be >= 1");
+            return LDPC_E_INVAL;
+        }
+    }
+    ldpc_engine *e = new (std::nothrow) ldpc_engine;
+    if (!e) { set_error("ldpc_engine_create: out of host memory"); return LDPC_E_NOMEM; }
+    e->device = dev;
+    e->ngraphs = ngraphs;
+    e->T = max_iter;
+    e->flags = flags;
+    e->early = !(flags & LDPC_NO_EARLY_STOP);
+    e->msg = (flags & LDPC_MSG_FP16) ? kF16 : (flags & LDPC_MSG_BF16) ? kBF16 : kF32;
+    e->V = V;
+    e->K = K;
+    e->graphs.assign(graphs, graphs + ngraphs);
+    const int32_t unit = 64 * V;
+    const size_t msg_bytes = e->msg == kF32 ? 4 : 2;
+
+    // device layout: per graph state, then counters, turnover list, graph table
+    size_t off = 0;
+    struct Offs { size_t lch, lpost, r, q, t, fail, desc, aggd, aggpre, aggbits, queue; };
+    std::vector<Offs> go(static_cast<size_t>(ngraphs));
+    for (int32_t c = 0; c < ngraphs; c++) {
+        const ldpc_graph *g = graphs[c];
+        const int32_t S = int32_t((int64_t(slots[c]) + unit - 1) / unit * unit);
+        e->S.push_back(S);
+        e->cap.push_back(queue_cap[c]);
+        Offs &o = go[size_t(c)];
+        o.lch = off;     off = al256(off + size_t(g->n) * S * 4);
+        o.lpost = off;   off = al256(off + size_t(g->n) * S * 4);
+        o.r = off;       off = al256(off + size_t(g->E) * S * msg_bytes);
+        o.q = off;       off = al256(off + size_t(S) * 4);
+        o.t = off;       off = al256(off + size_t(S) * 4);
+        o.fail = off;    off = al256(off + size_t(S) * 4);
+        o.desc = off;    off = al256(off + size_t(S) * sizeof(EngFrame));
+        o.aggd = off;    off = al256(off + size_t(g->hub_chunks) * S * 4);
+        o.aggpre = off;  off = al256(off + size_t(g->hub_chunks) * S * 4);
+        o.aggbits = off; off = al256(off + size_t(g->hub_chunks) * S * 4);
+        o.queue = off;   off = al256(off + size_t(queue_cap[c]) * sizeof(EngFrame));
+        e->total_slots += S;
+    }
+    const size_t off_counters = off; off = al256(off + size_t(ngraphs) * 3 * 4);
+    const size_t off_list = off;     off = al256(off + size_t(e->total_slots) * sizeof(int2));
+    const size_t off_lcount = off;   off = al256(off + 4);
+    const size_t off_graphs = off;   off = al256(off + size_t(ngraphs) * sizeof(EngGraph));
+    e->dbytes = off;
+
+    hipError_t err = hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking);
+    if (err != hipSuccess) return hip_fail(e, "ldpc_engine_create: hipStreamCreate", err);
+    err = hipMalloc(&e->dmem, e->dbytes);
+    if (err != hipSuccess) return hip_fail(e, "ldpc_engine_create: hipMalloc", err);
+    char *base = static_cast<char *>(e->dmem);
+    e->d_counters = reinterpret_cast<int32_t *>(base + off_counters);
+    e->d_list = reinterpret_cast<int2 *>(base + off_list);
+    e->d_list_count = reinterpret_cast<int32_t *>(base + off_lcount);
+    e->d_graphs = reinterpret_cast<EngGraph *>(base + off_graphs);
+
+    for (int32_t c = 0; c < ngraphs; c++) {
+        const ldpc_graph *g = graphs[c];
+        const Offs &o = go[size_t(c)];
+        EngGraph G{};
+        G.row_ptr = g->d_row_ptr; G.col_idx = g->d_col_idx; G.col_ptr = g->d_col_ptr;
+        G.csc_to_csr = g->d_csc_to_csr; G.class_rows = g->d_class_rows; G.hub_chunk_base = g->d_hub_chunk_base;
+        G.n = g->n;
+        G.S = e->S[size_t(c)];
+        for (int k = 0; k <= ldpc::kNumClasses; k++) G.class_begin[k] = g->class_begin[k];
+        G.lch = reinterpret_cast<float *>(base + o.lch);
+        G.lpost = reinterpret_cast<float *>(base + o.lpost);
+        G.r = base + o.r;
+        G.slot_q = reinterpret_cast<int32_t *>(base + o.q);
+        G.slot_t = reinterpret_cast<int32_t *>(base + o.t);
+        G.fail = reinterpret_cast<int32_t *>(base + o.fail);
+        G.slot_desc = reinterpret_cast<EngFrame *>(base + o.desc);
+        G.aggd = reinterpret_cast<float *>(base + o.aggd);
+        G.aggpre = reinterpret_cast<float *>(base + o.aggpre);
+        G.aggbits = reinterpret_cast<int32_t *>(base + o.aggbits);
+        G.queue = reinterpret_cast<EngFrame *>(base + o.queue);
+        G.cap = e->cap[size_t(c)];
+        G.head = e->d_counters + 3 * c;
+        G.tail = e->d_counters + 3 * c + 1;
+        G.retired = e->d_counters + 3 * c + 2;
+        e->hg.push_back(G);
+        // every slot starts empty, with defined message state
+        if ((err = hipMemsetAsync(base + o.lch, 0, o.q - o.lch, e->stream)) != hipSuccess ||
+            (err = hipMemsetAsync(G.slot_q, 0xff, size_t(G.S) * 4, e->stream)) != hipSuccess ||
+            (err = hipMemsetAsync(G.slot_t, 0, size_t(G.S) * 4, e->stream)) != hipSuccess ||
+            (err = hipMemsetAsync(G.fail, 0, size_t(G.S) * 4, e->stream)) != hipSuccess)
+            return hip_fail(e, "ldpc_engine_create: hipMemsetAsync", err);
+    }
+    if ((err = hipMemsetAsync(e->d_counters, 0, size_t(ngraphs) * 12, e->stream)) != hipSuccess ||
+        (err = hipMemsetAsync(e->d_list_count, 0, 4, e->stream)) != hipSuccess ||
+        (err = hipMemcpyAsync(e->d_graphs, e->hg.data(), e->hg.size() * sizeof(EngGraph), hipMemcpyHostToDevice,
+                              e->stream)) != hipSuccess)
+        return hip_fail(e, "ldpc_engine_create: initialisation", err);
+
+    // work prefix tables
+    const int vk[3] = {V, V < 2 ? V : 2, 1};
+    for (int k = 0; k < 3; k++) {
+        Prefix &p = e->pre_rows[k];
+        p.count = ngraphs;
+        p.p[0] = 0;
+        for (int32_t c = 0; c < ngraphs; c++) {
+            const ldpc_graph *g = graphs[c];
+            const int64_t rows = g->class_begin[k + 1] - g->class_begin[k];
+            p.p[c + 1] = int32_t(p.p[c] + rows * (e->S[size_t(c)] / (64 * vk[k])));
+        }
+        e->row_waves[k] = p.p[ngraphs];
+        e->has_rows[k] = e->row_waves[k] > 0;
+    }
+    e->pre_hub.count = ngraphs;
+    e->pre_hub.p[0] = 0;
+    e->pre_bit.count = ngraphs;
+    e->pre_bit.p[0] = 0;
+    e->pre_slots.count = ngraphs;
+    e->pre_slots.p[0] = 0;
+    for (int32_t c = 0; c < ngraphs; c++) {
+        const ldpc_graph *g = graphs[c];
+        const int64_t hubs = g->class_begin[ldpc::kClassHub + 1] - g->class_begin[ldpc::kClassHub];
+        e->pre_hub.p[c + 1] = int32_t(e->pre_hub.p[c] + hubs * (e->S[size_t(c)] / 64));
+        e->pre_bit.p[c + 1] = int32_t(e->pre_bit.p[c] + int64_t(g->n) * (e->S[size_t(c)] / (64 * V)));
+        e->pre_slots.p[c + 1] = e->pre_slots.p[c] + e->S[size_t(c)];
+    }
+    e->hub_blocks = e->pre_hub.p[ngraphs];
+    e->has_hub = e->hub_blocks > 0;
+    e->bit_waves = e->pre_bit.p[ngraphs];
+
+    // pinned staging for queue entries and counters
+    size_t stage = 0;
+    for (int32_t c = 0; c < ngraphs; c++) { e->stage_off.push_back(stage); stage += size_t(e->cap[size_t(c)]); }
+    if ((err = hipHostMalloc(reinterpret_cast<void **>(&e->h_stage), stage * sizeof(ldpc_frame), 0)) != hipSuccess ||
+        (err = hipHostMalloc(reinterpret_cast<void **>(&e->h_counters), size_t(ngraphs) * 12, 0)) != hipSuccess)
+        return hip_fail(e, "ldpc_engine_create: hipHostMalloc", err);
+    e->submitted.assign(size_t(ngraphs), 0);
+    e->head_seen.assign(size_t(ngraphs), 0);
+    e->retired_seen.assign(size_t(ngraphs), 0);
+
+    // capture K steps once
+    if ((err = hipStreamSynchronize(e->stream)) != hipSuccess) return hip_fail(e, "ldpc_engine_create: sync", err);
+    if ((err = hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return hip_fail(e, "ldpc_engine_create: hipStreamBeginCapture", err);
+    enqueue_steps(e, e->K);
+    err = hipStreamEndCapture(e->stream, &e->graph);
+    if (err != hipSuccess) return hip_fail(e, "ldpc_engine_create: hipStreamEndCapture", err);
+    if ((err = hipGraphInstantiate(&e->exec, e->graph, nullptr, nullptr, 0)) != hipSuccess)
+        return hip_fail(e, "ldpc_engine_create: hipGraphInstantiate", err);
+    *out = e;
+    return LDPC_OK;
+}
+
+extern "C" ldpc_status ldpc_engine_destroy(ldpc_engine *e) {
+    destroy_engine(e);
+    return LDPC_OK;
+}
+
+extern "C" ldpc_status ldpc_engine_info(const ldpc_engine *e, int64_t *device_bytes, int32_t *slots) {
+    if (!e) { set_error("ldpc_engine_info: NULL engine"); return LDPC_E_INVAL; }
+    if (device_bytes) *device_bytes = int64_t(e->dbytes);
+    if (slots) for (int32_t c = 0; c < e->ngraphs; c++) slots[c] = e->S[size_t(c)];
+    return LDPC_OK;
+}
+
+extern "C" ldpc_status ldpc_engine_capacity(const ldpc_engine *e, int32_t graph, int32_t *free_entries) {
+    if (!e || !free_entries || graph < 0 || graph >= e->ngraphs) { set_error("ldpc_engine_capacity: bad argument"); return LDPC_E_INVAL; }
+    const size_t c = size_t(graph);
+    *free_entries = int32_t(e->cap[c] - (e->submitted[c] - e->head_seen[c]));
+    return LDPC_OK;
+}
+
+extern "C" ldpc_status ldpc_engine_submit(ldpc_engine *e, int32_t graph, const ldpc_frame *frames, int32_t count,
+                                          void *hip_stream) {
+    if (!e || graph < 0 || graph >= e->ngraphs || count < 0 || (count > 0 && !frames)) {
+        set_error("ldpc_engine_submit: bad argument");
+        return LDPC_E_INVAL;
+    }
+    if (count == 0) return LDPC_OK;
+    const size_t c = size_t(graph);
+    const int64_t in_queue = e->submitted[c] - e->head_seen[c];
+    if (in_queue + count > e->cap[c]) {
+        set_error("ldpc_engine_submit: queue of graph " + std::to_string(graph) + " is full (" +
+                  std::to_string(e->cap[c] - in_queue) + " free)");
+        return LDPC_E_INVAL;
+    }
+    if (e->submitted[c] + count > INT32_MAX) { set_error("ldpc_engine_submit: frame counter overflow"); return LDPC_E_UNSUPPORTED; }
+    hipError_t err;
+    if (hip_stream) {
+        hipEvent_t ev;
+        if ((err = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) goto fail;
+        err = hipEventRecord(ev, static_cast<hipStream_t>(hip_stream));
+        if (err == hipSuccess) err = hipStreamWaitEvent(e->stream, ev, 0);
+        (void)hipEventDestroy(ev);
+        if (err != hipSuccess) goto fail;
+    }
+    {
+        const int32_t cap = e->cap[c];
+        ldpc_frame *ring = e->h_stage + e->stage_off[c];
+        EngFrame *dq = e->hg[c].queue;
+        int32_t pos = int32_t(e->submitted[c] % cap);
+        int32_t left = count;
+        const ldpc_frame *src = frames;
+        while (left > 0) {
+            const int32_t chunk = std::min(left, cap - pos);
+            std::memcpy(ring + pos, src, size_t(chunk) * sizeof(ldpc_frame));
+            if ((err = hipMemcpyAsync(dq + pos, ring + pos, size_t(chunk) * sizeof(ldpc_frame), hipMemcpyHostToDevice,
+                                      e->stream)) != hipSuccess)
+                goto fail;
+            src += chunk;
+            left -= chunk;
+            pos = (pos + chunk) % cap;
+        }
+        e->submitted[c] += count;
+        hipLaunchKernelGGL(eng_publish, dim3(1), dim3(1), 0, e->stream, e->hg[c].tail, int32_t(e->submitted[c]));
+        if ((err = hipGetLastError()) != hipSuccess) goto fail;
+    }
+    return LDPC_OK;
+fail:
+    set_error(std::string("ldpc_engine_submit: ") + hipGetErrorString(err));
+    (void)hipGetLastError();
+    return LDPC_E_DEVICE;
+}
+
+extern "C" ldpc_status ldpc_engine_step(ldpc_engine *e, int32_t replays) {
+    if (!e || replays < 0) { set_error("ldpc_engine_step: bad argument"); return LDPC_E_INVAL; }
+    for (int32_t i = 0; i < replays; i++) {
+        const hipError_t err = hipGraphLaunch(e->exec, e->stream);
+        if (err != hipSuccess) {
+            set_error(std::string("ldpc_engine_step: hipGraphLaunch: ") + hipGetErrorString(err));
+            (void)hipGetLastError();
+            return LDPC_E_DEVICE;
+        }
+    }
+    return LDPC_OK;
+}
+
+extern "C" ldpc_status ldpc_engine_poll(ldpc_engine *e, int64_t *retired, int64_t *pending) {
+    if (!e) { set_error("ldpc_engine_poll: NULL engine"); return LDPC_E_INVAL; }
+    hipError_t err = hipMemcpyAsync(e->h_counters, e->d_counters, size_t(e->ngraphs) * 12, hipMemcpyDeviceToHost,
+                                    e->stream);
+    if (err == hipSuccess) err = hipStreamSynchronize(e->stream);
+    if (err != hipSuccess) {
+        set_error(std::string("ldpc_engine_poll: ") + hipGetErrorString(err));
+        (void)hipGetLastError();
+        return LDPC_E_DEVICE;
+    }
+    for (int32_t c = 0; c < e->ngraphs; c++) {
+        e->head_seen[size_t(c)] = e->h_counters[3 * c];
+        e->retired_seen[size_t(c)] = e->h_counters[3 * c + 2];
+        if (retired) retired[c] = e->retired_seen[size_t(c)];
+        if (pending) pending[c] = e->submitted[size_t(c)] - e->retired_seen[size_t(c)];
+    }
+    return LDPC_OK;
+}
+
+extern "C" ldpc_status ldpc_engine_run(ldpc_engine *e, int32_t max_replays, int64_t *replays_out) {
+    if (!e || max_replays < 0) { set_error("ldpc_engine_run: bad argument"); return LDPC_E_INVAL; }
+    int64_t done = 0;
+    for (;;) {
+        ldpc_status st = ldpc_engine_poll(e, nullptr, nullptr);
+        if (st != LDPC_OK) return st;
+        bool finished = true;
+        for (int32_t c = 0; c < e->ngraphs; c++)
+            if (e->retired_seen[size_t(c)] < e->submitted[size_t(c)]) finished = false;
+        if (finished || (max_replays && done >= max_replays)) break;
+        // two replays in flight keep the device busy while the host reads the counters
+        st = ldpc_engine_step(e, done == 0 ? 2 : 1);
+        if (st != LDPC_OK) return st;
+        done += done == 0 ? 2 : 1;
+    }
+    if (replays_out) *replays_out = done;
+    return LDPC_OK;
+}

@@ -30,7 +30,20 @@ GRAPH_HOST_ONLY = 1 << 0
 
 EXPORTED = ("ldpc_graph_create", "ldpc_graph_destroy", "ldpc_graph_info", "ldpc_graph_arrays",
             "ldpc_decode_workspace_size", "ldpc_decode", "ldpc_decode_profiled", "ldpc_status_str",
-            "ldpc_last_error")
+            "ldpc_last_error", "ldpc_engine_create", "ldpc_engine_destroy", "ldpc_engine_info",
+            "ldpc_engine_submit", "ldpc_engine_capacity", "ldpc_engine_step", "ldpc_engine_poll",
+            "ldpc_engine_run")
+
+
+class Frame(ctypes.Structure):
+    """ldpc_frame: device pointers of one queued frame."""
+    _fields_ = [("llr", ctypes.c_void_p), ("bits", ctypes.c_void_p), ("ok", ctypes.c_void_p),
+                ("iters", ctypes.c_void_p), ("llr_out", ctypes.c_void_p), ("done", ctypes.c_void_p)]
+
+
+class EngineOpts(ctypes.Structure):
+    _fields_ = [("lane_slots", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class LdpcError(RuntimeError):
@@ -61,6 +74,17 @@ def load_library():
     lib.ldpc_decode_profiled.argtypes = [P, P, I32, I32, U32, P, P, P, P, P, ctypes.c_size_t, P, P, P, P]
     for f in ("ldpc_graph_create", "ldpc_graph_destroy", "ldpc_graph_info", "ldpc_graph_arrays",
               "ldpc_decode_workspace_size", "ldpc_decode", "ldpc_decode_profiled"):
+        getattr(lib, f).restype = ctypes.c_int
+    lib.ldpc_engine_create.argtypes = [P, I32, P, P, I32, U32, P, ctypes.POINTER(P)]
+    lib.ldpc_engine_destroy.argtypes = [P]
+    lib.ldpc_engine_info.argtypes = [P, P, P]
+    lib.ldpc_engine_submit.argtypes = [P, I32, P, I32, P]
+    lib.ldpc_engine_capacity.argtypes = [P, I32, P]
+    lib.ldpc_engine_step.argtypes = [P, I32]
+    lib.ldpc_engine_poll.argtypes = [P, P, P]
+    lib.ldpc_engine_run.argtypes = [P, I32, P]
+    for f in ("ldpc_engine_create", "ldpc_engine_destroy", "ldpc_engine_info", "ldpc_engine_submit",
+              "ldpc_engine_capacity", "ldpc_engine_step", "ldpc_engine_poll", "ldpc_engine_run"):
         getattr(lib, f).restype = ctypes.c_int
     lib.ldpc_status_str.argtypes = [ctypes.c_int]
     lib.ldpc_status_str.restype = ctypes.c_char_p
@@ -216,3 +240,111 @@ def decode_profiled(graph: Graph, llr, max_iter: int, flags: int = 0, want_llr: 
                                            _np_ptr(bit_ms), _np_ptr(edge_ms)), "ldpc_decode_profiled")
     out._workspace = workspace
     return out, dict(check_ms=check_ms, bit_ms=bit_ms, edge_ms=edge_ms)
+
+
+class Engine:
+    """Batched decoder with continuous refill (ldpc_engine_*) over several graphs."""
+
+    def __init__(self, graphs, slots, queue_cap, max_iter: int, flags: int = 0, lane_slots: int = 0,
+                 graph_steps: int = 0):
+        lib = load_library()
+        self._lib = lib
+        self.graphs = list(graphs)
+        ng = len(self.graphs)
+        hs = (ctypes.c_void_p * ng)(*[g.handle.value for g in self.graphs])
+        sl = np.ascontiguousarray(slots, dtype=np.int32)
+        qc = np.ascontiguousarray(queue_cap, dtype=np.int32)
+        if sl.size != ng or qc.size != ng:
+            raise ValueError("one slot count and one queue capacity per graph")
+        opts = EngineOpts(lane_slots, graph_steps)
+        self._h = ctypes.c_void_p()
+        _check(lib.ldpc_engine_create(hs, ng, _np_ptr(sl), _np_ptr(qc), int(max_iter), int(flags),
+                                      ctypes.byref(opts), ctypes.byref(self._h)), "ldpc_engine_create")
+        self.max_iter, self.flags, self.ngraphs = int(max_iter), int(flags), ng
+        self._keep = []   # tensors referenced by queued frames
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("engine has been closed")
+        return self._h
+
+    def info(self) -> dict:
+        b = ctypes.c_int64()
+        sl = np.zeros(self.ngraphs, np.int32)
+        _check(self._lib.ldpc_engine_info(self.handle, ctypes.byref(b), _np_ptr(sl)), "ldpc_engine_info")
+        return {"device_bytes": int(b.value), "slots": sl.tolist()}
+
+    def capacity(self, graph: int) -> int:
+        v = ctypes.c_int32()
+        _check(self._lib.ldpc_engine_capacity(self.handle, int(graph), ctypes.byref(v)), "ldpc_engine_capacity")
+        return int(v.value)
+
+    def submit(self, graph: int, frames, stream=None):
+        """Queue frames: a sequence of Frame structs (device pointers)."""
+        arr = (Frame * len(frames))(*frames)
+        st = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+        _check(self._lib.ldpc_engine_submit(self.handle, int(graph), arr, len(frames), st), "ldpc_engine_submit")
+
+    def step(self, replays: int = 1):
+        _check(self._lib.ldpc_engine_step(self.handle, int(replays)), "ldpc_engine_step")
+
+    def poll(self):
+        r = np.zeros(self.ngraphs, np.int64)
+        p = np.zeros(self.ngraphs, np.int64)
+        _check(self._lib.ldpc_engine_poll(self.handle, _np_ptr(r), _np_ptr(p)), "ldpc_engine_poll")
+        return r, p
+
+    def run(self, max_replays: int = 0) -> int:
+        n = ctypes.c_int64()
+        _check(self._lib.ldpc_engine_run(self.handle, int(max_replays), ctypes.byref(n)), "ldpc_engine_run")
+        self._keep.clear()
+        return int(n.value)
+
+    def close(self):
+        if self._h:
+            self._lib.ldpc_engine_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def frames_for(llr, bits, ok, iters, llr_out=None, done=None):
+    """Frame descriptors for row f of [F][n] tensors (outputs preallocated)."""
+    F, n = llr.shape
+    out = []
+    for f in range(F):
+        out.append(Frame(llr.data_ptr() + 4 * n * f, bits.data_ptr() + n * f, ok.data_ptr() + f,
+                         iters.data_ptr() + 4 * f,
+                         (llr_out.data_ptr() + 4 * n * f) if llr_out is not None else None,
+                         done.data_ptr() if done is not None else None))
+    return out
+
+
+def decode_batch(engine: Engine, jobs, want_llr: bool = False):
+    """Decode jobs [(graph_index, llr [F][n] float32 CUDA tensor), ...] with `engine`.
+
+    Every frame is queued (the queues must hold them), the engine runs until
+    all have finished, and one DecodeResult per job is returned.
+    """
+    import torch
+    torch.cuda.synchronize()
+    results = []
+    for gi, llr in jobs:
+        if llr.dtype != torch.float32 or not llr.is_cuda or llr.dim() != 2 or not llr.is_contiguous():
+            raise ValueError("llr must be a contiguous float32 CUDA tensor [frames][n]")
+        F, n = llr.shape
+        if n != engine.graphs[gi].n:
+            raise ValueError("llr width does not match the graph")
+        res = DecodeResult(bits=torch.empty((F, n), dtype=torch.uint8, device=llr.device),
+                           ok=torch.empty(F, dtype=torch.uint8, device=llr.device),
+                           iters=torch.empty(F, dtype=torch.int32, device=llr.device),
+                           llr=torch.empty((F, n), dtype=torch.float32, device=llr.device) if want_llr else None)
+        engine.submit(gi, frames_for(llr, res.bits, res.ok, res.iters, res.llr))
+        results.append(res)
+    engine.run()
+    return results

@@ -135,3 +135,27 @@ def test_decode_argument_checks_fail_before_device_work():
     assert lib.ldpc_decode(None, P(8), 1, 5, 0, P(8), P(8), P(8), None, P(256), 1, None) == ldpc.E_INVAL
     # frames == 0 is a no-op even with null buffers
     assert lib.ldpc_decode(g.handle, None, 0, 5, 0, None, None, None, None, None, 0, None) in (ldpc.OK, ldpc.E_INVAL)
+
+
+def test_engine_argument_checks_fail_before_device_work():
+    lib = ldpc.load_library()
+    P = ctypes.c_void_p
+    out = P()
+    one = (ctypes.c_int32 * 1)(64)
+    graphs = (P * 1)(None)
+    assert lib.ldpc_engine_create(None, 1, one, one, 10, 0, None, ctypes.byref(out)) == ldpc.E_INVAL
+    assert lib.ldpc_engine_create(graphs, 0, one, one, 10, 0, None, ctypes.byref(out)) == ldpc.E_INVAL
+    assert lib.ldpc_engine_create(graphs, 33, one, one, 10, 0, None, ctypes.byref(out)) == ldpc.E_INVAL
+    assert lib.ldpc_engine_create(graphs, 1, one, one, 0, 0, None, ctypes.byref(out)) == ldpc.E_INVAL
+    assert lib.ldpc_engine_create(graphs, 1, one, one, 10, ldpc.MSG_FP16 | ldpc.MSG_BF16, None,
+                                  ctypes.byref(out)) == ldpc.E_INVAL
+    bad = ldpc.EngineOpts(3, 0)
+    assert lib.ldpc_engine_create(graphs, 1, one, one, 10, 0, ctypes.byref(bad), ctypes.byref(out)) == ldpc.E_INVAL
+    assert not out
+    for f in ("ldpc_engine_step", "ldpc_engine_poll", "ldpc_engine_run", "ldpc_engine_info"):
+        fn = getattr(lib, f)
+        args = {"ldpc_engine_step": (None, 1), "ldpc_engine_poll": (None, None, None),
+                "ldpc_engine_run": (None, 0, None), "ldpc_engine_info": (None, None, None)}[f]
+        assert fn(*args) == ldpc.E_INVAL
+    assert lib.ldpc_engine_destroy(None) == ldpc.OK
+    assert ctypes.sizeof(ldpc.Frame) == 48

@@ -1,0 +1,149 @@
+"""GPU tests of the batched engine (continuous refill over several codes).
+
+The engine runs each frame with the same per-frame arithmetic and order as
+ldpc_decode, so its outputs must be bit-identical to decoding that frame with
+ldpc_decode alone, whatever else shares the launch; the plain path is itself
+held to the FP64 oracle (test_gpu_parity.py) and the engine is also checked
+against the oracle directly here.
+"""
+import numpy as np
+import pytest
+
+import ldpc_inputs as li
+from parity import compare, gpu_decode
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+
+
+def _announce(name, **kw):
+    print(f"[case] {name} {kw}", flush=True)
+
+
+def _engine_decode(codes, llrs, slots, T, flags=0, lane_slots=0, graph_steps=0, want_llr=True, cap=None):
+    import torch
+    from paper_1609_01567_amd import ldpc
+    graphs = [ldpc.Graph.from_code(c) for c in codes]
+    caps = cap or [max(1, x.shape[0]) for x in llrs]
+    eng = ldpc.Engine(graphs, slots, caps, T, flags=flags, lane_slots=lane_slots, graph_steps=graph_steps)
+    jobs = [(i, torch.from_numpy(np.ascontiguousarray(x)).cuda()) for i, x in enumerate(llrs)]
+    res = ldpc.decode_batch(eng, jobs, want_llr=want_llr)
+    torch.cuda.synchronize()
+    out = [dict(bits=r.bits.cpu().numpy(), ok=r.ok.cpu().numpy(), iters=r.iters.cpu().numpy(),
+                lpost=r.llr.cpu().numpy() if r.llr is not None else None) for r in res]
+    eng.close()
+    return out
+
+
+def _assert_same(a, b, what):
+    for k in ("bits", "ok", "iters", "lpost"):
+        if a.get(k) is None or b.get(k) is None:
+            continue
+        assert (a[k] == b[k]).all(), f"{what}: {k} differs"
+
+
+def test_engine_all_frames_at_once_equals_plain():
+    code = li.tiny_code()
+    llr = li.awgn_llr(code.n, 32, li.ebn0_to_sigma2(2.0, code.rate), seed=2001)
+    _announce("engine-once", frames=32)
+    eng = _engine_decode([code], [llr], [64], 50)[0]
+    plain = gpu_decode(code, llr, 50)
+    _assert_same(eng, plain, "engine vs plain")
+
+
+@pytest.mark.parametrize("lane_slots", [1, 2, 4])
+def test_engine_refill_equals_plain(lane_slots):
+    code = li.random_small_code(600, 300, 3, seed=8)
+    llr = li.awgn_llr(code.n, 700, li.ebn0_to_sigma2(1.2, code.rate), seed=9)
+    _announce("engine-refill", frames=700, lane_slots=lane_slots)
+    eng = _engine_decode([code], [llr], [64 * lane_slots], 30, lane_slots=lane_slots, graph_steps=5)[0]
+    plain = gpu_decode(code, llr, 30)
+    _assert_same(eng, plain, "engine refill vs plain")
+    compare(code, llr[:96], 30, gpu={k: v[:96] for k, v in eng.items()})
+
+
+def test_engine_mixed_codes_each_frame_as_alone():
+    """Uneven codes (all check-degree classes, rows up to 300 edges) in one engine."""
+    rng = np.random.default_rng(11)
+    cdeg = np.concatenate([[300, 140, 64, 40, 33], rng.integers(3, 33, size=95)])
+    E = int(cdeg.sum())
+    bdeg = np.full(700, E // 700)
+    bdeg[: E - bdeg.sum()] += 1
+    hub = li.socket_code(bdeg, cdeg, seed=12)
+    codes = [li.tiny_code(), hub, li.random_small_code(300, 150, 3, seed=31), li.code_14_7()]
+    frames = [150, 70, 333, 40]
+    snr = [2.0, None, 1.5, None]
+    llrs = []
+    for i, (c, f) in enumerate(zip(codes, frames)):
+        s2 = li.ebn0_to_sigma2(snr[i], c.rate) if snr[i] else 0.7
+        llrs.append(li.awgn_llr(c.n, f, s2, seed=50 + i))
+    _announce("engine-mixed", frames=frames)
+    out = _engine_decode(codes, llrs, [64, 64, 128, 64], 25, graph_steps=3)
+    for c, x, o in zip(codes, llrs, out):
+        _assert_same(o, gpu_decode(c, x, 25), f"mixed {c.name}")
+    compare(codes[1], llrs[1], 25, gpu=out[1])
+
+
+@pytest.mark.parametrize("msg", ["fp16", "bf16"])
+def test_engine_reduced_precision_equals_plain(msg):
+    from paper_1609_01567_amd import ldpc
+    flag = ldpc.MSG_FP16 if msg == "fp16" else ldpc.MSG_BF16
+    code = li.random_small_code(500, 250, 3, seed=5)
+    llr = li.awgn_llr(code.n, 300, li.ebn0_to_sigma2(1.5, code.rate), seed=6)
+    _announce("engine-precision", msg=msg)
+    eng = _engine_decode([code], [llr], [128], 40, flags=flag)[0]
+    plain = gpu_decode(code, llr, 40, flags=flag)
+    _assert_same(eng, plain, f"engine {msg} vs plain")
+
+
+def test_engine_no_early_stop_and_max_iter_one():
+    from paper_1609_01567_amd import ldpc
+    code = li.tiny_code()
+    llr = li.awgn_llr(code.n, 100, li.ebn0_to_sigma2(1.5, code.rate), seed=3)
+    _announce("engine-no-early-stop")
+    for T in (1, 7):
+        eng = _engine_decode([code], [llr], [64], T, flags=ldpc.NO_EARLY_STOP)[0]
+        assert (eng["iters"] == T).all()
+        _assert_same(eng, gpu_decode(code, llr, T, flags=ldpc.NO_EARLY_STOP), f"no early stop T={T}")
+
+
+def test_engine_queue_backpressure_and_incremental_submit():
+    import torch
+    from paper_1609_01567_amd import ldpc
+    code = li.random_small_code(300, 150, 3, seed=31)
+    llr = li.awgn_llr(code.n, 200, li.ebn0_to_sigma2(1.5, code.rate), seed=77)
+    _announce("engine-backpressure")
+    g = ldpc.Graph.from_code(code)
+    eng = ldpc.Engine([g], [64], [50], 30, graph_steps=2)
+    x = torch.from_numpy(llr).cuda()
+    bits = torch.empty((200, code.n), dtype=torch.uint8, device="cuda")
+    ok = torch.empty(200, dtype=torch.uint8, device="cuda")
+    it = torch.empty(200, dtype=torch.int32, device="cuda")
+    done = torch.zeros(1, dtype=torch.int32, device="cuda")
+    fr = ldpc.frames_for(x, bits, ok, it, done=done)
+    with pytest.raises(ldpc.LdpcError):
+        eng.submit(0, fr[:51])                     # more than the queue holds
+    sent = 0
+    while sent < 200:
+        free = eng.capacity(0)
+        k = min(free, 200 - sent)
+        if k > 0:
+            eng.submit(0, fr[sent:sent + k])
+            sent += k
+        eng.step(1)
+        eng.poll()
+    eng.run()
+    torch.cuda.synchronize()
+    assert int(done.item()) == 200
+    ref = gpu_decode(code, llr, 30)
+    assert (bits.cpu().numpy() == ref["bits"]).all()
+    assert (it.cpu().numpy() == ref["iters"]).all() and (ok.cpu().numpy() == ref["ok"]).all()
+    r, p = eng.poll()
+    assert r.tolist() == [200] and p.tolist() == [0]
+    eng.close()

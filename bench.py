@@ -64,6 +64,9 @@ def parse():
     ap.add_argument("--cpu-frames", type=int, default=16, help="oracle sample: frames per Eb/N0 point")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--engine-slots", type=str, default="256,512",
+                    help="slot-pool sizes tried for the refill engine on the same workload")
+    ap.add_argument("--no-engine", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates rocprof byte counters) and exit")
     return ap.parse_args()
@@ -127,6 +130,38 @@ def cpu_baseline(code, llrs, T, frames_per_point):
             "sample": f"{frames_per_point} frames at each of {len(llrs)} Eb/N0 points of the same workload "
                       f"({nf} frames, {float(np.concatenate(iters).mean()):.1f} mean iterations), FP64 C oracle, "
                       f"{dt:.1f} s wall"}
+
+
+def engine_large(torch, ldpc, g, d_llr, T, flags, slots, steps, warmup, graph_steps=8):
+    """The same frames through the refill engine (one graph, `slots` slots)."""
+    F = sum(x.shape[0] for x in d_llr)
+    n = g.n
+    eng = ldpc.Engine([g], [slots], [F], T, flags=flags & (ldpc.MSG_FP16 | ldpc.MSG_BF16),
+                      lane_slots=4, graph_steps=graph_steps)
+    bits = torch.empty((F, n), dtype=torch.uint8, device="cuda")
+    ok = torch.empty(F, dtype=torch.uint8, device="cuda")
+    it = torch.empty(F, dtype=torch.int32, device="cuda")
+    llr_all = torch.cat(d_llr, 0).contiguous()
+    frames = ldpc.frames_for(llr_all, bits, ok, it)
+    torch.cuda.synchronize()
+
+    def one():
+        eng.submit(0, frames)
+        return eng.run()
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    replays = 0
+    for _ in range(steps):
+        replays += one()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    out = {"slots": eng.info()["slots"][0], "ms_per_step": round(ms, 3), "replays_per_step": replays / steps,
+           "graph_steps": graph_steps, "iters": it.cpu().numpy(), "ok": ok.cpu().numpy()}
+    eng.close()
+    return out
 
 
 def main():
@@ -239,6 +274,20 @@ def main():
                  "bit_achieved_gbs": round(bit_bytes.sum() / (bit_ms.sum() * 1e-3) / 1e9, 1)}
         print(f"[bench] profiled pass done", file=sys.stderr, flush=True)
 
+    engine = None
+    if not args.no_engine:
+        tries = []
+        for sl in [int(x) for x in args.engine_slots.split(",") if x]:
+            r = engine_large(torch, ldpc, g, d_llr, T, flags, sl, args.steps, args.warmup)
+            ref_it = np.concatenate([o.iters.cpu().numpy() for o in outs])
+            same = bool((r["iters"] == ref_it).all())
+            tries.append({"slots": r["slots"], "ms_per_step": r["ms_per_step"],
+                          "gbits": round(frames_per_step * k / (r["ms_per_step"] * 1e-3) / 1e9, 4),
+                          "replays_per_step": r["replays_per_step"], "iters_equal_plain": same})
+        engine = {"note": "same 1024 frames per step through the refill engine (ldpc_engine_*); wall clock "
+                          "includes submission and host polling", "tries": tries}
+        print(f"[bench] engine done", file=sys.stderr, flush=True)
+
     ceiling = copy_ceiling(torch)
     cpu = None
     if not args.no_cpu_baseline:
@@ -267,6 +316,7 @@ def main():
         "per_point": per_point,
         "roofline": roofline,
         "phases": phase,
+        "engine_same_workload": engine,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -33,7 +33,8 @@ namespace {
 using namespace ldpc_dev;
 
 constexpr int kMaxGraphs = 32;
-constexpr int kTurnoverBlocks = 512;
+constexpr int kTurnoverBlocks = 1024;
+constexpr int kTurnChunk = 2048;   // bits per turnover workgroup (256 threads x 8)
 
 struct EngFrame {   // device mirror of ldpc_frame
     const float *llr;
@@ -60,6 +61,10 @@ struct EngGraph {
     EngFrame *queue;      // ring of cap entries
     int32_t cap;
     int32_t *head, *tail, *retired;   // monotonic counters
+    int32_t *list;        // turnover list of this step: slot | (stopped << 31)
+    int32_t *list_count;
+    int32_t *taken;       // frames admitted by this step's turnover (applied to head next step)
+    int32_t chunks;       // ceil(n / kTurnChunk)
 };
 
 struct Prefix {           // offsets of each graph's work items in one launch
@@ -295,9 +300,16 @@ __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict_
 
 template <int M, int V>
 __global__ __launch_bounds__(256) void eng_bit(const EngGraph *__restrict__ graphs, Prefix pre, int32_t T,
-                                               int32_t early, int32_t *__restrict__ list_count) {
+                                               int32_t early) {
     using MT = typename Codec<M>::T;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *list_count = 0;   // turnover list of this step starts empty
+    // The previous step's turnover and admission are complete: move each
+    // graph's queue head past the frames it admitted and empty its list.
+    if (blockIdx.x == 0 && threadIdx.x < pre.count) {
+        const EngGraph &H = graphs[threadIdx.x];
+        *H.head += *H.taken;
+        *H.taken = 0;
+        *H.list_count = 0;
+    }
     const int lane = threadIdx.x & 63;
     const int wave = wave_uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     if (wave >= pre.p[pre.count]) return;
@@ -348,11 +360,10 @@ __global__ __launch_bounds__(256) void eng_bit(const EngGraph *__restrict__ grap
 
 // ------------------------------------------------------ advance / turnover
 
-// One thread per slot: stop test, per-frame results, and the turnover list
-// (stopped frames, and empty slots while the graph has queued frames).
+// One thread per slot: stop test, per-frame results, and the graph's turnover
+// list (stopped frames, and empty slots while the graph has queued frames).
 __global__ __launch_bounds__(256) void eng_advance(const EngGraph *__restrict__ graphs, Prefix pre, int32_t T,
-                                                   int32_t early, int2 *__restrict__ list,
-                                                   int32_t *__restrict__ list_count) {
+                                                   int32_t early) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= pre.p[pre.count]) return;
     const int c = find_graph(pre, x);
@@ -360,7 +371,7 @@ __global__ __launch_bounds__(256) void eng_advance(const EngGraph *__restrict__ 
     const int s = x - pre.p[c];
     const int32_t q = G.slot_q[s];
     if (q < 0) {
-        if (*G.head < *G.tail) list[atomicAdd(list_count, 1)] = make_int2(c, s);
+        if (*G.head < *G.tail) G.list[atomicAdd(G.list_count, 1)] = s;
         return;
     }
     const int32_t t = G.slot_t[s];
@@ -370,62 +381,100 @@ __global__ __launch_bounds__(256) void eng_advance(const EngGraph *__restrict__ 
         *fr.ok = (t < T) ? uint8_t(1) : uint8_t(f != T);
         *fr.iters = t;
         atomicAdd(G.retired, 1);
-        list[atomicAdd(list_count, 1)] = make_int2(c, s);
+        G.list[atomicAdd(G.list_count, 1)] = s | int32_t(0x80000000u);
     } else {
         G.slot_t[s] = t + 1;
     }
 }
 
-// One workgroup per listed slot: write the stopped frame's estimate (bit = 1
-// iff Lpost < 0, Algorithm 6) and optional posterior, then take the next
-// queued frame of the graph (or leave the slot empty).
-__global__ __launch_bounds__(256) void eng_turnover(const EngGraph *__restrict__ graphs,
-                                                    const int2 *__restrict__ list,
-                                                    const int32_t *__restrict__ list_count) {
-    __shared__ int32_t claim;
-    const int cnt = *list_count;
-    for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
-        const int2 ent = list[i];
-        const EngGraph &G = graphs[ent.x];
-        const int s = ent.y;
+// Listed slot i of graph c, bits [ch * kTurnChunk, +kTurnChunk): write the
+// stopped frame's estimate (bit = 1 iff Lpost < 0, Algorithm 6) and optional
+// posterior, and copy the channel LLRs of the frame admitted into the slot
+// (queue entry head + i, if there is one).  Many workgroups per slot.
+__global__ __launch_bounds__(256) void eng_turnover(const EngGraph *__restrict__ graphs, int32_t ngraphs) {
+    __shared__ int32_t base[kMaxGraphs + 1];
+    if (threadIdx.x == 0) {
+        base[0] = 0;
+        for (int c = 0; c < ngraphs; c++) {
+            const EngGraph &H = graphs[c];
+            base[c + 1] = base[c] + *H.list_count * H.chunks;
+            // the tail is constant within a step: this is the number admitted now
+            if (blockIdx.x == 0) *H.taken = min(*H.list_count, *H.tail - *H.head);
+        }
+    }
+    __syncthreads();
+    const int total = base[ngraphs];
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        int c = 0;
+        while (c + 1 < ngraphs && u >= base[c + 1]) c++;
+        const EngGraph &G = graphs[c];
+        const int local = u - base[c];
+        const int i = local / G.chunks;
+        const int ch = local - i * G.chunks;
+        const int32_t ent = G.list[i];
+        const int s = ent & 0x7fffffff;
+        const bool stopped = ent < 0;
         const int32_t S = G.S, n = G.n;
-        if (G.slot_q[s] >= 0) {
+        const int v0 = ch * kTurnChunk + threadIdx.x;
+        if (stopped) {
             const EngFrame fr = G.slot_desc[s];
-            for (int v = threadIdx.x; v < n; v += blockDim.x) {
-                const float x = G.lpost[size_t(v) * S + s];
-                fr.bits[v] = x < 0.f;
-                if (fr.llr_out) fr.llr_out[v] = x;
+            float x[kTurnChunk / 256];
+#pragma unroll
+            for (int j = 0; j < kTurnChunk / 256; j++) {
+                const int v = v0 + j * 256;
+                x[j] = v < n ? G.lpost[size_t(v) * S + s] : 0.f;
             }
-            __threadfence();
-            __syncthreads();
-            if (threadIdx.x == 0 && fr.done) atomicAdd(fr.done, 1);
-        }
-        if (threadIdx.x == 0) {
-            const int32_t tl = *static_cast<volatile int32_t *>(G.tail);
-            int32_t h = *static_cast<volatile int32_t *>(G.head);
-            int32_t got = -1;
-            while (h < tl) {                      // head only grows: the loop ends
-                const int32_t prev = atomicCAS(G.head, h, h + 1);
-                if (prev == h) { got = h; break; }
-                h = prev;
+#pragma unroll
+            for (int j = 0; j < kTurnChunk / 256; j++) {
+                const int v = v0 + j * 256;
+                if (v < n) {
+                    fr.bits[v] = x[j] < 0.f;
+                    if (fr.llr_out) fr.llr_out[v] = x[j];
+                }
             }
-            claim = got;
         }
-        __syncthreads();
-        const int32_t nq = claim;
-        if (nq >= 0) {
-            const EngFrame fr = G.queue[nq % G.cap];
-            for (int v = threadIdx.x; v < n; v += blockDim.x) G.lch[size_t(v) * S + s] = fr.llr[v];
-            if (threadIdx.x == 0) {
-                G.slot_desc[s] = fr;
-                G.slot_t[s] = 0;
-                G.fail[s] = 0;
-                G.slot_q[s] = nq;
+        const int32_t qi = *G.head + i;
+        if (qi < *G.tail) {   // same test as min(list_count, tail - head) > i
+            const float *src = G.queue[qi % G.cap].llr;
+            float x[kTurnChunk / 256];
+#pragma unroll
+            for (int j = 0; j < kTurnChunk / 256; j++) {
+                const int v = v0 + j * 256;
+                x[j] = v < n ? src[v] : 0.f;
             }
-        } else if (threadIdx.x == 0) {
-            G.slot_q[s] = -1;
+#pragma unroll
+            for (int j = 0; j < kTurnChunk / 256; j++) {
+                const int v = v0 + j * 256;
+                if (v < n) G.lch[size_t(v) * S + s] = x[j];
+            }
         }
-        __syncthreads();   // `claim` is reused by the next entry
+    }
+}
+
+// One thread per listed slot, after the turnover: count the stopped frame as
+// done (its outputs are complete) and install the admitted frame, or leave the
+// slot empty when the graph's queue ran dry.
+__global__ __launch_bounds__(256) void eng_admit(const EngGraph *__restrict__ graphs, Prefix pre) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= pre.p[pre.count]) return;
+    const int c = find_graph(pre, x);
+    const EngGraph &G = graphs[c];
+    const int i = x - pre.p[c];
+    if (i >= *G.list_count) return;
+    const int32_t ent = G.list[i];
+    const int s = ent & 0x7fffffff;
+    if (ent < 0) {
+        const EngFrame old = G.slot_desc[s];
+        if (old.done) atomicAdd(old.done, 1);
+    }
+    const int32_t qi = *G.head + i;
+    if (i < *G.taken) {
+        G.slot_desc[s] = G.queue[qi % G.cap];
+        G.slot_t[s] = 0;
+        G.fail[s] = 0;
+        G.slot_q[s] = qi;
+    } else {
+        G.slot_q[s] = -1;
     }
 }
 
@@ -447,9 +496,7 @@ struct ldpc_engine {
     void *dmem = nullptr;
     size_t dbytes = 0;
     EngGraph *d_graphs = nullptr;
-    int32_t *d_counters = nullptr;   // [ngraphs][3]: head, tail, retired
-    int2 *d_list = nullptr;
-    int32_t *d_list_count = nullptr;
+    int32_t *d_counters = nullptr;   // [ngraphs][4]: head, tail, retired, list count; then [ngraphs] taken
     ldpc_frame *h_stage = nullptr;   // pinned mirror of every queue ring
     std::vector<size_t> stage_off;
     int32_t *h_counters = nullptr;   // pinned copy of d_counters
@@ -484,11 +531,11 @@ void enqueue_step(ldpc_engine *e) {
         hipLaunchKernelGGL((eng_check_hub<M>), dim3(unsigned(e->hub_blocks)), dim3(256), 0, st, e->d_graphs,
                            e->pre_hub, e->T, early);
     hipLaunchKernelGGL((eng_bit<M, V>), dim3(unsigned(std::max<int64_t>(1, (e->bit_waves + 3) / 4))), dim3(256), 0,
-                       st, e->d_graphs, e->pre_bit, e->T, early, e->d_list_count);
-    hipLaunchKernelGGL(eng_advance, dim3(unsigned((e->total_slots + 255) / 256)), dim3(256), 0, st, e->d_graphs,
-                       e->pre_slots, e->T, early, e->d_list, e->d_list_count);
-    hipLaunchKernelGGL(eng_turnover, dim3(unsigned(std::min<int64_t>(e->total_slots, kTurnoverBlocks))), dim3(256),
-                       0, st, e->d_graphs, e->d_list, e->d_list_count);
+                       st, e->d_graphs, e->pre_bit, e->T, early);
+    const unsigned slot_blocks = unsigned((e->total_slots + 255) / 256);
+    hipLaunchKernelGGL(eng_advance, dim3(slot_blocks), dim3(256), 0, st, e->d_graphs, e->pre_slots, e->T, early);
+    hipLaunchKernelGGL(eng_turnover, dim3(unsigned(kTurnoverBlocks)), dim3(256), 0, st, e->d_graphs, e->ngraphs);
+    hipLaunchKernelGGL(eng_admit, dim3(slot_blocks), dim3(256), 0, st, e->d_graphs, e->pre_slots);
 }
 
 template <int M>
@@ -588,7 +635,7 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
 
     // device layout: per graph state, then counters, turnover list, graph table
     size_t off = 0;
-    struct Offs { size_t lch, lpost, r, q, t, fail, desc, aggd, aggpre, aggbits, queue; };
+    struct Offs { size_t lch, lpost, r, q, t, fail, desc, aggd, aggpre, aggbits, queue, list; };
     std::vector<Offs> go(static_cast<size_t>(ngraphs));
     for (int32_t c = 0; c < ngraphs; c++) {
         const ldpc_graph *g = graphs[c];
@@ -607,11 +654,10 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
         o.aggpre = off;  off = al256(off + size_t(g->hub_chunks) * S * 4);
         o.aggbits = off; off = al256(off + size_t(g->hub_chunks) * S * 4);
         o.queue = off;   off = al256(off + size_t(queue_cap[c]) * sizeof(EngFrame));
+        o.list = off;    off = al256(off + size_t(S) * 4);
         e->total_slots += S;
     }
-    const size_t off_counters = off; off = al256(off + size_t(ngraphs) * 3 * 4);
-    const size_t off_list = off;     off = al256(off + size_t(e->total_slots) * sizeof(int2));
-    const size_t off_lcount = off;   off = al256(off + 4);
+    const size_t off_counters = off; off = al256(off + size_t(ngraphs) * 5 * 4);
     const size_t off_graphs = off;   off = al256(off + size_t(ngraphs) * sizeof(EngGraph));
     e->dbytes = off;
 
@@ -621,8 +667,6 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
     if (err != hipSuccess) return hip_fail(e, "ldpc_engine_create: hipMalloc", err);
     char *base = static_cast<char *>(e->dmem);
     e->d_counters = reinterpret_cast<int32_t *>(base + off_counters);
-    e->d_list = reinterpret_cast<int2 *>(base + off_list);
-    e->d_list_count = reinterpret_cast<int32_t *>(base + off_lcount);
     e->d_graphs = reinterpret_cast<EngGraph *>(base + off_graphs);
 
     for (int32_t c = 0; c < ngraphs; c++) {
@@ -646,9 +690,13 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
         G.aggbits = reinterpret_cast<int32_t *>(base + o.aggbits);
         G.queue = reinterpret_cast<EngFrame *>(base + o.queue);
         G.cap = e->cap[size_t(c)];
-        G.head = e->d_counters + 3 * c;
-        G.tail = e->d_counters + 3 * c + 1;
-        G.retired = e->d_counters + 3 * c + 2;
+        G.head = e->d_counters + 4 * c;
+        G.tail = e->d_counters + 4 * c + 1;
+        G.retired = e->d_counters + 4 * c + 2;
+        G.list_count = e->d_counters + 4 * c + 3;
+        G.taken = e->d_counters + 4 * c + 4 * ngraphs;
+        G.list = reinterpret_cast<int32_t *>(base + o.list);
+        G.chunks = (g->n + kTurnChunk - 1) / kTurnChunk;
         e->hg.push_back(G);
         // every slot starts empty, with defined message state
         if ((err = hipMemsetAsync(base + o.lch, 0, o.q - o.lch, e->stream)) != hipSuccess ||
@@ -657,8 +705,7 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
             (err = hipMemsetAsync(G.fail, 0, size_t(G.S) * 4, e->stream)) != hipSuccess)
             return hip_fail(e, "ldpc_engine_create: hipMemsetAsync", err);
     }
-    if ((err = hipMemsetAsync(e->d_counters, 0, size_t(ngraphs) * 12, e->stream)) != hipSuccess ||
-        (err = hipMemsetAsync(e->d_list_count, 0, 4, e->stream)) != hipSuccess ||
+    if ((err = hipMemsetAsync(e->d_counters, 0, size_t(ngraphs) * 20, e->stream)) != hipSuccess ||
         (err = hipMemcpyAsync(e->d_graphs, e->hg.data(), e->hg.size() * sizeof(EngGraph), hipMemcpyHostToDevice,
                               e->stream)) != hipSuccess)
         return hip_fail(e, "ldpc_engine_create: initialisation", err);
@@ -698,7 +745,7 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
     size_t stage = 0;
     for (int32_t c = 0; c < ngraphs; c++) { e->stage_off.push_back(stage); stage += size_t(e->cap[size_t(c)]); }
     if ((err = hipHostMalloc(reinterpret_cast<void **>(&e->h_stage), stage * sizeof(ldpc_frame), 0)) != hipSuccess ||
-        (err = hipHostMalloc(reinterpret_cast<void **>(&e->h_counters), size_t(ngraphs) * 12, 0)) != hipSuccess)
+        (err = hipHostMalloc(reinterpret_cast<void **>(&e->h_counters), size_t(ngraphs) * 20, 0)) != hipSuccess)
         return hip_fail(e, "ldpc_engine_create: hipHostMalloc", err);
     e->submitted.assign(size_t(ngraphs), 0);
     e->head_seen.assign(size_t(ngraphs), 0);
@@ -803,7 +850,7 @@ extern "C" ldpc_status ldpc_engine_step(ldpc_engine *e, int32_t replays) {
 
 extern "C" ldpc_status ldpc_engine_poll(ldpc_engine *e, int64_t *retired, int64_t *pending) {
     if (!e) { set_error("ldpc_engine_poll: NULL engine"); return LDPC_E_INVAL; }
-    hipError_t err = hipMemcpyAsync(e->h_counters, e->d_counters, size_t(e->ngraphs) * 12, hipMemcpyDeviceToHost,
+    hipError_t err = hipMemcpyAsync(e->h_counters, e->d_counters, size_t(e->ngraphs) * 20, hipMemcpyDeviceToHost,
                                     e->stream);
     if (err == hipSuccess) err = hipStreamSynchronize(e->stream);
     if (err != hipSuccess) {
@@ -812,8 +859,9 @@ extern "C" ldpc_status ldpc_engine_poll(ldpc_engine *e, int64_t *retired, int64_
         return LDPC_E_DEVICE;
     }
     for (int32_t c = 0; c < e->ngraphs; c++) {
-        e->head_seen[size_t(c)] = e->h_counters[3 * c];
-        e->retired_seen[size_t(c)] = e->h_counters[3 * c + 2];
+        // admissions of the last step are applied to head at the start of the next step
+        e->head_seen[size_t(c)] = int64_t(e->h_counters[4 * c]) + e->h_counters[4 * e->ngraphs + c];
+        e->retired_seen[size_t(c)] = e->h_counters[4 * c + 2];
         if (retired) retired[c] = e->retired_seen[size_t(c)];
         if (pending) pending[c] = e->submitted[size_t(c)] - e->retired_seen[size_t(c)];
     }

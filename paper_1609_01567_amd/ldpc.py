@@ -325,11 +325,12 @@ def frames_for(llr, bits, ok, iters, llr_out=None, done=None):
     return out
 
 
-def decode_batch(engine: Engine, jobs, want_llr: bool = False):
+def decode_batch(engine: Engine, jobs, want_llr: bool = False, max_replays: int = 0):
     """Decode jobs [(graph_index, llr [F][n] float32 CUDA tensor), ...] with `engine`.
 
     Every frame is queued (the queues must hold them), the engine runs until
-    all have finished, and one DecodeResult per job is returned.
+    all have finished (or max_replays replays; then LdpcError), and one
+    DecodeResult per job is returned.
     """
     import torch
     torch.cuda.synchronize()
@@ -346,5 +347,8 @@ def decode_batch(engine: Engine, jobs, want_llr: bool = False):
                            llr=torch.empty((F, n), dtype=torch.float32, device=llr.device) if want_llr else None)
         engine.submit(gi, frames_for(llr, res.bits, res.ok, res.iters, res.llr))
         results.append(res)
-    engine.run()
+    engine.run(max_replays)
+    _, pending = engine.poll()
+    if pending.any():
+        raise LdpcError(E_DEVICE, "decode_batch", f"frames still pending after {max_replays} replays: {pending}")
     return results

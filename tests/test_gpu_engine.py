@@ -33,7 +33,9 @@ def _engine_decode(codes, llrs, slots, T, flags=0, lane_slots=0, graph_steps=0, 
     caps = cap or [max(1, x.shape[0]) for x in llrs]
     eng = ldpc.Engine(graphs, slots, caps, T, flags=flags, lane_slots=lane_slots, graph_steps=graph_steps)
     jobs = [(i, torch.from_numpy(np.ascontiguousarray(x)).cuda()) for i, x in enumerate(llrs)]
-    res = ldpc.decode_batch(eng, jobs, want_llr=want_llr)
+    # bound: every frame needs at most T+1 steps once admitted; admissions follow slot turnover
+    steps = sum((x.shape[0] // max(1, sl) + 2) * (T + 2) for x, sl in zip(llrs, slots)) + 8
+    res = ldpc.decode_batch(eng, jobs, want_llr=want_llr, max_replays=steps)
     torch.cuda.synchronize()
     out = [dict(bits=r.bits.cpu().numpy(), ok=r.ok.cpu().numpy(), iters=r.iters.cpu().numpy(),
                 lpost=r.llr.cpu().numpy() if r.llr is not None else None) for r in res]
@@ -130,7 +132,9 @@ def test_engine_queue_backpressure_and_incremental_submit():
     with pytest.raises(ldpc.LdpcError):
         eng.submit(0, fr[:51])                     # more than the queue holds
     sent = 0
-    while sent < 200:
+    for _ in range(400):                          # bounded: the loop must not spin forever
+        if sent >= 200:
+            break
         free = eng.capacity(0)
         k = min(free, 200 - sent)
         if k > 0:
@@ -138,7 +142,8 @@ def test_engine_queue_backpressure_and_incremental_submit():
             sent += k
         eng.step(1)
         eng.poll()
-    eng.run()
+    assert sent == 200
+    eng.run(max_replays=400)
     torch.cuda.synchronize()
     assert int(done.item()) == 200
     ref = gpu_decode(code, llr, 30)

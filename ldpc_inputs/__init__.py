@@ -296,3 +296,83 @@ def random_small_code(n: int, m: int, bit_deg: int, seed: int) -> Code:
     """Regular-bit-degree random code with even checks (small test cases)."""
     bd = np.full(n, bit_deg, dtype=np.int64)
     return socket_code(bd, even_check_degrees(int(bd.sum()), m), seed, f"rand-{n}-{m}")
+
+
+# ---------------------------------------------------------------------------
+# systematic GF(2) encoder (C, gf2enc.c)
+# ---------------------------------------------------------------------------
+
+import ctypes as _ct
+import os as _os
+import subprocess as _sp
+
+_ENC_SRC = _os.path.join(_os.path.dirname(_os.path.abspath(__file__)), "gf2enc.c")
+_ENC_SO = _os.path.join(_os.path.dirname(_os.path.abspath(__file__)), "libgf2enc.so")
+_enc_lib = None
+
+
+def build_encoder() -> str:
+    tmp = _ENC_SO + ".tmp"
+    _sp.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall", "-o", tmp, _ENC_SRC])
+    _os.replace(tmp, _ENC_SO)
+    return _ENC_SO
+
+
+def _enc():
+    global _enc_lib
+    if _enc_lib is None:
+        if not _os.path.exists(_ENC_SO):
+            build_encoder()
+        lib = _ct.CDLL(_ENC_SO)
+        P = _ct.c_void_p
+        lib.gf2enc_create.argtypes = [_ct.c_int, _ct.c_int, _ct.c_long, P, P, _ct.POINTER(P), _ct.POINTER(_ct.c_int)]
+        lib.gf2enc_create.restype = _ct.c_int
+        lib.gf2enc_encode.argtypes = [P, _ct.c_int, P, P]
+        lib.gf2enc_encode.restype = _ct.c_int
+        lib.gf2enc_info_columns.argtypes = [P, P]
+        lib.gf2enc_info_columns.restype = _ct.c_int
+        lib.gf2enc_free.argtypes = [P]
+        _enc_lib = lib
+    return _enc_lib
+
+
+class Encoder:
+    """Systematic encoder of a Code: k = n - rank(H) information columns."""
+
+    def __init__(self, code: Code):
+        lib = _enc()
+        self._lib = lib
+        rows = np.ascontiguousarray(code.rows, np.int32)
+        cols = np.ascontiguousarray(code.cols, np.int32)
+        self._h = _ct.c_void_p()
+        k = _ct.c_int()
+        st = lib.gf2enc_create(code.m, code.n, rows.size, rows.ctypes.data_as(_ct.c_void_p),
+                               cols.ctypes.data_as(_ct.c_void_p), _ct.byref(self._h), _ct.byref(k))
+        if st != 0:
+            raise ValueError(f"encoder construction failed (status {st})")
+        self.k, self.n = int(k.value), code.n
+        self.info_cols = np.zeros(self.k, np.int32)
+        lib.gf2enc_info_columns(self._h, self.info_cols.ctypes.data_as(_ct.c_void_p))
+
+    def encode(self, info: np.ndarray) -> np.ndarray:
+        info = np.ascontiguousarray(np.atleast_2d(info), np.uint8)
+        if info.shape[1] != self.k:
+            raise ValueError("info width must be k")
+        cw = np.zeros((info.shape[0], self.n), np.uint8)
+        st = self._lib.gf2enc_encode(self._h, info.shape[0], info.ctypes.data_as(_ct.c_void_p),
+                                     cw.ctypes.data_as(_ct.c_void_p))
+        if st != 0:
+            raise RuntimeError(f"encoding failed (status {st})")
+        return cw
+
+    def random_codewords(self, frames: int, seed: int) -> np.ndarray:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        return self.encode(rng.integers(0, 2, size=(frames, self.k), dtype=np.uint8))
+
+    def __del__(self):
+        try:
+            if self._h:
+                self._lib.gf2enc_free(self._h)
+                self._h = _ct.c_void_p()
+        except Exception:
+            pass

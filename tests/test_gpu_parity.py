@@ -147,7 +147,8 @@ def test_determinism_and_sign_symmetry():
 def test_large_code_full_batch_sampled_frames():
     code = li.large_code()
     frames = 256
-    llr = li.awgn_llr(code.n, frames, li.ebn0_to_sigma2(1.0, code.rate), seed=2012)
+    cw = li.Encoder(code).random_codewords(frames, seed=3002)
+    llr = li.awgn_llr(code.n, frames, li.ebn0_to_sigma2(1.0, code.rate), seed=2012, codewords=cw)
     _announce("large-1.0dB", frames=frames)
     gpu = gpu_decode(code, llr, 50)
     # properties on every frame
@@ -155,6 +156,7 @@ def test_large_code_full_batch_sampled_frames():
     syn = code.syndrome(gpu["bits"]).any(axis=1)
     assert (syn == (gpu["ok"] == 0)).all()
     assert ((gpu["lpost"] < 0) == gpu["bits"].astype(bool)).all()
+    assert (gpu["bits"][gpu["ok"] == 1] == cw[gpu["ok"] == 1]).mean() > 0.999
     # oracle on sampled frames: first, last and across slot groups
     st = compare(code, llr, 50, frames=[0, 1, 127, 128, 200, 255], gpu=gpu)
     print(st)

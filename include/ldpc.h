@@ -280,6 +280,23 @@ LDPC_API ldpc_status ldpc_engine_poll(ldpc_engine *e, int64_t *retired, int64_t 
  */
 LDPC_API ldpc_status ldpc_engine_run(ldpc_engine *e, int32_t max_replays, int64_t *replays_out);
 
+/*
+ * Autotuner for ldpc_engine_create: times the decode of the given frames with
+ * candidate tile shapes and slot-pool sizes and returns the fastest.
+ * Candidates: lane_slots in {2, 4} x slot pools of {1/4, 1/2, 1} x the frame
+ * count of each graph (at least one 64*lane_slots group) x graph_steps in
+ * {4, 8}.  Each candidate engine decodes every frame twice; the second run is
+ * timed.  The frames' outputs are overwritten by the trials.
+ *
+ *  frames[c] / frame_counts[c]  host descriptor arrays of graph c's frames
+ *  slots_out [ngraphs], opts_out, best_ms (may be NULL): the winner.
+ * Errors: those of ldpc_engine_create / submit / run.
+ */
+LDPC_API ldpc_status ldpc_engine_autotune(const ldpc_graph *const *graphs, int32_t ngraphs,
+                                          const ldpc_frame *const *frames, const int32_t *frame_counts,
+                                          int32_t max_iter, uint32_t flags, int32_t *slots_out,
+                                          ldpc_engine_opts *opts_out, float *best_ms);
+
 /* Static string naming a status code. */
 LDPC_API const char *ldpc_status_str(ldpc_status s);
 

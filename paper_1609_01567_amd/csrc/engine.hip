@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -884,5 +886,60 @@ extern "C" ldpc_status ldpc_engine_run(ldpc_engine *e, int32_t max_replays, int6
         done += done == 0 ? 2 : 1;
     }
     if (replays_out) *replays_out = done;
+    return LDPC_OK;
+}
+
+extern "C" ldpc_status ldpc_engine_autotune(const ldpc_graph *const *graphs, int32_t ngraphs,
+                                            const ldpc_frame *const *frames, const int32_t *frame_counts,
+                                            int32_t max_iter, uint32_t flags, int32_t *slots_out,
+                                            ldpc_engine_opts *opts_out, float *best_ms) {
+    if (!graphs || !frames || !frame_counts || !slots_out || !opts_out || ngraphs < 1 || ngraphs > kMaxGraphs) {
+        set_error("ldpc_engine_autotune: bad argument");
+        return LDPC_E_INVAL;
+    }
+    std::vector<int32_t> caps(static_cast<size_t>(ngraphs));
+    for (int32_t c = 0; c < ngraphs; c++) {
+        if (frame_counts[c] < 0 || (frame_counts[c] > 0 && !frames[c])) {
+            set_error("ldpc_engine_autotune: bad frame list");
+            return LDPC_E_INVAL;
+        }
+        caps[size_t(c)] = std::max(1, frame_counts[c]);
+    }
+    const int lane_options[2] = {2, 4};
+    const float scale_options[3] = {0.25f, 0.5f, 1.0f};
+    const int step_options[2] = {4, 8};
+    float best = -1.f;
+    for (int ls : lane_options) {
+        for (float sc : scale_options) {
+            for (int gs : step_options) {
+                std::vector<int32_t> slots(static_cast<size_t>(ngraphs));
+                for (int32_t c = 0; c < ngraphs; c++)
+                    slots[size_t(c)] = std::max(64 * ls, int32_t(std::ceil(sc * float(frame_counts[c]))));
+                ldpc_engine_opts o{};
+                o.lane_slots = ls;
+                o.graph_steps = gs;
+                ldpc_engine *e = nullptr;
+                ldpc_status st = ldpc_engine_create(graphs, ngraphs, slots.data(), caps.data(), max_iter, flags, &o, &e);
+                if (st != LDPC_OK) return st;
+                float ms = 0.f;
+                for (int rep = 0; rep < 2 && st == LDPC_OK; rep++) {
+                    const auto t0 = std::chrono::steady_clock::now();
+                    for (int32_t c = 0; c < ngraphs && st == LDPC_OK; c++)
+                        if (frame_counts[c] > 0) st = ldpc_engine_submit(e, c, frames[c], frame_counts[c], nullptr);
+                    if (st == LDPC_OK) st = ldpc_engine_run(e, 0, nullptr);
+                    const auto t1 = std::chrono::steady_clock::now();
+                    ms = std::chrono::duration<float, std::milli>(t1 - t0).count();
+                }
+                ldpc_engine_destroy(e);
+                if (st != LDPC_OK) return st;
+                if (best < 0.f || ms < best) {
+                    best = ms;
+                    for (int32_t c = 0; c < ngraphs; c++) slots_out[c] = slots[size_t(c)];
+                    *opts_out = o;
+                }
+            }
+        }
+    }
+    if (best_ms) *best_ms = best;
     return LDPC_OK;
 }

@@ -32,7 +32,7 @@ EXPORTED = ("ldpc_graph_create", "ldpc_graph_destroy", "ldpc_graph_info", "ldpc_
             "ldpc_decode_workspace_size", "ldpc_decode", "ldpc_decode_profiled", "ldpc_status_str",
             "ldpc_last_error", "ldpc_engine_create", "ldpc_engine_destroy", "ldpc_engine_info",
             "ldpc_engine_submit", "ldpc_engine_capacity", "ldpc_engine_step", "ldpc_engine_poll",
-            "ldpc_engine_run")
+            "ldpc_engine_run", "ldpc_engine_autotune")
 
 
 class Frame(ctypes.Structure):
@@ -60,6 +60,10 @@ def load_library():
     global _lib
     if _lib is not None:
         return _lib
+    # torch first: torch ships its own HIP runtime under the same soname
+    # (libamdhip64.so.7).  Loaded first, it is the one this library binds to;
+    # loaded second, it would be a second runtime that sees no devices.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
                           "python paper_1609_01567_amd/build.py")
@@ -83,6 +87,8 @@ def load_library():
     lib.ldpc_engine_step.argtypes = [P, I32]
     lib.ldpc_engine_poll.argtypes = [P, P, P]
     lib.ldpc_engine_run.argtypes = [P, I32, P]
+    lib.ldpc_engine_autotune.argtypes = [P, I32, P, P, I32, U32, P, P, P]
+    lib.ldpc_engine_autotune.restype = ctypes.c_int
     for f in ("ldpc_engine_create", "ldpc_engine_destroy", "ldpc_engine_info", "ldpc_engine_submit",
               "ldpc_engine_capacity", "ldpc_engine_step", "ldpc_engine_poll", "ldpc_engine_run"):
         getattr(lib, f).restype = ctypes.c_int
@@ -352,3 +358,20 @@ def decode_batch(engine: Engine, jobs, want_llr: bool = False, max_replays: int 
     if pending.any():
         raise LdpcError(E_DEVICE, "decode_batch", f"frames still pending after {max_replays} replays: {pending}")
     return results
+
+
+def autotune(graphs, frame_lists, max_iter: int, flags: int = 0) -> dict:
+    """ldpc_engine_autotune over the given frames (lists of Frame per graph)."""
+    lib = load_library()
+    ng = len(graphs)
+    hs = (ctypes.c_void_p * ng)(*[g.handle.value for g in graphs])
+    arrays = [(Frame * len(fl))(*fl) for fl in frame_lists]
+    ptrs = (ctypes.c_void_p * ng)(*[ctypes.cast(a, ctypes.c_void_p).value for a in arrays])
+    counts = np.array([len(fl) for fl in frame_lists], np.int32)
+    slots = np.zeros(ng, np.int32)
+    opts = EngineOpts()
+    ms = ctypes.c_float()
+    _check(lib.ldpc_engine_autotune(hs, ng, ptrs, _np_ptr(counts), int(max_iter), int(flags), _np_ptr(slots),
+                                    ctypes.byref(opts), ctypes.byref(ms)), "ldpc_engine_autotune")
+    return {"slots": slots.tolist(), "lane_slots": int(opts.lane_slots), "graph_steps": int(opts.graph_steps),
+            "ms": float(ms.value)}

@@ -67,6 +67,7 @@ def parse():
     ap.add_argument("--engine-slots", type=str, default="256,512",
                     help="slot-pool sizes tried for the refill engine on the same workload")
     ap.add_argument("--no-engine", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates rocprof byte counters) and exit")
     return ap.parse_args()
@@ -162,6 +163,104 @@ def engine_large(torch, ldpc, g, d_llr, T, flags, slots, steps, warmup, graph_st
            "graph_steps": graph_steps, "iters": it.cpu().numpy(), "ok": ok.cpu().numpy()}
     eng.close()
     return out
+
+
+def bench_batched(torch, ldpc, steps, warmup, T=50):
+    """Eight uneven codes, 4096 frames (Zipf split), each 0.5 dB above its waterfall.
+
+    (a) plain FP32: one ldpc_decode per code, back to back on one stream;
+    (b) engine FP16: every code in one engine (autotuned), continuous refill;
+    (c) engine FP32: the same engine with FP32 messages (separates the batching
+        gain from the storage-precision gain).
+    Frame errors are counted against the transmitted codewords; (a) and (b)
+    see the same noise, so their difference is reported as paired counts.
+    """
+    from paper_1609_01567_amd import workloads
+    mix = workloads.batched_mix()
+    graphs = [ldpc.Graph.from_code(c) for c, *_ in mix]
+    d_llr = [torch.from_numpy(x).cuda() for *_, x in mix]
+    info_bits = sum(F * (c.n - c.m) for c, F, *_ in mix)
+    stream = torch.cuda.current_stream()
+
+    # (a) plain FP32 per code
+    wss = [ldpc.Workspace(ldpc.workspace_size(g, F)) for g, (_, F, *_) in zip(graphs, mix)]
+    outs = [ldpc.DecodeResult(bits=torch.empty((F, c.n), dtype=torch.uint8, device="cuda"),
+                              ok=torch.empty(F, dtype=torch.uint8, device="cuda"),
+                              iters=torch.empty(F, dtype=torch.int32, device="cuda"), llr=None)
+            for c, F, *_ in mix]
+
+    def plain_step():
+        for g, x, w, o in zip(graphs, d_llr, wss, outs):
+            ldpc.decode(g, x, T, workspace=w, stream=stream, out=o)
+
+    for _ in range(warmup):
+        plain_step()
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record(stream)
+    for _ in range(steps):
+        plain_step()
+    e.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = s.elapsed_time(e) / steps
+    plain_err = [(o.bits.cpu().numpy() != cw).any(axis=1) for o, (_, _, _, cw, _) in zip(outs, mix)]
+    plain_iters = [o.iters.cpu().numpy() for o in outs]
+
+    def engine_run(flags):
+        eouts = [ldpc.DecodeResult(bits=torch.empty((F, c.n), dtype=torch.uint8, device="cuda"),
+                                   ok=torch.empty(F, dtype=torch.uint8, device="cuda"),
+                                   iters=torch.empty(F, dtype=torch.int32, device="cuda"), llr=None)
+                 for c, F, *_ in mix]
+        frame_lists = [ldpc.frames_for(x, o.bits, o.ok, o.iters) for x, o in zip(d_llr, eouts)]
+        torch.cuda.synchronize()
+        tune = ldpc.autotune(graphs, frame_lists, T, flags)
+        eng = ldpc.Engine(graphs, tune["slots"], [len(fl) for fl in frame_lists], T, flags=flags,
+                          lane_slots=tune["lane_slots"], graph_steps=tune["graph_steps"])
+
+        def one():
+            for gi, fl in enumerate(frame_lists):
+                eng.submit(gi, fl)
+            eng.run()
+
+        for _ in range(warmup):
+            one()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            one()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        info = eng.info()
+        eng.close()
+        err = [(o.bits.cpu().numpy() != cw).any(axis=1) for o, (_, _, _, cw, _) in zip(eouts, mix)]
+        iters = [o.iters.cpu().numpy() for o in eouts]
+        return ms, tune, info, err, iters
+
+    f16_ms, f16_tune, f16_info, f16_err, f16_iters = engine_run(ldpc.MSG_FP16)
+    f32_ms, f32_tune, _, f32_err, f32_iters = engine_run(0)
+    same32 = all((a == b).all() for a, b in zip(f32_iters, plain_iters))
+    per_code = []
+    for (c, F, eb, *_), pe, he in zip(mix, plain_err, f16_err):
+        per_code.append({"code": c.name, "frames": F, "ebn0_db": eb, "fer_plain_fp32": round(float(pe.mean()), 5),
+                         "fer_engine_fp16": round(float(he.mean()), 5),
+                         "fail_only_fp16": int((he & ~pe).sum()), "fail_only_fp32": int((pe & ~he).sum())})
+    pe_all, he_all = np.concatenate(plain_err), np.concatenate(f16_err)
+    gb = lambda ms: round(info_bits / (ms * 1e-3) / 1e9, 4)
+    return {
+        "workload": "8 random irregular codes n in {576..64800}, rates 1/3..9/10, 4096 frames (Zipf split), "
+                    "random codewords, Eb/N0 = waterfall + 0.5 dB per code, max 50 iterations",
+        "info_bits_per_step": int(info_bits),
+        "plain_fp32_per_code": {"ms_per_step": round(plain_ms, 3), "gbits": gb(plain_ms)},
+        "engine_fp16": {"ms_per_step": round(f16_ms, 3), "gbits": gb(f16_ms), "tuning": f16_tune,
+                        "device_bytes": f16_info["device_bytes"]},
+        "engine_fp32": {"ms_per_step": round(f32_ms, 3), "gbits": gb(f32_ms), "tuning": f32_tune,
+                        "iters_equal_plain": bool(same32)},
+        "speedup_engine_fp16_vs_plain_fp32": round(plain_ms / f16_ms, 3),
+        "fer_plain_fp32": round(float(pe_all.mean()), 5), "fer_engine_fp16": round(float(he_all.mean()), 5),
+        "paired": {"fail_only_fp16": int((he_all & ~pe_all).sum()), "fail_only_fp32": int((pe_all & ~he_all).sum()),
+                   "frames": int(pe_all.size)},
+        "per_code": per_code,
+    }
 
 
 def main():
@@ -292,6 +391,11 @@ def main():
                           "includes submission and host polling", "tries": tries}
         print(f"[bench] engine done", file=sys.stderr, flush=True)
 
+    batched = None
+    if not args.no_batched:
+        batched = bench_batched(torch, ldpc, max(1, args.steps), args.warmup)
+        print(f"[bench] batched done", file=sys.stderr, flush=True)
+
     ceiling = copy_ceiling(torch)
     cpu = None
     if not args.no_cpu_baseline:
@@ -322,6 +426,7 @@ def main():
         "roofline": roofline,
         "phases": phase,
         "engine_same_workload": engine,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

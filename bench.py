@@ -182,29 +182,43 @@ def bench_batched(torch, ldpc, steps, warmup, T=50):
     info_bits = sum(F * (c.n - c.m) for c, F, *_ in mix)
     stream = torch.cuda.current_stream()
 
-    # (a) plain FP32 per code
-    wss = [ldpc.Workspace(ldpc.workspace_size(g, F)) for g, (_, F, *_) in zip(graphs, mix)]
-    outs = [ldpc.DecodeResult(bits=torch.empty((F, c.n), dtype=torch.uint8, device="cuda"),
-                              ok=torch.empty(F, dtype=torch.uint8, device="cuda"),
-                              iters=torch.empty(F, dtype=torch.int32, device="cuda"), llr=None)
-            for c, F, *_ in mix]
+    def plain_run(flags):
+        wss = [ldpc.Workspace(ldpc.workspace_size(g, F, flags)) for g, (_, F, *_) in zip(graphs, mix)]
+        outs = [ldpc.DecodeResult(bits=torch.empty((F, c.n), dtype=torch.uint8, device="cuda"),
+                                  ok=torch.empty(F, dtype=torch.uint8, device="cuda"),
+                                  iters=torch.empty(F, dtype=torch.int32, device="cuda"), llr=None)
+                for c, F, *_ in mix]
 
-    def plain_step():
-        for g, x, w, o in zip(graphs, d_llr, wss, outs):
-            ldpc.decode(g, x, T, workspace=w, stream=stream, out=o)
+        def plain_step():
+            for g, x, w, o in zip(graphs, d_llr, wss, outs):
+                ldpc.decode(g, x, T, flags=flags, workspace=w, stream=stream, out=o)
 
-    for _ in range(warmup):
-        plain_step()
-    torch.cuda.synchronize()
-    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    s.record(stream)
-    for _ in range(steps):
-        plain_step()
-    e.record(stream)
-    torch.cuda.synchronize()
-    plain_ms = s.elapsed_time(e) / steps
-    plain_err = [(o.bits.cpu().numpy() != cw).any(axis=1) for o, (_, _, _, cw, _) in zip(outs, mix)]
-    plain_iters = [o.iters.cpu().numpy() for o in outs]
+        for _ in range(warmup):
+            plain_step()
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record(stream)
+        for _ in range(steps):
+            plain_step()
+        e.record(stream)
+        torch.cuda.synchronize()
+        ms = s.elapsed_time(e) / steps
+        err = [(o.bits.cpu().numpy() != cw).any(axis=1) for o, (_, _, _, cw, _) in zip(outs, mix)]
+        iters = [o.iters.cpu().numpy() for o in outs]
+        del wss
+        return ms, err, iters
+
+    plain_ms, plain_err, plain_iters = plain_run(0)
+    p16_ms, p16_err, _ = plain_run(ldpc.MSG_FP16)
+
+    def alg_bytes(msg_bytes):
+        tot = 0.0
+        for (c, *_), it in zip(mix, plain_iters):
+            cb, bb = algorithmic_bytes(it, T, c.nnz, c.n, msg_bytes)
+            tot += cb.sum() + bb.sum()
+        return tot
+
+    b32, b16 = alg_bytes(4), alg_bytes(2)
 
     def engine_run(flags):
         eouts = [ldpc.DecodeResult(bits=torch.empty((F, c.n), dtype=torch.uint8, device="cuda"),
@@ -246,15 +260,20 @@ def bench_batched(torch, ldpc, steps, warmup, T=50):
                          "fail_only_fp16": int((he & ~pe).sum()), "fail_only_fp32": int((pe & ~he).sum())})
     pe_all, he_all = np.concatenate(plain_err), np.concatenate(f16_err)
     gb = lambda ms: round(info_bits / (ms * 1e-3) / 1e9, 4)
+    tbs = lambda b, ms: round(b / (ms * 1e-3) / 1e9, 1)
     return {
         "workload": "8 random irregular codes n in {576..64800}, rates 1/3..9/10, 4096 frames (Zipf split), "
                     "random codewords, Eb/N0 = waterfall + 0.5 dB per code, max 50 iterations",
         "info_bits_per_step": int(info_bits),
-        "plain_fp32_per_code": {"ms_per_step": round(plain_ms, 3), "gbits": gb(plain_ms)},
+        "algorithmic_bytes_per_step": {"fp32": round(b32), "fp16": round(b16)},
+        "plain_fp32_per_code": {"ms_per_step": round(plain_ms, 3), "gbits": gb(plain_ms),
+                                "alg_gbs": tbs(b32, plain_ms)},
+        "plain_fp16_per_code": {"ms_per_step": round(p16_ms, 3), "gbits": gb(p16_ms), "alg_gbs": tbs(b16, p16_ms),
+                                "fer": round(float(np.concatenate(p16_err).mean()), 5)},
         "engine_fp16": {"ms_per_step": round(f16_ms, 3), "gbits": gb(f16_ms), "tuning": f16_tune,
-                        "device_bytes": f16_info["device_bytes"]},
+                        "device_bytes": f16_info["device_bytes"], "alg_gbs": tbs(b16, f16_ms)},
         "engine_fp32": {"ms_per_step": round(f32_ms, 3), "gbits": gb(f32_ms), "tuning": f32_tune,
-                        "iters_equal_plain": bool(same32)},
+                        "iters_equal_plain": bool(same32), "alg_gbs": tbs(b32, f32_ms)},
         "speedup_engine_fp16_vs_plain_fp32": round(plain_ms / f16_ms, 3),
         "fer_plain_fp32": round(float(pe_all.mean()), 5), "fer_engine_fp16": round(float(he_all.mean()), 5),
         "paired": {"fail_only_fp16": int((he_all & ~pe_all).sum()), "fail_only_fp32": int((pe_all & ~he_all).sum()),

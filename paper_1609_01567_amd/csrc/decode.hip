@@ -517,8 +517,8 @@ template <int M, int V>
 void launch_check_pass(const ldpc_graph *g, int mode, const float *L, const Bufs &b, int32_t S, int32_t syn_iter,
                        hipStream_t st) {
     launch_rows<M, V, 8>(g, ldpc::kClassD8, mode, L, b, S, syn_iter, st);
-    launch_rows<M, (V < 2 ? V : 2), 16>(g, ldpc::kClassD16, mode, L, b, S, syn_iter, st);
-    launch_rows<M, 1, 32>(g, ldpc::kClassD32, mode, L, b, S, syn_iter, st);
+    launch_rows<M, ldpc::class_lane_slots(ldpc::kClassD16, V), 16>(g, ldpc::kClassD16, mode, L, b, S, syn_iter, st);
+    launch_rows<M, ldpc::class_lane_slots(ldpc::kClassD32, V), 32>(g, ldpc::kClassD32, mode, L, b, S, syn_iter, st);
     launch_hub<M>(g, mode, L, b, S, syn_iter, st);
 }
 

@@ -524,10 +524,10 @@ void enqueue_step(ldpc_engine *e) {
         hipLaunchKernelGGL((eng_check_rows<M, V, 8>), dim3(unsigned((e->row_waves[0] + 3) / 4)), dim3(256), 0, st,
                            e->d_graphs, e->pre_rows[0], int32_t(ldpc::kClassD8), e->T, early);
     if (e->has_rows[1])
-        hipLaunchKernelGGL((eng_check_rows<M, (V < 2 ? V : 2), 16>), dim3(unsigned((e->row_waves[1] + 3) / 4)),
+        hipLaunchKernelGGL((eng_check_rows<M, ldpc::class_lane_slots(ldpc::kClassD16, V), 16>), dim3(unsigned((e->row_waves[1] + 3) / 4)),
                            dim3(256), 0, st, e->d_graphs, e->pre_rows[1], int32_t(ldpc::kClassD16), e->T, early);
     if (e->has_rows[2])
-        hipLaunchKernelGGL((eng_check_rows<M, 1, 32>), dim3(unsigned((e->row_waves[2] + 3) / 4)), dim3(256), 0, st,
+        hipLaunchKernelGGL((eng_check_rows<M, ldpc::class_lane_slots(ldpc::kClassD32, V), 32>), dim3(unsigned((e->row_waves[2] + 3) / 4)), dim3(256), 0, st,
                            e->d_graphs, e->pre_rows[2], int32_t(ldpc::kClassD32), e->T, early);
     if (e->has_hub)
         hipLaunchKernelGGL((eng_check_hub<M>), dim3(unsigned(e->hub_blocks)), dim3(256), 0, st, e->d_graphs,
@@ -713,7 +713,8 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
         return hip_fail(e, "ldpc_engine_create: initialisation", err);
 
     // work prefix tables
-    const int vk[3] = {V, V < 2 ? V : 2, 1};
+    const int vk[3] = {ldpc::class_lane_slots(ldpc::kClassD8, V), ldpc::class_lane_slots(ldpc::kClassD16, V),
+                       ldpc::class_lane_slots(ldpc::kClassD32, V)};
     for (int k = 0; k < 3; k++) {
         Prefix &p = e->pre_rows[k];
         p.count = ngraphs;

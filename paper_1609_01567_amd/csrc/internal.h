@@ -19,6 +19,13 @@ inline int check_class_of(int d) {
     return d <= 8 ? kClassD8 : d <= 16 ? kClassD16 : d <= 32 ? kClassD32 : kClassHub;
 }
 
+// Frame slots per wavefront lane of the register check kernels for a class,
+// when the decode uses V slots per lane elsewhere.  Register use grows as
+// 2 * DMAX * slots per lane, so the widest rows use fewer slots.
+constexpr int class_lane_slots(int cls, int V) {
+    return cls == kClassD8 ? V : cls == kClassD16 ? V : (V < 2 ? V : 2);
+}
+
 void set_error(const std::string &msg);
 
 }  // namespace ldpc

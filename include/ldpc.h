@@ -297,6 +297,65 @@ LDPC_API ldpc_status ldpc_engine_autotune(const ldpc_graph *const *graphs, int32
                                           int32_t max_iter, uint32_t flags, int32_t *slots_out,
                                           ldpc_engine_opts *opts_out, float *best_ms);
 
+/* ------------------------------------------------------------------------
+ * Serving: a request loop over an engine (continuous batching).
+ *
+ * Clients submit decode requests (frames of one of the server's graphs, host
+ * LLRs).  A worker thread admits requests in arrival order as soon as the
+ * device-memory budget, a completion counter and the graph's engine queue
+ * allow, copies their LLRs to the device, and queues their frames; frames
+ * enter free slots at the next engine step, so requests that arrive while
+ * others are decoding share the device with them.  Finished requests are
+ * copied back to host memory and time-stamped; latency = completion - submit.
+ * Graphs and per-slot message state stay resident for the server's lifetime.
+ * ------------------------------------------------------------------------ */
+typedef struct ldpc_server ldpc_server;
+
+typedef struct {
+    int32_t lane_slots;    /* engine tile option (0 = default) */
+    int32_t graph_steps;   /* engine steps per replay (0 = default) */
+    int32_t max_requests;  /* requests in flight at once (0 = 4096) */
+    int32_t reserved[5];   /* must be 0 */
+} ldpc_server_opts;
+
+/*
+ * Create a server for `ngraphs` graphs with slot pools `slots` (as for
+ * ldpc_engine_create) and decode settings max_iter / flags.
+ *  hbm_budget   device bytes for request inputs and outputs (>= 1 MiB); a
+ *               request needs about frames * n * 5 bytes.
+ *  host_budget  pinned host bytes for transfers (>= 1 MiB).
+ * Errors: INVAL, NOMEM, DEVICE.
+ */
+LDPC_API ldpc_status ldpc_server_create(const ldpc_graph *const *graphs, int32_t ngraphs, const int32_t *slots,
+                                        int32_t max_iter, uint32_t flags, int64_t hbm_budget,
+                                        int64_t host_budget, const ldpc_server_opts *opts, ldpc_server **out);
+
+/* Queue a request of `frames` frames of graph `graph`; llr is host memory
+ * [frames][n], copied before the call returns.  id receives the request id.
+ * Errors: INVAL (bad graph, frames < 1, or a request larger than the budgets
+ * or the graph's queue could ever hold), NOMEM. */
+LDPC_API ldpc_status ldpc_server_submit(ldpc_server *s, int32_t graph, const float *llr, int32_t frames,
+                                        int64_t *id);
+
+/* Ids of requests completed since the last poll (up to max_ids), waiting up
+ * to wait_ms milliseconds for at least one. */
+LDPC_API ldpc_status ldpc_server_poll(ldpc_server *s, int64_t *ids, int32_t max_ids, int32_t *count,
+                                      int32_t wait_ms);
+
+/* Copy a completed request's results to host memory ([frames][n] bits,
+ * [frames] ok, [frames] iters; any may be NULL) and its latency in seconds,
+ * then release it.  Errors: INVAL (unknown or unfinished id). */
+LDPC_API ldpc_status ldpc_server_result(ldpc_server *s, int64_t id, uint8_t *bits, uint8_t *ok,
+                                        int32_t *iters, double *latency_s);
+
+/* Counters: [0] submitted, [1] admitted, [2] completed, [3] frames completed,
+ * [4] waiting for admission, [5] in flight, [6] device bytes in use,
+ * [7] peak device bytes in use. */
+LDPC_API ldpc_status ldpc_server_stats(ldpc_server *s, int64_t *stats);
+
+/* Stop accepting requests, finish those already submitted, release everything. */
+LDPC_API ldpc_status ldpc_server_destroy(ldpc_server *s);
+
 /* Static string naming a status code. */
 LDPC_API const char *ldpc_status_str(ldpc_status s);
 

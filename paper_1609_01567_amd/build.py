@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libldpc_hip.so")
-SOURCES = ["graph.cpp", "decode.hip", "engine.hip"]
+SOURCES = ["graph.cpp", "decode.hip", "engine.hip", "serve.cpp"]
 ARCH = os.environ.get("LDPC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
@@ -17,7 +17,7 @@ HIPCC_FLAGS = [
     "-Wall", "-Wno-unused-function",
     # keep the compiler from emitting packed fp32 VALU ops
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-fvisibility=hidden", "-DLDPC_BUILD",
+    "-fvisibility=hidden", "-DLDPC_BUILD", "-pthread",
 ]
 
 

@@ -1,0 +1,447 @@
+// Request-serving loop over an ldpc_engine (the ldpc_server_* entry points).
+//
+// Client threads submit requests (host LLRs, copied at submit).  One worker
+// thread owns the engine: it admits waiting requests in arrival order while
+// the device-memory budget, a completion counter and the graph's engine queue
+// allow, uploads their LLRs on a copy stream that the engine waits for,
+// queues their frames (each frame bumps the request's device counter when it
+// finishes), runs engine steps, and when a request's counter reaches its
+// frame count copies the results back and time-stamps the completion.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+using ldpc::set_error;
+using Clock = std::chrono::steady_clock;
+
+// First-fit allocator over [0, size) with coalescing; offsets aligned to 256.
+class Arena {
+   public:
+    explicit Arena(size_t size) : size_(size) { free_[0] = size; }
+    bool alloc(size_t bytes, size_t *off) {
+        bytes = (bytes + 255) & ~size_t(255);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes;
+                const size_t start = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[start] = rest;
+                used_ += bytes;
+                peak_ = std::max(peak_, used_);
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = (bytes + 255) & ~size_t(255);
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto next = std::next(it);
+        if (next != free_.end() && it->first + it->second == next->first) {
+            it->second += next->second;
+            free_.erase(next);
+        }
+        if (it != free_.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == it->first) {
+                prev->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t size() const { return size_; }
+    size_t used() const { return used_; }
+    size_t peak() const { return peak_; }
+
+   private:
+    size_t size_, used_ = 0, peak_ = 0;
+    std::map<size_t, size_t> free_;
+};
+
+struct Request {
+    int64_t id = 0;
+    int32_t graph = 0, frames = 0, n = 0;
+    std::vector<float> llr;
+    size_t dev_off = 0, dev_bytes = 0, stage_off = 0, stage_bytes = 0;
+    bool staged = false;
+    int32_t counter = -1;
+    std::vector<uint8_t> bits, ok;
+    std::vector<int32_t> iters;
+    Clock::time_point t_submit, t_done;
+};
+
+size_t req_dev_bytes(int32_t F, int32_t n) {
+    const size_t llr = (size_t(F) * n * 4 + 255) & ~size_t(255);
+    const size_t bits = (size_t(F) * n + 255) & ~size_t(255);
+    const size_t small = (size_t(F) * 5 + 255) & ~size_t(255);
+    return llr + bits + small;
+}
+
+}  // namespace
+
+struct ldpc_server {
+    ldpc_engine *engine = nullptr;
+    int device = -1;
+    int32_t ngraphs = 0;
+    std::vector<int32_t> n, queue_cap;
+    hipStream_t copy = nullptr;
+    char *dev = nullptr;          // device arena
+    char *pinned = nullptr;       // pinned host arena
+    int32_t *counters = nullptr;  // [max_requests] device completion counters
+    int32_t *h_counters = nullptr;
+    int32_t max_requests = 4096;
+    std::unique_ptr<Arena> dev_arena, host_arena;
+    std::vector<int32_t> free_counters;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request *> waiting;
+    std::vector<Request *> inflight, staged_uploads;
+    std::unordered_map<int64_t, Request *> all;
+    std::deque<int64_t> completed;
+    int64_t next_id = 1, n_submitted = 0, n_admitted = 0, n_completed = 0, frames_completed = 0;
+    bool stop = false;
+    std::string worker_error;
+    std::thread worker;
+};
+
+namespace {
+
+void fail_worker(ldpc_server *s, const std::string &what) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->worker_error.empty()) s->worker_error = what + ": " + ldpc_last_error();
+    s->stop = true;
+    s->cv_done.notify_all();
+}
+
+// Admit waiting requests in arrival order while resources allow (worker thread, lock held).
+bool admit_locked(ldpc_server *s) {
+    bool any = false;
+    while (!s->waiting.empty()) {
+        Request *r = s->waiting.front();
+        if (s->free_counters.empty()) break;
+        int32_t cap = 0;
+        if (ldpc_engine_capacity(s->engine, r->graph, &cap) != LDPC_OK || cap < r->frames) break;
+        size_t doff = 0, hoff = 0;
+        if (!s->dev_arena->alloc(r->dev_bytes, &doff)) break;
+        if (!s->host_arena->alloc(r->stage_bytes, &hoff)) {
+            s->dev_arena->release(doff, r->dev_bytes);
+            break;
+        }
+        r->dev_off = doff;
+        r->stage_off = hoff;
+        r->staged = true;
+        r->counter = s->free_counters.back();
+        s->free_counters.pop_back();
+        s->waiting.pop_front();
+        // upload LLRs, reset the counter, queue the frames
+        const int32_t F = r->frames, nn = r->n;
+        char *base = s->dev + doff;
+        float *d_llr = reinterpret_cast<float *>(base);
+        uint8_t *d_bits = reinterpret_cast<uint8_t *>(base + ((size_t(F) * nn * 4 + 255) & ~size_t(255)));
+        uint8_t *d_ok = d_bits + ((size_t(F) * nn + 255) & ~size_t(255));
+        int32_t *d_iters = reinterpret_cast<int32_t *>(d_ok + ((size_t(F) + 3) & ~size_t(3)));
+        std::memcpy(s->pinned + hoff, r->llr.data(), size_t(F) * nn * 4);
+        std::vector<float>().swap(r->llr);
+        hipError_t e = hipMemcpyAsync(d_llr, s->pinned + hoff, size_t(F) * nn * 4, hipMemcpyHostToDevice, s->copy);
+        if (e == hipSuccess) e = hipMemsetAsync(s->counters + r->counter, 0, 4, s->copy);
+        if (e != hipSuccess) {
+            set_error(std::string("upload failed: ") + hipGetErrorString(e));
+            return false;
+        }
+        std::vector<ldpc_frame> fr(static_cast<size_t>(F));
+        for (int32_t f = 0; f < F; f++) {
+            fr[size_t(f)].llr = d_llr + size_t(f) * nn;
+            fr[size_t(f)].bits = d_bits + size_t(f) * nn;
+            fr[size_t(f)].ok = d_ok + f;
+            fr[size_t(f)].iters = d_iters + f;
+            fr[size_t(f)].llr_out = nullptr;
+            fr[size_t(f)].done = s->counters + r->counter;
+        }
+        if (ldpc_engine_submit(s->engine, r->graph, fr.data(), F, s->copy) != LDPC_OK) return false;
+        s->inflight.push_back(r);
+        s->staged_uploads.push_back(r);
+        s->n_admitted++;
+        any = true;
+    }
+    (void)any;
+    return true;
+}
+
+void worker_main(ldpc_server *s) {
+    (void)hipSetDevice(s->device);
+    std::vector<Request *> finished;
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            if (!admit_locked(s)) {
+                lk.unlock();
+                fail_worker(s, "admission");
+                return;
+            }
+            if (s->inflight.empty()) {
+                if (s->stop && s->waiting.empty()) return;
+                s->cv_work.wait_for(lk, std::chrono::milliseconds(2));
+                continue;
+            }
+        }
+        if (ldpc_engine_step(s->engine, 1) != LDPC_OK || ldpc_engine_poll(s->engine, nullptr, nullptr) != LDPC_OK) {
+            fail_worker(s, "engine");
+            return;
+        }
+        // the engine stream waited for every upload queued before this step
+        if (hipMemcpy(s->h_counters, s->counters, size_t(s->max_requests) * 4, hipMemcpyDeviceToHost) != hipSuccess) {
+            set_error("counter read failed");
+            fail_worker(s, "poll");
+            return;
+        }
+        finished.clear();
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            for (Request *r : s->staged_uploads) {
+                s->host_arena->release(r->stage_off, r->stage_bytes);
+                r->staged = false;
+            }
+            s->staged_uploads.clear();
+            for (size_t i = 0; i < s->inflight.size();) {
+                Request *r = s->inflight[i];
+                if (s->h_counters[r->counter] >= r->frames) {
+                    finished.push_back(r);
+                    s->inflight[i] = s->inflight.back();
+                    s->inflight.pop_back();
+                } else {
+                    i++;
+                }
+            }
+        }
+        for (Request *r : finished) {
+            const int32_t F = r->frames, nn = r->n;
+            const char *base = s->dev + r->dev_off;
+            const uint8_t *d_bits = reinterpret_cast<const uint8_t *>(base + ((size_t(F) * nn * 4 + 255) & ~size_t(255)));
+            const uint8_t *d_ok = d_bits + ((size_t(F) * nn + 255) & ~size_t(255));
+            const int32_t *d_iters = reinterpret_cast<const int32_t *>(d_ok + ((size_t(F) + 3) & ~size_t(3)));
+            r->bits.resize(size_t(F) * nn);
+            r->ok.resize(size_t(F));
+            r->iters.resize(size_t(F));
+            if (hipMemcpy(r->bits.data(), d_bits, r->bits.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemcpy(r->ok.data(), d_ok, r->ok.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemcpy(r->iters.data(), d_iters, r->iters.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) {
+                set_error("result read failed");
+                fail_worker(s, "results");
+                return;
+            }
+            r->t_done = Clock::now();
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->dev_arena->release(r->dev_off, r->dev_bytes);
+            s->free_counters.push_back(r->counter);
+            r->counter = -1;
+            s->completed.push_back(r->id);
+            s->n_completed++;
+            s->frames_completed += F;
+        }
+        if (!finished.empty()) s->cv_done.notify_all();
+    }
+}
+
+}  // namespace
+
+extern "C" ldpc_status ldpc_server_create(const ldpc_graph *const *graphs, int32_t ngraphs, const int32_t *slots,
+                                          int32_t max_iter, uint32_t flags, int64_t hbm_budget, int64_t host_budget,
+                                          const ldpc_server_opts *opts, ldpc_server **out) {
+    if (!out || !graphs || !slots || ngraphs < 1) { set_error("ldpc_server_create: bad argument"); return LDPC_E_INVAL; }
+    if (hbm_budget < (1 << 20) || host_budget < (1 << 20)) {
+        set_error("ldpc_server_create: budgets must be >= 1 MiB");
+        return LDPC_E_INVAL;
+    }
+    ldpc_engine_opts eo{};
+    int32_t maxreq = 4096;
+    if (opts) {
+        for (int32_t r : opts->reserved)
+            if (r) { set_error("ldpc_server_create: reserved options must be 0"); return LDPC_E_INVAL; }
+        eo.lane_slots = opts->lane_slots;
+        eo.graph_steps = opts->graph_steps;
+        if (opts->max_requests < 0) { set_error("ldpc_server_create: max_requests < 0"); return LDPC_E_INVAL; }
+        if (opts->max_requests) maxreq = opts->max_requests;
+    }
+    std::vector<int32_t> caps(static_cast<size_t>(ngraphs));
+    for (int32_t c = 0; c < ngraphs; c++) caps[size_t(c)] = std::max<int32_t>(4096, slots[c] > 0 ? 4 * slots[c] : 1);
+    ldpc_server *s = new (std::nothrow) ldpc_server;
+    if (!s) { set_error("ldpc_server_create: out of host memory"); return LDPC_E_NOMEM; }
+    ldpc_status st = ldpc_engine_create(graphs, ngraphs, slots, caps.data(), max_iter, flags, &eo, &s->engine);
+    if (st != LDPC_OK) { delete s; return st; }
+    (void)hipGetDevice(&s->device);
+    s->ngraphs = ngraphs;
+    for (int32_t c = 0; c < ngraphs; c++) s->n.push_back(graphs[c]->n);
+    s->queue_cap = caps;
+    s->max_requests = maxreq;
+    hipError_t e = hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&s->dev), size_t(hbm_budget));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&s->counters), size_t(maxreq) * 4);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&s->pinned), size_t(host_budget), 0);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&s->h_counters), size_t(maxreq) * 4, 0);
+    if (e == hipSuccess) e = hipMemset(s->counters, 0, size_t(maxreq) * 4);
+    if (e != hipSuccess) {
+        set_error(std::string("ldpc_server_create: ") + hipGetErrorString(e));
+        (void)hipGetLastError();
+        if (s->copy) (void)hipStreamDestroy(s->copy);
+        if (s->dev) (void)hipFree(s->dev);
+        if (s->counters) (void)hipFree(s->counters);
+        if (s->pinned) (void)hipHostFree(s->pinned);
+        if (s->h_counters) (void)hipHostFree(s->h_counters);
+        ldpc_engine_destroy(s->engine);
+        delete s;
+        return e == hipErrorOutOfMemory ? LDPC_E_NOMEM : LDPC_E_DEVICE;
+    }
+    s->dev_arena.reset(new Arena(size_t(hbm_budget)));
+    s->host_arena.reset(new Arena(size_t(host_budget)));
+    for (int32_t i = maxreq - 1; i >= 0; i--) s->free_counters.push_back(i);
+    try {
+        s->worker = std::thread(worker_main, s);
+    } catch (...) {
+        set_error("ldpc_server_create: cannot start the worker thread");
+        ldpc_engine_destroy(s->engine);
+        delete s;
+        return LDPC_E_NOMEM;
+    }
+    *out = s;
+    return LDPC_OK;
+}
+
+extern "C" ldpc_status ldpc_server_submit(ldpc_server *s, int32_t graph, const float *llr, int32_t frames,
+                                          int64_t *id) {
+    if (!s || !llr || !id || graph < 0 || graph >= s->ngraphs || frames < 1) {
+        set_error("ldpc_server_submit: bad argument");
+        return LDPC_E_INVAL;
+    }
+    const int32_t nn = s->n[size_t(graph)];
+    Request *r = new (std::nothrow) Request;
+    if (!r) { set_error("ldpc_server_submit: out of host memory"); return LDPC_E_NOMEM; }
+    r->graph = graph;
+    r->frames = frames;
+    r->n = nn;
+    r->dev_bytes = req_dev_bytes(frames, nn);
+    r->stage_bytes = size_t(frames) * nn * 4;
+    if (r->dev_bytes > s->dev_arena->size() || r->stage_bytes > s->host_arena->size() ||
+        frames > s->queue_cap[size_t(graph)]) {
+        delete r;
+        set_error("ldpc_server_submit: request larger than the server's memory budgets");
+        return LDPC_E_INVAL;
+    }
+    try {
+        r->llr.assign(llr, llr + size_t(frames) * nn);
+    } catch (const std::bad_alloc &) {
+        delete r;
+        set_error("ldpc_server_submit: out of host memory");
+        return LDPC_E_NOMEM;
+    }
+    r->t_submit = Clock::now();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stop) {
+            delete r;
+            set_error("ldpc_server_submit: server is stopping: " + s->worker_error);
+            return LDPC_E_INVAL;
+        }
+        r->id = s->next_id++;
+        s->all[r->id] = r;
+        s->waiting.push_back(r);
+        s->n_submitted++;
+    }
+    s->cv_work.notify_one();
+    *id = r->id;
+    return LDPC_OK;
+}
+
+extern "C" ldpc_status ldpc_server_poll(ldpc_server *s, int64_t *ids, int32_t max_ids, int32_t *count,
+                                        int32_t wait_ms) {
+    if (!s || !count || max_ids < 0 || (max_ids > 0 && !ids)) { set_error("ldpc_server_poll: bad argument"); return LDPC_E_INVAL; }
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->completed.empty() && wait_ms > 0 && s->worker_error.empty())
+        s->cv_done.wait_for(lk, std::chrono::milliseconds(wait_ms), [&] { return !s->completed.empty() || s->stop; });
+    int32_t k = 0;
+    while (k < max_ids && !s->completed.empty()) {
+        ids[k++] = s->completed.front();
+        s->completed.pop_front();
+    }
+    *count = k;
+    if (!s->worker_error.empty()) {
+        set_error("ldpc_server_poll: worker failed: " + s->worker_error);
+        return LDPC_E_DEVICE;
+    }
+    return LDPC_OK;
+}
+
+extern "C" ldpc_status ldpc_server_result(ldpc_server *s, int64_t id, uint8_t *bits, uint8_t *ok, int32_t *iters,
+                                          double *latency_s) {
+    if (!s) { set_error("ldpc_server_result: NULL server"); return LDPC_E_INVAL; }
+    Request *r = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->all.find(id);
+        if (it == s->all.end() || it->second->bits.empty()) {
+            set_error("ldpc_server_result: unknown or unfinished request");
+            return LDPC_E_INVAL;
+        }
+        r = it->second;
+        s->all.erase(it);
+    }
+    if (bits) std::memcpy(bits, r->bits.data(), r->bits.size());
+    if (ok) std::memcpy(ok, r->ok.data(), r->ok.size());
+    if (iters) std::memcpy(iters, r->iters.data(), r->iters.size() * 4);
+    if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+    delete r;
+    return LDPC_OK;
+}
+
+extern "C" ldpc_status ldpc_server_stats(ldpc_server *s, int64_t *stats) {
+    if (!s || !stats) { set_error("ldpc_server_stats: bad argument"); return LDPC_E_INVAL; }
+    std::lock_guard<std::mutex> lk(s->mu);
+    stats[0] = s->n_submitted;
+    stats[1] = s->n_admitted;
+    stats[2] = s->n_completed;
+    stats[3] = s->frames_completed;
+    stats[4] = int64_t(s->waiting.size());
+    stats[5] = int64_t(s->inflight.size());
+    stats[6] = int64_t(s->dev_arena->used());
+    stats[7] = int64_t(s->dev_arena->peak());
+    return LDPC_OK;
+}
+
+extern "C" ldpc_status ldpc_server_destroy(ldpc_server *s) {
+    if (!s) return LDPC_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    ldpc_engine_destroy(s->engine);
+    (void)hipStreamSynchronize(s->copy);
+    (void)hipStreamDestroy(s->copy);
+    (void)hipFree(s->dev);
+    (void)hipFree(s->counters);
+    (void)hipHostFree(s->pinned);
+    (void)hipHostFree(s->h_counters);
+    (void)hipGetLastError();
+    for (auto &kv : s->all) delete kv.second;
+    delete s;
+    return LDPC_OK;
+}

@@ -32,13 +32,19 @@ EXPORTED = ("ldpc_graph_create", "ldpc_graph_destroy", "ldpc_graph_info", "ldpc_
             "ldpc_decode_workspace_size", "ldpc_decode", "ldpc_decode_profiled", "ldpc_status_str",
             "ldpc_last_error", "ldpc_engine_create", "ldpc_engine_destroy", "ldpc_engine_info",
             "ldpc_engine_submit", "ldpc_engine_capacity", "ldpc_engine_step", "ldpc_engine_poll",
-            "ldpc_engine_run", "ldpc_engine_autotune")
+            "ldpc_engine_run", "ldpc_engine_autotune", "ldpc_server_create", "ldpc_server_submit",
+            "ldpc_server_poll", "ldpc_server_result", "ldpc_server_stats", "ldpc_server_destroy")
 
 
 class Frame(ctypes.Structure):
     """ldpc_frame: device pointers of one queued frame."""
     _fields_ = [("llr", ctypes.c_void_p), ("bits", ctypes.c_void_p), ("ok", ctypes.c_void_p),
                 ("iters", ctypes.c_void_p), ("llr_out", ctypes.c_void_p), ("done", ctypes.c_void_p)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("lane_slots", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("max_requests", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 class EngineOpts(ctypes.Structure):
@@ -89,6 +95,15 @@ def load_library():
     lib.ldpc_engine_run.argtypes = [P, I32, P]
     lib.ldpc_engine_autotune.argtypes = [P, I32, P, P, I32, U32, P, P, P]
     lib.ldpc_engine_autotune.restype = ctypes.c_int
+    lib.ldpc_server_create.argtypes = [P, I32, P, I32, U32, I64, I64, P, ctypes.POINTER(P)]
+    lib.ldpc_server_submit.argtypes = [P, I32, P, I32, ctypes.POINTER(I64)]
+    lib.ldpc_server_poll.argtypes = [P, P, I32, ctypes.POINTER(I32), I32]
+    lib.ldpc_server_result.argtypes = [P, I64, P, P, P, ctypes.POINTER(ctypes.c_double)]
+    lib.ldpc_server_stats.argtypes = [P, P]
+    lib.ldpc_server_destroy.argtypes = [P]
+    for f in ("ldpc_server_create", "ldpc_server_submit", "ldpc_server_poll", "ldpc_server_result",
+              "ldpc_server_stats", "ldpc_server_destroy"):
+        getattr(lib, f).restype = ctypes.c_int
     for f in ("ldpc_engine_create", "ldpc_engine_destroy", "ldpc_engine_info", "ldpc_engine_submit",
               "ldpc_engine_capacity", "ldpc_engine_step", "ldpc_engine_poll", "ldpc_engine_run"):
         getattr(lib, f).restype = ctypes.c_int
@@ -375,3 +390,68 @@ def autotune(graphs, frame_lists, max_iter: int, flags: int = 0) -> dict:
                                     ctypes.byref(opts), ctypes.byref(ms)), "ldpc_engine_autotune")
     return {"slots": slots.tolist(), "lane_slots": int(opts.lane_slots), "graph_steps": int(opts.graph_steps),
             "ms": float(ms.value)}
+
+
+class Server:
+    """Request-serving loop (ldpc_server_*): host LLRs in, host results out."""
+
+    STAT_KEYS = ("submitted", "admitted", "completed", "frames_completed", "waiting", "in_flight",
+                 "device_bytes_in_use", "device_bytes_peak")
+
+    def __init__(self, graphs, slots, max_iter: int, flags: int = 0, hbm_budget: int = 1 << 30,
+                 host_budget: int = 1 << 28, lane_slots: int = 0, graph_steps: int = 0, max_requests: int = 0):
+        lib = load_library()
+        self._lib = lib
+        self.graphs = list(graphs)
+        ng = len(self.graphs)
+        hs = (ctypes.c_void_p * ng)(*[g.handle.value for g in self.graphs])
+        sl = np.ascontiguousarray(slots, dtype=np.int32)
+        opts = ServerOpts(lane_slots, graph_steps, max_requests)
+        self._h = ctypes.c_void_p()
+        _check(lib.ldpc_server_create(hs, ng, _np_ptr(sl), int(max_iter), int(flags), int(hbm_budget),
+                                      int(host_budget), ctypes.byref(opts), ctypes.byref(self._h)),
+               "ldpc_server_create")
+        self._frames = {}
+
+    def submit(self, graph: int, llr: np.ndarray) -> int:
+        llr = np.ascontiguousarray(llr, dtype=np.float32)
+        if llr.ndim != 2 or llr.shape[1] != self.graphs[graph].n:
+            raise ValueError("llr must be [frames][n] for the graph")
+        rid = ctypes.c_int64()
+        _check(self._lib.ldpc_server_submit(self._h, int(graph), _np_ptr(llr), llr.shape[0], ctypes.byref(rid)),
+               "ldpc_server_submit")
+        self._frames[int(rid.value)] = (llr.shape[0], self.graphs[graph].n)
+        return int(rid.value)
+
+    def poll(self, wait_ms: int = 0, max_ids: int = 4096):
+        ids = np.zeros(max_ids, np.int64)
+        cnt = ctypes.c_int32()
+        _check(self._lib.ldpc_server_poll(self._h, _np_ptr(ids), max_ids, ctypes.byref(cnt), int(wait_ms)),
+               "ldpc_server_poll")
+        return ids[: cnt.value].tolist()
+
+    def result(self, rid: int):
+        F, n = self._frames.pop(rid)
+        bits = np.zeros((F, n), np.uint8)
+        ok = np.zeros(F, np.uint8)
+        iters = np.zeros(F, np.int32)
+        lat = ctypes.c_double()
+        _check(self._lib.ldpc_server_result(self._h, int(rid), _np_ptr(bits), _np_ptr(ok), _np_ptr(iters),
+                                            ctypes.byref(lat)), "ldpc_server_result")
+        return bits, ok, iters, float(lat.value)
+
+    def stats(self) -> dict:
+        st = np.zeros(8, np.int64)
+        _check(self._lib.ldpc_server_stats(self._h, _np_ptr(st)), "ldpc_server_stats")
+        return dict(zip(self.STAT_KEYS, st.tolist()))
+
+    def close(self):
+        if self._h:
+            self._lib.ldpc_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -71,10 +71,20 @@ __global__ __launch_bounds__(256) void ingest_kernel(const float *__restrict__ l
     }
 }
 
-// Check pass for rows of degree <= DMAX held in registers.  One wavefront per
-// (row, slot group).  kFirst: iteration 1, Q = clamp(Lch), no R read.
-// kIter: Q = clamp(Lpost - R_old); when syn_iter > 0 the syndrome of the
-// previous estimate is checked and failing frames get fail[s] = syn_iter.
+// Plain-path slot state: kFirst is iteration 1 (L = Lch, no previous
+// messages); kIter reads Lpost and R_old.  When syn_iter > 0 the syndrome of
+// the previous estimate is checked and failing frames get fail[s] = syn_iter.
+template <int V>
+__device__ __forceinline__ void plain_syndrome(const int32_t (&st)[V], const int (&syn)[V], int32_t *fail, int s0,
+                                               int32_t syn_iter) {
+    if (syn_iter > 0) {
+#pragma unroll
+        for (int k = 0; k < V; k++)
+            if (st[k] == 0 && syn[k] && fail[s0 + k] != syn_iter) fail[s0 + k] = syn_iter;
+    }
+}
+
+// Rows of degree <= DMAX in registers: one wavefront per (row, slot group).
 template <int M, int V, int DMAX, int MODE>
 __global__ __launch_bounds__(256) void check_rows_kernel(
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx, const int32_t *__restrict__ rows,
@@ -99,77 +109,92 @@ __global__ __launch_bounds__(256) void check_rows_kernel(
     const int row = wave_uniform(rows[rk]);
     const int e0 = wave_uniform(row_ptr[row]);
     const int d = wave_uniform(row_ptr[row + 1]) - e0;
-
-    float u[DMAX][V];
-    float suf[DMAX][V];
-    uint32_t neg[V];
+    SlotSrc<V> src;
+#pragma unroll
+    for (int k = 0; k < V; k++) src.alt[k] = false;
+    src.any_alt = false;
+    src.read_r = MODE == kIter;
     int syn[V];
 #pragma unroll
-    for (int k = 0; k < V; k++) { neg[k] = 0u; syn[k] = 0; }
+    for (int k = 0; k < V; k++) syn[k] = 0;
+    row_rule<M, V, DMAX>(col_idx, e0, d, L, nullptr, R, S, s0, src, syn);
+    if (MODE == kIter) plain_syndrome<V>(st, syn, fail, s0, syn_iter);
+}
 
-#pragma unroll
-    for (int j = 0; j < DMAX; j++) {
-        if (j < d) {
-            const int v = wave_uniform(col_idx[e0 + j]);
-            float lv[V], r[V];
-            load_vec<kF32, V>(L + size_t(v) * S + s0, lv);
-            if (MODE == kIter) {
-                load_vec<M, V>(R + size_t(e0 + j) * S + s0, r);
-            } else {
-#pragma unroll
-                for (int k = 0; k < V; k++) r[k] = 0.f;
-            }
-#pragma unroll
-            for (int k = 0; k < V; k++) {
-                syn[k] ^= (lv[k] < 0.f);
-                const float q = clamp_msg(lv[k] - r[k]);
-                neg[k] |= uint32_t(q < 0.f) << j;
-                u[j][k] = tanh_complement(fabsf(q));
-            }
-        }
-    }
+// Rows of 9..128 edges: WPR wavefronts per (row, slot group), 8-edge chunks,
+// chunk aggregates exchanged through LDS.  A wavefront with more than one
+// chunk recomputes its chunks' inputs in the second phase.
+template <int M, int V, int WPR, int MODE>
+__global__ __launch_bounds__(256) void check_chunk_kernel(
+    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx, const int32_t *__restrict__ rows,
+    int32_t nrows, const float *__restrict__ L, typename Codec<M>::T *__restrict__ R,
+    const int32_t *__restrict__ iters, int32_t *__restrict__ fail, int32_t S, int32_t groups, int32_t syn_iter) {
+    constexpr int C = kRowChunk;
+    constexpr int RPB = 4 / WPR;
+    constexpr int MAXCH = WPR == 2 ? 2 : 16;
+    __shared__ ChunkShare<V, RPB * MAXCH> sh;
+    const int lane = threadIdx.x & 63;
+    const int wave = wave_uniform(threadIdx.x >> 6);
+    const int lr = wave / WPR;
+    const int wr = wave % WPR;
+    const int item = blockIdx.x * RPB + lr;
+    const int rk = item / groups;
+    const int g = item % groups;
+    const int s0 = (g * 64 + lane) * V;
 
-    // Exclusive suffixes, then exclusive prefixes combined on the fly.
-    float run[V];
+    int32_t st[V];
+    bool lane_active = false;
+    if (rk < nrows) {
+        load_i32<V>(iters + s0, st);
 #pragma unroll
-    for (int k = 0; k < V; k++) run[k] = 0.f;
-#pragma unroll
-    for (int j = DMAX - 1; j >= 0; j--) {
-        if (j < d) {
-#pragma unroll
-            for (int k = 0; k < V; k++) {
-                suf[j][k] = run[k];
-                run[k] = dplus(u[j][k], run[k]);
-            }
-        }
+        for (int k = 0; k < V; k++) lane_active |= (st[k] == 0);
     }
-    uint32_t parity[V];
-#pragma unroll
-    for (int k = 0; k < V; k++) { run[k] = 0.f; parity[k] = __builtin_popcount(neg[k]) & 1u; }
-#pragma unroll
-    for (int j = 0; j < DMAX; j++) {
-        if (j < d) {
-            float out[V];
-#pragma unroll
-            for (int k = 0; k < V; k++) {
-                const float mag = magnitude_from_complement(dplus(run[k], suf[j][k]));
-                const uint32_t sgn = parity[k] ^ ((neg[k] >> j) & 1u);
-                out[k] = sgn ? -mag : mag;
-                run[k] = dplus(run[k], u[j][k]);
-            }
-            store_vec<M, V>(R + size_t(e0 + j) * S + s0, out);
-        }
+    // same slots for every wavefront of a row: uniform over the row's wavefronts
+    const bool work = rk < nrows && __ballot(lane_active) != 0;
+    int row = 0, e0 = 0, d = 0, nch = 0;
+    if (work) {
+        row = wave_uniform(rows[rk]);
+        e0 = wave_uniform(row_ptr[row]);
+        d = wave_uniform(row_ptr[row + 1]) - e0;
+        nch = (d + C - 1) / C;
     }
-
-    if (MODE == kIter && syn_iter > 0) {
+    SlotSrc<V> src;
 #pragma unroll
-        for (int k = 0; k < V; k++) {
-            if (st[k] == 0 && syn[k] && fail[s0 + k] != syn_iter) fail[s0 + k] = syn_iter;
+    for (int k = 0; k < V; k++) src.alt[k] = false;
+    src.any_alt = false;
+    src.read_r = MODE == kIter;
+    const bool mine = work && lane_active;
+    float u[C][V], suf[C][V], agg[V];
+    uint32_t neg[V];
+    int syn[V];
+    for (int ch = wr; ch < nch; ch += WPR) {
+        if (mine) {
+            chunk_load<M, V, C>(col_idx, e0 + ch * C, min(C, d - ch * C), L, nullptr, R, S, s0, src, u, suf, agg,
+                                neg, syn);
+        } else {
+#pragma unroll
+            for (int k = 0; k < V; k++) { agg[k] = 0.f; neg[k] = 0u; syn[k] = 0; }
         }
+#pragma unroll
+        for (int k = 0; k < V; k++) sh.agg[lr * MAXCH + ch][lane][k] = agg[k];
+        sh.bits[lr * MAXCH + ch][lane] = pack_bits<V>(neg, syn);
+    }
+    __syncthreads();
+    if (!mine) return;
+    for (int ch = wr; ch < nch; ch += WPR) {
+        if (nch > WPR)
+            chunk_load<M, V, C>(col_idx, e0 + ch * C, min(C, d - ch * C), L, nullptr, R, S, s0, src, u, suf, agg,
+                                neg, syn);
+        float pre[V], post[V];
+        uint32_t parity[V];
+        int syn_row[V];
+        chunk_context<V, RPB * MAXCH>(sh, lr * MAXCH, nch, ch, lane, pre, post, parity, syn_row);
+        chunk_store<M, V, C>(e0 + ch * C, min(C, d - ch * C), u, suf, neg, pre, post, parity, R, S, s0);
+        if (MODE == kIter && ch == 0) plain_syndrome<V>(st, syn_row, fail, s0, syn_iter);
     }
 }
 
-// Check pass for long rows (degree > 32): one workgroup of four wavefronts per
+// Check pass for long rows (degree > 128): one workgroup of four wavefronts per
 // (row, 64-slot group).  The row is cut into 32-edge chunks; each chunk's
 // combined u (its D aggregate), sign parity and syndrome parity go to scratch,
 // one wavefront scans the chunk aggregates into per-chunk exclusive values,
@@ -493,6 +518,25 @@ void launch_rows(const ldpc_graph *g, int cls, int mode, const float *L, const B
                            g->d_col_idx, rows, nrows, L, R, b.iters, b.fail, S, groups, syn_iter);
 }
 
+template <int M, int V, int WPR>
+void launch_chunked(const ldpc_graph *g, int cls, int mode, const float *L, const Bufs &b, int32_t S,
+                    int32_t syn_iter, hipStream_t st) {
+    const int32_t nrows = g->class_begin[cls + 1] - g->class_begin[cls];
+    if (nrows == 0) return;
+    const int32_t groups = S / (64 * V);
+    const int64_t items = int64_t(nrows) * groups;
+    const unsigned blocks = unsigned((items + (4 / WPR) - 1) / (4 / WPR));
+    using T = typename Codec<M>::T;
+    T *R = static_cast<T *>(b.r);
+    const int32_t *rows = g->d_class_rows + g->class_begin[cls];
+    if (mode == kFirst)
+        hipLaunchKernelGGL((check_chunk_kernel<M, V, WPR, kFirst>), dim3(blocks), dim3(256), 0, st, g->d_row_ptr,
+                           g->d_col_idx, rows, nrows, L, R, b.iters, b.fail, S, groups, 0);
+    else
+        hipLaunchKernelGGL((check_chunk_kernel<M, V, WPR, kIter>), dim3(blocks), dim3(256), 0, st, g->d_row_ptr,
+                           g->d_col_idx, rows, nrows, L, R, b.iters, b.fail, S, groups, syn_iter);
+}
+
 template <int M>
 void launch_hub(const ldpc_graph *g, int mode, const float *L, const Bufs &b, int32_t S, int32_t syn_iter,
                 hipStream_t st) {
@@ -517,8 +561,9 @@ template <int M, int V>
 void launch_check_pass(const ldpc_graph *g, int mode, const float *L, const Bufs &b, int32_t S, int32_t syn_iter,
                        hipStream_t st) {
     launch_rows<M, V, 8>(g, ldpc::kClassD8, mode, L, b, S, syn_iter, st);
-    launch_rows<M, ldpc::class_lane_slots(ldpc::kClassD16, V), 16>(g, ldpc::kClassD16, mode, L, b, S, syn_iter, st);
-    launch_rows<M, ldpc::class_lane_slots(ldpc::kClassD32, V), 32>(g, ldpc::kClassD32, mode, L, b, S, syn_iter, st);
+    launch_chunked<M, V, ldpc::class_waves_per_row(ldpc::kClassD16)>(g, ldpc::kClassD16, mode, L, b, S, syn_iter, st);
+    launch_chunked<M, V, ldpc::class_waves_per_row(ldpc::kClassD128)>(g, ldpc::kClassD128, mode, L, b, S, syn_iter,
+                                                                       st);
     launch_hub<M>(g, mode, L, b, S, syn_iter, st);
 }
 

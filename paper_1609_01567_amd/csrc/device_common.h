@@ -104,4 +104,205 @@ __device__ __forceinline__ float clamp_msg(float q) { return fminf(fmaxf(q, -kLm
 
 __device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+
+// ----------------------------------------------------------- row building blocks
+
+// Where each of a lane's V frame slots takes its inputs in one check pass:
+// `read_r` false means every previous message is 0 (first iteration of every
+// slot); `alt[k]` marks a slot in its first iteration among slots that are not
+// (its L comes from the channel array and its previous message is 0).
+template <int V>
+struct SlotSrc {
+    bool alt[V];
+    bool any_alt;
+    bool read_r;
+};
+
+// Inputs of one edge for the lane's slots: Q = clamp(L - R_old), its sign bit
+// (into bit j of neg) and its u = 1 - tanh(|Q|/2); the sign of L feeds the
+// syndrome of the estimate that L holds (Algorithm 7).
+template <int M, int V>
+__device__ __forceinline__ void edge_input(const float *__restrict__ L, const float *__restrict__ Lalt,
+                                           const typename Codec<M>::T *__restrict__ R, size_t lofs, size_t rofs,
+                                           const SlotSrc<V> &src, int j, float (&u)[V], uint32_t (&neg)[V],
+                                           int (&syn)[V]) {
+    float lv[V], r[V];
+    load_vec<kF32, V>(L + lofs, lv);
+    if (src.any_alt) {
+        float lc[V];
+        load_vec<kF32, V>(Lalt + lofs, lc);
+#pragma unroll
+        for (int k = 0; k < V; k++) if (src.alt[k]) lv[k] = lc[k];
+    }
+    if (src.read_r) {
+        load_vec<M, V>(R + rofs, r);
+        if (src.any_alt) {
+#pragma unroll
+            for (int k = 0; k < V; k++) if (src.alt[k]) r[k] = 0.f;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < V; k++) r[k] = 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < V; k++) {
+        syn[k] ^= (lv[k] < 0.f);
+        const float q = clamp_msg(lv[k] - r[k]);
+        neg[k] |= uint32_t(q < 0.f) << j;
+        u[k] = tanh_complement(fabsf(q));
+    }
+}
+
+// Check rule for a whole row of d <= DMAX edges held in registers: exclusive
+// suffixes, then exclusive prefixes combined on the fly; R is updated in place.
+template <int M, int V, int DMAX>
+__device__ __forceinline__ void row_rule(const int32_t *__restrict__ col_idx, int e0, int d,
+                                         const float *__restrict__ L, const float *__restrict__ Lalt,
+                                         typename Codec<M>::T *__restrict__ R, int32_t S, int s0,
+                                         const SlotSrc<V> &src, int (&syn)[V]) {
+    float u[DMAX][V];
+    float suf[DMAX][V];
+    uint32_t neg[V];
+#pragma unroll
+    for (int k = 0; k < V; k++) neg[k] = 0u;
+#pragma unroll
+    for (int j = 0; j < DMAX; j++) {
+        if (j < d) {
+            const int v = wave_uniform(col_idx[e0 + j]);
+            edge_input<M, V>(L, Lalt, R, size_t(v) * S + s0, size_t(e0 + j) * S + s0, src, j, u[j], neg, syn);
+        }
+    }
+    float run[V];
+#pragma unroll
+    for (int k = 0; k < V; k++) run[k] = 0.f;
+#pragma unroll
+    for (int j = DMAX - 1; j >= 0; j--) {
+        if (j < d) {
+#pragma unroll
+            for (int k = 0; k < V; k++) {
+                suf[j][k] = run[k];
+                run[k] = dplus(u[j][k], run[k]);
+            }
+        }
+    }
+    uint32_t parity[V];
+#pragma unroll
+    for (int k = 0; k < V; k++) { run[k] = 0.f; parity[k] = __builtin_popcount(neg[k]) & 1u; }
+#pragma unroll
+    for (int j = 0; j < DMAX; j++) {
+        if (j < d) {
+            float out[V];
+#pragma unroll
+            for (int k = 0; k < V; k++) {
+                const float mag = magnitude_from_complement(dplus(run[k], suf[j][k]));
+                const uint32_t sgn = parity[k] ^ ((neg[k] >> j) & 1u);
+                out[k] = sgn ? -mag : mag;
+                run[k] = dplus(run[k], u[j][k]);
+            }
+            store_vec<M, V>(R + size_t(e0 + j) * S + s0, out);
+        }
+    }
+}
+
+// Chunked rows: a row is cut into chunks of C edges handled by different
+// wavefronts.  chunk_load forms a chunk's u's, exclusive in-chunk suffixes and
+// its aggregate (the u's combined), sign bits and syndrome parity;
+// chunk_store finishes the chunk given the aggregate of the chunks before it
+// (pre), of the chunks after it (post) and the row's total sign parity.
+constexpr int kRowChunk = 8;
+
+template <int M, int V, int C>
+__device__ __forceinline__ void chunk_load(const int32_t *__restrict__ col_idx, int j0, int dc,
+                                           const float *__restrict__ L, const float *__restrict__ Lalt,
+                                           const typename Codec<M>::T *__restrict__ R, int32_t S, int s0,
+                                           const SlotSrc<V> &src, float (&u)[C][V], float (&suf)[C][V],
+                                           float (&agg)[V], uint32_t (&neg)[V], int (&syn)[V]) {
+#pragma unroll
+    for (int k = 0; k < V; k++) { neg[k] = 0u; syn[k] = 0; }
+#pragma unroll
+    for (int j = 0; j < C; j++) {
+        if (j < dc) {
+            const int v = wave_uniform(col_idx[j0 + j]);
+            edge_input<M, V>(L, Lalt, R, size_t(v) * S + s0, size_t(j0 + j) * S + s0, src, j, u[j], neg, syn);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < V; k++) agg[k] = 0.f;
+#pragma unroll
+    for (int j = C - 1; j >= 0; j--) {
+        if (j < dc) {
+#pragma unroll
+            for (int k = 0; k < V; k++) {
+                suf[j][k] = agg[k];
+                agg[k] = dplus(u[j][k], agg[k]);
+            }
+        }
+    }
+}
+
+template <int M, int V, int C>
+__device__ __forceinline__ void chunk_store(int j0, int dc, const float (&u)[C][V], const float (&suf)[C][V],
+                                            const uint32_t (&neg)[V], const float (&pre)[V], const float (&post)[V],
+                                            const uint32_t (&parity)[V], typename Codec<M>::T *__restrict__ R,
+                                            int32_t S, int s0) {
+    float run[V];
+#pragma unroll
+    for (int k = 0; k < V; k++) run[k] = pre[k];
+#pragma unroll
+    for (int j = 0; j < C; j++) {
+        if (j < dc) {
+            float out[V];
+#pragma unroll
+            for (int k = 0; k < V; k++) {
+                const float mag = magnitude_from_complement(dplus(run[k], dplus(suf[j][k], post[k])));
+                const uint32_t sgn = parity[k] ^ ((neg[k] >> j) & 1u);
+                out[k] = sgn ? -mag : mag;
+                run[k] = dplus(run[k], u[j][k]);
+            }
+            store_vec<M, V>(R + size_t(j0 + j) * S + s0, out);
+        }
+    }
+}
+
+// Chunk aggregates of one row exchanged through LDS: each entry is a lane's
+// V aggregates plus packed sign parities (bits 0..V-1) and syndrome parities
+// (bits 8..8+V-1).
+template <int V, int ENTRIES>
+struct ChunkShare {
+    float agg[ENTRIES][64][V];
+    uint32_t bits[ENTRIES][64];
+};
+
+template <int V>
+__device__ __forceinline__ uint32_t pack_bits(const uint32_t (&neg)[V], const int (&syn)[V]) {
+    uint32_t b = 0u;
+#pragma unroll
+    for (int k = 0; k < V; k++) b |= ((__builtin_popcount(neg[k]) & 1u) << k) | (uint32_t(syn[k] & 1) << (8 + k));
+    return b;
+}
+
+// pre/post aggregates and total parities of chunk `ch` of a row of nch chunks
+// whose entries start at `base` in the shared table.
+template <int V, int ENTRIES>
+__device__ __forceinline__ void chunk_context(const ChunkShare<V, ENTRIES> &sh, int base, int nch, int ch, int lane,
+                                              float (&pre)[V], float (&post)[V], uint32_t (&parity)[V],
+                                              int (&syn)[V]) {
+    uint32_t tot = 0u;
+#pragma unroll
+    for (int k = 0; k < V; k++) { pre[k] = 0.f; post[k] = 0.f; }
+    for (int c = 0; c < nch; c++) {
+        tot ^= sh.bits[base + c][lane];
+        if (c < ch) {
+#pragma unroll
+            for (int k = 0; k < V; k++) pre[k] = dplus(pre[k], sh.agg[base + c][lane][k]);
+        }
+    }
+    for (int c = nch - 1; c > ch; c--) {
+#pragma unroll
+        for (int k = 0; k < V; k++) post[k] = dplus(sh.agg[base + c][lane][k], post[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < V; k++) { parity[k] = (tot >> k) & 1u; syn[k] = int((tot >> (8 + k)) & 1u); }
+}
+
 }  // namespace ldpc_dev

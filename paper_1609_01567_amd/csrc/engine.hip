@@ -87,6 +87,42 @@ __device__ __forceinline__ bool slot_stops(int32_t t, int32_t fail, int32_t T, i
 
 // ------------------------------------------------------------- check pass
 
+// Per-slot state of a lane's V slots: occupied, first iteration (L from the
+// channel array, no previous message), and whether the syndrome of the slot's
+// current estimate is checked in this pass.
+template <int V>
+struct EngLane {
+    int32_t t[V];
+    bool syn_on[V];
+    bool active;
+    SlotSrc<V> src;
+};
+
+template <int V>
+__device__ __forceinline__ void eng_lane(const EngGraph &G, int s0, int32_t T, int32_t early, EngLane<V> &ln) {
+    int32_t q[V];
+    load_i32<V>(G.slot_q + s0, q);
+    load_i32<V>(G.slot_t + s0, ln.t);
+    ln.active = false;
+    ln.src.any_alt = false;
+    ln.src.read_r = true;
+#pragma unroll
+    for (int k = 0; k < V; k++) {
+        const bool act = q[k] >= 0;
+        ln.src.alt[k] = act && ln.t[k] == 0;
+        ln.syn_on[k] = act && ln.t[k] >= 1 && (early || ln.t[k] == T);
+        ln.active |= act;
+        ln.src.any_alt |= ln.src.alt[k];
+    }
+}
+
+template <int V>
+__device__ __forceinline__ void eng_syndrome(const EngGraph &G, const EngLane<V> &ln, const int (&syn)[V], int s0) {
+#pragma unroll
+    for (int k = 0; k < V; k++)
+        if (ln.syn_on[k] && syn[k] && G.fail[s0 + k] != ln.t[k]) G.fail[s0 + k] = ln.t[k];
+}
+
 template <int M, int V, int DMAX>
 __global__ __launch_bounds__(256) void eng_check_rows(const EngGraph *__restrict__ graphs, Prefix pre, int32_t cls,
                                                       int32_t T, int32_t early) {
@@ -102,93 +138,87 @@ __global__ __launch_bounds__(256) void eng_check_rows(const EngGraph *__restrict
     const int g = local % groups;
     const int rk = local / groups;
     const int s0 = (g * 64 + lane) * V;
-
-    int32_t q[V], t[V];
-    load_i32<V>(G.slot_q + s0, q);
-    load_i32<V>(G.slot_t + s0, t);
-    bool lane_active = false, any_first = false;
-    bool first[V], syn_on[V];
-#pragma unroll
-    for (int k = 0; k < V; k++) {
-        const bool act = q[k] >= 0;
-        first[k] = act && t[k] == 0;
-        syn_on[k] = act && t[k] >= 1 && (early || t[k] == T);
-        lane_active |= act;
-        any_first |= first[k];
-    }
-    if (__ballot(lane_active) == 0) return;
-    if (!lane_active) return;
-
+    EngLane<V> ln;
+    eng_lane<V>(G, s0, T, early, ln);
+    if (__ballot(ln.active) == 0) return;
+    if (!ln.active) return;
     const int row = wave_uniform(G.class_rows[G.class_begin[cls] + rk]);
     const int e0 = wave_uniform(G.row_ptr[row]);
     const int d = wave_uniform(G.row_ptr[row + 1]) - e0;
-    MT *R = static_cast<MT *>(G.r);
-
-    float u[DMAX][V];
-    float suf[DMAX][V];
-    uint32_t neg[V];
     int syn[V];
 #pragma unroll
-    for (int k = 0; k < V; k++) { neg[k] = 0u; syn[k] = 0; }
-#pragma unroll
-    for (int j = 0; j < DMAX; j++) {
-        if (j < d) {
-            const int v = wave_uniform(G.col_idx[e0 + j]);
-            float lv[V], r[V];
-            load_vec<kF32, V>(G.lpost + size_t(v) * S + s0, lv);
-            if (any_first) {
-                float lc[V];
-                load_vec<kF32, V>(G.lch + size_t(v) * S + s0, lc);
-#pragma unroll
-                for (int k = 0; k < V; k++) if (first[k]) lv[k] = lc[k];
-            }
-            load_vec<M, V>(R + size_t(e0 + j) * S + s0, r);
-#pragma unroll
-            for (int k = 0; k < V; k++) {
-                if (first[k]) r[k] = 0.f;
-                syn[k] ^= (lv[k] < 0.f);
-                const float qv = clamp_msg(lv[k] - r[k]);
-                neg[k] |= uint32_t(qv < 0.f) << j;
-                u[j][k] = tanh_complement(fabsf(qv));
-            }
-        }
-    }
-    float run[V];
-#pragma unroll
-    for (int k = 0; k < V; k++) run[k] = 0.f;
-#pragma unroll
-    for (int j = DMAX - 1; j >= 0; j--) {
-        if (j < d) {
-#pragma unroll
-            for (int k = 0; k < V; k++) {
-                suf[j][k] = run[k];
-                run[k] = dplus(u[j][k], run[k]);
-            }
-        }
-    }
-    uint32_t parity[V];
-#pragma unroll
-    for (int k = 0; k < V; k++) { run[k] = 0.f; parity[k] = __builtin_popcount(neg[k]) & 1u; }
-#pragma unroll
-    for (int j = 0; j < DMAX; j++) {
-        if (j < d) {
-            float out[V];
-#pragma unroll
-            for (int k = 0; k < V; k++) {
-                const float mag = magnitude_from_complement(dplus(run[k], suf[j][k]));
-                const uint32_t sgn = parity[k] ^ ((neg[k] >> j) & 1u);
-                out[k] = sgn ? -mag : mag;
-                run[k] = dplus(run[k], u[j][k]);
-            }
-            store_vec<M, V>(R + size_t(e0 + j) * S + s0, out);
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < V; k++)
-        if (syn_on[k] && syn[k] && G.fail[s0 + k] != t[k]) G.fail[s0 + k] = t[k];
+    for (int k = 0; k < V; k++) syn[k] = 0;
+    row_rule<M, V, DMAX>(G.col_idx, e0, d, G.lpost, G.lch, static_cast<MT *>(G.r), S, s0, ln.src, syn);
+    eng_syndrome<V>(G, ln, syn, s0);
 }
 
-// Rows longer than 32 edges: one workgroup of four wavefronts per (row, 64 slots),
+// Rows of 9..128 edges over WPR wavefronts (see check_chunk_kernel in decode.hip).
+template <int M, int V, int WPR>
+__global__ __launch_bounds__(256) void eng_check_chunk(const EngGraph *__restrict__ graphs, Prefix pre, int32_t cls,
+                                                       int32_t T, int32_t early) {
+    using MT = typename Codec<M>::T;
+    constexpr int C = kRowChunk;
+    constexpr int RPB = 4 / WPR;
+    constexpr int MAXCH = WPR == 2 ? 2 : 16;
+    __shared__ ChunkShare<V, RPB * MAXCH> sh;
+    if (int(blockIdx.x) >= pre.p[pre.count]) return;      // uniform over the block
+    const int lane = threadIdx.x & 63;
+    const int wave = wave_uniform(threadIdx.x >> 6);
+    const int lr = wave / WPR;
+    const int wr = wave % WPR;
+    const int c = find_graph(pre, blockIdx.x);
+    const EngGraph &G = graphs[c];
+    const int32_t S = G.S;
+    const int groups = S / (64 * V);
+    const int item = (blockIdx.x - pre.p[c]) * RPB + lr;
+    const int rk = item / groups;
+    const int g = item % groups;
+    const int s0 = (g * 64 + lane) * V;
+    const int nrows = G.class_begin[cls + 1] - G.class_begin[cls];
+    EngLane<V> ln;
+    ln.active = false;
+    if (rk < nrows) eng_lane<V>(G, s0, T, early, ln);
+    const bool work = rk < nrows && __ballot(ln.active) != 0;
+    int e0 = 0, d = 0, nch = 0;
+    if (work) {
+        const int row = wave_uniform(G.class_rows[G.class_begin[cls] + rk]);
+        e0 = wave_uniform(G.row_ptr[row]);
+        d = wave_uniform(G.row_ptr[row + 1]) - e0;
+        nch = (d + C - 1) / C;
+    }
+    MT *R = static_cast<MT *>(G.r);
+    const bool mine = work && ln.active;
+    float u[C][V], suf[C][V], agg[V];
+    uint32_t neg[V];
+    int syn[V];
+    for (int ch = wr; ch < nch; ch += WPR) {
+        if (mine) {
+            chunk_load<M, V, C>(G.col_idx, e0 + ch * C, min(C, d - ch * C), G.lpost, G.lch, R, S, s0, ln.src, u, suf,
+                                agg, neg, syn);
+        } else {
+#pragma unroll
+            for (int k = 0; k < V; k++) { agg[k] = 0.f; neg[k] = 0u; syn[k] = 0; }
+        }
+#pragma unroll
+        for (int k = 0; k < V; k++) sh.agg[lr * MAXCH + ch][lane][k] = agg[k];
+        sh.bits[lr * MAXCH + ch][lane] = pack_bits<V>(neg, syn);
+    }
+    __syncthreads();
+    if (!mine) return;
+    for (int ch = wr; ch < nch; ch += WPR) {
+        if (nch > WPR)
+            chunk_load<M, V, C>(G.col_idx, e0 + ch * C, min(C, d - ch * C), G.lpost, G.lch, R, S, s0, ln.src, u, suf,
+                                agg, neg, syn);
+        float pre_a[V], post_a[V];
+        uint32_t parity[V];
+        int syn_row[V];
+        chunk_context<V, RPB * MAXCH>(sh, lr * MAXCH, nch, ch, lane, pre_a, post_a, parity, syn_row);
+        chunk_store<M, V, C>(e0 + ch * C, min(C, d - ch * C), u, suf, neg, pre_a, post_a, parity, R, S, s0);
+        if (ch == 0) eng_syndrome<V>(G, ln, syn_row, s0);
+    }
+}
+
+// Rows longer than 128 edges: one workgroup of four wavefronts per (row, 64 slots),
 // 32-edge chunks combined through an exclusive prefix/suffix scan in scratch.
 template <int M>
 __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict__ graphs, Prefix pre, int32_t T,
@@ -524,11 +554,13 @@ void enqueue_step(ldpc_engine *e) {
         hipLaunchKernelGGL((eng_check_rows<M, V, 8>), dim3(unsigned((e->row_waves[0] + 3) / 4)), dim3(256), 0, st,
                            e->d_graphs, e->pre_rows[0], int32_t(ldpc::kClassD8), e->T, early);
     if (e->has_rows[1])
-        hipLaunchKernelGGL((eng_check_rows<M, ldpc::class_lane_slots(ldpc::kClassD16, V), 16>), dim3(unsigned((e->row_waves[1] + 3) / 4)),
-                           dim3(256), 0, st, e->d_graphs, e->pre_rows[1], int32_t(ldpc::kClassD16), e->T, early);
+        hipLaunchKernelGGL((eng_check_chunk<M, V, ldpc::class_waves_per_row(ldpc::kClassD16)>),
+                           dim3(unsigned(e->row_waves[1])), dim3(256), 0, st, e->d_graphs, e->pre_rows[1],
+                           int32_t(ldpc::kClassD16), e->T, early);
     if (e->has_rows[2])
-        hipLaunchKernelGGL((eng_check_rows<M, ldpc::class_lane_slots(ldpc::kClassD32, V), 32>), dim3(unsigned((e->row_waves[2] + 3) / 4)), dim3(256), 0, st,
-                           e->d_graphs, e->pre_rows[2], int32_t(ldpc::kClassD32), e->T, early);
+        hipLaunchKernelGGL((eng_check_chunk<M, V, ldpc::class_waves_per_row(ldpc::kClassD128)>),
+                           dim3(unsigned(e->row_waves[2])), dim3(256), 0, st, e->d_graphs, e->pre_rows[2],
+                           int32_t(ldpc::kClassD128), e->T, early);
     if (e->has_hub)
         hipLaunchKernelGGL((eng_check_hub<M>), dim3(unsigned(e->hub_blocks)), dim3(256), 0, st, e->d_graphs,
                            e->pre_hub, e->T, early);
@@ -713,18 +745,18 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
         return hip_fail(e, "ldpc_engine_create: initialisation", err);
 
     // work prefix tables
-    const int vk[3] = {ldpc::class_lane_slots(ldpc::kClassD8, V), ldpc::class_lane_slots(ldpc::kClassD16, V),
-                       ldpc::class_lane_slots(ldpc::kClassD32, V)};
+    // D8: waves of one (row, slot group) each; chunked classes: 256-thread blocks of 4 / WPR (row, group) items
     for (int k = 0; k < 3; k++) {
         Prefix &p = e->pre_rows[k];
         p.count = ngraphs;
         p.p[0] = 0;
+        const int rpb = k == 0 ? 1 : 4 / ldpc::class_waves_per_row(k);
         for (int32_t c = 0; c < ngraphs; c++) {
             const ldpc_graph *g = graphs[c];
-            const int64_t rows = g->class_begin[k + 1] - g->class_begin[k];
-            p.p[c + 1] = int32_t(p.p[c] + rows * (e->S[size_t(c)] / (64 * vk[k])));
+            const int64_t items = int64_t(g->class_begin[k + 1] - g->class_begin[k]) * (e->S[size_t(c)] / (64 * V));
+            p.p[c + 1] = int32_t(p.p[c] + (items + rpb - 1) / rpb);
         }
-        e->row_waves[k] = p.p[ngraphs];
+        e->row_waves[k] = p.p[ngraphs];   // waves (D8) or blocks (chunked classes)
         e->has_rows[k] = e->row_waves[k] > 0;
     }
     e->pre_hub.count = ngraphs;

@@ -9,22 +9,24 @@
 
 namespace ldpc {
 
-// Check rows are grouped by degree into classes, one kernel shape per class
-// (register-resident rows up to 8, 16 or 32 edges, and a segmented path for
-// longer rows that splits a row into 32-edge chunks over several wavefronts).
-enum CheckClass : int { kClassD8 = 0, kClassD16 = 1, kClassD32 = 2, kClassHub = 3, kNumClasses = 4 };
+// Check rows are grouped by degree into classes, one kernel shape per class:
+// rows of up to 8 edges in one wavefront's registers; rows of 9..16 and
+// 17..128 edges cut into 8-edge chunks over 2 or 4 wavefronts that exchange
+// chunk aggregates through LDS; longer rows on a segmented path that splits
+// them into 32-edge chunks with aggregates in global scratch (no degree bound).
+enum CheckClass : int { kClassD8 = 0, kClassD16 = 1, kClassD128 = 2, kClassHub = 3, kNumClasses = 4 };
 constexpr int kHubChunk = 32;   // edges per chunk on the segmented path
 
 inline int check_class_of(int d) {
-    return d <= 8 ? kClassD8 : d <= 16 ? kClassD16 : d <= 32 ? kClassD32 : kClassHub;
+    return d <= 8 ? kClassD8 : d <= 16 ? kClassD16 : d <= 128 ? kClassD128 : kClassHub;
 }
 
-// Frame slots per wavefront lane of the register check kernels for a class,
-// when the decode uses V slots per lane elsewhere.  Register use grows as
-// 2 * DMAX * slots per lane, so the widest rows use fewer slots.
-constexpr int class_lane_slots(int cls, int V) {
-    return cls == kClassD8 ? V : cls == kClassD16 ? V : (V < 2 ? V : 2);
-}
+// Wavefronts per row of the chunked classes (rows per 256-thread block = 4 / this).
+constexpr int class_waves_per_row(int cls) { return cls == kClassD16 ? 2 : cls == kClassD128 ? 4 : 1; }
+
+// Frame slots per wavefront lane for a class when the decode uses V slots per
+// lane elsewhere (the segmented path always uses 1).
+constexpr int class_lane_slots(int cls, int V) { return cls == kClassHub ? 1 : V; }
 
 void set_error(const std::string &msg);
 

@@ -68,6 +68,8 @@ def parse():
                     help="slot-pool sizes tried for the refill engine on the same workload")
     ap.add_argument("--no-engine", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=3000)
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates rocprof byte counters) and exit")
     return ap.parse_args()
@@ -282,6 +284,102 @@ def bench_batched(torch, ldpc, steps, warmup, T=50):
     }
 
 
+def bench_served(torch, ldpc, capacity_fps, requests, loads=(0.25, 0.5, 0.75, 0.95), T=50, seed=4001):
+    """Poisson arrivals of requests (1..64 frames of one of the eight batch codes,
+    code drawn Zipf(1) by ascending n) at fractions of the measured batch
+    capacity; the server (continuous batching, FP16 messages) against plain
+    per-request FP32 launches in arrival order on one stream."""
+    from paper_1609_01567_amd import workloads
+    import ldpc_inputs as li
+    codes = li.batch_codes()
+    pts = workloads.operating_points()
+    pool_f = 128
+    pools = []
+    for i, c in enumerate(codes):
+        cw = li.Encoder(c).random_codewords(pool_f, seed=5100 + i)
+        pools.append(li.awgn_llr(c.n, pool_f, li.ebn0_to_sigma2(pts[c.name], c.rate), seed=5200 + i, codewords=cw))
+    kinfo = np.array([c.n - c.m for c in codes], np.float64)
+    zipf = 1.0 / np.arange(1, len(codes) + 1)
+    zipf /= zipf.sum()
+    mean_frames = 32.5
+    graphs = [ldpc.Graph.from_code(c) for c in codes]
+    out = {"capacity_frames_per_s": round(capacity_fps, 1), "requests_per_load": requests,
+           "workload": "Poisson arrivals; request = U{1..64} frames of one code (Zipf(1) over the 8 batch codes), "
+                       "Eb/N0 = waterfall + 0.5 dB, max 50 iterations", "loads": []}
+    srv = ldpc.Server(graphs, [256] * len(codes), T, flags=ldpc.MSG_FP16, hbm_budget=2 << 30,
+                      host_budget=1 << 30, lane_slots=4, graph_steps=2)
+    for rho in loads:
+        rng = np.random.default_rng(seed + int(rho * 100))
+        lam = rho * capacity_fps / mean_frames
+        gaps = rng.exponential(1.0 / lam, size=requests)
+        gis = rng.choice(len(codes), size=requests, p=zipf)
+        fs = rng.integers(1, 65, size=requests)
+        starts = rng.integers(0, pool_f - 64 + 1, size=requests)
+        lat, info = [], 0.0
+        pending = {}
+        t0 = time.perf_counter()
+        t_arr = t0
+        for r in range(requests):
+            t_arr += gaps[r]
+            while time.perf_counter() < t_arr:
+                for rid in srv.poll(0):
+                    _, _, _, l = srv.result(rid, want_bits=False)
+                    lat.append(l)
+                    info += pending.pop(rid)
+            gi, F, st = int(gis[r]), int(fs[r]), int(starts[r])
+            rid = srv.submit(gi, pools[gi][st:st + F])
+            pending[rid] = F * kinfo[gi]
+        deadline = time.perf_counter() + 60
+        while pending and time.perf_counter() < deadline:
+            for rid in srv.poll(20):
+                _, _, _, l = srv.result(rid, want_bits=False)
+                lat.append(l)
+                info += pending.pop(rid)
+        wall = time.perf_counter() - t0
+        lat = np.array(lat)
+        out["loads"].append({"offered": rho, "offered_req_per_s": round(lam, 1), "completed": int(lat.size),
+                             "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                             "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                             "gbits": round(info / wall / 1e9, 4), "wall_s": round(wall, 2)})
+        print(f"[bench] served load {rho}: p50 {out['loads'][-1]['p50_ms']} ms p99 {out['loads'][-1]['p99_ms']} ms "
+              f"{out['loads'][-1]['gbits']} Gbit/s", file=sys.stderr, flush=True)
+    out["server_stats"] = srv.stats()
+    srv.close()
+
+    # plain per-request FP32 launches, FIFO in arrival order, same request stream at the lowest load
+    rho = loads[0]
+    rng = np.random.default_rng(seed + int(rho * 100))
+    lam = rho * capacity_fps / mean_frames
+    n_plain = min(requests, 400)
+    gaps = rng.exponential(1.0 / lam, size=requests)[:n_plain]
+    gis = rng.choice(len(codes), size=requests, p=zipf)[:n_plain]
+    fs = rng.integers(1, 65, size=requests)[:n_plain]
+    starts = rng.integers(0, pool_f - 64 + 1, size=requests)[:n_plain]
+    d_pools = [torch.from_numpy(x).cuda() for x in pools]
+    lat, info = [], 0.0
+    t0 = time.perf_counter()
+    t_arr = t0
+    for r in range(n_plain):
+        t_arr += gaps[r]
+        while time.perf_counter() < t_arr:
+            pass
+        gi, F, st = int(gis[r]), int(fs[r]), int(starts[r])
+        x = d_pools[gi][st:st + F].contiguous()
+        res = ldpc.decode(graphs[gi], x, T)
+        res.bits.cpu()
+        lat.append(time.perf_counter() - t_arr)
+        info += F * kinfo[gi]
+    wall = time.perf_counter() - t0
+    lat = np.array(lat)
+    out["plain_per_request_fp32"] = {"offered": rho, "requests": n_plain,
+                                     "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                                     "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                                     "gbits": round(info / wall / 1e9, 4),
+                                     "note": "one ldpc_decode per request in arrival order; the stream falls behind "
+                                             "when its service time exceeds the arrival gap, so latency grows"}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -414,6 +512,11 @@ def main():
     if not args.no_batched:
         batched = bench_batched(torch, ldpc, max(1, args.steps), args.warmup)
         print(f"[bench] batched done", file=sys.stderr, flush=True)
+    served = None
+    if not args.no_served:
+        cap = 4096.0 / (batched["engine_fp16"]["ms_per_step"] * 1e-3) if batched else 150000.0
+        served = bench_served(torch, ldpc, cap, args.served_requests)
+        print(f"[bench] served done", file=sys.stderr, flush=True)
 
     ceiling = copy_ceiling(torch)
     cpu = None
@@ -446,6 +549,7 @@ def main():
         "phases": phase,
         "engine_same_workload": engine,
         "batched": batched,
+        "served": served,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

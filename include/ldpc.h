@@ -259,7 +259,9 @@ LDPC_API ldpc_status ldpc_engine_info(const ldpc_engine *e, int64_t *device_byte
 LDPC_API ldpc_status ldpc_engine_submit(ldpc_engine *e, int32_t graph, const ldpc_frame *frames,
                                         int32_t count, void *hip_stream);
 
-/* Free queue capacity of `graph` as of the last ldpc_engine_poll/run. */
+/* Free queue capacity of `graph`, from the newest queue counters the engine
+ * has seen: those of the last ldpc_engine_poll/run, or of any replay already
+ * finished on the device (checked without waiting). */
 LDPC_API ldpc_status ldpc_engine_capacity(const ldpc_engine *e, int32_t graph, int32_t *free_entries);
 
 /* Enqueue `replays` hipGraph replays (replays * graph_steps decode steps) on the
@@ -272,6 +274,10 @@ LDPC_API ldpc_status ldpc_engine_step(ldpc_engine *e, int32_t replays);
  * finished (pending, [ngraphs], may be NULL).
  */
 LDPC_API ldpc_status ldpc_engine_poll(ldpc_engine *e, int64_t *retired, int64_t *pending);
+
+/* The engine's HIP stream (owned by the engine; do not destroy it).  Work
+ * enqueued on it after ldpc_engine_step runs after those steps. */
+LDPC_API ldpc_status ldpc_engine_stream(const ldpc_engine *e, void **hip_stream);
 
 /*
  * Step until every submitted frame has finished or `max_replays` replays have

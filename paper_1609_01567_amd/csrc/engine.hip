@@ -532,6 +532,10 @@ struct ldpc_engine {
     ldpc_frame *h_stage = nullptr;   // pinned mirror of every queue ring
     std::vector<size_t> stage_off;
     int32_t *h_counters = nullptr;   // pinned copy of d_counters
+    int32_t *h_async[2] = {nullptr, nullptr};   // counters copied after replays, by replay parity
+    hipEvent_t ev_async[2] = {nullptr, nullptr};
+    bool async_pending[2] = {false, false};
+    int parity = 0;
     std::vector<int64_t> submitted, head_seen, retired_seen;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -599,6 +603,10 @@ void destroy_engine(ldpc_engine *e) {
     if (e->dmem) (void)hipFree(e->dmem);
     if (e->h_stage) (void)hipHostFree(e->h_stage);
     if (e->h_counters) (void)hipHostFree(e->h_counters);
+    for (int p = 0; p < 2; p++) {
+        if (e->h_async[p]) (void)hipHostFree(e->h_async[p]);
+        if (e->ev_async[p]) (void)hipEventDestroy(e->ev_async[p]);
+    }
     if (e->stream) (void)hipStreamDestroy(e->stream);
     (void)hipGetLastError();
     delete e;
@@ -780,7 +788,11 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
     size_t stage = 0;
     for (int32_t c = 0; c < ngraphs; c++) { e->stage_off.push_back(stage); stage += size_t(e->cap[size_t(c)]); }
     if ((err = hipHostMalloc(reinterpret_cast<void **>(&e->h_stage), stage * sizeof(ldpc_frame), 0)) != hipSuccess ||
-        (err = hipHostMalloc(reinterpret_cast<void **>(&e->h_counters), size_t(ngraphs) * 20, 0)) != hipSuccess)
+        (err = hipHostMalloc(reinterpret_cast<void **>(&e->h_counters), size_t(ngraphs) * 20, 0)) != hipSuccess ||
+        (err = hipHostMalloc(reinterpret_cast<void **>(&e->h_async[0]), size_t(ngraphs) * 20, 0)) != hipSuccess ||
+        (err = hipHostMalloc(reinterpret_cast<void **>(&e->h_async[1]), size_t(ngraphs) * 20, 0)) != hipSuccess ||
+        (err = hipEventCreateWithFlags(&e->ev_async[0], hipEventDisableTiming)) != hipSuccess ||
+        (err = hipEventCreateWithFlags(&e->ev_async[1], hipEventDisableTiming)) != hipSuccess)
         return hip_fail(e, "ldpc_engine_create: hipHostMalloc", err);
     e->submitted.assign(size_t(ngraphs), 0);
     e->head_seen.assign(size_t(ngraphs), 0);
@@ -811,8 +823,39 @@ extern "C" ldpc_status ldpc_engine_info(const ldpc_engine *e, int64_t *device_by
     return LDPC_OK;
 }
 
-extern "C" ldpc_status ldpc_engine_capacity(const ldpc_engine *e, int32_t graph, int32_t *free_entries) {
+namespace {
+
+// Take queue counters from replays that have already finished, without waiting.
+void absorb_counters(ldpc_engine *e, const int32_t *h) {
+    for (int32_t c = 0; c < e->ngraphs; c++) {
+        const int64_t head = int64_t(h[4 * c]) + h[4 * e->ngraphs + c];
+        e->head_seen[size_t(c)] = std::max(e->head_seen[size_t(c)], head);
+        e->retired_seen[size_t(c)] = std::max<int64_t>(e->retired_seen[size_t(c)], h[4 * c + 2]);
+    }
+}
+
+void refresh_counters(ldpc_engine *e) {
+    for (int p = 0; p < 2; p++) {
+        if (e->async_pending[p] && hipEventQuery(e->ev_async[p]) == hipSuccess) {
+            absorb_counters(e, e->h_async[p]);
+            e->async_pending[p] = false;
+        }
+    }
+    (void)hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" ldpc_status ldpc_engine_stream(const ldpc_engine *e, void **hip_stream) {
+    if (!e || !hip_stream) { set_error("ldpc_engine_stream: bad argument"); return LDPC_E_INVAL; }
+    *hip_stream = e->stream;
+    return LDPC_OK;
+}
+
+extern "C" ldpc_status ldpc_engine_capacity(const ldpc_engine *e_const, int32_t graph, int32_t *free_entries) {
+    ldpc_engine *e = const_cast<ldpc_engine *>(e_const);
     if (!e || !free_entries || graph < 0 || graph >= e->ngraphs) { set_error("ldpc_engine_capacity: bad argument"); return LDPC_E_INVAL; }
+    refresh_counters(e);
     const size_t c = size_t(graph);
     *free_entries = int32_t(e->cap[c] - (e->submitted[c] - e->head_seen[c]));
     return LDPC_OK;
@@ -826,6 +869,7 @@ extern "C" ldpc_status ldpc_engine_submit(ldpc_engine *e, int32_t graph, const l
     }
     if (count == 0) return LDPC_OK;
     const size_t c = size_t(graph);
+    refresh_counters(e);
     const int64_t in_queue = e->submitted[c] - e->head_seen[c];
     if (in_queue + count > e->cap[c]) {
         set_error("ldpc_engine_submit: queue of graph " + std::to_string(graph) + " is full (" +
@@ -873,9 +917,18 @@ fail:
 extern "C" ldpc_status ldpc_engine_step(ldpc_engine *e, int32_t replays) {
     if (!e || replays < 0) { set_error("ldpc_engine_step: bad argument"); return LDPC_E_INVAL; }
     for (int32_t i = 0; i < replays; i++) {
-        const hipError_t err = hipGraphLaunch(e->exec, e->stream);
+        hipError_t err = hipGraphLaunch(e->exec, e->stream);
+        if (err == hipSuccess) {
+            // counters of this replay, for capacity checks that must not wait
+            const int p = e->parity;
+            e->parity ^= 1;
+            err = hipMemcpyAsync(e->h_async[p], e->d_counters, size_t(e->ngraphs) * 20, hipMemcpyDeviceToHost,
+                                 e->stream);
+            if (err == hipSuccess) err = hipEventRecord(e->ev_async[p], e->stream);
+            e->async_pending[p] = err == hipSuccess;
+        }
         if (err != hipSuccess) {
-            set_error(std::string("ldpc_engine_step: hipGraphLaunch: ") + hipGetErrorString(err));
+            set_error(std::string("ldpc_engine_step: ") + hipGetErrorString(err));
             (void)hipGetLastError();
             return LDPC_E_DEVICE;
         }
@@ -893,10 +946,9 @@ extern "C" ldpc_status ldpc_engine_poll(ldpc_engine *e, int64_t *retired, int64_
         (void)hipGetLastError();
         return LDPC_E_DEVICE;
     }
+    // admissions of the last step are applied to head at the start of the next step
+    absorb_counters(e, e->h_counters);
     for (int32_t c = 0; c < e->ngraphs; c++) {
-        // admissions of the last step are applied to head at the start of the next step
-        e->head_seen[size_t(c)] = int64_t(e->h_counters[4 * c]) + e->h_counters[4 * e->ngraphs + c];
-        e->retired_seen[size_t(c)] = e->h_counters[4 * c + 2];
         if (retired) retired[c] = e->retired_seen[size_t(c)];
         if (pending) pending[c] = e->submitted[size_t(c)] - e->retired_seen[size_t(c)];
     }

@@ -80,20 +80,22 @@ struct Request {
     int64_t id = 0;
     int32_t graph = 0, frames = 0, n = 0;
     std::vector<float> llr;
-    size_t dev_off = 0, dev_bytes = 0, stage_off = 0, stage_bytes = 0;
+    size_t dev_off = 0, dev_bytes = 0, stage_off = 0, stage_bytes = 0, out_off = 0, out_bytes = 0;
     bool staged = false;
     int32_t counter = -1;
+    int64_t admit_round = 0;   // worker round of admission: counters of earlier replays predate its reset
     std::vector<uint8_t> bits, ok;
     std::vector<int32_t> iters;
     Clock::time_point t_submit, t_done;
 };
 
-size_t req_dev_bytes(int32_t F, int32_t n) {
-    const size_t llr = (size_t(F) * n * 4 + 255) & ~size_t(255);
-    const size_t bits = (size_t(F) * n + 255) & ~size_t(255);
-    const size_t small = (size_t(F) * 5 + 255) & ~size_t(255);
-    return llr + bits + small;
+// Device block of a request: [llr F*n f32][bits F*n u8][ok F u8, iters F i32], each part 256-aligned;
+// the outputs (bits, ok, iters) are contiguous so one copy brings them back.
+size_t req_llr_bytes(int32_t F, int32_t n) { return (size_t(F) * n * 4 + 255) & ~size_t(255); }
+size_t req_out_bytes(int32_t F, int32_t n) {
+    return ((size_t(F) * n + 255) & ~size_t(255)) + ((size_t(F) * 5 + 3 + 255) & ~size_t(255));
 }
+size_t req_dev_bytes(int32_t F, int32_t n) { return req_llr_bytes(F, n) + req_out_bytes(F, n); }
 
 }  // namespace
 
@@ -115,6 +117,9 @@ struct ldpc_server {
     std::condition_variable cv_work, cv_done;
     std::deque<Request *> waiting;
     std::vector<Request *> inflight, staged_uploads;
+    hipStream_t engine_stream = nullptr;
+    int32_t *h_cnt[2] = {nullptr, nullptr};
+    hipEvent_t ev_cnt[2] = {nullptr, nullptr}, ev_out[2] = {nullptr, nullptr};
     std::unordered_map<int64_t, Request *> all;
     std::deque<int64_t> completed;
     int64_t next_id = 1, n_submitted = 0, n_admitted = 0, n_completed = 0, frames_completed = 0;
@@ -132,31 +137,41 @@ void fail_worker(ldpc_server *s, const std::string &what) {
     s->cv_done.notify_all();
 }
 
-// Admit waiting requests in arrival order while resources allow (worker thread, lock held).
-bool admit_locked(ldpc_server *s) {
-    bool any = false;
+// Admit waiting requests in arrival order while resources allow (worker
+// thread, lock held).  Frames of all admitted requests of a graph go to the
+// engine in one submission that waits for the uploads on the copy stream.
+bool admit_locked(ldpc_server *s, int64_t round) {
+    std::vector<std::vector<ldpc_frame>> batch(static_cast<size_t>(s->ngraphs));
+    std::vector<int64_t> queued(static_cast<size_t>(s->ngraphs), 0);
     while (!s->waiting.empty()) {
         Request *r = s->waiting.front();
         if (s->free_counters.empty()) break;
         int32_t cap = 0;
-        if (ldpc_engine_capacity(s->engine, r->graph, &cap) != LDPC_OK || cap < r->frames) break;
-        size_t doff = 0, hoff = 0;
+        if (ldpc_engine_capacity(s->engine, r->graph, &cap) != LDPC_OK) return false;
+        if (cap - queued[size_t(r->graph)] < r->frames) break;
+        size_t doff = 0, hoff = 0, ooff = 0;
         if (!s->dev_arena->alloc(r->dev_bytes, &doff)) break;
         if (!s->host_arena->alloc(r->stage_bytes, &hoff)) {
             s->dev_arena->release(doff, r->dev_bytes);
             break;
         }
+        if (!s->host_arena->alloc(r->out_bytes, &ooff)) {
+            s->dev_arena->release(doff, r->dev_bytes);
+            s->host_arena->release(hoff, r->stage_bytes);
+            break;
+        }
         r->dev_off = doff;
         r->stage_off = hoff;
+        r->out_off = ooff;
         r->staged = true;
+        r->admit_round = round;
         r->counter = s->free_counters.back();
         s->free_counters.pop_back();
         s->waiting.pop_front();
-        // upload LLRs, reset the counter, queue the frames
         const int32_t F = r->frames, nn = r->n;
         char *base = s->dev + doff;
         float *d_llr = reinterpret_cast<float *>(base);
-        uint8_t *d_bits = reinterpret_cast<uint8_t *>(base + ((size_t(F) * nn * 4 + 255) & ~size_t(255)));
+        uint8_t *d_bits = reinterpret_cast<uint8_t *>(base + req_llr_bytes(F, nn));
         uint8_t *d_ok = d_bits + ((size_t(F) * nn + 255) & ~size_t(255));
         int32_t *d_iters = reinterpret_cast<int32_t *>(d_ok + ((size_t(F) + 3) & ~size_t(3)));
         std::memcpy(s->pinned + hoff, r->llr.data(), size_t(F) * nn * 4);
@@ -167,97 +182,166 @@ bool admit_locked(ldpc_server *s) {
             set_error(std::string("upload failed: ") + hipGetErrorString(e));
             return false;
         }
-        std::vector<ldpc_frame> fr(static_cast<size_t>(F));
+        std::vector<ldpc_frame> &fr = batch[size_t(r->graph)];
         for (int32_t f = 0; f < F; f++) {
-            fr[size_t(f)].llr = d_llr + size_t(f) * nn;
-            fr[size_t(f)].bits = d_bits + size_t(f) * nn;
-            fr[size_t(f)].ok = d_ok + f;
-            fr[size_t(f)].iters = d_iters + f;
-            fr[size_t(f)].llr_out = nullptr;
-            fr[size_t(f)].done = s->counters + r->counter;
+            ldpc_frame x;
+            x.llr = d_llr + size_t(f) * nn;
+            x.bits = d_bits + size_t(f) * nn;
+            x.ok = d_ok + f;
+            x.iters = d_iters + f;
+            x.llr_out = nullptr;
+            x.done = s->counters + r->counter;
+            fr.push_back(x);
         }
-        if (ldpc_engine_submit(s->engine, r->graph, fr.data(), F, s->copy) != LDPC_OK) return false;
+        queued[size_t(r->graph)] += F;
         s->inflight.push_back(r);
         s->staged_uploads.push_back(r);
         s->n_admitted++;
-        any = true;
     }
-    (void)any;
+    for (int32_t c = 0; c < s->ngraphs; c++) {
+        const std::vector<ldpc_frame> &fr = batch[size_t(c)];
+        if (!fr.empty() && ldpc_engine_submit(s->engine, c, fr.data(), int32_t(fr.size()), s->copy) != LDPC_OK)
+            return false;
+    }
     return true;
 }
 
+// Requests whose result copies have completed: hand them to the client.
+void complete_requests(ldpc_server *s, std::vector<Request *> &done) {
+    const auto now = Clock::now();
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (Request *r : done) {
+        const int32_t F = r->frames, nn = r->n;
+        const uint8_t *h = reinterpret_cast<const uint8_t *>(s->pinned + r->out_off);
+        const uint8_t *h_ok = h + ((size_t(F) * nn + 255) & ~size_t(255));
+        const uint8_t *h_it = h_ok + ((size_t(F) + 3) & ~size_t(3));
+        r->bits.assign(h, h + size_t(F) * nn);
+        r->ok.assign(h_ok, h_ok + F);
+        r->iters.resize(size_t(F));
+        std::memcpy(r->iters.data(), h_it, size_t(F) * 4);
+        r->t_done = now;
+        s->host_arena->release(r->out_off, r->out_bytes);
+        s->dev_arena->release(r->dev_off, r->dev_bytes);
+        s->free_counters.push_back(r->counter);
+        r->counter = -1;
+        s->completed.push_back(r->id);
+        s->n_completed++;
+        s->frames_completed += F;
+    }
+    if (!done.empty()) s->cv_done.notify_all();
+    done.clear();
+}
+
+// Pipeline: replay k runs while the host reads the counters of replay k-1,
+// queues the result copies of requests that finished by then (they run after
+// replay k on the engine stream) and completes the copies queued one round
+// earlier.
 void worker_main(ldpc_server *s) {
     (void)hipSetDevice(s->device);
-    std::vector<Request *> finished;
+    std::vector<Request *> draining[2], ready, uploaded[2];
+    int64_t k = 0;
+    bool prev_replay = false;
     for (;;) {
+        const int cur = int(k & 1), prv = cur ^ 1;
+        bool launched = false;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            if (!admit_locked(s)) {
+            if (!admit_locked(s, k)) {
                 lk.unlock();
                 fail_worker(s, "admission");
                 return;
             }
-            if (s->inflight.empty()) {
+            uploaded[cur].swap(s->staged_uploads);
+            s->staged_uploads.clear();
+            if (s->inflight.empty() && draining[0].empty() && draining[1].empty() && !prev_replay) {
                 if (s->stop && s->waiting.empty()) return;
                 s->cv_work.wait_for(lk, std::chrono::milliseconds(2));
                 continue;
             }
+            launched = !s->inflight.empty();
         }
-        if (ldpc_engine_step(s->engine, 1) != LDPC_OK || ldpc_engine_poll(s->engine, nullptr, nullptr) != LDPC_OK) {
-            fail_worker(s, "engine");
-            return;
-        }
-        // the engine stream waited for every upload queued before this step
-        if (hipMemcpy(s->h_counters, s->counters, size_t(s->max_requests) * 4, hipMemcpyDeviceToHost) != hipSuccess) {
-            set_error("counter read failed");
-            fail_worker(s, "poll");
-            return;
-        }
-        finished.clear();
-        {
-            std::lock_guard<std::mutex> lk(s->mu);
-            for (Request *r : s->staged_uploads) {
-                s->host_arena->release(r->stage_off, r->stage_bytes);
-                r->staged = false;
+        if (launched) {
+            hipError_t e = hipSuccess;
+            if (ldpc_engine_step(s->engine, 1) != LDPC_OK) e = hipErrorUnknown;
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(s->h_cnt[cur], s->counters, size_t(s->max_requests) * 4, hipMemcpyDeviceToHost,
+                                   s->engine_stream);
+            if (e == hipSuccess) e = hipEventRecord(s->ev_cnt[cur], s->engine_stream);
+            if (e != hipSuccess) {
+                set_error(std::string("engine step failed: ") + hipGetErrorString(e));
+                fail_worker(s, "engine");
+                return;
             }
-            s->staged_uploads.clear();
-            for (size_t i = 0; i < s->inflight.size();) {
-                Request *r = s->inflight[i];
-                if (s->h_counters[r->counter] >= r->frames) {
-                    finished.push_back(r);
-                    s->inflight[i] = s->inflight.back();
-                    s->inflight.pop_back();
-                } else {
-                    i++;
+        }
+        if (prev_replay) {
+            if (hipEventSynchronize(s->ev_cnt[prv]) != hipSuccess) {
+                set_error("event wait failed");
+                fail_worker(s, "poll");
+                return;
+            }
+            // uploads queued before replay k-1 have completed: the engine waited for them
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                for (Request *r : uploaded[prv]) {
+                    s->host_arena->release(r->stage_off, r->stage_bytes);
+                    r->staged = false;
                 }
             }
-        }
-        for (Request *r : finished) {
-            const int32_t F = r->frames, nn = r->n;
-            const char *base = s->dev + r->dev_off;
-            const uint8_t *d_bits = reinterpret_cast<const uint8_t *>(base + ((size_t(F) * nn * 4 + 255) & ~size_t(255)));
-            const uint8_t *d_ok = d_bits + ((size_t(F) * nn + 255) & ~size_t(255));
-            const int32_t *d_iters = reinterpret_cast<const int32_t *>(d_ok + ((size_t(F) + 3) & ~size_t(3)));
-            r->bits.resize(size_t(F) * nn);
-            r->ok.resize(size_t(F));
-            r->iters.resize(size_t(F));
-            if (hipMemcpy(r->bits.data(), d_bits, r->bits.size(), hipMemcpyDeviceToHost) != hipSuccess ||
-                hipMemcpy(r->ok.data(), d_ok, r->ok.size(), hipMemcpyDeviceToHost) != hipSuccess ||
-                hipMemcpy(r->iters.data(), d_iters, r->iters.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) {
-                set_error("result read failed");
+            uploaded[prv].clear();
+            // result copies queued one round earlier
+            if (!draining[prv].empty()) {
+                if (hipEventSynchronize(s->ev_out[prv]) != hipSuccess) {
+                    set_error("event wait failed");
+                    fail_worker(s, "results");
+                    return;
+                }
+                complete_requests(s, draining[prv]);
+            }
+            // requests finished by replay k-1: queue their result copies.  A request
+            // admitted in round k reused its counter after replay k-1's copy was
+            // queued, so only requests admitted before round k are judged here.
+            std::vector<Request *> fin;
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                for (size_t i = 0; i < s->inflight.size();) {
+                    Request *r = s->inflight[i];
+                    if (r->admit_round <= k - 1 && s->h_cnt[prv][r->counter] >= r->frames) {
+                        fin.push_back(r);
+                        s->inflight[i] = s->inflight.back();
+                        s->inflight.pop_back();
+                    } else {
+                        i++;
+                    }
+                }
+            }
+            for (Request *r : fin) {
+                const char *src = s->dev + r->dev_off + req_llr_bytes(r->frames, r->n);
+                if (hipMemcpyAsync(s->pinned + r->out_off, src, req_out_bytes(r->frames, r->n),
+                                   hipMemcpyDeviceToHost, s->engine_stream) != hipSuccess) {
+                    set_error("result copy failed");
+                    fail_worker(s, "results");
+                    return;
+                }
+                draining[cur].push_back(r);
+            }
+            if (!fin.empty() && hipEventRecord(s->ev_out[cur], s->engine_stream) != hipSuccess) {
+                set_error("event record failed");
                 fail_worker(s, "results");
                 return;
             }
-            r->t_done = Clock::now();
-            std::lock_guard<std::mutex> lk(s->mu);
-            s->dev_arena->release(r->dev_off, r->dev_bytes);
-            s->free_counters.push_back(r->counter);
-            r->counter = -1;
-            s->completed.push_back(r->id);
-            s->n_completed++;
-            s->frames_completed += F;
         }
-        if (!finished.empty()) s->cv_done.notify_all();
+        if (!launched) {
+            // nothing queued behind: finish outstanding copies now
+            if (hipStreamSynchronize(s->engine_stream) != hipSuccess) {
+                set_error("stream wait failed");
+                fail_worker(s, "results");
+                return;
+            }
+            for (int p = 0; p < 2; p++)
+                if (!draining[p].empty()) complete_requests(s, draining[p]);
+        }
+        prev_replay = launched;
+        k++;
     }
 }
 
@@ -298,6 +382,13 @@ extern "C" ldpc_status ldpc_server_create(const ldpc_graph *const *graphs, int32
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&s->pinned), size_t(host_budget), 0);
     if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&s->h_counters), size_t(maxreq) * 4, 0);
     if (e == hipSuccess) e = hipMemset(s->counters, 0, size_t(maxreq) * 4);
+    for (int p = 0; p < 2 && e == hipSuccess; p++) {
+        e = hipHostMalloc(reinterpret_cast<void **>(&s->h_cnt[p]), size_t(maxreq) * 4, 0);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_cnt[p], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_out[p], hipEventDisableTiming);
+    }
+    if (e == hipSuccess && ldpc_engine_stream(s->engine, reinterpret_cast<void **>(&s->engine_stream)) != LDPC_OK)
+        e = hipErrorUnknown;
     if (e != hipSuccess) {
         set_error(std::string("ldpc_server_create: ") + hipGetErrorString(e));
         (void)hipGetLastError();
@@ -339,7 +430,8 @@ extern "C" ldpc_status ldpc_server_submit(ldpc_server *s, int32_t graph, const f
     r->n = nn;
     r->dev_bytes = req_dev_bytes(frames, nn);
     r->stage_bytes = size_t(frames) * nn * 4;
-    if (r->dev_bytes > s->dev_arena->size() || r->stage_bytes > s->host_arena->size() ||
+    r->out_bytes = req_out_bytes(frames, nn);
+    if (r->dev_bytes > s->dev_arena->size() || r->stage_bytes + r->out_bytes + 512 > s->host_arena->size() ||
         frames > s->queue_cap[size_t(graph)]) {
         delete r;
         set_error("ldpc_server_submit: request larger than the server's memory budgets");
@@ -440,6 +532,11 @@ extern "C" ldpc_status ldpc_server_destroy(ldpc_server *s) {
     (void)hipFree(s->counters);
     (void)hipHostFree(s->pinned);
     (void)hipHostFree(s->h_counters);
+    for (int p = 0; p < 2; p++) {
+        if (s->h_cnt[p]) (void)hipHostFree(s->h_cnt[p]);
+        if (s->ev_cnt[p]) (void)hipEventDestroy(s->ev_cnt[p]);
+        if (s->ev_out[p]) (void)hipEventDestroy(s->ev_out[p]);
+    }
     (void)hipGetLastError();
     for (auto &kv : s->all) delete kv.second;
     delete s;

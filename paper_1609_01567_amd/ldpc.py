@@ -430,14 +430,15 @@ class Server:
                "ldpc_server_poll")
         return ids[: cnt.value].tolist()
 
-    def result(self, rid: int):
+    def result(self, rid: int, want_bits: bool = True):
+        """(bits [F][n] or None, ok [F], iters [F], latency seconds); releases the request."""
         F, n = self._frames.pop(rid)
-        bits = np.zeros((F, n), np.uint8)
+        bits = np.zeros((F, n), np.uint8) if want_bits else None
         ok = np.zeros(F, np.uint8)
         iters = np.zeros(F, np.int32)
         lat = ctypes.c_double()
-        _check(self._lib.ldpc_server_result(self._h, int(rid), _np_ptr(bits), _np_ptr(ok), _np_ptr(iters),
-                                            ctypes.byref(lat)), "ldpc_server_result")
+        _check(self._lib.ldpc_server_result(self._h, int(rid), _np_ptr(bits) if want_bits else None, _np_ptr(ok),
+                                            _np_ptr(iters), ctypes.byref(lat)), "ldpc_server_result")
         return bits, ok, iters, float(lat.value)
 
     def stats(self) -> dict:

@@ -306,7 +306,10 @@ def bench_served(torch, ldpc, capacity_fps, requests, loads=(0.25, 0.5, 0.75, 0.
     out = {"capacity_frames_per_s": round(capacity_fps, 1), "requests_per_load": requests,
            "workload": "Poisson arrivals; request = U{1..64} frames of one code (Zipf(1) over the 8 batch codes), "
                        "Eb/N0 = waterfall + 0.5 dB, max 50 iterations", "loads": []}
-    srv = ldpc.Server(graphs, [256] * len(codes), T, flags=ldpc.MSG_FP16, hbm_budget=2 << 30,
+    # slot pools follow each code's share of the request stream (the batched mix's Zipf split)
+    slots = [int(x) for x in li.batch_frame_split(4096, len(codes))]
+    out["slots"] = slots
+    srv = ldpc.Server(graphs, slots, T, flags=ldpc.MSG_FP16, hbm_budget=2 << 30,
                       host_budget=1 << 30, lane_slots=4, graph_steps=2)
     for rho in loads:
         rng = np.random.default_rng(seed + int(rho * 100))

@@ -32,7 +32,7 @@ EXPORTED = ("ldpc_graph_create", "ldpc_graph_destroy", "ldpc_graph_info", "ldpc_
             "ldpc_decode_workspace_size", "ldpc_decode", "ldpc_decode_profiled", "ldpc_status_str",
             "ldpc_last_error", "ldpc_engine_create", "ldpc_engine_destroy", "ldpc_engine_info",
             "ldpc_engine_submit", "ldpc_engine_capacity", "ldpc_engine_step", "ldpc_engine_poll",
-            "ldpc_engine_run", "ldpc_engine_autotune", "ldpc_server_create", "ldpc_server_submit",
+            "ldpc_engine_run", "ldpc_engine_stream", "ldpc_engine_autotune", "ldpc_server_create", "ldpc_server_submit",
             "ldpc_server_poll", "ldpc_server_result", "ldpc_server_stats", "ldpc_server_destroy")
 
 
@@ -93,6 +93,7 @@ def load_library():
     lib.ldpc_engine_step.argtypes = [P, I32]
     lib.ldpc_engine_poll.argtypes = [P, P, P]
     lib.ldpc_engine_run.argtypes = [P, I32, P]
+    lib.ldpc_engine_stream.argtypes = [P, ctypes.POINTER(P)]
     lib.ldpc_engine_autotune.argtypes = [P, I32, P, P, I32, U32, P, P, P]
     lib.ldpc_engine_autotune.restype = ctypes.c_int
     lib.ldpc_server_create.argtypes = [P, I32, P, I32, U32, I64, I64, P, ctypes.POINTER(P)]
@@ -105,7 +106,8 @@ def load_library():
               "ldpc_server_stats", "ldpc_server_destroy"):
         getattr(lib, f).restype = ctypes.c_int
     for f in ("ldpc_engine_create", "ldpc_engine_destroy", "ldpc_engine_info", "ldpc_engine_submit",
-              "ldpc_engine_capacity", "ldpc_engine_step", "ldpc_engine_poll", "ldpc_engine_run"):
+              "ldpc_engine_capacity", "ldpc_engine_step", "ldpc_engine_poll", "ldpc_engine_run",
+              "ldpc_engine_stream"):
         getattr(lib, f).restype = ctypes.c_int
     lib.ldpc_status_str.argtypes = [ctypes.c_int]
     lib.ldpc_status_str.restype = ctypes.c_char_p

@@ -69,6 +69,7 @@ def parse():
     ap.add_argument("--no-engine", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--served-requests", type=int, default=3000)
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates rocprof byte counters) and exit")
@@ -282,6 +283,85 @@ def bench_batched(torch, ldpc, steps, warmup, T=50):
                    "frames": int(pe_all.size)},
         "per_code": per_code,
     }
+
+
+def _mcnemar(b, c, N):
+    """Paired difference (b - c) / N of two decoders' frame-error rates with a 95% interval."""
+    d = (b - c) / N
+    half = 1.96 * np.sqrt(max(b + c - (b - c) ** 2 / N, 0.0)) / N
+    return [round(d - half, 5), round(d + half, 5)]
+
+
+def bench_precision(torch, ldpc, frames=1024, T=100, points=(1.5, 5.0), oracle_frames=32):
+    """Extreme-irregularity code (n=16200, check degrees 4..509): FP32 vs FP16 vs
+    BF16 message storage (FP32 arithmetic), all-zero codeword.
+
+    On the GPU, all frames at each Eb/N0 with early stop: FER, BER, mean
+    iterations, and paired discordance against FP32.  Against the FP64 oracle on
+    the first `oracle_frames` frames: posterior error at fixed T in {1, 5}
+    (every frame, no early stop) and, at max_iter with early stop, agreement of
+    hard decisions / iteration counts / flags and the posterior error of frames
+    the oracle decodes to a codeword.  1.5 dB lies below this code's threshold
+    (no precision decodes there); 5.0 dB is in its waterfall.
+    """
+    import oracle
+    import ldpc_inputs as li
+    code = li.extreme_code()
+    g = ldpc.Graph.from_code(code)
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    variants = (("fp32", 0), ("fp16", ldpc.MSG_FP16), ("bf16", ldpc.MSG_BF16))
+
+    def run(x, Tm, fl):
+        r = ldpc.decode(g, x, Tm, flags=fl, want_llr=True)
+        torch.cuda.synchronize()
+        return dict(bits=r.bits.cpu().numpy(), ok=r.ok.cpu().numpy(), iters=r.iters.cpu().numpy(),
+                    lpost=r.llr.cpu().numpy().astype(np.float64))
+
+    def err_stats(gl, ol):
+        e = np.abs(gl - ol)
+        rel = e / (1.0 + np.abs(ol))
+        if e.size == 0:
+            return None
+        return {"max": float(e.max()), "p99": float(np.percentile(e, 99)), "mean": float(e.mean()),
+                "max_rel": float(rel.max())}
+
+    out = {"workload": f"n={code.n} m={code.m} E={code.nnz}, check degrees {int(code.check_degrees().min())}.."
+                       f"{int(code.check_degrees().max())}, bit degrees 2..64 (power law), all-zero codeword, "
+                       f"{frames} frames per point, max {T} iterations, early stop",
+           "oracle_sample_frames": oracle_frames, "points": []}
+    for i, eb in enumerate(points):
+        llr = li.awgn_llr(code.n, frames, li.ebn0_to_sigma2(eb, code.rate), seed=2003 + 10 * i)
+        d = torch.from_numpy(llr).cuda()
+        res = {name: run(d, T, fl) for name, fl in variants}
+        fe = {name: (r["bits"] != 0).any(axis=1) for name, r in res.items()}
+        pt = {"ebn0_db": eb, "gpu": {}, "vs_oracle": {}}
+        for name, r in res.items():
+            b = int((fe[name] & ~fe["fp32"]).sum())
+            c = int((fe["fp32"] & ~fe[name]).sum())
+            pt["gpu"][name] = {"fer": float(fe[name].mean()), "ber": float((r["bits"] != 0).mean()),
+                               "mean_iters": float(r["iters"].mean()),
+                               "fail_only_this": b, "fail_only_fp32": c,
+                               "fer_diff_ci95": _mcnemar(b, c, frames)}
+        xs = llr[:oracle_frames]
+        dx = d[:oracle_frames].contiguous()
+        for Tf in (1, 5):
+            ora = oracle.decode(code, xs, Tf, early_stop=False, threads=threads)
+            for name, fl in variants:
+                gr = run(dx, Tf, fl | ldpc.NO_EARLY_STOP)
+                pt["vs_oracle"].setdefault(name, {})[f"fixed_T{Tf}"] = err_stats(gr["lpost"], ora["lpost"])
+        ora = oracle.decode(code, xs, T, threads=threads)
+        conv = ora["ok"] == 1
+        for name, _ in variants:
+            r = {k: v[:oracle_frames] for k, v in res[name].items()}
+            same = (r["bits"] == ora["bits"]).all(axis=1) & (r["iters"] == ora["iters"]) & (r["ok"] == ora["ok"])
+            both = conv & (r["ok"] == 1)
+            pt["vs_oracle"][name]["early_stop"] = {
+                "frames_identical": int(same.sum()), "oracle_converged": int(conv.sum()),
+                "posterior_err_converged": err_stats(r["lpost"][both], ora["lpost"][both])}
+        out["points"].append(pt)
+        print(f"[bench] precision {eb} dB: " + ", ".join(f"{k} FER {v['fer']:.4f}" for k, v in pt["gpu"].items()),
+              file=sys.stderr, flush=True)
+    return out
 
 
 def bench_served(torch, ldpc, capacity_fps, requests, loads=(0.25, 0.5, 0.75, 0.95), T=50, seed=4001):
@@ -521,6 +601,11 @@ def main():
         served = bench_served(torch, ldpc, cap, args.served_requests)
         print(f"[bench] served done", file=sys.stderr, flush=True)
 
+    precision = None
+    if not args.no_precision:
+        precision = bench_precision(torch, ldpc)
+        print(f"[bench] precision done", file=sys.stderr, flush=True)
+
     ceiling = copy_ceiling(torch)
     cpu = None
     if not args.no_cpu_baseline:
@@ -553,6 +638,7 @@ def main():
         "engine_same_workload": engine,
         "batched": batched,
         "served": served,
+        "precision": precision,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

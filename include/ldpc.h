@@ -203,6 +203,14 @@ LDPC_API ldpc_status ldpc_decode_profiled(const ldpc_graph *g, const float *llr_
  * bit-identical to decoding it alone with ldpc_decode and the same flags.
  * Steps are captured once into a hipGraph and replayed.
  *
+ * Repacking: once a graph has no queued frames left, the frames still running
+ * tend to be scattered over the pool, and every slot group holding one of
+ * them costs a full pass over its messages.  When at most half of the slots
+ * below the highest occupied one hold frames, the engine moves the frames
+ * above the first A slots (A = frames running) into the free slots below A,
+ * with their messages and LLRs, so later passes touch A slots only.  Moving a
+ * frame between slots does not change its arithmetic.
+ *
  * The engine owns its device memory (allocated at creation) and a HIP stream
  * of default priority; all of its work runs on that stream.  One engine must
  * not be driven from several host threads at once.
@@ -222,7 +230,8 @@ typedef struct {
 typedef struct {
     int32_t lane_slots;   /* frame slots per wavefront lane: 1, 2 or 4; 0 = 4 */
     int32_t graph_steps;  /* decode steps per captured hipGraph replay; 0 = 8 */
-    int32_t reserved[6];  /* must be 0 */
+    int32_t no_compaction;/* 1: never repack frames into the low slots (see below); 0 = repack */
+    int32_t reserved[5];  /* must be 0 */
 } ldpc_engine_opts;
 
 /*

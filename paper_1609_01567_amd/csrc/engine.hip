@@ -13,6 +13,8 @@
 //                             t_s = max_iter; write ok/iters; else t_s += 1
 //   turnover    (listed slots) write the estimate of stopped frames, admit the
 //                             next queued frame of the graph into the slot
+//   repack      (per graph)   once the queue is empty and the running frames are
+//                             scattered, move them into the lowest slots
 //
 // The check and bit arithmetic (device_common.h) and its order per frame are
 // those of decode.hip, so a frame's outputs do not depend on its neighbours.
@@ -25,6 +27,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "internal.h"
@@ -37,6 +40,10 @@ using namespace ldpc_dev;
 constexpr int kMaxGraphs = 32;
 constexpr int kTurnoverBlocks = 1024;
 constexpr int kTurnChunk = 2048;   // bits per turnover workgroup (256 threads x 8)
+constexpr int kCounterInts = 7;    // per graph: head, tail, retired, list count, taken, moves, extent
+constexpr int kRepackMinExtent = 32;   // below this many slots a repack saves no cache line
+constexpr int kMoveBlocks = 512;
+constexpr int kMoveRows = 64;      // rows of one graph's state arrays per move work unit
 
 struct EngFrame {   // device mirror of ldpc_frame
     const float *llr;
@@ -50,7 +57,7 @@ static_assert(sizeof(EngFrame) == sizeof(ldpc_frame), "ldpc_frame layout");
 
 struct EngGraph {
     const int32_t *row_ptr, *col_idx, *col_ptr, *csc_to_csr, *class_rows, *hub_chunk_base;
-    int32_t n, S;
+    int32_t n, S, E;
     int32_t class_begin[ldpc::kNumClasses + 1];
     float *lch, *lpost;
     void *r;
@@ -66,6 +73,9 @@ struct EngGraph {
     int32_t *list;        // turnover list of this step: slot | (stopped << 31)
     int32_t *list_count;
     int32_t *taken;       // frames admitted by this step's turnover (applied to head next step)
+    int32_t *moves;       // frames repacked by this step (slot pairs in move_src / move_dst)
+    int32_t *extent;      // one past the highest occupied slot (0: pool empty)
+    int32_t *move_src, *move_dst;
     int32_t chunks;       // ceil(n / kTurnChunk)
 };
 
@@ -123,270 +133,324 @@ __device__ __forceinline__ void eng_syndrome(const EngGraph &G, const EngLane<V>
         if (ln.syn_on[k] && syn[k] && G.fail[s0 + k] != ln.t[k]) G.fail[s0 + k] = ln.t[k];
 }
 
-template <int M, int V, int DMAX>
-__global__ __launch_bounds__(256) void eng_check_rows(const EngGraph *__restrict__ graphs, Prefix pre, int32_t cls,
-                                                      int32_t T, int32_t early) {
-    using MT = typename Codec<M>::T;
-    const int lane = threadIdx.x & 63;
-    const int wave = wave_uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    if (wave >= pre.p[pre.count]) return;
-    const int c = find_graph(pre, wave);
-    const EngGraph &G = graphs[c];
-    const int32_t S = G.S;
-    const int groups = S / (64 * V);
-    const int local = wave - pre.p[c];
-    const int g = local % groups;
-    const int rk = local / groups;
-    const int s0 = (g * 64 + lane) * V;
-    EngLane<V> ln;
-    eng_lane<V>(G, s0, T, early, ln);
-    if (__ballot(ln.active) == 0) return;
-    if (!ln.active) return;
-    const int row = wave_uniform(G.class_rows[G.class_begin[cls] + rk]);
-    const int e0 = wave_uniform(G.row_ptr[row]);
-    const int d = wave_uniform(G.row_ptr[row + 1]) - e0;
-    int syn[V];
-#pragma unroll
-    for (int k = 0; k < V; k++) syn[k] = 0;
-    row_rule<M, V, DMAX>(G.col_idx, e0, d, G.lpost, G.lch, static_cast<MT *>(G.r), S, s0, ln.src, syn);
-    eng_syndrome<V>(G, ln, syn, s0);
+// Work of one pass over the occupied slot groups of every graph.  Graph c owns
+// items [p[c], p[c+1]); an item is one (row or bit, slot group) pair, or for
+// the chunked classes a workgroup of `per` such pairs.  Only the groups below
+// each graph's extent (one past its highest occupied slot) count, so passes
+// over empty pools cost nothing but the launch.  Built by every workgroup.
+struct Work {
+    int32_t p[kMaxGraphs + 1];
+    int32_t groups[kMaxGraphs];
+};
+constexpr int kBitItems = -1;   // `cls` value for the bit pass: items are bits
+
+__device__ __forceinline__ void build_work(const EngGraph *__restrict__ graphs, int32_t ngraphs, int cls,
+                                           int unit, int per, Work &w) {
+    if (threadIdx.x == 0) {
+        w.p[0] = 0;
+        for (int c = 0; c < ngraphs; c++) {
+            const EngGraph &G = graphs[c];
+            const int32_t gr = (*G.extent + unit - 1) / unit;
+            const int32_t units = cls == kBitItems ? G.n : G.class_begin[cls + 1] - G.class_begin[cls];
+            w.groups[c] = gr;
+            w.p[c + 1] = w.p[c] + (units * gr + per - 1) / per;
+        }
+    }
+    __syncthreads();
 }
 
-// Rows of 9..128 edges over WPR wavefronts (see check_chunk_kernel in decode.hip).
+__device__ __forceinline__ int work_graph(const Work &w, int32_t ngraphs, int x) {
+    int c = 0;
+    while (c + 1 < ngraphs && x >= w.p[c + 1]) c++;
+    return c;
+}
+
+// Rows of up to DMAX edges: one wavefront per (row, slot group), looping over
+// the items of the pass.
+template <int M, int V, int DMAX>
+__global__ __launch_bounds__(256) void eng_check_rows(const EngGraph *__restrict__ graphs, int32_t ngraphs,
+                                                      int32_t cls, int32_t T, int32_t early) {
+    using MT = typename Codec<M>::T;
+    __shared__ Work w;
+    build_work(graphs, ngraphs, cls, 64 * V, 1, w);
+    const int lane = threadIdx.x & 63;
+    const int total = w.p[ngraphs];
+    const int stride = int(gridDim.x * (blockDim.x >> 6));
+    for (int item = wave_uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6); item < total; item += stride) {
+        const int c = work_graph(w, ngraphs, item);
+        const EngGraph &G = graphs[c];
+        const int groups = w.groups[c];
+        const int local = item - w.p[c];
+        const int g = local % groups;
+        const int rk = local / groups;
+        const int s0 = (g * 64 + lane) * V;
+        EngLane<V> ln;
+        eng_lane<V>(G, s0, T, early, ln);
+        if (!ln.active) continue;
+        const int row = wave_uniform(G.class_rows[G.class_begin[cls] + rk]);
+        const int e0 = wave_uniform(G.row_ptr[row]);
+        const int d = wave_uniform(G.row_ptr[row + 1]) - e0;
+        int syn[V];
+#pragma unroll
+        for (int k = 0; k < V; k++) syn[k] = 0;
+        row_rule<M, V, DMAX>(G.col_idx, e0, d, G.lpost, G.lch, static_cast<MT *>(G.r), G.S, s0, ln.src, syn);
+        eng_syndrome<V>(G, ln, syn, s0);
+    }
+}
+
+// Rows of 9..128 edges over WPR wavefronts (see check_chunk_kernel in decode.hip);
+// one workgroup item = 4 / WPR (row, slot group) pairs.
 template <int M, int V, int WPR>
-__global__ __launch_bounds__(256) void eng_check_chunk(const EngGraph *__restrict__ graphs, Prefix pre, int32_t cls,
-                                                       int32_t T, int32_t early) {
+__global__ __launch_bounds__(256) void eng_check_chunk(const EngGraph *__restrict__ graphs, int32_t ngraphs,
+                                                       int32_t cls, int32_t T, int32_t early) {
     using MT = typename Codec<M>::T;
     constexpr int C = kRowChunk;
     constexpr int RPB = 4 / WPR;
     constexpr int MAXCH = WPR == 2 ? 2 : 16;
     __shared__ ChunkShare<V, RPB * MAXCH> sh;
-    if (int(blockIdx.x) >= pre.p[pre.count]) return;      // uniform over the block
+    __shared__ Work w;
+    build_work(graphs, ngraphs, cls, 64 * V, RPB, w);
     const int lane = threadIdx.x & 63;
     const int wave = wave_uniform(threadIdx.x >> 6);
     const int lr = wave / WPR;
     const int wr = wave % WPR;
-    const int c = find_graph(pre, blockIdx.x);
-    const EngGraph &G = graphs[c];
-    const int32_t S = G.S;
-    const int groups = S / (64 * V);
-    const int item = (blockIdx.x - pre.p[c]) * RPB + lr;
-    const int rk = item / groups;
-    const int g = item % groups;
-    const int s0 = (g * 64 + lane) * V;
-    const int nrows = G.class_begin[cls + 1] - G.class_begin[cls];
-    EngLane<V> ln;
-    ln.active = false;
-    if (rk < nrows) eng_lane<V>(G, s0, T, early, ln);
-    const bool work = rk < nrows && __ballot(ln.active) != 0;
-    int e0 = 0, d = 0, nch = 0;
-    if (work) {
-        const int row = wave_uniform(G.class_rows[G.class_begin[cls] + rk]);
-        e0 = wave_uniform(G.row_ptr[row]);
-        d = wave_uniform(G.row_ptr[row + 1]) - e0;
-        nch = (d + C - 1) / C;
-    }
-    MT *R = static_cast<MT *>(G.r);
-    const bool mine = work && ln.active;
-    float u[C][V], suf[C][V], agg[V];
-    uint32_t neg[V];
-    int syn[V];
-    for (int ch = wr; ch < nch; ch += WPR) {
-        if (mine) {
-            chunk_load<M, V, C>(G.col_idx, e0 + ch * C, min(C, d - ch * C), G.lpost, G.lch, R, S, s0, ln.src, u, suf,
-                                agg, neg, syn);
-        } else {
-#pragma unroll
-            for (int k = 0; k < V; k++) { agg[k] = 0.f; neg[k] = 0u; syn[k] = 0; }
+    const int total = w.p[ngraphs];
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {     // uniform over the workgroup
+        const int c = work_graph(w, ngraphs, u);
+        const EngGraph &G = graphs[c];
+        const int groups = w.groups[c];
+        const int nrows = G.class_begin[cls + 1] - G.class_begin[cls];
+        const int item = (u - w.p[c]) * RPB + lr;
+        const bool valid = item < nrows * groups;                // uniform over the wavefront
+        const int rk = valid ? item / groups : 0;
+        const int g = valid ? item % groups : 0;
+        const int s0 = (g * 64 + lane) * V;
+        EngLane<V> ln;
+        ln.active = false;
+        if (valid) eng_lane<V>(G, s0, T, early, ln);
+        const bool work = valid && __ballot(ln.active) != 0;
+        int e0 = 0, d = 0, nch = 0;
+        if (work) {
+            const int row = wave_uniform(G.class_rows[G.class_begin[cls] + rk]);
+            e0 = wave_uniform(G.row_ptr[row]);
+            d = wave_uniform(G.row_ptr[row + 1]) - e0;
+            nch = (d + C - 1) / C;
         }
+        MT *R = static_cast<MT *>(G.r);
+        const int32_t S = G.S;
+        const bool mine = work && ln.active;
+        float u_[C][V], suf[C][V], agg[V];
+        uint32_t neg[V];
+        int syn[V];
+        for (int ch = wr; ch < nch; ch += WPR) {
+            if (mine) {
+                chunk_load<M, V, C>(G.col_idx, e0 + ch * C, min(C, d - ch * C), G.lpost, G.lch, R, S, s0, ln.src,
+                                    u_, suf, agg, neg, syn);
+            } else {
 #pragma unroll
-        for (int k = 0; k < V; k++) sh.agg[lr * MAXCH + ch][lane][k] = agg[k];
-        sh.bits[lr * MAXCH + ch][lane] = pack_bits<V>(neg, syn);
-    }
-    __syncthreads();
-    if (!mine) return;
-    for (int ch = wr; ch < nch; ch += WPR) {
-        if (nch > WPR)
-            chunk_load<M, V, C>(G.col_idx, e0 + ch * C, min(C, d - ch * C), G.lpost, G.lch, R, S, s0, ln.src, u, suf,
-                                agg, neg, syn);
-        float pre_a[V], post_a[V];
-        uint32_t parity[V];
-        int syn_row[V];
-        chunk_context<V, RPB * MAXCH>(sh, lr * MAXCH, nch, ch, lane, pre_a, post_a, parity, syn_row);
-        chunk_store<M, V, C>(e0 + ch * C, min(C, d - ch * C), u, suf, neg, pre_a, post_a, parity, R, S, s0);
-        if (ch == 0) eng_syndrome<V>(G, ln, syn_row, s0);
+                for (int k = 0; k < V; k++) { agg[k] = 0.f; neg[k] = 0u; syn[k] = 0; }
+            }
+#pragma unroll
+            for (int k = 0; k < V; k++) sh.agg[lr * MAXCH + ch][lane][k] = agg[k];
+            sh.bits[lr * MAXCH + ch][lane] = pack_bits<V>(neg, syn);
+        }
+        __syncthreads();
+        if (mine) {
+            for (int ch = wr; ch < nch; ch += WPR) {
+                if (nch > WPR)
+                    chunk_load<M, V, C>(G.col_idx, e0 + ch * C, min(C, d - ch * C), G.lpost, G.lch, R, S, s0,
+                                        ln.src, u_, suf, agg, neg, syn);
+                float pre_a[V], post_a[V];
+                uint32_t parity[V];
+                int syn_row[V];
+                chunk_context<V, RPB * MAXCH>(sh, lr * MAXCH, nch, ch, lane, pre_a, post_a, parity, syn_row);
+                chunk_store<M, V, C>(e0 + ch * C, min(C, d - ch * C), u_, suf, neg, pre_a, post_a, parity, R, S,
+                                     s0);
+                if (ch == 0) eng_syndrome<V>(G, ln, syn_row, s0);
+            }
+        }
+        __syncthreads();   // the shared aggregates are reused by the next item
     }
 }
 
 // Rows longer than 128 edges: one workgroup of four wavefronts per (row, 64 slots),
 // 32-edge chunks combined through an exclusive prefix/suffix scan in scratch.
 template <int M>
-__global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict__ graphs, Prefix pre, int32_t T,
-                                                     int32_t early) {
+__global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict__ graphs, int32_t ngraphs,
+                                                     int32_t T, int32_t early) {
     using MT = typename Codec<M>::T;
     constexpr int C = ldpc::kHubChunk;
     __shared__ int32_t total_bits[64];
+    __shared__ Work w;
+    build_work(graphs, ngraphs, ldpc::kClassHub, 64, 1, w);
     const int lane = threadIdx.x & 63;
     const int wv = wave_uniform(threadIdx.x >> 6);
     const int nw = blockDim.x >> 6;
-    if (int(blockIdx.x) >= pre.p[pre.count]) return;
-    const int c = find_graph(pre, blockIdx.x);
-    const EngGraph &G = graphs[c];
-    const int32_t S = G.S;
-    const int groups = S / 64;
-    const int local = blockIdx.x - pre.p[c];
-    const int g = local % groups;
-    const int rk = local / groups;
-    const int s = g * 64 + lane;
-    const int32_t qs = G.slot_q[s], ts = G.slot_t[s];
-    const bool active = qs >= 0;
-    const bool first = active && ts == 0;
-    const bool syn_on = active && ts >= 1 && (early || ts == T);
-    if (__ballot(active) == 0) return;   // same slots in every wavefront: uniform over the block
+    const int total = w.p[ngraphs];
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {     // uniform over the workgroup
+        const int c = work_graph(w, ngraphs, u);
+        const EngGraph &G = graphs[c];
+        const int32_t S = G.S;
+        const int groups = w.groups[c];
+        const int local = u - w.p[c];
+        const int g = local % groups;
+        const int rk = local / groups;
+        const int s = g * 64 + lane;
+        const int32_t qs = G.slot_q[s], ts = G.slot_t[s];
+        const bool active = qs >= 0;
+        const bool first = active && ts == 0;
+        const bool syn_on = active && ts >= 1 && (early || ts == T);
+        if (__ballot(active) == 0) continue;   // same slots in every wavefront: uniform over the workgroup
 
-    const int row = wave_uniform(G.class_rows[G.class_begin[ldpc::kClassHub] + rk]);
-    const int e0 = wave_uniform(G.row_ptr[row]);
-    const int d = wave_uniform(G.row_ptr[row + 1]) - e0;
-    const int nch = (d + C - 1) / C;
-    const int cb = wave_uniform(G.hub_chunk_base[rk]);
-    MT *R = static_cast<MT *>(G.r);
-    const float *L = first ? G.lch : G.lpost;
+        const int row = wave_uniform(G.class_rows[G.class_begin[ldpc::kClassHub] + rk]);
+        const int e0 = wave_uniform(G.row_ptr[row]);
+        const int d = wave_uniform(G.row_ptr[row + 1]) - e0;
+        const int nch = (d + C - 1) / C;
+        const int cb = wave_uniform(G.hub_chunk_base[rk]);
+        MT *R = static_cast<MT *>(G.r);
+        const float *L = first ? G.lch : G.lpost;
 
-    for (int ch = wv; ch < nch; ch += nw) {
-        const int j0 = e0 + ch * C;
-        const int dc = min(C, d - ch * C);
-        float agg = 0.f;
-        int32_t bits = 0;
+        for (int ch = wv; ch < nch; ch += nw) {
+            const int j0 = e0 + ch * C;
+            const int dc = min(C, d - ch * C);
+            float agg = 0.f;
+            int32_t bits = 0;
 #pragma unroll
-        for (int jj = 0; jj < C; jj++) {
-            if (jj < dc) {
-                const int v = wave_uniform(G.col_idx[j0 + jj]);
-                const float lv = L[size_t(v) * S + s];
-                const float r = first ? 0.f : Codec<M>::dec(R[size_t(j0 + jj) * S + s]);
-                const float qv = clamp_msg(lv - r);
-                bits ^= int32_t(qv < 0.f) | (int32_t(lv < 0.f) << 1);
-                agg = dplus(agg, tanh_complement(fabsf(qv)));
+            for (int jj = 0; jj < C; jj++) {
+                if (jj < dc) {
+                    const int v = wave_uniform(G.col_idx[j0 + jj]);
+                    const float lv = L[size_t(v) * S + s];
+                    const float r = first ? 0.f : Codec<M>::dec(R[size_t(j0 + jj) * S + s]);
+                    const float qv = clamp_msg(lv - r);
+                    bits ^= int32_t(qv < 0.f) | (int32_t(lv < 0.f) << 1);
+                    agg = dplus(agg, tanh_complement(fabsf(qv)));
+                }
+            }
+            G.aggd[size_t(cb + ch) * S + s] = agg;
+            G.aggbits[size_t(cb + ch) * S + s] = bits;
+        }
+        __syncthreads();
+        if (wv == 0) {
+            float pre_d = 0.f;
+            int32_t tot = 0;
+            for (int ch = 0; ch < nch; ch++) {
+                G.aggpre[size_t(cb + ch) * S + s] = pre_d;
+                pre_d = dplus(pre_d, G.aggd[size_t(cb + ch) * S + s]);
+                tot ^= G.aggbits[size_t(cb + ch) * S + s];
+            }
+            float sf = 0.f;
+            for (int ch = nch - 1; ch >= 0; ch--) {
+                const float dcur = G.aggd[size_t(cb + ch) * S + s];
+                G.aggd[size_t(cb + ch) * S + s] = dplus(G.aggpre[size_t(cb + ch) * S + s], sf);
+                sf = dplus(sf, dcur);
+            }
+            total_bits[lane] = tot;
+            if (syn_on && (tot & 2) && G.fail[s] != ts) G.fail[s] = ts;
+        }
+        __syncthreads();
+        const uint32_t parity = uint32_t(total_bits[lane]) & 1u;
+        for (int ch = wv; ch < nch; ch += nw) {
+            const int j0 = e0 + ch * C;
+            const int dc = min(C, d - ch * C);
+            float uu[C], sf[C];
+            uint32_t neg = 0u;
+#pragma unroll
+            for (int jj = 0; jj < C; jj++) {
+                if (jj < dc) {
+                    const int v = wave_uniform(G.col_idx[j0 + jj]);
+                    const float lv = L[size_t(v) * S + s];
+                    const float r = first ? 0.f : Codec<M>::dec(R[size_t(j0 + jj) * S + s]);
+                    const float qv = clamp_msg(lv - r);
+                    neg |= uint32_t(qv < 0.f) << jj;
+                    uu[jj] = tanh_complement(fabsf(qv));
+                }
+            }
+            float run = 0.f;
+#pragma unroll
+            for (int jj = C - 1; jj >= 0; jj--) {
+                if (jj < dc) {
+                    sf[jj] = run;
+                    run = dplus(uu[jj], run);
+                }
+            }
+            run = G.aggd[size_t(cb + ch) * S + s];
+#pragma unroll
+            for (int jj = 0; jj < C; jj++) {
+                if (jj < dc) {
+                    const float mag = magnitude_from_complement(dplus(run, sf[jj]));
+                    const uint32_t sgn = parity ^ ((neg >> jj) & 1u);
+                    R[size_t(j0 + jj) * S + s] = Codec<M>::enc(sgn ? -mag : mag);
+                    run = dplus(run, uu[jj]);
+                }
             }
         }
-        G.aggd[size_t(cb + ch) * S + s] = agg;
-        G.aggbits[size_t(cb + ch) * S + s] = bits;
-    }
-    __syncthreads();
-    if (wv == 0) {
-        float pre_d = 0.f;
-        int32_t tot = 0;
-        for (int ch = 0; ch < nch; ch++) {
-            G.aggpre[size_t(cb + ch) * S + s] = pre_d;
-            pre_d = dplus(pre_d, G.aggd[size_t(cb + ch) * S + s]);
-            tot ^= G.aggbits[size_t(cb + ch) * S + s];
-        }
-        float sf = 0.f;
-        for (int ch = nch - 1; ch >= 0; ch--) {
-            const float dcur = G.aggd[size_t(cb + ch) * S + s];
-            G.aggd[size_t(cb + ch) * S + s] = dplus(G.aggpre[size_t(cb + ch) * S + s], sf);
-            sf = dplus(sf, dcur);
-        }
-        total_bits[lane] = tot;
-        if (syn_on && (tot & 2) && G.fail[s] != ts) G.fail[s] = ts;
-    }
-    __syncthreads();
-    const uint32_t parity = uint32_t(total_bits[lane]) & 1u;
-    for (int ch = wv; ch < nch; ch += nw) {
-        const int j0 = e0 + ch * C;
-        const int dc = min(C, d - ch * C);
-        float u[C], sf[C];
-        uint32_t neg = 0u;
-#pragma unroll
-        for (int jj = 0; jj < C; jj++) {
-            if (jj < dc) {
-                const int v = wave_uniform(G.col_idx[j0 + jj]);
-                const float lv = L[size_t(v) * S + s];
-                const float r = first ? 0.f : Codec<M>::dec(R[size_t(j0 + jj) * S + s]);
-                const float qv = clamp_msg(lv - r);
-                neg |= uint32_t(qv < 0.f) << jj;
-                u[jj] = tanh_complement(fabsf(qv));
-            }
-        }
-        float run = 0.f;
-#pragma unroll
-        for (int jj = C - 1; jj >= 0; jj--) {
-            if (jj < dc) {
-                sf[jj] = run;
-                run = dplus(u[jj], run);
-            }
-        }
-        run = G.aggd[size_t(cb + ch) * S + s];
-#pragma unroll
-        for (int jj = 0; jj < C; jj++) {
-            if (jj < dc) {
-                const float mag = magnitude_from_complement(dplus(run, sf[jj]));
-                const uint32_t sgn = parity ^ ((neg >> jj) & 1u);
-                R[size_t(j0 + jj) * S + s] = Codec<M>::enc(sgn ? -mag : mag);
-                run = dplus(run, u[jj]);
-            }
-        }
+        // the next item's wavefront 0 rewrites total_bits only after the first
+        // barrier of that item, which every wavefront reaches after reading it here
     }
 }
 
 // --------------------------------------------------------------- bit pass
 
 template <int M, int V>
-__global__ __launch_bounds__(256) void eng_bit(const EngGraph *__restrict__ graphs, Prefix pre, int32_t T,
+__global__ __launch_bounds__(256) void eng_bit(const EngGraph *__restrict__ graphs, int32_t ngraphs, int32_t T,
                                                int32_t early) {
     using MT = typename Codec<M>::T;
     // The previous step's turnover and admission are complete: move each
     // graph's queue head past the frames it admitted and empty its list.
-    if (blockIdx.x == 0 && threadIdx.x < pre.count) {
+    if (blockIdx.x == 0 && threadIdx.x < ngraphs) {
         const EngGraph &H = graphs[threadIdx.x];
         *H.head += *H.taken;
         *H.taken = 0;
         *H.list_count = 0;
     }
+    __shared__ Work w;
+    build_work(graphs, ngraphs, kBitItems, 64 * V, 1, w);
     const int lane = threadIdx.x & 63;
-    const int wave = wave_uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    if (wave >= pre.p[pre.count]) return;
-    const int c = find_graph(pre, wave);
-    const EngGraph &G = graphs[c];
-    const int32_t S = G.S;
-    const int groups = S / (64 * V);
-    const int local = wave - pre.p[c];
-    const int g = local % groups;
-    const int v = local / groups;
-    const int s0 = (g * 64 + lane) * V;
+    const int total = w.p[ngraphs];
+    const int stride = int(gridDim.x * (blockDim.x >> 6));
+    for (int item = wave_uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6); item < total; item += stride) {
+        const int c = work_graph(w, ngraphs, item);
+        const EngGraph &G = graphs[c];
+        const int32_t S = G.S;
+        const int groups = w.groups[c];
+        const int local = item - w.p[c];
+        const int g = local % groups;
+        const int v = local / groups;
+        const int s0 = (g * 64 + lane) * V;
 
-    int32_t q[V], t[V], f[V];
-    load_i32<V>(G.slot_q + s0, q);
-    load_i32<V>(G.slot_t + s0, t);
-    load_i32<V>(G.fail + s0, f);
-    bool adv[V];
-    bool any = false, all = true;
+        int32_t q[V], t[V], f[V];
+        load_i32<V>(G.slot_q + s0, q);
+        load_i32<V>(G.slot_t + s0, t);
+        load_i32<V>(G.fail + s0, f);
+        bool adv[V];
+        bool any = false, all = true;
 #pragma unroll
-    for (int k = 0; k < V; k++) {
-        adv[k] = q[k] >= 0 && !slot_stops(t[k], f[k], T, early);
-        any |= adv[k];
-        all &= adv[k];
-    }
-    if (__ballot(any) == 0) return;
-    if (!any) return;
+        for (int k = 0; k < V; k++) {
+            adv[k] = q[k] >= 0 && !slot_stops(t[k], f[k], T, early);
+            any |= adv[k];
+            all &= adv[k];
+        }
+        if (!any) continue;
 
-    const MT *R = static_cast<const MT *>(G.r);
-    float sum[V];
-    load_vec<kF32, V>(G.lch + size_t(v) * S + s0, sum);
-    const int a = wave_uniform(G.col_ptr[v]);
-    const int b = wave_uniform(G.col_ptr[v + 1]);
-    for (int k = a; k < b; k++) {
-        const int e = wave_uniform(G.csc_to_csr[k]);
-        float r[V];
-        load_vec<M, V>(R + size_t(e) * S + s0, r);
+        const MT *R = static_cast<const MT *>(G.r);
+        float sum[V];
+        load_vec<kF32, V>(G.lch + size_t(v) * S + s0, sum);
+        const int a = wave_uniform(G.col_ptr[v]);
+        const int b = wave_uniform(G.col_ptr[v + 1]);
+        for (int k = a; k < b; k++) {
+            const int e = wave_uniform(G.csc_to_csr[k]);
+            float r[V];
+            load_vec<M, V>(R + size_t(e) * S + s0, r);
 #pragma unroll
-        for (int z = 0; z < V; z++) sum[z] += r[z];
-    }
-    if (all) {
-        store_vec<kF32, V>(G.lpost + size_t(v) * S + s0, sum);
-    } else {
+            for (int z = 0; z < V; z++) sum[z] += r[z];
+        }
+        if (all) {
+            store_vec<kF32, V>(G.lpost + size_t(v) * S + s0, sum);
+        } else {
 #pragma unroll
-        for (int k = 0; k < V; k++)
-            if (adv[k]) G.lpost[size_t(v) * S + s0 + k] = sum[k];
+            for (int k = 0; k < V; k++)
+                if (adv[k]) G.lpost[size_t(v) * S + s0 + k] = sum[k];
+        }
     }
 }
 
@@ -483,30 +547,148 @@ __global__ __launch_bounds__(256) void eng_turnover(const EngGraph *__restrict__
     }
 }
 
-// One thread per listed slot, after the turnover: count the stopped frame as
-// done (its outputs are complete) and install the admitted frame, or leave the
-// slot empty when the graph's queue ran dry.
-__global__ __launch_bounds__(256) void eng_admit(const EngGraph *__restrict__ graphs, Prefix pre) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= pre.p[pre.count]) return;
-    const int c = find_graph(pre, x);
-    const EngGraph &G = graphs[c];
-    const int i = x - pre.p[c];
-    if (i >= *G.list_count) return;
-    const int32_t ent = G.list[i];
-    const int s = ent & 0x7fffffff;
-    if (ent < 0) {
-        const EngFrame old = G.slot_desc[s];
-        if (old.done) atomicAdd(old.done, 1);
+// Exclusive prefix count of `flag` over a 1024-thread workgroup (16 wavefronts);
+// `total` receives the workgroup's count.  `sh` holds 16 ints.
+__device__ __forceinline__ int block_rank(bool flag, int32_t *sh, int &total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint64_t m = __ballot(flag);
+    const int in_wave = __popcll(m & ((uint64_t(1) << lane) - 1u));
+    if (lane == 0) sh[w] = __popcll(m);
+    __syncthreads();
+    int before = 0, tot = 0;
+    for (int i = 0; i < nw; i++) {
+        const int c = sh[i];
+        before += i < w ? c : 0;
+        tot += c;
     }
-    const int32_t qi = *G.head + i;
-    if (i < *G.taken) {
-        G.slot_desc[s] = G.queue[qi % G.cap];
-        G.slot_t[s] = 0;
-        G.fail[s] = 0;
-        G.slot_q[s] = qi;
-    } else {
-        G.slot_q[s] = -1;
+    __syncthreads();
+    total = tot;
+    return before + in_wave;
+}
+
+// One workgroup per graph, after the turnover.
+// Admission: every listed slot counts its stopped frame as done (its outputs
+// are complete) and takes the next queued frame, or stays empty when the
+// graph's queue ran dry.
+// Repack (REPACK): when nothing is queued any more, A slots hold frames and
+// X - 1 is the highest such slot, and 2 A <= X, the frames in slots >= A move
+// into the empty slots below A (k-th one up to the k-th hole).  This kernel
+// moves the per-slot bookkeeping; eng_repack_move copies the state columns.
+template <bool REPACK>
+__global__ __launch_bounds__(1024) void eng_admit(const EngGraph *__restrict__ graphs) {
+    __shared__ int32_t sh[16];
+    __shared__ int32_t red[2][16];
+    const EngGraph &G = graphs[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int32_t count = *G.list_count;
+    const int32_t taken = *G.taken;
+    const int32_t head = *G.head;
+    for (int i = tid; i < count; i += blockDim.x) {
+        const int32_t ent = G.list[i];
+        const int s = ent & 0x7fffffff;
+        if (ent < 0) {
+            const EngFrame old = G.slot_desc[s];
+            if (old.done) atomicAdd(old.done, 1);
+        }
+        if (i < taken) {
+            const int32_t qi = head + i;
+            G.slot_desc[s] = G.queue[qi % G.cap];
+            G.slot_t[s] = 0;
+            G.fail[s] = 0;
+            G.slot_q[s] = qi;
+        } else {
+            G.slot_q[s] = -1;
+        }
+    }
+    if (tid == 0) *G.moves = 0;
+    __syncthreads();
+    const int S = G.S;
+    int a = 0, x = 0;
+    for (int s = tid; s < S; s += blockDim.x)
+        if (G.slot_q[s] >= 0) { a++; x = s + 1; }
+    // workgroup sum of a, max of x
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_down(a, off);
+        x = max(x, __shfl_down(x, off));
+    }
+    if ((tid & 63) == 0) { red[0][tid >> 6] = a; red[1][tid >> 6] = x; }
+    __syncthreads();
+    int A = 0, X = 0;
+    for (int i = 0; i < int(blockDim.x >> 6); i++) { A += red[0][i]; X = max(X, red[1][i]); }
+    // queued frames fill the holes at the next turnovers; repack only a drained pool
+    if (!REPACK || head + taken < *G.tail || X < kRepackMinExtent || 2 * A > X) {
+        if (tid == 0) *G.extent = X;
+        return;
+    }
+    int holes = 0, srcs = 0;
+    for (int s0 = 0; s0 < X; s0 += blockDim.x) {
+        const int s = s0 + tid;
+        const bool occ = s < X && G.slot_q[s] >= 0;
+        int th = 0, ts = 0;
+        const int rh = block_rank(s < A && !occ, sh, th);
+        const int rs = block_rank(s >= A && occ, sh, ts);
+        if (s < A && !occ) G.move_dst[holes + rh] = s;
+        if (s >= A && occ) G.move_src[srcs + rs] = s;
+        holes += th;
+        srcs += ts;
+    }
+    __syncthreads();   // the move lists are complete (holes == srcs)
+    for (int k = tid; k < holes; k += blockDim.x) {
+        const int src = G.move_src[k], dst = G.move_dst[k];
+        G.slot_desc[dst] = G.slot_desc[src];
+        G.slot_q[dst] = G.slot_q[src];
+        G.slot_t[dst] = G.slot_t[src];
+        G.fail[dst] = G.fail[src];
+        G.slot_q[src] = -1;
+    }
+    if (tid == 0) {
+        *G.moves = holes;
+        *G.extent = A;
+    }
+}
+
+// Copy the state columns of the repacked frames: every message row (edge),
+// channel-LLR row and posterior row of the graph, slot move_src[k] to slot
+// move_dst[k].  Sources lie above every destination, so the copies are
+// independent.  MSG_BYTES is the stored message size.
+template <int MSG_BYTES>
+__global__ __launch_bounds__(256) void eng_repack_move(const EngGraph *__restrict__ graphs, int32_t ngraphs) {
+    using MsgWord = typename std::conditional<MSG_BYTES == 2, uint16_t, uint32_t>::type;
+    __shared__ int64_t base[kMaxGraphs + 1];
+    __shared__ int32_t nm[kMaxGraphs];
+    if (threadIdx.x == 0) {
+        base[0] = 0;
+        for (int c = 0; c < ngraphs; c++) {
+            const EngGraph &H = graphs[c];
+            nm[c] = *H.moves;
+            const int64_t rows = int64_t(H.E) + 2 * int64_t(H.n);
+            base[c + 1] = base[c] + (nm[c] > 0 ? (rows + kMoveRows - 1) / kMoveRows : 0);
+        }
+    }
+    __syncthreads();
+    const int64_t total = base[ngraphs];
+    for (int64_t u = blockIdx.x; u < total; u += gridDim.x) {
+        int c = 0;
+        while (c + 1 < ngraphs && u >= base[c + 1]) c++;
+        const EngGraph &G = graphs[c];
+        const int moves = nm[c];
+        const int64_t E = G.E, n = G.n, S = G.S;
+        const int64_t r0 = (u - base[c]) * kMoveRows;
+        const int rcount = int(min(int64_t(kMoveRows), E + 2 * n - r0));
+        for (int idx = threadIdx.x; idx < rcount * moves; idx += blockDim.x) {
+            const int rr = idx / moves;
+            const int k = idx - rr * moves;
+            const int64_t row = r0 + rr;
+            const int64_t src = G.move_src[k], dst = G.move_dst[k];
+            if (row < E) {
+                MsgWord *R = static_cast<MsgWord *>(G.r);
+                R[row * S + dst] = R[row * S + src];
+            } else {
+                float *L = row < E + n ? G.lch : G.lpost;
+                const int64_t v = row < E + n ? row - E : row - E - n;
+                L[v * S + dst] = L[v * S + src];
+            }
+        }
     }
 }
 
@@ -522,13 +704,14 @@ struct ldpc_engine {
     int32_t ngraphs = 0, T = 0, V = 4, K = 8, msg = kF32;
     uint32_t flags = 0;
     bool early = true;
+    bool repack = true;
     std::vector<const ldpc_graph *> graphs;
     std::vector<int32_t> S, cap;
     std::vector<EngGraph> hg;
     void *dmem = nullptr;
     size_t dbytes = 0;
     EngGraph *d_graphs = nullptr;
-    int32_t *d_counters = nullptr;   // [ngraphs][4]: head, tail, retired, list count; then [ngraphs] taken
+    int32_t *d_counters = nullptr;   // [ngraphs][4]: head, tail, retired, list count; then [ngraphs] taken, moves
     ldpc_frame *h_stage = nullptr;   // pinned mirror of every queue ring
     std::vector<size_t> stage_off;
     int32_t *h_counters = nullptr;   // pinned copy of d_counters
@@ -539,9 +722,10 @@ struct ldpc_engine {
     std::vector<int64_t> submitted, head_seen, retired_seen;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    Prefix pre_rows[3], pre_hub, pre_bit, pre_slots;
+    Prefix pre_slots;
     bool has_rows[3] = {false, false, false}, has_hub = false;
-    int64_t bit_waves = 0, hub_blocks = 0, total_slots = 0, row_waves[3] = {0, 0, 0};
+    int64_t bit_waves = 0, hub_blocks = 0, total_slots = 0, row_waves[3] = {0, 0, 0};   // with every slot occupied
+    unsigned grid_rows[3] = {1, 1, 1}, grid_hub = 1, grid_bit = 1;   // workgroups per launch (grid-stride)
 };
 
 namespace {
@@ -554,26 +738,30 @@ template <int M, int V>
 void enqueue_step(ldpc_engine *e) {
     hipStream_t st = e->stream;
     const int32_t early = e->early ? 1 : 0;
+    const int32_t ng = e->ngraphs;
     if (e->has_rows[0])
-        hipLaunchKernelGGL((eng_check_rows<M, V, 8>), dim3(unsigned((e->row_waves[0] + 3) / 4)), dim3(256), 0, st,
-                           e->d_graphs, e->pre_rows[0], int32_t(ldpc::kClassD8), e->T, early);
+        hipLaunchKernelGGL((eng_check_rows<M, V, 8>), dim3(e->grid_rows[0]), dim3(256), 0, st, e->d_graphs, ng,
+                           int32_t(ldpc::kClassD8), e->T, early);
     if (e->has_rows[1])
-        hipLaunchKernelGGL((eng_check_chunk<M, V, ldpc::class_waves_per_row(ldpc::kClassD16)>),
-                           dim3(unsigned(e->row_waves[1])), dim3(256), 0, st, e->d_graphs, e->pre_rows[1],
-                           int32_t(ldpc::kClassD16), e->T, early);
+        hipLaunchKernelGGL((eng_check_chunk<M, V, ldpc::class_waves_per_row(ldpc::kClassD16)>), dim3(e->grid_rows[1]),
+                           dim3(256), 0, st, e->d_graphs, ng, int32_t(ldpc::kClassD16), e->T, early);
     if (e->has_rows[2])
         hipLaunchKernelGGL((eng_check_chunk<M, V, ldpc::class_waves_per_row(ldpc::kClassD128)>),
-                           dim3(unsigned(e->row_waves[2])), dim3(256), 0, st, e->d_graphs, e->pre_rows[2],
-                           int32_t(ldpc::kClassD128), e->T, early);
+                           dim3(e->grid_rows[2]), dim3(256), 0, st, e->d_graphs, ng, int32_t(ldpc::kClassD128), e->T,
+                           early);
     if (e->has_hub)
-        hipLaunchKernelGGL((eng_check_hub<M>), dim3(unsigned(e->hub_blocks)), dim3(256), 0, st, e->d_graphs,
-                           e->pre_hub, e->T, early);
-    hipLaunchKernelGGL((eng_bit<M, V>), dim3(unsigned(std::max<int64_t>(1, (e->bit_waves + 3) / 4))), dim3(256), 0,
-                       st, e->d_graphs, e->pre_bit, e->T, early);
+        hipLaunchKernelGGL((eng_check_hub<M>), dim3(e->grid_hub), dim3(256), 0, st, e->d_graphs, ng, e->T, early);
+    hipLaunchKernelGGL((eng_bit<M, V>), dim3(e->grid_bit), dim3(256), 0, st, e->d_graphs, ng, e->T, early);
     const unsigned slot_blocks = unsigned((e->total_slots + 255) / 256);
     hipLaunchKernelGGL(eng_advance, dim3(slot_blocks), dim3(256), 0, st, e->d_graphs, e->pre_slots, e->T, early);
     hipLaunchKernelGGL(eng_turnover, dim3(unsigned(kTurnoverBlocks)), dim3(256), 0, st, e->d_graphs, e->ngraphs);
-    hipLaunchKernelGGL(eng_admit, dim3(slot_blocks), dim3(256), 0, st, e->d_graphs, e->pre_slots);
+    if (e->repack) {
+        hipLaunchKernelGGL(eng_admit<true>, dim3(unsigned(e->ngraphs)), dim3(1024), 0, st, e->d_graphs);
+        hipLaunchKernelGGL((eng_repack_move<sizeof(typename Codec<M>::T)>), dim3(unsigned(kMoveBlocks)), dim3(256), 0,
+                           st, e->d_graphs, e->ngraphs);
+    } else {
+        hipLaunchKernelGGL(eng_admit<false>, dim3(unsigned(e->ngraphs)), dim3(1024), 0, st, e->d_graphs);
+    }
 }
 
 template <int M>
@@ -592,6 +780,36 @@ void enqueue_steps(ldpc_engine *e, int steps) {
             case kBF16: enqueue_step_v<kBF16>(e); break;
             default: enqueue_step_v<kF32>(e); break;
         }
+    }
+}
+
+// Workgroups per launch: as many as the device keeps resident at once (the
+// kernels loop over their items), never more than a full pool needs.
+template <int M, int V>
+void size_grids(ldpc_engine *e, int cus) {
+    auto fit = [cus](const void *k, int64_t need) -> unsigned {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, 0) != hipSuccess || per_cu < 1) {
+            (void)hipGetLastError();
+            per_cu = 1;
+        }
+        return unsigned(std::max<int64_t>(1, std::min<int64_t>(need, int64_t(per_cu) * cus)));
+    };
+    e->grid_rows[0] = fit(reinterpret_cast<const void *>(&eng_check_rows<M, V, 8>), (e->row_waves[0] + 3) / 4);
+    e->grid_rows[1] = fit(reinterpret_cast<const void *>(&eng_check_chunk<M, V, ldpc::class_waves_per_row(ldpc::kClassD16)>),
+                          e->row_waves[1]);
+    e->grid_rows[2] = fit(reinterpret_cast<const void *>(&eng_check_chunk<M, V, ldpc::class_waves_per_row(ldpc::kClassD128)>),
+                          e->row_waves[2]);
+    e->grid_hub = fit(reinterpret_cast<const void *>(&eng_check_hub<M>), e->hub_blocks);
+    e->grid_bit = fit(reinterpret_cast<const void *>(&eng_bit<M, V>), (e->bit_waves + 3) / 4);
+}
+
+template <int M>
+void size_grids_v(ldpc_engine *e, int cus) {
+    switch (e->V) {
+        case 1: size_grids<M, 1>(e, cus); break;
+        case 2: size_grids<M, 2>(e, cus); break;
+        default: size_grids<M, 4>(e, cus); break;
     }
 }
 
@@ -633,6 +851,7 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
         return LDPC_E_INVAL;
     }
     int V = 4, K = 8;
+    bool repack = true;
     if (opts) {
         for (int32_t r : opts->reserved)
             if (r != 0) { set_error("ldpc_engine_create: reserved options must be 0"); return LDPC_E_INVAL; }
@@ -648,6 +867,11 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
             return LDPC_E_INVAL;
         }
         if (opts->graph_steps) K = opts->graph_steps;
+        if (opts->no_compaction != 0 && opts->no_compaction != 1) {
+            set_error("ldpc_engine_create: no_compaction must be 0 or 1");
+            return LDPC_E_INVAL;
+        }
+        repack = opts->no_compaction == 0;
     }
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) { (void)hipGetLastError(); set_error("ldpc_engine_create: no device"); return LDPC_E_DEVICE; }
@@ -671,13 +895,14 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
     e->msg = (flags & LDPC_MSG_FP16) ? kF16 : (flags & LDPC_MSG_BF16) ? kBF16 : kF32;
     e->V = V;
     e->K = K;
+    e->repack = repack;
     e->graphs.assign(graphs, graphs + ngraphs);
     const int32_t unit = 64 * V;
     const size_t msg_bytes = e->msg == kF32 ? 4 : 2;
 
     // device layout: per graph state, then counters, turnover list, graph table
     size_t off = 0;
-    struct Offs { size_t lch, lpost, r, q, t, fail, desc, aggd, aggpre, aggbits, queue, list; };
+    struct Offs { size_t lch, lpost, r, q, t, fail, desc, aggd, aggpre, aggbits, queue, list, msrc, mdst; };
     std::vector<Offs> go(static_cast<size_t>(ngraphs));
     for (int32_t c = 0; c < ngraphs; c++) {
         const ldpc_graph *g = graphs[c];
@@ -697,9 +922,11 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
         o.aggbits = off; off = al256(off + size_t(g->hub_chunks) * S * 4);
         o.queue = off;   off = al256(off + size_t(queue_cap[c]) * sizeof(EngFrame));
         o.list = off;    off = al256(off + size_t(S) * 4);
+        o.msrc = off;    off = al256(off + size_t(S) * 4);
+        o.mdst = off;    off = al256(off + size_t(S) * 4);
         e->total_slots += S;
     }
-    const size_t off_counters = off; off = al256(off + size_t(ngraphs) * 5 * 4);
+    const size_t off_counters = off; off = al256(off + size_t(ngraphs) * kCounterInts * 4);
     const size_t off_graphs = off;   off = al256(off + size_t(ngraphs) * sizeof(EngGraph));
     e->dbytes = off;
 
@@ -718,6 +945,7 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
         G.row_ptr = g->d_row_ptr; G.col_idx = g->d_col_idx; G.col_ptr = g->d_col_ptr;
         G.csc_to_csr = g->d_csc_to_csr; G.class_rows = g->d_class_rows; G.hub_chunk_base = g->d_hub_chunk_base;
         G.n = g->n;
+        G.E = int32_t(g->E);
         G.S = e->S[size_t(c)];
         for (int k = 0; k <= ldpc::kNumClasses; k++) G.class_begin[k] = g->class_begin[k];
         G.lch = reinterpret_cast<float *>(base + o.lch);
@@ -736,8 +964,12 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
         G.tail = e->d_counters + 4 * c + 1;
         G.retired = e->d_counters + 4 * c + 2;
         G.list_count = e->d_counters + 4 * c + 3;
-        G.taken = e->d_counters + 4 * c + 4 * ngraphs;
+        G.taken = e->d_counters + 4 * ngraphs + c;
+        G.moves = e->d_counters + 5 * ngraphs + c;
+        G.extent = e->d_counters + 6 * ngraphs + c;
         G.list = reinterpret_cast<int32_t *>(base + o.list);
+        G.move_src = reinterpret_cast<int32_t *>(base + o.msrc);
+        G.move_dst = reinterpret_cast<int32_t *>(base + o.mdst);
         G.chunks = (g->n + kTurnChunk - 1) / kTurnChunk;
         e->hg.push_back(G);
         // every slot starts empty, with defined message state
@@ -747,50 +979,53 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
             (err = hipMemsetAsync(G.fail, 0, size_t(G.S) * 4, e->stream)) != hipSuccess)
             return hip_fail(e, "ldpc_engine_create: hipMemsetAsync", err);
     }
-    if ((err = hipMemsetAsync(e->d_counters, 0, size_t(ngraphs) * 20, e->stream)) != hipSuccess ||
+    if ((err = hipMemsetAsync(e->d_counters, 0, size_t(ngraphs) * kCounterInts * 4, e->stream)) != hipSuccess ||
         (err = hipMemcpyAsync(e->d_graphs, e->hg.data(), e->hg.size() * sizeof(EngGraph), hipMemcpyHostToDevice,
                               e->stream)) != hipSuccess)
         return hip_fail(e, "ldpc_engine_create: initialisation", err);
 
-    // work prefix tables
-    // D8: waves of one (row, slot group) each; chunked classes: 256-thread blocks of 4 / WPR (row, group) items
+    // work sizes with every slot occupied: waves (D8 rows, bits) or workgroups (chunked and long rows)
     for (int k = 0; k < 3; k++) {
-        Prefix &p = e->pre_rows[k];
-        p.count = ngraphs;
-        p.p[0] = 0;
         const int rpb = k == 0 ? 1 : 4 / ldpc::class_waves_per_row(k);
+        int64_t tot = 0;
         for (int32_t c = 0; c < ngraphs; c++) {
             const ldpc_graph *g = graphs[c];
             const int64_t items = int64_t(g->class_begin[k + 1] - g->class_begin[k]) * (e->S[size_t(c)] / (64 * V));
-            p.p[c + 1] = int32_t(p.p[c] + (items + rpb - 1) / rpb);
+            tot += (items + rpb - 1) / rpb;
         }
-        e->row_waves[k] = p.p[ngraphs];   // waves (D8) or blocks (chunked classes)
-        e->has_rows[k] = e->row_waves[k] > 0;
+        e->row_waves[k] = tot;
+        e->has_rows[k] = tot > 0;
     }
-    e->pre_hub.count = ngraphs;
-    e->pre_hub.p[0] = 0;
-    e->pre_bit.count = ngraphs;
-    e->pre_bit.p[0] = 0;
     e->pre_slots.count = ngraphs;
     e->pre_slots.p[0] = 0;
     for (int32_t c = 0; c < ngraphs; c++) {
         const ldpc_graph *g = graphs[c];
         const int64_t hubs = g->class_begin[ldpc::kClassHub + 1] - g->class_begin[ldpc::kClassHub];
-        e->pre_hub.p[c + 1] = int32_t(e->pre_hub.p[c] + hubs * (e->S[size_t(c)] / 64));
-        e->pre_bit.p[c + 1] = int32_t(e->pre_bit.p[c] + int64_t(g->n) * (e->S[size_t(c)] / (64 * V)));
+        e->hub_blocks += hubs * (e->S[size_t(c)] / 64);
+        e->bit_waves += int64_t(g->n) * (e->S[size_t(c)] / (64 * V));
         e->pre_slots.p[c + 1] = e->pre_slots.p[c] + e->S[size_t(c)];
     }
-    e->hub_blocks = e->pre_hub.p[ngraphs];
     e->has_hub = e->hub_blocks > 0;
-    e->bit_waves = e->pre_bit.p[ngraphs];
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
+            (void)hipGetLastError();
+            cus = 1;
+        }
+        switch (e->msg) {
+            case kF16: size_grids_v<kF16>(e, cus); break;
+            case kBF16: size_grids_v<kBF16>(e, cus); break;
+            default: size_grids_v<kF32>(e, cus); break;
+        }
+    }
 
     // pinned staging for queue entries and counters
     size_t stage = 0;
     for (int32_t c = 0; c < ngraphs; c++) { e->stage_off.push_back(stage); stage += size_t(e->cap[size_t(c)]); }
     if ((err = hipHostMalloc(reinterpret_cast<void **>(&e->h_stage), stage * sizeof(ldpc_frame), 0)) != hipSuccess ||
-        (err = hipHostMalloc(reinterpret_cast<void **>(&e->h_counters), size_t(ngraphs) * 20, 0)) != hipSuccess ||
-        (err = hipHostMalloc(reinterpret_cast<void **>(&e->h_async[0]), size_t(ngraphs) * 20, 0)) != hipSuccess ||
-        (err = hipHostMalloc(reinterpret_cast<void **>(&e->h_async[1]), size_t(ngraphs) * 20, 0)) != hipSuccess ||
+        (err = hipHostMalloc(reinterpret_cast<void **>(&e->h_counters), size_t(ngraphs) * kCounterInts * 4, 0)) != hipSuccess ||
+        (err = hipHostMalloc(reinterpret_cast<void **>(&e->h_async[0]), size_t(ngraphs) * kCounterInts * 4, 0)) != hipSuccess ||
+        (err = hipHostMalloc(reinterpret_cast<void **>(&e->h_async[1]), size_t(ngraphs) * kCounterInts * 4, 0)) != hipSuccess ||
         (err = hipEventCreateWithFlags(&e->ev_async[0], hipEventDisableTiming)) != hipSuccess ||
         (err = hipEventCreateWithFlags(&e->ev_async[1], hipEventDisableTiming)) != hipSuccess)
         return hip_fail(e, "ldpc_engine_create: hipHostMalloc", err);
@@ -922,7 +1157,7 @@ extern "C" ldpc_status ldpc_engine_step(ldpc_engine *e, int32_t replays) {
             // counters of this replay, for capacity checks that must not wait
             const int p = e->parity;
             e->parity ^= 1;
-            err = hipMemcpyAsync(e->h_async[p], e->d_counters, size_t(e->ngraphs) * 20, hipMemcpyDeviceToHost,
+            err = hipMemcpyAsync(e->h_async[p], e->d_counters, size_t(e->ngraphs) * kCounterInts * 4, hipMemcpyDeviceToHost,
                                  e->stream);
             if (err == hipSuccess) err = hipEventRecord(e->ev_async[p], e->stream);
             e->async_pending[p] = err == hipSuccess;
@@ -938,7 +1173,7 @@ extern "C" ldpc_status ldpc_engine_step(ldpc_engine *e, int32_t replays) {
 
 extern "C" ldpc_status ldpc_engine_poll(ldpc_engine *e, int64_t *retired, int64_t *pending) {
     if (!e) { set_error("ldpc_engine_poll: NULL engine"); return LDPC_E_INVAL; }
-    hipError_t err = hipMemcpyAsync(e->h_counters, e->d_counters, size_t(e->ngraphs) * 20, hipMemcpyDeviceToHost,
+    hipError_t err = hipMemcpyAsync(e->h_counters, e->d_counters, size_t(e->ngraphs) * kCounterInts * 4, hipMemcpyDeviceToHost,
                                     e->stream);
     if (err == hipSuccess) err = hipStreamSynchronize(e->stream);
     if (err != hipSuccess) {

@@ -49,7 +49,7 @@ class ServerOpts(ctypes.Structure):
 
 class EngineOpts(ctypes.Structure):
     _fields_ = [("lane_slots", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("no_compaction", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class LdpcError(RuntimeError):
@@ -269,7 +269,7 @@ class Engine:
     """Batched decoder with continuous refill (ldpc_engine_*) over several graphs."""
 
     def __init__(self, graphs, slots, queue_cap, max_iter: int, flags: int = 0, lane_slots: int = 0,
-                 graph_steps: int = 0):
+                 graph_steps: int = 0, repack: bool = True):
         lib = load_library()
         self._lib = lib
         self.graphs = list(graphs)
@@ -279,7 +279,7 @@ class Engine:
         qc = np.ascontiguousarray(queue_cap, dtype=np.int32)
         if sl.size != ng or qc.size != ng:
             raise ValueError("one slot count and one queue capacity per graph")
-        opts = EngineOpts(lane_slots, graph_steps)
+        opts = EngineOpts(lane_slots, graph_steps, 0 if repack else 1)
         self._h = ctypes.c_void_p()
         _check(lib.ldpc_engine_create(hs, ng, _np_ptr(sl), _np_ptr(qc), int(max_iter), int(flags),
                                       ctypes.byref(opts), ctypes.byref(self._h)), "ldpc_engine_create")

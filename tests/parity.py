@@ -83,3 +83,29 @@ def compare(code, llr, max_iter: int, early_stop: bool = True, flags: int = 0, f
             f"iters gpu/oracle={int(g['iters'][f])}/{int(ora['iters'][f])} ok gpu/oracle="
             f"{int(g['ok'][f])}/{int(ora['ok'][f])} max|dL|={float(err[f].max()):.3e} stats={stats}")
     return stats
+
+
+def first_iteration_bound(code, llr, lmax: float = 64.0):
+    """[F][n]: sum over the checks of v of min(lmax, min |Lch| over the check's other bits)."""
+    F = llr.shape[0]
+    a = np.minimum(np.abs(llr.astype(np.float64)), lmax)          # [F][n]
+    rows, cols = code.rows.astype(np.int64), code.cols.astype(np.int64)
+    mag = a[:, cols]                                               # [F][E]
+    big = np.full((F, code.m), np.inf)
+    first = big.copy()
+    arg = np.full((F, code.m), -1, np.int64)
+    for e in range(code.nnz):     # smallest per check, and which edge holds it
+        c = rows[e]
+        upd = mag[:, e] < first[:, c]
+        first[upd, c] = mag[upd, e]
+        arg[upd, c] = e
+    second = big.copy()
+    for e in range(code.nnz):
+        c = rows[e]
+        x = np.where(arg[:, c] == e, np.inf, mag[:, e])
+        second[:, c] = np.minimum(second[:, c], x)
+    excl = np.where(arg[:, rows] == np.arange(code.nnz)[None, :], second[:, rows], first[:, rows])
+    excl = np.minimum(excl, lmax)                                  # degree-1 checks: clamp of the empty rule
+    bound = np.zeros((F, code.n))
+    np.add.at(bound.T, cols, excl.T)
+    return bound

@@ -26,12 +26,14 @@ def _announce(name, **kw):
     print(f"[case] {name} {kw}", flush=True)
 
 
-def _engine_decode(codes, llrs, slots, T, flags=0, lane_slots=0, graph_steps=0, want_llr=True, cap=None):
+def _engine_decode(codes, llrs, slots, T, flags=0, lane_slots=0, graph_steps=0, want_llr=True, cap=None,
+                   repack=True):
     import torch
     from paper_1609_01567_amd import ldpc
     graphs = [ldpc.Graph.from_code(c) for c in codes]
     caps = cap or [max(1, x.shape[0]) for x in llrs]
-    eng = ldpc.Engine(graphs, slots, caps, T, flags=flags, lane_slots=lane_slots, graph_steps=graph_steps)
+    eng = ldpc.Engine(graphs, slots, caps, T, flags=flags, lane_slots=lane_slots, graph_steps=graph_steps,
+                      repack=repack)
     jobs = [(i, torch.from_numpy(np.ascontiguousarray(x)).cuda()) for i, x in enumerate(llrs)]
     # bound: every frame needs at most T+1 steps once admitted; admissions follow slot turnover
     steps = sum((x.shape[0] // max(1, sl) + 2) * (T + 2) for x, sl in zip(llrs, slots)) + 8
@@ -152,3 +154,45 @@ def test_engine_queue_backpressure_and_incremental_submit():
     r, p = eng.poll()
     assert r.tolist() == [200] and p.tolist() == [0]
     eng.close()
+
+
+@pytest.mark.parametrize("lane_slots", [1, 2, 4])
+@pytest.mark.parametrize("msg", ["fp32", "fp16"])
+def test_engine_repack_equals_plain(lane_slots, msg):
+    """All frames admitted at once into a large pool: as frames finish, the
+    scattered survivors are repacked into the low slots again and again."""
+    from paper_1609_01567_amd import ldpc
+    flags = {"fp32": 0, "fp16": ldpc.MSG_FP16}[msg]
+    code = li.random_small_code(600, 300, 3, seed=8)
+    llr = li.awgn_llr(code.n, 900, li.ebn0_to_sigma2(1.0, code.rate), seed=19)
+    _announce("engine-repack", frames=900, lane_slots=lane_slots, msg=msg)
+    on = _engine_decode([code], [llr], [1024], 40, flags=flags, lane_slots=lane_slots, graph_steps=3)[0]
+    off = _engine_decode([code], [llr], [1024], 40, flags=flags, lane_slots=lane_slots, graph_steps=3,
+                         repack=False)[0]
+    plain = gpu_decode(code, llr, 40, flags=flags)
+    assert len(set(on["iters"].tolist())) > 10     # a spread of stopping iterations
+    _assert_same(on, off, "repack vs no repack")
+    _assert_same(on, plain, "repack vs plain")
+
+
+def test_engine_repack_with_long_rows_and_many_graphs():
+    """Repacking under rows of every class (the >128-edge path keeps per-slot
+    scratch) and with 16 graphs in one engine (counters of every graph)."""
+    rng = np.random.default_rng(11)
+    cdeg = np.concatenate([[300, 140, 64, 40, 33], rng.integers(3, 33, size=95)])
+    E = int(cdeg.sum())
+    bdeg = np.full(700, E // 700)
+    bdeg[: E - bdeg.sum()] += 1
+    hub = li.socket_code(bdeg, cdeg, seed=12)
+    codes = [hub] + [li.random_small_code(200 + 40 * i, 100 + 20 * i, 3, seed=60 + i) for i in range(15)]
+    llrs = [li.awgn_llr(hub.n, 150, 0.7, seed=13)]
+    llrs += [li.awgn_llr(c.n, 40 + 7 * i, li.ebn0_to_sigma2(1.0, c.rate), seed=80 + i)
+             for i, c in enumerate(codes[1:])]
+    _announce("engine-repack-16-graphs", frames=sum(x.shape[0] for x in llrs))
+    slots = [256] * len(codes)
+    on = _engine_decode(codes, llrs, slots, 25, lane_slots=2, graph_steps=4)
+    off = _engine_decode(codes, llrs, slots, 25, lane_slots=2, graph_steps=4, repack=False)
+    for i, (c, x) in enumerate(zip(codes, llrs)):
+        plain = gpu_decode(c, x, 25)
+        _assert_same(on[i], off[i], f"graph {i}: repack vs no repack")
+        _assert_same(on[i], plain, f"graph {i}: engine vs plain")

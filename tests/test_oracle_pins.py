@@ -11,6 +11,8 @@ or the mathematics fixes independently:
 * the paper's own probability-domain Algorithm 1 (q0/q1, r0/r1 products),
   written out independently, pins the LLR-domain form on a loopy graph;
 * closed forms: single parity check (tanh rule), path/repetition code (sum);
+* the magnitude of the exact check combination never exceeds its smallest
+  input, which bounds the posterior shift of the first iteration;
 * special cases: noiseless input stops after 1 iteration, all-zero LLRs give
   the tie decision 0, a degree-1 check adds +LMAX, sign symmetry is exact.
 """
@@ -211,6 +213,20 @@ def test_path_code_posterior_is_total_sum(n):
     got = oracle.decode(code, llr, max_iter=n - 1, early_stop=False)["lpost"]
     want = llr.astype(np.float64).sum(axis=1, keepdims=True) * np.ones((1, n))
     np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-12)
+
+
+def test_first_iteration_messages_no_larger_than_smallest_other_input():
+    """|a (+) b| <= min(|a|, |b|) for the exact check combination, so after one
+    iteration |Lpost - Lch| is at most the sum over the bit's checks of the
+    smallest clamped |Lch| among each check's other bits."""
+    from parity import first_iteration_bound
+    code = li.random_small_code(300, 150, 3, seed=31)
+    llr = li.awgn_llr(code.n, 12, 0.8, seed=77)
+    got = oracle.decode(code, llr, max_iter=1, early_stop=False)["lpost"]
+    moved = np.abs(got - llr.astype(np.float64))
+    bound = first_iteration_bound(code, llr)
+    assert (moved <= bound * (1 + 1e-12) + 1e-12).all()
+    assert (moved > 0.5 * bound).mean() > 0.05     # the bound is attained closely somewhere
 
 
 # ------------------------------------------------------- special cases

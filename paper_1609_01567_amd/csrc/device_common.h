@@ -155,7 +155,9 @@ __device__ __forceinline__ void edge_input(const float *__restrict__ L, const fl
 
 // Check rule for a whole row of d <= DMAX edges held in registers: exclusive
 // suffixes, then exclusive prefixes combined on the fly; R is updated in place.
-template <int M, int V, int DMAX>
+// UNIFORM: every lane of the wavefront works on the same row (indices are read
+// once per wavefront); otherwise each lane walks its own row.
+template <int M, int V, int DMAX, bool UNIFORM = true>
 __device__ __forceinline__ void row_rule(const int32_t *__restrict__ col_idx, int e0, int d,
                                          const float *__restrict__ L, const float *__restrict__ Lalt,
                                          typename Codec<M>::T *__restrict__ R, int32_t S, int s0,
@@ -168,7 +170,7 @@ __device__ __forceinline__ void row_rule(const int32_t *__restrict__ col_idx, in
 #pragma unroll
     for (int j = 0; j < DMAX; j++) {
         if (j < d) {
-            const int v = wave_uniform(col_idx[e0 + j]);
+            const int v = UNIFORM ? wave_uniform(col_idx[e0 + j]) : col_idx[e0 + j];
             edge_input<M, V>(L, Lalt, R, size_t(v) * S + s0, size_t(e0 + j) * S + s0, src, j, u[j], neg, syn);
         }
     }

@@ -138,22 +138,34 @@ __device__ __forceinline__ void eng_syndrome(const EngGraph &G, const EngLane<V>
 // the chunked classes a workgroup of `per` such pairs.  Only the groups below
 // each graph's extent (one past its highest occupied slot) count, so passes
 // over empty pools cost nothing but the launch.  Built by every workgroup.
+//
+// Packed items (PACK): once a graph's extent fits in 64 / rpw lanes (times V
+// slots), a wavefront takes rpw rows or bits at once, 64 / rpw lanes each
+// (rpw = 2, 4, 8 or 16), so a nearly drained pool costs few wavefronts.
 struct Work {
     int32_t p[kMaxGraphs + 1];
     int32_t groups[kMaxGraphs];
+    int32_t rpw[kMaxGraphs];
 };
+constexpr int kMaxPack = 16;
 constexpr int kBitItems = -1;   // `cls` value for the bit pass: items are bits
 
+template <bool PACK = false>
 __device__ __forceinline__ void build_work(const EngGraph *__restrict__ graphs, int32_t ngraphs, int cls,
                                            int unit, int per, Work &w) {
     if (threadIdx.x == 0) {
         w.p[0] = 0;
         for (int c = 0; c < ngraphs; c++) {
             const EngGraph &G = graphs[c];
-            const int32_t gr = (*G.extent + unit - 1) / unit;
+            const int32_t x = *G.extent;
+            const int32_t gr = (x + unit - 1) / unit;
             const int32_t units = cls == kBitItems ? G.n : G.class_begin[cls + 1] - G.class_begin[cls];
+            int32_t rpw = 1;
+            if (PACK && x > 0)
+                while (rpw < kMaxPack && (unit / (2 * rpw)) >= x) rpw *= 2;   // unit = 64 V slots per wavefront
             w.groups[c] = gr;
-            w.p[c + 1] = w.p[c] + (units * gr + per - 1) / per;
+            w.rpw[c] = rpw;
+            w.p[c + 1] = w.p[c] + (rpw > 1 ? (units + rpw - 1) / rpw : (units * gr + per - 1) / per);
         }
     }
     __syncthreads();
@@ -172,28 +184,45 @@ __global__ __launch_bounds__(256) void eng_check_rows(const EngGraph *__restrict
                                                       int32_t cls, int32_t T, int32_t early) {
     using MT = typename Codec<M>::T;
     __shared__ Work w;
-    build_work(graphs, ngraphs, cls, 64 * V, 1, w);
+    build_work<true>(graphs, ngraphs, cls, 64 * V, 1, w);
     const int lane = threadIdx.x & 63;
     const int total = w.p[ngraphs];
     const int stride = int(gridDim.x * (blockDim.x >> 6));
     for (int item = wave_uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6); item < total; item += stride) {
         const int c = work_graph(w, ngraphs, item);
         const EngGraph &G = graphs[c];
-        const int groups = w.groups[c];
         const int local = item - w.p[c];
-        const int g = local % groups;
-        const int rk = local / groups;
-        const int s0 = (g * 64 + lane) * V;
+        const int rpw = w.rpw[c];
+        const int nrows = G.class_begin[cls + 1] - G.class_begin[cls];
+        int rk, s0;
+        if (rpw == 1) {
+            const int groups = w.groups[c];
+            rk = local / groups;
+            s0 = ((local - rk * groups) * 64 + lane) * V;
+        } else {
+            const int lpr = 64 / rpw;
+            rk = local * rpw + lane / lpr;
+            s0 = (lane % lpr) * V;
+        }
         EngLane<V> ln;
-        eng_lane<V>(G, s0, T, early, ln);
+        ln.active = false;
+        if (rk < nrows) eng_lane<V>(G, s0, T, early, ln);
         if (!ln.active) continue;
-        const int row = wave_uniform(G.class_rows[G.class_begin[cls] + rk]);
-        const int e0 = wave_uniform(G.row_ptr[row]);
-        const int d = wave_uniform(G.row_ptr[row + 1]) - e0;
         int syn[V];
 #pragma unroll
         for (int k = 0; k < V; k++) syn[k] = 0;
-        row_rule<M, V, DMAX>(G.col_idx, e0, d, G.lpost, G.lch, static_cast<MT *>(G.r), G.S, s0, ln.src, syn);
+        MT *R = static_cast<MT *>(G.r);
+        if (rpw == 1) {
+            const int row = wave_uniform(G.class_rows[G.class_begin[cls] + rk]);
+            const int e0 = wave_uniform(G.row_ptr[row]);
+            const int d = wave_uniform(G.row_ptr[row + 1]) - e0;
+            row_rule<M, V, DMAX, true>(G.col_idx, e0, d, G.lpost, G.lch, R, G.S, s0, ln.src, syn);
+        } else {
+            const int row = G.class_rows[G.class_begin[cls] + rk];
+            const int e0 = G.row_ptr[row];
+            const int d = G.row_ptr[row + 1] - e0;
+            row_rule<M, V, DMAX, false>(G.col_idx, e0, d, G.lpost, G.lch, R, G.S, s0, ln.src, syn);
+        }
         eng_syndrome<V>(G, ln, syn, s0);
     }
 }
@@ -391,10 +420,49 @@ __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict_
 
 // --------------------------------------------------------------- bit pass
 
+// Posterior of bit v for the lane's V slots (iteration t_s + 1 of every slot
+// whose frame continues).  UNIFORM: one bit per wavefront.
+template <int M, int V, bool UNIFORM>
+__device__ __forceinline__ void bit_item(const EngGraph &G, int v, int s0, int32_t T, int32_t early) {
+    using MT = typename Codec<M>::T;
+    const int32_t S = G.S;
+    int32_t q[V], t[V], f[V];
+    load_i32<V>(G.slot_q + s0, q);
+    load_i32<V>(G.slot_t + s0, t);
+    load_i32<V>(G.fail + s0, f);
+    bool adv[V];
+    bool any = false, all = true;
+#pragma unroll
+    for (int k = 0; k < V; k++) {
+        adv[k] = q[k] >= 0 && !slot_stops(t[k], f[k], T, early);
+        any |= adv[k];
+        all &= adv[k];
+    }
+    if (!any) return;
+    const MT *R = static_cast<const MT *>(G.r);
+    float sum[V];
+    load_vec<kF32, V>(G.lch + size_t(v) * S + s0, sum);
+    const int a = UNIFORM ? wave_uniform(G.col_ptr[v]) : G.col_ptr[v];
+    const int b = UNIFORM ? wave_uniform(G.col_ptr[v + 1]) : G.col_ptr[v + 1];
+    for (int k = a; k < b; k++) {
+        const int e = UNIFORM ? wave_uniform(G.csc_to_csr[k]) : G.csc_to_csr[k];
+        float r[V];
+        load_vec<M, V>(R + size_t(e) * S + s0, r);
+#pragma unroll
+        for (int z = 0; z < V; z++) sum[z] += r[z];
+    }
+    if (all) {
+        store_vec<kF32, V>(G.lpost + size_t(v) * S + s0, sum);
+    } else {
+#pragma unroll
+        for (int k = 0; k < V; k++)
+            if (adv[k]) G.lpost[size_t(v) * S + s0 + k] = sum[k];
+    }
+}
+
 template <int M, int V>
 __global__ __launch_bounds__(256) void eng_bit(const EngGraph *__restrict__ graphs, int32_t ngraphs, int32_t T,
                                                int32_t early) {
-    using MT = typename Codec<M>::T;
     // The previous step's turnover and admission are complete: move each
     // graph's queue head past the frames it admitted and empty its list.
     if (blockIdx.x == 0 && threadIdx.x < ngraphs) {
@@ -404,52 +472,23 @@ __global__ __launch_bounds__(256) void eng_bit(const EngGraph *__restrict__ grap
         *H.list_count = 0;
     }
     __shared__ Work w;
-    build_work(graphs, ngraphs, kBitItems, 64 * V, 1, w);
+    build_work<true>(graphs, ngraphs, kBitItems, 64 * V, 1, w);
     const int lane = threadIdx.x & 63;
     const int total = w.p[ngraphs];
     const int stride = int(gridDim.x * (blockDim.x >> 6));
     for (int item = wave_uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6); item < total; item += stride) {
         const int c = work_graph(w, ngraphs, item);
         const EngGraph &G = graphs[c];
-        const int32_t S = G.S;
-        const int groups = w.groups[c];
         const int local = item - w.p[c];
-        const int g = local % groups;
-        const int v = local / groups;
-        const int s0 = (g * 64 + lane) * V;
-
-        int32_t q[V], t[V], f[V];
-        load_i32<V>(G.slot_q + s0, q);
-        load_i32<V>(G.slot_t + s0, t);
-        load_i32<V>(G.fail + s0, f);
-        bool adv[V];
-        bool any = false, all = true;
-#pragma unroll
-        for (int k = 0; k < V; k++) {
-            adv[k] = q[k] >= 0 && !slot_stops(t[k], f[k], T, early);
-            any |= adv[k];
-            all &= adv[k];
-        }
-        if (!any) continue;
-
-        const MT *R = static_cast<const MT *>(G.r);
-        float sum[V];
-        load_vec<kF32, V>(G.lch + size_t(v) * S + s0, sum);
-        const int a = wave_uniform(G.col_ptr[v]);
-        const int b = wave_uniform(G.col_ptr[v + 1]);
-        for (int k = a; k < b; k++) {
-            const int e = wave_uniform(G.csc_to_csr[k]);
-            float r[V];
-            load_vec<M, V>(R + size_t(e) * S + s0, r);
-#pragma unroll
-            for (int z = 0; z < V; z++) sum[z] += r[z];
-        }
-        if (all) {
-            store_vec<kF32, V>(G.lpost + size_t(v) * S + s0, sum);
+        const int rpw = w.rpw[c];
+        if (rpw == 1) {
+            const int groups = w.groups[c];
+            const int v = local / groups;
+            bit_item<M, V, true>(G, v, ((local - v * groups) * 64 + lane) * V, T, early);
         } else {
-#pragma unroll
-            for (int k = 0; k < V; k++)
-                if (adv[k]) G.lpost[size_t(v) * S + s0 + k] = sum[k];
+            const int lpr = 64 / rpw;
+            const int v = local * rpw + lane / lpr;
+            if (v < G.n) bit_item<M, V, false>(G, v, (lane % lpr) * V, T, early);
         }
     }
 }

@@ -347,13 +347,7 @@ __global__ __launch_bounds__(256) void bit_kernel(const int32_t *__restrict__ co
     load_vec<kF32, V>(Lch + size_t(v) * S + s0, sum);
     const int a = wave_uniform(col_ptr[v]);
     const int b = wave_uniform(col_ptr[v + 1]);
-    for (int k = a; k < b; k++) {
-        const int e = wave_uniform(csc_to_csr[k]);
-        float r[V];
-        load_vec<M, V>(R + size_t(e) * S + s0, r);
-#pragma unroll
-        for (int q = 0; q < V; q++) sum[q] += r[q];
-    }
+    bit_sum<M, V, true>(csc_to_csr, a, b, R, S, s0, sum);
     bool all = true;
 #pragma unroll
     for (int k = 0; k < V; k++) all &= act[k];
@@ -561,7 +555,7 @@ template <int M, int V>
 void launch_check_pass(const ldpc_graph *g, int mode, const float *L, const Bufs &b, int32_t S, int32_t syn_iter,
                        hipStream_t st) {
     launch_rows<M, V, 8>(g, ldpc::kClassD8, mode, L, b, S, syn_iter, st);
-    launch_chunked<M, V, ldpc::class_waves_per_row(ldpc::kClassD16)>(g, ldpc::kClassD16, mode, L, b, S, syn_iter, st);
+    launch_rows<M, ldpc::class_lane_slots(ldpc::kClassD16, V), 16>(g, ldpc::kClassD16, mode, L, b, S, syn_iter, st);
     launch_chunked<M, V, ldpc::class_waves_per_row(ldpc::kClassD128)>(g, ldpc::kClassD128, mode, L, b, S, syn_iter,
                                                                        st);
     launch_hub<M>(g, mode, L, b, S, syn_iter, st);

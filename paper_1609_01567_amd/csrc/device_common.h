@@ -118,38 +118,59 @@ struct SlotSrc {
     bool read_r;
 };
 
-// Inputs of one edge for the lane's slots: Q = clamp(L - R_old), its sign bit
-// (into bit j of neg) and its u = 1 - tanh(|Q|/2); the sign of L feeds the
-// syndrome of the estimate that L holds (Algorithm 7).
-template <int M, int V>
-__device__ __forceinline__ void edge_input(const float *__restrict__ L, const float *__restrict__ Lalt,
-                                           const typename Codec<M>::T *__restrict__ R, size_t lofs, size_t rofs,
-                                           const SlotSrc<V> &src, int j, float (&u)[V], uint32_t (&neg)[V],
-                                           int (&syn)[V]) {
-    float lv[V], r[V];
-    load_vec<kF32, V>(L + lofs, lv);
-    if (src.any_alt) {
-        float lc[V];
-        load_vec<kF32, V>(Lalt + lofs, lc);
+// Inputs of edges j0 .. j0+count-1 (1 <= count <= C) for the lane's slots:
+// Q = clamp(L - R_old), its sign bit (bit j of neg) and u = 1 - tanh(|Q|/2);
+// the sign of L feeds the syndrome of the estimate that L holds (Algorithm 7).
+// Every index load and then every message load is issued before any value is
+// used: positions past `count` repeat the last edge (same addresses, no
+// branch), so the loads of a row are in flight together instead of one edge
+// at a time.  UNIFORM: all lanes walk the same row (indices read once per
+// wavefront).
+template <int M, int V, int C, bool UNIFORM>
+__device__ __forceinline__ void gather_edges(const int32_t *__restrict__ col_idx, int j0, int count,
+                                             const float *__restrict__ L, const float *__restrict__ Lalt,
+                                             const typename Codec<M>::T *__restrict__ R, int32_t S, int s0,
+                                             const SlotSrc<V> &src, float (&u)[C][V], uint32_t (&neg)[V],
+                                             int (&syn)[V]) {
+    int vix[C];
 #pragma unroll
-        for (int k = 0; k < V; k++) if (src.alt[k]) lv[k] = lc[k];
+    for (int j = 0; j < C; j++) {
+        const int e = j0 + (j < count ? j : count - 1);
+        vix[j] = UNIFORM ? wave_uniform(col_idx[e]) : col_idx[e];
     }
-    if (src.read_r) {
-        load_vec<M, V>(R + rofs, r);
-        if (src.any_alt) {
+    float lv[C][V], r[C][V];
 #pragma unroll
-            for (int k = 0; k < V; k++) if (src.alt[k]) r[k] = 0.f;
+    for (int j = 0; j < C; j++) {
+        const int e = j0 + (j < count ? j : count - 1);
+        load_vec<kF32, V>(L + size_t(vix[j]) * S + s0, lv[j]);
+        if (src.read_r) {
+            load_vec<M, V>(R + size_t(e) * S + s0, r[j]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < V; k++) r[j][k] = 0.f;
         }
-    } else {
+    }
+    if (src.any_alt) {
 #pragma unroll
-        for (int k = 0; k < V; k++) r[k] = 0.f;
+        for (int j = 0; j < C; j++) {
+            float lc[V];
+            load_vec<kF32, V>(Lalt + size_t(vix[j]) * S + s0, lc);
+#pragma unroll
+            for (int k = 0; k < V; k++)
+                if (src.alt[k]) { lv[j][k] = lc[k]; r[j][k] = 0.f; }
+        }
     }
 #pragma unroll
-    for (int k = 0; k < V; k++) {
-        syn[k] ^= (lv[k] < 0.f);
-        const float q = clamp_msg(lv[k] - r[k]);
-        neg[k] |= uint32_t(q < 0.f) << j;
-        u[k] = tanh_complement(fabsf(q));
+    for (int j = 0; j < C; j++) {
+        if (j < count) {
+#pragma unroll
+            for (int k = 0; k < V; k++) {
+                syn[k] ^= (lv[j][k] < 0.f);
+                const float q = clamp_msg(lv[j][k] - r[j][k]);
+                neg[k] |= uint32_t(q < 0.f) << j;
+                u[j][k] = tanh_complement(fabsf(q));
+            }
+        }
     }
 }
 
@@ -167,13 +188,7 @@ __device__ __forceinline__ void row_rule(const int32_t *__restrict__ col_idx, in
     uint32_t neg[V];
 #pragma unroll
     for (int k = 0; k < V; k++) neg[k] = 0u;
-#pragma unroll
-    for (int j = 0; j < DMAX; j++) {
-        if (j < d) {
-            const int v = UNIFORM ? wave_uniform(col_idx[e0 + j]) : col_idx[e0 + j];
-            edge_input<M, V>(L, Lalt, R, size_t(v) * S + s0, size_t(e0 + j) * S + s0, src, j, u[j], neg, syn);
-        }
-    }
+    gather_edges<M, V, DMAX, UNIFORM>(col_idx, e0, d, L, Lalt, R, S, s0, src, u, neg, syn);
     float run[V];
 #pragma unroll
     for (int k = 0; k < V; k++) run[k] = 0.f;
@@ -206,6 +221,36 @@ __device__ __forceinline__ void row_rule(const int32_t *__restrict__ col_idx, in
     }
 }
 
+// Posterior sum Lch + sum of the bit's incoming messages, added in column
+// order (positions a .. b-1 of the bit-sorted edge list, mapped to message
+// rows by csc_to_csr).  Edges are fetched four at a time with all their loads
+// in flight; positions past b repeat the last edge and are not added.
+constexpr int kBitBatch = 4;
+
+template <int M, int V, bool UNIFORM>
+__device__ __forceinline__ void bit_sum(const int32_t *__restrict__ csc_to_csr, int a, int b,
+                                        const typename Codec<M>::T *__restrict__ R, int32_t S, int s0,
+                                        float (&sum)[V]) {
+    for (int k0 = a; k0 < b; k0 += kBitBatch) {
+        int e[kBitBatch];
+#pragma unroll
+        for (int j = 0; j < kBitBatch; j++) {
+            const int k = k0 + j < b ? k0 + j : b - 1;
+            e[j] = UNIFORM ? wave_uniform(csc_to_csr[k]) : csc_to_csr[k];
+        }
+        float r[kBitBatch][V];
+#pragma unroll
+        for (int j = 0; j < kBitBatch; j++) load_vec<M, V>(R + size_t(e[j]) * S + s0, r[j]);
+#pragma unroll
+        for (int j = 0; j < kBitBatch; j++) {
+            if (k0 + j < b) {
+#pragma unroll
+                for (int z = 0; z < V; z++) sum[z] += r[j][z];
+            }
+        }
+    }
+}
+
 // Chunked rows: a row is cut into chunks of C edges handled by different
 // wavefronts.  chunk_load forms a chunk's u's, exclusive in-chunk suffixes and
 // its aggregate (the u's combined), sign bits and syndrome parity;
@@ -221,13 +266,7 @@ __device__ __forceinline__ void chunk_load(const int32_t *__restrict__ col_idx, 
                                            float (&agg)[V], uint32_t (&neg)[V], int (&syn)[V]) {
 #pragma unroll
     for (int k = 0; k < V; k++) { neg[k] = 0u; syn[k] = 0; }
-#pragma unroll
-    for (int j = 0; j < C; j++) {
-        if (j < dc) {
-            const int v = wave_uniform(col_idx[j0 + j]);
-            edge_input<M, V>(L, Lalt, R, size_t(v) * S + s0, size_t(j0 + j) * S + s0, src, j, u[j], neg, syn);
-        }
-    }
+    gather_edges<M, V, C, true>(col_idx, j0, dc, L, Lalt, R, S, s0, src, u, neg, syn);
 #pragma unroll
     for (int k = 0; k < V; k++) agg[k] = 0.f;
 #pragma unroll

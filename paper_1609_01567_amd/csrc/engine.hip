@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -39,7 +40,6 @@ using namespace ldpc_dev;
 
 constexpr int kMaxGraphs = 32;
 constexpr int kTurnoverBlocks = 1024;
-constexpr int kTurnChunk = 2048;   // bits per turnover workgroup (256 threads x 8)
 constexpr int kCounterInts = 7;    // per graph: head, tail, retired, list count, taken, moves, extent
 constexpr int kRepackMinExtent = 32;   // below this many slots a repack saves no cache line
 constexpr int kMoveBlocks = 512;
@@ -76,7 +76,6 @@ struct EngGraph {
     int32_t *moves;       // frames repacked by this step (slot pairs in move_src / move_dst)
     int32_t *extent;      // one past the highest occupied slot (0: pool empty)
     int32_t *move_src, *move_dst;
-    int32_t chunks;       // ceil(n / kTurnChunk)
 };
 
 struct Prefix {           // offsets of each graph's work items in one launch
@@ -444,13 +443,7 @@ __device__ __forceinline__ void bit_item(const EngGraph &G, int v, int s0, int32
     load_vec<kF32, V>(G.lch + size_t(v) * S + s0, sum);
     const int a = UNIFORM ? wave_uniform(G.col_ptr[v]) : G.col_ptr[v];
     const int b = UNIFORM ? wave_uniform(G.col_ptr[v + 1]) : G.col_ptr[v + 1];
-    for (int k = a; k < b; k++) {
-        const int e = UNIFORM ? wave_uniform(G.csc_to_csr[k]) : G.csc_to_csr[k];
-        float r[V];
-        load_vec<M, V>(R + size_t(e) * S + s0, r);
-#pragma unroll
-        for (int z = 0; z < V; z++) sum[z] += r[z];
-    }
+    bit_sum<M, V, UNIFORM>(G.csc_to_csr, a, b, R, S, s0, sum);
     if (all) {
         store_vec<kF32, V>(G.lpost + size_t(v) * S + s0, sum);
     } else {
@@ -497,92 +490,153 @@ __global__ __launch_bounds__(256) void eng_bit(const EngGraph *__restrict__ grap
 
 // One thread per slot: stop test, per-frame results, and the graph's turnover
 // list (stopped frames, and empty slots while the graph has queued frames).
+// Pool sizes are multiples of 64, so a wavefront never spans two graphs; each
+// wavefront appends its entries in slot order with one atomic.
 __global__ __launch_bounds__(256) void eng_advance(const EngGraph *__restrict__ graphs, Prefix pre, int32_t T,
                                                    int32_t early) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= pre.p[pre.count]) return;
-    const int c = find_graph(pre, x);
-    const EngGraph &G = graphs[c];
-    const int s = x - pre.p[c];
-    const int32_t q = G.slot_q[s];
-    if (q < 0) {
-        if (*G.head < *G.tail) G.list[atomicAdd(G.list_count, 1)] = s;
-        return;
+    const int lane = threadIdx.x & 63;
+    int c = 0;
+    bool listme = false, stopped = false;
+    int32_t ent = 0;
+    if (x < pre.p[pre.count]) {
+        c = find_graph(pre, x);
+        const EngGraph &G = graphs[c];
+        const int s = x - pre.p[c];
+        const int32_t q = G.slot_q[s];
+        if (q < 0) {
+            listme = *G.head < *G.tail;
+            ent = s;
+        } else {
+            const int32_t t = G.slot_t[s];
+            const int32_t f = G.fail[s];
+            if (slot_stops(t, f, T, early)) {
+                const EngFrame fr = G.slot_desc[s];
+                *fr.ok = (t < T) ? uint8_t(1) : uint8_t(f != T);
+                *fr.iters = t;
+                listme = stopped = true;
+                ent = s | int32_t(0x80000000u);
+            } else {
+                G.slot_t[s] = t + 1;
+            }
+        }
     }
-    const int32_t t = G.slot_t[s];
-    const int32_t f = G.fail[s];
-    if (slot_stops(t, f, T, early)) {
-        const EngFrame fr = G.slot_desc[s];
-        *fr.ok = (t < T) ? uint8_t(1) : uint8_t(f != T);
-        *fr.iters = t;
-        atomicAdd(G.retired, 1);
-        G.list[atomicAdd(G.list_count, 1)] = s | int32_t(0x80000000u);
-    } else {
-        G.slot_t[s] = t + 1;
+    const uint64_t m = __ballot(listme);
+    if (m == 0) return;
+    const uint64_t ms = __ballot(stopped);
+    const int leader = __ffsll(static_cast<unsigned long long>(m)) - 1;
+    const EngGraph &G = graphs[__shfl(c, leader)];
+    int base = 0;
+    if (lane == leader) {
+        base = atomicAdd(G.list_count, __popcll(m));
+        if (ms) atomicAdd(G.retired, __popcll(ms));
     }
+    base = __shfl(base, leader);
+    if (listme) G.list[base + __popcll(m & ((uint64_t(1) << lane) - 1u))] = ent;
 }
 
-// Listed slot i of graph c, bits [ch * kTurnChunk, +kTurnChunk): write the
-// stopped frame's estimate (bit = 1 iff Lpost < 0, Algorithm 6) and optional
-// posterior, and copy the channel LLRs of the frame admitted into the slot
-// (queue entry head + i, if there is one).  Many workgroups per slot.
+// Workgroup item = (graph, 64 consecutive list entries, 64 bits).  Stopped
+// entries write their estimate (bit = 1 iff Lpost < 0, Algorithm 6) and the
+// optional posterior to the frame's outputs; entry i receives the channel LLRs
+// of queue entry head + i while there is one.  Each 64 x 64 tile goes through
+// LDS, so the slot-major state rows and the frame-major user rows are both
+// accessed in contiguous runs (the list is in slot order within each run).
+constexpr int kTile = 64;
+
 __global__ __launch_bounds__(256) void eng_turnover(const EngGraph *__restrict__ graphs, int32_t ngraphs) {
     __shared__ int32_t base[kMaxGraphs + 1];
-    if (threadIdx.x == 0) {
+    __shared__ float tile[kTile][kTile + 1];
+    __shared__ int32_t slot_of[kTile];
+    __shared__ uint8_t *bits_of[kTile];
+    __shared__ float *lout_of[kTile];
+    __shared__ const float *src_of[kTile];
+    __shared__ int32_t any_out, any_in;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
         base[0] = 0;
         for (int c = 0; c < ngraphs; c++) {
             const EngGraph &H = graphs[c];
-            base[c + 1] = base[c] + *H.list_count * H.chunks;
+            const int32_t cnt = *H.list_count;
+            base[c + 1] = base[c] + (cnt + kTile - 1) / kTile * ((H.n + kTile - 1) / kTile);
             // the tail is constant within a step: this is the number admitted now
-            if (blockIdx.x == 0) *H.taken = min(*H.list_count, *H.tail - *H.head);
+            if (blockIdx.x == 0) *H.taken = min(cnt, *H.tail - *H.head);
         }
     }
     __syncthreads();
     const int total = base[ngraphs];
-    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+    const int r = tid >> 6, l = tid & 63;
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {     // uniform over the workgroup
         int c = 0;
         while (c + 1 < ngraphs && u >= base[c + 1]) c++;
         const EngGraph &G = graphs[c];
-        const int local = u - base[c];
-        const int i = local / G.chunks;
-        const int ch = local - i * G.chunks;
-        const int32_t ent = G.list[i];
-        const int s = ent & 0x7fffffff;
-        const bool stopped = ent < 0;
         const int32_t S = G.S, n = G.n;
-        const int v0 = ch * kTurnChunk + threadIdx.x;
-        if (stopped) {
-            const EngFrame fr = G.slot_desc[s];
-            float x[kTurnChunk / 256];
-#pragma unroll
-            for (int j = 0; j < kTurnChunk / 256; j++) {
-                const int v = v0 + j * 256;
-                x[j] = v < n ? G.lpost[size_t(v) * S + s] : 0.f;
+        const int nvt = (n + kTile - 1) / kTile;
+        const int local = u - base[c];
+        const int i0 = (local / nvt) * kTile;
+        const int v0 = (local % nvt) * kTile;
+        if (tid < kTile) {
+            const int i = i0 + tid;
+            const int32_t cnt = *G.list_count;
+            int32_t s = 0;
+            uint8_t *bo = nullptr;
+            float *lo = nullptr;
+            const float *src = nullptr;
+            if (i < cnt) {
+                const int32_t ent = G.list[i];
+                s = ent & 0x7fffffff;
+                if (ent < 0) {
+                    const EngFrame fr = G.slot_desc[s];
+                    bo = fr.bits;
+                    lo = fr.llr_out;
+                }
+                const int32_t qi = *G.head + i;
+                if (qi < *G.tail) src = G.queue[qi % G.cap].llr;
             }
-#pragma unroll
-            for (int j = 0; j < kTurnChunk / 256; j++) {
-                const int v = v0 + j * 256;
-                if (v < n) {
-                    fr.bits[v] = x[j] < 0.f;
-                    if (fr.llr_out) fr.llr_out[v] = x[j];
+            slot_of[tid] = s;
+            bits_of[tid] = bo;
+            lout_of[tid] = lo;
+            src_of[tid] = src;
+            const uint64_t mo = __ballot(bo != nullptr), mi = __ballot(src != nullptr);
+            if (tid == 0) {
+                any_out = mo != 0;
+                any_in = mi != 0;
+            }
+        }
+        __syncthreads();
+        if (any_out) {
+            // posterior rows of the listed slots -> tile[v][entry]
+            for (int k = r; k < kTile; k += 4) {
+                const int v = v0 + k;
+                if (v < n && bits_of[l]) tile[k][l] = G.lpost[size_t(v) * S + slot_of[l]];
+            }
+            __syncthreads();
+            // tile -> each stopped frame's output row
+            for (int k = r; k < kTile; k += 4) {
+                const int v = v0 + l;
+                uint8_t *bo = bits_of[k];
+                if (v < n && bo) {
+                    const float x = tile[l][k];
+                    bo[v] = x < 0.f;
+                    if (lout_of[k]) lout_of[k][v] = x;
                 }
             }
+            __syncthreads();
         }
-        const int32_t qi = *G.head + i;
-        if (qi < *G.tail) {   // same test as min(list_count, tail - head) > i
-            const float *src = G.queue[qi % G.cap].llr;
-            float x[kTurnChunk / 256];
-#pragma unroll
-            for (int j = 0; j < kTurnChunk / 256; j++) {
-                const int v = v0 + j * 256;
-                x[j] = v < n ? src[v] : 0.f;
+        if (any_in) {
+            // each admitted frame's channel row -> tile[v][entry]
+            for (int k = r; k < kTile; k += 4) {
+                const int v = v0 + l;
+                const float *src = src_of[k];
+                if (v < n && src) tile[l][k] = src[v];
             }
-#pragma unroll
-            for (int j = 0; j < kTurnChunk / 256; j++) {
-                const int v = v0 + j * 256;
-                if (v < n) G.lch[size_t(v) * S + s] = x[j];
+            __syncthreads();
+            // tile -> channel rows of the slots
+            for (int k = r; k < kTile; k += 4) {
+                const int v = v0 + k;
+                if (v < n && src_of[l]) G.lch[size_t(v) * S + slot_of[l]] = tile[k][l];
             }
         }
+        __syncthreads();   // the tile and entry tables are reused by the next item
     }
 }
 
@@ -782,7 +836,7 @@ void enqueue_step(ldpc_engine *e) {
         hipLaunchKernelGGL((eng_check_rows<M, V, 8>), dim3(e->grid_rows[0]), dim3(256), 0, st, e->d_graphs, ng,
                            int32_t(ldpc::kClassD8), e->T, early);
     if (e->has_rows[1])
-        hipLaunchKernelGGL((eng_check_chunk<M, V, ldpc::class_waves_per_row(ldpc::kClassD16)>), dim3(e->grid_rows[1]),
+        hipLaunchKernelGGL((eng_check_rows<M, ldpc::class_lane_slots(ldpc::kClassD16, V), 16>), dim3(e->grid_rows[1]),
                            dim3(256), 0, st, e->d_graphs, ng, int32_t(ldpc::kClassD16), e->T, early);
     if (e->has_rows[2])
         hipLaunchKernelGGL((eng_check_chunk<M, V, ldpc::class_waves_per_row(ldpc::kClassD128)>),
@@ -823,7 +877,14 @@ void enqueue_steps(ldpc_engine *e, int steps) {
 }
 
 // Workgroups per launch: as many as the device keeps resident at once (the
-// kernels loop over their items), never more than a full pool needs.
+// kernels loop over their items), never more than a full pool needs.  The
+// residency figure is multiplied by LDPC_ENGINE_GRID_FACTOR (1..16, default 1).
+int grid_factor() {
+    const char *v = std::getenv("LDPC_ENGINE_GRID_FACTOR");
+    const int f = v ? std::atoi(v) : 1;
+    return f >= 1 && f <= 16 ? f : 1;
+}
+
 template <int M, int V>
 void size_grids(ldpc_engine *e, int cus) {
     auto fit = [cus](const void *k, int64_t need) -> unsigned {
@@ -832,11 +893,15 @@ void size_grids(ldpc_engine *e, int cus) {
             (void)hipGetLastError();
             per_cu = 1;
         }
-        return unsigned(std::max<int64_t>(1, std::min<int64_t>(need, int64_t(per_cu) * cus)));
+        if (const char *v = std::getenv("LDPC_ENGINE_BLOCKS_PER_CU")) {
+            const int b = std::atoi(v);
+            if (b >= 1 && b <= 32) per_cu = b;
+        }
+        return unsigned(std::max<int64_t>(1, std::min<int64_t>(need, int64_t(per_cu) * cus * grid_factor())));
     };
     e->grid_rows[0] = fit(reinterpret_cast<const void *>(&eng_check_rows<M, V, 8>), (e->row_waves[0] + 3) / 4);
-    e->grid_rows[1] = fit(reinterpret_cast<const void *>(&eng_check_chunk<M, V, ldpc::class_waves_per_row(ldpc::kClassD16)>),
-                          e->row_waves[1]);
+    e->grid_rows[1] = fit(reinterpret_cast<const void *>(&eng_check_rows<M, ldpc::class_lane_slots(ldpc::kClassD16, V), 16>),
+                          (e->row_waves[1] + 3) / 4);
     e->grid_rows[2] = fit(reinterpret_cast<const void *>(&eng_check_chunk<M, V, ldpc::class_waves_per_row(ldpc::kClassD128)>),
                           e->row_waves[2]);
     e->grid_hub = fit(reinterpret_cast<const void *>(&eng_check_hub<M>), e->hub_blocks);
@@ -1009,7 +1074,6 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
         G.list = reinterpret_cast<int32_t *>(base + o.list);
         G.move_src = reinterpret_cast<int32_t *>(base + o.msrc);
         G.move_dst = reinterpret_cast<int32_t *>(base + o.mdst);
-        G.chunks = (g->n + kTurnChunk - 1) / kTurnChunk;
         e->hg.push_back(G);
         // every slot starts empty, with defined message state
         if ((err = hipMemsetAsync(base + o.lch, 0, o.q - o.lch, e->stream)) != hipSuccess ||
@@ -1025,11 +1089,12 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
 
     // work sizes with every slot occupied: waves (D8 rows, bits) or workgroups (chunked and long rows)
     for (int k = 0; k < 3; k++) {
-        const int rpb = k == 0 ? 1 : 4 / ldpc::class_waves_per_row(k);
+        const int rpb = k < 2 ? 1 : 4 / ldpc::class_waves_per_row(k);
+        const int vk = ldpc::class_lane_slots(k, V);
         int64_t tot = 0;
         for (int32_t c = 0; c < ngraphs; c++) {
             const ldpc_graph *g = graphs[c];
-            const int64_t items = int64_t(g->class_begin[k + 1] - g->class_begin[k]) * (e->S[size_t(c)] / (64 * V));
+            const int64_t items = int64_t(g->class_begin[k + 1] - g->class_begin[k]) * (e->S[size_t(c)] / (64 * vk));
             tot += (items + rpb - 1) / rpb;
         }
         e->row_waves[k] = tot;

@@ -10,10 +10,11 @@
 namespace ldpc {
 
 // Check rows are grouped by degree into classes, one kernel shape per class:
-// rows of up to 8 edges in one wavefront's registers; rows of 9..16 and
-// 17..128 edges cut into 8-edge chunks over 2 or 4 wavefronts that exchange
-// chunk aggregates through LDS; longer rows on a segmented path that splits
-// them into 32-edge chunks with aggregates in global scratch (no degree bound).
+// rows of up to 8 and of 9..16 edges in one wavefront's registers (the latter
+// at most 2 frame slots per lane, which bounds register use); rows of 17..128
+// edges cut into 8-edge chunks over 4 wavefronts that exchange chunk
+// aggregates through LDS; longer rows on a segmented path that splits them
+// into 32-edge chunks with aggregates in global scratch (no degree bound).
 enum CheckClass : int { kClassD8 = 0, kClassD16 = 1, kClassD128 = 2, kClassHub = 3, kNumClasses = 4 };
 constexpr int kHubChunk = 32;   // edges per chunk on the segmented path
 
@@ -21,12 +22,12 @@ inline int check_class_of(int d) {
     return d <= 8 ? kClassD8 : d <= 16 ? kClassD16 : d <= 128 ? kClassD128 : kClassHub;
 }
 
-// Wavefronts per row of the chunked classes (rows per 256-thread block = 4 / this).
-constexpr int class_waves_per_row(int cls) { return cls == kClassD16 ? 2 : cls == kClassD128 ? 4 : 1; }
+// Wavefronts per row of the chunked class (rows per 256-thread block = 4 / this).
+constexpr int class_waves_per_row(int cls) { return cls == kClassD128 ? 4 : 1; }
 
 // Frame slots per wavefront lane for a class when the decode uses V slots per
 // lane elsewhere (the segmented path always uses 1).
-constexpr int class_lane_slots(int cls, int V) { return cls == kClassHub ? 1 : V; }
+constexpr int class_lane_slots(int cls, int V) { return cls == kClassHub ? 1 : cls == kClassD16 && V > 2 ? 2 : V; }
 
 void set_error(const std::string &msg);
 

@@ -45,6 +45,22 @@ template <> struct Codec<kBF16> {
     }
 };
 
+// Device arrays by address space.  A pointer that reaches a kernel through
+// memory (a table of per-graph arrays, a frame descriptor) is generic to the
+// compiler, which then emits flat accesses; flat loads also count against the
+// scalar/LDS wait counter, so a row's index loads end up waiting behind its
+// message loads.  Every array here is in global memory: gmem() states that for
+// data arrays, cload() reads an entry of a read-only table (graph indices) as
+// constant memory, which uniform addresses turn into scalar loads.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gmem(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
+template <typename T>
+__device__ __forceinline__ T cload(const T *p) {
+    return *(const __attribute__((address_space(4))) T *)p;
+}
+
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 template <int B> struct Raw;
@@ -57,7 +73,7 @@ template <int M, int V>
 __device__ __forceinline__ void load_vec(const typename Codec<M>::T *p, float (&out)[V]) {
     using T = typename Codec<M>::T;
     using W = typename Raw<sizeof(T) * V>::T;
-    const W raw = *reinterpret_cast<const W *>(p);
+    const W raw = *gmem(reinterpret_cast<const W *>(p));
     T e[V];
     __builtin_memcpy(e, &raw, sizeof(W));
 #pragma unroll
@@ -73,13 +89,13 @@ __device__ __forceinline__ void store_vec(typename Codec<M>::T *p, const float (
     for (int k = 0; k < V; k++) e[k] = Codec<M>::enc(in[k]);
     W raw;
     __builtin_memcpy(&raw, e, sizeof(W));
-    *reinterpret_cast<W *>(p) = raw;
+    *gmem(reinterpret_cast<W *>(p)) = raw;
 }
 
 template <int V>
 __device__ __forceinline__ void load_i32(const int32_t *p, int32_t (&out)[V]) {
     using W = typename Raw<4 * V>::T;
-    const W raw = *reinterpret_cast<const W *>(p);
+    const W raw = *gmem(reinterpret_cast<const W *>(p));
     __builtin_memcpy(out, &raw, sizeof(W));
 }
 
@@ -136,7 +152,7 @@ __device__ __forceinline__ void gather_edges(const int32_t *__restrict__ col_idx
 #pragma unroll
     for (int j = 0; j < C; j++) {
         const int e = j0 + (j < count ? j : count - 1);
-        vix[j] = UNIFORM ? wave_uniform(col_idx[e]) : col_idx[e];
+        vix[j] = UNIFORM ? wave_uniform(cload(col_idx + e)) : cload(col_idx + e);
     }
     float lv[C][V], r[C][V];
 #pragma unroll
@@ -236,7 +252,7 @@ __device__ __forceinline__ void bit_sum(const int32_t *__restrict__ csc_to_csr, 
 #pragma unroll
         for (int j = 0; j < kBitBatch; j++) {
             const int k = k0 + j < b ? k0 + j : b - 1;
-            e[j] = UNIFORM ? wave_uniform(csc_to_csr[k]) : csc_to_csr[k];
+            e[j] = UNIFORM ? wave_uniform(cload(csc_to_csr + k)) : cload(csc_to_csr + k);
         }
         float r[kBitBatch][V];
 #pragma unroll

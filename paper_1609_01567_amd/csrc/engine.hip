@@ -78,6 +78,27 @@ struct EngGraph {
     int32_t *move_src, *move_dst;
 };
 
+// Frame descriptors move as three 16-byte words through global loads/stores
+// (descriptor arrays are 256-byte aligned and 48 bytes per entry).
+static_assert(sizeof(EngFrame) == 48, "EngFrame layout");
+
+__device__ __forceinline__ EngFrame load_frame(const EngFrame *p) {
+    const auto q = gmem(reinterpret_cast<const u32x4 *>(p));
+    const u32x4 w[3] = {q[0], q[1], q[2]};
+    EngFrame f;
+    __builtin_memcpy(&f, w, sizeof(f));
+    return f;
+}
+
+__device__ __forceinline__ void store_frame(EngFrame *p, const EngFrame &f) {
+    u32x4 w[3];
+    __builtin_memcpy(w, &f, sizeof(f));
+    const auto q = gmem(reinterpret_cast<u32x4 *>(p));
+    q[0] = w[0];
+    q[1] = w[1];
+    q[2] = w[2];
+}
+
 struct Prefix {           // offsets of each graph's work items in one launch
     int32_t count;
     int32_t p[kMaxGraphs + 1];
@@ -129,7 +150,7 @@ template <int V>
 __device__ __forceinline__ void eng_syndrome(const EngGraph &G, const EngLane<V> &ln, const int (&syn)[V], int s0) {
 #pragma unroll
     for (int k = 0; k < V; k++)
-        if (ln.syn_on[k] && syn[k] && G.fail[s0 + k] != ln.t[k]) G.fail[s0 + k] = ln.t[k];
+        if (ln.syn_on[k] && syn[k] && gmem(G.fail)[s0 + k] != ln.t[k]) gmem(G.fail)[s0 + k] = ln.t[k];
 }
 
 // Work of one pass over the occupied slot groups of every graph.  Graph c owns
@@ -156,7 +177,7 @@ __device__ __forceinline__ void build_work(const EngGraph *__restrict__ graphs, 
         w.p[0] = 0;
         for (int c = 0; c < ngraphs; c++) {
             const EngGraph &G = graphs[c];
-            const int32_t x = *G.extent;
+            const int32_t x = *gmem(G.extent);
             const int32_t gr = (x + unit - 1) / unit;
             const int32_t units = cls == kBitItems ? G.n : G.class_begin[cls + 1] - G.class_begin[cls];
             int32_t rpw = 1;
@@ -212,14 +233,14 @@ __global__ __launch_bounds__(256) void eng_check_rows(const EngGraph *__restrict
         for (int k = 0; k < V; k++) syn[k] = 0;
         MT *R = static_cast<MT *>(G.r);
         if (rpw == 1) {
-            const int row = wave_uniform(G.class_rows[G.class_begin[cls] + rk]);
-            const int e0 = wave_uniform(G.row_ptr[row]);
-            const int d = wave_uniform(G.row_ptr[row + 1]) - e0;
+            const int row = wave_uniform(cload(G.class_rows + G.class_begin[cls] + rk));
+            const int e0 = wave_uniform(cload(G.row_ptr + (row)));
+            const int d = wave_uniform(cload(G.row_ptr + (row + 1))) - e0;
             row_rule<M, V, DMAX, true>(G.col_idx, e0, d, G.lpost, G.lch, R, G.S, s0, ln.src, syn);
         } else {
-            const int row = G.class_rows[G.class_begin[cls] + rk];
-            const int e0 = G.row_ptr[row];
-            const int d = G.row_ptr[row + 1] - e0;
+            const int row = cload(G.class_rows + G.class_begin[cls] + rk);
+            const int e0 = cload(G.row_ptr + (row));
+            const int d = cload(G.row_ptr + (row + 1)) - e0;
             row_rule<M, V, DMAX, false>(G.col_idx, e0, d, G.lpost, G.lch, R, G.S, s0, ln.src, syn);
         }
         eng_syndrome<V>(G, ln, syn, s0);
@@ -259,9 +280,9 @@ __global__ __launch_bounds__(256) void eng_check_chunk(const EngGraph *__restric
         const bool work = valid && __ballot(ln.active) != 0;
         int e0 = 0, d = 0, nch = 0;
         if (work) {
-            const int row = wave_uniform(G.class_rows[G.class_begin[cls] + rk]);
-            e0 = wave_uniform(G.row_ptr[row]);
-            d = wave_uniform(G.row_ptr[row + 1]) - e0;
+            const int row = wave_uniform(cload(G.class_rows + G.class_begin[cls] + rk));
+            e0 = wave_uniform(cload(G.row_ptr + (row)));
+            d = wave_uniform(cload(G.row_ptr + (row + 1))) - e0;
             nch = (d + C - 1) / C;
         }
         MT *R = static_cast<MT *>(G.r);
@@ -324,19 +345,19 @@ __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict_
         const int g = local % groups;
         const int rk = local / groups;
         const int s = g * 64 + lane;
-        const int32_t qs = G.slot_q[s], ts = G.slot_t[s];
+        const int32_t qs = gmem(G.slot_q)[s], ts = gmem(G.slot_t)[s];
         const bool active = qs >= 0;
         const bool first = active && ts == 0;
         const bool syn_on = active && ts >= 1 && (early || ts == T);
         if (__ballot(active) == 0) continue;   // same slots in every wavefront: uniform over the workgroup
 
-        const int row = wave_uniform(G.class_rows[G.class_begin[ldpc::kClassHub] + rk]);
-        const int e0 = wave_uniform(G.row_ptr[row]);
-        const int d = wave_uniform(G.row_ptr[row + 1]) - e0;
+        const int row = wave_uniform(cload(G.class_rows + G.class_begin[ldpc::kClassHub] + rk));
+        const int e0 = wave_uniform(cload(G.row_ptr + (row)));
+        const int d = wave_uniform(cload(G.row_ptr + (row + 1))) - e0;
         const int nch = (d + C - 1) / C;
-        const int cb = wave_uniform(G.hub_chunk_base[rk]);
-        MT *R = static_cast<MT *>(G.r);
-        const float *L = first ? G.lch : G.lpost;
+        const int cb = wave_uniform(cload(G.hub_chunk_base + (rk)));
+        auto R = gmem(static_cast<MT *>(G.r));
+        auto L = gmem(first ? G.lch : G.lpost);
 
         for (int ch = wv; ch < nch; ch += nw) {
             const int j0 = e0 + ch * C;
@@ -346,7 +367,7 @@ __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict_
 #pragma unroll
             for (int jj = 0; jj < C; jj++) {
                 if (jj < dc) {
-                    const int v = wave_uniform(G.col_idx[j0 + jj]);
+                    const int v = wave_uniform(cload(G.col_idx + (j0 + jj)));
                     const float lv = L[size_t(v) * S + s];
                     const float r = first ? 0.f : Codec<M>::dec(R[size_t(j0 + jj) * S + s]);
                     const float qv = clamp_msg(lv - r);
@@ -354,26 +375,26 @@ __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict_
                     agg = dplus(agg, tanh_complement(fabsf(qv)));
                 }
             }
-            G.aggd[size_t(cb + ch) * S + s] = agg;
-            G.aggbits[size_t(cb + ch) * S + s] = bits;
+            gmem(G.aggd)[size_t(cb + ch) * S + s] = agg;
+            gmem(G.aggbits)[size_t(cb + ch) * S + s] = bits;
         }
         __syncthreads();
         if (wv == 0) {
             float pre_d = 0.f;
             int32_t tot = 0;
             for (int ch = 0; ch < nch; ch++) {
-                G.aggpre[size_t(cb + ch) * S + s] = pre_d;
-                pre_d = dplus(pre_d, G.aggd[size_t(cb + ch) * S + s]);
-                tot ^= G.aggbits[size_t(cb + ch) * S + s];
+                gmem(G.aggpre)[size_t(cb + ch) * S + s] = pre_d;
+                pre_d = dplus(pre_d, gmem(G.aggd)[size_t(cb + ch) * S + s]);
+                tot ^= gmem(G.aggbits)[size_t(cb + ch) * S + s];
             }
             float sf = 0.f;
             for (int ch = nch - 1; ch >= 0; ch--) {
-                const float dcur = G.aggd[size_t(cb + ch) * S + s];
-                G.aggd[size_t(cb + ch) * S + s] = dplus(G.aggpre[size_t(cb + ch) * S + s], sf);
+                const float dcur = gmem(G.aggd)[size_t(cb + ch) * S + s];
+                gmem(G.aggd)[size_t(cb + ch) * S + s] = dplus(gmem(G.aggpre)[size_t(cb + ch) * S + s], sf);
                 sf = dplus(sf, dcur);
             }
             total_bits[lane] = tot;
-            if (syn_on && (tot & 2) && G.fail[s] != ts) G.fail[s] = ts;
+            if (syn_on && (tot & 2) && gmem(G.fail)[s] != ts) gmem(G.fail)[s] = ts;
         }
         __syncthreads();
         const uint32_t parity = uint32_t(total_bits[lane]) & 1u;
@@ -385,7 +406,7 @@ __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict_
 #pragma unroll
             for (int jj = 0; jj < C; jj++) {
                 if (jj < dc) {
-                    const int v = wave_uniform(G.col_idx[j0 + jj]);
+                    const int v = wave_uniform(cload(G.col_idx + (j0 + jj)));
                     const float lv = L[size_t(v) * S + s];
                     const float r = first ? 0.f : Codec<M>::dec(R[size_t(j0 + jj) * S + s]);
                     const float qv = clamp_msg(lv - r);
@@ -401,7 +422,7 @@ __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict_
                     run = dplus(uu[jj], run);
                 }
             }
-            run = G.aggd[size_t(cb + ch) * S + s];
+            run = gmem(G.aggd)[size_t(cb + ch) * S + s];
 #pragma unroll
             for (int jj = 0; jj < C; jj++) {
                 if (jj < dc) {
@@ -441,15 +462,15 @@ __device__ __forceinline__ void bit_item(const EngGraph &G, int v, int s0, int32
     const MT *R = static_cast<const MT *>(G.r);
     float sum[V];
     load_vec<kF32, V>(G.lch + size_t(v) * S + s0, sum);
-    const int a = UNIFORM ? wave_uniform(G.col_ptr[v]) : G.col_ptr[v];
-    const int b = UNIFORM ? wave_uniform(G.col_ptr[v + 1]) : G.col_ptr[v + 1];
+    const int a = UNIFORM ? wave_uniform(cload(G.col_ptr + (v))) : cload(G.col_ptr + (v));
+    const int b = UNIFORM ? wave_uniform(cload(G.col_ptr + (v + 1))) : cload(G.col_ptr + (v + 1));
     bit_sum<M, V, UNIFORM>(G.csc_to_csr, a, b, R, S, s0, sum);
     if (all) {
         store_vec<kF32, V>(G.lpost + size_t(v) * S + s0, sum);
     } else {
 #pragma unroll
         for (int k = 0; k < V; k++)
-            if (adv[k]) G.lpost[size_t(v) * S + s0 + k] = sum[k];
+            if (adv[k]) gmem(G.lpost)[size_t(v) * S + s0 + k] = sum[k];
     }
 }
 
@@ -460,9 +481,9 @@ __global__ __launch_bounds__(256) void eng_bit(const EngGraph *__restrict__ grap
     // graph's queue head past the frames it admitted and empty its list.
     if (blockIdx.x == 0 && threadIdx.x < ngraphs) {
         const EngGraph &H = graphs[threadIdx.x];
-        *H.head += *H.taken;
-        *H.taken = 0;
-        *H.list_count = 0;
+        *gmem(H.head) += *gmem(H.taken);
+        *gmem(H.taken) = 0;
+        *gmem(H.list_count) = 0;
     }
     __shared__ Work w;
     build_work<true>(graphs, ngraphs, kBitItems, 64 * V, 1, w);
@@ -503,21 +524,21 @@ __global__ __launch_bounds__(256) void eng_advance(const EngGraph *__restrict__ 
         c = find_graph(pre, x);
         const EngGraph &G = graphs[c];
         const int s = x - pre.p[c];
-        const int32_t q = G.slot_q[s];
+        const int32_t q = gmem(G.slot_q)[s];
         if (q < 0) {
-            listme = *G.head < *G.tail;
+            listme = *gmem(G.head) < *gmem(G.tail);
             ent = s;
         } else {
-            const int32_t t = G.slot_t[s];
-            const int32_t f = G.fail[s];
+            const int32_t t = gmem(G.slot_t)[s];
+            const int32_t f = gmem(G.fail)[s];
             if (slot_stops(t, f, T, early)) {
-                const EngFrame fr = G.slot_desc[s];
-                *fr.ok = (t < T) ? uint8_t(1) : uint8_t(f != T);
-                *fr.iters = t;
+                const EngFrame fr = load_frame(G.slot_desc + s);
+                *gmem(fr.ok) = (t < T) ? uint8_t(1) : uint8_t(f != T);
+                *gmem(fr.iters) = t;
                 listme = stopped = true;
                 ent = s | int32_t(0x80000000u);
             } else {
-                G.slot_t[s] = t + 1;
+                gmem(G.slot_t)[s] = t + 1;
             }
         }
     }
@@ -532,7 +553,7 @@ __global__ __launch_bounds__(256) void eng_advance(const EngGraph *__restrict__ 
         if (ms) atomicAdd(G.retired, __popcll(ms));
     }
     base = __shfl(base, leader);
-    if (listme) G.list[base + __popcll(m & ((uint64_t(1) << lane) - 1u))] = ent;
+    if (listme) gmem(G.list)[base + __popcll(m & ((uint64_t(1) << lane) - 1u))] = ent;
 }
 
 // Workgroup item = (graph, 64 consecutive list entries, 64 bits).  Stopped
@@ -556,10 +577,10 @@ __global__ __launch_bounds__(256) void eng_turnover(const EngGraph *__restrict__
         base[0] = 0;
         for (int c = 0; c < ngraphs; c++) {
             const EngGraph &H = graphs[c];
-            const int32_t cnt = *H.list_count;
+            const int32_t cnt = *gmem(H.list_count);
             base[c + 1] = base[c] + (cnt + kTile - 1) / kTile * ((H.n + kTile - 1) / kTile);
             // the tail is constant within a step: this is the number admitted now
-            if (blockIdx.x == 0) *H.taken = min(cnt, *H.tail - *H.head);
+            if (blockIdx.x == 0) *gmem(H.taken) = min(cnt, *gmem(H.tail) - *gmem(H.head));
         }
     }
     __syncthreads();
@@ -576,21 +597,21 @@ __global__ __launch_bounds__(256) void eng_turnover(const EngGraph *__restrict__
         const int v0 = (local % nvt) * kTile;
         if (tid < kTile) {
             const int i = i0 + tid;
-            const int32_t cnt = *G.list_count;
+            const int32_t cnt = *gmem(G.list_count);
             int32_t s = 0;
             uint8_t *bo = nullptr;
             float *lo = nullptr;
             const float *src = nullptr;
             if (i < cnt) {
-                const int32_t ent = G.list[i];
+                const int32_t ent = gmem(G.list)[i];
                 s = ent & 0x7fffffff;
                 if (ent < 0) {
-                    const EngFrame fr = G.slot_desc[s];
+                    const EngFrame fr = load_frame(G.slot_desc + s);
                     bo = fr.bits;
                     lo = fr.llr_out;
                 }
-                const int32_t qi = *G.head + i;
-                if (qi < *G.tail) src = G.queue[qi % G.cap].llr;
+                const int32_t qi = *gmem(G.head) + i;
+                if (qi < *gmem(G.tail)) src = load_frame(G.queue + qi % G.cap).llr;
             }
             slot_of[tid] = s;
             bits_of[tid] = bo;
@@ -607,7 +628,7 @@ __global__ __launch_bounds__(256) void eng_turnover(const EngGraph *__restrict__
             // posterior rows of the listed slots -> tile[v][entry]
             for (int k = r; k < kTile; k += 4) {
                 const int v = v0 + k;
-                if (v < n && bits_of[l]) tile[k][l] = G.lpost[size_t(v) * S + slot_of[l]];
+                if (v < n && bits_of[l]) tile[k][l] = gmem(G.lpost)[size_t(v) * S + slot_of[l]];
             }
             __syncthreads();
             // tile -> each stopped frame's output row
@@ -616,8 +637,8 @@ __global__ __launch_bounds__(256) void eng_turnover(const EngGraph *__restrict__
                 uint8_t *bo = bits_of[k];
                 if (v < n && bo) {
                     const float x = tile[l][k];
-                    bo[v] = x < 0.f;
-                    if (lout_of[k]) lout_of[k][v] = x;
+                    gmem(bo)[v] = x < 0.f;
+                    if (lout_of[k]) gmem(lout_of[k])[v] = x;
                 }
             }
             __syncthreads();
@@ -627,13 +648,13 @@ __global__ __launch_bounds__(256) void eng_turnover(const EngGraph *__restrict__
             for (int k = r; k < kTile; k += 4) {
                 const int v = v0 + l;
                 const float *src = src_of[k];
-                if (v < n && src) tile[l][k] = src[v];
+                if (v < n && src) tile[l][k] = gmem(src)[v];
             }
             __syncthreads();
             // tile -> channel rows of the slots
             for (int k = r; k < kTile; k += 4) {
                 const int v = v0 + k;
-                if (v < n && src_of[l]) G.lch[size_t(v) * S + slot_of[l]] = tile[k][l];
+                if (v < n && src_of[l]) gmem(G.lch)[size_t(v) * S + slot_of[l]] = tile[k][l];
             }
         }
         __syncthreads();   // the tile and entry tables are reused by the next item
@@ -673,32 +694,32 @@ __global__ __launch_bounds__(1024) void eng_admit(const EngGraph *__restrict__ g
     __shared__ int32_t red[2][16];
     const EngGraph &G = graphs[blockIdx.x];
     const int tid = threadIdx.x;
-    const int32_t count = *G.list_count;
-    const int32_t taken = *G.taken;
-    const int32_t head = *G.head;
+    const int32_t count = *gmem(G.list_count);
+    const int32_t taken = *gmem(G.taken);
+    const int32_t head = *gmem(G.head);
     for (int i = tid; i < count; i += blockDim.x) {
-        const int32_t ent = G.list[i];
+        const int32_t ent = gmem(G.list)[i];
         const int s = ent & 0x7fffffff;
         if (ent < 0) {
-            const EngFrame old = G.slot_desc[s];
+            const EngFrame old = load_frame(G.slot_desc + s);
             if (old.done) atomicAdd(old.done, 1);
         }
         if (i < taken) {
             const int32_t qi = head + i;
-            G.slot_desc[s] = G.queue[qi % G.cap];
-            G.slot_t[s] = 0;
-            G.fail[s] = 0;
-            G.slot_q[s] = qi;
+            store_frame(G.slot_desc + s, load_frame(G.queue + qi % G.cap));
+            gmem(G.slot_t)[s] = 0;
+            gmem(G.fail)[s] = 0;
+            gmem(G.slot_q)[s] = qi;
         } else {
-            G.slot_q[s] = -1;
+            gmem(G.slot_q)[s] = -1;
         }
     }
-    if (tid == 0) *G.moves = 0;
+    if (tid == 0) *gmem(G.moves) = 0;
     __syncthreads();
     const int S = G.S;
     int a = 0, x = 0;
     for (int s = tid; s < S; s += blockDim.x)
-        if (G.slot_q[s] >= 0) { a++; x = s + 1; }
+        if (gmem(G.slot_q)[s] >= 0) { a++; x = s + 1; }
     // workgroup sum of a, max of x
     for (int off = 32; off > 0; off >>= 1) {
         a += __shfl_down(a, off);
@@ -709,34 +730,34 @@ __global__ __launch_bounds__(1024) void eng_admit(const EngGraph *__restrict__ g
     int A = 0, X = 0;
     for (int i = 0; i < int(blockDim.x >> 6); i++) { A += red[0][i]; X = max(X, red[1][i]); }
     // queued frames fill the holes at the next turnovers; repack only a drained pool
-    if (!REPACK || head + taken < *G.tail || X < kRepackMinExtent || 2 * A > X) {
-        if (tid == 0) *G.extent = X;
+    if (!REPACK || head + taken < *gmem(G.tail) || X < kRepackMinExtent || 2 * A > X) {
+        if (tid == 0) *gmem(G.extent) = X;
         return;
     }
     int holes = 0, srcs = 0;
     for (int s0 = 0; s0 < X; s0 += blockDim.x) {
         const int s = s0 + tid;
-        const bool occ = s < X && G.slot_q[s] >= 0;
+        const bool occ = s < X && gmem(G.slot_q)[s] >= 0;
         int th = 0, ts = 0;
         const int rh = block_rank(s < A && !occ, sh, th);
         const int rs = block_rank(s >= A && occ, sh, ts);
-        if (s < A && !occ) G.move_dst[holes + rh] = s;
-        if (s >= A && occ) G.move_src[srcs + rs] = s;
+        if (s < A && !occ) gmem(G.move_dst)[holes + rh] = s;
+        if (s >= A && occ) gmem(G.move_src)[srcs + rs] = s;
         holes += th;
         srcs += ts;
     }
     __syncthreads();   // the move lists are complete (holes == srcs)
     for (int k = tid; k < holes; k += blockDim.x) {
-        const int src = G.move_src[k], dst = G.move_dst[k];
-        G.slot_desc[dst] = G.slot_desc[src];
-        G.slot_q[dst] = G.slot_q[src];
-        G.slot_t[dst] = G.slot_t[src];
-        G.fail[dst] = G.fail[src];
-        G.slot_q[src] = -1;
+        const int src = gmem(G.move_src)[k], dst = gmem(G.move_dst)[k];
+        store_frame(G.slot_desc + dst, load_frame(G.slot_desc + src));
+        gmem(G.slot_q)[dst] = gmem(G.slot_q)[src];
+        gmem(G.slot_t)[dst] = gmem(G.slot_t)[src];
+        gmem(G.fail)[dst] = gmem(G.fail)[src];
+        gmem(G.slot_q)[src] = -1;
     }
     if (tid == 0) {
-        *G.moves = holes;
-        *G.extent = A;
+        *gmem(G.moves) = holes;
+        *gmem(G.extent) = A;
     }
 }
 
@@ -753,7 +774,7 @@ __global__ __launch_bounds__(256) void eng_repack_move(const EngGraph *__restric
         base[0] = 0;
         for (int c = 0; c < ngraphs; c++) {
             const EngGraph &H = graphs[c];
-            nm[c] = *H.moves;
+            nm[c] = *gmem(H.moves);
             const int64_t rows = int64_t(H.E) + 2 * int64_t(H.n);
             base[c + 1] = base[c] + (nm[c] > 0 ? (rows + kMoveRows - 1) / kMoveRows : 0);
         }
@@ -772,12 +793,12 @@ __global__ __launch_bounds__(256) void eng_repack_move(const EngGraph *__restric
             const int rr = idx / moves;
             const int k = idx - rr * moves;
             const int64_t row = r0 + rr;
-            const int64_t src = G.move_src[k], dst = G.move_dst[k];
+            const int64_t src = gmem(G.move_src)[k], dst = gmem(G.move_dst)[k];
             if (row < E) {
-                MsgWord *R = static_cast<MsgWord *>(G.r);
+                auto R = gmem(static_cast<MsgWord *>(G.r));
                 R[row * S + dst] = R[row * S + src];
             } else {
-                float *L = row < E + n ? G.lch : G.lpost;
+                auto L = gmem(row < E + n ? G.lch : G.lpost);
                 const int64_t v = row < E + n ? row - E : row - E - n;
                 L[v * S + dst] = L[v * S + src];
             }

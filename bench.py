@@ -29,6 +29,15 @@ TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "check_rows_kernel_n64800_f256_4
 DOMINANT = "void check_rows_kernel<0, 4, 8, 1>"
 
 
+def kernel_source_sha():
+    """Hash of the sources the plain decoder's kernels are built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("decode.hip", "device_common.h"):
+        h.update(open(os.path.join(ROOT, "paper_1609_01567_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic():
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 PMC record.
 
@@ -36,13 +45,11 @@ def measured_traffic():
     for a plain 1 GiB copy.  None when the kernel source changed since the counters
     were taken.
     """
-    import hashlib
     try:
         rec = json.load(open(TRAFFIC_RECORD))
     except (OSError, ValueError):
         return None
-    src = open(os.path.join(ROOT, "paper_1609_01567_amd", "csrc", "decode.hip"), "rb").read()
-    if hashlib.sha256(src).hexdigest()[:16] != rec.get("source_sha"):
+    if kernel_source_sha() != rec.get("source_sha"):
         return None
     k = rec["kernels"].get(DOMINANT)
     if not k:
@@ -70,7 +77,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
-    ap.add_argument("--served-requests", type=int, default=3000)
+    ap.add_argument("--served-requests", type=int, default=20000,
+                    help="counted requests per load point (after a 2 s warm-up)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates rocprof byte counters) and exit")
     return ap.parse_args()
@@ -364,7 +372,8 @@ def bench_precision(torch, ldpc, frames=1024, T=100, points=(1.5, 5.0), oracle_f
     return out
 
 
-def bench_served(torch, ldpc, capacity_fps, requests, loads=(0.25, 0.5, 0.75, 0.95), T=50, seed=4001):
+def bench_served(torch, ldpc, capacity_fps, requests, loads=(0.25, 0.5, 0.75, 0.95), T=50, seed=4001,
+                 warmup_s=2.0):
     """Poisson arrivals of requests (1..64 frames of one of the eight batch codes,
     code drawn Zipf(1) by ascending n) at fractions of the measured batch
     capacity; the server (continuous batching, FP16 messages) against plain
@@ -383,7 +392,7 @@ def bench_served(torch, ldpc, capacity_fps, requests, loads=(0.25, 0.5, 0.75, 0.
     zipf /= zipf.sum()
     mean_frames = 32.5
     graphs = [ldpc.Graph.from_code(c) for c in codes]
-    out = {"capacity_frames_per_s": round(capacity_fps, 1), "requests_per_load": requests,
+    out = {"capacity_frames_per_s": round(capacity_fps, 1), "requests_per_load": requests, "warmup_s": warmup_s,
            "workload": "Poisson arrivals; request = U{1..64} frames of one code (Zipf(1) over the 8 batch codes), "
                        "Eb/N0 = waterfall + 0.5 dB, max 50 iterations", "loads": []}
     # slot pools follow each code's share of the request stream (the batched mix's Zipf split)
@@ -394,36 +403,48 @@ def bench_served(torch, ldpc, capacity_fps, requests, loads=(0.25, 0.5, 0.75, 0.
     for rho in loads:
         rng = np.random.default_rng(seed + int(rho * 100))
         lam = rho * capacity_fps / mean_frames
-        gaps = rng.exponential(1.0 / lam, size=requests)
-        gis = rng.choice(len(codes), size=requests, p=zipf)
-        fs = rng.integers(1, 65, size=requests)
-        starts = rng.integers(0, pool_f - 64 + 1, size=requests)
+        warm = int(round(warmup_s * lam))            # requests of the warm-up, not counted
+        total = warm + requests
+        gaps = rng.exponential(1.0 / lam, size=total)
+        gis = rng.choice(len(codes), size=total, p=zipf)
+        fs = rng.integers(1, 65, size=total)
+        starts = rng.integers(0, pool_f - 64 + 1, size=total)
         lat, info = [], 0.0
         pending = {}
+        t_first = t_last = None
         t0 = time.perf_counter()
         t_arr = t0
-        for r in range(requests):
+
+        def collect(rid):
+            nonlocal info, t_last
+            _, _, _, l = srv.result(rid, want_bits=False)
+            r, bits = pending.pop(rid)
+            if r >= warm:
+                lat.append(l)
+                info += bits
+                t_last = time.perf_counter()
+
+        for r in range(total):
             t_arr += gaps[r]
             while time.perf_counter() < t_arr:
                 for rid in srv.poll(0):
-                    _, _, _, l = srv.result(rid, want_bits=False)
-                    lat.append(l)
-                    info += pending.pop(rid)
+                    collect(rid)
             gi, F, st = int(gis[r]), int(fs[r]), int(starts[r])
+            if r == warm:
+                t_first = time.perf_counter()
             rid = srv.submit(gi, pools[gi][st:st + F])
-            pending[rid] = F * kinfo[gi]
+            pending[rid] = (r, F * kinfo[gi])
         deadline = time.perf_counter() + 60
         while pending and time.perf_counter() < deadline:
             for rid in srv.poll(20):
-                _, _, _, l = srv.result(rid, want_bits=False)
-                lat.append(l)
-                info += pending.pop(rid)
-        wall = time.perf_counter() - t0
+                collect(rid)
         lat = np.array(lat)
-        out["loads"].append({"offered": rho, "offered_req_per_s": round(lam, 1), "completed": int(lat.size),
+        window = (t_last or time.perf_counter()) - (t_first or t0)
+        out["loads"].append({"offered": rho, "offered_req_per_s": round(lam, 1), "warmup_requests": warm,
+                             "completed": int(lat.size),
                              "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
                              "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
-                             "gbits": round(info / wall / 1e9, 4), "wall_s": round(wall, 2)})
+                             "gbits": round(info / window / 1e9, 4), "window_s": round(window, 2)})
         print(f"[bench] served load {rho}: p50 {out['loads'][-1]['p50_ms']} ms p99 {out['loads'][-1]['p99_ms']} ms "
               f"{out['loads'][-1]['gbits']} Gbit/s", file=sys.stderr, flush=True)
     out["server_stats"] = srv.stats()
@@ -454,12 +475,22 @@ def bench_served(torch, ldpc, capacity_fps, requests, loads=(0.25, 0.5, 0.75, 0.
         info += F * kinfo[gi]
     wall = time.perf_counter() - t0
     lat = np.array(lat)
-    out["plain_per_request_fp32"] = {"offered": rho, "requests": n_plain,
+    # the same requests back to back (no arrival gaps): the most the per-request path sustains
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(n_plain):
+        gi, F, st = int(gis[r]), int(fs[r]), int(starts[r])
+        res = ldpc.decode(graphs[gi], d_pools[gi][st:st + F].contiguous(), T)
+        res.bits.cpu()
+    sat = info / (time.perf_counter() - t0) / 1e9
+    out["plain_per_request_fp32"] = {"offered": rho, "requests": n_plain, "saturated_gbits": round(sat, 4),
                                      "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
                                      "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
                                      "gbits": round(info / wall / 1e9, 4),
                                      "note": "one ldpc_decode per request in arrival order; the stream falls behind "
                                              "when its service time exceeds the arrival gap, so latency grows"}
+    best = max(x["gbits"] for x in out["loads"])
+    out["served_fp16_vs_plain_per_request_fp32"] = round(best / sat, 3) if sat > 0 else None
     return out
 
 

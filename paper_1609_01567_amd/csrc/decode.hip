@@ -87,7 +87,7 @@ __device__ __forceinline__ void plain_syndrome(const int32_t (&st)[V], const int
 // Rows of degree <= DMAX in registers: one wavefront per (row, slot group).
 template <int M, int V, int DMAX, int MODE>
 __global__ __launch_bounds__(256) void check_rows_kernel(
-    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx, const int32_t *__restrict__ rows,
+    const int32_t *__restrict__ rd, const int32_t *__restrict__ col_idx,
     int32_t nrows, const float *__restrict__ L, typename Codec<M>::T *__restrict__ R,
     const int32_t *__restrict__ iters, int32_t *__restrict__ fail, int32_t S, int32_t groups, int32_t syn_iter) {
     const int lane = threadIdx.x & 63;
@@ -106,18 +106,16 @@ __global__ __launch_bounds__(256) void check_rows_kernel(
     // Lanes whose frames have all stopped issue no loads or stores.
     if (!lane_active) return;
 
-    const int row = wave_uniform(rows[rk]);
-    const int e0 = wave_uniform(row_ptr[row]);
-    const int d = wave_uniform(row_ptr[row + 1]) - e0;
+    const int e0 = wave_uniform(rd[2 * rk]);
+    const int d = wave_uniform(rd[2 * rk + 1]);
     SlotSrc<V> src;
 #pragma unroll
     for (int k = 0; k < V; k++) src.alt[k] = false;
-    src.any_alt = false;
-    src.read_r = MODE == kIter;
     int syn[V];
 #pragma unroll
     for (int k = 0; k < V; k++) syn[k] = 0;
-    row_rule<M, V, DMAX>(col_idx, e0, d, L, nullptr, R, S, s0, src, syn);
+    constexpr int IN = MODE == kIter ? kInSteady : kInFirst;
+    row_rule<M, V, DMAX, true, IN>(col_idx, e0, d, L, nullptr, R, S, s0, src, syn);
     if (MODE == kIter) plain_syndrome<V>(st, syn, fail, s0, syn_iter);
 }
 
@@ -126,12 +124,13 @@ __global__ __launch_bounds__(256) void check_rows_kernel(
 // chunk recomputes its chunks' inputs in the second phase.
 template <int M, int V, int WPR, int MODE>
 __global__ __launch_bounds__(256) void check_chunk_kernel(
-    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx, const int32_t *__restrict__ rows,
+    const int32_t *__restrict__ rd, const int32_t *__restrict__ col_idx,
     int32_t nrows, const float *__restrict__ L, typename Codec<M>::T *__restrict__ R,
     const int32_t *__restrict__ iters, int32_t *__restrict__ fail, int32_t S, int32_t groups, int32_t syn_iter) {
     constexpr int C = kRowChunk;
     constexpr int RPB = 4 / WPR;
     constexpr int MAXCH = WPR == 2 ? 2 : 16;
+    constexpr int kChunkIn = MODE == kIter ? kInSteady : kInFirst;
     __shared__ ChunkShare<V, RPB * MAXCH> sh;
     const int lane = threadIdx.x & 63;
     const int wave = wave_uniform(threadIdx.x >> 6);
@@ -151,26 +150,23 @@ __global__ __launch_bounds__(256) void check_chunk_kernel(
     }
     // same slots for every wavefront of a row: uniform over the row's wavefronts
     const bool work = rk < nrows && __ballot(lane_active) != 0;
-    int row = 0, e0 = 0, d = 0, nch = 0;
+    int e0 = 0, d = 0, nch = 0;
     if (work) {
-        row = wave_uniform(rows[rk]);
-        e0 = wave_uniform(row_ptr[row]);
-        d = wave_uniform(row_ptr[row + 1]) - e0;
+        e0 = wave_uniform(rd[2 * rk]);
+        d = wave_uniform(rd[2 * rk + 1]);
         nch = (d + C - 1) / C;
     }
     SlotSrc<V> src;
 #pragma unroll
     for (int k = 0; k < V; k++) src.alt[k] = false;
-    src.any_alt = false;
-    src.read_r = MODE == kIter;
     const bool mine = work && lane_active;
     float u[C][V], suf[C][V], agg[V];
     uint32_t neg[V];
     int syn[V];
     for (int ch = wr; ch < nch; ch += WPR) {
         if (mine) {
-            chunk_load<M, V, C>(col_idx, e0 + ch * C, min(C, d - ch * C), L, nullptr, R, S, s0, src, u, suf, agg,
-                                neg, syn);
+            chunk_load<M, V, C, kChunkIn>(col_idx, e0 + ch * C, min(C, d - ch * C), L, nullptr, R, S, s0, src, u,
+                                          suf, agg, neg, syn);
         } else {
 #pragma unroll
             for (int k = 0; k < V; k++) { agg[k] = 0.f; neg[k] = 0u; syn[k] = 0; }
@@ -183,8 +179,8 @@ __global__ __launch_bounds__(256) void check_chunk_kernel(
     if (!mine) return;
     for (int ch = wr; ch < nch; ch += WPR) {
         if (nch > WPR)
-            chunk_load<M, V, C>(col_idx, e0 + ch * C, min(C, d - ch * C), L, nullptr, R, S, s0, src, u, suf, agg,
-                                neg, syn);
+            chunk_load<M, V, C, kChunkIn>(col_idx, e0 + ch * C, min(C, d - ch * C), L, nullptr, R, S, s0, src, u,
+                                          suf, agg, neg, syn);
         float pre[V], post[V];
         uint32_t parity[V];
         int syn_row[V];
@@ -201,7 +197,7 @@ __global__ __launch_bounds__(256) void check_chunk_kernel(
 // and each chunk is then finished with a local prefix/suffix pass.
 template <int M, int MODE>
 __global__ __launch_bounds__(256) void check_hub_kernel(
-    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx, const int32_t *__restrict__ rows,
+    const int32_t *__restrict__ rd, const int32_t *__restrict__ col_idx,
     int32_t nrows, const int32_t *__restrict__ chunk_base, const float *__restrict__ L,
     typename Codec<M>::T *__restrict__ R, const int32_t *__restrict__ iters, int32_t *__restrict__ fail,
     int32_t S, int32_t groups, int32_t syn_iter, float *__restrict__ aggD, float *__restrict__ aggPre,
@@ -218,9 +214,8 @@ __global__ __launch_bounds__(256) void check_hub_kernel(
     const bool active = iters[s] == 0;
     if (__ballot(active) == 0) return;   // same slots in every wave: uniform over the block
 
-    const int row = wave_uniform(rows[rk]);
-    const int e0 = wave_uniform(row_ptr[row]);
-    const int d = wave_uniform(row_ptr[row + 1]) - e0;
+    const int e0 = wave_uniform(rd[2 * rk]);
+    const int d = wave_uniform(rd[2 * rk + 1]);
     const int nch = (d + C - 1) / C;
     const int cb = wave_uniform(chunk_base[rk]);
 
@@ -363,9 +358,8 @@ __global__ __launch_bounds__(256) void bit_kernel(const int32_t *__restrict__ co
 // Syndrome of the current estimate for every non-empty check (any degree):
 // frames still running whose estimate fails get fail[s] = syn_iter.
 template <int V>
-__global__ __launch_bounds__(256) void syndrome_kernel(const int32_t *__restrict__ row_ptr,
-                                                       const int32_t *__restrict__ col_idx,
-                                                       const int32_t *__restrict__ rows, int32_t nrows,
+__global__ __launch_bounds__(256) void syndrome_kernel(const int32_t *__restrict__ rd,
+                                                       const int32_t *__restrict__ col_idx, int32_t nrows,
                                                        const float *__restrict__ Lpost,
                                                        const int32_t *__restrict__ iters, int32_t *__restrict__ fail,
                                                        int32_t S, int32_t groups, int32_t syn_iter) {
@@ -382,9 +376,8 @@ __global__ __launch_bounds__(256) void syndrome_kernel(const int32_t *__restrict
     for (int k = 0; k < V; k++) any_active |= (st[k] == 0);
     if (__ballot(any_active) == 0) return;
     if (!any_active) return;
-    const int row = wave_uniform(rows[rk]);
-    const int a = wave_uniform(row_ptr[row]);
-    const int b = wave_uniform(row_ptr[row + 1]);
+    const int a = wave_uniform(rd[2 * rk]);
+    const int b = a + wave_uniform(rd[2 * rk + 1]);
     int syn[V];
 #pragma unroll
     for (int k = 0; k < V; k++) syn[k] = 0;
@@ -503,13 +496,13 @@ void launch_rows(const ldpc_graph *g, int cls, int mode, const float *L, const B
     const unsigned blocks = blocks_for_waves(int64_t(nrows) * groups);
     using T = typename Codec<M>::T;
     T *R = static_cast<T *>(b.r);
-    const int32_t *rows = g->d_class_rows + g->class_begin[cls];
+    const int32_t *rd = g->d_class_rd + 2 * g->class_begin[cls];
     if (mode == kFirst)
-        hipLaunchKernelGGL((check_rows_kernel<M, V, DMAX, kFirst>), dim3(blocks), dim3(256), 0, st, g->d_row_ptr,
-                           g->d_col_idx, rows, nrows, L, R, b.iters, b.fail, S, groups, 0);
+        hipLaunchKernelGGL((check_rows_kernel<M, V, DMAX, kFirst>), dim3(blocks), dim3(256), 0, st, rd, g->d_col_idx,
+                           nrows, L, R, b.iters, b.fail, S, groups, 0);
     else
-        hipLaunchKernelGGL((check_rows_kernel<M, V, DMAX, kIter>), dim3(blocks), dim3(256), 0, st, g->d_row_ptr,
-                           g->d_col_idx, rows, nrows, L, R, b.iters, b.fail, S, groups, syn_iter);
+        hipLaunchKernelGGL((check_rows_kernel<M, V, DMAX, kIter>), dim3(blocks), dim3(256), 0, st, rd, g->d_col_idx,
+                           nrows, L, R, b.iters, b.fail, S, groups, syn_iter);
 }
 
 template <int M, int V, int WPR>
@@ -522,13 +515,13 @@ void launch_chunked(const ldpc_graph *g, int cls, int mode, const float *L, cons
     const unsigned blocks = unsigned((items + (4 / WPR) - 1) / (4 / WPR));
     using T = typename Codec<M>::T;
     T *R = static_cast<T *>(b.r);
-    const int32_t *rows = g->d_class_rows + g->class_begin[cls];
+    const int32_t *rd = g->d_class_rd + 2 * g->class_begin[cls];
     if (mode == kFirst)
-        hipLaunchKernelGGL((check_chunk_kernel<M, V, WPR, kFirst>), dim3(blocks), dim3(256), 0, st, g->d_row_ptr,
-                           g->d_col_idx, rows, nrows, L, R, b.iters, b.fail, S, groups, 0);
+        hipLaunchKernelGGL((check_chunk_kernel<M, V, WPR, kFirst>), dim3(blocks), dim3(256), 0, st, rd, g->d_col_idx,
+                           nrows, L, R, b.iters, b.fail, S, groups, 0);
     else
-        hipLaunchKernelGGL((check_chunk_kernel<M, V, WPR, kIter>), dim3(blocks), dim3(256), 0, st, g->d_row_ptr,
-                           g->d_col_idx, rows, nrows, L, R, b.iters, b.fail, S, groups, syn_iter);
+        hipLaunchKernelGGL((check_chunk_kernel<M, V, WPR, kIter>), dim3(blocks), dim3(256), 0, st, rd, g->d_col_idx,
+                           nrows, L, R, b.iters, b.fail, S, groups, syn_iter);
 }
 
 template <int M>
@@ -540,15 +533,14 @@ void launch_hub(const ldpc_graph *g, int mode, const float *L, const Bufs &b, in
     const unsigned blocks = unsigned(int64_t(nrows) * groups);
     using T = typename Codec<M>::T;
     T *R = static_cast<T *>(b.r);
-    const int32_t *rows = g->d_class_rows + g->class_begin[ldpc::kClassHub];
+    const int32_t *rd = g->d_class_rd + 2 * g->class_begin[ldpc::kClassHub];
     if (mode == kFirst)
-        hipLaunchKernelGGL((check_hub_kernel<M, kFirst>), dim3(blocks), dim3(256), 0, st, g->d_row_ptr, g->d_col_idx,
-                           rows, nrows, g->d_hub_chunk_base, L, R, b.iters, b.fail, S, groups, 0, b.aggd, b.aggpre,
-                           b.aggbits);
+        hipLaunchKernelGGL((check_hub_kernel<M, kFirst>), dim3(blocks), dim3(256), 0, st, rd, g->d_col_idx, nrows,
+                           g->d_hub_chunk_base, L, R, b.iters, b.fail, S, groups, 0, b.aggd, b.aggpre, b.aggbits);
     else
-        hipLaunchKernelGGL((check_hub_kernel<M, kIter>), dim3(blocks), dim3(256), 0, st, g->d_row_ptr, g->d_col_idx,
-                           rows, nrows, g->d_hub_chunk_base, L, R, b.iters, b.fail, S, groups, syn_iter, b.aggd,
-                           b.aggpre, b.aggbits);
+        hipLaunchKernelGGL((check_hub_kernel<M, kIter>), dim3(blocks), dim3(256), 0, st, rd, g->d_col_idx, nrows,
+                           g->d_hub_chunk_base, L, R, b.iters, b.fail, S, groups, syn_iter, b.aggd, b.aggpre,
+                           b.aggbits);
 }
 
 template <int M, int V>
@@ -597,7 +589,7 @@ void run_decode(const ldpc_graph *g, const Plan &p, const Bufs &b, const float *
     const int32_t nrows = g->class_begin[ldpc::kNumClasses];
     if (nrows > 0) {
         hipLaunchKernelGGL((syndrome_kernel<V>), dim3(blocks_for_waves(int64_t(nrows) * groups)), dim3(256), 0, st,
-                           g->d_row_ptr, g->d_col_idx, g->d_class_rows, nrows, b.lpost, b.iters, b.fail, S, groups, T);
+                           g->d_class_rd, g->d_col_idx, nrows, b.lpost, b.iters, b.fail, S, groups, T);
     }
     hipLaunchKernelGGL(finalize_kernel, dim3((F + 255) / 256), dim3(256), 0, st, b.iters, b.fail, F, T, iters_out, ok);
     hipLaunchKernelGGL(egress_kernel, tgrid, dim3(256), 0, st, b.lpost, S, F, g->n, bits, llr_out);

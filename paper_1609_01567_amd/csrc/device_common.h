@@ -123,15 +123,19 @@ __device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_rea
 
 // ----------------------------------------------------------- row building blocks
 
-// Where each of a lane's V frame slots takes its inputs in one check pass:
-// `read_r` false means every previous message is 0 (first iteration of every
-// slot); `alt[k]` marks a slot in its first iteration among slots that are not
-// (its L comes from the channel array and its previous message is 0).
+// Where a check pass takes each edge's inputs (a compile-time choice, so the
+// common case carries no per-slot selection):
+//   kInFirst   first iteration of every slot: L is the channel array and every
+//              previous message is 0 (Algorithm 3's q = p);
+//   kInSteady  every slot past its first iteration: L is the posterior, R_old
+//              is read;
+//   kInMixed   as kInSteady, except slots with SlotSrc::alt set, which are in
+//              their first iteration (channel LLR, previous message 0).
+enum Inputs { kInFirst = 0, kInSteady = 1, kInMixed = 2 };
+
 template <int V>
 struct SlotSrc {
     bool alt[V];
-    bool any_alt;
-    bool read_r;
 };
 
 // Inputs of edges j0 .. j0+count-1 (1 <= count <= C) for the lane's slots:
@@ -142,7 +146,7 @@ struct SlotSrc {
 // branch), so the loads of a row are in flight together instead of one edge
 // at a time.  UNIFORM: all lanes walk the same row (indices read once per
 // wavefront).
-template <int M, int V, int C, bool UNIFORM>
+template <int M, int V, int C, bool UNIFORM, int IN>
 __device__ __forceinline__ void gather_edges(const int32_t *__restrict__ col_idx, int j0, int count,
                                              const float *__restrict__ L, const float *__restrict__ Lalt,
                                              const typename Codec<M>::T *__restrict__ R, int32_t S, int s0,
@@ -159,14 +163,14 @@ __device__ __forceinline__ void gather_edges(const int32_t *__restrict__ col_idx
     for (int j = 0; j < C; j++) {
         const int e = j0 + (j < count ? j : count - 1);
         load_vec<kF32, V>(L + size_t(vix[j]) * S + s0, lv[j]);
-        if (src.read_r) {
+        if (IN != kInFirst) {
             load_vec<M, V>(R + size_t(e) * S + s0, r[j]);
         } else {
 #pragma unroll
             for (int k = 0; k < V; k++) r[j][k] = 0.f;
         }
     }
-    if (src.any_alt) {
+    if (IN == kInMixed) {
 #pragma unroll
         for (int j = 0; j < C; j++) {
             float lc[V];
@@ -194,7 +198,7 @@ __device__ __forceinline__ void gather_edges(const int32_t *__restrict__ col_idx
 // suffixes, then exclusive prefixes combined on the fly; R is updated in place.
 // UNIFORM: every lane of the wavefront works on the same row (indices are read
 // once per wavefront); otherwise each lane walks its own row.
-template <int M, int V, int DMAX, bool UNIFORM = true>
+template <int M, int V, int DMAX, bool UNIFORM, int IN>
 __device__ __forceinline__ void row_rule(const int32_t *__restrict__ col_idx, int e0, int d,
                                          const float *__restrict__ L, const float *__restrict__ Lalt,
                                          typename Codec<M>::T *__restrict__ R, int32_t S, int s0,
@@ -204,7 +208,7 @@ __device__ __forceinline__ void row_rule(const int32_t *__restrict__ col_idx, in
     uint32_t neg[V];
 #pragma unroll
     for (int k = 0; k < V; k++) neg[k] = 0u;
-    gather_edges<M, V, DMAX, UNIFORM>(col_idx, e0, d, L, Lalt, R, S, s0, src, u, neg, syn);
+    gather_edges<M, V, DMAX, UNIFORM, IN>(col_idx, e0, d, L, Lalt, R, S, s0, src, u, neg, syn);
     float run[V];
 #pragma unroll
     for (int k = 0; k < V; k++) run[k] = 0.f;
@@ -274,7 +278,7 @@ __device__ __forceinline__ void bit_sum(const int32_t *__restrict__ csc_to_csr, 
 // (pre), of the chunks after it (post) and the row's total sign parity.
 constexpr int kRowChunk = 8;
 
-template <int M, int V, int C>
+template <int M, int V, int C, int IN>
 __device__ __forceinline__ void chunk_load(const int32_t *__restrict__ col_idx, int j0, int dc,
                                            const float *__restrict__ L, const float *__restrict__ Lalt,
                                            const typename Codec<M>::T *__restrict__ R, int32_t S, int s0,
@@ -282,7 +286,7 @@ __device__ __forceinline__ void chunk_load(const int32_t *__restrict__ col_idx, 
                                            float (&agg)[V], uint32_t (&neg)[V], int (&syn)[V]) {
 #pragma unroll
     for (int k = 0; k < V; k++) { neg[k] = 0u; syn[k] = 0; }
-    gather_edges<M, V, C, true>(col_idx, j0, dc, L, Lalt, R, S, s0, src, u, neg, syn);
+    gather_edges<M, V, C, true, IN>(col_idx, j0, dc, L, Lalt, R, S, s0, src, u, neg, syn);
 #pragma unroll
     for (int k = 0; k < V; k++) agg[k] = 0.f;
 #pragma unroll

@@ -56,13 +56,13 @@ struct EngFrame {   // device mirror of ldpc_frame
 static_assert(sizeof(EngFrame) == sizeof(ldpc_frame), "ldpc_frame layout");
 
 struct EngGraph {
-    const int32_t *row_ptr, *col_idx, *col_ptr, *csc_to_csr, *class_rows, *hub_chunk_base;
+    const int32_t *col_idx, *col_ptr, *csc_to_csr, *hub_chunk_base;
+    const int32_t *class_rd;   // per class row (class order): first edge, degree
     int32_t n, S, E;
     int32_t class_begin[ldpc::kNumClasses + 1];
     float *lch, *lpost;
     void *r;
-    int32_t *slot_q;      // queue index of the frame in the slot, -1 if empty
-    int32_t *slot_t;      // iterations completed by that frame
+    int32_t *slot_t;      // iterations completed by the frame in the slot; -1: the slot is empty
     int32_t *fail;        // t of the last estimate whose syndrome failed
     EngFrame *slot_desc;  // descriptor of the frame in the slot
     float *aggd, *aggpre;
@@ -125,24 +125,22 @@ struct EngLane {
     int32_t t[V];
     bool syn_on[V];
     bool active;
+    bool any_alt;
     SlotSrc<V> src;
 };
 
 template <int V>
 __device__ __forceinline__ void eng_lane(const EngGraph &G, int s0, int32_t T, int32_t early, EngLane<V> &ln) {
-    int32_t q[V];
-    load_i32<V>(G.slot_q + s0, q);
     load_i32<V>(G.slot_t + s0, ln.t);
     ln.active = false;
-    ln.src.any_alt = false;
-    ln.src.read_r = true;
+    ln.any_alt = false;
 #pragma unroll
     for (int k = 0; k < V; k++) {
-        const bool act = q[k] >= 0;
-        ln.src.alt[k] = act && ln.t[k] == 0;
-        ln.syn_on[k] = act && ln.t[k] >= 1 && (early || ln.t[k] == T);
+        const bool act = ln.t[k] >= 0;
+        ln.src.alt[k] = ln.t[k] == 0;
+        ln.syn_on[k] = ln.t[k] >= 1 && (early || ln.t[k] == T);
         ln.active |= act;
-        ln.src.any_alt |= ln.src.alt[k];
+        ln.any_alt |= ln.src.alt[k];
     }
 }
 
@@ -199,12 +197,12 @@ __device__ __forceinline__ int work_graph(const Work &w, int32_t ngraphs, int x)
 
 // Rows of up to DMAX edges: one wavefront per (row, slot group), looping over
 // the items of the pass.
-template <int M, int V, int DMAX>
+template <int M, int V, int DMAX, bool PACK = true>
 __global__ __launch_bounds__(256) void eng_check_rows(const EngGraph *__restrict__ graphs, int32_t ngraphs,
                                                       int32_t cls, int32_t T, int32_t early) {
     using MT = typename Codec<M>::T;
     __shared__ Work w;
-    build_work<true>(graphs, ngraphs, cls, 64 * V, 1, w);
+    build_work<PACK>(graphs, ngraphs, cls, 64 * V, 1, w);
     const int lane = threadIdx.x & 63;
     const int total = w.p[ngraphs];
     const int stride = int(gridDim.x * (blockDim.x >> 6));
@@ -215,7 +213,7 @@ __global__ __launch_bounds__(256) void eng_check_rows(const EngGraph *__restrict
         const int rpw = w.rpw[c];
         const int nrows = G.class_begin[cls + 1] - G.class_begin[cls];
         int rk, s0;
-        if (rpw == 1) {
+        if (!PACK || rpw == 1) {
             const int groups = w.groups[c];
             rk = local / groups;
             s0 = ((local - rk * groups) * 64 + lane) * V;
@@ -232,16 +230,25 @@ __global__ __launch_bounds__(256) void eng_check_rows(const EngGraph *__restrict
 #pragma unroll
         for (int k = 0; k < V; k++) syn[k] = 0;
         MT *R = static_cast<MT *>(G.r);
-        if (rpw == 1) {
-            const int row = wave_uniform(cload(G.class_rows + G.class_begin[cls] + rk));
-            const int e0 = wave_uniform(cload(G.row_ptr + (row)));
-            const int d = wave_uniform(cload(G.row_ptr + (row + 1))) - e0;
-            row_rule<M, V, DMAX, true>(G.col_idx, e0, d, G.lpost, G.lch, R, G.S, s0, ln.src, syn);
+        // slots in their first iteration are rare: the wavefront takes the
+        // per-slot input selection only when one of its lanes holds one
+        const bool mixed = __ballot(ln.any_alt) != 0;
+        if (!PACK || rpw == 1) {
+            const u32x2 rdv = cload(reinterpret_cast<const u32x2 *>(G.class_rd) + G.class_begin[cls] + rk);
+            const int e0 = wave_uniform(int(rdv.x));
+            const int d = wave_uniform(int(rdv.y));
+            if (mixed)
+                row_rule<M, V, DMAX, true, kInMixed>(G.col_idx, e0, d, G.lpost, G.lch, R, G.S, s0, ln.src, syn);
+            else
+                row_rule<M, V, DMAX, true, kInSteady>(G.col_idx, e0, d, G.lpost, G.lch, R, G.S, s0, ln.src, syn);
         } else {
-            const int row = cload(G.class_rows + G.class_begin[cls] + rk);
-            const int e0 = cload(G.row_ptr + (row));
-            const int d = cload(G.row_ptr + (row + 1)) - e0;
-            row_rule<M, V, DMAX, false>(G.col_idx, e0, d, G.lpost, G.lch, R, G.S, s0, ln.src, syn);
+            const u32x2 rdv = cload(reinterpret_cast<const u32x2 *>(G.class_rd) + G.class_begin[cls] + rk);
+            const int e0 = int(rdv.x);
+            const int d = int(rdv.y);
+            if (mixed)
+                row_rule<M, V, DMAX, false, kInMixed>(G.col_idx, e0, d, G.lpost, G.lch, R, G.S, s0, ln.src, syn);
+            else
+                row_rule<M, V, DMAX, false, kInSteady>(G.col_idx, e0, d, G.lpost, G.lch, R, G.S, s0, ln.src, syn);
         }
         eng_syndrome<V>(G, ln, syn, s0);
     }
@@ -280,21 +287,25 @@ __global__ __launch_bounds__(256) void eng_check_chunk(const EngGraph *__restric
         const bool work = valid && __ballot(ln.active) != 0;
         int e0 = 0, d = 0, nch = 0;
         if (work) {
-            const int row = wave_uniform(cload(G.class_rows + G.class_begin[cls] + rk));
-            e0 = wave_uniform(cload(G.row_ptr + (row)));
-            d = wave_uniform(cload(G.row_ptr + (row + 1))) - e0;
+            const u32x2 rdv = cload(reinterpret_cast<const u32x2 *>(G.class_rd) + G.class_begin[cls] + rk);
+            e0 = wave_uniform(int(rdv.x));
+            d = wave_uniform(int(rdv.y));
             nch = (d + C - 1) / C;
         }
         MT *R = static_cast<MT *>(G.r);
         const int32_t S = G.S;
         const bool mine = work && ln.active;
+        const bool mixed = __ballot(ln.any_alt) != 0;   // uniform over the wavefront
         float u_[C][V], suf[C][V], agg[V];
         uint32_t neg[V];
         int syn[V];
         for (int ch = wr; ch < nch; ch += WPR) {
-            if (mine) {
-                chunk_load<M, V, C>(G.col_idx, e0 + ch * C, min(C, d - ch * C), G.lpost, G.lch, R, S, s0, ln.src,
-                                    u_, suf, agg, neg, syn);
+            if (mine && mixed) {
+                chunk_load<M, V, C, kInMixed>(G.col_idx, e0 + ch * C, min(C, d - ch * C), G.lpost, G.lch, R, S, s0,
+                                              ln.src, u_, suf, agg, neg, syn);
+            } else if (mine) {
+                chunk_load<M, V, C, kInSteady>(G.col_idx, e0 + ch * C, min(C, d - ch * C), G.lpost, G.lch, R, S,
+                                               s0, ln.src, u_, suf, agg, neg, syn);
             } else {
 #pragma unroll
                 for (int k = 0; k < V; k++) { agg[k] = 0.f; neg[k] = 0u; syn[k] = 0; }
@@ -306,9 +317,12 @@ __global__ __launch_bounds__(256) void eng_check_chunk(const EngGraph *__restric
         __syncthreads();
         if (mine) {
             for (int ch = wr; ch < nch; ch += WPR) {
-                if (nch > WPR)
-                    chunk_load<M, V, C>(G.col_idx, e0 + ch * C, min(C, d - ch * C), G.lpost, G.lch, R, S, s0,
-                                        ln.src, u_, suf, agg, neg, syn);
+                if (nch > WPR && mixed)
+                    chunk_load<M, V, C, kInMixed>(G.col_idx, e0 + ch * C, min(C, d - ch * C), G.lpost, G.lch, R, S,
+                                                  s0, ln.src, u_, suf, agg, neg, syn);
+                else if (nch > WPR)
+                    chunk_load<M, V, C, kInSteady>(G.col_idx, e0 + ch * C, min(C, d - ch * C), G.lpost, G.lch, R,
+                                                   S, s0, ln.src, u_, suf, agg, neg, syn);
                 float pre_a[V], post_a[V];
                 uint32_t parity[V];
                 int syn_row[V];
@@ -345,15 +359,15 @@ __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict_
         const int g = local % groups;
         const int rk = local / groups;
         const int s = g * 64 + lane;
-        const int32_t qs = gmem(G.slot_q)[s], ts = gmem(G.slot_t)[s];
-        const bool active = qs >= 0;
+        const int32_t ts = gmem(G.slot_t)[s];
+        const bool active = ts >= 0;
         const bool first = active && ts == 0;
         const bool syn_on = active && ts >= 1 && (early || ts == T);
         if (__ballot(active) == 0) continue;   // same slots in every wavefront: uniform over the workgroup
 
-        const int row = wave_uniform(cload(G.class_rows + G.class_begin[ldpc::kClassHub] + rk));
-        const int e0 = wave_uniform(cload(G.row_ptr + (row)));
-        const int d = wave_uniform(cload(G.row_ptr + (row + 1))) - e0;
+        const u32x2 rdv = cload(reinterpret_cast<const u32x2 *>(G.class_rd) + G.class_begin[ldpc::kClassHub] + rk);
+        const int e0 = wave_uniform(int(rdv.x));
+        const int d = wave_uniform(int(rdv.y));
         const int nch = (d + C - 1) / C;
         const int cb = wave_uniform(cload(G.hub_chunk_base + (rk)));
         auto R = gmem(static_cast<MT *>(G.r));
@@ -446,15 +460,14 @@ template <int M, int V, bool UNIFORM>
 __device__ __forceinline__ void bit_item(const EngGraph &G, int v, int s0, int32_t T, int32_t early) {
     using MT = typename Codec<M>::T;
     const int32_t S = G.S;
-    int32_t q[V], t[V], f[V];
-    load_i32<V>(G.slot_q + s0, q);
+    int32_t t[V], f[V];
     load_i32<V>(G.slot_t + s0, t);
     load_i32<V>(G.fail + s0, f);
     bool adv[V];
     bool any = false, all = true;
 #pragma unroll
     for (int k = 0; k < V; k++) {
-        adv[k] = q[k] >= 0 && !slot_stops(t[k], f[k], T, early);
+        adv[k] = t[k] >= 0 && !slot_stops(t[k], f[k], T, early);
         any |= adv[k];
         all &= adv[k];
     }
@@ -524,12 +537,11 @@ __global__ __launch_bounds__(256) void eng_advance(const EngGraph *__restrict__ 
         c = find_graph(pre, x);
         const EngGraph &G = graphs[c];
         const int s = x - pre.p[c];
-        const int32_t q = gmem(G.slot_q)[s];
-        if (q < 0) {
+        const int32_t t = gmem(G.slot_t)[s];
+        if (t < 0) {
             listme = *gmem(G.head) < *gmem(G.tail);
             ent = s;
         } else {
-            const int32_t t = gmem(G.slot_t)[s];
             const int32_t f = gmem(G.fail)[s];
             if (slot_stops(t, f, T, early)) {
                 const EngFrame fr = load_frame(G.slot_desc + s);
@@ -709,9 +721,8 @@ __global__ __launch_bounds__(1024) void eng_admit(const EngGraph *__restrict__ g
             store_frame(G.slot_desc + s, load_frame(G.queue + qi % G.cap));
             gmem(G.slot_t)[s] = 0;
             gmem(G.fail)[s] = 0;
-            gmem(G.slot_q)[s] = qi;
         } else {
-            gmem(G.slot_q)[s] = -1;
+            gmem(G.slot_t)[s] = -1;
         }
     }
     if (tid == 0) *gmem(G.moves) = 0;
@@ -719,7 +730,7 @@ __global__ __launch_bounds__(1024) void eng_admit(const EngGraph *__restrict__ g
     const int S = G.S;
     int a = 0, x = 0;
     for (int s = tid; s < S; s += blockDim.x)
-        if (gmem(G.slot_q)[s] >= 0) { a++; x = s + 1; }
+        if (gmem(G.slot_t)[s] >= 0) { a++; x = s + 1; }
     // workgroup sum of a, max of x
     for (int off = 32; off > 0; off >>= 1) {
         a += __shfl_down(a, off);
@@ -737,7 +748,7 @@ __global__ __launch_bounds__(1024) void eng_admit(const EngGraph *__restrict__ g
     int holes = 0, srcs = 0;
     for (int s0 = 0; s0 < X; s0 += blockDim.x) {
         const int s = s0 + tid;
-        const bool occ = s < X && gmem(G.slot_q)[s] >= 0;
+        const bool occ = s < X && gmem(G.slot_t)[s] >= 0;
         int th = 0, ts = 0;
         const int rh = block_rank(s < A && !occ, sh, th);
         const int rs = block_rank(s >= A && occ, sh, ts);
@@ -750,10 +761,9 @@ __global__ __launch_bounds__(1024) void eng_admit(const EngGraph *__restrict__ g
     for (int k = tid; k < holes; k += blockDim.x) {
         const int src = gmem(G.move_src)[k], dst = gmem(G.move_dst)[k];
         store_frame(G.slot_desc + dst, load_frame(G.slot_desc + src));
-        gmem(G.slot_q)[dst] = gmem(G.slot_q)[src];
         gmem(G.slot_t)[dst] = gmem(G.slot_t)[src];
         gmem(G.fail)[dst] = gmem(G.fail)[src];
-        gmem(G.slot_q)[src] = -1;
+        gmem(G.slot_t)[src] = -1;
     }
     if (tid == 0) {
         *gmem(G.moves) = holes;
@@ -819,6 +829,7 @@ struct ldpc_engine {
     uint32_t flags = 0;
     bool early = true;
     bool repack = true;
+    bool pack = true;        // packed row items for nearly drained pools
     std::vector<const ldpc_graph *> graphs;
     std::vector<int32_t> S, cap;
     std::vector<EngGraph> hg;
@@ -854,11 +865,21 @@ void enqueue_step(ldpc_engine *e) {
     const int32_t early = e->early ? 1 : 0;
     const int32_t ng = e->ngraphs;
     if (e->has_rows[0])
-        hipLaunchKernelGGL((eng_check_rows<M, V, 8>), dim3(e->grid_rows[0]), dim3(256), 0, st, e->d_graphs, ng,
-                           int32_t(ldpc::kClassD8), e->T, early);
+        if (e->pack)
+            hipLaunchKernelGGL((eng_check_rows<M, V, 8, true>), dim3(e->grid_rows[0]), dim3(256), 0, st, e->d_graphs, ng,
+                               int32_t(ldpc::kClassD8), e->T, early);
+        else
+            hipLaunchKernelGGL((eng_check_rows<M, V, 8, false>), dim3(e->grid_rows[0]), dim3(256), 0, st, e->d_graphs,
+                               ng, int32_t(ldpc::kClassD8), e->T, early);
     if (e->has_rows[1])
-        hipLaunchKernelGGL((eng_check_rows<M, ldpc::class_lane_slots(ldpc::kClassD16, V), 16>), dim3(e->grid_rows[1]),
-                           dim3(256), 0, st, e->d_graphs, ng, int32_t(ldpc::kClassD16), e->T, early);
+        if (e->pack)
+            hipLaunchKernelGGL((eng_check_rows<M, ldpc::class_lane_slots(ldpc::kClassD16, V), 16, true>),
+                               dim3(e->grid_rows[1]), dim3(256), 0, st, e->d_graphs, ng, int32_t(ldpc::kClassD16), e->T,
+                               early);
+        else
+            hipLaunchKernelGGL((eng_check_rows<M, ldpc::class_lane_slots(ldpc::kClassD16, V), 16, false>),
+                               dim3(e->grid_rows[1]), dim3(256), 0, st, e->d_graphs, ng, int32_t(ldpc::kClassD16), e->T,
+                               early);
     if (e->has_rows[2])
         hipLaunchKernelGGL((eng_check_chunk<M, V, ldpc::class_waves_per_row(ldpc::kClassD128)>),
                            dim3(e->grid_rows[2]), dim3(256), 0, st, e->d_graphs, ng, int32_t(ldpc::kClassD128), e->T,
@@ -1021,13 +1042,14 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
     e->V = V;
     e->K = K;
     e->repack = repack;
+    if (const char *v = std::getenv("LDPC_ENGINE_NO_PACK")) e->pack = v[0] != '1';
     e->graphs.assign(graphs, graphs + ngraphs);
     const int32_t unit = 64 * V;
     const size_t msg_bytes = e->msg == kF32 ? 4 : 2;
 
     // device layout: per graph state, then counters, turnover list, graph table
     size_t off = 0;
-    struct Offs { size_t lch, lpost, r, q, t, fail, desc, aggd, aggpre, aggbits, queue, list, msrc, mdst; };
+    struct Offs { size_t lch, lpost, r, t, fail, desc, aggd, aggpre, aggbits, queue, list, msrc, mdst; };
     std::vector<Offs> go(static_cast<size_t>(ngraphs));
     for (int32_t c = 0; c < ngraphs; c++) {
         const ldpc_graph *g = graphs[c];
@@ -1038,7 +1060,6 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
         o.lch = off;     off = al256(off + size_t(g->n) * S * 4);
         o.lpost = off;   off = al256(off + size_t(g->n) * S * 4);
         o.r = off;       off = al256(off + size_t(g->E) * S * msg_bytes);
-        o.q = off;       off = al256(off + size_t(S) * 4);
         o.t = off;       off = al256(off + size_t(S) * 4);
         o.fail = off;    off = al256(off + size_t(S) * 4);
         o.desc = off;    off = al256(off + size_t(S) * sizeof(EngFrame));
@@ -1067,8 +1088,8 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
         const ldpc_graph *g = graphs[c];
         const Offs &o = go[size_t(c)];
         EngGraph G{};
-        G.row_ptr = g->d_row_ptr; G.col_idx = g->d_col_idx; G.col_ptr = g->d_col_ptr;
-        G.csc_to_csr = g->d_csc_to_csr; G.class_rows = g->d_class_rows; G.hub_chunk_base = g->d_hub_chunk_base;
+        G.col_idx = g->d_col_idx; G.col_ptr = g->d_col_ptr; G.csc_to_csr = g->d_csc_to_csr;
+        G.class_rd = g->d_class_rd; G.hub_chunk_base = g->d_hub_chunk_base;
         G.n = g->n;
         G.E = int32_t(g->E);
         G.S = e->S[size_t(c)];
@@ -1076,7 +1097,6 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
         G.lch = reinterpret_cast<float *>(base + o.lch);
         G.lpost = reinterpret_cast<float *>(base + o.lpost);
         G.r = base + o.r;
-        G.slot_q = reinterpret_cast<int32_t *>(base + o.q);
         G.slot_t = reinterpret_cast<int32_t *>(base + o.t);
         G.fail = reinterpret_cast<int32_t *>(base + o.fail);
         G.slot_desc = reinterpret_cast<EngFrame *>(base + o.desc);
@@ -1097,9 +1117,8 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
         G.move_dst = reinterpret_cast<int32_t *>(base + o.mdst);
         e->hg.push_back(G);
         // every slot starts empty, with defined message state
-        if ((err = hipMemsetAsync(base + o.lch, 0, o.q - o.lch, e->stream)) != hipSuccess ||
-            (err = hipMemsetAsync(G.slot_q, 0xff, size_t(G.S) * 4, e->stream)) != hipSuccess ||
-            (err = hipMemsetAsync(G.slot_t, 0, size_t(G.S) * 4, e->stream)) != hipSuccess ||
+        if ((err = hipMemsetAsync(base + o.lch, 0, o.t - o.lch, e->stream)) != hipSuccess ||
+            (err = hipMemsetAsync(G.slot_t, 0xff, size_t(G.S) * 4, e->stream)) != hipSuccess ||
             (err = hipMemsetAsync(G.fail, 0, size_t(G.S) * 4, e->stream)) != hipSuccess)
             return hip_fail(e, "ldpc_engine_create: hipMemsetAsync", err);
     }

@@ -44,7 +44,7 @@ extern "C" const char *ldpc_status_str(ldpc_status s) {
 
 static void free_device(ldpc_graph *g) {
     int32_t **ptrs[] = {&g->d_row_ptr, &g->d_col_idx, &g->d_col_ptr, &g->d_csc_to_csr,
-                        &g->d_class_rows, &g->d_hub_chunk_base};
+                        &g->d_class_rows, &g->d_hub_chunk_base, &g->d_class_rd};
     for (int32_t **p : ptrs) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
@@ -55,7 +55,8 @@ static ldpc_status upload(ldpc_graph *g) {
     struct Item { int32_t **dst; const std::vector<int32_t> *src; };
     Item items[] = {{&g->d_row_ptr, &g->row_ptr}, {&g->d_col_idx, &g->col_idx},
                     {&g->d_col_ptr, &g->col_ptr}, {&g->d_csc_to_csr, &g->csc_to_csr},
-                    {&g->d_class_rows, &g->class_rows}, {&g->d_hub_chunk_base, &g->hub_chunk_base}};
+                    {&g->d_class_rows, &g->class_rows}, {&g->d_hub_chunk_base, &g->hub_chunk_base},
+                    {&g->d_class_rd, &g->class_rd}};
     if (hipGetDevice(&g->device) != hipSuccess) {
         set_error("ldpc_graph_create: no HIP device is available");
         (void)hipGetLastError();
@@ -163,6 +164,12 @@ extern "C" ldpc_status ldpc_graph_create(int32_t m, int32_t n, int64_t nnz, cons
         for (int c = 0; c < ldpc::kNumClasses; c++) {
             g->class_rows.insert(g->class_rows.end(), per_class[c].begin(), per_class[c].end());
             g->class_begin[c + 1] = static_cast<int32_t>(g->class_rows.size());
+        }
+        // row descriptors in class order: one load gives a row's first edge and degree
+        g->class_rd.reserve(2 * g->class_rows.size());
+        for (int32_t r : g->class_rows) {
+            g->class_rd.push_back(g->row_ptr[r]);
+            g->class_rd.push_back(g->row_ptr[r + 1] - g->row_ptr[r]);
         }
         g->hub_chunk_base.assign(1, 0);
         for (int32_t r : per_class[ldpc::kClassHub]) {

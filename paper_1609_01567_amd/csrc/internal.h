@@ -47,6 +47,7 @@ struct ldpc_graph {
 
     // Check rows listed by class (rows of degree 0 are in no class).
     std::vector<int32_t> class_rows;                 // concatenated, class by class
+    std::vector<int32_t> class_rd;                   // per class row: first edge, degree (pairs, class order)
     int32_t class_begin[ldpc::kNumClasses + 1] = {0};
     // Segmented path: first chunk index of each hub row (in class order) and total chunks.
     std::vector<int32_t> hub_chunk_base;             // [#hub rows + 1]
@@ -55,6 +56,6 @@ struct ldpc_graph {
     // Device copies.
     int32_t *d_row_ptr = nullptr, *d_col_idx = nullptr;
     int32_t *d_col_ptr = nullptr, *d_csc_to_csr = nullptr;
-    int32_t *d_class_rows = nullptr, *d_hub_chunk_base = nullptr;
+    int32_t *d_class_rows = nullptr, *d_hub_chunk_base = nullptr, *d_class_rd = nullptr;
     int64_t device_bytes = 0;
 };

@@ -111,6 +111,7 @@ __global__ __launch_bounds__(256) void check_rows_kernel(
     SlotSrc<V> src;
 #pragma unroll
     for (int k = 0; k < V; k++) src.alt[k] = false;
+    src.any = false;
     int syn[V];
 #pragma unroll
     for (int k = 0; k < V; k++) syn[k] = 0;
@@ -159,6 +160,7 @@ __global__ __launch_bounds__(256) void check_chunk_kernel(
     SlotSrc<V> src;
 #pragma unroll
     for (int k = 0; k < V; k++) src.alt[k] = false;
+    src.any = false;
     const bool mine = work && lane_active;
     float u[C][V], suf[C][V], agg[V];
     uint32_t neg[V];

@@ -130,12 +130,15 @@ __device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_rea
 //   kInSteady  every slot past its first iteration: L is the posterior, R_old
 //              is read;
 //   kInMixed   as kInSteady, except slots with SlotSrc::alt set, which are in
-//              their first iteration (channel LLR, previous message 0).
+//              their first iteration (channel LLR, previous message 0); the
+//              channel loads are issued only in lanes that hold such a slot
+//              (SlotSrc::any), so the common case pays one branch.
 enum Inputs { kInFirst = 0, kInSteady = 1, kInMixed = 2 };
 
 template <int V>
 struct SlotSrc {
     bool alt[V];
+    bool any;   // some alt[k] is set
 };
 
 // Inputs of edges j0 .. j0+count-1 (1 <= count <= C) for the lane's slots:
@@ -170,7 +173,7 @@ __device__ __forceinline__ void gather_edges(const int32_t *__restrict__ col_idx
             for (int k = 0; k < V; k++) r[j][k] = 0.f;
         }
     }
-    if (IN == kInMixed) {
+    if (IN == kInMixed && src.any) {
 #pragma unroll
         for (int j = 0; j < C; j++) {
             float lc[V];

@@ -125,7 +125,6 @@ struct EngLane {
     int32_t t[V];
     bool syn_on[V];
     bool active;
-    bool any_alt;
     SlotSrc<V> src;
 };
 
@@ -133,14 +132,14 @@ template <int V>
 __device__ __forceinline__ void eng_lane(const EngGraph &G, int s0, int32_t T, int32_t early, EngLane<V> &ln) {
     load_i32<V>(G.slot_t + s0, ln.t);
     ln.active = false;
-    ln.any_alt = false;
+    ln.src.any = false;
 #pragma unroll
     for (int k = 0; k < V; k++) {
         const bool act = ln.t[k] >= 0;
         ln.src.alt[k] = ln.t[k] == 0;
         ln.syn_on[k] = ln.t[k] >= 1 && (early || ln.t[k] == T);
         ln.active |= act;
-        ln.any_alt |= ln.src.alt[k];
+        ln.src.any |= ln.src.alt[k];
     }
 }
 
@@ -189,6 +188,10 @@ __device__ __forceinline__ void build_work(const EngGraph *__restrict__ graphs, 
     __syncthreads();
 }
 
+// Values read from the work table are the same in every lane; callers pass them
+// through wave_uniform so that the compiler keeps the item's indices in scalar
+// registers (LDS reads are otherwise treated as per-lane, which turns every
+// index load of the item into a vector load).
 __device__ __forceinline__ int work_graph(const Work &w, int32_t ngraphs, int x) {
     int c = 0;
     while (c + 1 < ngraphs && x >= w.p[c + 1]) c++;
@@ -197,60 +200,51 @@ __device__ __forceinline__ int work_graph(const Work &w, int32_t ngraphs, int x)
 
 // Rows of up to DMAX edges: one wavefront per (row, slot group), looping over
 // the items of the pass.
+// One (row, slots) item of the register-row classes.  UNIFORM: every lane works
+// on row rk (a scalar), so the row descriptor and the column indices come in
+// through scalar loads issued before the slot state is examined; otherwise
+// each lane has its own row (packed items).
+template <int M, int V, int DMAX, bool UNIFORM>
+__device__ __forceinline__ void rows_item(const EngGraph &G, int cls, int nrows, int rk, int s0, int32_t T,
+                                          int32_t early) {
+    using MT = typename Codec<M>::T;
+    if (!UNIFORM && rk >= nrows) return;
+    const u32x2 rdv = cload(reinterpret_cast<const u32x2 *>(G.class_rd) + G.class_begin[cls] + rk);
+    EngLane<V> ln;
+    eng_lane<V>(G, s0, T, early, ln);
+    if (!ln.active) return;
+    const int e0 = UNIFORM ? wave_uniform(int(rdv.x)) : int(rdv.x);
+    const int d = UNIFORM ? wave_uniform(int(rdv.y)) : int(rdv.y);
+    int syn[V];
+#pragma unroll
+    for (int k = 0; k < V; k++) syn[k] = 0;
+    MT *R = static_cast<MT *>(G.r);
+    row_rule<M, V, DMAX, UNIFORM, kInMixed>(G.col_idx, e0, d, G.lpost, G.lch, R, G.S, s0, ln.src, syn);
+    eng_syndrome<V>(G, ln, syn, s0);
+}
+
 template <int M, int V, int DMAX, bool PACK = true>
 __global__ __launch_bounds__(256) void eng_check_rows(const EngGraph *__restrict__ graphs, int32_t ngraphs,
                                                       int32_t cls, int32_t T, int32_t early) {
-    using MT = typename Codec<M>::T;
     __shared__ Work w;
     build_work<PACK>(graphs, ngraphs, cls, 64 * V, 1, w);
     const int lane = threadIdx.x & 63;
-    const int total = w.p[ngraphs];
+    const int total = wave_uniform(w.p[ngraphs]);
     const int stride = int(gridDim.x * (blockDim.x >> 6));
     for (int item = wave_uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6); item < total; item += stride) {
-        const int c = work_graph(w, ngraphs, item);
+        const int c = wave_uniform(work_graph(w, ngraphs, item));
         const EngGraph &G = graphs[c];
-        const int local = item - w.p[c];
-        const int rpw = w.rpw[c];
+        const int local = item - wave_uniform(w.p[c]);
+        const int rpw = wave_uniform(w.rpw[c]);
         const int nrows = G.class_begin[cls + 1] - G.class_begin[cls];
-        int rk, s0;
         if (!PACK || rpw == 1) {
-            const int groups = w.groups[c];
-            rk = local / groups;
-            s0 = ((local - rk * groups) * 64 + lane) * V;
+            const int groups = wave_uniform(w.groups[c]);
+            const int rk = local / groups;
+            rows_item<M, V, DMAX, true>(G, cls, nrows, rk, ((local - rk * groups) * 64 + lane) * V, T, early);
         } else {
             const int lpr = 64 / rpw;
-            rk = local * rpw + lane / lpr;
-            s0 = (lane % lpr) * V;
+            rows_item<M, V, DMAX, false>(G, cls, nrows, local * rpw + lane / lpr, (lane % lpr) * V, T, early);
         }
-        EngLane<V> ln;
-        ln.active = false;
-        if (rk < nrows) eng_lane<V>(G, s0, T, early, ln);
-        if (!ln.active) continue;
-        int syn[V];
-#pragma unroll
-        for (int k = 0; k < V; k++) syn[k] = 0;
-        MT *R = static_cast<MT *>(G.r);
-        // slots in their first iteration are rare: the wavefront takes the
-        // per-slot input selection only when one of its lanes holds one
-        const bool mixed = __ballot(ln.any_alt) != 0;
-        if (!PACK || rpw == 1) {
-            const u32x2 rdv = cload(reinterpret_cast<const u32x2 *>(G.class_rd) + G.class_begin[cls] + rk);
-            const int e0 = wave_uniform(int(rdv.x));
-            const int d = wave_uniform(int(rdv.y));
-            if (mixed)
-                row_rule<M, V, DMAX, true, kInMixed>(G.col_idx, e0, d, G.lpost, G.lch, R, G.S, s0, ln.src, syn);
-            else
-                row_rule<M, V, DMAX, true, kInSteady>(G.col_idx, e0, d, G.lpost, G.lch, R, G.S, s0, ln.src, syn);
-        } else {
-            const u32x2 rdv = cload(reinterpret_cast<const u32x2 *>(G.class_rd) + G.class_begin[cls] + rk);
-            const int e0 = int(rdv.x);
-            const int d = int(rdv.y);
-            if (mixed)
-                row_rule<M, V, DMAX, false, kInMixed>(G.col_idx, e0, d, G.lpost, G.lch, R, G.S, s0, ln.src, syn);
-            else
-                row_rule<M, V, DMAX, false, kInSteady>(G.col_idx, e0, d, G.lpost, G.lch, R, G.S, s0, ln.src, syn);
-        }
-        eng_syndrome<V>(G, ln, syn, s0);
     }
 }
 
@@ -270,13 +264,13 @@ __global__ __launch_bounds__(256) void eng_check_chunk(const EngGraph *__restric
     const int wave = wave_uniform(threadIdx.x >> 6);
     const int lr = wave / WPR;
     const int wr = wave % WPR;
-    const int total = w.p[ngraphs];
+    const int total = wave_uniform(w.p[ngraphs]);
     for (int u = blockIdx.x; u < total; u += gridDim.x) {     // uniform over the workgroup
-        const int c = work_graph(w, ngraphs, u);
+        const int c = wave_uniform(work_graph(w, ngraphs, u));
         const EngGraph &G = graphs[c];
-        const int groups = w.groups[c];
+        const int groups = wave_uniform(w.groups[c]);
         const int nrows = G.class_begin[cls + 1] - G.class_begin[cls];
-        const int item = (u - w.p[c]) * RPB + lr;
+        const int item = (u - wave_uniform(w.p[c])) * RPB + lr;
         const bool valid = item < nrows * groups;                // uniform over the wavefront
         const int rk = valid ? item / groups : 0;
         const int g = valid ? item % groups : 0;
@@ -295,17 +289,13 @@ __global__ __launch_bounds__(256) void eng_check_chunk(const EngGraph *__restric
         MT *R = static_cast<MT *>(G.r);
         const int32_t S = G.S;
         const bool mine = work && ln.active;
-        const bool mixed = __ballot(ln.any_alt) != 0;   // uniform over the wavefront
         float u_[C][V], suf[C][V], agg[V];
         uint32_t neg[V];
         int syn[V];
         for (int ch = wr; ch < nch; ch += WPR) {
-            if (mine && mixed) {
+            if (mine) {
                 chunk_load<M, V, C, kInMixed>(G.col_idx, e0 + ch * C, min(C, d - ch * C), G.lpost, G.lch, R, S, s0,
                                               ln.src, u_, suf, agg, neg, syn);
-            } else if (mine) {
-                chunk_load<M, V, C, kInSteady>(G.col_idx, e0 + ch * C, min(C, d - ch * C), G.lpost, G.lch, R, S,
-                                               s0, ln.src, u_, suf, agg, neg, syn);
             } else {
 #pragma unroll
                 for (int k = 0; k < V; k++) { agg[k] = 0.f; neg[k] = 0u; syn[k] = 0; }
@@ -317,12 +307,9 @@ __global__ __launch_bounds__(256) void eng_check_chunk(const EngGraph *__restric
         __syncthreads();
         if (mine) {
             for (int ch = wr; ch < nch; ch += WPR) {
-                if (nch > WPR && mixed)
+                if (nch > WPR)
                     chunk_load<M, V, C, kInMixed>(G.col_idx, e0 + ch * C, min(C, d - ch * C), G.lpost, G.lch, R, S,
                                                   s0, ln.src, u_, suf, agg, neg, syn);
-                else if (nch > WPR)
-                    chunk_load<M, V, C, kInSteady>(G.col_idx, e0 + ch * C, min(C, d - ch * C), G.lpost, G.lch, R,
-                                                   S, s0, ln.src, u_, suf, agg, neg, syn);
                 float pre_a[V], post_a[V];
                 uint32_t parity[V];
                 int syn_row[V];
@@ -349,13 +336,13 @@ __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict_
     const int lane = threadIdx.x & 63;
     const int wv = wave_uniform(threadIdx.x >> 6);
     const int nw = blockDim.x >> 6;
-    const int total = w.p[ngraphs];
+    const int total = wave_uniform(w.p[ngraphs]);
     for (int u = blockIdx.x; u < total; u += gridDim.x) {     // uniform over the workgroup
-        const int c = work_graph(w, ngraphs, u);
+        const int c = wave_uniform(work_graph(w, ngraphs, u));
         const EngGraph &G = graphs[c];
         const int32_t S = G.S;
-        const int groups = w.groups[c];
-        const int local = u - w.p[c];
+        const int groups = wave_uniform(w.groups[c]);
+        const int local = u - wave_uniform(w.p[c]);
         const int g = local % groups;
         const int rk = local / groups;
         const int s = g * 64 + lane;
@@ -501,15 +488,15 @@ __global__ __launch_bounds__(256) void eng_bit(const EngGraph *__restrict__ grap
     __shared__ Work w;
     build_work<true>(graphs, ngraphs, kBitItems, 64 * V, 1, w);
     const int lane = threadIdx.x & 63;
-    const int total = w.p[ngraphs];
+    const int total = wave_uniform(w.p[ngraphs]);
     const int stride = int(gridDim.x * (blockDim.x >> 6));
     for (int item = wave_uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6); item < total; item += stride) {
-        const int c = work_graph(w, ngraphs, item);
+        const int c = wave_uniform(work_graph(w, ngraphs, item));
         const EngGraph &G = graphs[c];
-        const int local = item - w.p[c];
-        const int rpw = w.rpw[c];
+        const int local = item - wave_uniform(w.p[c]);
+        const int rpw = wave_uniform(w.rpw[c]);
         if (rpw == 1) {
-            const int groups = w.groups[c];
+            const int groups = wave_uniform(w.groups[c]);
             const int v = local / groups;
             bit_item<M, V, true>(G, v, ((local - v * groups) * 64 + lane) * V, T, early);
         } else {
@@ -830,6 +817,7 @@ struct ldpc_engine {
     bool early = true;
     bool repack = true;
     bool pack = true;        // packed row items for nearly drained pools
+    bool direct = false;     // enqueue each step's kernels instead of replaying the captured graph
     std::vector<const ldpc_graph *> graphs;
     std::vector<int32_t> S, cap;
     std::vector<EngGraph> hg;
@@ -1043,6 +1031,7 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
     e->K = K;
     e->repack = repack;
     if (const char *v = std::getenv("LDPC_ENGINE_NO_PACK")) e->pack = v[0] != '1';
+    if (const char *v = std::getenv("LDPC_ENGINE_DIRECT")) e->direct = v[0] == '1';
     e->graphs.assign(graphs, graphs + ngraphs);
     const int32_t unit = 64 * V;
     const size_t msg_bytes = e->msg == kF32 ? 4 : 2;
@@ -1296,7 +1285,13 @@ fail:
 extern "C" ldpc_status ldpc_engine_step(ldpc_engine *e, int32_t replays) {
     if (!e || replays < 0) { set_error("ldpc_engine_step: bad argument"); return LDPC_E_INVAL; }
     for (int32_t i = 0; i < replays; i++) {
-        hipError_t err = hipGraphLaunch(e->exec, e->stream);
+        hipError_t err;
+        if (e->direct) {
+            enqueue_steps(e, e->K);
+            err = hipGetLastError();
+        } else {
+            err = hipGraphLaunch(e->exec, e->stream);
+        }
         if (err == hipSuccess) {
             // counters of this replay, for capacity checks that must not wait
             const int p = e->parity;

@@ -116,7 +116,7 @@ __global__ __launch_bounds__(256) void check_rows_kernel(
 #pragma unroll
     for (int k = 0; k < V; k++) syn[k] = 0;
     constexpr int IN = MODE == kIter ? kInSteady : kInFirst;
-    row_rule<M, V, DMAX, true, IN>(col_idx, e0, d, L, nullptr, R, S, s0, src, syn);
+    row_rule<M, V, DMAX, true, IN>(col_idx, e0, d, L, R, S, s0, src, syn);
     if (MODE == kIter) plain_syndrome<V>(st, syn, fail, s0, syn_iter);
 }
 
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(256) void check_chunk_kernel(
     int syn[V];
     for (int ch = wr; ch < nch; ch += WPR) {
         if (mine) {
-            chunk_load<M, V, C, kChunkIn>(col_idx, e0 + ch * C, min(C, d - ch * C), L, nullptr, R, S, s0, src, u,
+            chunk_load<M, V, C, kChunkIn>(col_idx, e0 + ch * C, min(C, d - ch * C), L, R, S, s0, src, u,
                                           suf, agg, neg, syn);
         } else {
 #pragma unroll
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(256) void check_chunk_kernel(
     if (!mine) return;
     for (int ch = wr; ch < nch; ch += WPR) {
         if (nch > WPR)
-            chunk_load<M, V, C, kChunkIn>(col_idx, e0 + ch * C, min(C, d - ch * C), L, nullptr, R, S, s0, src, u,
+            chunk_load<M, V, C, kChunkIn>(col_idx, e0 + ch * C, min(C, d - ch * C), L, R, S, s0, src, u,
                                           suf, agg, neg, syn);
         float pre[V], post[V];
         uint32_t parity[V];

@@ -130,9 +130,9 @@ __device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_rea
 //   kInSteady  every slot past its first iteration: L is the posterior, R_old
 //              is read;
 //   kInMixed   as kInSteady, except slots with SlotSrc::alt set, which are in
-//              their first iteration (channel LLR, previous message 0); the
-//              channel loads are issued only in lanes that hold such a slot
-//              (SlotSrc::any), so the common case pays one branch.
+//              their first iteration: their previous messages count as 0 (the
+//              caller has placed the channel LLRs in their posterior entries),
+//              so the common case pays one branch per lane (SlotSrc::any).
 enum Inputs { kInFirst = 0, kInSteady = 1, kInMixed = 2 };
 
 template <int V>
@@ -151,7 +151,7 @@ struct SlotSrc {
 // wavefront).
 template <int M, int V, int C, bool UNIFORM, int IN>
 __device__ __forceinline__ void gather_edges(const int32_t *__restrict__ col_idx, int j0, int count,
-                                             const float *__restrict__ L, const float *__restrict__ Lalt,
+                                             const float *__restrict__ L,
                                              const typename Codec<M>::T *__restrict__ R, int32_t S, int s0,
                                              const SlotSrc<V> &src, float (&u)[C][V], uint32_t (&neg)[V],
                                              int (&syn)[V]) {
@@ -176,11 +176,9 @@ __device__ __forceinline__ void gather_edges(const int32_t *__restrict__ col_idx
     if (IN == kInMixed && src.any) {
 #pragma unroll
         for (int j = 0; j < C; j++) {
-            float lc[V];
-            load_vec<kF32, V>(Lalt + size_t(vix[j]) * S + s0, lc);
 #pragma unroll
             for (int k = 0; k < V; k++)
-                if (src.alt[k]) { lv[j][k] = lc[k]; r[j][k] = 0.f; }
+                if (src.alt[k]) r[j][k] = 0.f;
         }
     }
 #pragma unroll
@@ -203,7 +201,7 @@ __device__ __forceinline__ void gather_edges(const int32_t *__restrict__ col_idx
 // once per wavefront); otherwise each lane walks its own row.
 template <int M, int V, int DMAX, bool UNIFORM, int IN>
 __device__ __forceinline__ void row_rule(const int32_t *__restrict__ col_idx, int e0, int d,
-                                         const float *__restrict__ L, const float *__restrict__ Lalt,
+                                         const float *__restrict__ L,
                                          typename Codec<M>::T *__restrict__ R, int32_t S, int s0,
                                          const SlotSrc<V> &src, int (&syn)[V]) {
     float u[DMAX][V];
@@ -211,7 +209,7 @@ __device__ __forceinline__ void row_rule(const int32_t *__restrict__ col_idx, in
     uint32_t neg[V];
 #pragma unroll
     for (int k = 0; k < V; k++) neg[k] = 0u;
-    gather_edges<M, V, DMAX, UNIFORM, IN>(col_idx, e0, d, L, Lalt, R, S, s0, src, u, neg, syn);
+    gather_edges<M, V, DMAX, UNIFORM, IN>(col_idx, e0, d, L, R, S, s0, src, u, neg, syn);
     float run[V];
 #pragma unroll
     for (int k = 0; k < V; k++) run[k] = 0.f;
@@ -283,13 +281,13 @@ constexpr int kRowChunk = 8;
 
 template <int M, int V, int C, int IN>
 __device__ __forceinline__ void chunk_load(const int32_t *__restrict__ col_idx, int j0, int dc,
-                                           const float *__restrict__ L, const float *__restrict__ Lalt,
+                                           const float *__restrict__ L,
                                            const typename Codec<M>::T *__restrict__ R, int32_t S, int s0,
                                            const SlotSrc<V> &src, float (&u)[C][V], float (&suf)[C][V],
                                            float (&agg)[V], uint32_t (&neg)[V], int (&syn)[V]) {
 #pragma unroll
     for (int k = 0; k < V; k++) { neg[k] = 0u; syn[k] = 0; }
-    gather_edges<M, V, C, true, IN>(col_idx, j0, dc, L, Lalt, R, S, s0, src, u, neg, syn);
+    gather_edges<M, V, C, true, IN>(col_idx, j0, dc, L, R, S, s0, src, u, neg, syn);
 #pragma unroll
     for (int k = 0; k < V; k++) agg[k] = 0.f;
 #pragma unroll

@@ -167,7 +167,13 @@ struct Work {
 constexpr int kMaxPack = 16;
 constexpr int kBitItems = -1;   // `cls` value for the bit pass: items are bits
 
-template <bool PACK = false>
+// PM (packing mode): kPackNone counts every graph unpacked; kPackAll packs the
+// graphs whose extent allows it; kPackOnlyFlat / kPackOnlyPacked keep only the
+// graphs that kPackAll leaves unpacked / packs (two launches, one lean kernel
+// body each).
+enum PackMode { kPackNone = 0, kPackAll = 1, kPackOnlyFlat = 2, kPackOnlyPacked = 3 };
+
+template <int PM = kPackNone>
 __device__ __forceinline__ void build_work(const EngGraph *__restrict__ graphs, int32_t ngraphs, int cls,
                                            int unit, int per, Work &w) {
     if (threadIdx.x == 0) {
@@ -178,11 +184,12 @@ __device__ __forceinline__ void build_work(const EngGraph *__restrict__ graphs, 
             const int32_t gr = (x + unit - 1) / unit;
             const int32_t units = cls == kBitItems ? G.n : G.class_begin[cls + 1] - G.class_begin[cls];
             int32_t rpw = 1;
-            if (PACK && x > 0)
+            if (PM != kPackNone && x > 0)
                 while (rpw < kMaxPack && (unit / (2 * rpw)) >= x) rpw *= 2;   // unit = 64 V slots per wavefront
+            const bool take = PM == kPackNone || PM == kPackAll || (PM == kPackOnlyFlat) == (rpw == 1);
             w.groups[c] = gr;
             w.rpw[c] = rpw;
-            w.p[c + 1] = w.p[c] + (rpw > 1 ? (units + rpw - 1) / rpw : (units * gr + per - 1) / per);
+            w.p[c + 1] = w.p[c] + (!take ? 0 : rpw > 1 ? (units + rpw - 1) / rpw : (units * gr + per - 1) / per);
         }
     }
     __syncthreads();
@@ -219,15 +226,15 @@ __device__ __forceinline__ void rows_item(const EngGraph &G, int cls, int nrows,
 #pragma unroll
     for (int k = 0; k < V; k++) syn[k] = 0;
     MT *R = static_cast<MT *>(G.r);
-    row_rule<M, V, DMAX, UNIFORM, kInMixed>(G.col_idx, e0, d, G.lpost, G.lch, R, G.S, s0, ln.src, syn);
+    row_rule<M, V, DMAX, UNIFORM, kInMixed>(G.col_idx, e0, d, G.lpost, R, G.S, s0, ln.src, syn);
     eng_syndrome<V>(G, ln, syn, s0);
 }
 
-template <int M, int V, int DMAX, bool PACK = true>
+template <int M, int V, int DMAX, int PM>
 __global__ __launch_bounds__(256) void eng_check_rows(const EngGraph *__restrict__ graphs, int32_t ngraphs,
                                                       int32_t cls, int32_t T, int32_t early) {
     __shared__ Work w;
-    build_work<PACK>(graphs, ngraphs, cls, 64 * V, 1, w);
+    build_work<PM>(graphs, ngraphs, cls, 64 * V, 1, w);
     const int lane = threadIdx.x & 63;
     const int total = wave_uniform(w.p[ngraphs]);
     const int stride = int(gridDim.x * (blockDim.x >> 6));
@@ -237,7 +244,7 @@ __global__ __launch_bounds__(256) void eng_check_rows(const EngGraph *__restrict
         const int local = item - wave_uniform(w.p[c]);
         const int rpw = wave_uniform(w.rpw[c]);
         const int nrows = G.class_begin[cls + 1] - G.class_begin[cls];
-        if (!PACK || rpw == 1) {
+        if (PM == kPackNone || PM == kPackOnlyFlat || (PM == kPackAll && rpw == 1)) {
             const int groups = wave_uniform(w.groups[c]);
             const int rk = local / groups;
             rows_item<M, V, DMAX, true>(G, cls, nrows, rk, ((local - rk * groups) * 64 + lane) * V, T, early);
@@ -294,7 +301,7 @@ __global__ __launch_bounds__(256) void eng_check_chunk(const EngGraph *__restric
         int syn[V];
         for (int ch = wr; ch < nch; ch += WPR) {
             if (mine) {
-                chunk_load<M, V, C, kInMixed>(G.col_idx, e0 + ch * C, min(C, d - ch * C), G.lpost, G.lch, R, S, s0,
+                chunk_load<M, V, C, kInMixed>(G.col_idx, e0 + ch * C, min(C, d - ch * C), G.lpost, R, S, s0,
                                               ln.src, u_, suf, agg, neg, syn);
             } else {
 #pragma unroll
@@ -308,7 +315,7 @@ __global__ __launch_bounds__(256) void eng_check_chunk(const EngGraph *__restric
         if (mine) {
             for (int ch = wr; ch < nch; ch += WPR) {
                 if (nch > WPR)
-                    chunk_load<M, V, C, kInMixed>(G.col_idx, e0 + ch * C, min(C, d - ch * C), G.lpost, G.lch, R, S,
+                    chunk_load<M, V, C, kInMixed>(G.col_idx, e0 + ch * C, min(C, d - ch * C), G.lpost, R, S,
                                                   s0, ln.src, u_, suf, agg, neg, syn);
                 float pre_a[V], post_a[V];
                 uint32_t parity[V];
@@ -358,7 +365,7 @@ __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict_
         const int nch = (d + C - 1) / C;
         const int cb = wave_uniform(cload(G.hub_chunk_base + (rk)));
         auto R = gmem(static_cast<MT *>(G.r));
-        auto L = gmem(first ? G.lch : G.lpost);
+        auto L = gmem(G.lpost);   // holds the channel LLRs in a frame's first pass
 
         for (int ch = wv; ch < nch; ch += nw) {
             const int j0 = e0 + ch * C;
@@ -486,7 +493,7 @@ __global__ __launch_bounds__(256) void eng_bit(const EngGraph *__restrict__ grap
         *gmem(H.list_count) = 0;
     }
     __shared__ Work w;
-    build_work<true>(graphs, ngraphs, kBitItems, 64 * V, 1, w);
+    build_work<kPackAll>(graphs, ngraphs, kBitItems, 64 * V, 1, w);
     const int lane = threadIdx.x & 63;
     const int total = wave_uniform(w.p[ngraphs]);
     const int stride = int(gridDim.x * (blockDim.x >> 6));
@@ -650,10 +657,15 @@ __global__ __launch_bounds__(256) void eng_turnover(const EngGraph *__restrict__
                 if (v < n && src) tile[l][k] = gmem(src)[v];
             }
             __syncthreads();
-            // tile -> channel rows of the slots
+            // tile -> channel rows of the slots; the posterior entries start as
+            // the channel LLRs, which the slot's first check pass reads
             for (int k = r; k < kTile; k += 4) {
                 const int v = v0 + k;
-                if (v < n && src_of[l]) gmem(G.lch)[size_t(v) * S + slot_of[l]] = tile[k][l];
+                if (v < n && src_of[l]) {
+                    const size_t at = size_t(v) * S + slot_of[l];
+                    gmem(G.lch)[at] = tile[k][l];
+                    gmem(G.lpost)[at] = tile[k][l];
+                }
             }
         }
         __syncthreads();   // the tile and entry tables are reused by the next item
@@ -839,6 +851,7 @@ struct ldpc_engine {
     bool has_rows[3] = {false, false, false}, has_hub = false;
     int64_t bit_waves = 0, hub_blocks = 0, total_slots = 0, row_waves[3] = {0, 0, 0};   // with every slot occupied
     unsigned grid_rows[3] = {1, 1, 1}, grid_hub = 1, grid_bit = 1;   // workgroups per launch (grid-stride)
+    unsigned grid_packed = 256;      // packed row items: few rows per graph once drained
 };
 
 namespace {
@@ -847,27 +860,31 @@ using ldpc::set_error;
 
 size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Register-row class `cls`: unpacked items in one launch and, when packing is
+// on, packed items in a second one, so neither kernel carries the other's body.
+template <int M, int V, int DMAX>
+void launch_rows(ldpc_engine *e, int cls, unsigned grid) {
+    const int32_t early = e->early ? 1 : 0;
+    if (e->pack) {
+        hipLaunchKernelGGL((eng_check_rows<M, V, DMAX, kPackOnlyFlat>), dim3(grid), dim3(256), 0, e->stream,
+                           e->d_graphs, e->ngraphs, int32_t(cls), e->T, early);
+        hipLaunchKernelGGL((eng_check_rows<M, V, DMAX, kPackOnlyPacked>), dim3(e->grid_packed), dim3(256), 0,
+                           e->stream, e->d_graphs, e->ngraphs, int32_t(cls), e->T, early);
+    } else {
+        hipLaunchKernelGGL((eng_check_rows<M, V, DMAX, kPackNone>), dim3(grid), dim3(256), 0, e->stream, e->d_graphs,
+                           e->ngraphs, int32_t(cls), e->T, early);
+    }
+}
+
 template <int M, int V>
 void enqueue_step(ldpc_engine *e) {
     hipStream_t st = e->stream;
     const int32_t early = e->early ? 1 : 0;
     const int32_t ng = e->ngraphs;
     if (e->has_rows[0])
-        if (e->pack)
-            hipLaunchKernelGGL((eng_check_rows<M, V, 8, true>), dim3(e->grid_rows[0]), dim3(256), 0, st, e->d_graphs, ng,
-                               int32_t(ldpc::kClassD8), e->T, early);
-        else
-            hipLaunchKernelGGL((eng_check_rows<M, V, 8, false>), dim3(e->grid_rows[0]), dim3(256), 0, st, e->d_graphs,
-                               ng, int32_t(ldpc::kClassD8), e->T, early);
+        launch_rows<M, V, 8>(e, ldpc::kClassD8, e->grid_rows[0]);
     if (e->has_rows[1])
-        if (e->pack)
-            hipLaunchKernelGGL((eng_check_rows<M, ldpc::class_lane_slots(ldpc::kClassD16, V), 16, true>),
-                               dim3(e->grid_rows[1]), dim3(256), 0, st, e->d_graphs, ng, int32_t(ldpc::kClassD16), e->T,
-                               early);
-        else
-            hipLaunchKernelGGL((eng_check_rows<M, ldpc::class_lane_slots(ldpc::kClassD16, V), 16, false>),
-                               dim3(e->grid_rows[1]), dim3(256), 0, st, e->d_graphs, ng, int32_t(ldpc::kClassD16), e->T,
-                               early);
+        launch_rows<M, ldpc::class_lane_slots(ldpc::kClassD16, V), 16>(e, ldpc::kClassD16, e->grid_rows[1]);
     if (e->has_rows[2])
         hipLaunchKernelGGL((eng_check_chunk<M, V, ldpc::class_waves_per_row(ldpc::kClassD128)>),
                            dim3(e->grid_rows[2]), dim3(256), 0, st, e->d_graphs, ng, int32_t(ldpc::kClassD128), e->T,
@@ -925,13 +942,17 @@ void size_grids(ldpc_engine *e, int cus) {
         }
         if (const char *v = std::getenv("LDPC_ENGINE_BLOCKS_PER_CU")) {
             const int b = std::atoi(v);
-            if (b >= 1 && b <= 32) per_cu = b;
+            if (b >= 1 && b <= 1024) per_cu = b;
         }
         return unsigned(std::max<int64_t>(1, std::min<int64_t>(need, int64_t(per_cu) * cus * grid_factor())));
     };
-    e->grid_rows[0] = fit(reinterpret_cast<const void *>(&eng_check_rows<M, V, 8>), (e->row_waves[0] + 3) / 4);
-    e->grid_rows[1] = fit(reinterpret_cast<const void *>(&eng_check_rows<M, ldpc::class_lane_slots(ldpc::kClassD16, V), 16>),
+    e->grid_rows[0] = fit(reinterpret_cast<const void *>(&eng_check_rows<M, V, 8, kPackOnlyFlat>),
+                          (e->row_waves[0] + 3) / 4);
+    e->grid_rows[1] = fit(reinterpret_cast<const void *>(&eng_check_rows<M, ldpc::class_lane_slots(ldpc::kClassD16, V), 16,
+                                                                         kPackOnlyFlat>),
                           (e->row_waves[1] + 3) / 4);
+    e->grid_packed = fit(reinterpret_cast<const void *>(&eng_check_rows<M, V, 8, kPackOnlyPacked>),
+                         std::max<int64_t>(1, (e->row_waves[0] + e->row_waves[1] + 3) / 4));
     e->grid_rows[2] = fit(reinterpret_cast<const void *>(&eng_check_chunk<M, V, ldpc::class_waves_per_row(ldpc::kClassD128)>),
                           e->row_waves[2]);
     e->grid_hub = fit(reinterpret_cast<const void *>(&eng_check_hub<M>), e->hub_blocks);

@@ -77,6 +77,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-simulate", action="store_true")
     ap.add_argument("--served-requests", type=int, default=20000,
                     help="counted requests per load point (after a 2 s warm-up)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -291,6 +292,35 @@ def bench_batched(torch, ldpc, steps, warmup, T=50):
                    "frames": int(pe_all.size)},
         "per_code": per_code,
     }
+
+
+def bench_simulate(torch, ldpc, code, points, frames=1024, calls=2, T=50, seed=2026):
+    """Monte-Carlo error-rate runs on the device (ldpc_simulate): all-zero
+    codeword, counter-based channel noise drawn on the GPU, decode, error
+    counts; frames/s and info Gbit/s include the noise generation."""
+    g = ldpc.Graph.from_code(code)
+    ws = ldpc.Workspace(ldpc.simulate_workspace_size(g, frames))
+    ldpc.simulate(g, frames, points[0], seed, T, workspace=ws)       # warm
+    torch.cuda.synchronize()
+    out = {"workload": f"n={code.n} m={code.m}, all-zero codeword, device noise (Philox4x32-10 + Box-Muller), "
+                       f"{frames * calls} frames per Eb/N0 point, max {T} iterations, fp32 messages", "points": []}
+    k = code.n - code.m
+    for i, eb in enumerate(points):
+        counts = torch.zeros(len(ldpc.SIM_FIELDS), dtype=torch.int64, device="cuda")
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for c in range(calls):
+            ldpc.simulate(g, frames, eb, seed + i, T, first_frame=c * frames, counts=counts, workspace=ws)
+        e.record()
+        torch.cuda.synchronize()
+        ms = s.elapsed_time(e)
+        r = ldpc.sim_counts(counts)
+        out["points"].append({"ebn0_db": eb, **r, "fer": r["frame_errors"] / r["frames"],
+                              "ber": r["bit_errors"] / (r["frames"] * code.n),
+                              "mean_iters": r["iterations"] / r["frames"],
+                              "frames_per_s": round(r["frames"] / (ms * 1e-3), 1),
+                              "gbits": round(r["frames"] * k / (ms * 1e-3) / 1e9, 4)})
+    return out
 
 
 def _mcnemar(b, c, N):
@@ -632,6 +662,11 @@ def main():
         served = bench_served(torch, ldpc, cap, args.served_requests)
         print(f"[bench] served done", file=sys.stderr, flush=True)
 
+    simulate = None
+    if not args.no_simulate:
+        simulate = bench_simulate(torch, ldpc, code, points)
+        print(f"[bench] simulate done", file=sys.stderr, flush=True)
+
     precision = None
     if not args.no_precision:
         precision = bench_precision(torch, ldpc)
@@ -670,6 +705,7 @@ def main():
         "batched": batched,
         "served": served,
         "precision": precision,
+        "simulate": simulate,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -189,6 +189,55 @@ LDPC_API ldpc_status ldpc_decode_profiled(const ldpc_graph *g, const float *llr_
                                           float *edge_ms);
 
 /* ------------------------------------------------------------------------
+ * Monte-Carlo error-rate runs on the device (the paper's error-rate
+ * simulation: channel, decode and error count, Sec. IV and V-A).
+ *
+ * Each frame sends the all-zero codeword over BPSK/AWGN: every bit is sent as
+ * +1 and receives y = 1 + sigma z, with sigma^2 = 1 / (2 R 10^(EbN0/10)) and
+ * the nominal rate R = (n - m)/n (Eqs. (3)-(4)); the decoder input is
+ * L = 2y / sigma^2.  The noise z comes from a counter-based generator, so a
+ * frame's noise depends only on (seed, frame index) and a run may be split
+ * over calls (first_frame) or repeated exactly:
+ *   Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+ *   easy as 1, 2, 3", SC 2011) with key = (seed & 0xffffffff, seed >> 32) and
+ *   counter = (q, f & 0xffffffff, f >> 32, 0) for bits 4q..4q+3 of global
+ *   frame f = first_frame + i; its outputs x0..x3 give uniforms
+ *   u = ((x >> 9) + 0.5) 2^-23, and the Box-Muller transform of (u0, u1)
+ *   gives z for bits 4q and 4q+1 (r cos(2 pi u1), r sin(2 pi u1) with
+ *   r = sqrt(-2 ln u0)), that of (u2, u3) bits 4q+2 and 4q+3.
+ * Frames are decoded exactly as by ldpc_decode with the same flags.  A
+ * frame's bit errors are the bits whose estimate is 1 (Lpost < 0); it is a
+ * frame error when that count is non-zero, and an undetected error when its
+ * estimate nevertheless passed the syndrome (a different codeword).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    uint64_t frames;        /* frames decoded */
+    uint64_t frame_errors;  /* frames whose estimate differs from the codeword sent */
+    uint64_t bit_errors;    /* code bits in error, summed over frames */
+    uint64_t undetected;    /* frame errors whose estimate passed the syndrome */
+    uint64_t iterations;    /* iteration counts, summed over frames */
+} ldpc_sim_counts;
+
+/* Workspace bytes ldpc_simulate needs for `frames` frames (0 for frames = 0). */
+LDPC_API ldpc_status ldpc_simulate_workspace_size(const ldpc_graph *g, int32_t frames, uint32_t flags,
+                                                  size_t *bytes);
+
+/*
+ * Draw `frames` frames (global indices first_frame .. first_frame+frames-1),
+ * decode them and add their counts to *counts.  Asynchronous on hip_stream.
+ *  counts     device pointer, added to atomically (zero it before a new run).
+ *  llr_out    device [frames][n] float (the channel LLRs drawn), or NULL.
+ *  workspace  device, 256-byte aligned, >= ldpc_simulate_workspace_size bytes.
+ * flags: those of ldpc_decode.  Errors: INVAL (NULL graph/counts/workspace,
+ * frames < 0, max_iter < 1, bad flags, n <= m, Eb/N0 not finite, small or
+ * misaligned workspace, wrong device), DEVICE (launch failure).
+ */
+LDPC_API ldpc_status ldpc_simulate(const ldpc_graph *g, int32_t frames, double ebn0_db, uint64_t seed,
+                                   uint64_t first_frame, int32_t max_iter, uint32_t flags,
+                                   ldpc_sim_counts *counts, float *llr_out, void *workspace,
+                                   size_t workspace_bytes, void *hip_stream);
+
+/* ------------------------------------------------------------------------
  * Batched decoding with continuous refill.
  *
  * An engine decodes frames of several codes (graphs) in one launch sequence.

@@ -21,10 +21,12 @@ from __future__ import annotations
 import dataclasses
 import numpy as np
 
+from .counter_noise import sim_channel_llr  # noqa: E402  (counter-based noise of Monte-Carlo runs)
+
 __all__ = [
     "Code", "socket_code", "ebn0_to_sigma2", "awgn_llr", "code_14_7",
     "tiny_code", "large_code", "extreme_code", "batch_codes", "BATCH_SPECS",
-    "tree_code", "spc_code", "path_code", "random_small_code",
+    "tree_code", "spc_code", "path_code", "random_small_code", "sim_channel_llr",
 ]
 
 

@@ -30,6 +30,8 @@
 // precision (D small) and weak ones full absolute precision.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include <algorithm>
 #include <cstdint>
 #include <string>
@@ -435,12 +437,127 @@ __global__ __launch_bounds__(256) void egress_kernel(const float *__restrict__ L
 
 // ------------------------------------------------------------------ driver
 
+// ------------------------------------------------------- Monte-Carlo runs
+
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC 2011): ten rounds, each two
+// 32x32 -> 64-bit products of counter words with fixed multipliers, mixed with
+// the other words and the round key; the key advances by two Weyl constants.
+__device__ __forceinline__ void philox4x32_10(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; r++) {
+        const uint64_t p0 = uint64_t(0xD2511F53u) * c[0];
+        const uint64_t p1 = uint64_t(0xCD9E8D57u) * c[2];
+        const uint32_t n0 = uint32_t(p1 >> 32) ^ c[1] ^ k0;
+        const uint32_t n2 = uint32_t(p0 >> 32) ^ c[3] ^ k1;
+        c[1] = uint32_t(p1);
+        c[3] = uint32_t(p0);
+        c[0] = n0;
+        c[2] = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// Uniform in (0, 1) from the top 23 bits (exact in FP32), then Box-Muller.
+__device__ __forceinline__ float unit_open(uint32_t x) { return (float(x >> 9) + 0.5f) * 0x1p-23f; }
+
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float &z0, float &z1) {
+    const float r = sqrtf(-2.f * logf(unit_open(a)));
+    float sn, cs;
+    sincospif(2.f * unit_open(b), &sn, &cs);
+    z0 = r * cs;
+    z1 = r * sn;
+}
+
+// Channel LLRs of the all-zero codeword over BPSK/AWGN, written straight into
+// the slot-major channel array: thread = frame slot, 4 bits per counter value
+// (L = k0 + k1 z with k0 = 2/sigma^2, k1 = 2/sigma).  Padding slots get 0.
+__global__ __launch_bounds__(256) void channel_kernel(float *__restrict__ Lch, int32_t S, int32_t F, int32_t n,
+                                                      uint32_t key0, uint32_t key1, uint64_t first_frame, float k0,
+                                                      float k1, float *__restrict__ llr_out) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    const int quads = (n + 3) / 4;
+    const uint64_t f = first_frame + uint64_t(s);
+    for (int q = blockIdx.y; q < quads; q += gridDim.y) {
+        float z[4] = {0.f, 0.f, 0.f, 0.f};
+        if (s < F) {
+            uint32_t c[4] = {uint32_t(q), uint32_t(f), uint32_t(f >> 32), 0u};
+            philox4x32_10(c, key0, key1);
+            box_muller(c[0], c[1], z[0], z[1]);
+            box_muller(c[2], c[3], z[2], z[3]);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int v = 4 * q + j;
+            if (v < n) {
+                const float L = s < F ? fmaf(k1, z[j], k0) : 0.f;
+                Lch[size_t(v) * S + s] = L;
+                if (llr_out && s < F) llr_out[size_t(s) * n + v] = L;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void zero_kernel(int32_t *__restrict__ x, int32_t count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) x[i] = 0;
+}
+
+// Bit errors of each frame's estimate against the all-zero codeword: bits whose
+// hard decision is 1 (Lpost < 0, Algorithm 6).  Thread = frame, 64 bits per
+// workgroup row; counts are added into err[frame].
+__global__ __launch_bounds__(256) void count_errors_kernel(const float *__restrict__ Lpost, int32_t S, int32_t F,
+                                                           int32_t n, int32_t *__restrict__ err) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= F) return;
+    for (int v0 = blockIdx.y * 64; v0 < n; v0 += gridDim.y * 64) {
+        const int v1 = min(n, v0 + 64);
+        int cnt = 0;
+        for (int v = v0; v < v1; v++) cnt += Lpost[size_t(v) * S + s] < 0.f;
+        if (cnt) atomicAdd(err + s, cnt);
+    }
+}
+
+// Per-frame results into the run's counts: one atomic per counter per workgroup.
+__global__ __launch_bounds__(256) void tally_kernel(const int32_t *__restrict__ err,
+                                                    const int32_t *__restrict__ iters,
+                                                    const uint8_t *__restrict__ ok, int32_t F,
+                                                    ldpc_sim_counts *__restrict__ out) {
+    __shared__ unsigned long long part[5][4];
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long v[5] = {0ull, 0ull, 0ull, 0ull, 0ull};
+    if (s < F) {
+        const int e = err[s];
+        v[0] = 1ull;
+        v[1] = e > 0;
+        v[2] = unsigned(e);
+        v[3] = e > 0 && ok[s];
+        v[4] = unsigned(iters[s]);
+    }
+#pragma unroll
+    for (int k = 0; k < 5; k++) {
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off);
+        if ((threadIdx.x & 63) == 0) part[k][threadIdx.x >> 6] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        const int k = threadIdx.x;
+        const unsigned long long sum = part[k][0] + part[k][1] + part[k][2] + part[k][3];
+        uint64_t *dst = k == 0 ? &out->frames : k == 1 ? &out->frame_errors : k == 2 ? &out->bit_errors
+                      : k == 3 ? &out->undetected : &out->iterations;
+        static_assert(sizeof(uint64_t) == sizeof(unsigned long long), "64-bit counters");
+        if (sum) atomicAdd(reinterpret_cast<unsigned long long *>(dst), sum);
+    }
+}
+
 struct Plan {
     int msg = kF32;
     int V = 1;
     int32_t S = 0;
     size_t off_lch = 0, off_lpost = 0, off_r = 0, off_iters = 0, off_fail = 0;
     size_t off_aggd = 0, off_aggpre = 0, off_aggbits = 0, total = 0;
+    size_t off_err = 0, off_it = 0, off_ok = 0;   // Monte-Carlo runs only
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -455,7 +572,7 @@ bool flags_ok(uint32_t flags) {
     return true;
 }
 
-Plan make_plan(const ldpc_graph *g, int32_t F, uint32_t flags) {
+Plan make_plan(const ldpc_graph *g, int32_t F, uint32_t flags, bool sim = false) {
     Plan p;
     p.msg = (flags & LDPC_MSG_FP16) ? kF16 : (flags & LDPC_MSG_BF16) ? kBF16 : kF32;
     if (flags & LDPC_LANE_SLOTS_1) p.V = 1;
@@ -475,6 +592,11 @@ Plan make_plan(const ldpc_graph *g, int32_t F, uint32_t flags) {
     p.off_aggd = off;    off = align256(off + size_t(g->hub_chunks) * S * 4);
     p.off_aggpre = off;  off = align256(off + size_t(g->hub_chunks) * S * 4);
     p.off_aggbits = off; off = align256(off + size_t(g->hub_chunks) * S * 4);
+    if (sim) {
+        p.off_err = off; off = align256(off + S * 4);
+        p.off_it = off;  off = align256(off + S * 4);
+        p.off_ok = off;  off = align256(off + S);
+    }
     p.total = off;
     return p;
 }
@@ -566,17 +688,38 @@ struct Marks {
     }
 };
 
+// A Monte-Carlo run (ldpc_simulate): the channel LLRs are drawn on the device
+// instead of read from llr_in, and the per-frame outputs are counted instead
+// of written out.
+struct SimRun {
+    bool on = false;
+    uint32_t key0 = 0, key1 = 0;
+    uint64_t first_frame = 0;
+    float k0 = 0.f, k1 = 0.f;
+    float *llr_out = nullptr;
+    int32_t *err = nullptr, *it = nullptr;
+    uint8_t *ok = nullptr;
+    ldpc_sim_counts *counts = nullptr;
+};
+
 template <int M, int V>
 void run_decode(const ldpc_graph *g, const Plan &p, const Bufs &b, const float *llr_in, int32_t F, int32_t T,
                 bool early_stop, uint8_t *bits, uint8_t *ok, int32_t *iters_out, float *llr_out, hipStream_t st,
-                const Marks &mk) {
+                const Marks &mk, const SimRun &sim = SimRun{}) {
     using MT = typename Codec<M>::T;
     const int32_t S = p.S;
     const int32_t groups = S / (64 * V);
     mk.mark(0, st);
     hipLaunchKernelGGL(init_state_kernel, dim3((S + 255) / 256), dim3(256), 0, st, b.iters, b.fail, F, S);
     const dim3 tgrid((g->n + 63) / 64, S / 64);
-    hipLaunchKernelGGL(ingest_kernel, tgrid, dim3(256), 0, st, llr_in, F, g->n, b.lch, S);
+    if (sim.on) {
+        const unsigned quads = unsigned(std::min(65535, (g->n + 3) / 4));
+        hipLaunchKernelGGL(channel_kernel, dim3(unsigned((S + 255) / 256), quads), dim3(256), 0, st, b.lch, S, F,
+                           g->n, sim.key0, sim.key1, sim.first_frame, sim.k0, sim.k1, sim.llr_out);
+        hipLaunchKernelGGL(zero_kernel, dim3(unsigned((S + 255) / 256)), dim3(256), 0, st, sim.err, S);
+    } else {
+        hipLaunchKernelGGL(ingest_kernel, tgrid, dim3(256), 0, st, llr_in, F, g->n, b.lch, S);
+    }
     mk.mark(1, st);
     const unsigned bit_blocks = blocks_for_waves(int64_t(g->n) * groups);
     for (int32_t t = 1; t <= T; t++) {
@@ -593,18 +736,30 @@ void run_decode(const ldpc_graph *g, const Plan &p, const Bufs &b, const float *
         hipLaunchKernelGGL((syndrome_kernel<V>), dim3(blocks_for_waves(int64_t(nrows) * groups)), dim3(256), 0, st,
                            g->d_class_rd, g->d_col_idx, nrows, b.lpost, b.iters, b.fail, S, groups, T);
     }
-    hipLaunchKernelGGL(finalize_kernel, dim3((F + 255) / 256), dim3(256), 0, st, b.iters, b.fail, F, T, iters_out, ok);
-    hipLaunchKernelGGL(egress_kernel, tgrid, dim3(256), 0, st, b.lpost, S, F, g->n, bits, llr_out);
+    if (sim.on) {
+        hipLaunchKernelGGL(finalize_kernel, dim3((F + 255) / 256), dim3(256), 0, st, b.iters, b.fail, F, T, sim.it,
+                           sim.ok);
+        const unsigned rows = unsigned(std::min(4096, (g->n + 63) / 64));
+        hipLaunchKernelGGL(count_errors_kernel, dim3(unsigned((F + 255) / 256), rows), dim3(256), 0, st, b.lpost, S, F,
+                           g->n, sim.err);
+        hipLaunchKernelGGL(tally_kernel, dim3(unsigned((F + 255) / 256)), dim3(256), 0, st, sim.err, sim.it, sim.ok, F,
+                           sim.counts);
+    } else {
+        hipLaunchKernelGGL(finalize_kernel, dim3((F + 255) / 256), dim3(256), 0, st, b.iters, b.fail, F, T, iters_out,
+                           ok);
+        hipLaunchKernelGGL(egress_kernel, tgrid, dim3(256), 0, st, b.lpost, S, F, g->n, bits, llr_out);
+    }
     mk.mark(2 * T + 2, st);
 }
 
 template <int M>
 void run_decode_v(const ldpc_graph *g, const Plan &p, const Bufs &b, const float *llr_in, int32_t F, int32_t T,
-                  bool es, uint8_t *bits, uint8_t *ok, int32_t *it, float *lo, hipStream_t st, const Marks &mk) {
+                  bool es, uint8_t *bits, uint8_t *ok, int32_t *it, float *lo, hipStream_t st, const Marks &mk,
+                  const SimRun &sim = SimRun{}) {
     switch (p.V) {
-        case 4: run_decode<M, 4>(g, p, b, llr_in, F, T, es, bits, ok, it, lo, st, mk); break;
-        case 2: run_decode<M, 2>(g, p, b, llr_in, F, T, es, bits, ok, it, lo, st, mk); break;
-        default: run_decode<M, 1>(g, p, b, llr_in, F, T, es, bits, ok, it, lo, st, mk); break;
+        case 4: run_decode<M, 4>(g, p, b, llr_in, F, T, es, bits, ok, it, lo, st, mk, sim); break;
+        case 2: run_decode<M, 2>(g, p, b, llr_in, F, T, es, bits, ok, it, lo, st, mk, sim); break;
+        default: run_decode<M, 1>(g, p, b, llr_in, F, T, es, bits, ok, it, lo, st, mk, sim); break;
     }
 }
 
@@ -621,6 +776,19 @@ extern "C" ldpc_status ldpc_decode_workspace_size(const ldpc_graph *g, int32_t f
 }
 
 namespace {
+
+Bufs bufs_at(char *ws, const Plan &p) {
+    Bufs b;
+    b.lch = reinterpret_cast<float *>(ws + p.off_lch);
+    b.lpost = reinterpret_cast<float *>(ws + p.off_lpost);
+    b.r = ws + p.off_r;
+    b.iters = reinterpret_cast<int32_t *>(ws + p.off_iters);
+    b.fail = reinterpret_cast<int32_t *>(ws + p.off_fail);
+    b.aggd = reinterpret_cast<float *>(ws + p.off_aggd);
+    b.aggpre = reinterpret_cast<float *>(ws + p.off_aggpre);
+    b.aggbits = reinterpret_cast<int32_t *>(ws + p.off_aggbits);
+    return b;
+}
 
 ldpc_status decode_core(const char *fn, const ldpc_graph *g, const float *llr_in, int32_t frames, int32_t max_iter,
                         uint32_t flags, uint8_t *bits_out, uint8_t *syndrome_ok, int32_t *iters, float *llr_out,
@@ -652,16 +820,7 @@ ldpc_status decode_core(const char *fn, const ldpc_graph *g, const float *llr_in
         set_error(f + ": the current device is not the graph's device");
         return LDPC_E_INVAL;
     }
-    char *ws = static_cast<char *>(workspace);
-    Bufs b;
-    b.lch = reinterpret_cast<float *>(ws + p.off_lch);
-    b.lpost = reinterpret_cast<float *>(ws + p.off_lpost);
-    b.r = ws + p.off_r;
-    b.iters = reinterpret_cast<int32_t *>(ws + p.off_iters);
-    b.fail = reinterpret_cast<int32_t *>(ws + p.off_fail);
-    b.aggd = reinterpret_cast<float *>(ws + p.off_aggd);
-    b.aggpre = reinterpret_cast<float *>(ws + p.off_aggpre);
-    b.aggbits = reinterpret_cast<int32_t *>(ws + p.off_aggbits);
+    const Bufs b = bufs_at(static_cast<char *>(workspace), p);
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     const bool es = !(flags & LDPC_NO_EARLY_STOP);
     (void)hipGetLastError();
@@ -731,4 +890,86 @@ extern "C" ldpc_status ldpc_decode_profiled(const ldpc_graph *g, const float *ll
     }
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     return stt;
+}
+
+extern "C" ldpc_status ldpc_simulate_workspace_size(const ldpc_graph *g, int32_t frames, uint32_t flags,
+                                                    size_t *bytes) {
+    if (!g || !bytes) { set_error("ldpc_simulate_workspace_size: NULL argument"); return LDPC_E_INVAL; }
+    if (frames < 0) { set_error("ldpc_simulate_workspace_size: frames < 0"); return LDPC_E_INVAL; }
+    if (!flags_ok(flags)) { set_error("ldpc_simulate_workspace_size: bad flags"); return LDPC_E_INVAL; }
+    *bytes = frames == 0 ? 0 : make_plan(g, frames, flags, true).total;
+    return LDPC_OK;
+}
+
+extern "C" ldpc_status ldpc_simulate(const ldpc_graph *g, int32_t frames, double ebn0_db, uint64_t seed,
+                                     uint64_t first_frame, int32_t max_iter, uint32_t flags,
+                                     ldpc_sim_counts *counts, float *llr_out, void *workspace,
+                                     size_t workspace_bytes, void *hip_stream) {
+    const std::string f("ldpc_simulate");
+    if (!g || !counts) { set_error(f + ": NULL graph or counts"); return LDPC_E_INVAL; }
+    if (g->host_only) { set_error(f + ": graph was built host-only"); return LDPC_E_INVAL; }
+    if (frames < 0) { set_error(f + ": frames < 0"); return LDPC_E_INVAL; }
+    if (max_iter < 1) { set_error(f + ": max_iter must be >= 1"); return LDPC_E_INVAL; }
+    if (!flags_ok(flags)) { set_error(f + ": bad flags"); return LDPC_E_INVAL; }
+    if (g->n <= g->m) { set_error(f + ": the nominal rate (n - m)/n must be positive"); return LDPC_E_INVAL; }
+    if (!std::isfinite(ebn0_db)) { set_error(f + ": Eb/N0 must be finite"); return LDPC_E_INVAL; }
+    if (frames == 0) return LDPC_OK;
+    if (!workspace) { set_error(f + ": NULL workspace"); return LDPC_E_INVAL; }
+    if (reinterpret_cast<uintptr_t>(workspace) & 255u) {
+        set_error(f + ": workspace must be 256-byte aligned");
+        return LDPC_E_INVAL;
+    }
+    const Plan p = make_plan(g, frames, flags, true);
+    if (workspace_bytes < p.total) {
+        set_error(f + ": workspace too small (" + std::to_string(workspace_bytes) + " < " + std::to_string(p.total) +
+                  ")");
+        return LDPC_E_INVAL;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != g->device) {
+        (void)hipGetLastError();
+        set_error(f + ": the current device is not the graph's device");
+        return LDPC_E_INVAL;
+    }
+    char *ws = static_cast<char *>(workspace);
+    const Bufs b = bufs_at(ws, p);
+    // sigma^2 = 1 / (2 R 10^(EbN0/10)) with the nominal rate R = (n - m)/n (Eqs. (3)-(4));
+    // L = 2y/sigma^2 = 2/sigma^2 + (2/sigma) z for y = 1 + sigma z
+    const double rate = double(g->n - g->m) / double(g->n);
+    const double sigma2 = 1.0 / (2.0 * rate * std::pow(10.0, ebn0_db / 10.0));
+    SimRun sim;
+    sim.on = true;
+    sim.key0 = uint32_t(seed);
+    sim.key1 = uint32_t(seed >> 32);
+    sim.first_frame = first_frame;
+    sim.k0 = float(2.0 / sigma2);
+    sim.k1 = float(2.0 / std::sqrt(sigma2));
+    sim.llr_out = llr_out;
+    sim.err = reinterpret_cast<int32_t *>(ws + p.off_err);
+    sim.it = reinterpret_cast<int32_t *>(ws + p.off_it);
+    sim.ok = reinterpret_cast<uint8_t *>(ws + p.off_ok);
+    sim.counts = counts;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const bool es = !(flags & LDPC_NO_EARLY_STOP);
+    (void)hipGetLastError();
+    switch (p.msg) {
+        case kF16:
+            run_decode_v<kF16>(g, p, b, nullptr, frames, max_iter, es, nullptr, nullptr, nullptr, nullptr, st, Marks{},
+                               sim);
+            break;
+        case kBF16:
+            run_decode_v<kBF16>(g, p, b, nullptr, frames, max_iter, es, nullptr, nullptr, nullptr, nullptr, st,
+                                Marks{}, sim);
+            break;
+        default:
+            run_decode_v<kF32>(g, p, b, nullptr, frames, max_iter, es, nullptr, nullptr, nullptr, nullptr, st, Marks{},
+                               sim);
+            break;
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error(f + ": launch failed: " + hipGetErrorString(e));
+        return LDPC_E_DEVICE;
+    }
+    return LDPC_OK;
 }

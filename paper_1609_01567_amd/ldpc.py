@@ -29,7 +29,8 @@ LANE_SLOTS_4 = 1 << 5
 GRAPH_HOST_ONLY = 1 << 0
 
 EXPORTED = ("ldpc_graph_create", "ldpc_graph_destroy", "ldpc_graph_info", "ldpc_graph_arrays",
-            "ldpc_decode_workspace_size", "ldpc_decode", "ldpc_decode_profiled", "ldpc_status_str",
+            "ldpc_decode_workspace_size", "ldpc_decode", "ldpc_decode_profiled", "ldpc_simulate_workspace_size",
+            "ldpc_simulate", "ldpc_status_str",
             "ldpc_last_error", "ldpc_engine_create", "ldpc_engine_destroy", "ldpc_engine_info",
             "ldpc_engine_submit", "ldpc_engine_capacity", "ldpc_engine_step", "ldpc_engine_poll",
             "ldpc_engine_run", "ldpc_engine_stream", "ldpc_engine_autotune", "ldpc_server_create", "ldpc_server_submit",
@@ -82,8 +83,12 @@ def load_library():
     lib.ldpc_decode_workspace_size.argtypes = [P, I32, U32, ctypes.POINTER(ctypes.c_size_t)]
     lib.ldpc_decode.argtypes = [P, P, I32, I32, U32, P, P, P, P, P, ctypes.c_size_t, P]
     lib.ldpc_decode_profiled.argtypes = [P, P, I32, I32, U32, P, P, P, P, P, ctypes.c_size_t, P, P, P, P]
+    lib.ldpc_simulate_workspace_size.argtypes = [P, I32, U32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.ldpc_simulate.argtypes = [P, I32, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64, I32, U32, P, P, P,
+                                  ctypes.c_size_t, P]
     for f in ("ldpc_graph_create", "ldpc_graph_destroy", "ldpc_graph_info", "ldpc_graph_arrays",
-              "ldpc_decode_workspace_size", "ldpc_decode", "ldpc_decode_profiled"):
+              "ldpc_decode_workspace_size", "ldpc_decode", "ldpc_decode_profiled", "ldpc_simulate_workspace_size",
+              "ldpc_simulate"):
         getattr(lib, f).restype = ctypes.c_int
     lib.ldpc_engine_create.argtypes = [P, I32, P, P, I32, U32, P, ctypes.POINTER(P)]
     lib.ldpc_engine_destroy.argtypes = [P]
@@ -263,6 +268,51 @@ def decode_profiled(graph: Graph, llr, max_iter: int, flags: int = 0, want_llr: 
                                            _np_ptr(bit_ms), _np_ptr(edge_ms)), "ldpc_decode_profiled")
     out._workspace = workspace
     return out, dict(check_ms=check_ms, bit_ms=bit_ms, edge_ms=edge_ms)
+
+
+SIM_FIELDS = ("frames", "frame_errors", "bit_errors", "undetected", "iterations")
+
+
+def simulate_workspace_size(graph: Graph, frames: int, flags: int = 0) -> int:
+    n = ctypes.c_size_t()
+    _check(graph._lib.ldpc_simulate_workspace_size(graph.handle, int(frames), int(flags), ctypes.byref(n)),
+           "ldpc_simulate_workspace_size")
+    return int(n.value)
+
+
+def simulate(graph: Graph, frames: int, ebn0_db: float, seed: int, max_iter: int, flags: int = 0,
+             first_frame: int = 0, counts=None, want_llr: bool = False, workspace: Workspace | None = None,
+             stream=None):
+    """Enqueue ldpc_simulate (all-zero codeword over BPSK/AWGN, noise drawn on the device).
+
+    `counts` is a CUDA int64 tensor of 5 counters (SIM_FIELDS), added to;
+    a zeroed one is made when None.  Returns (counts, llr or None); read them
+    after the stream reaches this point.
+    """
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if counts is None:
+        counts = torch.zeros(len(SIM_FIELDS), dtype=torch.int64, device=dev)
+    if counts.dtype != torch.int64 or not counts.is_cuda or counts.numel() != len(SIM_FIELDS):
+        raise ValueError("counts must be a CUDA int64 tensor of 5 counters")
+    llr = torch.empty((frames, graph.n), dtype=torch.float32, device=dev) if want_llr else None
+    need = simulate_workspace_size(graph, frames, flags)
+    if workspace is None or not workspace.fits(need):
+        workspace = Workspace(need, device=dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    _check(graph._lib.ldpc_simulate(graph.handle, int(frames), float(ebn0_db), int(seed) & (2 ** 64 - 1),
+                                    int(first_frame), int(max_iter), int(flags), ctypes.c_void_p(counts.data_ptr()),
+                                    ctypes.c_void_p(llr.data_ptr()) if llr is not None else None,
+                                    ctypes.c_void_p(workspace.ptr), ctypes.c_size_t(workspace.nbytes),
+                                    ctypes.c_void_p(stream.cuda_stream)), "ldpc_simulate")
+    counts._workspace = workspace   # keep the workspace alive until the stream has consumed it
+    return counts, llr
+
+
+def sim_counts(counts) -> dict:
+    """The 5 counters of a simulate() run as a dict (synchronizes on the tensor)."""
+    return dict(zip(SIM_FIELDS, (int(x) for x in counts.cpu().tolist())))
 
 
 class Engine:

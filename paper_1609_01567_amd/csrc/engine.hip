@@ -176,9 +176,12 @@ enum PackMode { kPackNone = 0, kPackAll = 1, kPackOnlyFlat = 2, kPackOnlyPacked 
 template <int PM = kPackNone>
 __device__ __forceinline__ void build_work(const EngGraph *__restrict__ graphs, int32_t ngraphs, int cls,
                                            int unit, int per, Work &w) {
-    if (threadIdx.x == 0) {
-        w.p[0] = 0;
-        for (int c = 0; c < ngraphs; c++) {
+    // wavefront 0, one lane per graph (at most 32): the graphs' extents load in
+    // parallel and an inclusive scan over the lanes gives the item offsets
+    if (threadIdx.x < 64) {
+        const int c = threadIdx.x;
+        int32_t items = 0;
+        if (c < ngraphs) {
             const EngGraph &G = graphs[c];
             const int32_t x = *gmem(G.extent);
             const int32_t gr = (x + unit - 1) / unit;
@@ -189,8 +192,14 @@ __device__ __forceinline__ void build_work(const EngGraph *__restrict__ graphs, 
             const bool take = PM == kPackNone || PM == kPackAll || (PM == kPackOnlyFlat) == (rpw == 1);
             w.groups[c] = gr;
             w.rpw[c] = rpw;
-            w.p[c + 1] = w.p[c] + (!take ? 0 : rpw > 1 ? (units + rpw - 1) / rpw : (units * gr + per - 1) / per);
+            items = !take ? 0 : rpw > 1 ? (units + rpw - 1) / rpw : (units * gr + per - 1) / per;
         }
+        for (int off = 1; off < 32; off <<= 1) {
+            const int32_t y = __shfl_up(items, off);
+            if (c >= off) items += y;
+        }
+        if (c == 0) w.p[0] = 0;
+        if (c < ngraphs) w.p[c + 1] = items;
     }
     __syncthreads();
 }

@@ -241,7 +241,8 @@ def bench_batched(torch, ldpc, steps, warmup, T=50):
         torch.cuda.synchronize()
         tune = ldpc.autotune(graphs, frame_lists, T, flags)
         eng = ldpc.Engine(graphs, tune["slots"], [len(fl) for fl in frame_lists], T, flags=flags,
-                          lane_slots=tune["lane_slots"], graph_steps=tune["graph_steps"])
+                          lane_slots=tune["lane_slots"], graph_steps=tune["graph_steps"],
+                          iters_per_step=tune["iters_per_step"])
 
         def one():
             for gi, fl in enumerate(frame_lists):

@@ -280,7 +280,11 @@ typedef struct {
     int32_t lane_slots;   /* frame slots per wavefront lane: 1, 2 or 4; 0 = 4 */
     int32_t graph_steps;  /* decode steps per captured hipGraph replay; 0 = 8 */
     int32_t no_compaction;/* 1: never repack frames into the low slots (see below); 0 = repack */
-    int32_t reserved[5];  /* must be 0 */
+    int32_t iters_per_step;/* decoder iterations per step (1..16; 0 = 1).  Stopped frames leave
+                             their slot, and queued frames enter, once per step, so more
+                             iterations per step spend fewer launches on that bookkeeping
+                             but keep finished frames in their slots longer */
+    int32_t reserved[4];  /* must be 0 */
 } ldpc_engine_opts;
 
 /*
@@ -291,7 +295,7 @@ typedef struct {
  *              of 64 * lane_slots).
  *  queue_cap   [ngraphs] queue capacity per graph (>= 1): frames submitted but not
  *              yet admitted to a slot.
- *  max_iter    >= 1; flags: LDPC_NO_EARLY_STOP, LDPC_MSG_FP16 / LDPC_MSG_BF16.
+ *  max_iter    1..2^30-1; flags: LDPC_NO_EARLY_STOP, LDPC_MSG_FP16 / LDPC_MSG_BF16.
  *  opts        may be NULL.
  * Errors: INVAL, NOMEM (device memory), DEVICE.
  */
@@ -348,8 +352,9 @@ LDPC_API ldpc_status ldpc_engine_run(ldpc_engine *e, int32_t max_replays, int64_
  * Autotuner for ldpc_engine_create: times the decode of the given frames with
  * candidate tile shapes and slot-pool sizes and returns the fastest.
  * Candidates: lane_slots in {2, 4} x slot pools of {1/4, 1/2, 1} x the frame
- * count of each graph (at least one 64*lane_slots group) x graph_steps in
- * {4, 8}.  Each candidate engine decodes every frame twice; the second run is
+ * count of each graph (at least one 64*lane_slots group) x (graph_steps,
+ * iters_per_step) in {(4,1), (8,1), (2,2), (4,2), (1,4), (2,4)}.  Each
+ * candidate engine decodes every frame twice; the second run is
  * timed.  The frames' outputs are overwritten by the trials.
  *
  *  frames[c] / frame_counts[c]  host descriptor arrays of graph c's frames

@@ -99,6 +99,14 @@ __device__ __forceinline__ void load_i32(const int32_t *p, int32_t (&out)[V]) {
     __builtin_memcpy(out, &raw, sizeof(W));
 }
 
+template <int V>
+__device__ __forceinline__ void store_i32(int32_t *p, const int32_t (&in)[V]) {
+    using W = typename Raw<4 * V>::T;
+    W raw;
+    __builtin_memcpy(&raw, in, sizeof(W));
+    *gmem(reinterpret_cast<W *>(p)) = raw;
+}
+
 // -------------------------------------------------------------- check math
 
 // u = 1 - tanh(x/2) = 2w/(1+w) with w = e^-x, for x = |Q| >= 0.

@@ -5,12 +5,14 @@
 // order).  Each slot carries its own iteration count, so frames of one graph
 // sit at different iterations in the same wavefront.  One decode step is
 //
-//   check pass  (all graphs)  iteration t_s+1 of every occupied slot s, and the
-//                             syndrome of its estimate t_s (Algorithm 7)
-//   bit pass    (all graphs)  Lpost / hard decision of iteration t_s+1
-//                             (Algorithm 4), skipped for frames that stop
-//   advance     (all slots)   stop test: estimate t_s passed (early stop) or
-//                             t_s = max_iter; write ok/iters; else t_s += 1
+//   I times (I = iterations per step, 1 by default):
+//     check pass  (all graphs)  iteration t_s+1 of every running slot s, and the
+//                               syndrome of its estimate t_s (Algorithm 7)
+//     bit pass    (all graphs)  stop test: estimate t_s passed (early stop) or
+//                               t_s = max_iter, and the frame stops; else the
+//                               Lpost / hard decision of iteration t_s+1
+//                               (Algorithm 4) and t_s += 1
+//   advance     (all slots)   write ok/iters of the stopped frames and list them
 //   turnover    (listed slots) write the estimate of stopped frames, admit the
 //                             next queued frame of the graph into the slot
 //   repack      (per graph)   once the queue is empty and the running frames are
@@ -62,7 +64,8 @@ struct EngGraph {
     int32_t class_begin[ldpc::kNumClasses + 1];
     float *lch, *lpost;
     void *r;
-    int32_t *slot_t;      // iterations completed by the frame in the slot; -1: the slot is empty
+    int32_t *slot_t;      // [2][S] iterations completed by the frame in the slot (-1: empty;
+                          // + kStopped: stopped), ping-pong between the passes of a step
     int32_t *fail;        // t of the last estimate whose syndrome failed
     EngFrame *slot_desc;  // descriptor of the frame in the slot
     float *aggd, *aggpre;
@@ -99,6 +102,29 @@ __device__ __forceinline__ void store_frame(EngFrame *p, const EngFrame &f) {
     q[2] = w[2];
 }
 
+// Queue and step counters of every graph, in one array of kCounterInts per
+// graph: [4c] head, [4c+1] tail, [4c+2] retired, [4c+3] list count, then
+// [4G+c] taken, [5G+c] moves, [6G+c] extent (G graphs).  Kernels that size
+// their work from them read them here directly, one lane per graph.
+__device__ __forceinline__ int ctr_list_count(int c) { return 4 * c + 3; }
+__device__ __forceinline__ int ctr_taken(int ng, int c) { return 4 * ng + c; }
+__device__ __forceinline__ int ctr_moves(int ng, int c) { return 5 * ng + c; }
+__device__ __forceinline__ int ctr_extent(int ng, int c) { return 6 * ng + c; }
+
+// Wavefront 0, lane c < ngraphs holding graph c's item count: p[0..ngraphs]
+// receives the exclusive offsets (p[ngraphs] is the total).  At most 32 graphs,
+// so a scan over the low 32 lanes covers them.  The caller synchronises.
+template <typename I>
+__device__ __forceinline__ void scan_items(I items, int32_t ngraphs, I *p) {
+    const int c = threadIdx.x;
+    for (int off = 1; off < 32; off <<= 1) {
+        const I y = __shfl_up(items, off);
+        if (c >= off) items += y;
+    }
+    if (c == 0) p[0] = 0;
+    if (c < ngraphs) p[c + 1] = items;
+}
+
 struct Prefix {           // offsets of each graph's work items in one launch
     int32_t count;
     int32_t p[kMaxGraphs + 1];
@@ -109,6 +135,14 @@ __device__ __forceinline__ int find_graph(const Prefix &pre, int x) {
     while (c + 1 < pre.count && x >= pre.p[c + 1]) c++;
     return c;
 }
+
+// Slot state values: -1 empty; t in [0, kStopped) running with t iterations
+// done; kStopped + t stopped after estimate t, waiting for the turnover.
+// Within a step, pass j reads row j % 2 of slot_t and the bit pass writes the
+// state for pass j + 1 into the other row; the step starts from row 0, which
+// holds every slot's state, and for slots at or above the graph's extent
+// (empty) only row 0 is kept.
+constexpr int32_t kStopped = 1 << 30;
 
 // Frame in slot stops after its estimate t: passed the syndrome (early stop) or t = max_iter.
 __device__ __forceinline__ bool slot_stops(int32_t t, int32_t fail, int32_t T, int32_t early) {
@@ -129,15 +163,16 @@ struct EngLane {
 };
 
 template <int V>
-__device__ __forceinline__ void eng_lane(const EngGraph &G, int s0, int32_t T, int32_t early, EngLane<V> &ln) {
-    load_i32<V>(G.slot_t + s0, ln.t);
+__device__ __forceinline__ void eng_lane(const EngGraph &G, int s0, int32_t T, int32_t early, int32_t par,
+                                         EngLane<V> &ln) {
+    load_i32<V>(G.slot_t + par * G.S + s0, ln.t);
     ln.active = false;
     ln.src.any = false;
 #pragma unroll
     for (int k = 0; k < V; k++) {
-        const bool act = ln.t[k] >= 0;
+        const bool act = ln.t[k] >= 0 && ln.t[k] < kStopped;
         ln.src.alt[k] = ln.t[k] == 0;
-        ln.syn_on[k] = ln.t[k] >= 1 && (early || ln.t[k] == T);
+        ln.syn_on[k] = act && ln.t[k] >= 1 && (early || ln.t[k] == T);
         ln.active |= act;
         ln.src.any |= ln.src.alt[k];
     }
@@ -174,8 +209,8 @@ constexpr int kBitItems = -1;   // `cls` value for the bit pass: items are bits
 enum PackMode { kPackNone = 0, kPackAll = 1, kPackOnlyFlat = 2, kPackOnlyPacked = 3 };
 
 template <int PM = kPackNone>
-__device__ __forceinline__ void build_work(const EngGraph *__restrict__ graphs, int32_t ngraphs, int cls,
-                                           int unit, int per, Work &w) {
+__device__ __forceinline__ void build_work(const EngGraph *__restrict__ graphs, int32_t ngraphs,
+                                           const int32_t *__restrict__ counters, int cls, int unit, int per, Work &w) {
     // wavefront 0, one lane per graph (at most 32): the graphs' extents load in
     // parallel and an inclusive scan over the lanes gives the item offsets
     if (threadIdx.x < 64) {
@@ -183,7 +218,7 @@ __device__ __forceinline__ void build_work(const EngGraph *__restrict__ graphs, 
         int32_t items = 0;
         if (c < ngraphs) {
             const EngGraph &G = graphs[c];
-            const int32_t x = *gmem(G.extent);
+            const int32_t x = gmem(counters)[ctr_extent(ngraphs, c)];
             const int32_t gr = (x + unit - 1) / unit;
             const int32_t units = cls == kBitItems ? G.n : G.class_begin[cls + 1] - G.class_begin[cls];
             int32_t rpw = 1;
@@ -194,12 +229,7 @@ __device__ __forceinline__ void build_work(const EngGraph *__restrict__ graphs, 
             w.rpw[c] = rpw;
             items = !take ? 0 : rpw > 1 ? (units + rpw - 1) / rpw : (units * gr + per - 1) / per;
         }
-        for (int off = 1; off < 32; off <<= 1) {
-            const int32_t y = __shfl_up(items, off);
-            if (c >= off) items += y;
-        }
-        if (c == 0) w.p[0] = 0;
-        if (c < ngraphs) w.p[c + 1] = items;
+        scan_items<int32_t>(items, ngraphs, w.p);
     }
     __syncthreads();
 }
@@ -222,12 +252,12 @@ __device__ __forceinline__ int work_graph(const Work &w, int32_t ngraphs, int x)
 // each lane has its own row (packed items).
 template <int M, int V, int DMAX, bool UNIFORM>
 __device__ __forceinline__ void rows_item(const EngGraph &G, int cls, int nrows, int rk, int s0, int32_t T,
-                                          int32_t early) {
+                                          int32_t early, int32_t par) {
     using MT = typename Codec<M>::T;
     if (!UNIFORM && rk >= nrows) return;
     const u32x2 rdv = cload(reinterpret_cast<const u32x2 *>(G.class_rd) + G.class_begin[cls] + rk);
     EngLane<V> ln;
-    eng_lane<V>(G, s0, T, early, ln);
+    eng_lane<V>(G, s0, T, early, par, ln);
     if (!ln.active) return;
     const int e0 = UNIFORM ? wave_uniform(int(rdv.x)) : int(rdv.x);
     const int d = UNIFORM ? wave_uniform(int(rdv.y)) : int(rdv.y);
@@ -241,9 +271,10 @@ __device__ __forceinline__ void rows_item(const EngGraph &G, int cls, int nrows,
 
 template <int M, int V, int DMAX, int PM>
 __global__ __launch_bounds__(256) void eng_check_rows(const EngGraph *__restrict__ graphs, int32_t ngraphs,
-                                                      int32_t cls, int32_t T, int32_t early) {
+                                                      const int32_t *__restrict__ counters, int32_t cls, int32_t T,
+                                                      int32_t early, int32_t par) {
     __shared__ Work w;
-    build_work<PM>(graphs, ngraphs, cls, 64 * V, 1, w);
+    build_work<PM>(graphs, ngraphs, counters, cls, 64 * V, 1, w);
     const int lane = threadIdx.x & 63;
     const int total = wave_uniform(w.p[ngraphs]);
     const int stride = int(gridDim.x * (blockDim.x >> 6));
@@ -256,10 +287,10 @@ __global__ __launch_bounds__(256) void eng_check_rows(const EngGraph *__restrict
         if (PM == kPackNone || PM == kPackOnlyFlat || (PM == kPackAll && rpw == 1)) {
             const int groups = wave_uniform(w.groups[c]);
             const int rk = local / groups;
-            rows_item<M, V, DMAX, true>(G, cls, nrows, rk, ((local - rk * groups) * 64 + lane) * V, T, early);
+            rows_item<M, V, DMAX, true>(G, cls, nrows, rk, ((local - rk * groups) * 64 + lane) * V, T, early, par);
         } else {
             const int lpr = 64 / rpw;
-            rows_item<M, V, DMAX, false>(G, cls, nrows, local * rpw + lane / lpr, (lane % lpr) * V, T, early);
+            rows_item<M, V, DMAX, false>(G, cls, nrows, local * rpw + lane / lpr, (lane % lpr) * V, T, early, par);
         }
     }
 }
@@ -268,14 +299,15 @@ __global__ __launch_bounds__(256) void eng_check_rows(const EngGraph *__restrict
 // one workgroup item = 4 / WPR (row, slot group) pairs.
 template <int M, int V, int WPR>
 __global__ __launch_bounds__(256) void eng_check_chunk(const EngGraph *__restrict__ graphs, int32_t ngraphs,
-                                                       int32_t cls, int32_t T, int32_t early) {
+                                                       const int32_t *__restrict__ counters, int32_t cls, int32_t T,
+                                                       int32_t early, int32_t par) {
     using MT = typename Codec<M>::T;
     constexpr int C = kRowChunk;
     constexpr int RPB = 4 / WPR;
     constexpr int MAXCH = WPR == 2 ? 2 : 16;
     __shared__ ChunkShare<V, RPB * MAXCH> sh;
     __shared__ Work w;
-    build_work(graphs, ngraphs, cls, 64 * V, RPB, w);
+    build_work(graphs, ngraphs, counters, cls, 64 * V, RPB, w);
     const int lane = threadIdx.x & 63;
     const int wave = wave_uniform(threadIdx.x >> 6);
     const int lr = wave / WPR;
@@ -293,7 +325,7 @@ __global__ __launch_bounds__(256) void eng_check_chunk(const EngGraph *__restric
         const int s0 = (g * 64 + lane) * V;
         EngLane<V> ln;
         ln.active = false;
-        if (valid) eng_lane<V>(G, s0, T, early, ln);
+        if (valid) eng_lane<V>(G, s0, T, early, par, ln);
         const bool work = valid && __ballot(ln.active) != 0;
         int e0 = 0, d = 0, nch = 0;
         if (work) {
@@ -343,12 +375,13 @@ __global__ __launch_bounds__(256) void eng_check_chunk(const EngGraph *__restric
 // 32-edge chunks combined through an exclusive prefix/suffix scan in scratch.
 template <int M>
 __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict__ graphs, int32_t ngraphs,
-                                                     int32_t T, int32_t early) {
+                                                     const int32_t *__restrict__ counters, int32_t T, int32_t early,
+                                                     int32_t par) {
     using MT = typename Codec<M>::T;
     constexpr int C = ldpc::kHubChunk;
     __shared__ int32_t total_bits[64];
     __shared__ Work w;
-    build_work(graphs, ngraphs, ldpc::kClassHub, 64, 1, w);
+    build_work(graphs, ngraphs, counters, ldpc::kClassHub, 64, 1, w);
     const int lane = threadIdx.x & 63;
     const int wv = wave_uniform(threadIdx.x >> 6);
     const int nw = blockDim.x >> 6;
@@ -362,8 +395,8 @@ __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict_
         const int g = local % groups;
         const int rk = local / groups;
         const int s = g * 64 + lane;
-        const int32_t ts = gmem(G.slot_t)[s];
-        const bool active = ts >= 0;
+        const int32_t ts = gmem(G.slot_t)[par * S + s];
+        const bool active = ts >= 0 && ts < kStopped;
         const bool first = active && ts == 0;
         const bool syn_on = active && ts >= 1 && (early || ts == T);
         if (__ballot(active) == 0) continue;   // same slots in every wavefront: uniform over the workgroup
@@ -458,21 +491,30 @@ __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict_
 // --------------------------------------------------------------- bit pass
 
 // Posterior of bit v for the lane's V slots (iteration t_s + 1 of every slot
-// whose frame continues).  UNIFORM: one bit per wavefront.
+// whose frame continues).  UNIFORM: one bit per wavefront.  The items of bit 0
+// cover every slot below the extent once, and write the slots' next state.
 template <int M, int V, bool UNIFORM>
-__device__ __forceinline__ void bit_item(const EngGraph &G, int v, int s0, int32_t T, int32_t early) {
+__device__ __forceinline__ void bit_item(const EngGraph &G, int v, int s0, int32_t T, int32_t early,
+                                         int32_t par) {
     using MT = typename Codec<M>::T;
     const int32_t S = G.S;
     int32_t t[V], f[V];
-    load_i32<V>(G.slot_t + s0, t);
+    load_i32<V>(G.slot_t + par * S + s0, t);
     load_i32<V>(G.fail + s0, f);
     bool adv[V];
     bool any = false, all = true;
 #pragma unroll
     for (int k = 0; k < V; k++) {
-        adv[k] = t[k] >= 0 && !slot_stops(t[k], f[k], T, early);
+        adv[k] = t[k] >= 0 && t[k] < kStopped && !slot_stops(t[k], f[k], T, early);
         any |= adv[k];
         all &= adv[k];
+    }
+    if (v == 0) {
+        int32_t nx[V];
+#pragma unroll
+        for (int k = 0; k < V; k++)
+            nx[k] = adv[k] ? t[k] + 1 : (t[k] >= 0 && t[k] < kStopped) ? t[k] + kStopped : t[k];
+        store_i32<V>(G.slot_t + (par ^ 1) * S + s0, nx);
     }
     if (!any) return;
     const MT *R = static_cast<const MT *>(G.r);
@@ -491,10 +533,12 @@ __device__ __forceinline__ void bit_item(const EngGraph &G, int v, int s0, int32
 }
 
 template <int M, int V>
-__global__ __launch_bounds__(256) void eng_bit(const EngGraph *__restrict__ graphs, int32_t ngraphs, int32_t T,
-                                               int32_t early) {
+__global__ __launch_bounds__(256) void eng_bit(const EngGraph *__restrict__ graphs, int32_t ngraphs,
+                                               const int32_t *__restrict__ counters, int32_t T, int32_t early,
+                                               int32_t par) {
     // The previous step's turnover and admission are complete: move each
-    // graph's queue head past the frames it admitted and empty its list.
+    // graph's queue head past the frames it admitted and empty its list
+    // (a no-op in the later passes of a step).
     if (blockIdx.x == 0 && threadIdx.x < ngraphs) {
         const EngGraph &H = graphs[threadIdx.x];
         *gmem(H.head) += *gmem(H.taken);
@@ -502,7 +546,7 @@ __global__ __launch_bounds__(256) void eng_bit(const EngGraph *__restrict__ grap
         *gmem(H.list_count) = 0;
     }
     __shared__ Work w;
-    build_work<kPackAll>(graphs, ngraphs, kBitItems, 64 * V, 1, w);
+    build_work<kPackAll>(graphs, ngraphs, counters, kBitItems, 64 * V, 1, w);
     const int lane = threadIdx.x & 63;
     const int total = wave_uniform(w.p[ngraphs]);
     const int stride = int(gridDim.x * (blockDim.x >> 6));
@@ -514,23 +558,25 @@ __global__ __launch_bounds__(256) void eng_bit(const EngGraph *__restrict__ grap
         if (rpw == 1) {
             const int groups = wave_uniform(w.groups[c]);
             const int v = local / groups;
-            bit_item<M, V, true>(G, v, ((local - v * groups) * 64 + lane) * V, T, early);
+            bit_item<M, V, true>(G, v, ((local - v * groups) * 64 + lane) * V, T, early, par);
         } else {
             const int lpr = 64 / rpw;
             const int v = local * rpw + lane / lpr;
-            if (v < G.n) bit_item<M, V, false>(G, v, (lane % lpr) * V, T, early);
+            if (v < G.n) bit_item<M, V, false>(G, v, (lane % lpr) * V, T, early, par);
         }
     }
 }
 
 // ------------------------------------------------------ advance / turnover
 
-// One thread per slot: stop test, per-frame results, and the graph's turnover
-// list (stopped frames, and empty slots while the graph has queued frames).
+// One thread per slot, after the step's last bit pass (which wrote row `par`
+// of the slot states): per-frame results of the stopped frames, the graph's
+// turnover list (stopped frames, and empty slots while the graph has queued
+// frames), and row 0 brought up to date for the next step.
 // Pool sizes are multiples of 64, so a wavefront never spans two graphs; each
 // wavefront appends its entries in slot order with one atomic.
 __global__ __launch_bounds__(256) void eng_advance(const EngGraph *__restrict__ graphs, Prefix pre, int32_t T,
-                                                   int32_t early) {
+                                                   const int32_t *__restrict__ counters, int32_t par) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     int c = 0;
@@ -540,21 +586,20 @@ __global__ __launch_bounds__(256) void eng_advance(const EngGraph *__restrict__ 
         c = find_graph(pre, x);
         const EngGraph &G = graphs[c];
         const int s = x - pre.p[c];
-        const int32_t t = gmem(G.slot_t)[s];
+        const bool fresh = par && s < gmem(counters)[ctr_extent(pre.count, c)];   // row 1 holds this slot's state
+        const int32_t t = gmem(G.slot_t)[fresh ? G.S + s : s];
+        if (fresh) gmem(G.slot_t)[s] = t;
         if (t < 0) {
             listme = *gmem(G.head) < *gmem(G.tail);
             ent = s;
-        } else {
+        } else if (t >= kStopped) {
+            const int32_t ts = t - kStopped;
             const int32_t f = gmem(G.fail)[s];
-            if (slot_stops(t, f, T, early)) {
-                const EngFrame fr = load_frame(G.slot_desc + s);
-                *gmem(fr.ok) = (t < T) ? uint8_t(1) : uint8_t(f != T);
-                *gmem(fr.iters) = t;
-                listme = stopped = true;
-                ent = s | int32_t(0x80000000u);
-            } else {
-                gmem(G.slot_t)[s] = t + 1;
-            }
+            const EngFrame fr = load_frame(G.slot_desc + s);
+            *gmem(fr.ok) = (ts < T) ? uint8_t(1) : uint8_t(f != T);
+            *gmem(fr.iters) = ts;
+            listme = stopped = true;
+            ent = s | int32_t(0x80000000u);
         }
     }
     const uint64_t m = __ballot(listme);
@@ -579,7 +624,8 @@ __global__ __launch_bounds__(256) void eng_advance(const EngGraph *__restrict__ 
 // accessed in contiguous runs (the list is in slot order within each run).
 constexpr int kTile = 64;
 
-__global__ __launch_bounds__(256) void eng_turnover(const EngGraph *__restrict__ graphs, int32_t ngraphs) {
+__global__ __launch_bounds__(256) void eng_turnover(const EngGraph *__restrict__ graphs, int32_t ngraphs,
+                                                    int32_t *__restrict__ counters) {
     __shared__ int32_t base[kMaxGraphs + 1];
     __shared__ float tile[kTile][kTile + 1];
     __shared__ int32_t slot_of[kTile];
@@ -588,15 +634,16 @@ __global__ __launch_bounds__(256) void eng_turnover(const EngGraph *__restrict__
     __shared__ const float *src_of[kTile];
     __shared__ int32_t any_out, any_in;
     const int tid = threadIdx.x;
-    if (tid == 0) {
-        base[0] = 0;
-        for (int c = 0; c < ngraphs; c++) {
-            const EngGraph &H = graphs[c];
-            const int32_t cnt = *gmem(H.list_count);
-            base[c + 1] = base[c] + (cnt + kTile - 1) / kTile * ((H.n + kTile - 1) / kTile);
+    if (tid < 64) {   // one lane per graph
+        int32_t items = 0;
+        if (tid < ngraphs) {
+            const auto ctr = gmem(counters);
+            const int32_t cnt = ctr[ctr_list_count(tid)];
+            items = (cnt + kTile - 1) / kTile * ((graphs[tid].n + kTile - 1) / kTile);
             // the tail is constant within a step: this is the number admitted now
-            if (blockIdx.x == 0) *gmem(H.taken) = min(cnt, *gmem(H.tail) - *gmem(H.head));
+            if (blockIdx.x == 0) ctr[ctr_taken(ngraphs, tid)] = min(cnt, ctr[4 * tid + 1] - ctr[4 * tid]);
         }
+        scan_items<int32_t>(items, ngraphs, base);
     }
     __syncthreads();
     const int total = base[ngraphs];
@@ -700,7 +747,7 @@ __device__ __forceinline__ int block_rank(bool flag, int32_t *sh, int &total) {
     return before + in_wave;
 }
 
-// One workgroup per graph, after the turnover.
+// One workgroup per graph, after the turnover.  Slot states are row 0.
 // Admission: every listed slot counts its stopped frame as done (its outputs
 // are complete) and takes the next queued frame, or stays empty when the
 // graph's queue ran dry.
@@ -784,18 +831,21 @@ __global__ __launch_bounds__(1024) void eng_admit(const EngGraph *__restrict__ g
 // move_dst[k].  Sources lie above every destination, so the copies are
 // independent.  MSG_BYTES is the stored message size.
 template <int MSG_BYTES>
-__global__ __launch_bounds__(256) void eng_repack_move(const EngGraph *__restrict__ graphs, int32_t ngraphs) {
+__global__ __launch_bounds__(256) void eng_repack_move(const EngGraph *__restrict__ graphs, int32_t ngraphs,
+                                                       const int32_t *__restrict__ counters) {
     using MsgWord = typename std::conditional<MSG_BYTES == 2, uint16_t, uint32_t>::type;
-    __shared__ int64_t base[kMaxGraphs + 1];
+    __shared__ long long base[kMaxGraphs + 1];
     __shared__ int32_t nm[kMaxGraphs];
-    if (threadIdx.x == 0) {
-        base[0] = 0;
-        for (int c = 0; c < ngraphs; c++) {
-            const EngGraph &H = graphs[c];
-            nm[c] = *gmem(H.moves);
-            const int64_t rows = int64_t(H.E) + 2 * int64_t(H.n);
-            base[c + 1] = base[c] + (nm[c] > 0 ? (rows + kMoveRows - 1) / kMoveRows : 0);
+    if (threadIdx.x < 64) {   // one lane per graph
+        long long items = 0;
+        if (threadIdx.x < ngraphs) {
+            const int c = threadIdx.x;
+            const int32_t moves = gmem(counters)[ctr_moves(ngraphs, c)];
+            nm[c] = moves;
+            const long long rows = (long long)graphs[c].E + 2 * (long long)graphs[c].n;
+            items = moves > 0 ? (rows + kMoveRows - 1) / kMoveRows : 0;
         }
+        scan_items<long long>(items, ngraphs, base);
     }
     __syncthreads();
     const int64_t total = base[ngraphs];
@@ -833,7 +883,7 @@ __global__ void eng_publish(int32_t *tail, int32_t value) { *tail = value; }
 struct ldpc_engine {
     int device = -1;
     hipStream_t stream = nullptr;
-    int32_t ngraphs = 0, T = 0, V = 4, K = 8, msg = kF32;
+    int32_t ngraphs = 0, T = 0, V = 4, K = 8, I = 1, msg = kF32;   // I: decoder iterations per step
     uint32_t flags = 0;
     bool early = true;
     bool repack = true;
@@ -845,7 +895,7 @@ struct ldpc_engine {
     void *dmem = nullptr;
     size_t dbytes = 0;
     EngGraph *d_graphs = nullptr;
-    int32_t *d_counters = nullptr;   // [ngraphs][4]: head, tail, retired, list count; then [ngraphs] taken, moves
+    int32_t *d_counters = nullptr;   // [ngraphs][4]: head, tail, retired, list count; then [ngraphs] taken, moves, extent
     ldpc_frame *h_stage = nullptr;   // pinned mirror of every queue ring
     std::vector<size_t> stage_off;
     int32_t *h_counters = nullptr;   // pinned copy of d_counters
@@ -872,16 +922,16 @@ size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 // Register-row class `cls`: unpacked items in one launch and, when packing is
 // on, packed items in a second one, so neither kernel carries the other's body.
 template <int M, int V, int DMAX>
-void launch_rows(ldpc_engine *e, int cls, unsigned grid) {
+void launch_rows(ldpc_engine *e, int cls, unsigned grid, int32_t par) {
     const int32_t early = e->early ? 1 : 0;
     if (e->pack) {
         hipLaunchKernelGGL((eng_check_rows<M, V, DMAX, kPackOnlyFlat>), dim3(grid), dim3(256), 0, e->stream,
-                           e->d_graphs, e->ngraphs, int32_t(cls), e->T, early);
+                           e->d_graphs, e->ngraphs, e->d_counters, int32_t(cls), e->T, early, par);
         hipLaunchKernelGGL((eng_check_rows<M, V, DMAX, kPackOnlyPacked>), dim3(e->grid_packed), dim3(256), 0,
-                           e->stream, e->d_graphs, e->ngraphs, int32_t(cls), e->T, early);
+                           e->stream, e->d_graphs, e->ngraphs, e->d_counters, int32_t(cls), e->T, early, par);
     } else {
         hipLaunchKernelGGL((eng_check_rows<M, V, DMAX, kPackNone>), dim3(grid), dim3(256), 0, e->stream, e->d_graphs,
-                           e->ngraphs, int32_t(cls), e->T, early);
+                           e->ngraphs, e->d_counters, int32_t(cls), e->T, early, par);
     }
 }
 
@@ -890,24 +940,31 @@ void enqueue_step(ldpc_engine *e) {
     hipStream_t st = e->stream;
     const int32_t early = e->early ? 1 : 0;
     const int32_t ng = e->ngraphs;
-    if (e->has_rows[0])
-        launch_rows<M, V, 8>(e, ldpc::kClassD8, e->grid_rows[0]);
-    if (e->has_rows[1])
-        launch_rows<M, ldpc::class_lane_slots(ldpc::kClassD16, V), 16>(e, ldpc::kClassD16, e->grid_rows[1]);
-    if (e->has_rows[2])
-        hipLaunchKernelGGL((eng_check_chunk<M, V, ldpc::class_waves_per_row(ldpc::kClassD128)>),
-                           dim3(e->grid_rows[2]), dim3(256), 0, st, e->d_graphs, ng, int32_t(ldpc::kClassD128), e->T,
-                           early);
-    if (e->has_hub)
-        hipLaunchKernelGGL((eng_check_hub<M>), dim3(e->grid_hub), dim3(256), 0, st, e->d_graphs, ng, e->T, early);
-    hipLaunchKernelGGL((eng_bit<M, V>), dim3(e->grid_bit), dim3(256), 0, st, e->d_graphs, ng, e->T, early);
+    for (int32_t j = 0; j < e->I; j++) {
+        const int32_t par = j & 1;
+        if (e->has_rows[0])
+            launch_rows<M, V, 8>(e, ldpc::kClassD8, e->grid_rows[0], par);
+        if (e->has_rows[1])
+            launch_rows<M, ldpc::class_lane_slots(ldpc::kClassD16, V), 16>(e, ldpc::kClassD16, e->grid_rows[1], par);
+        if (e->has_rows[2])
+            hipLaunchKernelGGL((eng_check_chunk<M, V, ldpc::class_waves_per_row(ldpc::kClassD128)>),
+                               dim3(e->grid_rows[2]), dim3(256), 0, st, e->d_graphs, ng, e->d_counters,
+                               int32_t(ldpc::kClassD128), e->T, early, par);
+        if (e->has_hub)
+            hipLaunchKernelGGL((eng_check_hub<M>), dim3(e->grid_hub), dim3(256), 0, st, e->d_graphs, ng,
+                               e->d_counters, e->T, early, par);
+        hipLaunchKernelGGL((eng_bit<M, V>), dim3(e->grid_bit), dim3(256), 0, st, e->d_graphs, ng, e->d_counters,
+                           e->T, early, par);
+    }
     const unsigned slot_blocks = unsigned((e->total_slots + 255) / 256);
-    hipLaunchKernelGGL(eng_advance, dim3(slot_blocks), dim3(256), 0, st, e->d_graphs, e->pre_slots, e->T, early);
-    hipLaunchKernelGGL(eng_turnover, dim3(unsigned(kTurnoverBlocks)), dim3(256), 0, st, e->d_graphs, e->ngraphs);
+    hipLaunchKernelGGL(eng_advance, dim3(slot_blocks), dim3(256), 0, st, e->d_graphs, e->pre_slots, e->T,
+                       e->d_counters, int32_t(e->I & 1));
+    hipLaunchKernelGGL(eng_turnover, dim3(unsigned(kTurnoverBlocks)), dim3(256), 0, st, e->d_graphs, e->ngraphs,
+                       e->d_counters);
     if (e->repack) {
         hipLaunchKernelGGL(eng_admit<true>, dim3(unsigned(e->ngraphs)), dim3(1024), 0, st, e->d_graphs);
         hipLaunchKernelGGL((eng_repack_move<sizeof(typename Codec<M>::T)>), dim3(unsigned(kMoveBlocks)), dim3(256), 0,
-                           st, e->d_graphs, e->ngraphs);
+                           st, e->d_graphs, e->ngraphs, e->d_counters);
     } else {
         hipLaunchKernelGGL(eng_admit<false>, dim3(unsigned(e->ngraphs)), dim3(1024), 0, st, e->d_graphs);
     }
@@ -1008,13 +1065,16 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
                                           const ldpc_engine_opts *opts, ldpc_engine **out) {
     if (!out || !graphs || !slots || !queue_cap) { set_error("ldpc_engine_create: NULL argument"); return LDPC_E_INVAL; }
     if (ngraphs < 1 || ngraphs > kMaxGraphs) { set_error("ldpc_engine_create: ngraphs must be in 1..32"); return LDPC_E_INVAL; }
-    if (max_iter < 1) { set_error("ldpc_engine_create: max_iter must be >= 1"); return LDPC_E_INVAL; }
+    if (max_iter < 1 || max_iter >= kStopped) {
+        set_error("ldpc_engine_create: max_iter must be in 1..2^30-1");
+        return LDPC_E_INVAL;
+    }
     const uint32_t known = LDPC_NO_EARLY_STOP | LDPC_MSG_FP16 | LDPC_MSG_BF16;
     if ((flags & ~known) || ((flags & LDPC_MSG_FP16) && (flags & LDPC_MSG_BF16))) {
         set_error("ldpc_engine_create: bad flags");
         return LDPC_E_INVAL;
     }
-    int V = 4, K = 8;
+    int V = 4, K = 8, I = 1;
     bool repack = true;
     if (opts) {
         for (int32_t r : opts->reserved)
@@ -1036,6 +1096,11 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
             return LDPC_E_INVAL;
         }
         repack = opts->no_compaction == 0;
+        if (opts->iters_per_step < 0 || opts->iters_per_step > 16) {
+            set_error("ldpc_engine_create: iters_per_step must be in 0..16");
+            return LDPC_E_INVAL;
+        }
+        if (opts->iters_per_step) I = opts->iters_per_step;
     }
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) { (void)hipGetLastError(); set_error("ldpc_engine_create: no device"); return LDPC_E_DEVICE; }
@@ -1059,6 +1124,7 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
     e->msg = (flags & LDPC_MSG_FP16) ? kF16 : (flags & LDPC_MSG_BF16) ? kBF16 : kF32;
     e->V = V;
     e->K = K;
+    e->I = I;
     e->repack = repack;
     if (const char *v = std::getenv("LDPC_ENGINE_NO_PACK")) e->pack = v[0] != '1';
     if (const char *v = std::getenv("LDPC_ENGINE_DIRECT")) e->direct = v[0] == '1';
@@ -1079,7 +1145,7 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
         o.lch = off;     off = al256(off + size_t(g->n) * S * 4);
         o.lpost = off;   off = al256(off + size_t(g->n) * S * 4);
         o.r = off;       off = al256(off + size_t(g->E) * S * msg_bytes);
-        o.t = off;       off = al256(off + size_t(S) * 4);
+        o.t = off;       off = al256(off + size_t(2) * S * 4);
         o.fail = off;    off = al256(off + size_t(S) * 4);
         o.desc = off;    off = al256(off + size_t(S) * sizeof(EngFrame));
         o.aggd = off;    off = al256(off + size_t(g->hub_chunks) * S * 4);
@@ -1137,7 +1203,7 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
         e->hg.push_back(G);
         // every slot starts empty, with defined message state
         if ((err = hipMemsetAsync(base + o.lch, 0, o.t - o.lch, e->stream)) != hipSuccess ||
-            (err = hipMemsetAsync(G.slot_t, 0xff, size_t(G.S) * 4, e->stream)) != hipSuccess ||
+            (err = hipMemsetAsync(G.slot_t, 0xff, size_t(2) * G.S * 4, e->stream)) != hipSuccess ||
             (err = hipMemsetAsync(G.fail, 0, size_t(G.S) * 4, e->stream)) != hipSuccess)
             return hip_fail(e, "ldpc_engine_create: hipMemsetAsync", err);
     }
@@ -1396,17 +1462,20 @@ extern "C" ldpc_status ldpc_engine_autotune(const ldpc_graph *const *graphs, int
     }
     const int lane_options[2] = {2, 4};
     const float scale_options[3] = {0.25f, 0.5f, 1.0f};
-    const int step_options[2] = {4, 8};
+    // (steps per replay, iterations per step): at most 16 iterations per replay,
+    // since the host looks at the counters once per replay
+    const int step_options[6][2] = {{4, 1}, {8, 1}, {2, 2}, {4, 2}, {1, 4}, {2, 4}};
     float best = -1.f;
     for (int ls : lane_options) {
         for (float sc : scale_options) {
-            for (int gs : step_options) {
+            for (const auto &gi : step_options) {
                 std::vector<int32_t> slots(static_cast<size_t>(ngraphs));
                 for (int32_t c = 0; c < ngraphs; c++)
                     slots[size_t(c)] = std::max(64 * ls, int32_t(std::ceil(sc * float(frame_counts[c]))));
                 ldpc_engine_opts o{};
                 o.lane_slots = ls;
-                o.graph_steps = gs;
+                o.graph_steps = gi[0];
+                o.iters_per_step = gi[1];
                 ldpc_engine *e = nullptr;
                 ldpc_status st = ldpc_engine_create(graphs, ngraphs, slots.data(), caps.data(), max_iter, flags, &o, &e);
                 if (st != LDPC_OK) return st;

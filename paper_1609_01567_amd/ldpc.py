@@ -50,7 +50,8 @@ class ServerOpts(ctypes.Structure):
 
 class EngineOpts(ctypes.Structure):
     _fields_ = [("lane_slots", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
-                ("no_compaction", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("no_compaction", ctypes.c_int32), ("iters_per_step", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class LdpcError(RuntimeError):
@@ -319,7 +320,7 @@ class Engine:
     """Batched decoder with continuous refill (ldpc_engine_*) over several graphs."""
 
     def __init__(self, graphs, slots, queue_cap, max_iter: int, flags: int = 0, lane_slots: int = 0,
-                 graph_steps: int = 0, repack: bool = True):
+                 graph_steps: int = 0, repack: bool = True, iters_per_step: int = 0):
         lib = load_library()
         self._lib = lib
         self.graphs = list(graphs)
@@ -329,7 +330,7 @@ class Engine:
         qc = np.ascontiguousarray(queue_cap, dtype=np.int32)
         if sl.size != ng or qc.size != ng:
             raise ValueError("one slot count and one queue capacity per graph")
-        opts = EngineOpts(lane_slots, graph_steps, 0 if repack else 1)
+        opts = EngineOpts(lane_slots, graph_steps, 0 if repack else 1, iters_per_step)
         self._h = ctypes.c_void_p()
         _check(lib.ldpc_engine_create(hs, ng, _np_ptr(sl), _np_ptr(qc), int(max_iter), int(flags),
                                       ctypes.byref(opts), ctypes.byref(self._h)), "ldpc_engine_create")
@@ -441,7 +442,7 @@ def autotune(graphs, frame_lists, max_iter: int, flags: int = 0) -> dict:
     _check(lib.ldpc_engine_autotune(hs, ng, ptrs, _np_ptr(counts), int(max_iter), int(flags), _np_ptr(slots),
                                     ctypes.byref(opts), ctypes.byref(ms)), "ldpc_engine_autotune")
     return {"slots": slots.tolist(), "lane_slots": int(opts.lane_slots), "graph_steps": int(opts.graph_steps),
-            "ms": float(ms.value)}
+            "iters_per_step": int(opts.iters_per_step), "ms": float(ms.value)}
 
 
 class Server:

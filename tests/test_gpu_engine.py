@@ -27,13 +27,13 @@ def _announce(name, **kw):
 
 
 def _engine_decode(codes, llrs, slots, T, flags=0, lane_slots=0, graph_steps=0, want_llr=True, cap=None,
-                   repack=True):
+                   repack=True, iters_per_step=0):
     import torch
     from paper_1609_01567_amd import ldpc
     graphs = [ldpc.Graph.from_code(c) for c in codes]
     caps = cap or [max(1, x.shape[0]) for x in llrs]
     eng = ldpc.Engine(graphs, slots, caps, T, flags=flags, lane_slots=lane_slots, graph_steps=graph_steps,
-                      repack=repack)
+                      repack=repack, iters_per_step=iters_per_step)
     jobs = [(i, torch.from_numpy(np.ascontiguousarray(x)).cuda()) for i, x in enumerate(llrs)]
     # bound: every frame needs at most T+1 steps once admitted; admissions follow slot turnover
     steps = sum((x.shape[0] // max(1, sl) + 2) * (T + 2) for x, sl in zip(llrs, slots)) + 8
@@ -70,6 +70,52 @@ def test_engine_refill_equals_plain(lane_slots):
     plain = gpu_decode(code, llr, 30)
     _assert_same(eng, plain, "engine refill vs plain")
     compare(code, llr[:96], 30, gpu={k: v[:96] for k, v in eng.items()})
+
+
+def _mixed_codes():
+    rng = np.random.default_rng(11)
+    cdeg = np.concatenate([[300, 140, 64, 40, 33], rng.integers(3, 33, size=95)])
+    E = int(cdeg.sum())
+    bdeg = np.full(700, E // 700)
+    bdeg[: E - bdeg.sum()] += 1
+    hub = li.socket_code(bdeg, cdeg, seed=12)
+    codes = [li.tiny_code(), hub, li.random_small_code(300, 150, 3, seed=31), li.code_14_7()]
+    frames = [150, 70, 333, 40]
+    snr = [2.0, None, 1.5, None]
+    llrs = []
+    for i, (c, f) in enumerate(zip(codes, frames)):
+        s2 = li.ebn0_to_sigma2(snr[i], c.rate) if snr[i] else 0.7
+        llrs.append(li.awgn_llr(c.n, f, s2, seed=50 + i))
+    return codes, llrs
+
+
+@pytest.mark.parametrize("iters_per_step", [2, 3, 4])
+def test_engine_iterations_per_step_each_frame_as_alone(iters_per_step):
+    """Several decoder iterations between turnovers: frames that stop inside a
+    step sit out its remaining passes, and slots refill at step ends (pools
+    smaller than the frame counts), over every check-degree class."""
+    codes, llrs = _mixed_codes()
+    _announce("engine-iters-per-step", iters_per_step=iters_per_step)
+    out = _engine_decode(codes, llrs, [64, 64, 128, 64], 25, lane_slots=2, graph_steps=3,
+                         iters_per_step=iters_per_step)
+    for c, x, o in zip(codes, llrs, out):
+        _assert_same(o, gpu_decode(c, x, 25), f"{iters_per_step} iterations per step: {c.name}")
+
+
+def test_engine_iterations_per_step_repack_and_max_iter():
+    """Repacking between multi-iteration steps, and max_iter not a multiple of
+    the iterations per step (with and without early stop)."""
+    from paper_1609_01567_amd import ldpc
+    code = li.random_small_code(600, 300, 3, seed=8)
+    llr = li.awgn_llr(code.n, 900, li.ebn0_to_sigma2(1.0, code.rate), seed=19)
+    _announce("engine-iters-per-step-repack")
+    on = _engine_decode([code], [llr], [1024], 40, flags=ldpc.MSG_FP16, graph_steps=2, iters_per_step=3)[0]
+    _assert_same(on, gpu_decode(code, llr, 40, flags=ldpc.MSG_FP16), "3 iterations per step, repack")
+    small = llr[:100]
+    for T in (1, 7):
+        eng = _engine_decode([code], [small], [64], T, flags=ldpc.NO_EARLY_STOP, iters_per_step=4)[0]
+        assert (eng["iters"] == T).all()
+        _assert_same(eng, gpu_decode(code, small, T, flags=ldpc.NO_EARLY_STOP), f"T={T}, 4 per step")
 
 
 def test_engine_mixed_codes_each_frame_as_alone():

@@ -10,7 +10,9 @@ Parity status: every function here is pinned by the CPU tests
 (tests/test_oracle_pins.py): brute-force bitwise MAP on cycle-free graphs,
 the probability-domain form of Algorithm 1, closed forms on single-parity-check
 and path codes, noiseless and all-zero inputs, the degree-1 clamp, sign
-symmetry, and the paper's Tables I and II for the adjacency lists.
+symmetry, and the paper's Tables I and II for the adjacency lists.  The
+Min-Sum rules are pinned by brute-force max-log MAP on single parity checks,
+brute-force max-marginals on cycle-free graphs, and the path-code closed form.
 """
 from __future__ import annotations
 
@@ -24,6 +26,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ldpc_oracle.c")
 _SO = os.path.join(_HERE, "liboracle.so")
 LMAX = 64.0
+# check rules: name -> (code, default parameter); "ms" is the normalized rule with alpha = 1
+RULES = {"sp": (0, 0.0), "nms": (1, 0.75), "oms": (2, 0.25), "ms": (1, 1.0)}
 _lib = None
 
 
@@ -47,6 +51,11 @@ def _load():
                                            ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                            ctypes.c_double, P, P, P, P, P, P, ctypes.c_int]
         lib.ldpc_oracle_decode.restype = ctypes.c_int
+        lib.ldpc_oracle_decode_rule.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long, P, P, P,
+                                                ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                                ctypes.c_double, ctypes.c_int, ctypes.c_double, P, P, P, P, P, P,
+                                                ctypes.c_int]
+        lib.ldpc_oracle_decode_rule.restype = ctypes.c_int
         lib.ldpc_oracle_adjacency.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long, P, P, P, P, P, P]
         lib.ldpc_oracle_adjacency.restype = ctypes.c_int
         _lib = lib
@@ -58,8 +67,12 @@ def _ptr(a):
 
 
 def decode(code, llr, max_iter: int, early_stop: bool = True, lmax: float = LMAX,
-           threads: int = 0, want_lpost: bool = True, tie_margin: float = 1e-3) -> dict:
+           threads: int = 0, want_lpost: bool = True, tie_margin: float = 1e-3, rule: str = "sp",
+           param: float | None = None) -> dict:
     """Decode every row of `llr` ([F][n] float32) on the CPU in FP64.
+
+    rule: "sp" (sum-product, the paper's decoder), "ms" (Min-Sum), "nms"
+    (normalized Min-Sum, param = alpha) or "oms" (offset Min-Sum, param = beta).
 
     Returns a dict with bits [F][n] u8, ok [F] u8, iters [F] i32,
     min_abs [F] f64 (smallest |Lpost| over all iterations run), tie_risk [F]
@@ -79,10 +92,12 @@ def decode(code, llr, max_iter: int, early_stop: bool = True, lmax: float = LMAX
     min_abs = np.zeros(F, np.float64)
     tie_risk = np.zeros(F, np.uint8)
     lpost = np.zeros((F, n), np.float64) if want_lpost else None
-    st = lib.ldpc_oracle_decode(code.m, code.n, rows.size, _ptr(rows), _ptr(cols), _ptr(llr), F,
-                                int(max_iter), int(bool(early_stop)), float(lmax), float(tie_margin),
-                                _ptr(lpost) if want_lpost else None, _ptr(bits), _ptr(ok), _ptr(iters),
-                                _ptr(min_abs), _ptr(tie_risk), int(threads))
+    kind, default = RULES[rule]
+    p = default if param is None or rule == "ms" else float(param)
+    st = lib.ldpc_oracle_decode_rule(code.m, code.n, rows.size, _ptr(rows), _ptr(cols), _ptr(llr), F,
+                                     int(max_iter), int(bool(early_stop)), float(lmax), float(tie_margin),
+                                     kind, p, _ptr(lpost) if want_lpost else None, _ptr(bits), _ptr(ok),
+                                     _ptr(iters), _ptr(min_abs), _ptr(tie_risk), int(threads))
     if st != 0:
         raise ValueError(f"oracle rejected the input (status {st})")
     out = dict(bits=bits, ok=ok, iters=iters, min_abs=min_abs, tie_risk=tie_risk)

@@ -36,6 +36,16 @@
  *
  * Every extrinsic sum skips the destination edge explicitly (the "continue" of
  * Algorithm 5), so no quantity is ever formed as "total minus own".
+ *
+ * Min-Sum family.  Section 3.1 names Min-Sum and adaptive normalized / offset
+ * Min-Sum (Wu, Song, Jiang, Zhao, IEEE Commun. Lett. 14(7), 2010) as derived
+ * decoders that suit the edge-level approach.  They keep Algorithm 1's bit rule
+ * and replace the check rule's magnitude phi(sum phi(|Q|)) by the smallest
+ * |Q| among the other bits of the check, m = min_{j' in N_i \ j} |Q[j'->i]|:
+ *   normalized: |R| = alpha * m          (alpha in (0, 1]; alpha = 1 is plain Min-Sum)
+ *   offset:     |R| = max(m - beta, 0)   (beta >= 0)
+ * with the same sign product and the same clamp; an empty set gives m = inf,
+ * so a degree-1 check sends +lmax under every rule.
  */
 #include <math.h>
 #include <stdint.h>
@@ -46,6 +56,9 @@
 #endif
 
 #define ORACLE_OK 0
+#define RULE_SUM_PRODUCT 0
+#define RULE_MIN_SUM_NORMALIZED 1
+#define RULE_MIN_SUM_OFFSET 2
 #define ORACLE_E_INVAL 1
 #define ORACLE_E_RANGE 2
 #define ORACLE_E_NOMEM 4
@@ -102,8 +115,9 @@ static double clamp(double x, double lim) {
 
 /* Decode one frame.  Work buffers: R, Q, P (per edge), lpost (per bit), chat (per bit). */
 static void decode_frame(const graph_t *g, const float *llr, int max_iter, int early_stop, double lmax,
-                         double tie_margin, double *R, double *Q, double *P, double *lpost, uint8_t *chat,
-                         uint8_t *ok_out, int *iters_out, double *min_abs_out, uint8_t *tie_risk_out) {
+                         double tie_margin, int rule, double rule_param, double *R, double *Q, double *P,
+                         double *lpost, uint8_t *chat, uint8_t *ok_out, int *iters_out, double *min_abs_out,
+                         uint8_t *tie_risk_out) {
     const int m = g->m, n = g->n;
     const long E = g->E;
     double min_abs = INFINITY;
@@ -128,6 +142,31 @@ static void decode_frame(const graph_t *g, const float *llr, int max_iter, int e
                 Q[e] = clamp(s, lmax);
             }
         }
+        if (rule != RULE_SUM_PRODUCT) {
+            /* Min-Sum family: sign product and smallest magnitude over the other
+               bits of check i, then the normalization or the offset. */
+            for (int i = 0; i < m; i++) {
+                for (int a = g->chk_start[i]; a < g->chk_start[i + 1]; a++) {
+                    const int e = g->chk_edge[a];
+                    double mn = INFINITY;
+                    int negative = 0;
+                    for (int b = g->chk_start[i]; b < g->chk_start[i + 1]; b++) {
+                        if (b == a) continue;          /* skip the destination bit */
+                        const int e2 = g->chk_edge[b];
+                        if (fabs(Q[e2]) < mn) mn = fabs(Q[e2]);
+                        negative ^= (Q[e2] < 0.0);
+                    }
+                    double mag;
+                    if (rule == RULE_MIN_SUM_NORMALIZED) {
+                        mag = rule_param * mn;
+                    } else {
+                        mag = mn - rule_param;
+                        if (mag < 0.0) mag = 0.0;
+                    }
+                    R[e] = clamp(negative ? -mag : mag, lmax);
+                }
+            }
+        } else {
         /* Each incoming message enters the check rule through phi(|Q|). */
         for (long e = 0; e < E; e++) P[e] = phi(fabs(Q[e]));
 
@@ -147,6 +186,7 @@ static void decode_frame(const graph_t *g, const float *llr, int max_iter, int e
                 const double mag = phi(s);             /* phi(0) = inf for an empty product */
                 R[e] = clamp(negative ? -mag : mag, lmax);
             }
+        }
         }
 
         /* Algorithm 4: the estimate uses the channel value and every incoming r. */
@@ -186,16 +226,22 @@ static void decode_frame(const graph_t *g, const float *llr, int max_iter, int e
     *tie_risk_out = (uint8_t)tie_risk;
 }
 
-/* Public entry.  llr: [frames][n] float32 LLRs.  Outputs per frame: lpost [frames][n]
- * (may be NULL), bits [frames][n], ok [frames], iters [frames], min_abs [frames]
- * (smallest |Lpost| over all bits and all iterations run; may be NULL) and
- * tie_risk [frames] (1 if a sign flip of some bit with |Lpost| < tie_margin could
- * change bits, ok or iters; may be NULL). */
-int ldpc_oracle_decode(int m, int n, long nnz, const int *rows, const int *cols,
-                       const float *llr, int frames, int max_iter, int early_stop, double lmax,
-                       double tie_margin, double *lpost_out, uint8_t *bits_out, uint8_t *ok_out,
-                       int *iters_out, double *min_abs_out, uint8_t *tie_risk_out, int nthreads) {
+/* Public entry.  llr: [frames][n] float32 LLRs.  rule: RULE_* above with its
+ * parameter (alpha for the normalized rule, beta for the offset rule; ignored
+ * for sum-product).  Outputs per frame: lpost [frames][n] (may be NULL),
+ * bits [frames][n], ok [frames], iters [frames], min_abs [frames] (smallest
+ * |Lpost| over all bits and all iterations run; may be NULL) and tie_risk
+ * [frames] (1 if a sign flip of some bit with |Lpost| < tie_margin could change
+ * bits, ok or iters; may be NULL). */
+int ldpc_oracle_decode_rule(int m, int n, long nnz, const int *rows, const int *cols,
+                            const float *llr, int frames, int max_iter, int early_stop, double lmax,
+                            double tie_margin, int rule, double rule_param, double *lpost_out, uint8_t *bits_out,
+                            uint8_t *ok_out, int *iters_out, double *min_abs_out, uint8_t *tie_risk_out,
+                            int nthreads) {
     if (max_iter < 1 || frames < 0 || !(lmax > 0.0)) return ORACLE_E_INVAL;
+    if (rule == RULE_MIN_SUM_NORMALIZED && !(rule_param > 0.0 && rule_param <= 1.0)) return ORACLE_E_INVAL;
+    if (rule == RULE_MIN_SUM_OFFSET && !(rule_param >= 0.0 && rule_param < lmax)) return ORACLE_E_INVAL;
+    if (rule < RULE_SUM_PRODUCT || rule > RULE_MIN_SUM_OFFSET) return ORACLE_E_INVAL;
     graph_t g;
     int st = graph_build(&g, m, n, nnz, rows, cols);
     if (st) return st;
@@ -219,8 +265,8 @@ int ldpc_oracle_decode(int m, int n, long nnz, const int *rows, const int *cols,
             for (int f = 0; f < frames; f++) {
                 double mn;
                 uint8_t risk;
-                decode_frame(&g, llr + (size_t)f * n, max_iter, early_stop, lmax, tie_margin, R, Q, P, lp, ch,
-                             &ok_out[f], &iters_out[f], &mn, &risk);
+                decode_frame(&g, llr + (size_t)f * n, max_iter, early_stop, lmax, tie_margin, rule, rule_param, R,
+                             Q, P, lp, ch, &ok_out[f], &iters_out[f], &mn, &risk);
                 if (min_abs_out) min_abs_out[f] = mn;
                 if (tie_risk_out) tie_risk_out[f] = risk;
                 if (lpost_out) memcpy(lpost_out + (size_t)f * n, lp, sizeof(double) * (size_t)n);
@@ -231,6 +277,16 @@ int ldpc_oracle_decode(int m, int n, long nnz, const int *rows, const int *cols,
     }
     graph_free(&g);
     return status;
+}
+
+/* Sum-product decode (the paper's rule): ldpc_oracle_decode_rule with RULE_SUM_PRODUCT. */
+int ldpc_oracle_decode(int m, int n, long nnz, const int *rows, const int *cols,
+                       const float *llr, int frames, int max_iter, int early_stop, double lmax,
+                       double tie_margin, double *lpost_out, uint8_t *bits_out, uint8_t *ok_out,
+                       int *iters_out, double *min_abs_out, uint8_t *tie_risk_out, int nthreads) {
+    return ldpc_oracle_decode_rule(m, n, nnz, rows, cols, llr, frames, max_iter, early_stop, lmax, tie_margin,
+                                   RULE_SUM_PRODUCT, 0.0, lpost_out, bits_out, ok_out, iters_out, min_abs_out,
+                                   tie_risk_out, nthreads);
 }
 
 /* The oracle's adjacency lists (bit_start[n+1], bit_edge[nnz], chk_start[m+1], chk_edge[nnz]). */

@@ -189,6 +189,47 @@ LDPC_API ldpc_status ldpc_decode_profiled(const ldpc_graph *g, const float *llr_
                                           float *edge_ms);
 
 /* ------------------------------------------------------------------------
+ * Check-node rules.
+ *
+ * The paper's decoder is sum-product (Algorithm 1, no simplification).  Its
+ * Section 3.1 names Min-Sum and adaptive normalized / offset Min-Sum (Wu,
+ * Song, Jiang, Zhao, IEEE Commun. Lett. 14(7), 2010) as derived decoders that
+ * suit the same edge-level approach.  They keep the bit rule and the sign of
+ * the check rule and replace the magnitude phi(sum phi(|Q|)) over the other
+ * bits of the check by m = min |Q| over the other bits:
+ *   LDPC_RULE_MIN_SUM_NORMALIZED  |R| = alpha * m, param = alpha in (0, 1]
+ *                                 (alpha = 1 is plain Min-Sum);
+ *   LDPC_RULE_MIN_SUM_OFFSET      |R| = max(m - beta, 0), param = beta in [0, 64).
+ * |R| is clamped to 64 as for sum-product; a degree-1 check sends +64.
+ * The arithmetic is fp32 (the products alpha * m and differences m - beta
+ * are rounded once); storage follows the LDPC_MSG_* flags.
+ * ------------------------------------------------------------------------ */
+typedef enum {
+    LDPC_RULE_SUM_PRODUCT = 0,
+    LDPC_RULE_MIN_SUM_NORMALIZED = 1,
+    LDPC_RULE_MIN_SUM_OFFSET = 2
+} ldpc_rule_kind;
+
+typedef struct {
+    int32_t kind;          /* ldpc_rule_kind */
+    float param;           /* alpha or beta; ignored for sum-product */
+    int32_t reserved[2];   /* must be 0 */
+} ldpc_rule;
+
+/*
+ * ldpc_decode with a selectable check rule.  rule (host pointer, read during
+ * the call) may be NULL for sum-product; every other argument and the results
+ * are those of ldpc_decode, including the workspace size.  Errors: those of
+ * ldpc_decode; INVAL for an unknown kind, a parameter out of range or
+ * non-zero reserved fields.
+ */
+LDPC_API ldpc_status ldpc_decode_rule(const ldpc_graph *g, const float *llr_in, int32_t frames,
+                                      int32_t max_iter, uint32_t flags, const ldpc_rule *rule,
+                                      uint8_t *bits_out, uint8_t *syndrome_ok, int32_t *iters,
+                                      float *llr_out, void *workspace, size_t workspace_bytes,
+                                      void *hip_stream);
+
+/* ------------------------------------------------------------------------
  * Monte-Carlo error-rate runs on the device (the paper's error-rate
  * simulation: channel, decode and error count, Sec. IV and V-A).
  *
@@ -236,6 +277,13 @@ LDPC_API ldpc_status ldpc_simulate(const ldpc_graph *g, int32_t frames, double e
                                    uint64_t first_frame, int32_t max_iter, uint32_t flags,
                                    ldpc_sim_counts *counts, float *llr_out, void *workspace,
                                    size_t workspace_bytes, void *hip_stream);
+
+/* ldpc_simulate with a selectable check rule (NULL: sum-product); the
+ * arguments, counts and errors are those of ldpc_simulate and ldpc_decode_rule. */
+LDPC_API ldpc_status ldpc_simulate_rule(const ldpc_graph *g, int32_t frames, double ebn0_db, uint64_t seed,
+                                        uint64_t first_frame, int32_t max_iter, uint32_t flags,
+                                        const ldpc_rule *rule, ldpc_sim_counts *counts, float *llr_out,
+                                        void *workspace, size_t workspace_bytes, void *hip_stream);
 
 /* ------------------------------------------------------------------------
  * Batched decoding with continuous refill.

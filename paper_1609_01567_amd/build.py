@@ -17,6 +17,10 @@ HIPCC_FLAGS = [
     "-Wall", "-Wno-unused-function",
     # keep the compiler from emitting packed fp32 VALU ops
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit multiply-add contraction: the check and bit rules are inlined
+    # into many kernels, and each must round every operation the same way
+    # (fused operations are written out as fmaf where they are wanted)
+    "-ffp-contract=off",
     "-fvisibility=hidden", "-DLDPC_BUILD", "-pthread",
 ]
 

@@ -87,11 +87,13 @@ __device__ __forceinline__ void plain_syndrome(const int32_t (&st)[V], const int
 }
 
 // Rows of degree <= DMAX in registers: one wavefront per (row, slot group).
-template <int M, int V, int DMAX, int MODE>
+// RULE: the check rule (CheckRule); rp its parameter.
+template <int M, int V, int DMAX, int MODE, int RULE>
 __global__ __launch_bounds__(256) void check_rows_kernel(
     const int32_t *__restrict__ rd, const int32_t *__restrict__ col_idx,
     int32_t nrows, const float *__restrict__ L, typename Codec<M>::T *__restrict__ R,
-    const int32_t *__restrict__ iters, int32_t *__restrict__ fail, int32_t S, int32_t groups, int32_t syn_iter) {
+    const int32_t *__restrict__ iters, int32_t *__restrict__ fail, int32_t S, int32_t groups, int32_t syn_iter,
+    float rp) {
     const int lane = threadIdx.x & 63;
     const int wave = wave_uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const int g = wave % groups;
@@ -118,18 +120,19 @@ __global__ __launch_bounds__(256) void check_rows_kernel(
 #pragma unroll
     for (int k = 0; k < V; k++) syn[k] = 0;
     constexpr int IN = MODE == kIter ? kInSteady : kInFirst;
-    row_rule<M, V, DMAX, true, IN>(col_idx, e0, d, L, R, S, s0, src, syn);
+    row_rule<M, V, DMAX, true, IN, RULE>(col_idx, e0, d, L, R, S, s0, src, syn, rp);
     if (MODE == kIter) plain_syndrome<V>(st, syn, fail, s0, syn_iter);
 }
 
 // Rows of 9..128 edges: WPR wavefronts per (row, slot group), 8-edge chunks,
 // chunk aggregates exchanged through LDS.  A wavefront with more than one
 // chunk recomputes its chunks' inputs in the second phase.
-template <int M, int V, int WPR, int MODE>
+template <int M, int V, int WPR, int MODE, int RULE>
 __global__ __launch_bounds__(256) void check_chunk_kernel(
     const int32_t *__restrict__ rd, const int32_t *__restrict__ col_idx,
     int32_t nrows, const float *__restrict__ L, typename Codec<M>::T *__restrict__ R,
-    const int32_t *__restrict__ iters, int32_t *__restrict__ fail, int32_t S, int32_t groups, int32_t syn_iter) {
+    const int32_t *__restrict__ iters, int32_t *__restrict__ fail, int32_t S, int32_t groups, int32_t syn_iter,
+    float rp) {
     constexpr int C = kRowChunk;
     constexpr int RPB = 4 / WPR;
     constexpr int MAXCH = WPR == 2 ? 2 : 16;
@@ -169,11 +172,11 @@ __global__ __launch_bounds__(256) void check_chunk_kernel(
     int syn[V];
     for (int ch = wr; ch < nch; ch += WPR) {
         if (mine) {
-            chunk_load<M, V, C, kChunkIn>(col_idx, e0 + ch * C, min(C, d - ch * C), L, R, S, s0, src, u,
-                                          suf, agg, neg, syn);
+            chunk_load<M, V, C, kChunkIn, RULE>(col_idx, e0 + ch * C, min(C, d - ch * C), L, R, S, s0, src, u,
+                                                suf, agg, neg, syn);
         } else {
 #pragma unroll
-            for (int k = 0; k < V; k++) { agg[k] = 0.f; neg[k] = 0u; syn[k] = 0; }
+            for (int k = 0; k < V; k++) { agg[k] = CheckRule<RULE>::identity(); neg[k] = 0u; syn[k] = 0; }
         }
 #pragma unroll
         for (int k = 0; k < V; k++) sh.agg[lr * MAXCH + ch][lane][k] = agg[k];
@@ -183,13 +186,13 @@ __global__ __launch_bounds__(256) void check_chunk_kernel(
     if (!mine) return;
     for (int ch = wr; ch < nch; ch += WPR) {
         if (nch > WPR)
-            chunk_load<M, V, C, kChunkIn>(col_idx, e0 + ch * C, min(C, d - ch * C), L, R, S, s0, src, u,
-                                          suf, agg, neg, syn);
+            chunk_load<M, V, C, kChunkIn, RULE>(col_idx, e0 + ch * C, min(C, d - ch * C), L, R, S, s0, src, u,
+                                                suf, agg, neg, syn);
         float pre[V], post[V];
         uint32_t parity[V];
         int syn_row[V];
-        chunk_context<V, RPB * MAXCH>(sh, lr * MAXCH, nch, ch, lane, pre, post, parity, syn_row);
-        chunk_store<M, V, C>(e0 + ch * C, min(C, d - ch * C), u, suf, neg, pre, post, parity, R, S, s0);
+        chunk_context<V, RPB * MAXCH, RULE>(sh, lr * MAXCH, nch, ch, lane, pre, post, parity, syn_row);
+        chunk_store<M, V, C, RULE>(e0 + ch * C, min(C, d - ch * C), u, suf, neg, pre, post, parity, R, S, s0, rp);
         if (MODE == kIter && ch == 0) plain_syndrome<V>(st, syn_row, fail, s0, syn_iter);
     }
 }
@@ -199,13 +202,14 @@ __global__ __launch_bounds__(256) void check_chunk_kernel(
 // combined u (its D aggregate), sign parity and syndrome parity go to scratch,
 // one wavefront scans the chunk aggregates into per-chunk exclusive values,
 // and each chunk is then finished with a local prefix/suffix pass.
-template <int M, int MODE>
+template <int M, int MODE, int RULE>
 __global__ __launch_bounds__(256) void check_hub_kernel(
     const int32_t *__restrict__ rd, const int32_t *__restrict__ col_idx,
     int32_t nrows, const int32_t *__restrict__ chunk_base, const float *__restrict__ L,
     typename Codec<M>::T *__restrict__ R, const int32_t *__restrict__ iters, int32_t *__restrict__ fail,
     int32_t S, int32_t groups, int32_t syn_iter, float *__restrict__ aggD, float *__restrict__ aggPre,
-    int32_t *__restrict__ aggBits) {
+    int32_t *__restrict__ aggBits, float rp) {
+    using Rule = CheckRule<RULE>;
     constexpr int C = ldpc::kHubChunk;
     __shared__ int32_t total_bits[64];
     const int lane = threadIdx.x & 63;
@@ -227,7 +231,7 @@ __global__ __launch_bounds__(256) void check_hub_kernel(
     for (int c = wv; c < nch; c += nw) {
         const int j0 = e0 + c * C;
         const int dc = min(C, d - c * C);
-        float agg = 0.f;
+        float agg = Rule::identity();
         int32_t bits = 0;
 #pragma unroll
         for (int jj = 0; jj < C; jj++) {
@@ -237,7 +241,7 @@ __global__ __launch_bounds__(256) void check_hub_kernel(
                 const float r = (MODE == kIter) ? Codec<M>::dec(R[size_t(j0 + jj) * S + s]) : 0.f;
                 const float q = clamp_msg(lv - r);
                 bits ^= int32_t(q < 0.f) | (int32_t(lv < 0.f) << 1);
-                agg = dplus(agg, tanh_complement(fabsf(q)));
+                agg = Rule::combine(agg, Rule::input(fabsf(q)));
             }
         }
         aggD[size_t(cb + c) * S + s] = agg;
@@ -247,18 +251,18 @@ __global__ __launch_bounds__(256) void check_hub_kernel(
 
     // Phase B: exclusive prefix and suffix over chunks, serial in wave 0.
     if (wv == 0) {
-        float pre = 0.f;
+        float pre = Rule::identity();
         int32_t tot = 0;
         for (int c = 0; c < nch; c++) {
             aggPre[size_t(cb + c) * S + s] = pre;
-            pre = dplus(pre, aggD[size_t(cb + c) * S + s]);
+            pre = Rule::combine(pre, aggD[size_t(cb + c) * S + s]);
             tot ^= aggBits[size_t(cb + c) * S + s];
         }
-        float suf = 0.f;
+        float suf = Rule::identity();
         for (int c = nch - 1; c >= 0; c--) {
             const float dcur = aggD[size_t(cb + c) * S + s];
-            aggD[size_t(cb + c) * S + s] = dplus(aggPre[size_t(cb + c) * S + s], suf);
-            suf = dplus(suf, dcur);
+            aggD[size_t(cb + c) * S + s] = Rule::combine(aggPre[size_t(cb + c) * S + s], suf);
+            suf = Rule::combine(suf, dcur);
         }
         total_bits[lane] = tot;
         if (MODE == kIter && syn_iter > 0 && active && (tot & 2) && fail[s] != syn_iter) fail[s] = syn_iter;
@@ -280,25 +284,25 @@ __global__ __launch_bounds__(256) void check_hub_kernel(
                 const float r = (MODE == kIter) ? Codec<M>::dec(R[size_t(j0 + jj) * S + s]) : 0.f;
                 const float q = clamp_msg(lv - r);
                 neg |= uint32_t(q < 0.f) << jj;
-                u[jj] = tanh_complement(fabsf(q));
+                u[jj] = Rule::input(fabsf(q));
             }
         }
-        float run = 0.f;
+        float run = Rule::identity();
 #pragma unroll
         for (int jj = C - 1; jj >= 0; jj--) {
             if (jj < dc) {
                 sf[jj] = run;
-                run = dplus(u[jj], run);
+                run = Rule::combine(u[jj], run);
             }
         }
         run = aggD[size_t(cb + c) * S + s];
 #pragma unroll
         for (int jj = 0; jj < C; jj++) {
             if (jj < dc) {
-                const float mag = magnitude_from_complement(dplus(run, sf[jj]));
+                const float mag = Rule::magnitude(Rule::combine(run, sf[jj]), rp);
                 const uint32_t sgn = parity ^ ((neg >> jj) & 1u);
                 R[size_t(j0 + jj) * S + s] = Codec<M>::enc(sgn ? -mag : mag);
-                run = dplus(run, u[jj]);
+                run = Rule::combine(run, u[jj]);
             }
         }
     }
@@ -611,9 +615,9 @@ struct Bufs {
 
 inline unsigned blocks_for_waves(int64_t waves) { return unsigned((waves + 3) / 4); }
 
-template <int M, int V, int DMAX>
+template <int M, int V, int DMAX, int RULE>
 void launch_rows(const ldpc_graph *g, int cls, int mode, const float *L, const Bufs &b, int32_t S, int32_t syn_iter,
-                 hipStream_t st) {
+                 float rp, hipStream_t st) {
     const int32_t nrows = g->class_begin[cls + 1] - g->class_begin[cls];
     if (nrows == 0) return;
     const int32_t groups = S / (64 * V);
@@ -622,16 +626,16 @@ void launch_rows(const ldpc_graph *g, int cls, int mode, const float *L, const B
     T *R = static_cast<T *>(b.r);
     const int32_t *rd = g->d_class_rd + 2 * g->class_begin[cls];
     if (mode == kFirst)
-        hipLaunchKernelGGL((check_rows_kernel<M, V, DMAX, kFirst>), dim3(blocks), dim3(256), 0, st, rd, g->d_col_idx,
-                           nrows, L, R, b.iters, b.fail, S, groups, 0);
+        hipLaunchKernelGGL((check_rows_kernel<M, V, DMAX, kFirst, RULE>), dim3(blocks), dim3(256), 0, st, rd,
+                           g->d_col_idx, nrows, L, R, b.iters, b.fail, S, groups, 0, rp);
     else
-        hipLaunchKernelGGL((check_rows_kernel<M, V, DMAX, kIter>), dim3(blocks), dim3(256), 0, st, rd, g->d_col_idx,
-                           nrows, L, R, b.iters, b.fail, S, groups, syn_iter);
+        hipLaunchKernelGGL((check_rows_kernel<M, V, DMAX, kIter, RULE>), dim3(blocks), dim3(256), 0, st, rd,
+                           g->d_col_idx, nrows, L, R, b.iters, b.fail, S, groups, syn_iter, rp);
 }
 
-template <int M, int V, int WPR>
+template <int M, int V, int WPR, int RULE>
 void launch_chunked(const ldpc_graph *g, int cls, int mode, const float *L, const Bufs &b, int32_t S,
-                    int32_t syn_iter, hipStream_t st) {
+                    int32_t syn_iter, float rp, hipStream_t st) {
     const int32_t nrows = g->class_begin[cls + 1] - g->class_begin[cls];
     if (nrows == 0) return;
     const int32_t groups = S / (64 * V);
@@ -641,15 +645,15 @@ void launch_chunked(const ldpc_graph *g, int cls, int mode, const float *L, cons
     T *R = static_cast<T *>(b.r);
     const int32_t *rd = g->d_class_rd + 2 * g->class_begin[cls];
     if (mode == kFirst)
-        hipLaunchKernelGGL((check_chunk_kernel<M, V, WPR, kFirst>), dim3(blocks), dim3(256), 0, st, rd, g->d_col_idx,
-                           nrows, L, R, b.iters, b.fail, S, groups, 0);
+        hipLaunchKernelGGL((check_chunk_kernel<M, V, WPR, kFirst, RULE>), dim3(blocks), dim3(256), 0, st, rd,
+                           g->d_col_idx, nrows, L, R, b.iters, b.fail, S, groups, 0, rp);
     else
-        hipLaunchKernelGGL((check_chunk_kernel<M, V, WPR, kIter>), dim3(blocks), dim3(256), 0, st, rd, g->d_col_idx,
-                           nrows, L, R, b.iters, b.fail, S, groups, syn_iter);
+        hipLaunchKernelGGL((check_chunk_kernel<M, V, WPR, kIter, RULE>), dim3(blocks), dim3(256), 0, st, rd,
+                           g->d_col_idx, nrows, L, R, b.iters, b.fail, S, groups, syn_iter, rp);
 }
 
-template <int M>
-void launch_hub(const ldpc_graph *g, int mode, const float *L, const Bufs &b, int32_t S, int32_t syn_iter,
+template <int M, int RULE>
+void launch_hub(const ldpc_graph *g, int mode, const float *L, const Bufs &b, int32_t S, int32_t syn_iter, float rp,
                 hipStream_t st) {
     const int32_t nrows = g->class_begin[ldpc::kClassHub + 1] - g->class_begin[ldpc::kClassHub];
     if (nrows == 0) return;
@@ -659,22 +663,40 @@ void launch_hub(const ldpc_graph *g, int mode, const float *L, const Bufs &b, in
     T *R = static_cast<T *>(b.r);
     const int32_t *rd = g->d_class_rd + 2 * g->class_begin[ldpc::kClassHub];
     if (mode == kFirst)
-        hipLaunchKernelGGL((check_hub_kernel<M, kFirst>), dim3(blocks), dim3(256), 0, st, rd, g->d_col_idx, nrows,
-                           g->d_hub_chunk_base, L, R, b.iters, b.fail, S, groups, 0, b.aggd, b.aggpre, b.aggbits);
+        hipLaunchKernelGGL((check_hub_kernel<M, kFirst, RULE>), dim3(blocks), dim3(256), 0, st, rd, g->d_col_idx,
+                           nrows, g->d_hub_chunk_base, L, R, b.iters, b.fail, S, groups, 0, b.aggd, b.aggpre,
+                           b.aggbits, rp);
     else
-        hipLaunchKernelGGL((check_hub_kernel<M, kIter>), dim3(blocks), dim3(256), 0, st, rd, g->d_col_idx, nrows,
-                           g->d_hub_chunk_base, L, R, b.iters, b.fail, S, groups, syn_iter, b.aggd, b.aggpre,
-                           b.aggbits);
+        hipLaunchKernelGGL((check_hub_kernel<M, kIter, RULE>), dim3(blocks), dim3(256), 0, st, rd, g->d_col_idx,
+                           nrows, g->d_hub_chunk_base, L, R, b.iters, b.fail, S, groups, syn_iter, b.aggd, b.aggpre,
+                           b.aggbits, rp);
 }
 
-template <int M, int V>
+template <int M, int V, int RULE>
 void launch_check_pass(const ldpc_graph *g, int mode, const float *L, const Bufs &b, int32_t S, int32_t syn_iter,
-                       hipStream_t st) {
-    launch_rows<M, V, 8>(g, ldpc::kClassD8, mode, L, b, S, syn_iter, st);
-    launch_rows<M, ldpc::class_lane_slots(ldpc::kClassD16, V), 16>(g, ldpc::kClassD16, mode, L, b, S, syn_iter, st);
-    launch_chunked<M, V, ldpc::class_waves_per_row(ldpc::kClassD128)>(g, ldpc::kClassD128, mode, L, b, S, syn_iter,
-                                                                       st);
-    launch_hub<M>(g, mode, L, b, S, syn_iter, st);
+                       float rp, hipStream_t st) {
+    launch_rows<M, V, 8, RULE>(g, ldpc::kClassD8, mode, L, b, S, syn_iter, rp, st);
+    launch_rows<M, ldpc::class_lane_slots(ldpc::kClassD16, V), 16, RULE>(g, ldpc::kClassD16, mode, L, b, S, syn_iter,
+                                                                         rp, st);
+    launch_chunked<M, V, ldpc::class_waves_per_row(ldpc::kClassD128), RULE>(g, ldpc::kClassD128, mode, L, b, S,
+                                                                             syn_iter, rp, st);
+    launch_hub<M, RULE>(g, mode, L, b, S, syn_iter, rp, st);
+}
+
+// The check rule of a decode call: kind (RuleKind) and parameter.
+struct RuleSel {
+    int kind = kRuleSP;
+    float param = 0.f;
+};
+
+template <int M, int V>
+void launch_check_pass_rule(const ldpc_graph *g, int mode, const float *L, const Bufs &b, int32_t S,
+                            int32_t syn_iter, const RuleSel &rule, hipStream_t st) {
+    switch (rule.kind) {
+        case kRuleNMS: launch_check_pass<M, V, kRuleNMS>(g, mode, L, b, S, syn_iter, rule.param, st); break;
+        case kRuleOMS: launch_check_pass<M, V, kRuleOMS>(g, mode, L, b, S, syn_iter, rule.param, st); break;
+        default: launch_check_pass<M, V, kRuleSP>(g, mode, L, b, S, syn_iter, 0.f, st); break;
+    }
 }
 
 // Optional event marks for the profiled entry point: mark(i) records event i
@@ -705,7 +727,7 @@ struct SimRun {
 template <int M, int V>
 void run_decode(const ldpc_graph *g, const Plan &p, const Bufs &b, const float *llr_in, int32_t F, int32_t T,
                 bool early_stop, uint8_t *bits, uint8_t *ok, int32_t *iters_out, float *llr_out, hipStream_t st,
-                const Marks &mk, const SimRun &sim = SimRun{}) {
+                const Marks &mk, const SimRun &sim, const RuleSel &rule) {
     using MT = typename Codec<M>::T;
     const int32_t S = p.S;
     const int32_t groups = S / (64 * V);
@@ -724,7 +746,7 @@ void run_decode(const ldpc_graph *g, const Plan &p, const Bufs &b, const float *
     const unsigned bit_blocks = blocks_for_waves(int64_t(g->n) * groups);
     for (int32_t t = 1; t <= T; t++) {
         const int32_t syn_iter = (early_stop && t > 1) ? t - 1 : 0;
-        launch_check_pass<M, V>(g, t == 1 ? kFirst : kIter, t == 1 ? b.lch : b.lpost, b, S, syn_iter, st);
+        launch_check_pass_rule<M, V>(g, t == 1 ? kFirst : kIter, t == 1 ? b.lch : b.lpost, b, S, syn_iter, rule, st);
         mk.mark(2 * t, st);
         hipLaunchKernelGGL((bit_kernel<M, V>), dim3(bit_blocks), dim3(256), 0, st, g->d_col_ptr, g->d_csc_to_csr,
                            g->n, b.lch, static_cast<const MT *>(b.r), b.lpost, b.iters, b.fail, S, groups, t,
@@ -755,11 +777,36 @@ void run_decode(const ldpc_graph *g, const Plan &p, const Bufs &b, const float *
 template <int M>
 void run_decode_v(const ldpc_graph *g, const Plan &p, const Bufs &b, const float *llr_in, int32_t F, int32_t T,
                   bool es, uint8_t *bits, uint8_t *ok, int32_t *it, float *lo, hipStream_t st, const Marks &mk,
-                  const SimRun &sim = SimRun{}) {
+                  const SimRun &sim, const RuleSel &rule) {
     switch (p.V) {
-        case 4: run_decode<M, 4>(g, p, b, llr_in, F, T, es, bits, ok, it, lo, st, mk, sim); break;
-        case 2: run_decode<M, 2>(g, p, b, llr_in, F, T, es, bits, ok, it, lo, st, mk, sim); break;
-        default: run_decode<M, 1>(g, p, b, llr_in, F, T, es, bits, ok, it, lo, st, mk, sim); break;
+        case 4: run_decode<M, 4>(g, p, b, llr_in, F, T, es, bits, ok, it, lo, st, mk, sim, rule); break;
+        case 2: run_decode<M, 2>(g, p, b, llr_in, F, T, es, bits, ok, it, lo, st, mk, sim, rule); break;
+        default: run_decode<M, 1>(g, p, b, llr_in, F, T, es, bits, ok, it, lo, st, mk, sim, rule); break;
+    }
+}
+
+// Validate an ldpc_rule (NULL: sum-product) into `out`.
+bool rule_from(const ldpc_rule *r, RuleSel &out, std::string &why) {
+    out = RuleSel{};
+    if (!r) return true;
+    for (int32_t x : r->reserved)
+        if (x != 0) { why = "reserved rule fields must be 0"; return false; }
+    switch (r->kind) {
+        case LDPC_RULE_SUM_PRODUCT:
+            return true;
+        case LDPC_RULE_MIN_SUM_NORMALIZED:
+            if (!(r->param > 0.f && r->param <= 1.f)) { why = "alpha must be in (0, 1]"; return false; }
+            out.kind = kRuleNMS;
+            out.param = r->param;
+            return true;
+        case LDPC_RULE_MIN_SUM_OFFSET:
+            if (!(r->param >= 0.f && r->param < kLmax)) { why = "beta must be in [0, 64)"; return false; }
+            out.kind = kRuleOMS;
+            out.param = r->param;
+            return true;
+        default:
+            why = "unknown rule kind";
+            return false;
     }
 }
 
@@ -791,10 +838,14 @@ Bufs bufs_at(char *ws, const Plan &p) {
 }
 
 ldpc_status decode_core(const char *fn, const ldpc_graph *g, const float *llr_in, int32_t frames, int32_t max_iter,
-                        uint32_t flags, uint8_t *bits_out, uint8_t *syndrome_ok, int32_t *iters, float *llr_out,
-                        void *workspace, size_t workspace_bytes, void *hip_stream, const Marks &mk) {
+                        uint32_t flags, const ldpc_rule *rule_in, uint8_t *bits_out, uint8_t *syndrome_ok,
+                        int32_t *iters, float *llr_out, void *workspace, size_t workspace_bytes, void *hip_stream,
+                        const Marks &mk) {
     const std::string f(fn);
     if (!g) { set_error(f + ": graph is NULL"); return LDPC_E_INVAL; }
+    RuleSel rule;
+    std::string why;
+    if (!rule_from(rule_in, rule, why)) { set_error(f + ": " + why); return LDPC_E_INVAL; }
     if (g->host_only) { set_error(f + ": graph was built host-only"); return LDPC_E_INVAL; }
     if (frames < 0) { set_error(f + ": frames < 0"); return LDPC_E_INVAL; }
     if (max_iter < 1) { set_error(f + ": max_iter must be >= 1"); return LDPC_E_INVAL; }
@@ -825,9 +876,18 @@ ldpc_status decode_core(const char *fn, const ldpc_graph *g, const float *llr_in
     const bool es = !(flags & LDPC_NO_EARLY_STOP);
     (void)hipGetLastError();
     switch (p.msg) {
-        case kF16: run_decode_v<kF16>(g, p, b, llr_in, frames, max_iter, es, bits_out, syndrome_ok, iters, llr_out, st, mk); break;
-        case kBF16: run_decode_v<kBF16>(g, p, b, llr_in, frames, max_iter, es, bits_out, syndrome_ok, iters, llr_out, st, mk); break;
-        default: run_decode_v<kF32>(g, p, b, llr_in, frames, max_iter, es, bits_out, syndrome_ok, iters, llr_out, st, mk); break;
+        case kF16:
+            run_decode_v<kF16>(g, p, b, llr_in, frames, max_iter, es, bits_out, syndrome_ok, iters, llr_out, st, mk,
+                               SimRun{}, rule);
+            break;
+        case kBF16:
+            run_decode_v<kBF16>(g, p, b, llr_in, frames, max_iter, es, bits_out, syndrome_ok, iters, llr_out, st, mk,
+                                SimRun{}, rule);
+            break;
+        default:
+            run_decode_v<kF32>(g, p, b, llr_in, frames, max_iter, es, bits_out, syndrome_ok, iters, llr_out, st, mk,
+                               SimRun{}, rule);
+            break;
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
@@ -842,8 +902,16 @@ ldpc_status decode_core(const char *fn, const ldpc_graph *g, const float *llr_in
 extern "C" ldpc_status ldpc_decode(const ldpc_graph *g, const float *llr_in, int32_t frames, int32_t max_iter,
                                    uint32_t flags, uint8_t *bits_out, uint8_t *syndrome_ok, int32_t *iters,
                                    float *llr_out, void *workspace, size_t workspace_bytes, void *hip_stream) {
-    return decode_core("ldpc_decode", g, llr_in, frames, max_iter, flags, bits_out, syndrome_ok, iters, llr_out,
-                       workspace, workspace_bytes, hip_stream, Marks{});
+    return decode_core("ldpc_decode", g, llr_in, frames, max_iter, flags, nullptr, bits_out, syndrome_ok, iters,
+                       llr_out, workspace, workspace_bytes, hip_stream, Marks{});
+}
+
+extern "C" ldpc_status ldpc_decode_rule(const ldpc_graph *g, const float *llr_in, int32_t frames, int32_t max_iter,
+                                        uint32_t flags, const ldpc_rule *rule, uint8_t *bits_out,
+                                        uint8_t *syndrome_ok, int32_t *iters, float *llr_out, void *workspace,
+                                        size_t workspace_bytes, void *hip_stream) {
+    return decode_core("ldpc_decode_rule", g, llr_in, frames, max_iter, flags, rule, bits_out, syndrome_ok, iters,
+                       llr_out, workspace, workspace_bytes, hip_stream, Marks{});
 }
 
 extern "C" ldpc_status ldpc_decode_profiled(const ldpc_graph *g, const float *llr_in, int32_t frames,
@@ -853,8 +921,8 @@ extern "C" ldpc_status ldpc_decode_profiled(const ldpc_graph *g, const float *ll
                                             float *bit_ms, float *edge_ms) {
     if (!check_ms || !bit_ms || !edge_ms) { set_error("ldpc_decode_profiled: NULL timing array"); return LDPC_E_INVAL; }
     if (frames <= 0 || max_iter < 1)
-        return decode_core("ldpc_decode_profiled", g, llr_in, frames, max_iter, flags, bits_out, syndrome_ok, iters,
-                           llr_out, workspace, workspace_bytes, hip_stream, Marks{});
+        return decode_core("ldpc_decode_profiled", g, llr_in, frames, max_iter, flags, nullptr, bits_out, syndrome_ok,
+                           iters, llr_out, workspace, workspace_bytes, hip_stream, Marks{});
     const int nev = 2 * max_iter + 3;
     std::vector<hipEvent_t> ev(size_t(nev), nullptr);
     for (int i = 0; i < nev; i++) {
@@ -867,8 +935,8 @@ extern "C" ldpc_status ldpc_decode_profiled(const ldpc_graph *g, const float *ll
     }
     Marks mk;
     mk.ev = ev.data();
-    ldpc_status stt = decode_core("ldpc_decode_profiled", g, llr_in, frames, max_iter, flags, bits_out, syndrome_ok,
-                                  iters, llr_out, workspace, workspace_bytes, hip_stream, mk);
+    ldpc_status stt = decode_core("ldpc_decode_profiled", g, llr_in, frames, max_iter, flags, nullptr, bits_out,
+                                  syndrome_ok, iters, llr_out, workspace, workspace_bytes, hip_stream, mk);
     if (stt == LDPC_OK) {
         if (hipStreamSynchronize(static_cast<hipStream_t>(hip_stream)) != hipSuccess) {
             (void)hipGetLastError();
@@ -901,12 +969,17 @@ extern "C" ldpc_status ldpc_simulate_workspace_size(const ldpc_graph *g, int32_t
     return LDPC_OK;
 }
 
-extern "C" ldpc_status ldpc_simulate(const ldpc_graph *g, int32_t frames, double ebn0_db, uint64_t seed,
-                                     uint64_t first_frame, int32_t max_iter, uint32_t flags,
-                                     ldpc_sim_counts *counts, float *llr_out, void *workspace,
-                                     size_t workspace_bytes, void *hip_stream) {
-    const std::string f("ldpc_simulate");
+namespace {
+
+ldpc_status simulate_core(const char *fn, const ldpc_graph *g, int32_t frames, double ebn0_db, uint64_t seed,
+                          uint64_t first_frame, int32_t max_iter, uint32_t flags, const ldpc_rule *rule_in,
+                          ldpc_sim_counts *counts, float *llr_out, void *workspace, size_t workspace_bytes,
+                          void *hip_stream) {
+    const std::string f(fn);
     if (!g || !counts) { set_error(f + ": NULL graph or counts"); return LDPC_E_INVAL; }
+    RuleSel rule;
+    std::string why;
+    if (!rule_from(rule_in, rule, why)) { set_error(f + ": " + why); return LDPC_E_INVAL; }
     if (g->host_only) { set_error(f + ": graph was built host-only"); return LDPC_E_INVAL; }
     if (frames < 0) { set_error(f + ": frames < 0"); return LDPC_E_INVAL; }
     if (max_iter < 1) { set_error(f + ": max_iter must be >= 1"); return LDPC_E_INVAL; }
@@ -955,15 +1028,15 @@ extern "C" ldpc_status ldpc_simulate(const ldpc_graph *g, int32_t frames, double
     switch (p.msg) {
         case kF16:
             run_decode_v<kF16>(g, p, b, nullptr, frames, max_iter, es, nullptr, nullptr, nullptr, nullptr, st, Marks{},
-                               sim);
+                               sim, rule);
             break;
         case kBF16:
             run_decode_v<kBF16>(g, p, b, nullptr, frames, max_iter, es, nullptr, nullptr, nullptr, nullptr, st,
-                                Marks{}, sim);
+                                Marks{}, sim, rule);
             break;
         default:
             run_decode_v<kF32>(g, p, b, nullptr, frames, max_iter, es, nullptr, nullptr, nullptr, nullptr, st, Marks{},
-                               sim);
+                               sim, rule);
             break;
     }
     const hipError_t e = hipGetLastError();
@@ -972,4 +1045,22 @@ extern "C" ldpc_status ldpc_simulate(const ldpc_graph *g, int32_t frames, double
         return LDPC_E_DEVICE;
     }
     return LDPC_OK;
+}
+
+}  // namespace
+
+extern "C" ldpc_status ldpc_simulate(const ldpc_graph *g, int32_t frames, double ebn0_db, uint64_t seed,
+                                     uint64_t first_frame, int32_t max_iter, uint32_t flags,
+                                     ldpc_sim_counts *counts, float *llr_out, void *workspace,
+                                     size_t workspace_bytes, void *hip_stream) {
+    return simulate_core("ldpc_simulate", g, frames, ebn0_db, seed, first_frame, max_iter, flags, nullptr, counts,
+                         llr_out, workspace, workspace_bytes, hip_stream);
+}
+
+extern "C" ldpc_status ldpc_simulate_rule(const ldpc_graph *g, int32_t frames, double ebn0_db, uint64_t seed,
+                                          uint64_t first_frame, int32_t max_iter, uint32_t flags,
+                                          const ldpc_rule *rule, ldpc_sim_counts *counts, float *llr_out,
+                                          void *workspace, size_t workspace_bytes, void *hip_stream) {
+    return simulate_core("ldpc_simulate_rule", g, frames, ebn0_db, seed, first_frame, max_iter, flags, rule, counts,
+                         llr_out, workspace, workspace_bytes, hip_stream);
 }

@@ -109,10 +109,11 @@ __device__ __forceinline__ void store_i32(int32_t *p, const int32_t (&in)[V]) {
 
 // -------------------------------------------------------------- check math
 
-// u = 1 - tanh(x/2) = 2w/(1+w) with w = e^-x, for x = |Q| >= 0.
+// u = 1 - tanh(x/2) = 2w/(1+w) = w / ((1+w)/2) with w = e^-x, for x = |Q| >= 0
+// (the halved denominator is one fma and saves the doubling).
 __device__ __forceinline__ float tanh_complement(float x) {
     const float w = __builtin_amdgcn_exp2f(-x * kLog2e);
-    return 2.f * w * __builtin_amdgcn_rcpf(1.f + w);
+    return w * __builtin_amdgcn_rcpf(fmaf(0.5f, w, 0.5f));
 }
 
 // Complement of a product of complements: 1 - (1-a)(1-b) = a + b(1-a).
@@ -125,6 +126,45 @@ __device__ __forceinline__ float magnitude_from_complement(float D) {
 }
 
 __device__ __forceinline__ float clamp_msg(float q) { return fminf(fmaxf(q, -kLmax), kLmax); }
+
+// Check-node rules.  Every rule takes the sign of R from the other inputs' sign
+// product and its magnitude from an aggregate of the other inputs, formed with
+// an associative operation (exclusive prefix/suffix combinations, never "total
+// minus own"):
+//   kRuleSP   sum-product (Algorithm 1): input u = 1 - tanh(|Q|/2), aggregate
+//             D = 1 - prod(1 - u), |R| = ln((2 - D)/D);
+//   kRuleNMS  normalized Min-Sum: aggregate min |Q|, |R| = alpha * min
+//             (alpha = 1: plain Min-Sum);
+//   kRuleOMS  offset Min-Sum: aggregate min |Q|, |R| = max(min - beta, 0);
+// the derived decoders Section 3.1 names for the edge-level approach (after
+// Wu, Song, Jiang and Zhao, IEEE Commun. Lett. 14(7), 2010).  |R| is clamped to
+// LMAX; an empty aggregate (degree-1 check) gives LMAX under every rule.
+enum RuleKind { kRuleSP = 0, kRuleNMS = 1, kRuleOMS = 2 };
+
+template <int RULE> struct CheckRule;
+
+template <> struct CheckRule<kRuleSP> {
+    static __device__ __forceinline__ float identity() { return 0.f; }
+    static __device__ __forceinline__ float input(float qa) { return tanh_complement(qa); }
+    static __device__ __forceinline__ float combine(float a, float b) { return dplus(a, b); }
+    static __device__ __forceinline__ float magnitude(float agg, float) { return magnitude_from_complement(agg); }
+};
+
+template <> struct CheckRule<kRuleNMS> {
+    static __device__ __forceinline__ float identity() { return __builtin_inff(); }
+    static __device__ __forceinline__ float input(float qa) { return qa; }
+    static __device__ __forceinline__ float combine(float a, float b) { return fminf(a, b); }
+    static __device__ __forceinline__ float magnitude(float m, float alpha) { return fminf(alpha * m, kLmax); }
+};
+
+template <> struct CheckRule<kRuleOMS> {
+    static __device__ __forceinline__ float identity() { return __builtin_inff(); }
+    static __device__ __forceinline__ float input(float qa) { return qa; }
+    static __device__ __forceinline__ float combine(float a, float b) { return fminf(a, b); }
+    static __device__ __forceinline__ float magnitude(float m, float beta) {
+        return fminf(fmaxf(m - beta, 0.f), kLmax);
+    }
+};
 
 __device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
@@ -150,14 +190,15 @@ struct SlotSrc {
 };
 
 // Inputs of edges j0 .. j0+count-1 (1 <= count <= C) for the lane's slots:
-// Q = clamp(L - R_old), its sign bit (bit j of neg) and u = 1 - tanh(|Q|/2);
+// Q = clamp(L - R_old), its sign bit (bit j of neg) and the rule's input u
+// (1 - tanh(|Q|/2) for sum-product, |Q| for Min-Sum);
 // the sign of L feeds the syndrome of the estimate that L holds (Algorithm 7).
 // Every index load and then every message load is issued before any value is
 // used: positions past `count` repeat the last edge (same addresses, no
 // branch), so the loads of a row are in flight together instead of one edge
 // at a time.  UNIFORM: all lanes walk the same row (indices read once per
 // wavefront).
-template <int M, int V, int C, bool UNIFORM, int IN>
+template <int M, int V, int C, bool UNIFORM, int IN, int RULE = kRuleSP>
 __device__ __forceinline__ void gather_edges(const int32_t *__restrict__ col_idx, int j0, int count,
                                              const float *__restrict__ L,
                                              const typename Codec<M>::T *__restrict__ R, int32_t S, int s0,
@@ -197,7 +238,7 @@ __device__ __forceinline__ void gather_edges(const int32_t *__restrict__ col_idx
                 syn[k] ^= (lv[j][k] < 0.f);
                 const float q = clamp_msg(lv[j][k] - r[j][k]);
                 neg[k] |= uint32_t(q < 0.f) << j;
-                u[j][k] = tanh_complement(fabsf(q));
+                u[j][k] = CheckRule<RULE>::input(fabsf(q));
             }
         }
     }
@@ -207,47 +248,77 @@ __device__ __forceinline__ void gather_edges(const int32_t *__restrict__ col_idx
 // suffixes, then exclusive prefixes combined on the fly; R is updated in place.
 // UNIFORM: every lane of the wavefront works on the same row (indices are read
 // once per wavefront); otherwise each lane walks its own row.
-template <int M, int V, int DMAX, bool UNIFORM, int IN>
-__device__ __forceinline__ void row_rule(const int32_t *__restrict__ col_idx, int e0, int d,
+template <int M, int V, int DMAX, bool UNIFORM, int IN, int RULE = kRuleSP>
+__device__ __forceinline__ void row_rule_n(const int32_t *__restrict__ col_idx, int e0, int d,
                                          const float *__restrict__ L,
                                          typename Codec<M>::T *__restrict__ R, int32_t S, int s0,
-                                         const SlotSrc<V> &src, int (&syn)[V]) {
+                                         const SlotSrc<V> &src, int (&syn)[V], float rp = 0.f) {
+    using Rule = CheckRule<RULE>;
     float u[DMAX][V];
     float suf[DMAX][V];
     uint32_t neg[V];
 #pragma unroll
     for (int k = 0; k < V; k++) neg[k] = 0u;
-    gather_edges<M, V, DMAX, UNIFORM, IN>(col_idx, e0, d, L, R, S, s0, src, u, neg, syn);
+    gather_edges<M, V, DMAX, UNIFORM, IN, RULE>(col_idx, e0, d, L, R, S, s0, src, u, neg, syn);
     float run[V];
 #pragma unroll
-    for (int k = 0; k < V; k++) run[k] = 0.f;
+    for (int k = 0; k < V; k++) run[k] = Rule::identity();
 #pragma unroll
     for (int j = DMAX - 1; j >= 0; j--) {
         if (j < d) {
 #pragma unroll
             for (int k = 0; k < V; k++) {
                 suf[j][k] = run[k];
-                run[k] = dplus(u[j][k], run[k]);
+                run[k] = Rule::combine(u[j][k], run[k]);
             }
         }
     }
     uint32_t parity[V];
 #pragma unroll
-    for (int k = 0; k < V; k++) { run[k] = 0.f; parity[k] = __builtin_popcount(neg[k]) & 1u; }
+    for (int k = 0; k < V; k++) { run[k] = Rule::identity(); parity[k] = __builtin_popcount(neg[k]) & 1u; }
 #pragma unroll
     for (int j = 0; j < DMAX; j++) {
         if (j < d) {
             float out[V];
 #pragma unroll
             for (int k = 0; k < V; k++) {
-                const float mag = magnitude_from_complement(dplus(run[k], suf[j][k]));
+                const float mag = Rule::magnitude(Rule::combine(run[k], suf[j][k]), rp);
                 const uint32_t sgn = parity[k] ^ ((neg[k] >> j) & 1u);
                 out[k] = sgn ? -mag : mag;
-                run[k] = dplus(run[k], u[j][k]);
+                run[k] = Rule::combine(run[k], u[j][k]);
             }
             store_vec<M, V>(R + size_t(e0 + j) * S + s0, out);
         }
     }
+}
+
+// row_rule_n with the degree as a compile-time constant when every lane works
+// on the same row of at most 8 edges: the row's code is then straight-line
+// (no per-position test of the degree).  Other rows take the generic form.
+template <int M, int V, int D, bool UNIFORM, int IN, int RULE>
+__device__ __forceinline__ bool row_rule_fixed(const int32_t *__restrict__ col_idx, int e0, int d,
+                                               const float *__restrict__ L, typename Codec<M>::T *__restrict__ R,
+                                               int32_t S, int s0, const SlotSrc<V> &src, int (&syn)[V], float rp) {
+    if (d != D) return false;
+    row_rule_n<M, V, D, UNIFORM, IN, RULE>(col_idx, e0, D, L, R, S, s0, src, syn, rp);
+    return true;
+}
+
+template <int M, int V, int DMAX, bool UNIFORM, int IN, int RULE = kRuleSP>
+__device__ __forceinline__ void row_rule(const int32_t *__restrict__ col_idx, int e0, int d,
+                                         const float *__restrict__ L,
+                                         typename Codec<M>::T *__restrict__ R, int32_t S, int s0,
+                                         const SlotSrc<V> &src, int (&syn)[V], float rp = 0.f) {
+    if constexpr (UNIFORM && DMAX == 8) {
+        if (row_rule_fixed<M, V, 8, UNIFORM, IN, RULE>(col_idx, e0, d, L, R, S, s0, src, syn, rp) ||
+            row_rule_fixed<M, V, 7, UNIFORM, IN, RULE>(col_idx, e0, d, L, R, S, s0, src, syn, rp) ||
+            row_rule_fixed<M, V, 6, UNIFORM, IN, RULE>(col_idx, e0, d, L, R, S, s0, src, syn, rp) ||
+            row_rule_fixed<M, V, 5, UNIFORM, IN, RULE>(col_idx, e0, d, L, R, S, s0, src, syn, rp) ||
+            row_rule_fixed<M, V, 4, UNIFORM, IN, RULE>(col_idx, e0, d, L, R, S, s0, src, syn, rp) ||
+            row_rule_fixed<M, V, 3, UNIFORM, IN, RULE>(col_idx, e0, d, L, R, S, s0, src, syn, rp))
+            return;
+    }
+    row_rule_n<M, V, DMAX, UNIFORM, IN, RULE>(col_idx, e0, d, L, R, S, s0, src, syn, rp);
 }
 
 // Posterior sum Lch + sum of the bit's incoming messages, added in column
@@ -287,7 +358,7 @@ __device__ __forceinline__ void bit_sum(const int32_t *__restrict__ csc_to_csr, 
 // (pre), of the chunks after it (post) and the row's total sign parity.
 constexpr int kRowChunk = 8;
 
-template <int M, int V, int C, int IN>
+template <int M, int V, int C, int IN, int RULE = kRuleSP>
 __device__ __forceinline__ void chunk_load(const int32_t *__restrict__ col_idx, int j0, int dc,
                                            const float *__restrict__ L,
                                            const typename Codec<M>::T *__restrict__ R, int32_t S, int s0,
@@ -295,26 +366,27 @@ __device__ __forceinline__ void chunk_load(const int32_t *__restrict__ col_idx, 
                                            float (&agg)[V], uint32_t (&neg)[V], int (&syn)[V]) {
 #pragma unroll
     for (int k = 0; k < V; k++) { neg[k] = 0u; syn[k] = 0; }
-    gather_edges<M, V, C, true, IN>(col_idx, j0, dc, L, R, S, s0, src, u, neg, syn);
+    gather_edges<M, V, C, true, IN, RULE>(col_idx, j0, dc, L, R, S, s0, src, u, neg, syn);
 #pragma unroll
-    for (int k = 0; k < V; k++) agg[k] = 0.f;
+    for (int k = 0; k < V; k++) agg[k] = CheckRule<RULE>::identity();
 #pragma unroll
     for (int j = C - 1; j >= 0; j--) {
         if (j < dc) {
 #pragma unroll
             for (int k = 0; k < V; k++) {
                 suf[j][k] = agg[k];
-                agg[k] = dplus(u[j][k], agg[k]);
+                agg[k] = CheckRule<RULE>::combine(u[j][k], agg[k]);
             }
         }
     }
 }
 
-template <int M, int V, int C>
+template <int M, int V, int C, int RULE = kRuleSP>
 __device__ __forceinline__ void chunk_store(int j0, int dc, const float (&u)[C][V], const float (&suf)[C][V],
                                             const uint32_t (&neg)[V], const float (&pre)[V], const float (&post)[V],
                                             const uint32_t (&parity)[V], typename Codec<M>::T *__restrict__ R,
-                                            int32_t S, int s0) {
+                                            int32_t S, int s0, float rp = 0.f) {
+    using Rule = CheckRule<RULE>;
     float run[V];
 #pragma unroll
     for (int k = 0; k < V; k++) run[k] = pre[k];
@@ -324,10 +396,10 @@ __device__ __forceinline__ void chunk_store(int j0, int dc, const float (&u)[C][
             float out[V];
 #pragma unroll
             for (int k = 0; k < V; k++) {
-                const float mag = magnitude_from_complement(dplus(run[k], dplus(suf[j][k], post[k])));
+                const float mag = Rule::magnitude(Rule::combine(run[k], Rule::combine(suf[j][k], post[k])), rp);
                 const uint32_t sgn = parity[k] ^ ((neg[k] >> j) & 1u);
                 out[k] = sgn ? -mag : mag;
-                run[k] = dplus(run[k], u[j][k]);
+                run[k] = Rule::combine(run[k], u[j][k]);
             }
             store_vec<M, V>(R + size_t(j0 + j) * S + s0, out);
         }
@@ -353,23 +425,24 @@ __device__ __forceinline__ uint32_t pack_bits(const uint32_t (&neg)[V], const in
 
 // pre/post aggregates and total parities of chunk `ch` of a row of nch chunks
 // whose entries start at `base` in the shared table.
-template <int V, int ENTRIES>
+template <int V, int ENTRIES, int RULE = kRuleSP>
 __device__ __forceinline__ void chunk_context(const ChunkShare<V, ENTRIES> &sh, int base, int nch, int ch, int lane,
                                               float (&pre)[V], float (&post)[V], uint32_t (&parity)[V],
                                               int (&syn)[V]) {
+    using Rule = CheckRule<RULE>;
     uint32_t tot = 0u;
 #pragma unroll
-    for (int k = 0; k < V; k++) { pre[k] = 0.f; post[k] = 0.f; }
+    for (int k = 0; k < V; k++) { pre[k] = Rule::identity(); post[k] = Rule::identity(); }
     for (int c = 0; c < nch; c++) {
         tot ^= sh.bits[base + c][lane];
         if (c < ch) {
 #pragma unroll
-            for (int k = 0; k < V; k++) pre[k] = dplus(pre[k], sh.agg[base + c][lane][k]);
+            for (int k = 0; k < V; k++) pre[k] = Rule::combine(pre[k], sh.agg[base + c][lane][k]);
         }
     }
     for (int c = nch - 1; c > ch; c--) {
 #pragma unroll
-        for (int k = 0; k < V; k++) post[k] = dplus(sh.agg[base + c][lane][k], post[k]);
+        for (int k = 0; k < V; k++) post[k] = Rule::combine(sh.agg[base + c][lane][k], post[k]);
     }
 #pragma unroll
     for (int k = 0; k < V; k++) { parity[k] = (tot >> k) & 1u; syn[k] = int((tot >> (8 + k)) & 1u); }

@@ -29,8 +29,8 @@ LANE_SLOTS_4 = 1 << 5
 GRAPH_HOST_ONLY = 1 << 0
 
 EXPORTED = ("ldpc_graph_create", "ldpc_graph_destroy", "ldpc_graph_info", "ldpc_graph_arrays",
-            "ldpc_decode_workspace_size", "ldpc_decode", "ldpc_decode_profiled", "ldpc_simulate_workspace_size",
-            "ldpc_simulate", "ldpc_status_str",
+            "ldpc_decode_workspace_size", "ldpc_decode", "ldpc_decode_rule", "ldpc_decode_profiled",
+            "ldpc_simulate_workspace_size", "ldpc_simulate", "ldpc_simulate_rule", "ldpc_status_str",
             "ldpc_last_error", "ldpc_engine_create", "ldpc_engine_destroy", "ldpc_engine_info",
             "ldpc_engine_submit", "ldpc_engine_capacity", "ldpc_engine_step", "ldpc_engine_poll",
             "ldpc_engine_run", "ldpc_engine_stream", "ldpc_engine_autotune", "ldpc_server_create", "ldpc_server_submit",
@@ -46,6 +46,25 @@ class Frame(ctypes.Structure):
 class ServerOpts(ctypes.Structure):
     _fields_ = [("lane_slots", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("max_requests", ctypes.c_int32),
                 ("reserved", ctypes.c_int32 * 5)]
+
+
+class Rule(ctypes.Structure):
+    """ldpc_rule: check rule kind and parameter."""
+    _fields_ = [("kind", ctypes.c_int32), ("param", ctypes.c_float), ("reserved", ctypes.c_int32 * 2)]
+
+
+# check rules by name: (kind, default parameter); "ms" is the normalized rule with alpha = 1
+RULE_SUM_PRODUCT, RULE_MIN_SUM_NORMALIZED, RULE_MIN_SUM_OFFSET = 0, 1, 2
+RULES = {"sp": (RULE_SUM_PRODUCT, 0.0), "ms": (RULE_MIN_SUM_NORMALIZED, 1.0),
+         "nms": (RULE_MIN_SUM_NORMALIZED, 0.75), "oms": (RULE_MIN_SUM_OFFSET, 0.25)}
+
+
+def make_rule(rule=None, param=None):
+    """A Rule from a name in RULES (None: sum-product) and an optional parameter."""
+    if isinstance(rule, Rule):
+        return rule
+    kind, default = RULES["sp" if rule is None else rule]
+    return Rule(kind, default if (param is None or rule == "ms") else float(param))
 
 
 class EngineOpts(ctypes.Structure):
@@ -83,13 +102,16 @@ def load_library():
     lib.ldpc_graph_arrays.argtypes = [P, P, P, P, P, P]
     lib.ldpc_decode_workspace_size.argtypes = [P, I32, U32, ctypes.POINTER(ctypes.c_size_t)]
     lib.ldpc_decode.argtypes = [P, P, I32, I32, U32, P, P, P, P, P, ctypes.c_size_t, P]
+    lib.ldpc_decode_rule.argtypes = [P, P, I32, I32, U32, P, P, P, P, P, P, ctypes.c_size_t, P]
     lib.ldpc_decode_profiled.argtypes = [P, P, I32, I32, U32, P, P, P, P, P, ctypes.c_size_t, P, P, P, P]
     lib.ldpc_simulate_workspace_size.argtypes = [P, I32, U32, ctypes.POINTER(ctypes.c_size_t)]
     lib.ldpc_simulate.argtypes = [P, I32, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64, I32, U32, P, P, P,
                                   ctypes.c_size_t, P]
+    lib.ldpc_simulate_rule.argtypes = [P, I32, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64, I32, U32, P, P, P,
+                                       P, ctypes.c_size_t, P]
     for f in ("ldpc_graph_create", "ldpc_graph_destroy", "ldpc_graph_info", "ldpc_graph_arrays",
-              "ldpc_decode_workspace_size", "ldpc_decode", "ldpc_decode_profiled", "ldpc_simulate_workspace_size",
-              "ldpc_simulate"):
+              "ldpc_decode_workspace_size", "ldpc_decode", "ldpc_decode_rule", "ldpc_decode_profiled",
+              "ldpc_simulate_workspace_size", "ldpc_simulate", "ldpc_simulate_rule"):
         getattr(lib, f).restype = ctypes.c_int
     lib.ldpc_engine_create.argtypes = [P, I32, P, P, I32, U32, P, ctypes.POINTER(P)]
     lib.ldpc_engine_destroy.argtypes = [P]
@@ -245,15 +267,23 @@ def _prepare(graph: Graph, llr, flags: int, want_llr: bool, workspace, stream, o
 
 
 def decode(graph: Graph, llr, max_iter: int, flags: int = 0, want_llr: bool = False,
-           workspace: Workspace | None = None, stream=None, out: DecodeResult | None = None) -> DecodeResult:
+           workspace: Workspace | None = None, stream=None, out: DecodeResult | None = None, rule=None,
+           rule_param=None) -> DecodeResult:
     """Enqueue ldpc_decode on `stream` (default: torch's current stream) and return the output tensors.
 
     `llr` is a contiguous float32 CUDA tensor [F][n].  The call does not
     synchronize; read the outputs after the stream reaches this point (torch
-    does that for you when you use them on the same stream).
+    does that for you when you use them on the same stream).  `rule` selects
+    the check rule by name ("sp", "ms", "nms", "oms"; None is sum-product) with
+    an optional `rule_param`; any rule goes through ldpc_decode_rule.
     """
     out, workspace, args, outs = _prepare(graph, llr, flags, want_llr, workspace, stream, out)
-    _check(graph._lib.ldpc_decode(*args, int(max_iter), int(flags), *outs), "ldpc_decode")
+    if rule is None:
+        _check(graph._lib.ldpc_decode(*args, int(max_iter), int(flags), *outs), "ldpc_decode")
+    else:
+        r = make_rule(rule, rule_param)
+        _check(graph._lib.ldpc_decode_rule(*args, int(max_iter), int(flags), ctypes.byref(r), *outs),
+               "ldpc_decode_rule")
     out._workspace = workspace   # keep the workspace alive until the stream has consumed it
     return out
 
@@ -283,12 +313,13 @@ def simulate_workspace_size(graph: Graph, frames: int, flags: int = 0) -> int:
 
 def simulate(graph: Graph, frames: int, ebn0_db: float, seed: int, max_iter: int, flags: int = 0,
              first_frame: int = 0, counts=None, want_llr: bool = False, workspace: Workspace | None = None,
-             stream=None):
+             stream=None, rule=None, rule_param=None):
     """Enqueue ldpc_simulate (all-zero codeword over BPSK/AWGN, noise drawn on the device).
 
     `counts` is a CUDA int64 tensor of 5 counters (SIM_FIELDS), added to;
     a zeroed one is made when None.  Returns (counts, llr or None); read them
-    after the stream reaches this point.
+    after the stream reaches this point.  `rule` / `rule_param` as in decode()
+    (through ldpc_simulate_rule).
     """
     import torch
     dev = torch.device("cuda", torch.cuda.current_device())
@@ -302,11 +333,15 @@ def simulate(graph: Graph, frames: int, ebn0_db: float, seed: int, max_iter: int
         workspace = Workspace(need, device=dev)
     if stream is None:
         stream = torch.cuda.current_stream(dev)
-    _check(graph._lib.ldpc_simulate(graph.handle, int(frames), float(ebn0_db), int(seed) & (2 ** 64 - 1),
-                                    int(first_frame), int(max_iter), int(flags), ctypes.c_void_p(counts.data_ptr()),
-                                    ctypes.c_void_p(llr.data_ptr()) if llr is not None else None,
-                                    ctypes.c_void_p(workspace.ptr), ctypes.c_size_t(workspace.nbytes),
-                                    ctypes.c_void_p(stream.cuda_stream)), "ldpc_simulate")
+    head = (graph.handle, int(frames), float(ebn0_db), int(seed) & (2 ** 64 - 1), int(first_frame), int(max_iter),
+            int(flags))
+    tail = (ctypes.c_void_p(counts.data_ptr()), ctypes.c_void_p(llr.data_ptr()) if llr is not None else None,
+            ctypes.c_void_p(workspace.ptr), ctypes.c_size_t(workspace.nbytes), ctypes.c_void_p(stream.cuda_stream))
+    if rule is None:
+        _check(graph._lib.ldpc_simulate(*head, *tail), "ldpc_simulate")
+    else:
+        r = make_rule(rule, rule_param)
+        _check(graph._lib.ldpc_simulate_rule(*head, ctypes.byref(r), *tail), "ldpc_simulate_rule")
     counts._workspace = workspace   # keep the workspace alive until the stream has consumed it
     return counts, llr
 

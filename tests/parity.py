@@ -29,12 +29,12 @@ RTOL = 1e-4
 TIE_MARGIN = 1e-3
 
 
-def gpu_decode(code, llr: np.ndarray, max_iter: int, flags: int = 0, graph=None):
+def gpu_decode(code, llr: np.ndarray, max_iter: int, flags: int = 0, graph=None, rule=None, param=None):
     import torch
     from paper_1609_01567_amd import ldpc
     g = graph if graph is not None else ldpc.Graph.from_code(code)
     x = torch.from_numpy(np.ascontiguousarray(llr, dtype=np.float32)).cuda()
-    res = ldpc.decode(g, x, max_iter, flags=flags, want_llr=True)
+    res = ldpc.decode(g, x, max_iter, flags=flags, want_llr=True, rule=rule, rule_param=param)
     torch.cuda.synchronize()
     return dict(bits=res.bits.cpu().numpy(), ok=res.ok.cpu().numpy(), iters=res.iters.cpu().numpy(),
                 lpost=res.llr.cpu().numpy())
@@ -42,19 +42,21 @@ def gpu_decode(code, llr: np.ndarray, max_iter: int, flags: int = 0, graph=None)
 
 def compare(code, llr, max_iter: int, early_stop: bool = True, flags: int = 0, frames=None,
             gpu=None, atol: float = ATOL, rtol: float = RTOL, margin: float = TIE_MARGIN,
-            require_all: bool = False, posterior_all: bool = False):
+            require_all: bool = False, posterior_all: bool = False, rule=None, param=None):
     """Decode on both sides and assert the parity bar; returns a stats dict.
 
     `frames` restricts the oracle to a subset of rows of `llr` (full-size
     cases); `gpu` may carry a GPU result decoded earlier for all rows.
+    `rule` / `param` select the check rule on both sides (None: sum-product).
     """
     from paper_1609_01567_amd import ldpc
     if not early_stop:
         flags |= ldpc.NO_EARLY_STOP
     if gpu is None:
-        gpu = gpu_decode(code, llr, max_iter, flags)
+        gpu = gpu_decode(code, llr, max_iter, flags, rule=rule, param=param)
     idx = np.arange(llr.shape[0]) if frames is None else np.asarray(frames)
-    ora = oracle.decode(code, llr[idx], max_iter, early_stop=early_stop, tie_margin=margin)
+    ora = oracle.decode(code, llr[idx], max_iter, early_stop=early_stop, tie_margin=margin,
+                        rule=rule or "sp", param=param)
     g = {k: v[idx] for k, v in gpu.items()}
     clear = ora["tie_risk"] == 0
     if require_all:

@@ -137,6 +137,28 @@ def test_decode_argument_checks_fail_before_device_work():
     assert lib.ldpc_decode(g.handle, None, 0, 5, 0, None, None, None, None, None, 0, None) in (ldpc.OK, ldpc.E_INVAL)
 
 
+def test_decode_rule_argument_checks():
+    lib = ldpc.load_library()
+    g = ldpc.Graph.from_code(li.code_14_7(), host_only=True)
+    P = ctypes.c_void_p
+    bufs = (P(8), P(8), None, P(256), 1 << 20, None)   # ok, iters, llr_out, workspace, bytes, stream
+    cases = [(ldpc.Rule(7, 0.0), b"kind"), (ldpc.Rule(ldpc.RULE_MIN_SUM_NORMALIZED, 0.0), b"alpha"),
+             (ldpc.Rule(ldpc.RULE_MIN_SUM_NORMALIZED, 1.5), b"alpha"),
+             (ldpc.Rule(ldpc.RULE_MIN_SUM_NORMALIZED, float("nan")), b"alpha"),
+             (ldpc.Rule(ldpc.RULE_MIN_SUM_OFFSET, -0.5), b"beta"), (ldpc.Rule(ldpc.RULE_MIN_SUM_OFFSET, 64.0), b"beta"),
+             (ldpc.Rule(ldpc.RULE_SUM_PRODUCT, 0.0, (ctypes.c_int32 * 2)(1, 0)), b"reserved")]
+    for rule, word in cases:
+        st = lib.ldpc_decode_rule(g.handle, P(8), 1, 5, 0, ctypes.byref(rule), P(8), *bufs)
+        assert st == ldpc.E_INVAL and word in lib.ldpc_last_error()
+        st = lib.ldpc_simulate_rule(g.handle, 1, 1.0, 1, 0, 5, 0, ctypes.byref(rule), P(8), None, P(256), 1 << 20,
+                                    None)
+        assert st == ldpc.E_INVAL and word in lib.ldpc_last_error()
+    # a valid rule gets as far as the graph checks
+    for rule in (None, ldpc.make_rule("ms"), ldpc.make_rule("nms", 0.8), ldpc.make_rule("oms", 0.3)):
+        st = lib.ldpc_decode_rule(g.handle, P(8), 1, 5, 0, ctypes.byref(rule) if rule else None, P(8), *bufs)
+        assert st == ldpc.E_INVAL and b"host-only" in lib.ldpc_last_error()
+
+
 def test_engine_argument_checks_fail_before_device_work():
     lib = ldpc.load_library()
     P = ctypes.c_void_p
@@ -151,6 +173,9 @@ def test_engine_argument_checks_fail_before_device_work():
                                   ctypes.byref(out)) == ldpc.E_INVAL
     bad = ldpc.EngineOpts(3, 0)
     assert lib.ldpc_engine_create(graphs, 1, one, one, 10, 0, ctypes.byref(bad), ctypes.byref(out)) == ldpc.E_INVAL
+    for ips in (-1, 17):
+        bad = ldpc.EngineOpts(0, 0, 0, ips)
+        assert lib.ldpc_engine_create(graphs, 1, one, one, 10, 0, ctypes.byref(bad), ctypes.byref(out)) == ldpc.E_INVAL
     assert not out
     for f in ("ldpc_engine_step", "ldpc_engine_poll", "ldpc_engine_run", "ldpc_engine_info"):
         fn = getattr(lib, f)

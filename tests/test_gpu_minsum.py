@@ -1,0 +1,183 @@
+"""GPU parity of the Min-Sum family check rules (ldpc_decode_rule,
+ldpc_simulate_rule) against the FP64 oracle, which is pinned independently
+(max-log MAP on single parity checks, max-marginals on trees, path-code closed
+forms).
+
+Min-Sum's check map passes the smallest input magnitude through unchanged, so
+it does not contract differences the way the sum-product rule does: an FP32
+and an FP64 run of the same frame separate roughly geometrically with the
+iterations, and on frames that stay undecoded for tens of iterations they end
+up on different trajectories.  Two regimes therefore carry the parity bar:
+
+* exact arithmetic: channel LLRs quantized to multiples of 1/8 (|L| <= 16),
+  as Min-Sum decoders are usually fed.  Plain and offset Min-Sum (beta a
+  multiple of 1/8), and normalized Min-Sum with alpha = 1/2 for a few
+  iterations, then only add, subtract, halve, compare and clamp values with
+  few significant bits, which both precisions (and FP16 storage) hold
+  exactly.  Every output, posteriors included, must then equal the oracle's
+  bit for bit on every frame, converged or not;
+* continuous LLRs: every frame's posterior after a fixed small number of
+  iterations must be within 1e-3 + 1e-4 |L| of the oracle's.
+"""
+import numpy as np
+import pytest
+
+import ldpc_inputs as li
+from parity import ATOL, RTOL, compare, first_iteration_bound, gpu_decode
+
+pytestmark = pytest.mark.gpu
+
+RULES = [("ms", None), ("nms", 0.75), ("oms", 0.25)]
+# rules whose arithmetic stays exact on LLRs quantized to 1/8 (with the iteration limit for alpha = 1/2)
+EXACT_RULES = [("ms", None, 50), ("oms", 0.5, 50), ("nms", 0.5, 8)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+
+
+def _announce(name, **kw):
+    print(f"[case] {name} {kw}", flush=True)
+
+
+def _classes_code():
+    rng = np.random.default_rng(11)
+    cdeg = np.concatenate([[300, 140, 64, 40, 33], rng.integers(3, 33, size=95)])
+    E = int(cdeg.sum())
+    bdeg = np.full(700, E // 700)
+    bdeg[: E - bdeg.sum()] += 1
+    return li.socket_code(bdeg, cdeg, seed=12)
+
+
+def _quantized(llr):
+    """LLRs rounded to multiples of 1/8 and clipped to +-16 (a uniform 8-bit quantizer)."""
+    return np.clip(np.round(llr.astype(np.float64) * 8.0) / 8.0, -16.0, 16.0).astype(np.float32)
+
+
+def _assert_identical(code, llr, T, rule, param, flags=0, frames=None):
+    import oracle
+    gpu = gpu_decode(code, llr, T, flags=flags, rule=rule, param=param)
+    idx = np.arange(llr.shape[0]) if frames is None else np.asarray(frames)
+    ora = oracle.decode(code, llr[idx], T, rule=rule, param=param)
+    for k in ("bits", "ok", "iters"):
+        assert (gpu[k][idx] == ora[k]).all(), k
+    assert (gpu["lpost"][idx].astype(np.float64) == ora["lpost"]).all()
+    return gpu, ora
+
+
+@pytest.mark.parametrize("rule,param,T", EXACT_RULES)
+def test_exact_regime_identical_to_oracle(rule, param, T):
+    """Every kernel class, degenerate rows and columns, ragged frame counts."""
+    cases = [(li.tiny_code(), li.awgn_llr(1024, 96, li.ebn0_to_sigma2(2.0, 0.5), seed=2001)),
+             (_classes_code(), li.awgn_llr(700, 70, 0.7, seed=13)),
+             (li.Code(m=4, n=5, rows=np.array([0, 1, 1, 1, 3, 3], np.int32),
+                      cols=np.array([0, 0, 1, 2, 2, 3], np.int32)),
+              np.random.default_rng(2).normal(0.5, 2.0, size=(333, 5)).astype(np.float32))]
+    for code, llr in cases:
+        _announce("minsum-exact", rule=rule, n=code.n, frames=llr.shape[0])
+        gpu, ora = _assert_identical(code, _quantized(llr), T, rule, param)
+        print(rule, code.n, "converged", int(ora["ok"].sum()), "of", llr.shape[0])
+
+
+@pytest.mark.parametrize("rule,param,T", EXACT_RULES[:2])
+def test_exact_regime_fp16_storage_identical(rule, param, T):
+    """|R| <= 64 in steps of 1/8 needs 9 significant bits: FP16 storage is exact too."""
+    from paper_1609_01567_amd import ldpc
+    code = _classes_code()
+    llr = _quantized(li.awgn_llr(code.n, 70, 0.7, seed=14))
+    _announce("minsum-exact-fp16", rule=rule)
+    _assert_identical(code, llr, T, rule, param, flags=ldpc.MSG_FP16)
+
+
+def test_exact_regime_large_code_sampled_frames():
+    code = li.large_code()
+    frames = 256
+    cw = li.Encoder(code).random_codewords(frames, seed=3002)
+    llr = _quantized(li.awgn_llr(code.n, frames, li.ebn0_to_sigma2(1.4, code.rate), seed=2032, codewords=cw))
+    _announce("minsum-exact-large", frames=frames)
+    gpu, ora = _assert_identical(code, llr, 50, "ms", None, frames=[0, 1, 127, 128, 255])
+    syn = code.syndrome(gpu["bits"]).any(axis=1)
+    assert (syn == (gpu["ok"] == 0)).all()
+    assert ((gpu["lpost"] < 0) == gpu["bits"].astype(bool)).all()
+
+
+@pytest.mark.parametrize("rule,param", RULES)
+def test_continuous_llrs_fixed_iterations(rule, param):
+    """Posteriors of every frame after 1, 2 and 3 iterations, over every class."""
+    for code, llr in ((li.tiny_code(), li.awgn_llr(1024, 96, li.ebn0_to_sigma2(2.0, 0.5), seed=2001)),
+                      (_classes_code(), li.awgn_llr(700, 70, 0.7, seed=13))):
+        _announce("minsum-continuous", rule=rule, n=code.n)
+        for T in (1, 2, 3):
+            compare(code, llr, T, early_stop=False, posterior_all=True, rule=rule, param=param)
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_reduced_precision_first_iteration_bound(prec):
+    """Iteration 1 under normalized Min-Sum: |R| <= min of the other |Lch|, and
+    storage rounds it once, so the posterior error stays below the FP32 bar
+    plus u times the first-iteration bound."""
+    from paper_1609_01567_amd import ldpc
+    import oracle
+    flag = ldpc.MSG_FP16 if prec == "fp16" else ldpc.MSG_BF16
+    u = 2.0 ** -11 if prec == "fp16" else 2.0 ** -8
+    code = _classes_code()
+    llr = li.awgn_llr(code.n, 70, 0.7, seed=72)
+    _announce("minsum-precision", prec=prec)
+    gpu = gpu_decode(code, llr, 1, flags=flag | ldpc.NO_EARLY_STOP, rule="nms", param=0.75)
+    ora = oracle.decode(code, llr, 1, early_stop=False, rule="nms", param=0.75)
+    bound = ATOL + RTOL * np.abs(ora["lpost"]) + u * first_iteration_bound(code, llr)
+    err = np.abs(gpu["lpost"].astype(np.float64) - ora["lpost"])
+    assert (err <= bound).all(), f"max excess {(err - bound).max():.3e}"
+    assert err.max() > 1e-4
+
+
+@pytest.mark.parametrize("rule,param", RULES)
+def test_tile_shapes_identical_and_alpha_one_is_min_sum(rule, param):
+    from paper_1609_01567_amd import ldpc
+    code = li.random_small_code(600, 300, 3, seed=8)
+    llr = li.awgn_llr(code.n, 300, li.ebn0_to_sigma2(1.2, code.rate), seed=9)
+    _announce("minsum-tiles", rule=rule)
+    ref = gpu_decode(code, llr, 30, flags=ldpc.LANE_SLOTS_1, rule=rule, param=param)
+    for fl in (ldpc.LANE_SLOTS_2, ldpc.LANE_SLOTS_4):
+        out = gpu_decode(code, llr, 30, flags=fl, rule=rule, param=param)
+        for k in ref:
+            assert (out[k] == ref[k]).all(), (fl, k)
+    if rule == "ms":
+        for other, p in (("nms", 1.0), ("oms", 0.0)):
+            out = gpu_decode(code, llr, 30, flags=ldpc.LANE_SLOTS_1, rule=other, param=p)
+            for k in ref:
+                assert (out[k] == ref[k]).all(), (other, k)
+
+
+@pytest.mark.parametrize("rule,param", RULES)
+def test_simulate_counts_equal_decode_of_the_same_llrs(rule, param):
+    import torch
+    from paper_1609_01567_amd import ldpc
+    code = li.random_small_code(600, 300, 3, seed=8)
+    g = ldpc.Graph.from_code(code)
+    _announce("minsum-simulate", rule=rule)
+    counts, llr = ldpc.simulate(g, 257, 1.6, 5, 30, want_llr=True, rule=rule, rule_param=param)
+    torch.cuda.synchronize()
+    got = ldpc.sim_counts(counts)
+    out = gpu_decode(code, llr.cpu().numpy(), 30, rule=rule, param=param)
+    err = out["bits"].astype(np.int64).sum(axis=1)
+    want = dict(frames=257, frame_errors=int((err > 0).sum()), bit_errors=int(err.sum()),
+                undetected=int(((err > 0) & (out["ok"] == 1)).sum()), iterations=int(out["iters"].sum()))
+    assert got == want
+
+
+def test_rule_argument_errors():
+    import torch
+    from paper_1609_01567_amd import ldpc
+    code = li.tiny_code()
+    g = ldpc.Graph.from_code(code)
+    x = torch.zeros((4, code.n), dtype=torch.float32, device="cuda")
+    for rule, p in (("nms", 0.0), ("nms", 2.0), ("oms", -1.0), ("oms", 100.0)):
+        with pytest.raises(ldpc.LdpcError):
+            ldpc.decode(g, x, 5, rule=rule, rule_param=p)
+        with pytest.raises(ldpc.LdpcError):
+            ldpc.simulate(g, 4, 1.0, 1, 5, rule=rule, rule_param=p)
+    torch.cuda.synchronize()

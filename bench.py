@@ -26,7 +26,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak, GB/s
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "check_rows_kernel_n64800_f256_4pts.json")
-DOMINANT = "void check_rows_kernel<0, 4, 8, 1>"
+DOMINANT = "void check_rows_kernel<0, 4, 8, 1, 0>"   # FP32, 4 slots per lane, rows <= 8, steady state, sum-product
 
 
 def kernel_source_sha():

@@ -27,6 +27,7 @@ __all__ = [
     "Code", "socket_code", "ebn0_to_sigma2", "awgn_llr", "code_14_7",
     "tiny_code", "large_code", "extreme_code", "batch_codes", "BATCH_SPECS",
     "tree_code", "spc_code", "path_code", "random_small_code", "sim_channel_llr",
+    "lifted_code", "large_qc_code",
 ]
 
 
@@ -178,6 +179,33 @@ def large_code(seed: int = 1002) -> Code:
     n, m = 64800, 32400
     bd = _block_profile(n, {8: 12960, 3: 19440, 2: 32400})
     return socket_code(bd, even_check_degrees(int(bd.sum()), m), seed, "large-64800")
+
+
+def lifted_code(base: Code, Z: int, seed: int, name: str = "") -> Code:
+    """Quasi-cyclic lifting of a base graph (a protograph without parallel edges).
+
+    Every base edge (i, j) becomes a Z x Z circulant with a seeded shift
+    s_ij in [0, Z): check i*Z + r joins bit j*Z + ((r + s_ij) mod Z).  Rows and
+    bits keep the base order block by block, so a block of Z consecutive checks
+    touches Z consecutive (rotated) bits of each of its column blocks.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shifts = rng.integers(0, Z, size=base.nnz)
+    r = np.arange(Z, dtype=np.int64)
+    rows = (base.rows.astype(np.int64)[:, None] * Z + r[None, :]).ravel()
+    cols = (base.cols.astype(np.int64)[:, None] * Z + (r[None, :] + shifts[:, None]) % Z).ravel()
+    order = np.lexsort((cols, rows))
+    return Code(m=base.m * Z, n=base.n * Z, rows=rows[order].astype(np.int32),
+                cols=cols[order].astype(np.int32), name=name)
+
+
+def large_qc_code(seed: int = 1012) -> Code:
+    """n=64800, m=32400 rate 1/2 with the large code's degree profile, lifted by Z=360
+    from a 90 x 180 base graph (36 degree-8, 54 degree-3, 90 degree-2 columns;
+    every base row of degree 7)."""
+    bd = _block_profile(180, {8: 36, 3: 54, 2: 90})
+    base = socket_code(bd, even_check_degrees(int(bd.sum()), 90), seed, "base-90-180")
+    return lifted_code(base, 360, seed + 1, "qc-64800")
 
 
 def _power_law(rng, lo, hi, alpha, size):

@@ -86,3 +86,32 @@ def test_channel_llr_statistics():
     # same noise: a transmitted 1 moves y by -2, i.e. the LLR by -4/sigma^2
     np.testing.assert_allclose(llr[:, ::2] - flipped[:, ::2], 4.0 / s2, rtol=0, atol=2e-5)
     assert (flipped[:, 1::2] == llr[:, 1::2]).all()
+
+
+def test_lifted_code_structure():
+    """Each base edge expands to a Z x Z circulant: check i*Z + r meets bit
+    j*Z + ((r + s) mod Z) for one shift s per base edge, degrees scale by Z."""
+    base = li.random_small_code(12, 6, 3, seed=3)
+    Z = 16
+    code = li.lifted_code(base, Z, seed=4)
+    assert (code.m, code.n, code.nnz) == (base.m * Z, base.n * Z, base.nnz * Z)
+    np.testing.assert_array_equal(np.bincount(code.cols, minlength=code.n), np.repeat(base.bit_degrees(), Z))
+    np.testing.assert_array_equal(code.check_degrees(), np.repeat(base.check_degrees(), Z))
+    bi, bj = code.rows // Z, code.cols // Z
+    for i, j in zip(base.rows.tolist(), base.cols.tolist()):
+        sel = (bi == i) & (bj == j)
+        r, c = code.rows[sel] % Z, code.cols[sel] % Z
+        assert sel.sum() == Z and sorted(r.tolist()) == list(range(Z))
+        shift = (c - r) % Z
+        assert (shift == shift[0]).all()            # one circulant per base edge
+    key = code.rows.astype(np.int64) * code.n + code.cols
+    assert np.unique(key).size == key.size
+
+
+def test_large_qc_code_profile_and_encoder():
+    code = li.large_qc_code()
+    assert (code.n, code.m, code.nnz) == (64800, 32400, 226800)
+    assert set(code.check_degrees().tolist()) == {7}
+    assert np.bincount(np.bincount(code.cols, minlength=code.n)).tolist() == [0, 0, 32400, 19440, 0, 0, 0, 0, 12960]
+    cw = li.Encoder(code).random_codewords(3, seed=5)
+    assert not code.syndrome(cw).any()

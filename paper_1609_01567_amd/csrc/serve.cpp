@@ -1,9 +1,10 @@
 // Request-serving loop over an ldpc_engine (the ldpc_server_* entry points).
 //
-// Client threads submit requests (host LLRs, copied at submit).  One worker
-// thread owns the engine: it admits waiting requests in arrival order while
-// the device-memory budget, a completion counter and the graph's engine queue
-// allow, uploads their LLRs on a copy stream that the engine waits for,
+// Client threads submit requests (host LLRs, copied at submit: straight into
+// the pinned staging arena while it has room, else into host memory).  One
+// worker thread owns the engine: it admits waiting requests in arrival order
+// while the device-memory budget, a completion counter and the graph's engine
+// queue allow, uploads their LLRs on a copy stream that the engine waits for,
 // queues their frames (each frame bumps the request's device counter when it
 // finishes), runs engine steps, and when a request's counter reaches its
 // frame count copies the results back and time-stamps the completion.
@@ -82,7 +83,10 @@ struct Request {
     std::vector<float> llr;
     size_t dev_off = 0, dev_bytes = 0, stage_off = 0, stage_bytes = 0, out_off = 0, out_bytes = 0;
     bool staged = false;
+    bool prestaged = false;    // LLRs copied into the pinned arena at submit
+    bool ready = false;        // the submitting thread has finished copying the LLRs
     int32_t counter = -1;
+    uint32_t counter_base = 0; // the counter's value when the request took it
     int64_t admit_round = 0;   // worker round of admission: counters of earlier replays predate its reset
     std::vector<uint8_t> bits, ok;
     std::vector<int32_t> iters;
@@ -112,6 +116,8 @@ struct ldpc_server {
     int32_t max_requests = 4096;
     std::unique_ptr<Arena> dev_arena, host_arena;
     std::vector<int32_t> free_counters;
+    std::vector<uint32_t> counter_total;   // frames counted on each counter so far (host mirror)
+    int64_t unstaged_waiting = 0;          // waiting requests whose LLRs are not in the pinned arena
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -145,19 +151,19 @@ bool admit_locked(ldpc_server *s, int64_t round) {
     std::vector<int64_t> queued(static_cast<size_t>(s->ngraphs), 0);
     while (!s->waiting.empty()) {
         Request *r = s->waiting.front();
-        if (s->free_counters.empty()) break;
+        if (!r->ready || s->free_counters.empty()) break;
         int32_t cap = 0;
         if (ldpc_engine_capacity(s->engine, r->graph, &cap) != LDPC_OK) return false;
         if (cap - queued[size_t(r->graph)] < r->frames) break;
-        size_t doff = 0, hoff = 0, ooff = 0;
+        size_t doff = 0, hoff = r->stage_off, ooff = 0;
         if (!s->dev_arena->alloc(r->dev_bytes, &doff)) break;
-        if (!s->host_arena->alloc(r->stage_bytes, &hoff)) {
+        if (!r->prestaged && !s->host_arena->alloc(r->stage_bytes, &hoff)) {
             s->dev_arena->release(doff, r->dev_bytes);
             break;
         }
         if (!s->host_arena->alloc(r->out_bytes, &ooff)) {
             s->dev_arena->release(doff, r->dev_bytes);
-            s->host_arena->release(hoff, r->stage_bytes);
+            if (!r->prestaged) s->host_arena->release(hoff, r->stage_bytes);
             break;
         }
         r->dev_off = doff;
@@ -166,6 +172,7 @@ bool admit_locked(ldpc_server *s, int64_t round) {
         r->staged = true;
         r->admit_round = round;
         r->counter = s->free_counters.back();
+        r->counter_base = s->counter_total[size_t(r->counter)];
         s->free_counters.pop_back();
         s->waiting.pop_front();
         const int32_t F = r->frames, nn = r->n;
@@ -174,10 +181,13 @@ bool admit_locked(ldpc_server *s, int64_t round) {
         uint8_t *d_bits = reinterpret_cast<uint8_t *>(base + req_llr_bytes(F, nn));
         uint8_t *d_ok = d_bits + ((size_t(F) * nn + 255) & ~size_t(255));
         int32_t *d_iters = reinterpret_cast<int32_t *>(d_ok + ((size_t(F) + 3) & ~size_t(3)));
-        std::memcpy(s->pinned + hoff, r->llr.data(), size_t(F) * nn * 4);
-        std::vector<float>().swap(r->llr);
+        if (!r->prestaged) {
+            std::memcpy(s->pinned + hoff, r->llr.data(), size_t(F) * nn * 4);
+            std::vector<float>().swap(r->llr);
+            s->unstaged_waiting--;
+        }
+        // the request's counter keeps counting from its previous total (no reset)
         hipError_t e = hipMemcpyAsync(d_llr, s->pinned + hoff, size_t(F) * nn * 4, hipMemcpyHostToDevice, s->copy);
-        if (e == hipSuccess) e = hipMemsetAsync(s->counters + r->counter, 0, 4, s->copy);
         if (e != hipSuccess) {
             set_error(std::string("upload failed: ") + hipGetErrorString(e));
             return false;
@@ -222,6 +232,7 @@ void complete_requests(ldpc_server *s, std::vector<Request *> &done) {
         r->t_done = now;
         s->host_arena->release(r->out_off, r->out_bytes);
         s->dev_arena->release(r->dev_off, r->dev_bytes);
+        s->counter_total[size_t(r->counter)] = r->counter_base + uint32_t(F);
         s->free_counters.push_back(r->counter);
         r->counter = -1;
         s->completed.push_back(r->id);
@@ -305,7 +316,8 @@ void worker_main(ldpc_server *s) {
                 std::lock_guard<std::mutex> lk(s->mu);
                 for (size_t i = 0; i < s->inflight.size();) {
                     Request *r = s->inflight[i];
-                    if (r->admit_round <= k - 1 && s->h_cnt[prv][r->counter] >= r->frames) {
+                    const uint32_t counted = uint32_t(s->h_cnt[prv][r->counter]) - r->counter_base;
+                    if (r->admit_round <= k - 1 && counted >= uint32_t(r->frames)) {
                         fin.push_back(r);
                         s->inflight[i] = s->inflight.back();
                         s->inflight.pop_back();
@@ -404,6 +416,7 @@ extern "C" ldpc_status ldpc_server_create(const ldpc_graph *const *graphs, int32
     s->dev_arena.reset(new Arena(size_t(hbm_budget)));
     s->host_arena.reset(new Arena(size_t(host_budget)));
     for (int32_t i = maxreq - 1; i >= 0; i--) s->free_counters.push_back(i);
+    s->counter_total.assign(size_t(maxreq), 0u);
     try {
         s->worker = std::thread(worker_main, s);
     } catch (...) {
@@ -437,14 +450,16 @@ extern "C" ldpc_status ldpc_server_submit(ldpc_server *s, int32_t graph, const f
         set_error("ldpc_server_submit: request larger than the server's memory budgets");
         return LDPC_E_INVAL;
     }
-    try {
-        r->llr.assign(llr, llr + size_t(frames) * nn);
-    } catch (const std::bad_alloc &) {
-        delete r;
-        set_error("ldpc_server_submit: out of host memory");
-        return LDPC_E_NOMEM;
-    }
     r->t_submit = Clock::now();
+    // The LLRs go straight into the pinned staging arena when every request
+    // already waiting is staged there and the arena stays at most half full;
+    // otherwise into host memory (the worker stages them at admission).  The
+    // decision and the queue position are taken under one lock, so a request
+    // staged in host memory never has a pinned-staged request behind it, and
+    // the half of the arena left free always holds the head request's outputs:
+    // the queue never waits on memory that only a later request could release.
+    // The copy itself runs after the lock; the worker admits a request only
+    // once it is marked ready.
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stop) {
@@ -452,13 +467,32 @@ extern "C" ldpc_status ldpc_server_submit(ldpc_server *s, int32_t graph, const f
             set_error("ldpc_server_submit: server is stopping: " + s->worker_error);
             return LDPC_E_INVAL;
         }
+        if (s->unstaged_waiting == 0 && s->host_arena->used() + r->stage_bytes <= s->host_arena->size() / 2)
+            r->prestaged = s->host_arena->alloc(r->stage_bytes, &r->stage_off);
+        if (!r->prestaged) {
+            try {
+                r->llr.reserve(size_t(frames) * nn);
+            } catch (const std::bad_alloc &) {
+                delete r;
+                set_error("ldpc_server_submit: out of host memory");
+                return LDPC_E_NOMEM;
+            }
+            s->unstaged_waiting++;
+        }
         r->id = s->next_id++;
         s->all[r->id] = r;
         s->waiting.push_back(r);
         s->n_submitted++;
     }
+    if (r->prestaged) std::memcpy(s->pinned + r->stage_off, llr, size_t(frames) * nn * 4);
+    else r->llr.assign(llr, llr + size_t(frames) * nn);   // within the reserved capacity
+    const int64_t rid = r->id;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        r->ready = true;
+    }
     s->cv_work.notify_one();
-    *id = r->id;
+    *id = rid;
     return LDPC_OK;
 }
 

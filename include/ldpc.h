@@ -332,7 +332,9 @@ typedef struct {
                              their slot, and queued frames enter, once per step, so more
                              iterations per step spend fewer launches on that bookkeeping
                              but keep finished frames in their slots longer */
-    int32_t reserved[4];  /* must be 0 */
+    int32_t rule;         /* check rule, an ldpc_rule_kind (0 = sum-product) */
+    float rule_param;     /* its parameter (alpha or beta, as for ldpc_decode_rule) */
+    int32_t reserved[2];  /* must be 0 */
 } ldpc_engine_opts;
 
 /*
@@ -432,7 +434,9 @@ typedef struct {
     int32_t lane_slots;    /* engine tile option (0 = default) */
     int32_t graph_steps;   /* engine steps per replay (0 = default) */
     int32_t max_requests;  /* requests in flight at once (0 = 4096) */
-    int32_t reserved[5];   /* must be 0 */
+    int32_t rule;          /* check rule of the server's engine, an ldpc_rule_kind (0 = sum-product) */
+    float rule_param;      /* its parameter (alpha or beta) */
+    int32_t reserved[3];   /* must be 0 */
 } ldpc_server_opts;
 
 /*

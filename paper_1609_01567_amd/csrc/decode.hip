@@ -791,23 +791,10 @@ bool rule_from(const ldpc_rule *r, RuleSel &out, std::string &why) {
     if (!r) return true;
     for (int32_t x : r->reserved)
         if (x != 0) { why = "reserved rule fields must be 0"; return false; }
-    switch (r->kind) {
-        case LDPC_RULE_SUM_PRODUCT:
-            return true;
-        case LDPC_RULE_MIN_SUM_NORMALIZED:
-            if (!(r->param > 0.f && r->param <= 1.f)) { why = "alpha must be in (0, 1]"; return false; }
-            out.kind = kRuleNMS;
-            out.param = r->param;
-            return true;
-        case LDPC_RULE_MIN_SUM_OFFSET:
-            if (!(r->param >= 0.f && r->param < kLmax)) { why = "beta must be in [0, 64)"; return false; }
-            out.kind = kRuleOMS;
-            out.param = r->param;
-            return true;
-        default:
-            why = "unknown rule kind";
-            return false;
-    }
+    if (!ldpc::rule_ok(r->kind, r->param, why)) return false;
+    out.kind = r->kind == LDPC_RULE_MIN_SUM_NORMALIZED ? kRuleNMS : r->kind == LDPC_RULE_MIN_SUM_OFFSET ? kRuleOMS : kRuleSP;
+    out.param = out.kind == kRuleSP ? 0.f : r->param;
+    return true;
 }
 
 }  // namespace

@@ -250,9 +250,9 @@ __device__ __forceinline__ int work_graph(const Work &w, int32_t ngraphs, int x)
 // on row rk (a scalar), so the row descriptor and the column indices come in
 // through scalar loads issued before the slot state is examined; otherwise
 // each lane has its own row (packed items).
-template <int M, int V, int DMAX, bool UNIFORM>
+template <int M, int V, int DMAX, bool UNIFORM, int RULE>
 __device__ __forceinline__ void rows_item(const EngGraph &G, int cls, int nrows, int rk, int s0, int32_t T,
-                                          int32_t early, int32_t par) {
+                                          int32_t early, int32_t par, float rp) {
     using MT = typename Codec<M>::T;
     if (!UNIFORM && rk >= nrows) return;
     const u32x2 rdv = cload(reinterpret_cast<const u32x2 *>(G.class_rd) + G.class_begin[cls] + rk);
@@ -265,14 +265,14 @@ __device__ __forceinline__ void rows_item(const EngGraph &G, int cls, int nrows,
 #pragma unroll
     for (int k = 0; k < V; k++) syn[k] = 0;
     MT *R = static_cast<MT *>(G.r);
-    row_rule<M, V, DMAX, UNIFORM, kInMixed>(G.col_idx, e0, d, G.lpost, R, G.S, s0, ln.src, syn);
+    row_rule<M, V, DMAX, UNIFORM, kInMixed, RULE>(G.col_idx, e0, d, G.lpost, R, G.S, s0, ln.src, syn, rp);
     eng_syndrome<V>(G, ln, syn, s0);
 }
 
-template <int M, int V, int DMAX, int PM>
+template <int M, int V, int DMAX, int PM, int RULE>
 __global__ __launch_bounds__(256) void eng_check_rows(const EngGraph *__restrict__ graphs, int32_t ngraphs,
                                                       const int32_t *__restrict__ counters, int32_t cls, int32_t T,
-                                                      int32_t early, int32_t par) {
+                                                      int32_t early, int32_t par, float rp) {
     __shared__ Work w;
     build_work<PM>(graphs, ngraphs, counters, cls, 64 * V, 1, w);
     const int lane = threadIdx.x & 63;
@@ -287,20 +287,22 @@ __global__ __launch_bounds__(256) void eng_check_rows(const EngGraph *__restrict
         if (PM == kPackNone || PM == kPackOnlyFlat || (PM == kPackAll && rpw == 1)) {
             const int groups = wave_uniform(w.groups[c]);
             const int rk = local / groups;
-            rows_item<M, V, DMAX, true>(G, cls, nrows, rk, ((local - rk * groups) * 64 + lane) * V, T, early, par);
+            rows_item<M, V, DMAX, true, RULE>(G, cls, nrows, rk, ((local - rk * groups) * 64 + lane) * V, T, early, par,
+                                              rp);
         } else {
             const int lpr = 64 / rpw;
-            rows_item<M, V, DMAX, false>(G, cls, nrows, local * rpw + lane / lpr, (lane % lpr) * V, T, early, par);
+            rows_item<M, V, DMAX, false, RULE>(G, cls, nrows, local * rpw + lane / lpr, (lane % lpr) * V, T, early,
+                                               par, rp);
         }
     }
 }
 
 // Rows of 9..128 edges over WPR wavefronts (see check_chunk_kernel in decode.hip);
 // one workgroup item = 4 / WPR (row, slot group) pairs.
-template <int M, int V, int WPR>
+template <int M, int V, int WPR, int RULE>
 __global__ __launch_bounds__(256) void eng_check_chunk(const EngGraph *__restrict__ graphs, int32_t ngraphs,
                                                        const int32_t *__restrict__ counters, int32_t cls, int32_t T,
-                                                       int32_t early, int32_t par) {
+                                                       int32_t early, int32_t par, float rp) {
     using MT = typename Codec<M>::T;
     constexpr int C = kRowChunk;
     constexpr int RPB = 4 / WPR;
@@ -342,11 +344,11 @@ __global__ __launch_bounds__(256) void eng_check_chunk(const EngGraph *__restric
         int syn[V];
         for (int ch = wr; ch < nch; ch += WPR) {
             if (mine) {
-                chunk_load<M, V, C, kInMixed>(G.col_idx, e0 + ch * C, min(C, d - ch * C), G.lpost, R, S, s0,
-                                              ln.src, u_, suf, agg, neg, syn);
+                chunk_load<M, V, C, kInMixed, RULE>(G.col_idx, e0 + ch * C, min(C, d - ch * C), G.lpost, R, S, s0,
+                                                    ln.src, u_, suf, agg, neg, syn);
             } else {
 #pragma unroll
-                for (int k = 0; k < V; k++) { agg[k] = 0.f; neg[k] = 0u; syn[k] = 0; }
+                for (int k = 0; k < V; k++) { agg[k] = CheckRule<RULE>::identity(); neg[k] = 0u; syn[k] = 0; }
             }
 #pragma unroll
             for (int k = 0; k < V; k++) sh.agg[lr * MAXCH + ch][lane][k] = agg[k];
@@ -356,14 +358,14 @@ __global__ __launch_bounds__(256) void eng_check_chunk(const EngGraph *__restric
         if (mine) {
             for (int ch = wr; ch < nch; ch += WPR) {
                 if (nch > WPR)
-                    chunk_load<M, V, C, kInMixed>(G.col_idx, e0 + ch * C, min(C, d - ch * C), G.lpost, R, S,
-                                                  s0, ln.src, u_, suf, agg, neg, syn);
+                    chunk_load<M, V, C, kInMixed, RULE>(G.col_idx, e0 + ch * C, min(C, d - ch * C), G.lpost, R, S,
+                                                        s0, ln.src, u_, suf, agg, neg, syn);
                 float pre_a[V], post_a[V];
                 uint32_t parity[V];
                 int syn_row[V];
-                chunk_context<V, RPB * MAXCH>(sh, lr * MAXCH, nch, ch, lane, pre_a, post_a, parity, syn_row);
-                chunk_store<M, V, C>(e0 + ch * C, min(C, d - ch * C), u_, suf, neg, pre_a, post_a, parity, R, S,
-                                     s0);
+                chunk_context<V, RPB * MAXCH, RULE>(sh, lr * MAXCH, nch, ch, lane, pre_a, post_a, parity, syn_row);
+                chunk_store<M, V, C, RULE>(e0 + ch * C, min(C, d - ch * C), u_, suf, neg, pre_a, post_a, parity, R, S,
+                                           s0, rp);
                 if (ch == 0) eng_syndrome<V>(G, ln, syn_row, s0);
             }
         }
@@ -373,11 +375,12 @@ __global__ __launch_bounds__(256) void eng_check_chunk(const EngGraph *__restric
 
 // Rows longer than 128 edges: one workgroup of four wavefronts per (row, 64 slots),
 // 32-edge chunks combined through an exclusive prefix/suffix scan in scratch.
-template <int M>
+template <int M, int RULE>
 __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict__ graphs, int32_t ngraphs,
                                                      const int32_t *__restrict__ counters, int32_t T, int32_t early,
-                                                     int32_t par) {
+                                                     int32_t par, float rp) {
     using MT = typename Codec<M>::T;
+    using Rule = CheckRule<RULE>;
     constexpr int C = ldpc::kHubChunk;
     __shared__ int32_t total_bits[64];
     __shared__ Work w;
@@ -412,7 +415,7 @@ __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict_
         for (int ch = wv; ch < nch; ch += nw) {
             const int j0 = e0 + ch * C;
             const int dc = min(C, d - ch * C);
-            float agg = 0.f;
+            float agg = Rule::identity();
             int32_t bits = 0;
 #pragma unroll
             for (int jj = 0; jj < C; jj++) {
@@ -422,7 +425,7 @@ __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict_
                     const float r = first ? 0.f : Codec<M>::dec(R[size_t(j0 + jj) * S + s]);
                     const float qv = clamp_msg(lv - r);
                     bits ^= int32_t(qv < 0.f) | (int32_t(lv < 0.f) << 1);
-                    agg = dplus(agg, tanh_complement(fabsf(qv)));
+                    agg = Rule::combine(agg, Rule::input(fabsf(qv)));
                 }
             }
             gmem(G.aggd)[size_t(cb + ch) * S + s] = agg;
@@ -430,18 +433,18 @@ __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict_
         }
         __syncthreads();
         if (wv == 0) {
-            float pre_d = 0.f;
+            float pre_d = Rule::identity();
             int32_t tot = 0;
             for (int ch = 0; ch < nch; ch++) {
                 gmem(G.aggpre)[size_t(cb + ch) * S + s] = pre_d;
-                pre_d = dplus(pre_d, gmem(G.aggd)[size_t(cb + ch) * S + s]);
+                pre_d = Rule::combine(pre_d, gmem(G.aggd)[size_t(cb + ch) * S + s]);
                 tot ^= gmem(G.aggbits)[size_t(cb + ch) * S + s];
             }
-            float sf = 0.f;
+            float sf = Rule::identity();
             for (int ch = nch - 1; ch >= 0; ch--) {
                 const float dcur = gmem(G.aggd)[size_t(cb + ch) * S + s];
-                gmem(G.aggd)[size_t(cb + ch) * S + s] = dplus(gmem(G.aggpre)[size_t(cb + ch) * S + s], sf);
-                sf = dplus(sf, dcur);
+                gmem(G.aggd)[size_t(cb + ch) * S + s] = Rule::combine(gmem(G.aggpre)[size_t(cb + ch) * S + s], sf);
+                sf = Rule::combine(sf, dcur);
             }
             total_bits[lane] = tot;
             if (syn_on && (tot & 2) && gmem(G.fail)[s] != ts) gmem(G.fail)[s] = ts;
@@ -461,25 +464,25 @@ __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict_
                     const float r = first ? 0.f : Codec<M>::dec(R[size_t(j0 + jj) * S + s]);
                     const float qv = clamp_msg(lv - r);
                     neg |= uint32_t(qv < 0.f) << jj;
-                    uu[jj] = tanh_complement(fabsf(qv));
+                    uu[jj] = Rule::input(fabsf(qv));
                 }
             }
-            float run = 0.f;
+            float run = Rule::identity();
 #pragma unroll
             for (int jj = C - 1; jj >= 0; jj--) {
                 if (jj < dc) {
                     sf[jj] = run;
-                    run = dplus(uu[jj], run);
+                    run = Rule::combine(uu[jj], run);
                 }
             }
             run = gmem(G.aggd)[size_t(cb + ch) * S + s];
 #pragma unroll
             for (int jj = 0; jj < C; jj++) {
                 if (jj < dc) {
-                    const float mag = magnitude_from_complement(dplus(run, sf[jj]));
+                    const float mag = Rule::magnitude(Rule::combine(run, sf[jj]), rp);
                     const uint32_t sgn = parity ^ ((neg >> jj) & 1u);
                     R[size_t(j0 + jj) * S + s] = Codec<M>::enc(sgn ? -mag : mag);
-                    run = dplus(run, uu[jj]);
+                    run = Rule::combine(run, uu[jj]);
                 }
             }
         }
@@ -884,6 +887,8 @@ struct ldpc_engine {
     int device = -1;
     hipStream_t stream = nullptr;
     int32_t ngraphs = 0, T = 0, V = 4, K = 8, I = 1, msg = kF32;   // I: decoder iterations per step
+    int rule = kRuleSP;      // check rule (RuleKind) and its parameter
+    float rule_param = 0.f;
     uint32_t flags = 0;
     bool early = true;
     bool repack = true;
@@ -921,38 +926,41 @@ size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Register-row class `cls`: unpacked items in one launch and, when packing is
 // on, packed items in a second one, so neither kernel carries the other's body.
-template <int M, int V, int DMAX>
+template <int M, int V, int DMAX, int RULE>
 void launch_rows(ldpc_engine *e, int cls, unsigned grid, int32_t par) {
     const int32_t early = e->early ? 1 : 0;
+    const float rp = e->rule_param;
     if (e->pack) {
-        hipLaunchKernelGGL((eng_check_rows<M, V, DMAX, kPackOnlyFlat>), dim3(grid), dim3(256), 0, e->stream,
-                           e->d_graphs, e->ngraphs, e->d_counters, int32_t(cls), e->T, early, par);
-        hipLaunchKernelGGL((eng_check_rows<M, V, DMAX, kPackOnlyPacked>), dim3(e->grid_packed), dim3(256), 0,
-                           e->stream, e->d_graphs, e->ngraphs, e->d_counters, int32_t(cls), e->T, early, par);
+        hipLaunchKernelGGL((eng_check_rows<M, V, DMAX, kPackOnlyFlat, RULE>), dim3(grid), dim3(256), 0, e->stream,
+                           e->d_graphs, e->ngraphs, e->d_counters, int32_t(cls), e->T, early, par, rp);
+        hipLaunchKernelGGL((eng_check_rows<M, V, DMAX, kPackOnlyPacked, RULE>), dim3(e->grid_packed), dim3(256), 0,
+                           e->stream, e->d_graphs, e->ngraphs, e->d_counters, int32_t(cls), e->T, early, par, rp);
     } else {
-        hipLaunchKernelGGL((eng_check_rows<M, V, DMAX, kPackNone>), dim3(grid), dim3(256), 0, e->stream, e->d_graphs,
-                           e->ngraphs, e->d_counters, int32_t(cls), e->T, early, par);
+        hipLaunchKernelGGL((eng_check_rows<M, V, DMAX, kPackNone, RULE>), dim3(grid), dim3(256), 0, e->stream,
+                           e->d_graphs, e->ngraphs, e->d_counters, int32_t(cls), e->T, early, par, rp);
     }
 }
 
-template <int M, int V>
-void enqueue_step(ldpc_engine *e) {
+template <int M, int V, int RULE>
+void enqueue_step_rule(ldpc_engine *e) {
     hipStream_t st = e->stream;
     const int32_t early = e->early ? 1 : 0;
     const int32_t ng = e->ngraphs;
+    const float rp = e->rule_param;
     for (int32_t j = 0; j < e->I; j++) {
         const int32_t par = j & 1;
         if (e->has_rows[0])
-            launch_rows<M, V, 8>(e, ldpc::kClassD8, e->grid_rows[0], par);
+            launch_rows<M, V, 8, RULE>(e, ldpc::kClassD8, e->grid_rows[0], par);
         if (e->has_rows[1])
-            launch_rows<M, ldpc::class_lane_slots(ldpc::kClassD16, V), 16>(e, ldpc::kClassD16, e->grid_rows[1], par);
+            launch_rows<M, ldpc::class_lane_slots(ldpc::kClassD16, V), 16, RULE>(e, ldpc::kClassD16, e->grid_rows[1],
+                                                                                 par);
         if (e->has_rows[2])
-            hipLaunchKernelGGL((eng_check_chunk<M, V, ldpc::class_waves_per_row(ldpc::kClassD128)>),
+            hipLaunchKernelGGL((eng_check_chunk<M, V, ldpc::class_waves_per_row(ldpc::kClassD128), RULE>),
                                dim3(e->grid_rows[2]), dim3(256), 0, st, e->d_graphs, ng, e->d_counters,
-                               int32_t(ldpc::kClassD128), e->T, early, par);
+                               int32_t(ldpc::kClassD128), e->T, early, par, rp);
         if (e->has_hub)
-            hipLaunchKernelGGL((eng_check_hub<M>), dim3(e->grid_hub), dim3(256), 0, st, e->d_graphs, ng,
-                               e->d_counters, e->T, early, par);
+            hipLaunchKernelGGL((eng_check_hub<M, RULE>), dim3(e->grid_hub), dim3(256), 0, st, e->d_graphs, ng,
+                               e->d_counters, e->T, early, par, rp);
         hipLaunchKernelGGL((eng_bit<M, V>), dim3(e->grid_bit), dim3(256), 0, st, e->d_graphs, ng, e->d_counters,
                            e->T, early, par);
     }
@@ -967,6 +975,15 @@ void enqueue_step(ldpc_engine *e) {
                            st, e->d_graphs, e->ngraphs, e->d_counters);
     } else {
         hipLaunchKernelGGL(eng_admit<false>, dim3(unsigned(e->ngraphs)), dim3(1024), 0, st, e->d_graphs);
+    }
+}
+
+template <int M, int V>
+void enqueue_step(ldpc_engine *e) {
+    switch (e->rule) {
+        case kRuleNMS: enqueue_step_rule<M, V, kRuleNMS>(e); break;
+        case kRuleOMS: enqueue_step_rule<M, V, kRuleOMS>(e); break;
+        default: enqueue_step_rule<M, V, kRuleSP>(e); break;
     }
 }
 
@@ -1012,16 +1029,17 @@ void size_grids(ldpc_engine *e, int cus) {
         }
         return unsigned(std::max<int64_t>(1, std::min<int64_t>(need, int64_t(per_cu) * cus * grid_factor())));
     };
-    e->grid_rows[0] = fit(reinterpret_cast<const void *>(&eng_check_rows<M, V, 8, kPackOnlyFlat>),
+    e->grid_rows[0] = fit(reinterpret_cast<const void *>(&eng_check_rows<M, V, 8, kPackOnlyFlat, kRuleSP>),
                           (e->row_waves[0] + 3) / 4);
     e->grid_rows[1] = fit(reinterpret_cast<const void *>(&eng_check_rows<M, ldpc::class_lane_slots(ldpc::kClassD16, V), 16,
-                                                                         kPackOnlyFlat>),
+                                                                         kPackOnlyFlat, kRuleSP>),
                           (e->row_waves[1] + 3) / 4);
-    e->grid_packed = fit(reinterpret_cast<const void *>(&eng_check_rows<M, V, 8, kPackOnlyPacked>),
+    e->grid_packed = fit(reinterpret_cast<const void *>(&eng_check_rows<M, V, 8, kPackOnlyPacked, kRuleSP>),
                          std::max<int64_t>(1, (e->row_waves[0] + e->row_waves[1] + 3) / 4));
-    e->grid_rows[2] = fit(reinterpret_cast<const void *>(&eng_check_chunk<M, V, ldpc::class_waves_per_row(ldpc::kClassD128)>),
+    e->grid_rows[2] = fit(reinterpret_cast<const void *>(&eng_check_chunk<M, V, ldpc::class_waves_per_row(ldpc::kClassD128),
+                                                                          kRuleSP>),
                           e->row_waves[2]);
-    e->grid_hub = fit(reinterpret_cast<const void *>(&eng_check_hub<M>), e->hub_blocks);
+    e->grid_hub = fit(reinterpret_cast<const void *>(&eng_check_hub<M, kRuleSP>), e->hub_blocks);
     e->grid_bit = fit(reinterpret_cast<const void *>(&eng_bit<M, V>), (e->bit_waves + 3) / 4);
 }
 
@@ -1101,6 +1119,11 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
             return LDPC_E_INVAL;
         }
         if (opts->iters_per_step) I = opts->iters_per_step;
+        std::string why;
+        if (!ldpc::rule_ok(opts->rule, opts->rule_param, why)) {
+            set_error("ldpc_engine_create: " + why);
+            return LDPC_E_INVAL;
+        }
     }
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) { (void)hipGetLastError(); set_error("ldpc_engine_create: no device"); return LDPC_E_DEVICE; }
@@ -1125,6 +1148,10 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
     e->V = V;
     e->K = K;
     e->I = I;
+    if (opts && opts->rule != LDPC_RULE_SUM_PRODUCT) {
+        e->rule = opts->rule == LDPC_RULE_MIN_SUM_NORMALIZED ? kRuleNMS : kRuleOMS;
+        e->rule_param = opts->rule_param;
+    }
     e->repack = repack;
     if (const char *v = std::getenv("LDPC_ENGINE_NO_PACK")) e->pack = v[0] != '1';
     if (const char *v = std::getenv("LDPC_ENGINE_DIRECT")) e->direct = v[0] == '1';

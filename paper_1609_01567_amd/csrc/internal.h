@@ -31,6 +31,23 @@ constexpr int class_lane_slots(int cls, int V) { return cls == kClassHub ? 1 : c
 
 void set_error(const std::string &msg);
 
+// Host-side check of a check rule (ldpc_rule_kind and its parameter): false
+// with a reason for an unknown kind or a parameter out of range.
+inline bool rule_ok(int32_t kind, float param, std::string &why) {
+    switch (kind) {
+        case LDPC_RULE_SUM_PRODUCT: return true;
+        case LDPC_RULE_MIN_SUM_NORMALIZED:
+            if (param > 0.f && param <= 1.f) return true;
+            why = "alpha must be in (0, 1]";
+            return false;
+        case LDPC_RULE_MIN_SUM_OFFSET:
+            if (param >= 0.f && param < 64.f) return true;
+            why = "beta must be in [0, 64)";
+            return false;
+        default: why = "unknown rule kind"; return false;
+    }
+}
+
 }  // namespace ldpc
 
 struct ldpc_graph {

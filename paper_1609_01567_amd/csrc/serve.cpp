@@ -374,6 +374,8 @@ extern "C" ldpc_status ldpc_server_create(const ldpc_graph *const *graphs, int32
             if (r) { set_error("ldpc_server_create: reserved options must be 0"); return LDPC_E_INVAL; }
         eo.lane_slots = opts->lane_slots;
         eo.graph_steps = opts->graph_steps;
+        eo.rule = opts->rule;
+        eo.rule_param = opts->rule_param;
         if (opts->max_requests < 0) { set_error("ldpc_server_create: max_requests < 0"); return LDPC_E_INVAL; }
         if (opts->max_requests) maxreq = opts->max_requests;
     }

@@ -45,7 +45,7 @@ class Frame(ctypes.Structure):
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("lane_slots", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("max_requests", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("rule", ctypes.c_int32), ("rule_param", ctypes.c_float), ("reserved", ctypes.c_int32 * 3)]
 
 
 class Rule(ctypes.Structure):
@@ -70,7 +70,7 @@ def make_rule(rule=None, param=None):
 class EngineOpts(ctypes.Structure):
     _fields_ = [("lane_slots", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
                 ("no_compaction", ctypes.c_int32), ("iters_per_step", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("rule", ctypes.c_int32), ("rule_param", ctypes.c_float), ("reserved", ctypes.c_int32 * 2)]
 
 
 class LdpcError(RuntimeError):
@@ -355,7 +355,7 @@ class Engine:
     """Batched decoder with continuous refill (ldpc_engine_*) over several graphs."""
 
     def __init__(self, graphs, slots, queue_cap, max_iter: int, flags: int = 0, lane_slots: int = 0,
-                 graph_steps: int = 0, repack: bool = True, iters_per_step: int = 0):
+                 graph_steps: int = 0, repack: bool = True, iters_per_step: int = 0, rule=None, rule_param=None):
         lib = load_library()
         self._lib = lib
         self.graphs = list(graphs)
@@ -365,7 +365,8 @@ class Engine:
         qc = np.ascontiguousarray(queue_cap, dtype=np.int32)
         if sl.size != ng or qc.size != ng:
             raise ValueError("one slot count and one queue capacity per graph")
-        opts = EngineOpts(lane_slots, graph_steps, 0 if repack else 1, iters_per_step)
+        r = make_rule(rule, rule_param)
+        opts = EngineOpts(lane_slots, graph_steps, 0 if repack else 1, iters_per_step, r.kind, r.param)
         self._h = ctypes.c_void_p()
         _check(lib.ldpc_engine_create(hs, ng, _np_ptr(sl), _np_ptr(qc), int(max_iter), int(flags),
                                       ctypes.byref(opts), ctypes.byref(self._h)), "ldpc_engine_create")
@@ -487,14 +488,16 @@ class Server:
                  "device_bytes_in_use", "device_bytes_peak")
 
     def __init__(self, graphs, slots, max_iter: int, flags: int = 0, hbm_budget: int = 1 << 30,
-                 host_budget: int = 1 << 28, lane_slots: int = 0, graph_steps: int = 0, max_requests: int = 0):
+                 host_budget: int = 1 << 28, lane_slots: int = 0, graph_steps: int = 0, max_requests: int = 0,
+                 rule=None, rule_param=None):
         lib = load_library()
         self._lib = lib
         self.graphs = list(graphs)
         ng = len(self.graphs)
         hs = (ctypes.c_void_p * ng)(*[g.handle.value for g in self.graphs])
         sl = np.ascontiguousarray(slots, dtype=np.int32)
-        opts = ServerOpts(lane_slots, graph_steps, max_requests)
+        r = make_rule(rule, rule_param)
+        opts = ServerOpts(lane_slots, graph_steps, max_requests, r.kind, r.param)
         self._h = ctypes.c_void_p()
         _check(lib.ldpc_server_create(hs, ng, _np_ptr(sl), int(max_iter), int(flags), int(hbm_budget),
                                       int(host_budget), ctypes.byref(opts), ctypes.byref(self._h)),

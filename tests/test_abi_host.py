@@ -176,6 +176,9 @@ def test_engine_argument_checks_fail_before_device_work():
     for ips in (-1, 17):
         bad = ldpc.EngineOpts(0, 0, 0, ips)
         assert lib.ldpc_engine_create(graphs, 1, one, one, 10, 0, ctypes.byref(bad), ctypes.byref(out)) == ldpc.E_INVAL
+    for kind, p in ((9, 0.0), (ldpc.RULE_MIN_SUM_NORMALIZED, 0.0), (ldpc.RULE_MIN_SUM_OFFSET, 64.0)):
+        bad = ldpc.EngineOpts(0, 0, 0, 0, kind, p)
+        assert lib.ldpc_engine_create(graphs, 1, one, one, 10, 0, ctypes.byref(bad), ctypes.byref(out)) == ldpc.E_INVAL
     assert not out
     for f in ("ldpc_engine_step", "ldpc_engine_poll", "ldpc_engine_run", "ldpc_engine_info"):
         fn = getattr(lib, f)

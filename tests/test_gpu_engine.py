@@ -27,13 +27,13 @@ def _announce(name, **kw):
 
 
 def _engine_decode(codes, llrs, slots, T, flags=0, lane_slots=0, graph_steps=0, want_llr=True, cap=None,
-                   repack=True, iters_per_step=0):
+                   repack=True, iters_per_step=0, rule=None, param=None):
     import torch
     from paper_1609_01567_amd import ldpc
     graphs = [ldpc.Graph.from_code(c) for c in codes]
     caps = cap or [max(1, x.shape[0]) for x in llrs]
     eng = ldpc.Engine(graphs, slots, caps, T, flags=flags, lane_slots=lane_slots, graph_steps=graph_steps,
-                      repack=repack, iters_per_step=iters_per_step)
+                      repack=repack, iters_per_step=iters_per_step, rule=rule, rule_param=param)
     jobs = [(i, torch.from_numpy(np.ascontiguousarray(x)).cuda()) for i, x in enumerate(llrs)]
     # bound: every frame needs at most T+1 steps once admitted; admissions follow slot turnover
     steps = sum((x.shape[0] // max(1, sl) + 2) * (T + 2) for x, sl in zip(llrs, slots)) + 8
@@ -100,6 +100,20 @@ def test_engine_iterations_per_step_each_frame_as_alone(iters_per_step):
                          iters_per_step=iters_per_step)
     for c, x, o in zip(codes, llrs, out):
         _assert_same(o, gpu_decode(c, x, 25), f"{iters_per_step} iterations per step: {c.name}")
+
+
+@pytest.mark.parametrize("rule,param,ips", [("ms", None, 1), ("nms", 0.75, 2), ("oms", 0.25, 3)])
+def test_engine_min_sum_rules_each_frame_as_alone(rule, param, ips):
+    """Min-Sum family rules in the engine, over every check-degree class, with
+    slot refill: each frame equals its plain ldpc_decode_rule decode."""
+    from paper_1609_01567_amd import ldpc
+    codes, llrs = _mixed_codes()
+    _announce("engine-min-sum", rule=rule, iters_per_step=ips)
+    for flags in (0, ldpc.MSG_FP16):
+        out = _engine_decode(codes, llrs, [64, 64, 128, 64], 25, flags=flags, lane_slots=2, graph_steps=3,
+                             iters_per_step=ips, rule=rule, param=param)
+        for c, x, o in zip(codes, llrs, out):
+            _assert_same(o, gpu_decode(c, x, 25, flags=flags, rule=rule, param=param), f"{rule} {flags}: {c.name}")
 
 
 def test_engine_iterations_per_step_repack_and_max_iter():

@@ -68,6 +68,22 @@ def test_served_results_equal_alone():
         assert lat > 0
 
 
+def test_served_min_sum_results_equal_alone():
+    from paper_1609_01567_amd import ldpc
+    codes = _codes()
+    graphs = [ldpc.Graph.from_code(c) for c in codes]
+    srv = ldpc.Server(graphs, [128, 128, 64], 30, flags=ldpc.MSG_FP16, graph_steps=2, rule="oms", rule_param=0.25)
+    reqs = _requests(codes, 40, seed=3)
+    print(f"[case] serve-min-sum requests={len(reqs)}", flush=True)
+    ids = [srv.submit(gi, llr) for gi, llr in reqs]
+    res = _drain(srv, ids)
+    srv.close()
+    for rid, (gi, llr) in zip(ids, reqs):
+        bits, ok, iters, _ = res[rid]
+        ref = gpu_decode(codes[gi], llr, 30, flags=ldpc.MSG_FP16, rule="oms", param=0.25)
+        assert (bits == ref["bits"]).all() and (ok == ref["ok"]).all() and (iters == ref["iters"]).all(), rid
+
+
 def test_admission_respects_device_budget():
     from paper_1609_01567_amd import ldpc
     code = li.random_small_code(600, 300, 3, seed=8)

@@ -327,7 +327,8 @@ def bench_simulate(torch, ldpc, code, points, frames=1024, calls=2, T=50, seed=2
 
 
 def bench_minsum(torch, ldpc, g, d_llr, cws, points, T, steps, rules=(("oms", 0.25, "fp32"), ("oms", 0.25, "fp16"),
-                                                                    ("nms", 0.875, "fp32"), ("ms", None, "fp32"))):
+                                                                    ("oms", 0.25, "q8"), ("nms", 0.875, "fp32"),
+                                                                    ("ms", None, "fp32"))):
     """Min-Sum family check rules (ldpc_decode_rule) on the headline workload:
     throughput and frame errors against sum-product on the same frames (paired).
     On this degree-2-heavy code a normalization below ~0.85 stalls decoding
@@ -338,7 +339,7 @@ def bench_minsum(torch, ldpc, g, d_llr, cws, points, T, steps, rules=(("oms", 0.
     E = g.nnz
 
     def run(rule, param, msg):
-        flags = ldpc.MSG_FP16 if msg == "fp16" else 0
+        flags = {"fp32": 0, "fp16": ldpc.MSG_FP16, "q8": ldpc.MSG_Q8}[msg]
         ws = ldpc.Workspace(ldpc.workspace_size(g, F, flags))
         outs = [None] * len(points)
 

@@ -54,6 +54,8 @@ enum {
     LDPC_NO_EARLY_STOP = 1u << 0, /* run exactly max_iter iterations (no syndrome stop) */
     LDPC_MSG_FP16 = 1u << 1,      /* store check->bit messages as IEEE fp16 (math stays fp32) */
     LDPC_MSG_BF16 = 1u << 2,      /* store check->bit messages as bfloat16 (math stays fp32) */
+    LDPC_MSG_Q8 = 1u << 6,        /* store them as 8-bit fixed point: steps of 1/2, saturating at +-63.5
+                                     (round to nearest even; math stays fp32) */
     /* Tile shape (at most one; default: chosen from the frame count).  Each
      * wavefront lane holds 1, 2 or 4 consecutive frame slots, so one memory
      * access of a wavefront spans 64, 128 or 256 frames of one edge or bit.
@@ -144,7 +146,7 @@ LDPC_API ldpc_status ldpc_decode_workspace_size(const ldpc_graph *g, int32_t fra
  *  llr_in       device float [frames][n], channel LLRs, finite.
  *  frames       >= 0 (0 is a no-op).
  *  max_iter     >= 1.
- *  flags        LDPC_NO_EARLY_STOP | at most one of LDPC_MSG_FP16, LDPC_MSG_BF16 |
+ *  flags        LDPC_NO_EARLY_STOP | at most one of LDPC_MSG_FP16, LDPC_MSG_BF16, LDPC_MSG_Q8 |
  *               at most one LDPC_LANE_SLOTS_* tile-shape flag.
  *  bits_out     device uint8 [frames][n]: the estimate (0/1).
  *  syndrome_ok  device uint8 [frames]: 1 iff the returned estimate is a codeword.
@@ -345,7 +347,7 @@ typedef struct {
  *              of 64 * lane_slots).
  *  queue_cap   [ngraphs] queue capacity per graph (>= 1): frames submitted but not
  *              yet admitted to a slot.
- *  max_iter    1..2^30-1; flags: LDPC_NO_EARLY_STOP, LDPC_MSG_FP16 / LDPC_MSG_BF16.
+ *  max_iter    1..2^30-1; flags: LDPC_NO_EARLY_STOP, LDPC_MSG_FP16 / LDPC_MSG_BF16 / LDPC_MSG_Q8.
  *  opts        may be NULL.
  * Errors: INVAL, NOMEM (device memory), DEVICE.
  */

@@ -569,16 +569,16 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 constexpr uint32_t kLaneSlotFlags = LDPC_LANE_SLOTS_1 | LDPC_LANE_SLOTS_2 | LDPC_LANE_SLOTS_4;
 
 bool flags_ok(uint32_t flags) {
-    const uint32_t known = LDPC_NO_EARLY_STOP | LDPC_MSG_FP16 | LDPC_MSG_BF16 | kLaneSlotFlags;
+    const uint32_t known = LDPC_NO_EARLY_STOP | LDPC_MSG_FP16 | LDPC_MSG_BF16 | LDPC_MSG_Q8 | kLaneSlotFlags;
     if (flags & ~known) return false;
-    if ((flags & LDPC_MSG_FP16) && (flags & LDPC_MSG_BF16)) return false;
+    if (__builtin_popcount(flags & (LDPC_MSG_FP16 | LDPC_MSG_BF16 | LDPC_MSG_Q8)) > 1) return false;
     if (__builtin_popcount(flags & kLaneSlotFlags) > 1) return false;
     return true;
 }
 
 Plan make_plan(const ldpc_graph *g, int32_t F, uint32_t flags, bool sim = false) {
     Plan p;
-    p.msg = (flags & LDPC_MSG_FP16) ? kF16 : (flags & LDPC_MSG_BF16) ? kBF16 : kF32;
+    p.msg = (flags & LDPC_MSG_FP16) ? kF16 : (flags & LDPC_MSG_BF16) ? kBF16 : (flags & LDPC_MSG_Q8) ? kQ8 : kF32;
     if (flags & LDPC_LANE_SLOTS_1) p.V = 1;
     else if (flags & LDPC_LANE_SLOTS_2) p.V = 2;
     else if (flags & LDPC_LANE_SLOTS_4) p.V = 4;
@@ -586,7 +586,7 @@ Plan make_plan(const ldpc_graph *g, int32_t F, uint32_t flags, bool sim = false)
     const int32_t unit = 64 * p.V;
     p.S = (std::max<int32_t>(F, 1) + unit - 1) / unit * unit;
     const size_t S = size_t(p.S);
-    const size_t msg_bytes = p.msg == kF32 ? 4 : 2;
+    const size_t msg_bytes = p.msg == kF32 ? 4 : p.msg == kQ8 ? 1 : 2;
     size_t off = 0;
     p.off_lch = off;     off = align256(off + size_t(g->n) * S * 4);
     p.off_lpost = off;   off = align256(off + size_t(g->n) * S * 4);
@@ -871,6 +871,10 @@ ldpc_status decode_core(const char *fn, const ldpc_graph *g, const float *llr_in
             run_decode_v<kBF16>(g, p, b, llr_in, frames, max_iter, es, bits_out, syndrome_ok, iters, llr_out, st, mk,
                                 SimRun{}, rule);
             break;
+        case kQ8:
+            run_decode_v<kQ8>(g, p, b, llr_in, frames, max_iter, es, bits_out, syndrome_ok, iters, llr_out, st, mk,
+                              SimRun{}, rule);
+            break;
         default:
             run_decode_v<kF32>(g, p, b, llr_in, frames, max_iter, es, bits_out, syndrome_ok, iters, llr_out, st, mk,
                                SimRun{}, rule);
@@ -1020,6 +1024,10 @@ ldpc_status simulate_core(const char *fn, const ldpc_graph *g, int32_t frames, d
         case kBF16:
             run_decode_v<kBF16>(g, p, b, nullptr, frames, max_iter, es, nullptr, nullptr, nullptr, nullptr, st,
                                 Marks{}, sim, rule);
+            break;
+        case kQ8:
+            run_decode_v<kQ8>(g, p, b, nullptr, frames, max_iter, es, nullptr, nullptr, nullptr, nullptr, st, Marks{},
+                              sim, rule);
             break;
         default:
             run_decode_v<kF32>(g, p, b, nullptr, frames, max_iter, es, nullptr, nullptr, nullptr, nullptr, st, Marks{},

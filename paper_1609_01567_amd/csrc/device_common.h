@@ -20,7 +20,7 @@ constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn2 = 0.6931471805599453f;
 constexpr int32_t kPadSlot = 0x7fffffff;   // iters value of a padding slot: never active
 
-enum MsgType { kF32 = 0, kF16 = 1, kBF16 = 2 };
+enum MsgType { kF32 = 0, kF16 = 1, kBF16 = 2, kQ8 = 3 };
 enum Mode { kFirst = 0, kIter = 1 };
 
 // ----------------------------------------------------------------- storage
@@ -44,6 +44,14 @@ template <> struct Codec<kBF16> {
         return static_cast<T>((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
     }
 };
+// 8-bit fixed point: steps of 1/2, saturating at +-63.5 (127 steps).
+template <> struct Codec<kQ8> {
+    using T = int8_t;
+    __device__ static float dec(T x) { return float(x) * 0.5f; }
+    __device__ static T enc(float x) {                                     // round to nearest even, saturate
+        return static_cast<T>(fminf(fmaxf(rintf(x * 2.f), -127.f), 127.f));
+    }
+};
 
 // Device arrays by address space.  A pointer that reaches a kernel through
 // memory (a table of per-graph arrays, a frame descriptor) is generic to the
@@ -64,6 +72,7 @@ __device__ __forceinline__ T cload(const T *p) {
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 template <int B> struct Raw;
+template <> struct Raw<1> { using T = uint8_t; };
 template <> struct Raw<2> { using T = uint16_t; };
 template <> struct Raw<4> { using T = uint32_t; };
 template <> struct Raw<8> { using T = u32x2; };

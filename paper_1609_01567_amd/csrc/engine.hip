@@ -836,7 +836,8 @@ __global__ __launch_bounds__(1024) void eng_admit(const EngGraph *__restrict__ g
 template <int MSG_BYTES>
 __global__ __launch_bounds__(256) void eng_repack_move(const EngGraph *__restrict__ graphs, int32_t ngraphs,
                                                        const int32_t *__restrict__ counters) {
-    using MsgWord = typename std::conditional<MSG_BYTES == 2, uint16_t, uint32_t>::type;
+    using MsgWord = typename std::conditional<MSG_BYTES == 1, uint8_t,
+                                              typename std::conditional<MSG_BYTES == 2, uint16_t, uint32_t>::type>::type;
     __shared__ long long base[kMaxGraphs + 1];
     __shared__ int32_t nm[kMaxGraphs];
     if (threadIdx.x < 64) {   // one lane per graph
@@ -1001,6 +1002,7 @@ void enqueue_steps(ldpc_engine *e, int steps) {
         switch (e->msg) {
             case kF16: enqueue_step_v<kF16>(e); break;
             case kBF16: enqueue_step_v<kBF16>(e); break;
+            case kQ8: enqueue_step_v<kQ8>(e); break;
             default: enqueue_step_v<kF32>(e); break;
         }
     }
@@ -1087,8 +1089,8 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
         set_error("ldpc_engine_create: max_iter must be in 1..2^30-1");
         return LDPC_E_INVAL;
     }
-    const uint32_t known = LDPC_NO_EARLY_STOP | LDPC_MSG_FP16 | LDPC_MSG_BF16;
-    if ((flags & ~known) || ((flags & LDPC_MSG_FP16) && (flags & LDPC_MSG_BF16))) {
+    const uint32_t known = LDPC_NO_EARLY_STOP | LDPC_MSG_FP16 | LDPC_MSG_BF16 | LDPC_MSG_Q8;
+    if ((flags & ~known) || __builtin_popcount(flags & (LDPC_MSG_FP16 | LDPC_MSG_BF16 | LDPC_MSG_Q8)) > 1) {
         set_error("ldpc_engine_create: bad flags");
         return LDPC_E_INVAL;
     }
@@ -1144,7 +1146,7 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
     e->T = max_iter;
     e->flags = flags;
     e->early = !(flags & LDPC_NO_EARLY_STOP);
-    e->msg = (flags & LDPC_MSG_FP16) ? kF16 : (flags & LDPC_MSG_BF16) ? kBF16 : kF32;
+    e->msg = (flags & LDPC_MSG_FP16) ? kF16 : (flags & LDPC_MSG_BF16) ? kBF16 : (flags & LDPC_MSG_Q8) ? kQ8 : kF32;
     e->V = V;
     e->K = K;
     e->I = I;
@@ -1157,7 +1159,7 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
     if (const char *v = std::getenv("LDPC_ENGINE_DIRECT")) e->direct = v[0] == '1';
     e->graphs.assign(graphs, graphs + ngraphs);
     const int32_t unit = 64 * V;
-    const size_t msg_bytes = e->msg == kF32 ? 4 : 2;
+    const size_t msg_bytes = e->msg == kF32 ? 4 : e->msg == kQ8 ? 1 : 2;
 
     // device layout: per graph state, then counters, turnover list, graph table
     size_t off = 0;
@@ -1271,6 +1273,7 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
         switch (e->msg) {
             case kF16: size_grids_v<kF16>(e, cus); break;
             case kBF16: size_grids_v<kBF16>(e, cus); break;
+            case kQ8: size_grids_v<kQ8>(e, cus); break;
             default: size_grids_v<kF32>(e, cus); break;
         }
     }

@@ -22,6 +22,7 @@ OK, E_INVAL, E_RANGE, E_DUP_EDGE, E_NOMEM, E_DEVICE, E_UNSUPPORTED = range(7)
 NO_EARLY_STOP = 1 << 0
 MSG_FP16 = 1 << 1
 MSG_BF16 = 1 << 2
+MSG_Q8 = 1 << 6          # 8-bit fixed-point messages: steps of 1/2, saturating at +-63.5
 LANE_SLOTS_1 = 1 << 3
 LANE_SLOTS_2 = 1 << 4
 LANE_SLOTS_4 = 1 << 5

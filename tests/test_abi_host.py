@@ -112,12 +112,15 @@ def test_workspace_size_rules():
     assert ldpc.workspace_size(g, 0) == 0
     w32 = ldpc.workspace_size(g, 32)
     w16 = ldpc.workspace_size(g, 32, ldpc.MSG_FP16)
-    assert w32 > w16 > 0
+    w8 = ldpc.workspace_size(g, 32, ldpc.MSG_Q8)
+    assert w32 > w16 > w8 > 0
+    assert w16 - w8 >= code.nnz * 64 - 256          # one byte less per stored message
     # fp32: Lch + Lpost (n*S*4 each) + R (E*S*4) with S = 64 slots, plus small state
     assert w32 >= (2 * code.n + code.nnz) * 64 * 4
     assert ldpc.workspace_size(g, 1000) > ldpc.workspace_size(g, 100) > w32
-    with pytest.raises(ldpc.LdpcError):
-        ldpc.workspace_size(g, 8, ldpc.MSG_FP16 | ldpc.MSG_BF16)
+    for bad in (ldpc.MSG_FP16 | ldpc.MSG_BF16, ldpc.MSG_FP16 | ldpc.MSG_Q8, ldpc.MSG_BF16 | ldpc.MSG_Q8):
+        with pytest.raises(ldpc.LdpcError):
+            ldpc.workspace_size(g, 8, bad)
     with pytest.raises(ldpc.LdpcError):
         ldpc.workspace_size(g, -1)
 

@@ -109,7 +109,7 @@ def test_engine_min_sum_rules_each_frame_as_alone(rule, param, ips):
     from paper_1609_01567_amd import ldpc
     codes, llrs = _mixed_codes()
     _announce("engine-min-sum", rule=rule, iters_per_step=ips)
-    for flags in (0, ldpc.MSG_FP16):
+    for flags in (0, ldpc.MSG_FP16, ldpc.MSG_Q8):
         out = _engine_decode(codes, llrs, [64, 64, 128, 64], 25, flags=flags, lane_slots=2, graph_steps=3,
                              iters_per_step=ips, rule=rule, param=param)
         for c, x, o in zip(codes, llrs, out):

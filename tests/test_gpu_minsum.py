@@ -114,6 +114,53 @@ def test_continuous_llrs_fixed_iterations(rule, param):
             compare(code, llr, T, early_stop=False, posterior_all=True, rule=rule, param=param)
 
 
+def _quantized_half(llr):
+    """LLRs rounded to multiples of 1/2 and clipped to +-16."""
+    return np.clip(np.round(llr.astype(np.float64) * 2.0) / 2.0, -16.0, 16.0).astype(np.float32)
+
+
+def test_fixed_point_messages_exact_regime():
+    """8-bit fixed-point messages (steps of 1/2, saturating at 63.5) under plain
+    Min-Sum on LLRs in steps of 1/2: every message is a step of 1/2 or a
+    clamped 64, which storage saturates to 63.5, exactly what the oracle gives
+    with its clamp at 63.5.  All outputs must match it bit for bit."""
+    import oracle
+    from paper_1609_01567_amd import ldpc
+    for code, llr in ((li.tiny_code(), li.awgn_llr(1024, 96, li.ebn0_to_sigma2(2.0, 0.5), seed=2001)),
+                      (_classes_code(), li.awgn_llr(700, 70, 0.7, seed=13))):
+        q = _quantized_half(llr)
+        _announce("q8-exact", n=code.n)
+        gpu = gpu_decode(code, q, 50, flags=ldpc.MSG_Q8, rule="ms")
+        ora = oracle.decode(code, q, 50, rule="ms", lmax=63.5)
+        for k in ("bits", "ok", "iters"):
+            assert (gpu[k] == ora[k]).all(), k
+        assert (gpu["lpost"].astype(np.float64) == ora["lpost"]).all()
+
+
+@pytest.mark.parametrize("rule,param", [(None, None), ("nms", 0.75)])
+def test_fixed_point_first_iteration_bound(rule, param):
+    """Iteration 1 with 8-bit messages: each stored message is off by at most
+    1/4 (rounding) or 1/2 (saturation of 64 to 63.5), so the posterior stays
+    within the FP32 bar plus half the bit's degree."""
+    import oracle
+    from paper_1609_01567_amd import ldpc
+    code = _classes_code()
+    llr = li.awgn_llr(code.n, 70, 0.7, seed=72)
+    _announce("q8-bound", rule=rule)
+    gpu = gpu_decode(code, llr, 1, flags=ldpc.MSG_Q8 | ldpc.NO_EARLY_STOP, rule=rule, param=param)
+    ora = oracle.decode(code, llr, 1, early_stop=False, rule=rule or "sp", param=param)
+    deg = np.bincount(code.cols, minlength=code.n).astype(np.float64)
+    bound = ATOL + RTOL * np.abs(ora["lpost"]) + 0.5 * deg[None, :]
+    err = np.abs(gpu["lpost"].astype(np.float64) - ora["lpost"])
+    assert (err <= bound).all(), f"max excess {(err - bound).max():.3e}"
+    assert err.max() > 1e-3                      # the messages really are stored in steps of 1/2
+    for fl in (ldpc.LANE_SLOTS_1, ldpc.LANE_SLOTS_2, ldpc.LANE_SLOTS_4):
+        out = gpu_decode(code, llr, 20, flags=ldpc.MSG_Q8 | fl, rule=rule, param=param)
+        ref = out if fl == ldpc.LANE_SLOTS_1 else ref
+        for k in ref:
+            assert (out[k] == ref[k]).all(), (fl, k)
+
+
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
 def test_reduced_precision_first_iteration_bound(prec):
     """Iteration 1 under normalized Min-Sum: |R| <= min of the other |Lch|, and

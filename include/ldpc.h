@@ -294,13 +294,15 @@ LDPC_API ldpc_status ldpc_simulate_rule(const ldpc_graph *g, int32_t frames, dou
  * Each graph gets a pool of frame slots in HBM that keep the per-frame state
  * of ldpc_decode (channel and posterior LLRs per bit, one message per edge).
  * Frames are queued per graph; a decode *step* is, over every graph at once,
- * one check pass and one bit pass (the same arithmetic and order as
- * ldpc_decode, Algorithm 2's loop body), then the per-frame stop test
- * (Algorithm 7 syndrome, or max_iter reached), the output of frames that
- * stopped, and the admission of queued frames into the freed slots.  Frames of
+ * one or more iterations (iters_per_step) of a check pass and a bit pass (the
+ * same arithmetic and order as ldpc_decode, Algorithm 2's loop body, with the
+ * per-frame stop test of Algorithm 7 or max_iter in the bit pass: a frame that
+ * stops sits out the step's remaining passes), then the output of frames that
+ * stopped and the admission of queued frames into the freed slots.  Frames of
  * one graph therefore advance at their own pace: a frame's result is
- * bit-identical to decoding it alone with ldpc_decode and the same flags.
- * Steps are captured once into a hipGraph and replayed.
+ * bit-identical to decoding it alone with ldpc_decode (ldpc_decode_rule for a
+ * Min-Sum rule) and the same flags.  Steps are captured once into a hipGraph
+ * and replayed.
  *
  * Repacking: once a graph has no queued frames left, the frames still running
  * tend to be scattered over the pool, and every slot group holding one of

@@ -542,7 +542,7 @@ __global__ __launch_bounds__(256) void eng_bit(const EngGraph *__restrict__ grap
     // The previous step's turnover and admission are complete: move each
     // graph's queue head past the frames it admitted and empty its list
     // (a no-op in the later passes of a step).
-    if (blockIdx.x == 0 && threadIdx.x < ngraphs) {
+    if (blockIdx.x == 0 && int(threadIdx.x) < ngraphs) {
         const EngGraph &H = graphs[threadIdx.x];
         *gmem(H.head) += *gmem(H.taken);
         *gmem(H.taken) = 0;
@@ -842,7 +842,7 @@ __global__ __launch_bounds__(256) void eng_repack_move(const EngGraph *__restric
     __shared__ int32_t nm[kMaxGraphs];
     if (threadIdx.x < 64) {   // one lane per graph
         long long items = 0;
-        if (threadIdx.x < ngraphs) {
+        if (int(threadIdx.x) < ngraphs) {
             const int c = threadIdx.x;
             const int32_t moves = gmem(counters)[ctr_moves(ngraphs, c)];
             nm[c] = moves;

@@ -87,7 +87,7 @@ struct Request {
     bool ready = false;        // the submitting thread has finished copying the LLRs
     int32_t counter = -1;
     uint32_t counter_base = 0; // the counter's value when the request took it
-    int64_t admit_round = 0;   // worker round of admission: counters of earlier replays predate its reset
+    int64_t admit_cycle = 0;   // worker cycle of admission: counters copied by earlier replays predate it
     std::vector<uint8_t> bits, ok;
     std::vector<int32_t> iters;
     Clock::time_point t_submit, t_done;
@@ -146,7 +146,7 @@ void fail_worker(ldpc_server *s, const std::string &what) {
 // Admit waiting requests in arrival order while resources allow (worker
 // thread, lock held).  Frames of all admitted requests of a graph go to the
 // engine in one submission that waits for the uploads on the copy stream.
-bool admit_locked(ldpc_server *s, int64_t round) {
+bool admit_locked(ldpc_server *s, int64_t cycle) {
     std::vector<std::vector<ldpc_frame>> batch(static_cast<size_t>(s->ngraphs));
     std::vector<int64_t> queued(static_cast<size_t>(s->ngraphs), 0);
     while (!s->waiting.empty()) {
@@ -170,7 +170,7 @@ bool admit_locked(ldpc_server *s, int64_t round) {
         r->stage_off = hoff;
         r->out_off = ooff;
         r->staged = true;
-        r->admit_round = round;
+        r->admit_cycle = cycle;
         r->counter = s->free_counters.back();
         r->counter_base = s->counter_total[size_t(r->counter)];
         s->free_counters.pop_back();
@@ -245,7 +245,7 @@ void complete_requests(ldpc_server *s, std::vector<Request *> &done) {
 
 // Pipeline: replay k runs while the host reads the counters of replay k-1,
 // queues the result copies of requests that finished by then (they run after
-// replay k on the engine stream) and completes the copies queued one round
+// replay k on the engine stream) and completes the copies queued one cycle
 // earlier.
 void worker_main(ldpc_server *s) {
     (void)hipSetDevice(s->device);
@@ -299,7 +299,7 @@ void worker_main(ldpc_server *s) {
                 }
             }
             uploaded[prv].clear();
-            // result copies queued one round earlier
+            // result copies queued one cycle earlier
             if (!draining[prv].empty()) {
                 if (hipEventSynchronize(s->ev_out[prv]) != hipSuccess) {
                     set_error("event wait failed");
@@ -309,15 +309,15 @@ void worker_main(ldpc_server *s) {
                 complete_requests(s, draining[prv]);
             }
             // requests finished by replay k-1: queue their result copies.  A request
-            // admitted in round k reused its counter after replay k-1's copy was
-            // queued, so only requests admitted before round k are judged here.
+            // admitted in cycle k took its counter after replay k-1's copy was
+            // queued, so only requests admitted before cycle k are checked here.
             std::vector<Request *> fin;
             {
                 std::lock_guard<std::mutex> lk(s->mu);
                 for (size_t i = 0; i < s->inflight.size();) {
                     Request *r = s->inflight[i];
                     const uint32_t counted = uint32_t(s->h_cnt[prv][r->counter]) - r->counter_base;
-                    if (r->admit_round <= k - 1 && counted >= uint32_t(r->frames)) {
+                    if (r->admit_cycle <= k - 1 && counted >= uint32_t(r->frames)) {
                         fin.push_back(r);
                         s->inflight[i] = s->inflight.back();
                         s->inflight.pop_back();

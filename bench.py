@@ -82,6 +82,8 @@ def parse():
     ap.add_argument("--no-structured", action="store_true")
     ap.add_argument("--served-requests", type=int, default=20000,
                     help="counted requests per load point (after a 2 s warm-up)")
+    ap.add_argument("--served-iters-per-step", type=int, default=4,
+                    help="decoder iterations per engine step in the server")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates rocprof byte counters) and exit")
     return ap.parse_args()
@@ -511,7 +513,7 @@ def bench_precision(torch, ldpc, frames=1024, T=100, points=(1.5, 5.0), oracle_f
 
 
 def bench_served(torch, ldpc, capacity_fps, requests, loads=(0.25, 0.5, 0.75, 0.95), T=50, seed=4001,
-                 warmup_s=2.0):
+                 warmup_s=2.0, client_threads=4, iters_per_step=4):
     """Poisson arrivals of requests (1..64 frames of one of the eight batch codes,
     code drawn Zipf(1) by ascending n) at fractions of the measured batch
     capacity; the server (continuous batching, FP16 messages) against plain
@@ -530,14 +532,17 @@ def bench_served(torch, ldpc, capacity_fps, requests, loads=(0.25, 0.5, 0.75, 0.
     zipf /= zipf.sum()
     mean_frames = 32.5
     graphs = [ldpc.Graph.from_code(c) for c in codes]
+    import queue
+    import threading
     out = {"capacity_frames_per_s": round(capacity_fps, 1), "requests_per_load": requests, "warmup_s": warmup_s,
+           "client_threads": client_threads, "iters_per_step": iters_per_step,
            "workload": "Poisson arrivals; request = U{1..64} frames of one code (Zipf(1) over the 8 batch codes), "
                        "Eb/N0 = waterfall + 0.5 dB, max 50 iterations", "loads": []}
     # slot pools follow each code's share of the request stream (the batched mix's Zipf split)
     slots = [int(x) for x in li.batch_frame_split(4096, len(codes))]
     out["slots"] = slots
     srv = ldpc.Server(graphs, slots, T, flags=ldpc.MSG_FP16, hbm_budget=2 << 30,
-                      host_budget=1 << 30, lane_slots=4, graph_steps=2)
+                      host_budget=1 << 30, lane_slots=4, graph_steps=2, iters_per_step=iters_per_step)
     for rho in loads:
         rng = np.random.default_rng(seed + int(rho * 100))
         lam = rho * capacity_fps / mean_frames
@@ -549,33 +554,63 @@ def bench_served(torch, ldpc, capacity_fps, requests, loads=(0.25, 0.5, 0.75, 0.
         starts = rng.integers(0, pool_f - 64 + 1, size=total)
         lat, info = [], 0.0
         pending = {}
+        unmatched = []
+        lock = threading.Lock()
+        work = queue.Queue()
         t_first = t_last = None
+
+        # Client threads make the submit calls (each copies about 1 MB of LLRs on
+        # average), so the arrival process is not limited by one thread's copy rate.
+        # A request's latency runs from its arrival: the wait for a client thread
+        # plus the server's own submit-to-completion time.
+        def submitter():
+            while True:
+                item = work.get()
+                if item is None:
+                    return
+                r, gi, F, st, t_arrival = item
+                t_sub = time.perf_counter()
+                rid = srv.submit(gi, pools[gi][st:st + F])
+                with lock:
+                    pending[rid] = (r, F * kinfo[gi], t_sub - t_arrival)
+
+        def collect(rids):
+            nonlocal info, t_last
+            for rid in unmatched + rids:
+                with lock:
+                    entry = pending.pop(rid, None)
+                if entry is None:                      # completed before its submitter recorded it
+                    if rid not in unmatched:
+                        unmatched.append(rid)
+                    continue
+                if rid in unmatched:
+                    unmatched.remove(rid)
+                _, _, _, l = srv.result(rid, want_bits=False)
+                r, bits, wait = entry
+                if r >= warm:
+                    lat.append(l + wait)
+                    info += bits
+                    t_last = time.perf_counter()
+
+        threads = [threading.Thread(target=submitter, daemon=True) for _ in range(client_threads)]
+        for th in threads:
+            th.start()
         t0 = time.perf_counter()
         t_arr = t0
-
-        def collect(rid):
-            nonlocal info, t_last
-            _, _, _, l = srv.result(rid, want_bits=False)
-            r, bits = pending.pop(rid)
-            if r >= warm:
-                lat.append(l)
-                info += bits
-                t_last = time.perf_counter()
-
         for r in range(total):
             t_arr += gaps[r]
             while time.perf_counter() < t_arr:
-                for rid in srv.poll(0):
-                    collect(rid)
-            gi, F, st = int(gis[r]), int(fs[r]), int(starts[r])
+                collect(srv.poll(0))
             if r == warm:
                 t_first = time.perf_counter()
-            rid = srv.submit(gi, pools[gi][st:st + F])
-            pending[rid] = (r, F * kinfo[gi])
+            work.put((r, int(gis[r]), int(fs[r]), int(starts[r]), t_arr))
+        for _ in threads:
+            work.put(None)
+        for th in threads:
+            th.join()
         deadline = time.perf_counter() + 60
-        while pending and time.perf_counter() < deadline:
-            for rid in srv.poll(20):
-                collect(rid)
+        while (pending or unmatched) and time.perf_counter() < deadline:
+            collect(srv.poll(20))
         lat = np.array(lat)
         window = (t_last or time.perf_counter()) - (t_first or t0)
         out["loads"].append({"offered": rho, "offered_req_per_s": round(lam, 1), "warmup_requests": warm,
@@ -767,7 +802,7 @@ def main():
     served = None
     if not args.no_served:
         cap = 4096.0 / (batched["engine_fp16"]["ms_per_step"] * 1e-3) if batched else 150000.0
-        served = bench_served(torch, ldpc, cap, args.served_requests)
+        served = bench_served(torch, ldpc, cap, args.served_requests, iters_per_step=args.served_iters_per_step)
         print(f"[bench] served done", file=sys.stderr, flush=True)
 
     simulate = None

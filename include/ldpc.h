@@ -440,7 +440,8 @@ typedef struct {
     int32_t max_requests;  /* requests in flight at once (0 = 4096) */
     int32_t rule;          /* check rule of the server's engine, an ldpc_rule_kind (0 = sum-product) */
     float rule_param;      /* its parameter (alpha or beta) */
-    int32_t reserved[3];   /* must be 0 */
+    int32_t iters_per_step;/* decoder iterations per engine step (as for ldpc_engine_opts; 0 = 1) */
+    int32_t reserved[2];   /* must be 0 */
 } ldpc_server_opts;
 
 /*

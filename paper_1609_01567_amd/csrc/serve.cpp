@@ -376,6 +376,7 @@ extern "C" ldpc_status ldpc_server_create(const ldpc_graph *const *graphs, int32
         eo.graph_steps = opts->graph_steps;
         eo.rule = opts->rule;
         eo.rule_param = opts->rule_param;
+        eo.iters_per_step = opts->iters_per_step;
         if (opts->max_requests < 0) { set_error("ldpc_server_create: max_requests < 0"); return LDPC_E_INVAL; }
         if (opts->max_requests) maxreq = opts->max_requests;
     }

@@ -46,7 +46,8 @@ class Frame(ctypes.Structure):
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("lane_slots", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("max_requests", ctypes.c_int32),
-                ("rule", ctypes.c_int32), ("rule_param", ctypes.c_float), ("reserved", ctypes.c_int32 * 3)]
+                ("rule", ctypes.c_int32), ("rule_param", ctypes.c_float), ("iters_per_step", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class Rule(ctypes.Structure):
@@ -490,7 +491,7 @@ class Server:
 
     def __init__(self, graphs, slots, max_iter: int, flags: int = 0, hbm_budget: int = 1 << 30,
                  host_budget: int = 1 << 28, lane_slots: int = 0, graph_steps: int = 0, max_requests: int = 0,
-                 rule=None, rule_param=None):
+                 rule=None, rule_param=None, iters_per_step: int = 0):
         lib = load_library()
         self._lib = lib
         self.graphs = list(graphs)
@@ -498,7 +499,7 @@ class Server:
         hs = (ctypes.c_void_p * ng)(*[g.handle.value for g in self.graphs])
         sl = np.ascontiguousarray(slots, dtype=np.int32)
         r = make_rule(rule, rule_param)
-        opts = ServerOpts(lane_slots, graph_steps, max_requests, r.kind, r.param)
+        opts = ServerOpts(lane_slots, graph_steps, max_requests, r.kind, r.param, iters_per_step)
         self._h = ctypes.c_void_p()
         _check(lib.ldpc_server_create(hs, ng, _np_ptr(sl), int(max_iter), int(flags), int(hbm_budget),
                                       int(host_budget), ctypes.byref(opts), ctypes.byref(self._h)),

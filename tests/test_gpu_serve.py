@@ -49,13 +49,14 @@ def _drain(srv, ids, deadline_s=60.0):
     return out
 
 
-def test_served_results_equal_alone():
+@pytest.mark.parametrize("iters_per_step", [1, 4])
+def test_served_results_equal_alone(iters_per_step):
     from paper_1609_01567_amd import ldpc
     codes = _codes()
     graphs = [ldpc.Graph.from_code(c) for c in codes]
-    srv = ldpc.Server(graphs, [128, 128, 64], 30, graph_steps=2)
+    srv = ldpc.Server(graphs, [128, 128, 64], 30, graph_steps=2, iters_per_step=iters_per_step)
     reqs = _requests(codes, 60, seed=1)
-    print(f"[case] serve-mix requests={len(reqs)}", flush=True)
+    print(f"[case] serve-mix requests={len(reqs)} iters_per_step={iters_per_step}", flush=True)
     ids = [srv.submit(gi, llr) for gi, llr in reqs]
     res = _drain(srv, ids)
     st = srv.stats()

@@ -86,7 +86,65 @@ def parse():
                     help="decoder iterations per engine step in the server")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates rocprof byte counters) and exit")
+    ap.add_argument("--engine-timeline", action="store_true",
+                    help="only run the batched mix through the autotuned FP16 engine one replay at a time, "
+                         "printing each replay's time and the frames still pending per code, and exit")
+    ap.add_argument("--timeline-one-iteration", action="store_true",
+                    help="with --engine-timeline: one step of one iteration per replay (per-iteration counts)")
     return ap.parse_args()
+
+
+def engine_timeline(torch, ldpc, T=50, reps=2, gap_s=0.002, one_iteration=False):
+    """The batched mix, one engine replay at a time (FP16 messages, autotuned).
+
+    After every replay the host waits for the engine and records the replay's
+    wall time and the frames still pending per code; a short sleep between
+    replays separates them in a kernel trace.  The last of `reps` batches is
+    reported, with the edge-frames each code still had running (the work an
+    iteration at full activity would do for them).  one_iteration: the tuned
+    pools and lane width, but one step of one iteration per replay.
+    """
+    from paper_1609_01567_amd import workloads
+    mix = workloads.batched_mix()
+    graphs = [ldpc.Graph.from_code(c) for c, *_ in mix]
+    d_llr = [torch.from_numpy(x).cuda() for *_, x in mix]
+    outs = [ldpc.DecodeResult(bits=torch.empty((F, c.n), dtype=torch.uint8, device="cuda"),
+                              ok=torch.empty(F, dtype=torch.uint8, device="cuda"),
+                              iters=torch.empty(F, dtype=torch.int32, device="cuda"), llr=None) for c, F, *_ in mix]
+    frame_lists = [ldpc.frames_for(x, o.bits, o.ok, o.iters) for x, o in zip(d_llr, outs)]
+    torch.cuda.synchronize()
+    tune = ldpc.autotune(graphs, frame_lists, T, ldpc.MSG_FP16)
+    if one_iteration:
+        tune.update(graph_steps=1, iters_per_step=1)
+    eng = ldpc.Engine(graphs, tune["slots"], [len(fl) for fl in frame_lists], T, flags=ldpc.MSG_FP16,
+                      lane_slots=tune["lane_slots"], graph_steps=tune["graph_steps"],
+                      iters_per_step=tune["iters_per_step"])
+    edges = [c.nnz for c, *_ in mix]
+    replays = []
+    for _ in range(reps):
+        for gi, fl in enumerate(frame_lists):
+            eng.submit(gi, fl)
+        torch.cuda.synchronize()
+        replays = []
+        while True:
+            t0 = time.perf_counter()
+            eng.step(1)
+            _, pending = eng.poll()
+            ms = (time.perf_counter() - t0) * 1e3
+            replays.append({"ms": round(ms, 3), "pending": pending.tolist(),
+                            "pending_edge_frames": int(sum(e * p for e, p in zip(edges, pending.tolist())))})
+            time.sleep(gap_s)
+            if not pending.any():
+                break
+            if len(replays) > 4 * T:
+                raise RuntimeError("engine timeline: frames still pending after many replays")
+    eng.close()
+    iters = [o.iters.cpu().numpy() for o in outs]
+    return {"metric": "engine_timeline", "tuning": tune,
+            "iterations_per_replay": tune["graph_steps"] * tune["iters_per_step"],
+            "codes": [{"code": c.name, "frames": F, "edges": c.nnz, "mean_iters": round(float(it.mean()), 2),
+                       "frac_at_max_iter": round(float((it == T).mean()), 4)} for (c, F, *_), it in zip(mix, iters)],
+            "replays": replays, "total_ms": round(sum(r["ms"] for r in replays), 3)}
 
 
 def copy_ceiling(torch, nbytes=1 << 30, reps=5):
@@ -686,6 +744,9 @@ def main():
         b.copy_(a)          # one dispatch: reads 1 GiB, writes 1 GiB
         torch.cuda.synchronize()
         print(json.dumps({"calib_copy_bytes_read": 1 << 30, "calib_copy_bytes_written": 1 << 30}))
+        return
+    if args.engine_timeline:
+        print(json.dumps(engine_timeline(torch, ldpc, one_iteration=args.timeline_one_iteration)))
         return
     flags = {"fp32": 0, "fp16": ldpc.MSG_FP16, "bf16": ldpc.MSG_BF16}[args.msg]
     flags |= {0: 0, 1: ldpc.LANE_SLOTS_1, 2: ldpc.LANE_SLOTS_2, 4: ldpc.LANE_SLOTS_4}[args.lane_slots]

@@ -208,9 +208,17 @@ constexpr int kBitItems = -1;   // `cls` value for the bit pass: items are bits
 // body each).
 enum PackMode { kPackNone = 0, kPackAll = 1, kPackOnlyFlat = 2, kPackOnlyPacked = 3 };
 
-template <int PM = kPackNone>
+// Lane-width split, for the chunked class (which has no packed form): the
+// launch at the engine's lane width (kSplitWide) takes the graphs whose extent
+// exceeds half of `wide_unit` slots (64 lanes at that width); a second launch
+// at one slot per lane (kSplitNarrow) takes the others, so a drained pool pays
+// for 64-slot groups instead of 64 V-slot ones.
+enum LaneSplit { kSplitNone = 0, kSplitWide = 1, kSplitNarrow = 2 };
+
+template <int PM = kPackNone, int SPLIT = kSplitNone>
 __device__ __forceinline__ void build_work(const EngGraph *__restrict__ graphs, int32_t ngraphs,
-                                           const int32_t *__restrict__ counters, int cls, int unit, int per, Work &w) {
+                                           const int32_t *__restrict__ counters, int cls, int unit, int per, Work &w,
+                                           int wide_unit = 0) {
     // wavefront 0, one lane per graph (at most 32): the graphs' extents load in
     // parallel and an inclusive scan over the lanes gives the item offsets
     if (threadIdx.x < 64) {
@@ -224,7 +232,8 @@ __device__ __forceinline__ void build_work(const EngGraph *__restrict__ graphs, 
             int32_t rpw = 1;
             if (PM != kPackNone && x > 0)
                 while (rpw < kMaxPack && (unit / (2 * rpw)) >= x) rpw *= 2;   // unit = 64 V slots per wavefront
-            const bool take = PM == kPackNone || PM == kPackAll || (PM == kPackOnlyFlat) == (rpw == 1);
+            bool take = PM == kPackNone || PM == kPackAll || (PM == kPackOnlyFlat) == (rpw == 1);
+            if (SPLIT != kSplitNone) take = (SPLIT == kSplitNarrow) == (x > 0 && 2 * x <= wide_unit);
             w.groups[c] = gr;
             w.rpw[c] = rpw;
             items = !take ? 0 : rpw > 1 ? (units + rpw - 1) / rpw : (units * gr + per - 1) / per;
@@ -298,18 +307,19 @@ __global__ __launch_bounds__(256) void eng_check_rows(const EngGraph *__restrict
 }
 
 // Rows of 9..128 edges over WPR wavefronts (see check_chunk_kernel in decode.hip);
-// one workgroup item = 4 / WPR (row, slot group) pairs.
-template <int M, int V, int WPR, int RULE>
+// one workgroup item = 4 / WPR (row, slot group) pairs.  SPLIT selects the
+// graphs by extent (LaneSplit); wide_unit is 64 times the engine's lane width.
+template <int M, int V, int WPR, int RULE, int SPLIT>
 __global__ __launch_bounds__(256) void eng_check_chunk(const EngGraph *__restrict__ graphs, int32_t ngraphs,
                                                        const int32_t *__restrict__ counters, int32_t cls, int32_t T,
-                                                       int32_t early, int32_t par, float rp) {
+                                                       int32_t early, int32_t par, float rp, int32_t wide_unit) {
     using MT = typename Codec<M>::T;
     constexpr int C = kRowChunk;
     constexpr int RPB = 4 / WPR;
     constexpr int MAXCH = WPR == 2 ? 2 : 16;
     __shared__ ChunkShare<V, RPB * MAXCH> sh;
     __shared__ Work w;
-    build_work(graphs, ngraphs, counters, cls, 64 * V, RPB, w);
+    build_work<kPackNone, SPLIT>(graphs, ngraphs, counters, cls, 64 * V, RPB, w, wide_unit);
     const int lane = threadIdx.x & 63;
     const int wave = wave_uniform(threadIdx.x >> 6);
     const int lr = wave / WPR;
@@ -917,6 +927,8 @@ struct ldpc_engine {
     int64_t bit_waves = 0, hub_blocks = 0, total_slots = 0, row_waves[3] = {0, 0, 0};   // with every slot occupied
     unsigned grid_rows[3] = {1, 1, 1}, grid_hub = 1, grid_bit = 1;   // workgroups per launch (grid-stride)
     unsigned grid_packed = 256;      // packed row items: few rows per graph once drained
+    unsigned grid_chunk_narrow = 1;  // chunked rows of drained pools at one slot per lane
+    int64_t chunk_rows = 0;          // rows of the chunked class over all graphs
 };
 
 namespace {
@@ -955,10 +967,26 @@ void enqueue_step_rule(ldpc_engine *e) {
         if (e->has_rows[1])
             launch_rows<M, ldpc::class_lane_slots(ldpc::kClassD16, V), 16, RULE>(e, ldpc::kClassD16, e->grid_rows[1],
                                                                                  par);
-        if (e->has_rows[2])
-            hipLaunchKernelGGL((eng_check_chunk<M, V, ldpc::class_waves_per_row(ldpc::kClassD128), RULE>),
-                               dim3(e->grid_rows[2]), dim3(256), 0, st, e->d_graphs, ng, e->d_counters,
-                               int32_t(ldpc::kClassD128), e->T, early, par, rp);
+        if (e->has_rows[2]) {
+            constexpr int W = ldpc::class_waves_per_row(ldpc::kClassD128);
+            const int32_t wide_unit = 64 * V;
+            bool split = false;
+            if constexpr (V > 1) {
+                split = e->pack;
+                if (split) {
+                    hipLaunchKernelGGL((eng_check_chunk<M, V, W, RULE, kSplitWide>), dim3(e->grid_rows[2]), dim3(256),
+                                       0, st, e->d_graphs, ng, e->d_counters, int32_t(ldpc::kClassD128), e->T, early,
+                                       par, rp, wide_unit);
+                    hipLaunchKernelGGL((eng_check_chunk<M, 1, W, RULE, kSplitNarrow>), dim3(e->grid_chunk_narrow),
+                                       dim3(256), 0, st, e->d_graphs, ng, e->d_counters, int32_t(ldpc::kClassD128),
+                                       e->T, early, par, rp, wide_unit);
+                }
+            }
+            if (!split)
+                hipLaunchKernelGGL((eng_check_chunk<M, V, W, RULE, kSplitNone>), dim3(e->grid_rows[2]), dim3(256), 0,
+                                   st, e->d_graphs, ng, e->d_counters, int32_t(ldpc::kClassD128), e->T, early, par,
+                                   rp, wide_unit);
+        }
         if (e->has_hub)
             hipLaunchKernelGGL((eng_check_hub<M, RULE>), dim3(e->grid_hub), dim3(256), 0, st, e->d_graphs, ng,
                                e->d_counters, e->T, early, par, rp);
@@ -1039,8 +1067,14 @@ void size_grids(ldpc_engine *e, int cus) {
     e->grid_packed = fit(reinterpret_cast<const void *>(&eng_check_rows<M, V, 8, kPackOnlyPacked, kRuleSP>),
                          std::max<int64_t>(1, (e->row_waves[0] + e->row_waves[1] + 3) / 4));
     e->grid_rows[2] = fit(reinterpret_cast<const void *>(&eng_check_chunk<M, V, ldpc::class_waves_per_row(ldpc::kClassD128),
-                                                                          kRuleSP>),
+                                                                          kRuleSP, kSplitWide>),
                           e->row_waves[2]);
+    // the narrow launch covers at most 32 V slots per row of each graph: V / 2 groups of 64
+    if constexpr (V > 1)
+        e->grid_chunk_narrow = fit(reinterpret_cast<const void *>(
+                                       &eng_check_chunk<M, 1, ldpc::class_waves_per_row(ldpc::kClassD128), kRuleSP,
+                                                        kSplitNarrow>),
+                                   std::max<int64_t>(1, e->chunk_rows * (V / 2)));
     e->grid_hub = fit(reinterpret_cast<const void *>(&eng_check_hub<M, kRuleSP>), e->hub_blocks);
     e->grid_bit = fit(reinterpret_cast<const void *>(&eng_bit<M, V>), (e->bit_waves + 3) / 4);
 }
@@ -1254,6 +1288,8 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
         e->row_waves[k] = tot;
         e->has_rows[k] = tot > 0;
     }
+    for (int32_t c = 0; c < ngraphs; c++)
+        e->chunk_rows += graphs[c]->class_begin[ldpc::kClassD128 + 1] - graphs[c]->class_begin[ldpc::kClassD128];
     e->pre_slots.count = ngraphs;
     e->pre_slots.p[0] = 0;
     for (int32_t c = 0; c < ngraphs; c++) {

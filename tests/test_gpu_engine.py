@@ -235,6 +235,32 @@ def test_engine_repack_equals_plain(lane_slots, msg):
     _assert_same(on, plain, "repack vs plain")
 
 
+@pytest.mark.parametrize("lane_slots", [2, 4])
+@pytest.mark.parametrize("msg", ["fp32", "fp16"])
+def test_engine_chunked_rows_drained_pools_equal_plain(lane_slots, msg):
+    """Rows of 17..64 edges (the chunked class).  A pool whose extent is at most
+    32 V slots runs them at one slot per lane: here one graph starts that way
+    (40 frames), and one gets there by finishing and repacking (700 frames)."""
+    from paper_1609_01567_amd import ldpc
+    flags = {"fp32": 0, "fp16": ldpc.MSG_FP16}[msg]
+    rng = np.random.default_rng(23)
+    cdeg = rng.integers(17, 65, size=150)
+    E = int(cdeg.sum())
+    bdeg = np.full(1500, E // 1500)
+    bdeg[: E - bdeg.sum()] += 1
+    code = li.socket_code(bdeg, cdeg, seed=24)
+    assert int(cdeg.min()) > 16
+    small = li.awgn_llr(code.n, 40, li.ebn0_to_sigma2(4.0, code.rate), seed=25)
+    big = li.awgn_llr(code.n, 700, li.ebn0_to_sigma2(4.0, code.rate), seed=26)
+    _announce("engine-chunk-drained", lane_slots=lane_slots, msg=msg)
+    out = _engine_decode([code, code], [small, big], [256, 768], 30, flags=flags, lane_slots=lane_slots,
+                         graph_steps=2, iters_per_step=2)
+    for x, o, what in ((small, out[0], "40 frames"), (big, out[1], "700 frames")):
+        plain = gpu_decode(code, x, 30, flags=flags)
+        _assert_same(o, plain, f"{what}: engine vs plain")
+    assert len(set(out[1]["iters"].tolist())) > 5
+
+
 def test_engine_repack_with_long_rows_and_many_graphs():
     """Repacking under rows of every class (the >128-edge path keeps per-slot
     scratch) and with 16 graphs in one engine (counters of every graph)."""

@@ -45,3 +45,30 @@ def test_many_frames_in_one_call():
     _properties(code, out, 30)
     # messages of this call: E x S x 4 bytes = 0.94 GB; every slot group up to the ragged last one
     print(compare(code, llr, 30, frames=[0, 1, 63, 64, 32767, 65471, 65472, F - 1], gpu=out))
+
+
+def test_batched_mix_full_size_engine_equals_plain():
+    """The batched workload at full size (eight codes, 4096 frames) through the
+    engine in the shape the autotuner picks for it (4 slots per lane, 4 steps
+    per replay, 2 iterations per step, the tuned pools), FP16 messages: every
+    frame is bit-identical to a plain FP16 decode of its code.  The plain FP32
+    decode of every code is held to the oracle on its first and last frames."""
+    import torch
+    from paper_1609_01567_amd import ldpc, workloads
+    mix = workloads.batched_mix()
+    T = 50
+    print(f"[case] batched mix, {sum(F for _, F, *_ in mix)} frames", flush=True)
+    graphs = [ldpc.Graph.from_code(c) for c, *_ in mix]
+    eng = ldpc.Engine(graphs, [1507, 754, 502, 377, 302, 256, 256, 256], [F for _, F, *_ in mix], T,
+                      flags=ldpc.MSG_FP16, lane_slots=4, graph_steps=4, iters_per_step=2)
+    jobs = [(i, torch.from_numpy(np.ascontiguousarray(x)).cuda()) for i, (*_, x) in enumerate(mix)]
+    res = ldpc.decode_batch(eng, jobs, want_llr=True, max_replays=200)
+    torch.cuda.synchronize()
+    eng.close()
+    for (code, F, eb, cw, llr), g, r in zip(mix, graphs, res):
+        plain = gpu_decode(code, llr, T, flags=ldpc.MSG_FP16, graph=g)
+        for k, v in (("bits", r.bits), ("ok", r.ok), ("iters", r.iters), ("lpost", r.llr)):
+            assert (v.cpu().numpy() == plain[k]).all(), f"{code.name}: engine {k} differs from plain"
+        p32 = gpu_decode(code, llr, T, graph=g)
+        _properties(code, p32, T)
+        print(code.name, compare(code, llr, T, frames=[0, F - 1], gpu=p32), flush=True)

@@ -84,6 +84,8 @@ def parse():
                     help="counted requests per load point (after a 2 s warm-up)")
     ap.add_argument("--served-iters-per-step", type=int, default=4,
                     help="decoder iterations per engine step in the server")
+    ap.add_argument("--no-compact", action="store_true",
+                    help="time the headline decode without tail compaction (LDPC_COMPACT_TAIL)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates rocprof byte counters) and exit")
     ap.add_argument("--engine-timeline", action="store_true",
@@ -761,7 +763,10 @@ def main():
             for i, eb in enumerate(points)]
     g = ldpc.Graph.from_code(code)
     d_llr = [torch.from_numpy(x).cuda() for x in llrs]
-    ws = ldpc.Workspace(ldpc.workspace_size(g, F, flags))
+    # the timed decodes compact their tails; the profiled pass below times the
+    # full-width kernels without it
+    timed_flags = flags | (0 if args.no_compact else ldpc.COMPACT_TAIL)
+    ws = ldpc.Workspace(ldpc.workspace_size(g, F, timed_flags))
     outs = [ldpc.DecodeResult(bits=torch.empty((F, n), dtype=torch.uint8, device="cuda"),
                               ok=torch.empty(F, dtype=torch.uint8, device="cuda"),
                               iters=torch.empty(F, dtype=torch.int32, device="cuda"), llr=None) for _ in points]
@@ -769,7 +774,7 @@ def main():
 
     def step():
         for i in range(len(points)):
-            ldpc.decode(g, d_llr[i], T, flags=flags, workspace=ws, stream=stream, out=outs[i])
+            ldpc.decode(g, d_llr[i], T, flags=timed_flags, workspace=ws, stream=stream, out=outs[i])
 
     for _ in range(args.warmup):
         step()
@@ -910,6 +915,7 @@ def main():
                                f"degree 7), {F} frames at each Eb/N0 in {points} dB, max {T} iterations, "
                                f"syndrome early stop, {args.msg} messages",
                    "frames_per_step": frames_per_step, "info_bits_per_frame": k},
+        "tail_compaction": not args.no_compact,
         "hbm_frac_step": round(hbm_frac, 4),
         "copy_ceiling_gbs": round(ceiling, 1),
         "per_point": per_point,

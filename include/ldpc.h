@@ -62,7 +62,20 @@ enum {
      * Results do not depend on the choice. */
     LDPC_LANE_SLOTS_1 = 1u << 3,
     LDPC_LANE_SLOTS_2 = 1u << 4,
-    LDPC_LANE_SLOTS_4 = 1u << 5
+    LDPC_LANE_SLOTS_4 = 1u << 5,
+    /* Tail compaction (ldpc_decode / ldpc_decode_rule / ldpc_decode_profiled
+     * only; ignored with LDPC_NO_EARLY_STOP and below 256 frame slots).  Every
+     * 4 iterations from iteration 8 the call counts the frames still running;
+     * once they fit in half of the slots in use, it copies their state into a
+     * smaller slot range (at most half, then at most a quarter of the slots)
+     * and runs the remaining iterations there, one frame slot per lane, then
+     * copies the posteriors back; once no frame runs it skips the remaining
+     * iterations.  Results are identical.  The call waits on the stream for
+     * each count (the device keeps two iterations of queued work meanwhile),
+     * so it returns only shortly before the decode ends and cannot be
+     * captured into a graph.  The workspace grows by three quarters of the
+     * per-slot state. */
+    LDPC_COMPACT_TAIL = 1u << 7
 };
 
 /* Graph flags. */
@@ -147,7 +160,7 @@ LDPC_API ldpc_status ldpc_decode_workspace_size(const ldpc_graph *g, int32_t fra
  *  frames       >= 0 (0 is a no-op).
  *  max_iter     >= 1.
  *  flags        LDPC_NO_EARLY_STOP | at most one of LDPC_MSG_FP16, LDPC_MSG_BF16, LDPC_MSG_Q8 |
- *               at most one LDPC_LANE_SLOTS_* tile-shape flag.
+ *               at most one LDPC_LANE_SLOTS_* tile-shape flag | LDPC_COMPACT_TAIL.
  *  bits_out     device uint8 [frames][n]: the estimate (0/1).
  *  syndrome_ok  device uint8 [frames]: 1 iff the returned estimate is a codeword.
  *  iters        device int32 [frames]: iterations run, 1..max_iter (the

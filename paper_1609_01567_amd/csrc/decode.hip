@@ -555,6 +555,95 @@ __global__ __launch_bounds__(256) void tally_kernel(const int32_t *__restrict__ 
     }
 }
 
+// ------------------------------------------------------- tail compaction
+//
+// Once few frames of a call are still running, their state is copied into a
+// smaller slot range (slot k of the copy holds slot map[k] of the full state)
+// and the remaining iterations run there at one slot per lane.  Only the
+// running frames move; the per-frame arithmetic is unchanged, so results are
+// identical.  A frame "runs" while iters[s] == 0.
+
+// One workgroup: the running slots in slot order (map) and their number.
+__global__ __launch_bounds__(1024) void running_list_kernel(const int32_t *__restrict__ iters, int32_t S,
+                                                            int32_t *__restrict__ map, int32_t cap,
+                                                            int32_t *__restrict__ count) {
+    __shared__ int32_t part[16];
+    __shared__ int32_t base;
+    if (threadIdx.x == 0) base = 0;
+    __syncthreads();
+    for (int s0 = 0; s0 < S; s0 += blockDim.x) {
+        const int s = s0 + int(threadIdx.x);
+        const bool run = s < S && iters[s] == 0;
+        const uint64_t m = __ballot(run);
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        if (lane == 0) part[w] = __popcll(m);
+        __syncthreads();
+        int before = base;
+        for (int i = 0; i < w; i++) before += part[i];
+        const int idx = before + __popcll(m & ((uint64_t(1) << lane) - 1u));
+        if (run && map && idx < cap) map[idx] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int tot = 0;
+            for (int i = 0; i < int(blockDim.x >> 6); i++) tot += part[i];
+            base += tot;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *count = base;
+}
+
+// Copy rows of [rows][S] state into [rows][Sc]: element (r, k) takes
+// src[r][map[k]] for k < count, 0 above.  W is the element type.
+template <typename W>
+__global__ __launch_bounds__(256) void gather_slots_kernel(const W *__restrict__ src, int32_t S, W *__restrict__ dst,
+                                                           int32_t Sc, int64_t rows, const int32_t *__restrict__ map,
+                                                           const int32_t *__restrict__ count) {
+    const int32_t K = min(*count, Sc);
+    const int64_t total = rows * Sc;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t r = i / Sc;
+        const int k = int(i - r * Sc);
+        dst[i] = k < K ? src[r * S + map[k]] : W(0);
+    }
+}
+
+// Per-slot state of the copy: running frames keep their fail marks; the
+// slots above count are padding.
+__global__ __launch_bounds__(256) void gather_state_kernel(const int32_t *__restrict__ fail, int32_t Sc,
+                                                           const int32_t *__restrict__ map,
+                                                           const int32_t *__restrict__ count, int32_t *__restrict__ c_iters,
+                                                           int32_t *__restrict__ c_fail) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= Sc) return;
+    const bool live = k < *count;
+    c_iters[k] = live ? 0 : kPadSlot;
+    c_fail[k] = live ? fail[map[k]] : 0;
+}
+
+// Back to the full state: posterior rows, iteration counts and fail marks of
+// the moved frames (the messages are not needed after the last iteration).
+__global__ __launch_bounds__(256) void scatter_slots_kernel(const float *__restrict__ c_lpost, int32_t Sc,
+                                                            float *__restrict__ lpost, int32_t S, int64_t n,
+                                                            const int32_t *__restrict__ c_iters,
+                                                            const int32_t *__restrict__ c_fail, int32_t *__restrict__ iters,
+                                                            int32_t *__restrict__ fail, const int32_t *__restrict__ map,
+                                                            const int32_t *__restrict__ count) {
+    const int32_t K = min(*count, Sc);
+    const int64_t total = n * Sc;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t v = i / Sc;
+        const int k = int(i - v * Sc);
+        if (k < K) {
+            lpost[v * S + map[k]] = c_lpost[i];
+            if (v == 0) {
+                iters[map[k]] = c_iters[k];
+                fail[map[k]] = c_fail[k];
+            }
+        }
+    }
+}
+
 struct Plan {
     int msg = kF32;
     int V = 1;
@@ -562,6 +651,13 @@ struct Plan {
     size_t off_lch = 0, off_lpost = 0, off_r = 0, off_iters = 0, off_fail = 0;
     size_t off_aggd = 0, off_aggpre = 0, off_aggbits = 0, total = 0;
     size_t off_err = 0, off_it = 0, off_ok = 0;   // Monte-Carlo runs only
+    // tail compaction (LDPC_COMPACT_TAIL): two copies of the state, for S/2
+    // and S/4 slots (level 1 and 2), and the word the running counts go through
+    struct Level {
+        int32_t Sc = 0;
+        size_t off_lch = 0, off_lpost = 0, off_r = 0, off_iters = 0, off_fail = 0, off_map = 0, off_count = 0;
+    } lv[2];
+    size_t off_probe = 0;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -569,7 +665,8 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 constexpr uint32_t kLaneSlotFlags = LDPC_LANE_SLOTS_1 | LDPC_LANE_SLOTS_2 | LDPC_LANE_SLOTS_4;
 
 bool flags_ok(uint32_t flags) {
-    const uint32_t known = LDPC_NO_EARLY_STOP | LDPC_MSG_FP16 | LDPC_MSG_BF16 | LDPC_MSG_Q8 | kLaneSlotFlags;
+    const uint32_t known =
+        LDPC_NO_EARLY_STOP | LDPC_MSG_FP16 | LDPC_MSG_BF16 | LDPC_MSG_Q8 | kLaneSlotFlags | LDPC_COMPACT_TAIL;
     if (flags & ~known) return false;
     if (__builtin_popcount(flags & (LDPC_MSG_FP16 | LDPC_MSG_BF16 | LDPC_MSG_Q8)) > 1) return false;
     if (__builtin_popcount(flags & kLaneSlotFlags) > 1) return false;
@@ -601,6 +698,23 @@ Plan make_plan(const ldpc_graph *g, int32_t F, uint32_t flags, bool sim = false)
         p.off_it = off;  off = align256(off + S * 4);
         p.off_ok = off;  off = align256(off + S);
     }
+    // Pools below 256 slots are left as they are (S is then a multiple of
+    // 256, so both copies hold whole 64-slot groups).
+    if ((flags & LDPC_COMPACT_TAIL) && !(flags & LDPC_NO_EARLY_STOP) && !sim && p.S >= 256) {
+        for (int l = 0; l < 2; l++) {
+            Plan::Level &L = p.lv[l];
+            L.Sc = p.S / (2 << l);
+            const size_t Sc = size_t(L.Sc);
+            L.off_lch = off;   off = align256(off + size_t(g->n) * Sc * 4);
+            L.off_lpost = off; off = align256(off + size_t(g->n) * Sc * 4);
+            L.off_r = off;     off = align256(off + size_t(g->E) * Sc * msg_bytes);
+            L.off_iters = off; off = align256(off + Sc * 4);
+            L.off_fail = off;  off = align256(off + Sc * 4);
+            L.off_map = off;   off = align256(off + Sc * 4);
+            L.off_count = off; off = align256(off + 4);
+        }
+        p.off_probe = off; off = align256(off + 4);
+    }
     p.total = off;
     return p;
 }
@@ -611,6 +725,7 @@ struct Bufs {
     int32_t *iters, *fail;
     float *aggd, *aggpre;
     int32_t *aggbits;
+    char *base = nullptr;   // the workspace (for the compaction copy's offsets)
 };
 
 inline unsigned blocks_for_waves(int64_t waves) { return unsigned((waves + 3) / 4); }
@@ -724,6 +839,77 @@ struct SimRun {
     ldpc_sim_counts *counts = nullptr;
 };
 
+// State copies of the compacted tail (LDPC_COMPACT_TAIL) and the pinned word the
+// running-frame counts come back through (one per host thread, kept for the
+// thread's lifetime; a call waits for its last count before it returns).
+struct CompactLevel {
+    Bufs b;                       // lch, lpost, r, iters, fail of the copy; hub scratch shared
+    int32_t Sc = 0;               // capacity in slots
+    int32_t *map = nullptr;       // slot k of the copy holds slot map[k] of the level above
+    int32_t *count = nullptr;     // frames moved in
+};
+
+struct Compact {
+    bool on = false;
+    CompactLevel lv[2];
+    int32_t *probe = nullptr;     // device word of the periodic counts
+    int32_t *host_count = nullptr;
+};
+
+int32_t *pinned_count_word() {
+    static thread_local int32_t *word = nullptr;
+    if (!word) {
+        void *h = nullptr;
+        if (hipHostMalloc(&h, 256, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        word = static_cast<int32_t *>(h);
+    }
+    return word;
+}
+
+Compact compact_at(const Plan &p, const Bufs &b, bool wanted) {
+    Compact c;
+    if (!wanted || p.lv[0].Sc == 0 || !b.base) return c;
+    char *ws = b.base;
+    for (int l = 0; l < 2; l++) {
+        const Plan::Level &L = p.lv[l];
+        CompactLevel &C = c.lv[l];
+        C.b = b;
+        C.b.lch = reinterpret_cast<float *>(ws + L.off_lch);
+        C.b.lpost = reinterpret_cast<float *>(ws + L.off_lpost);
+        C.b.r = ws + L.off_r;
+        C.b.iters = reinterpret_cast<int32_t *>(ws + L.off_iters);
+        C.b.fail = reinterpret_cast<int32_t *>(ws + L.off_fail);
+        C.Sc = L.Sc;
+        C.map = reinterpret_cast<int32_t *>(ws + L.off_map);
+        C.count = reinterpret_cast<int32_t *>(ws + L.off_count);
+    }
+    c.probe = reinterpret_cast<int32_t *>(ws + p.off_probe);
+    c.host_count = pinned_count_word();
+    c.on = c.host_count != nullptr;
+    return c;
+}
+
+// List the running frames of `from` (S slots; at most Sp of them run: frames
+// only ever stop) and copy their messages, channel and posterior LLRs and fail
+// marks into the first Sp slots of `to`.
+template <int M>
+void enqueue_compaction(const ldpc_graph *g, const Bufs &from, int32_t S, const CompactLevel &to, int32_t Sp,
+                        hipStream_t st) {
+    using W = typename Raw<sizeof(typename Codec<M>::T)>::T;
+    hipLaunchKernelGGL(running_list_kernel, dim3(1), dim3(1024), 0, st, from.iters, S, to.map, Sp, to.count);
+    hipLaunchKernelGGL((gather_slots_kernel<W>), dim3(4096), dim3(256), 0, st, static_cast<const W *>(from.r), S,
+                       static_cast<W *>(to.b.r), Sp, int64_t(g->E), to.map, to.count);
+    hipLaunchKernelGGL((gather_slots_kernel<float>), dim3(2048), dim3(256), 0, st, from.lch, S, to.b.lch, Sp,
+                       int64_t(g->n), to.map, to.count);
+    hipLaunchKernelGGL((gather_slots_kernel<float>), dim3(2048), dim3(256), 0, st, from.lpost, S, to.b.lpost, Sp,
+                       int64_t(g->n), to.map, to.count);
+    hipLaunchKernelGGL(gather_state_kernel, dim3(unsigned((Sp + 255) / 256)), dim3(256), 0, st, from.fail, Sp,
+                       to.map, to.count, to.b.iters, to.b.fail);
+}
+
 template <int M, int V>
 void run_decode(const ldpc_graph *g, const Plan &p, const Bufs &b, const float *llr_in, int32_t F, int32_t T,
                 bool early_stop, uint8_t *bits, uint8_t *ok, int32_t *iters_out, float *llr_out, hipStream_t st,
@@ -744,14 +930,86 @@ void run_decode(const ldpc_graph *g, const Plan &p, const Bufs &b, const float *
     }
     mk.mark(1, st);
     const unsigned bit_blocks = blocks_for_waves(int64_t(g->n) * groups);
+
+    // Tail compaction: every kEvery iterations a one-workgroup kernel counts
+    // the running frames into pinned host memory; the host reads the count
+    // kLag iterations later (the device is then still busy with those).  Once
+    // the running frames fit in half of the current slots (and in the next
+    // copy), it moves them into that copy: S -> at most S/2 -> at most S/4.
+    constexpr int32_t kFirstCheck = 8, kEvery = 4, kLag = 2;
+    Compact cp = compact_at(p, b, early_stop && !sim.on);
+    hipEvent_t ev = nullptr;
+    if (cp.on && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        cp.on = false;
+    }
+    int level = 0;                // 0: the full state; 1, 2: the copies
+    int32_t Sl[3] = {S, 0, 0};    // slots in use at each level
+    int32_t check = 0;            // iteration after which a count is in flight (0: none)
     for (int32_t t = 1; t <= T; t++) {
         const int32_t syn_iter = (early_stop && t > 1) ? t - 1 : 0;
-        launch_check_pass_rule<M, V>(g, t == 1 ? kFirst : kIter, t == 1 ? b.lch : b.lpost, b, S, syn_iter, rule, st);
-        mk.mark(2 * t, st);
-        hipLaunchKernelGGL((bit_kernel<M, V>), dim3(bit_blocks), dim3(256), 0, st, g->d_col_ptr, g->d_csc_to_csr,
-                           g->n, b.lch, static_cast<const MT *>(b.r), b.lpost, b.iters, b.fail, S, groups, t,
-                           int32_t(early_stop));
-        mk.mark(2 * t + 1, st);
+        if (check > 0 && t == check + kLag + 1) {
+            check = 0;
+            int32_t K = -1;
+            if (hipEventSynchronize(ev) == hipSuccess) K = *cp.host_count;
+            (void)hipGetLastError();
+            if (K == 0) {   // every frame has stopped: the remaining iterations have no work
+                for (int32_t u = t; u <= T; u++) {
+                    mk.mark(2 * u, st);
+                    mk.mark(2 * u + 1, st);
+                }
+                break;
+            }
+            const int32_t need = (K + 63) / 64 * 64;
+            if (K > 0 && level < 2 && need <= cp.lv[level].Sc && 2 * need <= Sl[level]) {
+                const Bufs &from = level == 0 ? b : cp.lv[level - 1].b;
+                enqueue_compaction<M>(g, from, Sl[level], cp.lv[level], need, st);
+                level++;
+                Sl[level] = need;
+            }
+        }
+        if (level > 0) {
+            const Bufs &cb = cp.lv[level - 1].b;
+            const int32_t Sp = Sl[level];
+            launch_check_pass_rule<M, 1>(g, kIter, cb.lpost, cb, Sp, syn_iter, rule, st);
+            mk.mark(2 * t, st);
+            hipLaunchKernelGGL((bit_kernel<M, 1>), dim3(blocks_for_waves(int64_t(g->n) * (Sp / 64))), dim3(256), 0, st,
+                               g->d_col_ptr, g->d_csc_to_csr, g->n, cb.lch, static_cast<const MT *>(cb.r), cb.lpost,
+                               cb.iters, cb.fail, Sp, Sp / 64, t, int32_t(early_stop));
+            mk.mark(2 * t + 1, st);
+        } else {
+            launch_check_pass_rule<M, V>(g, t == 1 ? kFirst : kIter, t == 1 ? b.lch : b.lpost, b, S, syn_iter, rule,
+                                         st);
+            mk.mark(2 * t, st);
+            hipLaunchKernelGGL((bit_kernel<M, V>), dim3(bit_blocks), dim3(256), 0, st, g->d_col_ptr, g->d_csc_to_csr,
+                               g->n, b.lch, static_cast<const MT *>(b.r), b.lpost, b.iters, b.fail, S, groups, t,
+                               int32_t(early_stop));
+            mk.mark(2 * t + 1, st);
+        }
+        if (cp.on && check == 0 && t >= kFirstCheck && t % kEvery == 0 && t + kLag + 2 <= T) {
+            const int32_t *it_now = level == 0 ? b.iters : cp.lv[level - 1].b.iters;
+            hipLaunchKernelGGL(running_list_kernel, dim3(1), dim3(1024), 0, st, it_now, Sl[level], nullptr, 0,
+                               cp.probe);
+            if (hipMemcpyAsync(cp.host_count, cp.probe, sizeof(int32_t), hipMemcpyDeviceToHost, st) == hipSuccess &&
+                hipEventRecord(ev, st) == hipSuccess) {
+                check = t;
+            } else {
+                (void)hipGetLastError();
+                cp.on = false;
+            }
+        }
+    }
+    // posteriors, iteration counts and fail marks back up the levels
+    for (int l = level; l > 0; l--) {
+        const CompactLevel &C = cp.lv[l - 1];
+        const Bufs &up = l == 1 ? b : cp.lv[l - 2].b;
+        hipLaunchKernelGGL(scatter_slots_kernel, dim3(2048), dim3(256), 0, st, C.b.lpost, Sl[l], up.lpost, Sl[l - 1],
+                           int64_t(g->n), C.b.iters, C.b.fail, up.iters, up.fail, C.map, C.count);
+    }
+    if (ev) {
+        // a count still in flight would land in the shared pinned word later
+        if (check > 0) (void)hipEventSynchronize(ev);
+        (void)hipEventDestroy(ev);
     }
     const int32_t nrows = g->class_begin[ldpc::kNumClasses];
     if (nrows > 0) {
@@ -821,6 +1079,7 @@ Bufs bufs_at(char *ws, const Plan &p) {
     b.aggd = reinterpret_cast<float *>(ws + p.off_aggd);
     b.aggpre = reinterpret_cast<float *>(ws + p.off_aggpre);
     b.aggbits = reinterpret_cast<int32_t *>(ws + p.off_aggbits);
+    b.base = ws;
     return b;
 }
 

@@ -123,6 +123,25 @@ def test_workspace_size_rules():
             ldpc.workspace_size(g, 8, bad)
     with pytest.raises(ldpc.LdpcError):
         ldpc.workspace_size(g, -1)
+    with pytest.raises(ldpc.LdpcError):
+        ldpc.workspace_size(g, 8, 1 << 8)               # no such flag
+
+
+def test_compact_tail_workspace():
+    """Tail compaction adds copies of the state for a half and a quarter of the
+    slots, from 256 slots up, and nothing without early stopping."""
+    code = li.tiny_code()
+    g = ldpc.Graph.from_code(code, host_only=True)
+    for msg, mb in ((0, 4), (ldpc.MSG_FP16, 2), (ldpc.MSG_Q8, 1)):
+        base = ldpc.workspace_size(g, 1000, msg)
+        comp = ldpc.workspace_size(g, 1000, msg | ldpc.COMPACT_TAIL)
+        # S = 1024 slots (4 per lane): copies of 512 and 256 slots
+        per_slot = 2 * code.n * 4 + code.nnz * mb + 3 * 4       # Lch, Lpost, messages; iters, fail, map
+        assert comp - base >= per_slot * 768
+        assert comp - base <= per_slot * 768 + 16 * 256
+        assert ldpc.workspace_size(g, 1000, msg | ldpc.COMPACT_TAIL | ldpc.NO_EARLY_STOP) == \
+            ldpc.workspace_size(g, 1000, msg | ldpc.NO_EARLY_STOP)
+    assert ldpc.workspace_size(g, 100, ldpc.COMPACT_TAIL) == ldpc.workspace_size(g, 100)   # 128 slots
 
 
 def test_decode_argument_checks_fail_before_device_work():

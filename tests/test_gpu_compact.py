@@ -1,0 +1,105 @@
+"""GPU tests of tail compaction (LDPC_COMPACT_TAIL): once few frames of a call
+still run, they move into a smaller slot range and finish there one slot per
+lane.  Only the schedule changes, so every output must be bit-identical to the
+same decode without the flag (which is itself held to the oracle)."""
+import numpy as np
+import pytest
+
+import ldpc_inputs as li
+from parity import compare, gpu_decode
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+
+
+def _same(a, b, what):
+    for k in ("bits", "ok", "iters", "lpost"):
+        assert (a[k] == b[k]).all(), f"{what}: {k} differs"
+
+
+def _mixed_code():
+    rng = np.random.default_rng(31)
+    cdeg = np.concatenate([[300, 140, 64, 40, 33], rng.integers(3, 33, size=95)])
+    E = int(cdeg.sum())
+    bdeg = np.full(700, E // 700)
+    bdeg[: E - bdeg.sum()] += 1
+    return li.socket_code(bdeg, cdeg, seed=32)
+
+
+@pytest.mark.parametrize("msg", ["fp32", "fp16", "q8"])
+@pytest.mark.parametrize("lane", [0, 2])
+def test_compact_tail_equals_plain(msg, lane):
+    from paper_1609_01567_amd import ldpc
+    flags = {"fp32": 0, "fp16": ldpc.MSG_FP16, "q8": ldpc.MSG_Q8}[msg]
+    flags |= {0: 0, 2: ldpc.LANE_SLOTS_2}[lane]
+    rule = "oms" if msg == "q8" else None
+    param = 0.5 if msg == "q8" else None
+    code = li.random_small_code(600, 300, 3, seed=8)
+    llr = li.awgn_llr(code.n, 1000, li.ebn0_to_sigma2(1.8, code.rate), seed=33)
+    print(f"[case] compact msg={msg} lane={lane} frames=1000", flush=True)
+    a = gpu_decode(code, llr, 40, flags=flags, rule=rule, param=param)
+    b = gpu_decode(code, llr, 40, flags=flags | ldpc.COMPACT_TAIL, rule=rule, param=param)
+    its = a["iters"]
+    assert (its > 24).sum() > 0 and (its < 12).sum() > 400     # a tail that compaction reaches
+    _same(a, b, f"{msg} lane {lane}")
+
+
+def test_compact_tail_every_check_class():
+    """Rows of every class (registers, chunks, more than 128 edges)."""
+    from paper_1609_01567_amd import ldpc
+    code = _mixed_code()
+    llr = li.awgn_llr(code.n, 600, 0.2, seed=34)
+    print("[case] compact mixed classes frames=600", flush=True)
+    a = gpu_decode(code, llr, 30)
+    b = gpu_decode(code, llr, 30, flags=ldpc.COMPACT_TAIL)
+    assert len(set(a["iters"].tolist())) > 5
+    _same(a, b, "mixed classes")
+
+
+def test_compact_tail_all_stop_early():
+    """Every frame stops early: the call skips the iterations with no work."""
+    from paper_1609_01567_amd import ldpc
+    code = li.random_small_code(600, 300, 3, seed=8)
+    llr = li.awgn_llr(code.n, 512, li.ebn0_to_sigma2(4.0, code.rate), seed=35)
+    print("[case] compact all-stop frames=512", flush=True)
+    a = gpu_decode(code, llr, 50)
+    b = gpu_decode(code, llr, 50, flags=ldpc.COMPACT_TAIL)
+    assert a["iters"].max() <= 10
+    _same(a, b, "all stop early")
+
+
+def test_compact_tail_large_code_and_oracle():
+    """The headline code at 256 frames (copy of 64 slots), then the oracle on
+    sampled frames of the compacted decode."""
+    from paper_1609_01567_amd import ldpc
+    code = li.large_code()
+    cw = li.Encoder(code).random_codewords(256, seed=3005)
+    llr = li.awgn_llr(code.n, 256, li.ebn0_to_sigma2(1.4, code.rate), seed=2042, codewords=cw)
+    print("[case] compact large n=64800 frames=256", flush=True)
+    a = gpu_decode(code, llr, 50)
+    b = gpu_decode(code, llr, 50, flags=ldpc.COMPACT_TAIL)
+    _same(a, b, "large code")
+    late = [int(f) for f in np.argsort(-b["iters"])[:3]]
+    print(compare(code, llr, 50, frames=late + [0], gpu=b))
+
+
+def test_compact_tail_profiled_entry_point():
+    """The profiled entry point takes the flag too and times every pass."""
+    import torch
+    from paper_1609_01567_amd import ldpc
+    code = li.random_small_code(600, 300, 3, seed=8)
+    llr = li.awgn_llr(code.n, 1000, li.ebn0_to_sigma2(1.8, code.rate), seed=33)
+    g = ldpc.Graph.from_code(code)
+    x = torch.from_numpy(llr).cuda()
+    ref = gpu_decode(code, llr, 40, graph=g)
+    res, tm = ldpc.decode_profiled(g, x, 40, flags=ldpc.COMPACT_TAIL)
+    torch.cuda.synchronize()
+    assert (res.iters.cpu().numpy() == ref["iters"]).all()
+    assert (res.bits.cpu().numpy() == ref["bits"]).all()
+    assert len(tm["check_ms"]) == 40 and (np.asarray(tm["check_ms"]) >= 0).all()

@@ -359,23 +359,26 @@ def bench_batched(torch, ldpc, steps, warmup, T=50):
     }
 
 
-def bench_simulate(torch, ldpc, code, points, frames=1024, calls=2, T=50, seed=2026):
+def bench_simulate(torch, ldpc, code, points, frames=1024, calls=2, T=50, seed=2026, compact=True):
     """Monte-Carlo error-rate runs on the device (ldpc_simulate): all-zero
     codeword, counter-based channel noise drawn on the GPU, decode, error
     counts; frames/s and info Gbit/s include the noise generation."""
     g = ldpc.Graph.from_code(code)
-    ws = ldpc.Workspace(ldpc.simulate_workspace_size(g, frames))
-    ldpc.simulate(g, frames, points[0], seed, T, workspace=ws)       # warm
+    flags = ldpc.COMPACT_TAIL if compact else 0
+    ws = ldpc.Workspace(ldpc.simulate_workspace_size(g, frames, flags))
+    ldpc.simulate(g, frames, points[0], seed, T, flags=flags, workspace=ws)       # warm
     torch.cuda.synchronize()
     out = {"workload": f"n={code.n} m={code.m}, all-zero codeword, device noise (Philox4x32-10 + Box-Muller), "
-                       f"{frames * calls} frames per Eb/N0 point, max {T} iterations, fp32 messages", "points": []}
+                       f"{frames * calls} frames per Eb/N0 point, max {T} iterations, fp32 messages",
+           "tail_compaction": compact, "points": []}
     k = code.n - code.m
     for i, eb in enumerate(points):
         counts = torch.zeros(len(ldpc.SIM_FIELDS), dtype=torch.int64, device="cuda")
         s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         s.record()
         for c in range(calls):
-            ldpc.simulate(g, frames, eb, seed + i, T, first_frame=c * frames, counts=counts, workspace=ws)
+            ldpc.simulate(g, frames, eb, seed + i, T, flags=flags, first_frame=c * frames, counts=counts,
+                          workspace=ws)
         e.record()
         torch.cuda.synchronize()
         ms = s.elapsed_time(e)
@@ -446,7 +449,7 @@ def bench_minsum(torch, ldpc, g, d_llr, cws, points, T, steps, rules=(("oms", 0.
     return out
 
 
-def bench_structured(torch, ldpc, li, points, F, T, steps):
+def bench_structured(torch, ldpc, li, points, F, T, steps, compact=True):
     """The headline workload on a quasi-cyclic stand-in: the same degree profile
     lifted by Z = 360 from a 90 x 180 base graph.  The generic decoder runs it
     unchanged; the circulant structure only changes which posterior lines
@@ -459,12 +462,13 @@ def bench_structured(torch, ldpc, li, points, F, T, steps):
             for i, eb in enumerate(points)]
     g = ldpc.Graph.from_code(code)
     d_llr = [torch.from_numpy(x).cuda() for x in llrs]
-    ws = ldpc.Workspace(ldpc.workspace_size(g, F, 0))
+    timed_flags = ldpc.COMPACT_TAIL if compact else 0
+    ws = ldpc.Workspace(ldpc.workspace_size(g, F, timed_flags))
     outs = [None] * len(points)
 
     def step():
         for i in range(len(points)):
-            outs[i] = ldpc.decode(g, d_llr[i], T, workspace=ws)
+            outs[i] = ldpc.decode(g, d_llr[i], T, flags=timed_flags, workspace=ws)
 
     step()
     torch.cuda.synchronize()
@@ -488,7 +492,7 @@ def bench_structured(torch, ldpc, li, points, F, T, steps):
     return {"workload": f"n={n} m={code.m} E={E} quasi-cyclic (Z=360, base 90x180, the headline degree profile), "
                         f"{F} random codewords at each Eb/N0 in {points} dB, max {T} iterations, fp32 messages",
             "ms_per_step": round(ms, 3), "gbits": round(len(points) * F * k / (ms * 1e-3) / 1e9, 4),
-            "fer": fer, "mean_iters": round(float(it.mean()), 2),
+            "tail_compaction": compact, "fer": fer, "mean_iters": round(float(it.mean()), 2),
             "check_avg_launch_ms": round(chk_ms / launches, 5),
             "check_achieved_gbs": round(achieved, 1), "check_frac": round(achieved / HBM_PEAK_GBS, 4)}
 
@@ -873,12 +877,12 @@ def main():
 
     simulate = None
     if not args.no_simulate:
-        simulate = bench_simulate(torch, ldpc, code, points)
+        simulate = bench_simulate(torch, ldpc, code, points, compact=not args.no_compact)
         print(f"[bench] simulate done", file=sys.stderr, flush=True)
 
     structured = None
     if not args.no_structured:
-        structured = bench_structured(torch, ldpc, li, points, F, T, max(1, args.steps))
+        structured = bench_structured(torch, ldpc, li, points, F, T, max(1, args.steps), compact=not args.no_compact)
         print(f"[bench] structured done", file=sys.stderr, flush=True)
 
     minsum = None

@@ -63,8 +63,8 @@ enum {
     LDPC_LANE_SLOTS_1 = 1u << 3,
     LDPC_LANE_SLOTS_2 = 1u << 4,
     LDPC_LANE_SLOTS_4 = 1u << 5,
-    /* Tail compaction (ldpc_decode / ldpc_decode_rule / ldpc_decode_profiled
-     * only; ignored with LDPC_NO_EARLY_STOP and below 256 frame slots).  Every
+    /* Tail compaction (the ldpc_decode and ldpc_simulate entry points; ignored
+     * with LDPC_NO_EARLY_STOP and below 256 frame slots).  Every
      * 4 iterations from iteration 8 the call counts the frames still running;
      * once they fit in half of the slots in use, it copies their state into a
      * smaller slot range (at most half, then at most a quarter of the slots)

@@ -700,7 +700,7 @@ Plan make_plan(const ldpc_graph *g, int32_t F, uint32_t flags, bool sim = false)
     }
     // Pools below 256 slots are left as they are (S is then a multiple of
     // 256, so both copies hold whole 64-slot groups).
-    if ((flags & LDPC_COMPACT_TAIL) && !(flags & LDPC_NO_EARLY_STOP) && !sim && p.S >= 256) {
+    if ((flags & LDPC_COMPACT_TAIL) && !(flags & LDPC_NO_EARLY_STOP) && p.S >= 256) {
         for (int l = 0; l < 2; l++) {
             Plan::Level &L = p.lv[l];
             L.Sc = p.S / (2 << l);
@@ -937,7 +937,7 @@ void run_decode(const ldpc_graph *g, const Plan &p, const Bufs &b, const float *
     // the running frames fit in half of the current slots (and in the next
     // copy), it moves them into that copy: S -> at most S/2 -> at most S/4.
     constexpr int32_t kFirstCheck = 8, kEvery = 4, kLag = 2;
-    Compact cp = compact_at(p, b, early_stop && !sim.on);
+    Compact cp = compact_at(p, b, early_stop);
     hipEvent_t ev = nullptr;
     if (cp.on && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();

@@ -74,10 +74,11 @@ def test_counts_equal_decode_of_the_same_llrs_and_oracle():
     assert (ora["iters"][clear] == out["iters"][:64][clear]).all()
 
 
-@pytest.mark.parametrize("flags_name", ["fp16", "no_early_stop"])
+@pytest.mark.parametrize("flags_name", ["fp16", "no_early_stop", "compact_tail"])
 def test_counts_equal_decode_under_flags(flags_name):
     from paper_1609_01567_amd import ldpc
-    flags = {"fp16": ldpc.MSG_FP16, "no_early_stop": ldpc.NO_EARLY_STOP}[flags_name]
+    flags = {"fp16": ldpc.MSG_FP16, "no_early_stop": ldpc.NO_EARLY_STOP,
+             "compact_tail": ldpc.COMPACT_TAIL}[flags_name]
     code = li.random_small_code(600, 300, 3, seed=8)
     print(f"[case] counts flags={flags_name}", flush=True)
     counts, llr = _run(code, 257, 1.4, seed=5, T=30, flags=flags)

@@ -698,8 +698,9 @@ Plan make_plan(const ldpc_graph *g, int32_t F, uint32_t flags, bool sim = false)
         p.off_it = off;  off = align256(off + S * 4);
         p.off_ok = off;  off = align256(off + S);
     }
-    // Pools below 256 slots are left as they are (S is then a multiple of
-    // 256, so both copies hold whole 64-slot groups).
+    // Pools below 256 slots are left as they are.  The copies' capacities
+    // (S/2, S/4) need not be multiples of 64: the slot count a compaction
+    // uses is the running count rounded up to 64, and it must fit.
     if ((flags & LDPC_COMPACT_TAIL) && !(flags & LDPC_NO_EARLY_STOP) && p.S >= 256) {
         for (int l = 0; l < 2; l++) {
             Plan::Level &L = p.lv[l];

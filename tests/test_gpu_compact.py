@@ -50,6 +50,18 @@ def test_compact_tail_equals_plain(msg, lane):
     _same(a, b, f"{msg} lane {lane}")
 
 
+def test_compact_tail_one_slot_per_lane_ragged_pool():
+    """One slot per lane and 300 frames: 320 slots, copies of 160 and 80."""
+    from paper_1609_01567_amd import ldpc
+    code = li.random_small_code(600, 300, 3, seed=8)
+    llr = li.awgn_llr(code.n, 300, li.ebn0_to_sigma2(1.8, code.rate), seed=36)
+    print("[case] compact lane=1 frames=300", flush=True)
+    a = gpu_decode(code, llr, 40, flags=ldpc.LANE_SLOTS_1)
+    b = gpu_decode(code, llr, 40, flags=ldpc.LANE_SLOTS_1 | ldpc.COMPACT_TAIL)
+    assert (a["iters"] > 20).sum() > 0
+    _same(a, b, "lane 1, 300 frames")
+
+
 def test_compact_tail_every_check_class():
     """Rows of every class (registers, chunks, more than 128 edges)."""
     from paper_1609_01567_amd import ldpc

@@ -861,7 +861,8 @@ int32_t *pinned_count_word() {
     static thread_local int32_t *word = nullptr;
     if (!word) {
         void *h = nullptr;
-        if (hipHostMalloc(&h, 256, hipHostMallocDefault) != hipSuccess) {
+        // portable: a thread may decode on several devices
+        if (hipHostMalloc(&h, 256, hipHostMallocPortable) != hipSuccess) {
             (void)hipGetLastError();
             return nullptr;
         }

@@ -170,8 +170,9 @@ LDPC_API ldpc_status ldpc_decode_workspace_size(const ldpc_graph *g, int32_t fra
  *               256-byte aligned; caller-owned; contents are scratch.
  *  hip_stream   hipStream_t to enqueue on (NULL = default stream).
  *
- * The call only enqueues work and returns; outputs are valid once the
- * stream has reached this point.  Inputs must not be modified and outputs
+ * The call only enqueues work and returns (with LDPC_COMPACT_TAIL it also
+ * waits for its periodic running-frame counts, see that flag); outputs are
+ * valid once the stream has reached this point.  Inputs must not be modified and outputs
  * must not be read before then.  Errors (returned synchronously; nothing is
  * enqueued): INVAL (bad sizes or pointers, workspace too small or unaligned,
  * graph built HOST_ONLY, wrong current device), DEVICE (launch failure).

@@ -332,3 +332,77 @@ def test_tie_risk_flags():
     assert z["tie_risk"][0] == 1
     big = oracle.decode(code, np.full((1, code.n), 9.0, np.float32), 5)
     assert big["tie_risk"][0] == 0 and big["iters"][0] == 1
+
+
+# ------------------------------------------- stop rule against GF(2) syndromes
+
+def _per_iteration_runs(code, llr, tmax):
+    """Early stop off, one run per T = 1..tmax: bits [T][F][n], ok [T][F], lpost [T][F][n]."""
+    bits, ok, lpost = [], [], []
+    for T in range(1, tmax + 1):
+        r = oracle.decode(code, llr, max_iter=T, early_stop=False)
+        bits.append(r["bits"])
+        ok.append(r["ok"])
+        lpost.append(r["lpost"])
+    return np.array(bits), np.array(ok), np.array(lpost)
+
+
+@pytest.mark.parametrize("case", ["tiny-1.2dB", "small-0.5dB", "small-1.5dB"])
+def test_stop_rule_matches_gf2_syndrome_of_each_iteration(case):
+    """Algorithm 2 returns the first estimate whose syndrome (Algorithm 7) is zero.
+
+    The syndromes here come from ldpc_inputs.Code.syndrome (H c^T over GF(2)
+    with numpy), not from the oracle.  For every frame: the early-stop decode
+    reports iters = the first T whose estimate has a zero syndrome and ok = 1,
+    with that iteration's estimate and posterior; a frame with no such T up to
+    max_iter reports iters = max_iter, ok = 0 and the estimate of max_iter.
+    With early stop off, ok is the syndrome test of the last estimate.
+    """
+    if case == "tiny-1.2dB":
+        code, tmax = li.tiny_code(), 20
+        llr = li.awgn_llr(code.n, 24, li.ebn0_to_sigma2(1.2, code.rate), seed=515)
+    elif case == "small-0.5dB":
+        code, tmax = li.random_small_code(300, 150, 3, seed=31), 16
+        llr = li.awgn_llr(code.n, 24, li.ebn0_to_sigma2(0.5, code.rate), seed=516)
+    else:
+        code, tmax = li.random_small_code(300, 150, 3, seed=31), 16
+        llr = li.awgn_llr(code.n, 24, li.ebn0_to_sigma2(1.5, code.rate), seed=517)
+    bits, ok_off, lpost = _per_iteration_runs(code, llr, tmax)
+    F = llr.shape[0]
+    zero = np.array([~code.syndrome(bits[t]).any(axis=1) for t in range(tmax)])   # [T][F]
+    # the estimate is the sign of the posterior (tie -> 0), and ok of a run
+    # without early stop is the GF(2) syndrome test of its last estimate
+    assert (bits == (lpost < 0)).all()
+    assert (ok_off == zero).all()
+    es = oracle.decode(code, llr, max_iter=tmax, early_stop=True)
+    first = np.where(zero.any(axis=0), zero.argmax(axis=0) + 1, 0)                 # 0: never
+    for f in range(F):
+        if first[f]:
+            t = int(first[f])
+            assert es["iters"][f] == t and es["ok"][f] == 1, (f, t, es["iters"][f], es["ok"][f])
+        else:
+            t = tmax
+            assert es["iters"][f] == tmax and es["ok"][f] == 0, (f, es["iters"][f], es["ok"][f])
+        assert (es["bits"][f] == bits[t - 1, f]).all()
+        assert (es["lpost"][f] == lpost[t - 1, f]).all()
+    # the sample exercises every branch: stops after iteration 1, stops later,
+    # never stops (the low-SNR case), and estimates that fail before passing
+    if case == "small-0.5dB":
+        assert (first == 0).sum() >= 5
+    else:
+        assert (first > 1).sum() >= 5
+    assert ((first > 1) & ~zero[0]).any() or (first == 0).any()
+
+
+def test_stop_rule_noisy_frame_fails_then_passes():
+    """A frame whose channel decision is not a codeword must not stop at
+    iteration 1, and a frame that reaches a codeword must stop there, not run on."""
+    code = li.tiny_code()
+    llr = li.awgn_llr(code.n, 32, li.ebn0_to_sigma2(2.0, code.rate), seed=2001)
+    chan = (llr < 0).astype(np.uint8)
+    assert code.syndrome(chan).any(axis=1).all()          # every channel decision is a non-codeword
+    es = oracle.decode(code, llr, max_iter=50)
+    r1 = oracle.decode(code, llr, max_iter=1, early_stop=False)
+    fail1 = code.syndrome(r1["bits"]).any(axis=1)
+    assert (es["iters"][fail1] > 1).all()
+    assert (es["ok"] == ~code.syndrome(es["bits"]).any(axis=1)).all()

@@ -68,7 +68,10 @@ def parse():
     ap.add_argument("--msg", choices=["fp32", "fp16", "bf16"], default="fp32")
     ap.add_argument("--lane-slots", type=int, choices=[0, 1, 2, 4], default=0,
                     help="frame slots per wavefront lane (0: library default)")
-    ap.add_argument("--cpu-frames", type=int, default=16, help="oracle sample: frames per Eb/N0 point")
+    ap.add_argument("--cpu-frames", type=int, default=64,
+                    help="oracle sample on all host threads: frames per Eb/N0 point")
+    ap.add_argument("--cpu-frames-1core", type=int, default=4,
+                    help="oracle sample on one thread: frames per Eb/N0 point")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--engine-slots", type=str, default="256,512",
@@ -186,27 +189,49 @@ def algorithmic_bytes(iters: np.ndarray, T: int, E: int, n: int, msg_bytes: int)
     return check, bit
 
 
-def cpu_baseline(code, llrs, T, frames_per_point):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(code, llrs, T, frames_per_point, frames_per_point_1core):
+    """The FP64 oracle on the host cores, on a bounded sample of the same frames:
+    every thread this process may use, and one thread (the paper's serial CPU
+    program is the other point of its Table III comparison)."""
     import oracle
     threads = os.cpu_count() or 1
     try:
         threads = len(os.sched_getaffinity(0))
     except AttributeError:
         pass
-    sample = [x[:frames_per_point] for x in llrs]
-    oracle.decode(code, sample[0][:1], 2, threads=threads, want_lpost=False)   # load/warm
-    t0 = time.perf_counter()
-    iters = []
-    for x in sample:
-        r = oracle.decode(code, x, T, threads=threads, want_lpost=False)
-        iters.append(r["iters"])
-    dt = time.perf_counter() - t0
     k = code.n - code.m
-    nf = sum(x.shape[0] for x in sample)
-    return {"value": nf * k / dt / 1e9, "unit": "Gbit/s", "cores": threads, "kind": "oracle",
+    oracle.decode(code, llrs[0][:1], 2, threads=threads, want_lpost=False)   # load/warm
+
+    def run(fpp, nthreads):
+        sample = [x[:fpp] for x in llrs]
+        t0 = time.perf_counter()
+        iters = [oracle.decode(code, x, T, threads=nthreads, want_lpost=False)["iters"] for x in sample]
+        dt = time.perf_counter() - t0
+        nf = sum(x.shape[0] for x in sample)
+        return nf * k / dt / 1e9, nf, float(np.concatenate(iters).mean()), dt
+
+    v, nf, mi, dt = run(frames_per_point, threads)
+    v1, nf1, mi1, dt1 = run(frames_per_point_1core, 1)
+    model = cpu_model()
+    return {"value": v, "unit": "Gbit/s", "cores": threads, "kind": "oracle",
             "sample": f"{frames_per_point} frames at each of {len(llrs)} Eb/N0 points of the same workload "
-                      f"({nf} frames, {float(np.concatenate(iters).mean()):.1f} mean iterations), FP64 C oracle, "
-                      f"{dt:.1f} s wall"}
+                      f"({nf} frames, {mi:.1f} mean iterations), FP64 C oracle (gcc -O2, OpenMP over frames), "
+                      f"{dt:.1f} s wall on {threads} threads",
+            "cpu_model": model,
+            "single_core": {"value": v1, "unit": "Gbit/s", "cores": 1,
+                            "sample": f"{frames_per_point_1core} frames at each point ({nf1} frames, {mi1:.1f} mean "
+                                      f"iterations), {dt1:.1f} s wall on one thread"}}
 
 
 def engine_large(torch, ldpc, g, d_llr, T, flags, slots, steps, warmup, graph_steps=8):
@@ -758,18 +783,19 @@ def main():
     flags |= {0: 0, 1: ldpc.LANE_SLOTS_1, 2: ldpc.LANE_SLOTS_2, 4: ldpc.LANE_SLOTS_4}[args.lane_slots]
     msg_bytes = 4 if args.msg == "fp32" else 2
     points = [float(x) for x in args.ebn0.split(",")]
-    code = li.large_code()
+    code, cws, llrs = li.headline_workload(args.frames, points)
     n, m, E, F, T = code.n, code.m, code.nnz, args.frames, args.max_iter
     k = n - m
-    enc = li.Encoder(code)
-    cws = [enc.random_codewords(F, seed=3002 + i) for i in range(len(points))]
-    llrs = [li.awgn_llr(n, F, li.ebn0_to_sigma2(eb, code.rate), seed=2002 + 10 * i, codewords=cws[i])
-            for i, eb in enumerate(points)]
     g = ldpc.Graph.from_code(code)
     d_llr = [torch.from_numpy(x).cuda() for x in llrs]
     # the timed decodes compact their tails; the profiled pass below times the
     # full-width kernels without it
-    timed_flags = flags | (0 if args.no_compact else ldpc.COMPACT_TAIL)
+    from paper_1609_01567_amd import workloads
+    # the decode configuration of the timed step (and of the full-size parity
+    # tests): one call of F frames per point with the headline flags
+    timed_flags = flags | (0 if args.no_compact else workloads.headline_flags())
+    if F > workloads.HEADLINE_FRAMES_PER_CALL:
+        raise SystemExit(f"--frames above {workloads.HEADLINE_FRAMES_PER_CALL} per call is not the timed configuration")
     ws = ldpc.Workspace(ldpc.workspace_size(g, F, timed_flags))
     outs = [ldpc.DecodeResult(bits=torch.empty((F, n), dtype=torch.uint8, device="cuda"),
                               ok=torch.empty(F, dtype=torch.uint8, device="cuda"),
@@ -898,7 +924,7 @@ def main():
     ceiling = copy_ceiling(torch)
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(code, llrs, T, args.cpu_frames)
+        cpu = cpu_baseline(code, llrs, T, args.cpu_frames, args.cpu_frames_1core)
         print(f"[bench] cpu baseline done", file=sys.stderr, flush=True)
 
     line = {

@@ -27,7 +27,7 @@ __all__ = [
     "Code", "socket_code", "ebn0_to_sigma2", "awgn_llr", "code_14_7",
     "tiny_code", "large_code", "extreme_code", "batch_codes", "BATCH_SPECS",
     "tree_code", "spc_code", "path_code", "random_small_code", "sim_channel_llr",
-    "lifted_code", "large_qc_code",
+    "lifted_code", "large_qc_code", "headline_workload", "HEADLINE_POINTS_DB",
 ]
 
 
@@ -406,3 +406,23 @@ class Encoder:
                 self._h = _ct.c_void_p()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# the rate-1/2 n = 64800 workload (random codewords at four Eb/N0 points)
+# ---------------------------------------------------------------------------
+
+HEADLINE_POINTS_DB = (0.8, 1.0, 1.2, 1.4)
+
+
+def headline_workload(frames: int = 256, points=HEADLINE_POINTS_DB):
+    """(code, codewords, llrs): the large rate-1/2 code, `frames` random
+    codewords per Eb/N0 point (information seed 3002 + i through the systematic
+    GF(2) encoder) and their channel LLRs (noise seed 2002 + 10 i), one
+    [frames][n] float32 array per point."""
+    code = large_code()
+    enc = Encoder(code)
+    cws = [enc.random_codewords(frames, seed=3002 + i) for i in range(len(points))]
+    llrs = [awgn_llr(code.n, frames, ebn0_to_sigma2(eb, code.rate), seed=2002 + 10 * i, codewords=cws[i])
+            for i, eb in enumerate(points)]
+    return code, cws, llrs

@@ -25,27 +25,32 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ldpc_oracle.c")
 _SO = os.path.join(_HERE, "liboracle.so")
+# the same source built with FP32 arithmetic: a diagnostic of how two
+# precisions of the algorithm drift apart (see decode(fp32_build=True))
+_SO_F32 = os.path.join(_HERE, "liboracle_f32.so")
 LMAX = 64.0
 # check rules: name -> (code, default parameter); "ms" is the normalized rule with alpha = 1
 RULES = {"sp": (0, 0.0), "nms": (1, 0.75), "oms": (2, 0.25), "ms": (1, 1.0)}
-_lib = None
+_libs = {}
 
 
 def build() -> str:
-    """Compile the oracle with gcc (OpenMP over frames, strict IEEE arithmetic)."""
-    tmp = _SO + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-                           "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"])
-    os.replace(tmp, _SO)
+    """Compile the oracle with gcc (OpenMP over frames, strict IEEE arithmetic),
+    plus its FP32 build (the same steps in float; a diagnostic only)."""
+    for so, real in ((_SO, "double"), (_SO_F32, "float")):
+        tmp = so + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-Wall", "-Wextra", f"-DORACLE_REAL={real}", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, so)
     return _SO
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_SO):
+def _load(fp32_build: bool = False):
+    so = _SO_F32 if fp32_build else _SO
+    if so not in _libs:
+        if not os.path.exists(so):
             build()
-        lib = ctypes.CDLL(_SO)
+        lib = ctypes.CDLL(so)
         P = ctypes.c_void_p
         lib.ldpc_oracle_decode.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long, P, P, P,
                                            ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
@@ -58,8 +63,8 @@ def _load():
         lib.ldpc_oracle_decode_rule.restype = ctypes.c_int
         lib.ldpc_oracle_adjacency.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_long, P, P, P, P, P, P]
         lib.ldpc_oracle_adjacency.restype = ctypes.c_int
-        _lib = lib
-    return _lib
+        _libs[so] = lib
+    return _libs[so]
 
 
 def _ptr(a):
@@ -68,7 +73,7 @@ def _ptr(a):
 
 def decode(code, llr, max_iter: int, early_stop: bool = True, lmax: float = LMAX,
            threads: int = 0, want_lpost: bool = True, tie_margin: float = 1e-3, rule: str = "sp",
-           param: float | None = None) -> dict:
+           param: float | None = None, fp32_build: bool = False) -> dict:
     """Decode every row of `llr` ([F][n] float32) on the CPU in FP64.
 
     rule: "sp" (sum-product, the paper's decoder), "ms" (Min-Sum), "nms"
@@ -78,8 +83,11 @@ def decode(code, llr, max_iter: int, early_stop: bool = True, lmax: float = LMAX
     min_abs [F] f64 (smallest |Lpost| over all iterations run), tie_risk [F]
     u8 (1 if flipping the sign of bits with |Lpost| < tie_margin could change
     bits, ok or iters) and, if asked, lpost [F][n] f64.
+
+    fp32_build: run the same algorithm compiled with FP32 arithmetic instead
+    (a diagnostic of precision drift, never a reference).
     """
-    lib = _load()
+    lib = _load(fp32_build)
     rows = np.ascontiguousarray(code.rows, dtype=np.int32)
     cols = np.ascontiguousarray(code.cols, dtype=np.int32)
     llr = np.ascontiguousarray(np.atleast_2d(llr), dtype=np.float32)

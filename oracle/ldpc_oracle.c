@@ -47,13 +47,23 @@
  * with the same sign product and the same clamp; an empty set gives m = inf,
  * so a degree-1 check sends +lmax under every rule.
  */
-#include <math.h>
 #include <stdint.h>
+#include <tgmath.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
+
+/* The arithmetic type.  The oracle is FP64; ORACLE_REAL=float builds the same
+ * steps in FP32 (tgmath.h picks the float forms of log1p, expm1 and fabs).
+ * That build is a diagnostic for the tests only: it shows how far two
+ * precisions of this very algorithm drift apart on frames that never
+ * converge, and it is never a reference. */
+#ifndef ORACLE_REAL
+#define ORACLE_REAL double
+#endif
+typedef ORACLE_REAL real;
 
 #define ORACLE_OK 0
 #define RULE_SUM_PRODUCT 0
@@ -104,19 +114,19 @@ static int graph_build(graph_t *g, int m, int n, long E, const int *row, const i
 }
 
 /* phi(x) = ln((e^x+1)/(e^x-1)) = log1p(2/expm1(x)) for x >= 0; phi(0) = +inf, phi(+inf) = 0. */
-static double phi(double x) {
-    if (x == 0.0) return INFINITY;
-    return log1p(2.0 / expm1(x));
+static real phi(real x) {
+    if (x == (real)0) return (real)INFINITY;
+    return log1p((real)2 / expm1(x));
 }
 
-static double clamp(double x, double lim) {
+static real clamp(real x, real lim) {
     return x > lim ? lim : (x < -lim ? -lim : x);
 }
 
 /* Decode one frame.  Work buffers: R, Q, P (per edge), lpost (per bit), chat (per bit). */
-static void decode_frame(const graph_t *g, const float *llr, int max_iter, int early_stop, double lmax,
-                         double tie_margin, int rule, double rule_param, double *R, double *Q, double *P,
-                         double *lpost, uint8_t *chat, uint8_t *ok_out, int *iters_out, double *min_abs_out,
+static void decode_frame(const graph_t *g, const float *llr, int max_iter, int early_stop, real lmax,
+                         double tie_margin, int rule, real rule_param, real *R, real *Q, real *P,
+                         real *lpost, uint8_t *chat, uint8_t *ok_out, int *iters_out, double *min_abs_out,
                          uint8_t *tie_risk_out) {
     const int m = g->m, n = g->n;
     const long E = g->E;
@@ -126,7 +136,7 @@ static void decode_frame(const graph_t *g, const float *llr, int max_iter, int e
     /* Algorithm 3: before any check update the bit->check messages are the
        channel values, which is the bit rule with every r at its neutral value
        (R = 0 in LLR form). */
-    for (long e = 0; e < E; e++) R[e] = 0.0;
+    for (long e = 0; e < E; e++) R[e] = (real)0;
 
     for (t = 1; t <= max_iter; t++) {
         /* Algorithm 1, "Values to Check Nodes": Q[j->i] = L_j + sum over the
@@ -134,7 +144,7 @@ static void decode_frame(const graph_t *g, const float *llr, int max_iter, int e
         for (int j = 0; j < n; j++) {
             for (int a = g->bit_start[j]; a < g->bit_start[j + 1]; a++) {
                 const int e = g->bit_edge[a];
-                double s = (double)llr[j];
+                real s = (real)llr[j];
                 for (int b = g->bit_start[j]; b < g->bit_start[j + 1]; b++) {
                     if (b == a) continue;              /* skip the destination check */
                     s += R[g->bit_edge[b]];
@@ -148,20 +158,20 @@ static void decode_frame(const graph_t *g, const float *llr, int max_iter, int e
             for (int i = 0; i < m; i++) {
                 for (int a = g->chk_start[i]; a < g->chk_start[i + 1]; a++) {
                     const int e = g->chk_edge[a];
-                    double mn = INFINITY;
+                    real mn = (real)INFINITY;
                     int negative = 0;
                     for (int b = g->chk_start[i]; b < g->chk_start[i + 1]; b++) {
                         if (b == a) continue;          /* skip the destination bit */
                         const int e2 = g->chk_edge[b];
                         if (fabs(Q[e2]) < mn) mn = fabs(Q[e2]);
-                        negative ^= (Q[e2] < 0.0);
+                        negative ^= (Q[e2] < (real)0);
                     }
-                    double mag;
+                    real mag;
                     if (rule == RULE_MIN_SUM_NORMALIZED) {
                         mag = rule_param * mn;
                     } else {
                         mag = mn - rule_param;
-                        if (mag < 0.0) mag = 0.0;
+                        if (mag < (real)0) mag = (real)0;
                     }
                     R[e] = clamp(negative ? -mag : mag, lmax);
                 }
@@ -175,15 +185,15 @@ static void decode_frame(const graph_t *g, const float *llr, int max_iter, int e
         for (int i = 0; i < m; i++) {
             for (int a = g->chk_start[i]; a < g->chk_start[i + 1]; a++) {
                 const int e = g->chk_edge[a];
-                double s = 0.0;
+                real s = (real)0;
                 int negative = 0;
                 for (int b = g->chk_start[i]; b < g->chk_start[i + 1]; b++) {
                     if (b == a) continue;              /* skip the destination bit */
                     const int e2 = g->chk_edge[b];
                     s += P[e2];
-                    negative ^= (Q[e2] < 0.0);
+                    negative ^= (Q[e2] < (real)0);
                 }
-                const double mag = phi(s);             /* phi(0) = inf for an empty product */
+                const real mag = phi(s);             /* phi(0) = inf for an empty product */
                 R[e] = clamp(negative ? -mag : mag, lmax);
             }
         }
@@ -193,12 +203,12 @@ static void decode_frame(const graph_t *g, const float *llr, int max_iter, int e
         long near_degree = 0;                          /* diagnostics only, see below */
         int near = 0;
         for (int j = 0; j < n; j++) {
-            double s = (double)llr[j];
+            real s = (real)llr[j];
             for (int a = g->bit_start[j]; a < g->bit_start[j + 1]; a++) s += R[g->bit_edge[a]];
             lpost[j] = s;
-            chat[j] = (uint8_t)(s < 0.0);              /* Algorithm 6: 1 only if Q1 > Q0 */
-            if (fabs(s) < min_abs) min_abs = fabs(s);
-            if (fabs(s) < tie_margin) { near = 1; near_degree += g->bit_start[j + 1] - g->bit_start[j]; }
+            chat[j] = (uint8_t)(s < (real)0);              /* Algorithm 6: 1 only if Q1 > Q0 */
+            if (fabs((double)s) < min_abs) min_abs = fabs((double)s);
+            if (fabs((double)s) < tie_margin) { near = 1; near_degree += g->bit_start[j + 1] - g->bit_start[j]; }
         }
 
         /* Algorithm 7: z = c H^T; the estimate is a codeword iff z = 0. */
@@ -254,8 +264,8 @@ int ldpc_oracle_decode_rule(int m, int n, long nnz, const int *rows, const int *
 #pragma omp parallel
     {
         const size_t Eb = (size_t)(nnz > 0 ? nnz : 1);
-        double *R = malloc(sizeof(double) * Eb), *Q = malloc(sizeof(double) * Eb), *P = malloc(sizeof(double) * Eb);
-        double *lp = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+        real *R = malloc(sizeof(real) * Eb), *Q = malloc(sizeof(real) * Eb), *P = malloc(sizeof(real) * Eb);
+        real *lp = malloc(sizeof(real) * (size_t)(n > 0 ? n : 1));
         uint8_t *ch = malloc((size_t)(n > 0 ? n : 1));
         if (!R || !Q || !P || !lp || !ch) {
 #pragma omp atomic write
@@ -265,11 +275,12 @@ int ldpc_oracle_decode_rule(int m, int n, long nnz, const int *rows, const int *
             for (int f = 0; f < frames; f++) {
                 double mn;
                 uint8_t risk;
-                decode_frame(&g, llr + (size_t)f * n, max_iter, early_stop, lmax, tie_margin, rule, rule_param, R,
-                             Q, P, lp, ch, &ok_out[f], &iters_out[f], &mn, &risk);
+                decode_frame(&g, llr + (size_t)f * n, max_iter, early_stop, (real)lmax, tie_margin, rule,
+                             (real)rule_param, R, Q, P, lp, ch, &ok_out[f], &iters_out[f], &mn, &risk);
                 if (min_abs_out) min_abs_out[f] = mn;
                 if (tie_risk_out) tie_risk_out[f] = risk;
-                if (lpost_out) memcpy(lpost_out + (size_t)f * n, lp, sizeof(double) * (size_t)n);
+                if (lpost_out)
+                    for (int j = 0; j < n; j++) lpost_out[(size_t)f * n + j] = (double)lp[j];
                 memcpy(bits_out + (size_t)f * n, ch, (size_t)n);
             }
         }

@@ -1085,6 +1085,24 @@ Bufs bufs_at(char *ws, const Plan &p) {
     return b;
 }
 
+// Tail compaction waits on the host for its periodic counts, which a stream
+// under graph capture cannot do: such a call is refused before anything is
+// enqueued.
+bool capture_blocks_compaction(hipStream_t st, uint32_t flags, const std::string &f) {
+    if (!(flags & LDPC_COMPACT_TAIL)) return false;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error(f + ": cannot query the stream's capture state");
+        return true;
+    }
+    if (cs != hipStreamCaptureStatusNone) {
+        set_error(f + ": LDPC_COMPACT_TAIL waits on the host and cannot run on a capturing stream");
+        return true;
+    }
+    return false;
+}
+
 ldpc_status decode_core(const char *fn, const ldpc_graph *g, const float *llr_in, int32_t frames, int32_t max_iter,
                         uint32_t flags, const ldpc_rule *rule_in, uint8_t *bits_out, uint8_t *syndrome_ok,
                         int32_t *iters, float *llr_out, void *workspace, size_t workspace_bytes, void *hip_stream,
@@ -1121,6 +1139,7 @@ ldpc_status decode_core(const char *fn, const ldpc_graph *g, const float *llr_in
     }
     const Bufs b = bufs_at(static_cast<char *>(workspace), p);
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (capture_blocks_compaction(st, flags, f)) return LDPC_E_INVAL;
     const bool es = !(flags & LDPC_NO_EARLY_STOP);
     (void)hipGetLastError();
     switch (p.msg) {
@@ -1275,6 +1294,7 @@ ldpc_status simulate_core(const char *fn, const ldpc_graph *g, int32_t frames, d
     sim.ok = reinterpret_cast<uint8_t *>(ws + p.off_ok);
     sim.counts = counts;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (capture_blocks_compaction(st, flags, f)) return LDPC_E_INVAL;
     const bool es = !(flags & LDPC_NO_EARLY_STOP);
     (void)hipGetLastError();
     switch (p.msg) {

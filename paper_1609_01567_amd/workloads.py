@@ -94,5 +94,36 @@ def batched_mix(frames_total=4096, seed_base=0):
     return out
 
 
+# ---------------------------------------------------------------------------
+# the rate-1/2 n = 64800 throughput workload, decoded as the benchmark times it
+# ---------------------------------------------------------------------------
+
+HEADLINE_FRAMES_PER_CALL = 256     # one ldpc_decode per Eb/N0 point
+
+
+def headline_flags(early_stop: bool = True) -> int:
+    from . import ldpc
+    return ldpc.COMPACT_TAIL if early_stop else ldpc.NO_EARLY_STOP
+
+
+def headline_decode(graph, d_llrs, max_iter: int, want_llr: bool = False, early_stop: bool = True,
+                    workspace=None, outs=None, stream=None):
+    """Enqueue the decode of each point's frames ([F][n] float32 device tensors
+    in `d_llrs`) the way the benchmark times them: calls of
+    HEADLINE_FRAMES_PER_CALL frames, headline_flags(), the default lane width,
+    one workspace shared by the calls.  Returns one DecodeResult per point."""
+    from . import ldpc
+    flags = headline_flags(early_stop)
+    if workspace is None:
+        workspace = ldpc.Workspace(ldpc.workspace_size(graph, HEADLINE_FRAMES_PER_CALL, flags))
+    res = []
+    for i, x in enumerate(d_llrs):
+        if x.shape[0] > HEADLINE_FRAMES_PER_CALL:
+            raise ValueError("more frames than one headline call holds")
+        res.append(ldpc.decode(graph, x, max_iter, flags=flags, want_llr=want_llr, workspace=workspace,
+                               stream=stream, out=None if outs is None else outs[i]))
+    return res
+
+
 if __name__ == "__main__":
     calibrate()

@@ -12,11 +12,14 @@ Parity bar (from the decoder's contract):
     are counted and their mismatches reported;
   * posterior LLRs agree to |L_gpu - L_oracle| <= 1e-3 + 1e-4 |L_oracle| on
     those frames when the oracle decodes them to a codeword, and on every
-    frame in the fixed-iteration checks (posterior_all=True).  A frame that
-    never converges keeps oscillating until max_iter, and any two precisions
-    drift apart on it (an FP32 build of the oracle's own arithmetic drifts
-    ~1.5e-3 from FP64 after 30 such iterations): its drift is reported in the
-    stats, its bits, flag and iteration count are still held bit-exact.
+    frame in the fixed-iteration checks (posterior_all=True).
+  * a frame that never converges keeps oscillating until max_iter, and any
+    two precisions drift apart on it, more with every iteration: the oracle's
+    own source built with FP32 arithmetic exceeds the bar on such frames by
+    orders of magnitude at 80 iterations (a CPU pin in test_oracle_pins.py).
+    On those frames the GPU posterior must stay within the bar plus
+    DRIFT_FACTOR times the drift of that FP32 build from FP64 (frame maximum);
+    bits, flag and iteration count are still held bit-exact.
 """
 from __future__ import annotations
 
@@ -27,6 +30,13 @@ import oracle
 ATOL = 1e-3
 RTOL = 1e-4
 TIE_MARGIN = 1e-3
+# GPU drift allowed on non-converging frames, as a multiple of the drift of an
+# FP32 build of the oracle's own arithmetic: the GPU rounds the same algorithm
+# in FP32 but through the hardware exp2/log2/reciprocal (about 1 ulp each) and
+# a different exact form of the check rule, so its rounding noise per
+# iteration is a small multiple of that build's; the iterations amplify both
+# the same way.
+DRIFT_FACTOR = 8.0
 
 
 def gpu_decode(code, llr: np.ndarray, max_iter: int, flags: int = 0, graph=None, rule=None, param=None):
@@ -68,8 +78,27 @@ def compare(code, llr, max_iter: int, early_stop: bool = True, flags: int = 0, f
     within = (err <= atol + rtol * np.abs(ora["lpost"])).all(axis=1)
     conv = ora["ok"] == 1
     post = clear & (conv | posterior_all)
+    if not early_stop and posterior_all:
+        # Without early stop no decision feeds back into the decode, so ties
+        # cannot change the posterior: it is held on every frame, and every
+        # hard decision is held except those of bits within the tie margin.
+        post = np.ones_like(clear)
+        sure = np.abs(ora["lpost"]) >= margin
+        same_bits = ((g["bits"] == ora["bits"]) | ~sure).all(axis=1)
+        same_ok = same_ok | ~clear
+        clear = np.ones_like(clear)
     bad = (clear & ~(same_bits & same_iter & same_ok)) | (post & ~within)
     drift = clear & ~post
+    drift_ratio = np.zeros(0)
+    if drift.any():
+        sel = np.flatnonzero(drift)
+        o32 = oracle.decode(code, llr[idx][sel], max_iter, early_stop=early_stop, tie_margin=margin,
+                            rule=rule or "sp", param=param, fp32_build=True)
+        d32 = np.abs(o32["lpost"] - ora["lpost"][sel]).max(axis=1)
+        excess = (err[sel] - (atol + rtol * np.abs(ora["lpost"][sel]))).max(axis=1)
+        drift_ratio = np.where(excess > 0, excess / np.maximum(d32, 1e-30), 0.0)
+        over = excess > DRIFT_FACTOR * d32
+        bad[sel[over]] = True
     stats = dict(frames=int(idx.size), clear=int(clear.sum()), near_tie=int((~clear).sum()),
                  clear_by_min_abs=int((ora["min_abs"] >= margin).sum()),
                  mismatched_near_tie=int((~clear & ~(same_bits & same_iter & same_ok)).sum()),
@@ -77,7 +106,8 @@ def compare(code, llr, max_iter: int, early_stop: bool = True, flags: int = 0, f
                  max_err=float(err[post].max()) if post.any() else 0.0,
                  max_rel=float((err / (1.0 + np.abs(ora["lpost"])))[post].max()) if post.any() else 0.0,
                  nonconverged_clear=int(drift.sum()),
-                 nonconverged_max_err=float(err[drift].max()) if drift.any() else 0.0)
+                 nonconverged_max_err=float(err[drift].max()) if drift.any() else 0.0,
+                 nonconverged_max_excess_over_fp32_drift=float(drift_ratio.max()) if drift_ratio.size else 0.0)
     if bad.any():
         f = int(np.flatnonzero(bad)[0])
         raise AssertionError(

@@ -204,6 +204,29 @@ LDPC_API ldpc_status ldpc_decode_profiled(const ldpc_graph *g, const float *llr_
                                           void *hip_stream, float *check_ms, float *bit_ms,
                                           float *edge_ms);
 
+/*
+ * For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): ldpc_decode without a
+ * workspace argument.  The decode state lives in one file-scope device array
+ * of LDPC_NOALLOC_SCRATCH_BYTES per device, which the library holds from its
+ * first use on that device until the process ends; the call itself allocates
+ * nothing.  Arguments, results and errors are those of ldpc_decode, except:
+ *  - frames whose state (ldpc_decode_workspace_size with the same flags)
+ *    exceeds LDPC_NOALLOC_SCRATCH_BYTES are refused with RANGE;
+ *  - LDPC_COMPACT_TAIL is refused with INVAL (it keeps host memory of its own);
+ *  - DEVICE if the array's device address cannot be looked up.
+ * Every call on one device uses the same array, which keeps the last call's
+ * contents; a call writes every part of it before reading it, so nothing
+ * needs clearing.  Calls that overlap on one device (several streams or host
+ * threads) race and give undefined results: serialize them, e.g. on one
+ * stream.
+ */
+#define LDPC_NOALLOC_SCRATCH_BYTES (128u << 20)
+LDPC_API ldpc_status ldpc_decode_noalloc(const ldpc_graph *g, const float *llr_in, int32_t frames,
+                                         int32_t max_iter, uint32_t flags,
+                                         uint8_t *bits_out, uint8_t *syndrome_ok, int32_t *iters,
+                                         float *llr_out, void *hip_stream);
+
 /* ------------------------------------------------------------------------
  * Check-node rules.
  *

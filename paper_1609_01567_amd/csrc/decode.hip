@@ -34,6 +34,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1339,4 +1340,77 @@ extern "C" ldpc_status ldpc_simulate_rule(const ldpc_graph *g, int32_t frames, d
                                           void *workspace, size_t workspace_bytes, void *hip_stream) {
     return simulate_core("ldpc_simulate_rule", g, frames, ebn0_db, seed, first_frame, max_iter, flags, rule, counts,
                          llr_out, workspace, workspace_bytes, hip_stream);
+}
+
+// ---------------------------------------------------------------------------
+// Decoding without allocation (ldpc_decode_noalloc): the workspace of
+// ldpc_decode is this file-scope device array instead of caller memory.  Each
+// device the library runs on holds its own copy until the process ends.  In
+// host code `scratch` only names the symbol; its device address comes from
+// hipGetSymbolAddress, once per device with that device current, and only
+// that address is ever handed to a kernel.
+static __device__ __align__(256) unsigned char scratch[LDPC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on device `dev` (the current device), looked up
+// on the first call for that device; NULL (with the error set) on failure.
+void *scratch_address(int dev, const std::string &f) {
+    if (dev < 0 || dev >= kMaxScratchDevices) {
+        set_error(f + ": device ordinal " + std::to_string(dev) + " is beyond the scratch table");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            set_error(f + ": hipGetSymbolAddress(scratch) failed: " + hipGetErrorString(e));
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" ldpc_status ldpc_decode_noalloc(const ldpc_graph *g, const float *llr_in, int32_t frames,
+                                           int32_t max_iter, uint32_t flags, uint8_t *bits_out,
+                                           uint8_t *syndrome_ok, int32_t *iters, float *llr_out,
+                                           void *hip_stream) {
+    const std::string f("ldpc_decode_noalloc");
+    if (!g) { set_error(f + ": graph is NULL"); return LDPC_E_INVAL; }
+    if (g->host_only) { set_error(f + ": graph was built host-only"); return LDPC_E_INVAL; }
+    if (frames < 0) { set_error(f + ": frames < 0"); return LDPC_E_INVAL; }
+    if (!flags_ok(flags)) { set_error(f + ": bad flags"); return LDPC_E_INVAL; }
+    // compaction keeps a pinned host word and events of its own
+    if (flags & LDPC_COMPACT_TAIL) {
+        set_error(f + ": LDPC_COMPACT_TAIL allocates and is not available here");
+        return LDPC_E_INVAL;
+    }
+    if (frames == 0 || max_iter < 1)   // no-op or an argument error, reported by the decode itself
+        return decode_core(f.c_str(), g, llr_in, frames, max_iter, flags, nullptr, bits_out, syndrome_ok, iters,
+                           llr_out, nullptr, 0, hip_stream, Marks{});
+    const size_t need = make_plan(g, frames, flags).total;
+    if (need > size_t(LDPC_NOALLOC_SCRATCH_BYTES)) {
+        set_error(f + ": " + std::to_string(frames) + " frames need " + std::to_string(need) +
+                  " bytes of state; the static scratch holds " + std::to_string(size_t(LDPC_NOALLOC_SCRATCH_BYTES)));
+        return LDPC_E_RANGE;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != g->device) {
+        (void)hipGetLastError();
+        set_error(f + ": the current device is not the graph's device");
+        return LDPC_E_INVAL;
+    }
+    void *ws = scratch_address(dev, f);
+    if (!ws) return LDPC_E_DEVICE;
+    return decode_core(f.c_str(), g, llr_in, frames, max_iter, flags, nullptr, bits_out, syndrome_ok, iters, llr_out,
+                       ws, size_t(LDPC_NOALLOC_SCRATCH_BYTES), hip_stream, Marks{});
 }

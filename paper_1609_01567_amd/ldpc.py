@@ -32,8 +32,8 @@ GRAPH_HOST_ONLY = 1 << 0
 
 EXPORTED = ("ldpc_graph_create", "ldpc_graph_destroy", "ldpc_graph_info", "ldpc_graph_arrays",
             "ldpc_decode_workspace_size", "ldpc_decode", "ldpc_decode_rule", "ldpc_decode_profiled",
-            "ldpc_simulate_workspace_size", "ldpc_simulate", "ldpc_simulate_rule", "ldpc_status_str",
-            "ldpc_last_error", "ldpc_engine_create", "ldpc_engine_destroy", "ldpc_engine_info",
+            "ldpc_decode_noalloc", "ldpc_simulate_workspace_size", "ldpc_simulate", "ldpc_simulate_rule",
+            "ldpc_status_str", "ldpc_last_error", "ldpc_engine_create", "ldpc_engine_destroy", "ldpc_engine_info",
             "ldpc_engine_submit", "ldpc_engine_capacity", "ldpc_engine_step", "ldpc_engine_poll",
             "ldpc_engine_run", "ldpc_engine_stream", "ldpc_engine_autotune", "ldpc_server_create", "ldpc_server_submit",
             "ldpc_server_poll", "ldpc_server_result", "ldpc_server_stats", "ldpc_server_destroy")
@@ -107,6 +107,7 @@ def load_library():
     lib.ldpc_decode.argtypes = [P, P, I32, I32, U32, P, P, P, P, P, ctypes.c_size_t, P]
     lib.ldpc_decode_rule.argtypes = [P, P, I32, I32, U32, P, P, P, P, P, P, ctypes.c_size_t, P]
     lib.ldpc_decode_profiled.argtypes = [P, P, I32, I32, U32, P, P, P, P, P, ctypes.c_size_t, P, P, P, P]
+    lib.ldpc_decode_noalloc.argtypes = [P, P, I32, I32, U32, P, P, P, P, P]
     lib.ldpc_simulate_workspace_size.argtypes = [P, I32, U32, ctypes.POINTER(ctypes.c_size_t)]
     lib.ldpc_simulate.argtypes = [P, I32, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64, I32, U32, P, P, P,
                                   ctypes.c_size_t, P]
@@ -114,7 +115,7 @@ def load_library():
                                        P, ctypes.c_size_t, P]
     for f in ("ldpc_graph_create", "ldpc_graph_destroy", "ldpc_graph_info", "ldpc_graph_arrays",
               "ldpc_decode_workspace_size", "ldpc_decode", "ldpc_decode_rule", "ldpc_decode_profiled",
-              "ldpc_simulate_workspace_size", "ldpc_simulate", "ldpc_simulate_rule"):
+              "ldpc_decode_noalloc", "ldpc_simulate_workspace_size", "ldpc_simulate", "ldpc_simulate_rule"):
         getattr(lib, f).restype = ctypes.c_int
     lib.ldpc_engine_create.argtypes = [P, I32, P, P, I32, U32, P, ctypes.POINTER(P)]
     lib.ldpc_engine_destroy.argtypes = [P]
@@ -302,6 +303,40 @@ def decode_profiled(graph: Graph, llr, max_iter: int, flags: int = 0, want_llr: 
                                            _np_ptr(bit_ms), _np_ptr(edge_ms)), "ldpc_decode_profiled")
     out._workspace = workspace
     return out, dict(check_ms=check_ms, bit_ms=bit_ms, edge_ms=edge_ms)
+
+
+# bytes of the library's static per-device decode state (ldpc_decode_noalloc)
+NOALLOC_SCRATCH_BYTES = 128 << 20
+
+
+def decode_noalloc(graph: Graph, llr, max_iter: int, flags: int = 0, want_llr: bool = False, stream=None,
+                   out: DecodeResult | None = None) -> DecodeResult:
+    """Enqueue ldpc_decode_noalloc: the decode state lives in the library's static device array.
+
+    Pass preallocated `out` tensors to keep the call free of allocation.  Calls
+    on one device share that array: serialize them (e.g. on one stream).
+    """
+    import torch
+    if llr.dtype != torch.float32 or not llr.is_cuda or llr.dim() != 2 or not llr.is_contiguous():
+        raise ValueError("llr must be a contiguous float32 CUDA tensor [frames][n]")
+    F, n = llr.shape
+    if n != graph.n:
+        raise ValueError("llr width does not match the graph")
+    dev = llr.device
+    if out is None:
+        out = DecodeResult(bits=torch.empty((F, n), dtype=torch.uint8, device=dev),
+                           ok=torch.empty(F, dtype=torch.uint8, device=dev),
+                           iters=torch.empty(F, dtype=torch.int32, device=dev),
+                           llr=torch.empty((F, n), dtype=torch.float32, device=dev) if want_llr else None)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    _check(graph._lib.ldpc_decode_noalloc(
+        graph.handle, ctypes.c_void_p(llr.data_ptr()), int(F), int(max_iter), int(flags),
+        ctypes.c_void_p(out.bits.data_ptr()), ctypes.c_void_p(out.ok.data_ptr()),
+        ctypes.c_void_p(out.iters.data_ptr()),
+        ctypes.c_void_p(out.llr.data_ptr()) if out.llr is not None else None,
+        ctypes.c_void_p(stream.cuda_stream)), "ldpc_decode_noalloc")
+    return out
 
 
 SIM_FIELDS = ("frames", "frame_errors", "bit_errors", "undetected", "iterations")

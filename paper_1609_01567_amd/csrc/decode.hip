@@ -36,6 +36,7 @@
 #include <cstdint>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "internal.h"
@@ -57,22 +58,33 @@ __global__ __launch_bounds__(256) void init_state_kernel(int32_t *__restrict__ i
     }
 }
 
-// llr_in [F][n] -> Lch [n][S] (zeros in padding slots), 64x64 tiles through LDS.
+// llr_in [F][n] -> Lch [n][S] (zeros in padding slots, -0 stored as +0), 64x64
+// tiles through LDS; with post16, also their 16-bit copy for the first check pass.
 __global__ __launch_bounds__(256) void ingest_kernel(const float *__restrict__ llr, int32_t F, int32_t n,
-                                                     float *__restrict__ Lch, int32_t S) {
+                                                     float *__restrict__ Lch, int32_t S, _Float16 *__restrict__ post16) {
     __shared__ float tile[64][65];
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int v0 = blockIdx.x * 64, s0 = blockIdx.y * 64;
     for (int i = ty; i < 64; i += 4) {
         const int f = s0 + i, v = v0 + tx;
-        tile[i][tx] = (f < F && v < n) ? llr[size_t(f) * n + v] : 0.f;
+        tile[i][tx] = (f < F && v < n) ? canon_llr(llr[size_t(f) * n + v]) : 0.f;
     }
     __syncthreads();
     for (int i = ty; i < 64; i += 4) {
         const int v = v0 + i;
-        if (v < n) Lch[size_t(v) * S + s0 + tx] = tile[tx][i];
+        if (v < n) {
+            Lch[size_t(v) * S + s0 + tx] = tile[tx][i];
+            if (post16) post16[size_t(v) * S + s0 + tx] = post16_enc(tile[tx][i]);
+        }
     }
 }
+
+// Element type of the array a check pass takes L from: the channel LLRs in
+// iteration 1, the posterior afterwards, both in the check pass's storage
+// (Post): with 16-bit messages the ingest stores a 16-bit copy of the channel
+// LLRs there, otherwise iteration 1 reads the fp32 channel array.
+template <int M, int MODE>
+using CheckL = typename Post<M>::T;
 
 // Plain-path slot state: kFirst is iteration 1 (L = Lch, no previous
 // messages); kIter reads Lpost and R_old.  When syn_iter > 0 the syndrome of
@@ -88,11 +100,13 @@ __device__ __forceinline__ void plain_syndrome(const int32_t (&st)[V], const int
 }
 
 // Rows of degree <= DMAX in registers: one wavefront per (row, slot group).
-// RULE: the check rule (CheckRule); rp its parameter.
+// RULE: the check rule (CheckRule); rp its parameter.  At least four
+// wavefronts per SIMD (at most 128 registers): a row keeps all of its loads in
+// flight, so the number of resident wavefronts bounds the memory parallelism.
 template <int M, int V, int DMAX, int MODE, int RULE>
-__global__ __launch_bounds__(256) void check_rows_kernel(
+__global__ __launch_bounds__(256, 4) void check_rows_kernel(
     const int32_t *__restrict__ rd, const int32_t *__restrict__ col_idx,
-    int32_t nrows, const float *__restrict__ L, typename Codec<M>::T *__restrict__ R,
+    int32_t nrows, const CheckL<M, MODE> *__restrict__ L, typename Codec<M>::T *__restrict__ R,
     const int32_t *__restrict__ iters, int32_t *__restrict__ fail, int32_t S, int32_t groups, int32_t syn_iter,
     float rp) {
     const int lane = threadIdx.x & 63;
@@ -131,7 +145,7 @@ __global__ __launch_bounds__(256) void check_rows_kernel(
 template <int M, int V, int WPR, int MODE, int RULE>
 __global__ __launch_bounds__(256) void check_chunk_kernel(
     const int32_t *__restrict__ rd, const int32_t *__restrict__ col_idx,
-    int32_t nrows, const float *__restrict__ L, typename Codec<M>::T *__restrict__ R,
+    int32_t nrows, const CheckL<M, MODE> *__restrict__ L, typename Codec<M>::T *__restrict__ R,
     const int32_t *__restrict__ iters, int32_t *__restrict__ fail, int32_t S, int32_t groups, int32_t syn_iter,
     float rp) {
     constexpr int C = kRowChunk;
@@ -169,31 +183,31 @@ __global__ __launch_bounds__(256) void check_chunk_kernel(
     src.any = false;
     const bool mine = work && lane_active;
     float u[C][V], suf[C][V], agg[V];
-    uint32_t neg[V];
+    uint32_t par[V];
     int syn[V];
     for (int ch = wr; ch < nch; ch += WPR) {
         if (mine) {
             chunk_load<M, V, C, kChunkIn, RULE>(col_idx, e0 + ch * C, min(C, d - ch * C), L, R, S, s0, src, u,
-                                                suf, agg, neg, syn);
+                                                suf, agg, par, syn);
         } else {
 #pragma unroll
-            for (int k = 0; k < V; k++) { agg[k] = CheckRule<RULE>::identity(); neg[k] = 0u; syn[k] = 0; }
+            for (int k = 0; k < V; k++) { agg[k] = CheckRule<RULE>::identity(); par[k] = 0u; syn[k] = 0; }
         }
 #pragma unroll
         for (int k = 0; k < V; k++) sh.agg[lr * MAXCH + ch][lane][k] = agg[k];
-        sh.bits[lr * MAXCH + ch][lane] = pack_bits<V>(neg, syn);
+        sh.bits[lr * MAXCH + ch][lane] = pack_bits<V>(par, syn);
     }
     __syncthreads();
     if (!mine) return;
     for (int ch = wr; ch < nch; ch += WPR) {
         if (nch > WPR)
             chunk_load<M, V, C, kChunkIn, RULE>(col_idx, e0 + ch * C, min(C, d - ch * C), L, R, S, s0, src, u,
-                                                suf, agg, neg, syn);
+                                                suf, agg, par, syn);
         float pre[V], post[V];
         uint32_t parity[V];
         int syn_row[V];
         chunk_context<V, RPB * MAXCH, RULE>(sh, lr * MAXCH, nch, ch, lane, pre, post, parity, syn_row);
-        chunk_store<M, V, C, RULE>(e0 + ch * C, min(C, d - ch * C), u, suf, neg, pre, post, parity, R, S, s0, rp);
+        chunk_store<M, V, C, RULE>(e0 + ch * C, min(C, d - ch * C), u, suf, pre, post, parity, R, S, s0, rp);
         if (MODE == kIter && ch == 0) plain_syndrome<V>(st, syn_row, fail, s0, syn_iter);
     }
 }
@@ -206,7 +220,7 @@ __global__ __launch_bounds__(256) void check_chunk_kernel(
 template <int M, int MODE, int RULE>
 __global__ __launch_bounds__(256) void check_hub_kernel(
     const int32_t *__restrict__ rd, const int32_t *__restrict__ col_idx,
-    int32_t nrows, const int32_t *__restrict__ chunk_base, const float *__restrict__ L,
+    int32_t nrows, const int32_t *__restrict__ chunk_base, const CheckL<M, MODE> *__restrict__ L,
     typename Codec<M>::T *__restrict__ R, const int32_t *__restrict__ iters, int32_t *__restrict__ fail,
     int32_t S, int32_t groups, int32_t syn_iter, float *__restrict__ aggD, float *__restrict__ aggPre,
     int32_t *__restrict__ aggBits, float rp) {
@@ -238,7 +252,7 @@ __global__ __launch_bounds__(256) void check_hub_kernel(
         for (int jj = 0; jj < C; jj++) {
             if (jj < dc) {
                 const int v = wave_uniform(col_idx[j0 + jj]);
-                const float lv = L[size_t(v) * S + s];
+                const float lv = Codec<CodecOf<CheckL<M, MODE>>::kMsg>::dec(L[size_t(v) * S + s]);
                 const float r = (MODE == kIter) ? Codec<M>::dec(R[size_t(j0 + jj) * S + s]) : 0.f;
                 const float q = clamp_msg(lv - r);
                 bits ^= int32_t(q < 0.f) | (int32_t(lv < 0.f) << 1);
@@ -281,7 +295,7 @@ __global__ __launch_bounds__(256) void check_hub_kernel(
         for (int jj = 0; jj < C; jj++) {
             if (jj < dc) {
                 const int v = wave_uniform(col_idx[j0 + jj]);
-                const float lv = L[size_t(v) * S + s];
+                const float lv = Codec<CodecOf<CheckL<M, MODE>>::kMsg>::dec(L[size_t(v) * S + s]);
                 const float r = (MODE == kIter) ? Codec<M>::dec(R[size_t(j0 + jj) * S + s]) : 0.f;
                 const float q = clamp_msg(lv - r);
                 neg |= uint32_t(q < 0.f) << jj;
@@ -310,13 +324,17 @@ __global__ __launch_bounds__(256) void check_hub_kernel(
 }
 
 // Bit pass: Lpost = Lch + sum of R over the bit's checks (Algorithm 4); one
-// wavefront per (bit, slot group).  A frame whose previous estimate passed
-// the syndrome (no fail mark for iteration t-1) is finished: its Lpost is left
-// as is and the wavefront of bit 0 records iters = t-1.
+// wavefront per (bit, slot group).  The posterior goes to the check pass's
+// storage `post` (Post<M>) and, when Lpost is not NULL, also to the fp32 array
+// Lpost (16-bit message formats only; otherwise `post` is the fp32 array).  A
+// frame whose previous estimate passed the syndrome (no fail mark for
+// iteration t-1) is finished: its posterior is left as is and the wavefront
+// of bit 0 records iters = t-1.
 template <int M, int V>
 __global__ __launch_bounds__(256) void bit_kernel(const int32_t *__restrict__ col_ptr,
                                                   const int32_t *__restrict__ csc_to_csr, int32_t n,
                                                   const float *__restrict__ Lch, const typename Codec<M>::T *__restrict__ R,
+                                                  typename Post<M>::T *__restrict__ post,
                                                   float *__restrict__ Lpost, int32_t *__restrict__ iters,
                                                   const int32_t *__restrict__ fail, int32_t S, int32_t groups,
                                                   int32_t t, int32_t early_stop) {
@@ -356,20 +374,25 @@ __global__ __launch_bounds__(256) void bit_kernel(const int32_t *__restrict__ co
 #pragma unroll
     for (int k = 0; k < V; k++) all &= act[k];
     if (all) {
-        store_vec<kF32, V>(Lpost + size_t(v) * S + s0, sum);
+        store_post<V>(post + size_t(v) * S + s0, sum);
+        if (Lpost) store_vec<kF32, V>(Lpost + size_t(v) * S + s0, sum);
     } else {
 #pragma unroll
-        for (int k = 0; k < V; k++)
-            if (act[k]) Lpost[size_t(v) * S + s0 + k] = sum[k];
+        for (int k = 0; k < V; k++) {
+            if (act[k]) {
+                store_post1(post + size_t(v) * S + s0 + k, sum[k]);
+                if (Lpost) Lpost[size_t(v) * S + s0 + k] = sum[k];
+            }
+        }
     }
 }
 
 // Syndrome of the current estimate for every non-empty check (any degree):
 // frames still running whose estimate fails get fail[s] = syn_iter.
-template <int V>
+template <int V, typename PT>
 __global__ __launch_bounds__(256) void syndrome_kernel(const int32_t *__restrict__ rd,
                                                        const int32_t *__restrict__ col_idx, int32_t nrows,
-                                                       const float *__restrict__ Lpost,
+                                                       const PT *__restrict__ Lpost,
                                                        const int32_t *__restrict__ iters, int32_t *__restrict__ fail,
                                                        int32_t S, int32_t groups, int32_t syn_iter) {
     const int lane = threadIdx.x & 63;
@@ -393,7 +416,7 @@ __global__ __launch_bounds__(256) void syndrome_kernel(const int32_t *__restrict
     for (int e = a; e < b; e++) {
         const int v = wave_uniform(col_idx[e]);
         float lv[V];
-        load_vec<kF32, V>(Lpost + size_t(v) * S + s0, lv);
+        load_vec<CodecOf<PT>::kMsg, V>(Lpost + size_t(v) * S + s0, lv);
 #pragma unroll
         for (int k = 0; k < V; k++) syn[k] ^= (lv[k] < 0.f);
     }
@@ -419,15 +442,21 @@ __global__ __launch_bounds__(256) void finalize_kernel(const int32_t *__restrict
     }
 }
 
-// Lpost [n][S] -> bits [F][n] (1 iff Lpost < 0, Algorithm 6) and optional llr_out [F][n].
-__global__ __launch_bounds__(256) void egress_kernel(const float *__restrict__ Lpost, int32_t S, int32_t F,
-                                                     int32_t n, uint8_t *__restrict__ bits, float *__restrict__ llr_out) {
+// Posterior [n][S] -> bits [F][n] (1 iff Lpost < 0, Algorithm 6) and optional
+// llr_out [F][n].  With llr_out the fp32 posterior Lpost is read (its signs
+// are those of the check-pass storage); without it, the storage `post`.
+template <typename PT>
+__global__ __launch_bounds__(256) void egress_kernel(const PT *__restrict__ post, const float *__restrict__ Lpost,
+                                                     int32_t S, int32_t F, int32_t n, uint8_t *__restrict__ bits,
+                                                     float *__restrict__ llr_out) {
     __shared__ float tile[64][65];
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int v0 = blockIdx.x * 64, s0 = blockIdx.y * 64;
     for (int i = ty; i < 64; i += 4) {
         const int v = v0 + i;
-        tile[i][tx] = v < n ? Lpost[size_t(v) * S + s0 + tx] : 0.f;
+        tile[i][tx] = v >= n ? 0.f
+                      : llr_out ? Lpost[size_t(v) * S + s0 + tx]
+                                : Codec<CodecOf<PT>::kMsg>::dec(post[size_t(v) * S + s0 + tx]);
     }
     __syncthreads();
     for (int i = ty; i < 64; i += 4) {
@@ -479,7 +508,8 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float &z0, fl
 // (L = k0 + k1 z with k0 = 2/sigma^2, k1 = 2/sigma).  Padding slots get 0.
 __global__ __launch_bounds__(256) void channel_kernel(float *__restrict__ Lch, int32_t S, int32_t F, int32_t n,
                                                       uint32_t key0, uint32_t key1, uint64_t first_frame, float k0,
-                                                      float k1, float *__restrict__ llr_out) {
+                                                      float k1, float *__restrict__ llr_out,
+                                                      _Float16 *__restrict__ post16) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= S) return;
     const int quads = (n + 3) / 4;
@@ -496,8 +526,9 @@ __global__ __launch_bounds__(256) void channel_kernel(float *__restrict__ Lch, i
         for (int j = 0; j < 4; j++) {
             const int v = 4 * q + j;
             if (v < n) {
-                const float L = s < F ? fmaf(k1, z[j], k0) : 0.f;
+                const float L = s < F ? canon_llr(fmaf(k1, z[j], k0)) : 0.f;
                 Lch[size_t(v) * S + s] = L;
+                if (post16) post16[size_t(v) * S + s] = post16_enc(L);
                 if (llr_out && s < F) llr_out[size_t(s) * n + v] = L;
             }
         }
@@ -512,14 +543,15 @@ __global__ __launch_bounds__(256) void zero_kernel(int32_t *__restrict__ x, int3
 // Bit errors of each frame's estimate against the all-zero codeword: bits whose
 // hard decision is 1 (Lpost < 0, Algorithm 6).  Thread = frame, 64 bits per
 // workgroup row; counts are added into err[frame].
-__global__ __launch_bounds__(256) void count_errors_kernel(const float *__restrict__ Lpost, int32_t S, int32_t F,
+template <typename PT>
+__global__ __launch_bounds__(256) void count_errors_kernel(const PT *__restrict__ Lpost, int32_t S, int32_t F,
                                                            int32_t n, int32_t *__restrict__ err) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= F) return;
     for (int v0 = blockIdx.y * 64; v0 < n; v0 += gridDim.y * 64) {
         const int v1 = min(n, v0 + 64);
         int cnt = 0;
-        for (int v = v0; v < v1; v++) cnt += Lpost[size_t(v) * S + s] < 0.f;
+        for (int v = v0; v < v1; v++) cnt += Codec<CodecOf<PT>::kMsg>::dec(Lpost[size_t(v) * S + s]) < 0.f;
         if (cnt) atomicAdd(err + s, cnt);
     }
 }
@@ -624,8 +656,9 @@ __global__ __launch_bounds__(256) void gather_state_kernel(const int32_t *__rest
 
 // Back to the full state: posterior rows, iteration counts and fail marks of
 // the moved frames (the messages are not needed after the last iteration).
-__global__ __launch_bounds__(256) void scatter_slots_kernel(const float *__restrict__ c_lpost, int32_t Sc,
-                                                            float *__restrict__ lpost, int32_t S, int64_t n,
+template <typename PT>
+__global__ __launch_bounds__(256) void scatter_slots_kernel(const PT *__restrict__ c_lpost, int32_t Sc,
+                                                            PT *__restrict__ lpost, int32_t S, int64_t n,
                                                             const int32_t *__restrict__ c_iters,
                                                             const int32_t *__restrict__ c_fail, int32_t *__restrict__ iters,
                                                             int32_t *__restrict__ fail, const int32_t *__restrict__ map,
@@ -637,7 +670,7 @@ __global__ __launch_bounds__(256) void scatter_slots_kernel(const float *__restr
         const int k = int(i - v * Sc);
         if (k < K) {
             lpost[v * S + map[k]] = c_lpost[i];
-            if (v == 0) {
+            if (v == 0 && c_iters) {
                 iters[map[k]] = c_iters[k];
                 fail[map[k]] = c_fail[k];
             }
@@ -649,14 +682,15 @@ struct Plan {
     int msg = kF32;
     int V = 1;
     int32_t S = 0;
-    size_t off_lch = 0, off_lpost = 0, off_r = 0, off_iters = 0, off_fail = 0;
+    size_t off_lch = 0, off_lpost = 0, off_post = 0, off_r = 0, off_iters = 0, off_fail = 0;
     size_t off_aggd = 0, off_aggpre = 0, off_aggbits = 0, total = 0;
     size_t off_err = 0, off_it = 0, off_ok = 0;   // Monte-Carlo runs only
     // tail compaction (LDPC_COMPACT_TAIL): two copies of the state, for S/2
     // and S/4 slots (level 1 and 2), and the word the running counts go through
     struct Level {
         int32_t Sc = 0;
-        size_t off_lch = 0, off_lpost = 0, off_r = 0, off_iters = 0, off_fail = 0, off_map = 0, off_count = 0;
+        size_t off_lch = 0, off_lpost = 0, off_post = 0, off_r = 0, off_iters = 0, off_fail = 0, off_map = 0,
+               off_count = 0;
     } lv[2];
     size_t off_probe = 0;
 };
@@ -688,6 +722,10 @@ Plan make_plan(const ldpc_graph *g, int32_t F, uint32_t flags, bool sim = false)
     size_t off = 0;
     p.off_lch = off;     off = align256(off + size_t(g->n) * S * 4);
     p.off_lpost = off;   off = align256(off + size_t(g->n) * S * 4);
+    // 16-bit message formats keep a 16-bit copy of the posterior for the check pass
+    const bool post16 = p.msg == kF16 || p.msg == kBF16;
+    p.off_post = p.off_lpost;
+    if (post16) { p.off_post = off; off = align256(off + size_t(g->n) * S * 2); }
     p.off_r = off;       off = align256(off + size_t(g->E) * S * msg_bytes);
     p.off_iters = off;   off = align256(off + S * 4);
     p.off_fail = off;    off = align256(off + S * 4);
@@ -709,6 +747,8 @@ Plan make_plan(const ldpc_graph *g, int32_t F, uint32_t flags, bool sim = false)
             const size_t Sc = size_t(L.Sc);
             L.off_lch = off;   off = align256(off + size_t(g->n) * Sc * 4);
             L.off_lpost = off; off = align256(off + size_t(g->n) * Sc * 4);
+            L.off_post = L.off_lpost;
+            if (post16) { L.off_post = off; off = align256(off + size_t(g->n) * Sc * 2); }
             L.off_r = off;     off = align256(off + size_t(g->E) * Sc * msg_bytes);
             L.off_iters = off; off = align256(off + Sc * 4);
             L.off_fail = off;  off = align256(off + Sc * 4);
@@ -723,6 +763,7 @@ Plan make_plan(const ldpc_graph *g, int32_t F, uint32_t flags, bool sim = false)
 
 struct Bufs {
     float *lch, *lpost;
+    void *post;             // posterior in the check pass's storage (Post<M>); lpost for 32/8-bit messages
     void *r;
     int32_t *iters, *fail;
     float *aggd, *aggpre;
@@ -733,7 +774,7 @@ struct Bufs {
 inline unsigned blocks_for_waves(int64_t waves) { return unsigned((waves + 3) / 4); }
 
 template <int M, int V, int DMAX, int RULE>
-void launch_rows(const ldpc_graph *g, int cls, int mode, const float *L, const Bufs &b, int32_t S, int32_t syn_iter,
+void launch_rows(const ldpc_graph *g, int cls, int mode, const void *L, const Bufs &b, int32_t S, int32_t syn_iter,
                  float rp, hipStream_t st) {
     const int32_t nrows = g->class_begin[cls + 1] - g->class_begin[cls];
     if (nrows == 0) return;
@@ -744,14 +785,16 @@ void launch_rows(const ldpc_graph *g, int cls, int mode, const float *L, const B
     const int32_t *rd = g->d_class_rd + 2 * g->class_begin[cls];
     if (mode == kFirst)
         hipLaunchKernelGGL((check_rows_kernel<M, V, DMAX, kFirst, RULE>), dim3(blocks), dim3(256), 0, st, rd,
-                           g->d_col_idx, nrows, L, R, b.iters, b.fail, S, groups, 0, rp);
+                           g->d_col_idx, nrows, static_cast<const CheckL<M, kFirst> *>(L), R, b.iters, b.fail, S,
+                           groups, 0, rp);
     else
         hipLaunchKernelGGL((check_rows_kernel<M, V, DMAX, kIter, RULE>), dim3(blocks), dim3(256), 0, st, rd,
-                           g->d_col_idx, nrows, L, R, b.iters, b.fail, S, groups, syn_iter, rp);
+                           g->d_col_idx, nrows, static_cast<const CheckL<M, kIter> *>(L), R, b.iters, b.fail, S,
+                           groups, syn_iter, rp);
 }
 
 template <int M, int V, int WPR, int RULE>
-void launch_chunked(const ldpc_graph *g, int cls, int mode, const float *L, const Bufs &b, int32_t S,
+void launch_chunked(const ldpc_graph *g, int cls, int mode, const void *L, const Bufs &b, int32_t S,
                     int32_t syn_iter, float rp, hipStream_t st) {
     const int32_t nrows = g->class_begin[cls + 1] - g->class_begin[cls];
     if (nrows == 0) return;
@@ -763,14 +806,16 @@ void launch_chunked(const ldpc_graph *g, int cls, int mode, const float *L, cons
     const int32_t *rd = g->d_class_rd + 2 * g->class_begin[cls];
     if (mode == kFirst)
         hipLaunchKernelGGL((check_chunk_kernel<M, V, WPR, kFirst, RULE>), dim3(blocks), dim3(256), 0, st, rd,
-                           g->d_col_idx, nrows, L, R, b.iters, b.fail, S, groups, 0, rp);
+                           g->d_col_idx, nrows, static_cast<const CheckL<M, kFirst> *>(L), R, b.iters, b.fail, S,
+                           groups, 0, rp);
     else
         hipLaunchKernelGGL((check_chunk_kernel<M, V, WPR, kIter, RULE>), dim3(blocks), dim3(256), 0, st, rd,
-                           g->d_col_idx, nrows, L, R, b.iters, b.fail, S, groups, syn_iter, rp);
+                           g->d_col_idx, nrows, static_cast<const CheckL<M, kIter> *>(L), R, b.iters, b.fail, S,
+                           groups, syn_iter, rp);
 }
 
 template <int M, int RULE>
-void launch_hub(const ldpc_graph *g, int mode, const float *L, const Bufs &b, int32_t S, int32_t syn_iter, float rp,
+void launch_hub(const ldpc_graph *g, int mode, const void *L, const Bufs &b, int32_t S, int32_t syn_iter, float rp,
                 hipStream_t st) {
     const int32_t nrows = g->class_begin[ldpc::kClassHub + 1] - g->class_begin[ldpc::kClassHub];
     if (nrows == 0) return;
@@ -781,16 +826,16 @@ void launch_hub(const ldpc_graph *g, int mode, const float *L, const Bufs &b, in
     const int32_t *rd = g->d_class_rd + 2 * g->class_begin[ldpc::kClassHub];
     if (mode == kFirst)
         hipLaunchKernelGGL((check_hub_kernel<M, kFirst, RULE>), dim3(blocks), dim3(256), 0, st, rd, g->d_col_idx,
-                           nrows, g->d_hub_chunk_base, L, R, b.iters, b.fail, S, groups, 0, b.aggd, b.aggpre,
+                           nrows, g->d_hub_chunk_base, static_cast<const CheckL<M, kFirst> *>(L), R, b.iters, b.fail, S, groups, 0, b.aggd, b.aggpre,
                            b.aggbits, rp);
     else
         hipLaunchKernelGGL((check_hub_kernel<M, kIter, RULE>), dim3(blocks), dim3(256), 0, st, rd, g->d_col_idx,
-                           nrows, g->d_hub_chunk_base, L, R, b.iters, b.fail, S, groups, syn_iter, b.aggd, b.aggpre,
+                           nrows, g->d_hub_chunk_base, static_cast<const CheckL<M, kIter> *>(L), R, b.iters, b.fail, S, groups, syn_iter, b.aggd, b.aggpre,
                            b.aggbits, rp);
 }
 
 template <int M, int V, int RULE>
-void launch_check_pass(const ldpc_graph *g, int mode, const float *L, const Bufs &b, int32_t S, int32_t syn_iter,
+void launch_check_pass(const ldpc_graph *g, int mode, const void *L, const Bufs &b, int32_t S, int32_t syn_iter,
                        float rp, hipStream_t st) {
     launch_rows<M, V, 8, RULE>(g, ldpc::kClassD8, mode, L, b, S, syn_iter, rp, st);
     launch_rows<M, ldpc::class_lane_slots(ldpc::kClassD16, V), 16, RULE>(g, ldpc::kClassD16, mode, L, b, S, syn_iter,
@@ -807,7 +852,7 @@ struct RuleSel {
 };
 
 template <int M, int V>
-void launch_check_pass_rule(const ldpc_graph *g, int mode, const float *L, const Bufs &b, int32_t S,
+void launch_check_pass_rule(const ldpc_graph *g, int mode, const void *L, const Bufs &b, int32_t S,
                             int32_t syn_iter, const RuleSel &rule, hipStream_t st) {
     switch (rule.kind) {
         case kRuleNMS: launch_check_pass<M, V, kRuleNMS>(g, mode, L, b, S, syn_iter, rule.param, st); break;
@@ -882,6 +927,7 @@ Compact compact_at(const Plan &p, const Bufs &b, bool wanted) {
         C.b = b;
         C.b.lch = reinterpret_cast<float *>(ws + L.off_lch);
         C.b.lpost = reinterpret_cast<float *>(ws + L.off_lpost);
+        C.b.post = ws + L.off_post;
         C.b.r = ws + L.off_r;
         C.b.iters = reinterpret_cast<int32_t *>(ws + L.off_iters);
         C.b.fail = reinterpret_cast<int32_t *>(ws + L.off_fail);
@@ -900,15 +946,19 @@ Compact compact_at(const Plan &p, const Bufs &b, bool wanted) {
 // marks into the first Sp slots of `to`.
 template <int M>
 void enqueue_compaction(const ldpc_graph *g, const Bufs &from, int32_t S, const CompactLevel &to, int32_t Sp,
-                        hipStream_t st) {
+                        bool keep32, hipStream_t st) {
     using W = typename Raw<sizeof(typename Codec<M>::T)>::T;
+    using PW = typename Raw<sizeof(typename Post<M>::T)>::T;
     hipLaunchKernelGGL(running_list_kernel, dim3(1), dim3(1024), 0, st, from.iters, S, to.map, Sp, to.count);
     hipLaunchKernelGGL((gather_slots_kernel<W>), dim3(4096), dim3(256), 0, st, static_cast<const W *>(from.r), S,
                        static_cast<W *>(to.b.r), Sp, int64_t(g->E), to.map, to.count);
     hipLaunchKernelGGL((gather_slots_kernel<float>), dim3(2048), dim3(256), 0, st, from.lch, S, to.b.lch, Sp,
                        int64_t(g->n), to.map, to.count);
-    hipLaunchKernelGGL((gather_slots_kernel<float>), dim3(2048), dim3(256), 0, st, from.lpost, S, to.b.lpost, Sp,
-                       int64_t(g->n), to.map, to.count);
+    hipLaunchKernelGGL((gather_slots_kernel<PW>), dim3(2048), dim3(256), 0, st, static_cast<const PW *>(from.post), S,
+                       static_cast<PW *>(to.b.post), Sp, int64_t(g->n), to.map, to.count);
+    if (keep32)
+        hipLaunchKernelGGL((gather_slots_kernel<float>), dim3(2048), dim3(256), 0, st, from.lpost, S, to.b.lpost, Sp,
+                           int64_t(g->n), to.map, to.count);
     hipLaunchKernelGGL(gather_state_kernel, dim3(unsigned((Sp + 255) / 256)), dim3(256), 0, st, from.fail, Sp,
                        to.map, to.count, to.b.iters, to.b.fail);
 }
@@ -918,18 +968,22 @@ void run_decode(const ldpc_graph *g, const Plan &p, const Bufs &b, const float *
                 bool early_stop, uint8_t *bits, uint8_t *ok, int32_t *iters_out, float *llr_out, hipStream_t st,
                 const Marks &mk, const SimRun &sim, const RuleSel &rule) {
     using MT = typename Codec<M>::T;
+    using PT = typename Post<M>::T;
     const int32_t S = p.S;
     const int32_t groups = S / (64 * V);
+    // 16-bit message formats write the fp32 posterior only when it is an output
+    const bool keep32 = kPost16<M> && llr_out && !sim.on;
+    _Float16 *post16 = kPost16<M> ? static_cast<_Float16 *>(b.post) : nullptr;
     mk.mark(0, st);
     hipLaunchKernelGGL(init_state_kernel, dim3((S + 255) / 256), dim3(256), 0, st, b.iters, b.fail, F, S);
     const dim3 tgrid((g->n + 63) / 64, S / 64);
     if (sim.on) {
         const unsigned quads = unsigned(std::min(65535, (g->n + 3) / 4));
         hipLaunchKernelGGL(channel_kernel, dim3(unsigned((S + 255) / 256), quads), dim3(256), 0, st, b.lch, S, F,
-                           g->n, sim.key0, sim.key1, sim.first_frame, sim.k0, sim.k1, sim.llr_out);
+                           g->n, sim.key0, sim.key1, sim.first_frame, sim.k0, sim.k1, sim.llr_out, post16);
         hipLaunchKernelGGL(zero_kernel, dim3(unsigned((S + 255) / 256)), dim3(256), 0, st, sim.err, S);
     } else {
-        hipLaunchKernelGGL(ingest_kernel, tgrid, dim3(256), 0, st, llr_in, F, g->n, b.lch, S);
+        hipLaunchKernelGGL(ingest_kernel, tgrid, dim3(256), 0, st, llr_in, F, g->n, b.lch, S, post16);
     }
     mk.mark(1, st);
     const unsigned bit_blocks = blocks_for_waves(int64_t(g->n) * groups);
@@ -966,7 +1020,7 @@ void run_decode(const ldpc_graph *g, const Plan &p, const Bufs &b, const float *
             const int32_t need = (K + 63) / 64 * 64;
             if (K > 0 && level < 2 && need <= cp.lv[level].Sc && 2 * need <= Sl[level]) {
                 const Bufs &from = level == 0 ? b : cp.lv[level - 1].b;
-                enqueue_compaction<M>(g, from, Sl[level], cp.lv[level], need, st);
+                enqueue_compaction<M>(g, from, Sl[level], cp.lv[level], need, keep32, st);
                 level++;
                 Sl[level] = need;
             }
@@ -974,18 +1028,21 @@ void run_decode(const ldpc_graph *g, const Plan &p, const Bufs &b, const float *
         if (level > 0) {
             const Bufs &cb = cp.lv[level - 1].b;
             const int32_t Sp = Sl[level];
-            launch_check_pass_rule<M, 1>(g, kIter, cb.lpost, cb, Sp, syn_iter, rule, st);
+            launch_check_pass_rule<M, 1>(g, kIter, cb.post, cb, Sp, syn_iter, rule, st);
             mk.mark(2 * t, st);
             hipLaunchKernelGGL((bit_kernel<M, 1>), dim3(blocks_for_waves(int64_t(g->n) * (Sp / 64))), dim3(256), 0, st,
-                               g->d_col_ptr, g->d_csc_to_csr, g->n, cb.lch, static_cast<const MT *>(cb.r), cb.lpost,
+                               g->d_col_ptr, g->d_csc_to_csr, g->n, cb.lch, static_cast<const MT *>(cb.r),
+                               static_cast<PT *>(cb.post), keep32 ? cb.lpost : nullptr,
                                cb.iters, cb.fail, Sp, Sp / 64, t, int32_t(early_stop));
             mk.mark(2 * t + 1, st);
         } else {
-            launch_check_pass_rule<M, V>(g, t == 1 ? kFirst : kIter, t == 1 ? b.lch : b.lpost, b, S, syn_iter, rule,
+            const void *L1 = kPost16<M> ? b.post : static_cast<const void *>(b.lch);
+            launch_check_pass_rule<M, V>(g, t == 1 ? kFirst : kIter, t == 1 ? L1 : b.post, b, S, syn_iter, rule,
                                          st);
             mk.mark(2 * t, st);
             hipLaunchKernelGGL((bit_kernel<M, V>), dim3(bit_blocks), dim3(256), 0, st, g->d_col_ptr, g->d_csc_to_csr,
-                               g->n, b.lch, static_cast<const MT *>(b.r), b.lpost, b.iters, b.fail, S, groups, t,
+                               g->n, b.lch, static_cast<const MT *>(b.r), static_cast<PT *>(b.post),
+                               keep32 ? b.lpost : nullptr, b.iters, b.fail, S, groups, t,
                                int32_t(early_stop));
             mk.mark(2 * t + 1, st);
         }
@@ -1006,8 +1063,12 @@ void run_decode(const ldpc_graph *g, const Plan &p, const Bufs &b, const float *
     for (int l = level; l > 0; l--) {
         const CompactLevel &C = cp.lv[l - 1];
         const Bufs &up = l == 1 ? b : cp.lv[l - 2].b;
-        hipLaunchKernelGGL(scatter_slots_kernel, dim3(2048), dim3(256), 0, st, C.b.lpost, Sl[l], up.lpost, Sl[l - 1],
-                           int64_t(g->n), C.b.iters, C.b.fail, up.iters, up.fail, C.map, C.count);
+        hipLaunchKernelGGL((scatter_slots_kernel<PT>), dim3(2048), dim3(256), 0, st, static_cast<const PT *>(C.b.post),
+                           Sl[l], static_cast<PT *>(up.post), Sl[l - 1], int64_t(g->n), C.b.iters, C.b.fail, up.iters,
+                           up.fail, C.map, C.count);
+        if (keep32)
+            hipLaunchKernelGGL((scatter_slots_kernel<float>), dim3(2048), dim3(256), 0, st, C.b.lpost, Sl[l], up.lpost,
+                               Sl[l - 1], int64_t(g->n), nullptr, nullptr, up.iters, up.fail, C.map, C.count);
     }
     if (ev) {
         // a count still in flight would land in the shared pinned word later
@@ -1016,21 +1077,23 @@ void run_decode(const ldpc_graph *g, const Plan &p, const Bufs &b, const float *
     }
     const int32_t nrows = g->class_begin[ldpc::kNumClasses];
     if (nrows > 0) {
-        hipLaunchKernelGGL((syndrome_kernel<V>), dim3(blocks_for_waves(int64_t(nrows) * groups)), dim3(256), 0, st,
-                           g->d_class_rd, g->d_col_idx, nrows, b.lpost, b.iters, b.fail, S, groups, T);
+        hipLaunchKernelGGL((syndrome_kernel<V, PT>), dim3(blocks_for_waves(int64_t(nrows) * groups)), dim3(256), 0, st,
+                           g->d_class_rd, g->d_col_idx, nrows, static_cast<const PT *>(b.post), b.iters, b.fail, S,
+                           groups, T);
     }
     if (sim.on) {
         hipLaunchKernelGGL(finalize_kernel, dim3((F + 255) / 256), dim3(256), 0, st, b.iters, b.fail, F, T, sim.it,
                            sim.ok);
         const unsigned rows = unsigned(std::min(4096, (g->n + 63) / 64));
-        hipLaunchKernelGGL(count_errors_kernel, dim3(unsigned((F + 255) / 256), rows), dim3(256), 0, st, b.lpost, S, F,
-                           g->n, sim.err);
+        hipLaunchKernelGGL((count_errors_kernel<PT>), dim3(unsigned((F + 255) / 256), rows), dim3(256), 0, st,
+                           static_cast<const PT *>(b.post), S, F, g->n, sim.err);
         hipLaunchKernelGGL(tally_kernel, dim3(unsigned((F + 255) / 256)), dim3(256), 0, st, sim.err, sim.it, sim.ok, F,
                            sim.counts);
     } else {
         hipLaunchKernelGGL(finalize_kernel, dim3((F + 255) / 256), dim3(256), 0, st, b.iters, b.fail, F, T, iters_out,
                            ok);
-        hipLaunchKernelGGL(egress_kernel, tgrid, dim3(256), 0, st, b.lpost, S, F, g->n, bits, llr_out);
+        hipLaunchKernelGGL((egress_kernel<PT>), tgrid, dim3(256), 0, st, static_cast<const PT *>(b.post), b.lpost, S, F,
+                           g->n, bits, llr_out);
     }
     mk.mark(2 * T + 2, st);
 }
@@ -1076,6 +1139,7 @@ Bufs bufs_at(char *ws, const Plan &p) {
     Bufs b;
     b.lch = reinterpret_cast<float *>(ws + p.off_lch);
     b.lpost = reinterpret_cast<float *>(ws + p.off_lpost);
+    b.post = ws + p.off_post;
     b.r = ws + p.off_r;
     b.iters = reinterpret_cast<int32_t *>(ws + p.off_iters);
     b.fail = reinterpret_cast<int32_t *>(ws + p.off_fail);

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 namespace ldpc_dev {
 
@@ -52,6 +53,29 @@ template <> struct Codec<kQ8> {
         return static_cast<T>(fminf(fmaxf(rintf(x * 2.f), -127.f), 127.f));
     }
 };
+
+// Storage of the posterior that the check pass gathers to form the bit->check
+// messages Q = L - R_old (in a frame's first iteration it holds the channel
+// LLRs, the messages of Algorithm 3).  With 16-bit messages it is kept at 16
+// bits too (IEEE fp16, for fp16 and bf16 messages alike); otherwise fp32.  The fp16
+// value is rounded so that its sign is that of the fp32 sum it came from: a
+// negative sum that rounds to zero is stored as the smallest negative
+// subnormal, and a zero sum of either sign as +0.  The hard decision
+// (posterior < 0, Algorithm 6) is the same read from either copy.
+template <int M> struct Post { using T = float; static constexpr int kMsg = kF32; };
+template <> struct Post<kF16> { using T = _Float16; static constexpr int kMsg = kF16; };
+template <> struct Post<kBF16> { using T = _Float16; static constexpr int kMsg = kF16; };
+template <int M> constexpr bool kPost16 = Post<M>::kMsg == kF16;
+
+template <typename T> struct CodecOf;
+template <> struct CodecOf<float> { static constexpr int kMsg = kF32; };
+template <> struct CodecOf<_Float16> { static constexpr int kMsg = kF16; };
+
+__device__ __forceinline__ _Float16 post16_enc(float x) {
+    uint16_t b = __builtin_bit_cast(uint16_t, static_cast<_Float16>(x));   // round to nearest even
+    if ((b & 0x7fffu) == 0u) b = x < 0.f ? uint16_t(0x8001u) : uint16_t(0u);
+    return __builtin_bit_cast(_Float16, b);
+}
 
 // Device arrays by address space.  A pointer that reaches a kernel through
 // memory (a table of per-graph arrays, a frame descriptor) is generic to the
@@ -101,6 +125,37 @@ __device__ __forceinline__ void store_vec(typename Codec<M>::T *p, const float (
     *gmem(reinterpret_cast<W *>(p)) = raw;
 }
 
+// Store a lane's V posterior values in the check pass's storage (Post).
+template <int V, typename T>
+__device__ __forceinline__ void store_post(T *p, const float (&in)[V]) {
+    if constexpr (sizeof(T) == 4) {
+        store_vec<kF32, V>(reinterpret_cast<float *>(p), in);
+    } else {
+        using W = typename Raw<2 * V>::T;
+        _Float16 e[V];
+#pragma unroll
+        for (int k = 0; k < V; k++) e[k] = post16_enc(in[k]);
+        W raw;
+        __builtin_memcpy(&raw, e, sizeof(W));
+        *gmem(reinterpret_cast<W *>(p)) = raw;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void store_post1(T *p, float x) {
+    if constexpr (sizeof(T) == 4) *gmem(p) = x;
+    else *gmem(p) = post16_enc(x);
+}
+
+// Element s0 of row `row` (a wave-uniform row start) as a uniform base plus a
+// 32-bit per-lane byte offset, the form global loads and stores take with the
+// base in scalar registers (no per-lane 64-bit address arithmetic).
+template <typename T>
+__device__ __forceinline__ T *lane_elem(T *row, int s0) {
+    using B = std::conditional_t<std::is_const_v<T>, const char, char>;
+    return reinterpret_cast<T *>(reinterpret_cast<B *>(row) + uint32_t(s0) * uint32_t(sizeof(T)));
+}
+
 template <int V>
 __device__ __forceinline__ void load_i32(const int32_t *p, int32_t (&out)[V]) {
     using W = typename Raw<4 * V>::T;
@@ -118,11 +173,10 @@ __device__ __forceinline__ void store_i32(int32_t *p, const int32_t (&in)[V]) {
 
 // -------------------------------------------------------------- check math
 
-// u = 1 - tanh(x/2) = 2w/(1+w) = w / ((1+w)/2) with w = e^-x, for x = |Q| >= 0
-// (the halved denominator is one fma and saves the doubling).
+// u = 1 - tanh(x/2) = 2 / (1 + e^x) = 1 / ((1 + e^x)/2), for 0 <= x = |Q| <= LMAX
+// (e^64 is a normal fp32 number; the halved denominator is one fma).
 __device__ __forceinline__ float tanh_complement(float x) {
-    const float w = __builtin_amdgcn_exp2f(-x * kLog2e);
-    return w * __builtin_amdgcn_rcpf(fmaf(0.5f, w, 0.5f));
+    return __builtin_amdgcn_rcpf(fmaf(0.5f, __builtin_amdgcn_exp2f(x * kLog2e), 0.5f));
 }
 
 // Complement of a product of complements: 1 - (1-a)(1-b) = a + b(1-a).
@@ -135,6 +189,19 @@ __device__ __forceinline__ float magnitude_from_complement(float D) {
 }
 
 __device__ __forceinline__ float clamp_msg(float q) { return fminf(fmaxf(q, -kLmax), kLmax); }
+
+// Signs travel in the sign bit of the rule inputs: u carries the sign of its
+// Q, the row's sign parity is the XOR of those bits, and an output magnitude
+// (>= 0) takes its sign by OR-ing in a sign bit.  The values a check pass
+// reads never hold -0 (channel LLRs are stored with -0 replaced by +0, and
+// sums and differences of such values round exact zeros to +0), so the sign
+// bit of Q is exactly Q < 0, the sign Algorithm 1 uses (sgn(0) = +1).
+__device__ __forceinline__ uint32_t sign_of(float x) { return __float_as_uint(x) & 0x80000000u; }
+__device__ __forceinline__ float signed_mag(float mag, uint32_t sign) {
+    return __uint_as_float(__float_as_uint(mag) | (sign & 0x80000000u));
+}
+// A channel LLR as the check and bit passes store it: -0 becomes +0.
+__device__ __forceinline__ float canon_llr(float x) { return x + 0.f; }
 
 // Check-node rules.  Every rule takes the sign of R from the other inputs' sign
 // product and its magnitude from an aggregate of the other inputs, formed with
@@ -198,20 +265,34 @@ struct SlotSrc {
     bool any;   // some alt[k] is set
 };
 
+// L - R for fp16 L and R held as halves of 32-bit words (half 0: bits 0-15,
+// half 1: bits 16-31): one mixed-precision fma converts both halves to fp32
+// on the fly and rounds L * 1 - R once, the fp32 difference of the two values.
+template <int HALF>
+__device__ __forceinline__ float sub_f16_halves(uint32_t l, uint32_t r) {
+    float q;
+    if constexpr (HALF == 0)
+        asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel_hi:[1,0,1]" : "=v"(q) : "v"(l), "v"(r));
+    else
+        asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(q) : "v"(l), "v"(r));
+    return q;
+}
+
 // Inputs of edges j0 .. j0+count-1 (1 <= count <= C) for the lane's slots:
-// Q = clamp(L - R_old), its sign bit (bit j of neg) and the rule's input u
-// (1 - tanh(|Q|/2) for sum-product, |Q| for Min-Sum);
+// Q = clamp(L - R_old) and the rule's input u (1 - tanh(|Q|/2) for
+// sum-product, |Q| for Min-Sum) carrying the sign of Q in its sign bit; the
+// XOR of those sign bits goes into par (bit 31);
 // the sign of L feeds the syndrome of the estimate that L holds (Algorithm 7).
 // Every index load and then every message load is issued before any value is
 // used: positions past `count` repeat the last edge (same addresses, no
 // branch), so the loads of a row are in flight together instead of one edge
 // at a time.  UNIFORM: all lanes walk the same row (indices read once per
 // wavefront).
-template <int M, int V, int C, bool UNIFORM, int IN, int RULE = kRuleSP>
+template <int M, int V, int C, bool UNIFORM, int IN, int RULE = kRuleSP, typename LT>
 __device__ __forceinline__ void gather_edges(const int32_t *__restrict__ col_idx, int j0, int count,
-                                             const float *__restrict__ L,
+                                             const LT *__restrict__ L,
                                              const typename Codec<M>::T *__restrict__ R, int32_t S, int s0,
-                                             const SlotSrc<V> &src, float (&u)[C][V], uint32_t (&neg)[V],
+                                             const SlotSrc<V> &src, float (&u)[C][V], uint32_t (&par)[V],
                                              int (&syn)[V]) {
     int vix[C];
 #pragma unroll
@@ -219,13 +300,68 @@ __device__ __forceinline__ void gather_edges(const int32_t *__restrict__ col_idx
         const int e = j0 + (j < count ? j : count - 1);
         vix[j] = UNIFORM ? wave_uniform(cload(col_idx + e)) : cload(col_idx + e);
     }
+    if constexpr (M == kF16 && CodecOf<LT>::kMsg == kF16 && V % 2 == 0) {
+        // fp16 posterior and messages: the words as loaded, two slots each
+        constexpr int W = V / 2;
+        uint32_t lw[C][W], rw[C][W];
+#pragma unroll
+        for (int j = 0; j < C; j++) {
+            const int e = j0 + (j < count ? j : count - 1);
+            using RawW = typename Raw<4 * W>::T;
+            const RawW a = *gmem(reinterpret_cast<const RawW *>(lane_elem(L + size_t(vix[j]) * S, s0)));
+            __builtin_memcpy(lw[j], &a, sizeof(RawW));
+            if (IN != kInFirst) {
+                const RawW b = *gmem(reinterpret_cast<const RawW *>(lane_elem(R + size_t(e) * S, s0)));
+                __builtin_memcpy(rw[j], &b, sizeof(RawW));
+            } else {
+#pragma unroll
+                for (int w = 0; w < W; w++) rw[j][w] = 0u;
+            }
+        }
+        if (IN == kInMixed && src.any) {
+            uint32_t keep[W];   // first-iteration slots: previous message 0
+#pragma unroll
+            for (int w = 0; w < W; w++)
+                keep[w] = (src.alt[2 * w] ? 0u : 0x0000ffffu) | (src.alt[2 * w + 1] ? 0u : 0xffff0000u);
+#pragma unroll
+            for (int j = 0; j < C; j++) {
+#pragma unroll
+                for (int w = 0; w < W; w++) rw[j][w] &= keep[w];
+            }
+        }
+        uint32_t sw[W];   // syndrome: XOR of the posterior words (stored signs are the decisions)
+#pragma unroll
+        for (int w = 0; w < W; w++) sw[w] = 0u;
+#pragma unroll
+        for (int j = 0; j < C; j++) {
+            if (j < count) {
+#pragma unroll
+                for (int w = 0; w < W; w++) {
+                    sw[w] ^= lw[j][w];
+                    const float q0 = clamp_msg(sub_f16_halves<0>(lw[j][w], rw[j][w]));
+                    const float q1 = clamp_msg(sub_f16_halves<1>(lw[j][w], rw[j][w]));
+                    const uint32_t s0q = sign_of(q0), s1q = sign_of(q1);
+                    par[2 * w] ^= s0q;
+                    par[2 * w + 1] ^= s1q;
+                    u[j][2 * w] = signed_mag(CheckRule<RULE>::input(fabsf(q0)), s0q);
+                    u[j][2 * w + 1] = signed_mag(CheckRule<RULE>::input(fabsf(q1)), s1q);
+                }
+            }
+        }
+#pragma unroll
+        for (int w = 0; w < W; w++) {
+            syn[2 * w] ^= int((sw[w] >> 15) & 1u);
+            syn[2 * w + 1] ^= int(sw[w] >> 31);
+        }
+        return;
+    }
     float lv[C][V], r[C][V];
 #pragma unroll
     for (int j = 0; j < C; j++) {
         const int e = j0 + (j < count ? j : count - 1);
-        load_vec<kF32, V>(L + size_t(vix[j]) * S + s0, lv[j]);
+        load_vec<CodecOf<LT>::kMsg, V>(lane_elem(L + size_t(vix[j]) * S, s0), lv[j]);
         if (IN != kInFirst) {
-            load_vec<M, V>(R + size_t(e) * S + s0, r[j]);
+            load_vec<M, V>(lane_elem(R + size_t(e) * S, s0), r[j]);
         } else {
 #pragma unroll
             for (int k = 0; k < V; k++) r[j][k] = 0.f;
@@ -246,8 +382,9 @@ __device__ __forceinline__ void gather_edges(const int32_t *__restrict__ col_idx
             for (int k = 0; k < V; k++) {
                 syn[k] ^= (lv[j][k] < 0.f);
                 const float q = clamp_msg(lv[j][k] - r[j][k]);
-                neg[k] |= uint32_t(q < 0.f) << j;
-                u[j][k] = CheckRule<RULE>::input(fabsf(q));
+                const uint32_t sq = sign_of(q);
+                par[k] ^= sq;
+                u[j][k] = signed_mag(CheckRule<RULE>::input(fabsf(q)), sq);
             }
         }
     }
@@ -257,18 +394,18 @@ __device__ __forceinline__ void gather_edges(const int32_t *__restrict__ col_idx
 // suffixes, then exclusive prefixes combined on the fly; R is updated in place.
 // UNIFORM: every lane of the wavefront works on the same row (indices are read
 // once per wavefront); otherwise each lane walks its own row.
-template <int M, int V, int DMAX, bool UNIFORM, int IN, int RULE = kRuleSP>
+template <int M, int V, int DMAX, bool UNIFORM, int IN, int RULE = kRuleSP, typename LT>
 __device__ __forceinline__ void row_rule_n(const int32_t *__restrict__ col_idx, int e0, int d,
-                                         const float *__restrict__ L,
+                                         const LT *__restrict__ L,
                                          typename Codec<M>::T *__restrict__ R, int32_t S, int s0,
                                          const SlotSrc<V> &src, int (&syn)[V], float rp = 0.f) {
     using Rule = CheckRule<RULE>;
     float u[DMAX][V];
     float suf[DMAX][V];
-    uint32_t neg[V];
+    uint32_t par[V];
 #pragma unroll
-    for (int k = 0; k < V; k++) neg[k] = 0u;
-    gather_edges<M, V, DMAX, UNIFORM, IN, RULE>(col_idx, e0, d, L, R, S, s0, src, u, neg, syn);
+    for (int k = 0; k < V; k++) par[k] = 0u;
+    gather_edges<M, V, DMAX, UNIFORM, IN, RULE>(col_idx, e0, d, L, R, S, s0, src, u, par, syn);
     float run[V];
 #pragma unroll
     for (int k = 0; k < V; k++) run[k] = Rule::identity();
@@ -278,13 +415,12 @@ __device__ __forceinline__ void row_rule_n(const int32_t *__restrict__ col_idx, 
 #pragma unroll
             for (int k = 0; k < V; k++) {
                 suf[j][k] = run[k];
-                run[k] = Rule::combine(u[j][k], run[k]);
+                run[k] = Rule::combine(fabsf(u[j][k]), run[k]);
             }
         }
     }
-    uint32_t parity[V];
 #pragma unroll
-    for (int k = 0; k < V; k++) { run[k] = Rule::identity(); parity[k] = __builtin_popcount(neg[k]) & 1u; }
+    for (int k = 0; k < V; k++) run[k] = Rule::identity();
 #pragma unroll
     for (int j = 0; j < DMAX; j++) {
         if (j < d) {
@@ -292,11 +428,10 @@ __device__ __forceinline__ void row_rule_n(const int32_t *__restrict__ col_idx, 
 #pragma unroll
             for (int k = 0; k < V; k++) {
                 const float mag = Rule::magnitude(Rule::combine(run[k], suf[j][k]), rp);
-                const uint32_t sgn = parity[k] ^ ((neg[k] >> j) & 1u);
-                out[k] = sgn ? -mag : mag;
-                run[k] = Rule::combine(run[k], u[j][k]);
+                out[k] = signed_mag(mag, par[k] ^ __float_as_uint(u[j][k]));   // sign of the other inputs
+                run[k] = Rule::combine(run[k], fabsf(u[j][k]));
             }
-            store_vec<M, V>(R + size_t(e0 + j) * S + s0, out);
+            store_vec<M, V>(lane_elem(R + size_t(e0 + j) * S, s0), out);
         }
     }
 }
@@ -304,18 +439,18 @@ __device__ __forceinline__ void row_rule_n(const int32_t *__restrict__ col_idx, 
 // row_rule_n with the degree as a compile-time constant when every lane works
 // on the same row of at most 8 edges: the row's code is then straight-line
 // (no per-position test of the degree).  Other rows take the generic form.
-template <int M, int V, int D, bool UNIFORM, int IN, int RULE>
+template <int M, int V, int D, bool UNIFORM, int IN, int RULE, typename LT>
 __device__ __forceinline__ bool row_rule_fixed(const int32_t *__restrict__ col_idx, int e0, int d,
-                                               const float *__restrict__ L, typename Codec<M>::T *__restrict__ R,
+                                               const LT *__restrict__ L, typename Codec<M>::T *__restrict__ R,
                                                int32_t S, int s0, const SlotSrc<V> &src, int (&syn)[V], float rp) {
     if (d != D) return false;
     row_rule_n<M, V, D, UNIFORM, IN, RULE>(col_idx, e0, D, L, R, S, s0, src, syn, rp);
     return true;
 }
 
-template <int M, int V, int DMAX, bool UNIFORM, int IN, int RULE = kRuleSP>
+template <int M, int V, int DMAX, bool UNIFORM, int IN, int RULE = kRuleSP, typename LT>
 __device__ __forceinline__ void row_rule(const int32_t *__restrict__ col_idx, int e0, int d,
-                                         const float *__restrict__ L,
+                                         const LT *__restrict__ L,
                                          typename Codec<M>::T *__restrict__ R, int32_t S, int s0,
                                          const SlotSrc<V> &src, int (&syn)[V], float rp = 0.f) {
     if constexpr (UNIFORM && DMAX == 8) {
@@ -367,15 +502,15 @@ __device__ __forceinline__ void bit_sum(const int32_t *__restrict__ csc_to_csr, 
 // (pre), of the chunks after it (post) and the row's total sign parity.
 constexpr int kRowChunk = 8;
 
-template <int M, int V, int C, int IN, int RULE = kRuleSP>
+template <int M, int V, int C, int IN, int RULE = kRuleSP, typename LT>
 __device__ __forceinline__ void chunk_load(const int32_t *__restrict__ col_idx, int j0, int dc,
-                                           const float *__restrict__ L,
+                                           const LT *__restrict__ L,
                                            const typename Codec<M>::T *__restrict__ R, int32_t S, int s0,
                                            const SlotSrc<V> &src, float (&u)[C][V], float (&suf)[C][V],
-                                           float (&agg)[V], uint32_t (&neg)[V], int (&syn)[V]) {
+                                           float (&agg)[V], uint32_t (&par)[V], int (&syn)[V]) {
 #pragma unroll
-    for (int k = 0; k < V; k++) { neg[k] = 0u; syn[k] = 0; }
-    gather_edges<M, V, C, true, IN, RULE>(col_idx, j0, dc, L, R, S, s0, src, u, neg, syn);
+    for (int k = 0; k < V; k++) { par[k] = 0u; syn[k] = 0; }
+    gather_edges<M, V, C, true, IN, RULE>(col_idx, j0, dc, L, R, S, s0, src, u, par, syn);
 #pragma unroll
     for (int k = 0; k < V; k++) agg[k] = CheckRule<RULE>::identity();
 #pragma unroll
@@ -384,7 +519,7 @@ __device__ __forceinline__ void chunk_load(const int32_t *__restrict__ col_idx, 
 #pragma unroll
             for (int k = 0; k < V; k++) {
                 suf[j][k] = agg[k];
-                agg[k] = CheckRule<RULE>::combine(u[j][k], agg[k]);
+                agg[k] = CheckRule<RULE>::combine(fabsf(u[j][k]), agg[k]);
             }
         }
     }
@@ -392,7 +527,7 @@ __device__ __forceinline__ void chunk_load(const int32_t *__restrict__ col_idx, 
 
 template <int M, int V, int C, int RULE = kRuleSP>
 __device__ __forceinline__ void chunk_store(int j0, int dc, const float (&u)[C][V], const float (&suf)[C][V],
-                                            const uint32_t (&neg)[V], const float (&pre)[V], const float (&post)[V],
+                                            const float (&pre)[V], const float (&post)[V],
                                             const uint32_t (&parity)[V], typename Codec<M>::T *__restrict__ R,
                                             int32_t S, int s0, float rp = 0.f) {
     using Rule = CheckRule<RULE>;
@@ -406,9 +541,8 @@ __device__ __forceinline__ void chunk_store(int j0, int dc, const float (&u)[C][
 #pragma unroll
             for (int k = 0; k < V; k++) {
                 const float mag = Rule::magnitude(Rule::combine(run[k], Rule::combine(suf[j][k], post[k])), rp);
-                const uint32_t sgn = parity[k] ^ ((neg[k] >> j) & 1u);
-                out[k] = sgn ? -mag : mag;
-                run[k] = Rule::combine(run[k], u[j][k]);
+                out[k] = signed_mag(mag, (parity[k] << 31) ^ __float_as_uint(u[j][k]));
+                run[k] = Rule::combine(run[k], fabsf(u[j][k]));
             }
             store_vec<M, V>(R + size_t(j0 + j) * S + s0, out);
         }
@@ -425,10 +559,10 @@ struct ChunkShare {
 };
 
 template <int V>
-__device__ __forceinline__ uint32_t pack_bits(const uint32_t (&neg)[V], const int (&syn)[V]) {
+__device__ __forceinline__ uint32_t pack_bits(const uint32_t (&par)[V], const int (&syn)[V]) {
     uint32_t b = 0u;
 #pragma unroll
-    for (int k = 0; k < V; k++) b |= ((__builtin_popcount(neg[k]) & 1u) << k) | (uint32_t(syn[k] & 1) << (8 + k));
+    for (int k = 0; k < V; k++) b |= ((par[k] >> 31) << k) | (uint32_t(syn[k] & 1) << (8 + k));
     return b;
 }
 

@@ -61,8 +61,11 @@ struct EngGraph {
     const int32_t *col_idx, *col_ptr, *csc_to_csr, *hub_chunk_base;
     const int32_t *class_rd;   // per class row (class order): first edge, degree
     int32_t n, S, E;
+    int32_t post16;       // the posterior storage is fp16 (16-bit message formats)
     int32_t class_begin[ldpc::kNumClasses + 1];
     float *lch, *lpost;
+    void *post;           // posterior in the check pass's storage (Post<M>); lpost for 32/8-bit messages
+    int32_t *want32;      // [S] 16-bit formats: 1 if the slot's frame asks for its posterior (lpost kept)
     void *r;
     int32_t *slot_t;      // [2][S] iterations completed by the frame in the slot (-1: empty;
                           // + kStopped: stopped), ping-pong between the passes of a step
@@ -274,12 +277,13 @@ __device__ __forceinline__ void rows_item(const EngGraph &G, int cls, int nrows,
 #pragma unroll
     for (int k = 0; k < V; k++) syn[k] = 0;
     MT *R = static_cast<MT *>(G.r);
-    row_rule<M, V, DMAX, UNIFORM, kInMixed, RULE>(G.col_idx, e0, d, G.lpost, R, G.S, s0, ln.src, syn, rp);
+    row_rule<M, V, DMAX, UNIFORM, kInMixed, RULE>(G.col_idx, e0, d, static_cast<const typename Post<M>::T *>(G.post),
+                                                  R, G.S, s0, ln.src, syn, rp);
     eng_syndrome<V>(G, ln, syn, s0);
 }
 
 template <int M, int V, int DMAX, int PM, int RULE>
-__global__ __launch_bounds__(256) void eng_check_rows(const EngGraph *__restrict__ graphs, int32_t ngraphs,
+__global__ __launch_bounds__(256, 4) void eng_check_rows(const EngGraph *__restrict__ graphs, int32_t ngraphs,
                                                       const int32_t *__restrict__ counters, int32_t cls, int32_t T,
                                                       int32_t early, int32_t par, float rp) {
     __shared__ Work w;
@@ -347,34 +351,35 @@ __global__ __launch_bounds__(256) void eng_check_chunk(const EngGraph *__restric
             nch = (d + C - 1) / C;
         }
         MT *R = static_cast<MT *>(G.r);
+        const auto *PL = static_cast<const typename Post<M>::T *>(G.post);
         const int32_t S = G.S;
         const bool mine = work && ln.active;
         float u_[C][V], suf[C][V], agg[V];
-        uint32_t neg[V];
+        uint32_t par[V];
         int syn[V];
         for (int ch = wr; ch < nch; ch += WPR) {
             if (mine) {
-                chunk_load<M, V, C, kInMixed, RULE>(G.col_idx, e0 + ch * C, min(C, d - ch * C), G.lpost, R, S, s0,
-                                                    ln.src, u_, suf, agg, neg, syn);
+                chunk_load<M, V, C, kInMixed, RULE>(G.col_idx, e0 + ch * C, min(C, d - ch * C), PL, R, S, s0,
+                                                    ln.src, u_, suf, agg, par, syn);
             } else {
 #pragma unroll
-                for (int k = 0; k < V; k++) { agg[k] = CheckRule<RULE>::identity(); neg[k] = 0u; syn[k] = 0; }
+                for (int k = 0; k < V; k++) { agg[k] = CheckRule<RULE>::identity(); par[k] = 0u; syn[k] = 0; }
             }
 #pragma unroll
             for (int k = 0; k < V; k++) sh.agg[lr * MAXCH + ch][lane][k] = agg[k];
-            sh.bits[lr * MAXCH + ch][lane] = pack_bits<V>(neg, syn);
+            sh.bits[lr * MAXCH + ch][lane] = pack_bits<V>(par, syn);
         }
         __syncthreads();
         if (mine) {
             for (int ch = wr; ch < nch; ch += WPR) {
                 if (nch > WPR)
-                    chunk_load<M, V, C, kInMixed, RULE>(G.col_idx, e0 + ch * C, min(C, d - ch * C), G.lpost, R, S,
-                                                        s0, ln.src, u_, suf, agg, neg, syn);
+                    chunk_load<M, V, C, kInMixed, RULE>(G.col_idx, e0 + ch * C, min(C, d - ch * C), PL, R, S,
+                                                        s0, ln.src, u_, suf, agg, par, syn);
                 float pre_a[V], post_a[V];
                 uint32_t parity[V];
                 int syn_row[V];
                 chunk_context<V, RPB * MAXCH, RULE>(sh, lr * MAXCH, nch, ch, lane, pre_a, post_a, parity, syn_row);
-                chunk_store<M, V, C, RULE>(e0 + ch * C, min(C, d - ch * C), u_, suf, neg, pre_a, post_a, parity, R, S,
+                chunk_store<M, V, C, RULE>(e0 + ch * C, min(C, d - ch * C), u_, suf, pre_a, post_a, parity, R, S,
                                            s0, rp);
                 if (ch == 0) eng_syndrome<V>(G, ln, syn_row, s0);
             }
@@ -420,7 +425,7 @@ __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict_
         const int nch = (d + C - 1) / C;
         const int cb = wave_uniform(cload(G.hub_chunk_base + (rk)));
         auto R = gmem(static_cast<MT *>(G.r));
-        auto L = gmem(G.lpost);   // holds the channel LLRs in a frame's first pass
+        auto L = gmem(static_cast<const typename Post<M>::T *>(G.post));   // channel LLRs in a first pass
 
         for (int ch = wv; ch < nch; ch += nw) {
             const int j0 = e0 + ch * C;
@@ -431,7 +436,7 @@ __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict_
             for (int jj = 0; jj < C; jj++) {
                 if (jj < dc) {
                     const int v = wave_uniform(cload(G.col_idx + (j0 + jj)));
-                    const float lv = L[size_t(v) * S + s];
+                    const float lv = Codec<Post<M>::kMsg>::dec(L[size_t(v) * S + s]);
                     const float r = first ? 0.f : Codec<M>::dec(R[size_t(j0 + jj) * S + s]);
                     const float qv = clamp_msg(lv - r);
                     bits ^= int32_t(qv < 0.f) | (int32_t(lv < 0.f) << 1);
@@ -470,7 +475,7 @@ __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict_
             for (int jj = 0; jj < C; jj++) {
                 if (jj < dc) {
                     const int v = wave_uniform(cload(G.col_idx + (j0 + jj)));
-                    const float lv = L[size_t(v) * S + s];
+                    const float lv = Codec<Post<M>::kMsg>::dec(L[size_t(v) * S + s]);
                     const float r = first ? 0.f : Codec<M>::dec(R[size_t(j0 + jj) * S + s]);
                     const float qv = clamp_msg(lv - r);
                     neg |= uint32_t(qv < 0.f) << jj;
@@ -536,12 +541,21 @@ __device__ __forceinline__ void bit_item(const EngGraph &G, int v, int s0, int32
     const int a = UNIFORM ? wave_uniform(cload(G.col_ptr + (v))) : cload(G.col_ptr + (v));
     const int b = UNIFORM ? wave_uniform(cload(G.col_ptr + (v + 1))) : cload(G.col_ptr + (v + 1));
     bit_sum<M, V, UNIFORM>(G.csc_to_csr, a, b, R, S, s0, sum);
+    using PT = typename Post<M>::T;
+    PT *post = static_cast<PT *>(G.post);
     if (all) {
-        store_vec<kF32, V>(G.lpost + size_t(v) * S + s0, sum);
+        store_post<V>(post + size_t(v) * S + s0, sum);
     } else {
 #pragma unroll
         for (int k = 0; k < V; k++)
-            if (adv[k]) gmem(G.lpost)[size_t(v) * S + s0 + k] = sum[k];
+            if (adv[k]) store_post1(post + size_t(v) * S + s0 + k, sum[k]);
+    }
+    if constexpr (kPost16<M>) {
+        int32_t w[V];
+        load_i32<V>(G.want32 + s0, w);
+#pragma unroll
+        for (int k = 0; k < V; k++)
+            if (adv[k] && w[k]) gmem(G.lpost)[size_t(v) * S + s0 + k] = sum[k];
     }
 }
 
@@ -637,6 +651,13 @@ __global__ __launch_bounds__(256) void eng_advance(const EngGraph *__restrict__ 
 // accessed in contiguous runs (the list is in slot order within each run).
 constexpr int kTile = 64;
 
+// Posterior of bit v in slot s from the check pass's storage.
+__device__ __forceinline__ float post_value(const EngGraph &G, int v, int s) {
+    const size_t at = size_t(v) * G.S + s;
+    return G.post16 ? float(gmem(static_cast<const _Float16 *>(G.post))[at])
+                    : gmem(static_cast<const float *>(G.post))[at];
+}
+
 __global__ __launch_bounds__(256) void eng_turnover(const EngGraph *__restrict__ graphs, int32_t ngraphs,
                                                     int32_t *__restrict__ counters) {
     __shared__ int32_t base[kMaxGraphs + 1];
@@ -703,7 +724,8 @@ __global__ __launch_bounds__(256) void eng_turnover(const EngGraph *__restrict__
             // posterior rows of the listed slots -> tile[v][entry]
             for (int k = r; k < kTile; k += 4) {
                 const int v = v0 + k;
-                if (v < n && bits_of[l]) tile[k][l] = gmem(G.lpost)[size_t(v) * S + slot_of[l]];
+                if (v < n && bits_of[l])
+                    tile[k][l] = lout_of[l] ? gmem(G.lpost)[size_t(v) * S + slot_of[l]] : post_value(G, v, slot_of[l]);
             }
             __syncthreads();
             // tile -> each stopped frame's output row
@@ -723,7 +745,7 @@ __global__ __launch_bounds__(256) void eng_turnover(const EngGraph *__restrict__
             for (int k = r; k < kTile; k += 4) {
                 const int v = v0 + l;
                 const float *src = src_of[k];
-                if (v < n && src) tile[l][k] = gmem(src)[v];
+                if (v < n && src) tile[l][k] = canon_llr(gmem(src)[v]);
             }
             __syncthreads();
             // tile -> channel rows of the slots; the posterior entries start as
@@ -733,7 +755,8 @@ __global__ __launch_bounds__(256) void eng_turnover(const EngGraph *__restrict__
                 if (v < n && src_of[l]) {
                     const size_t at = size_t(v) * S + slot_of[l];
                     gmem(G.lch)[at] = tile[k][l];
-                    gmem(G.lpost)[at] = tile[k][l];
+                    if (G.post16) *gmem(static_cast<_Float16 *>(G.post) + at) = post16_enc(tile[k][l]);
+                    else *gmem(static_cast<float *>(G.post) + at) = tile[k][l];
                 }
             }
         }
@@ -786,9 +809,11 @@ __global__ __launch_bounds__(1024) void eng_admit(const EngGraph *__restrict__ g
         }
         if (i < taken) {
             const int32_t qi = head + i;
-            store_frame(G.slot_desc + s, load_frame(G.queue + qi % G.cap));
+            const EngFrame fr = load_frame(G.queue + qi % G.cap);
+            store_frame(G.slot_desc + s, fr);
             gmem(G.slot_t)[s] = 0;
             gmem(G.fail)[s] = 0;
+            gmem(G.want32)[s] = fr.llr_out != nullptr;
         } else {
             gmem(G.slot_t)[s] = -1;
         }
@@ -831,6 +856,7 @@ __global__ __launch_bounds__(1024) void eng_admit(const EngGraph *__restrict__ g
         store_frame(G.slot_desc + dst, load_frame(G.slot_desc + src));
         gmem(G.slot_t)[dst] = gmem(G.slot_t)[src];
         gmem(G.fail)[dst] = gmem(G.fail)[src];
+        gmem(G.want32)[dst] = gmem(G.want32)[src];
         gmem(G.slot_t)[src] = -1;
     }
     if (tid == 0) {
@@ -840,8 +866,8 @@ __global__ __launch_bounds__(1024) void eng_admit(const EngGraph *__restrict__ g
 }
 
 // Copy the state columns of the repacked frames: every message row (edge),
-// channel-LLR row and posterior row of the graph, slot move_src[k] to slot
-// move_dst[k].  Sources lie above every destination, so the copies are
+// channel-LLR row and posterior row of the graph (both posterior copies for
+// 16-bit messages), slot move_src[k] to slot move_dst[k].  Sources lie above every destination, so the copies are
 // independent.  MSG_BYTES is the stored message size.
 template <int MSG_BYTES>
 __global__ __launch_bounds__(256) void eng_repack_move(const EngGraph *__restrict__ graphs, int32_t ngraphs,
@@ -856,7 +882,7 @@ __global__ __launch_bounds__(256) void eng_repack_move(const EngGraph *__restric
             const int c = threadIdx.x;
             const int32_t moves = gmem(counters)[ctr_moves(ngraphs, c)];
             nm[c] = moves;
-            const long long rows = (long long)graphs[c].E + 2 * (long long)graphs[c].n;
+            const long long rows = (long long)graphs[c].E + (graphs[c].post16 ? 3 : 2) * (long long)graphs[c].n;
             items = moves > 0 ? (rows + kMoveRows - 1) / kMoveRows : 0;
         }
         scan_items<long long>(items, ngraphs, base);
@@ -870,7 +896,7 @@ __global__ __launch_bounds__(256) void eng_repack_move(const EngGraph *__restric
         const int moves = nm[c];
         const int64_t E = G.E, n = G.n, S = G.S;
         const int64_t r0 = (u - base[c]) * kMoveRows;
-        const int rcount = int(min(int64_t(kMoveRows), E + 2 * n - r0));
+        const int rcount = int(min(int64_t(kMoveRows), E + (G.post16 ? 3 : 2) * n - r0));
         for (int idx = threadIdx.x; idx < rcount * moves; idx += blockDim.x) {
             const int rr = idx / moves;
             const int k = idx - rr * moves;
@@ -879,9 +905,14 @@ __global__ __launch_bounds__(256) void eng_repack_move(const EngGraph *__restric
             if (row < E) {
                 auto R = gmem(static_cast<MsgWord *>(G.r));
                 R[row * S + dst] = R[row * S + src];
+            } else if (row >= E + n && row < E + 2 * n && G.post16) {
+                auto P = gmem(static_cast<uint16_t *>(G.post));
+                const int64_t v = row - E - n;
+                P[v * S + dst] = P[v * S + src];
             } else {
+                // channel rows, then the fp32 posterior (after the fp16 rows when there are some)
                 auto L = gmem(row < E + n ? G.lch : G.lpost);
-                const int64_t v = row < E + n ? row - E : row - E - n;
+                const int64_t v = row < E + n ? row - E : row - E - (G.post16 ? 2 : 1) * n;
                 L[v * S + dst] = L[v * S + src];
             }
         }
@@ -1197,7 +1228,8 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
 
     // device layout: per graph state, then counters, turnover list, graph table
     size_t off = 0;
-    struct Offs { size_t lch, lpost, r, t, fail, desc, aggd, aggpre, aggbits, queue, list, msrc, mdst; };
+    struct Offs { size_t lch, lpost, post, r, t, fail, want, desc, aggd, aggpre, aggbits, queue, list, msrc, mdst; };
+    const bool post16 = e->msg == kF16 || e->msg == kBF16;
     std::vector<Offs> go(static_cast<size_t>(ngraphs));
     for (int32_t c = 0; c < ngraphs; c++) {
         const ldpc_graph *g = graphs[c];
@@ -1207,9 +1239,12 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
         Offs &o = go[size_t(c)];
         o.lch = off;     off = al256(off + size_t(g->n) * S * 4);
         o.lpost = off;   off = al256(off + size_t(g->n) * S * 4);
+        o.post = o.lpost;
+        if (post16) { o.post = off; off = al256(off + size_t(g->n) * S * 2); }
         o.r = off;       off = al256(off + size_t(g->E) * S * msg_bytes);
         o.t = off;       off = al256(off + size_t(2) * S * 4);
         o.fail = off;    off = al256(off + size_t(S) * 4);
+        o.want = off;    off = al256(off + size_t(S) * 4);
         o.desc = off;    off = al256(off + size_t(S) * sizeof(EngFrame));
         o.aggd = off;    off = al256(off + size_t(g->hub_chunks) * S * 4);
         o.aggpre = off;  off = al256(off + size_t(g->hub_chunks) * S * 4);
@@ -1244,6 +1279,9 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
         for (int k = 0; k <= ldpc::kNumClasses; k++) G.class_begin[k] = g->class_begin[k];
         G.lch = reinterpret_cast<float *>(base + o.lch);
         G.lpost = reinterpret_cast<float *>(base + o.lpost);
+        G.post = base + o.post;
+        G.post16 = post16 ? 1 : 0;
+        G.want32 = reinterpret_cast<int32_t *>(base + o.want);
         G.r = base + o.r;
         G.slot_t = reinterpret_cast<int32_t *>(base + o.t);
         G.fail = reinterpret_cast<int32_t *>(base + o.fail);
@@ -1267,7 +1305,8 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
         // every slot starts empty, with defined message state
         if ((err = hipMemsetAsync(base + o.lch, 0, o.t - o.lch, e->stream)) != hipSuccess ||
             (err = hipMemsetAsync(G.slot_t, 0xff, size_t(2) * G.S * 4, e->stream)) != hipSuccess ||
-            (err = hipMemsetAsync(G.fail, 0, size_t(G.S) * 4, e->stream)) != hipSuccess)
+            (err = hipMemsetAsync(G.fail, 0, size_t(G.S) * 4, e->stream)) != hipSuccess ||
+            (err = hipMemsetAsync(G.want32, 0, size_t(G.S) * 4, e->stream)) != hipSuccess)
             return hip_fail(e, "ldpc_engine_create: hipMemsetAsync", err);
     }
     if ((err = hipMemsetAsync(e->d_counters, 0, size_t(ngraphs) * kCounterInts * 4, e->stream)) != hipSuccess ||

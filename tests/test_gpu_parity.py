@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import ldpc_inputs as li
+import oracle
 from parity import compare, gpu_decode
 
 pytestmark = pytest.mark.gpu
@@ -98,6 +99,27 @@ def test_degree_classes_and_segmented_rows():
     _announce("classes", frames=70, max_deg=300)
     print(compare(code, llr, 25))
     compare(code, llr, 3, early_stop=False, posterior_all=True)
+
+
+def test_degree_classes_converging_frames():
+    """Rows of every register and chunk class (degrees 3..64) on frames that
+    converge at different iterations, so the syndrome fold of each class
+    decides when a frame stops."""
+    rng = np.random.default_rng(21)
+    cdeg = np.concatenate([[64, 48, 33, 20, 17], rng.integers(3, 17, size=115)])
+    E = int(cdeg.sum())
+    n = 2 * len(cdeg) + 400
+    bdeg = np.full(n, E // n)
+    bdeg[: E - bdeg.sum()] += 1
+    code = li.socket_code(bdeg, cdeg, seed=22)
+    sigma2 = li.ebn0_to_sigma2(3.5, code.rate)
+    llr = li.awgn_llr(n, 130, sigma2, seed=23)
+    _announce("classes-converging", frames=130, max_deg=64)
+    st = compare(code, llr, 30)
+    print(st)
+    ora = oracle.decode(code, llr, 30)
+    assert (ora["ok"] == 1).sum() >= 20, "too few converging frames to exercise early stopping"
+    assert len(np.unique(ora["iters"][ora["ok"] == 1])) >= 3
 
 
 def test_degree_one_checks_and_empty_nodes():

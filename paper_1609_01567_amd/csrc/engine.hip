@@ -921,6 +921,18 @@ __global__ __launch_bounds__(256) void eng_repack_move(const EngGraph *__restric
 
 __global__ void eng_publish(int32_t *tail, int32_t value) { *tail = value; }
 
+// Between steps: apply the last admissions to the queue heads and empty the
+// turnover lists, as the first bit pass of a step does (used before an
+// admission outside the step sequence).
+__global__ void eng_open_lists(const EngGraph *__restrict__ graphs, int32_t ngraphs) {
+    if (int(threadIdx.x) < ngraphs) {
+        const EngGraph &H = graphs[threadIdx.x];
+        *gmem(H.head) += *gmem(H.taken);
+        *gmem(H.taken) = 0;
+        *gmem(H.list_count) = 0;
+    }
+}
+
 }  // namespace
 
 // ===================================================================== host
@@ -1530,12 +1542,46 @@ extern "C" ldpc_status ldpc_engine_poll(ldpc_engine *e, int64_t *retired, int64_
     return LDPC_OK;
 }
 
+namespace {
+
+// Admit queued frames into empty slots now, outside the step sequence: the
+// bookkeeping that ends a step (list the empty slots, load the queued frames'
+// channel LLRs, install them), so that a run starting on empty pools does not
+// spend its first step's iterations on them.  Call at a step boundary only.
+hipError_t admit_now(ldpc_engine *e) {
+    hipStream_t st = e->stream;
+    hipLaunchKernelGGL(eng_open_lists, dim3(1), dim3(64), 0, st, e->d_graphs, e->ngraphs);
+    hipLaunchKernelGGL(eng_advance, dim3(unsigned((e->total_slots + 255) / 256)), dim3(256), 0, st, e->d_graphs,
+                       e->pre_slots, e->T, e->d_counters, int32_t(0));
+    hipLaunchKernelGGL(eng_turnover, dim3(unsigned(kTurnoverBlocks)), dim3(256), 0, st, e->d_graphs, e->ngraphs,
+                       e->d_counters);
+    hipLaunchKernelGGL(eng_admit<false>, dim3(unsigned(e->ngraphs)), dim3(1024), 0, st, e->d_graphs);
+    return hipGetLastError();
+}
+
+}  // namespace
+
 extern "C" ldpc_status ldpc_engine_run(ldpc_engine *e, int32_t max_replays, int64_t *replays_out) {
     if (!e || max_replays < 0) { set_error("ldpc_engine_run: bad argument"); return LDPC_E_INVAL; }
     int64_t done = 0;
     for (;;) {
         ldpc_status st = ldpc_engine_poll(e, nullptr, nullptr);
         if (st != LDPC_OK) return st;
+        if (done == 0) {
+            // every submitted frame still queued (none in a slot): admit before the first step
+            bool empty = true, queued = false;
+            for (int32_t c = 0; c < e->ngraphs; c++) {
+                empty &= e->head_seen[size_t(c)] == e->retired_seen[size_t(c)];
+                queued |= e->submitted[size_t(c)] > e->head_seen[size_t(c)];
+            }
+            if (empty && queued) {
+                const hipError_t err = admit_now(e);
+                if (err != hipSuccess) {
+                    set_error(std::string("ldpc_engine_run: ") + hipGetErrorString(err));
+                    return LDPC_E_DEVICE;
+                }
+            }
+        }
         bool finished = true;
         for (int32_t c = 0; c < e->ngraphs; c++)
             if (e->retired_seen[size_t(c)] < e->submitted[size_t(c)]) finished = false;

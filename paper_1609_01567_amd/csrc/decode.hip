@@ -212,8 +212,35 @@ __global__ __launch_bounds__(256) void check_chunk_kernel(
     }
 }
 
-// Check pass for long rows (degree > 128): one workgroup of four wavefronts per
-// (row, 64-slot group).  The row is cut into 32-edge chunks; each chunk's
+// Check pass for rows of 129..512 edges: one workgroup of sixteen wavefronts
+// per (row, 64-slot group), one 32-edge chunk per wavefront, chunk aggregates
+// exchanged through LDS (wide_row); every input is read once.
+template <int M, int MODE, int RULE>
+__global__ __launch_bounds__(1024) void check_wide_kernel(
+    const int32_t *__restrict__ rd, const int32_t *__restrict__ col_idx, int32_t nrows,
+    const CheckL<M, MODE> *__restrict__ L, typename Codec<M>::T *__restrict__ R, const int32_t *__restrict__ iters,
+    int32_t *__restrict__ fail, int32_t S, int32_t groups, int32_t syn_iter, float rp) {
+    __shared__ ChunkShare<1, kWideWaves> sh;
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_uniform(threadIdx.x >> 6);
+    const int g = blockIdx.x % groups;
+    const int rk = blockIdx.x / groups;
+    if (rk >= nrows) return;
+    const int s = g * 64 + lane;
+    const bool active = iters[s] == 0;
+    if (__ballot(active) == 0) return;   // same slots in every wave: uniform over the block
+    const int e0 = wave_uniform(rd[2 * rk]);
+    const int d = wave_uniform(rd[2 * rk + 1]);
+    SlotSrc<1> src;
+    src.alt[0] = false;
+    src.any = false;
+    constexpr int IN = MODE == kIter ? kInSteady : kInFirst;
+    const bool syn = wide_row<M, kWideChunk, IN, RULE>(col_idx, e0, d, L, R, S, s, src, active, sh, wv, lane, rp);
+    if (MODE == kIter && wv == 0 && syn_iter > 0 && active && syn && fail[s] != syn_iter) fail[s] = syn_iter;
+}
+
+// Check pass for rows longer than 512 edges: one workgroup of four wavefronts
+// per (row, 64-slot group).  The row is cut into 32-edge chunks; each chunk's
 // combined u (its D aggregate), sign parity and syndrome parity go to scratch,
 // one wavefront scans the chunk aggregates into per-chunk exclusive values,
 // and each chunk is then finished with a local prefix/suffix pass.
@@ -820,18 +847,34 @@ void launch_hub(const ldpc_graph *g, int mode, const void *L, const Bufs &b, int
     const int32_t nrows = g->class_begin[ldpc::kClassHub + 1] - g->class_begin[ldpc::kClassHub];
     if (nrows == 0) return;
     const int32_t groups = S / 64;
-    const unsigned blocks = unsigned(int64_t(nrows) * groups);
     using T = typename Codec<M>::T;
     T *R = static_cast<T *>(b.r);
     const int32_t *rd = g->d_class_rd + 2 * g->class_begin[ldpc::kClassHub];
-    if (mode == kFirst)
-        hipLaunchKernelGGL((check_hub_kernel<M, kFirst, RULE>), dim3(blocks), dim3(256), 0, st, rd, g->d_col_idx,
-                           nrows, g->d_hub_chunk_base, static_cast<const CheckL<M, kFirst> *>(L), R, b.iters, b.fail, S, groups, 0, b.aggd, b.aggpre,
-                           b.aggbits, rp);
-    else
-        hipLaunchKernelGGL((check_hub_kernel<M, kIter, RULE>), dim3(blocks), dim3(256), 0, st, rd, g->d_col_idx,
-                           nrows, g->d_hub_chunk_base, static_cast<const CheckL<M, kIter> *>(L), R, b.iters, b.fail, S, groups, syn_iter, b.aggd, b.aggpre,
-                           b.aggbits, rp);
+    // rows above kWideRowMax lead the class (longest first): segmented path
+    const int32_t nseg = g->hub_seg_rows, nwide = nrows - nseg;
+    if (nseg > 0) {
+        const unsigned blocks = unsigned(int64_t(nseg) * groups);
+        if (mode == kFirst)
+            hipLaunchKernelGGL((check_hub_kernel<M, kFirst, RULE>), dim3(blocks), dim3(256), 0, st, rd, g->d_col_idx,
+                               nseg, g->d_hub_chunk_base, static_cast<const CheckL<M, kFirst> *>(L), R, b.iters,
+                               b.fail, S, groups, 0, b.aggd, b.aggpre, b.aggbits, rp);
+        else
+            hipLaunchKernelGGL((check_hub_kernel<M, kIter, RULE>), dim3(blocks), dim3(256), 0, st, rd, g->d_col_idx,
+                               nseg, g->d_hub_chunk_base, static_cast<const CheckL<M, kIter> *>(L), R, b.iters,
+                               b.fail, S, groups, syn_iter, b.aggd, b.aggpre, b.aggbits, rp);
+    }
+    if (nwide > 0) {
+        const unsigned blocks = unsigned(int64_t(nwide) * groups);
+        const dim3 block(64 * kWideWaves);
+        if (mode == kFirst)
+            hipLaunchKernelGGL((check_wide_kernel<M, kFirst, RULE>), dim3(blocks), block, 0, st, rd + 2 * nseg,
+                               g->d_col_idx, nwide, static_cast<const CheckL<M, kFirst> *>(L), R, b.iters, b.fail, S,
+                               groups, 0, rp);
+        else
+            hipLaunchKernelGGL((check_wide_kernel<M, kIter, RULE>), dim3(blocks), block, 0, st, rd + 2 * nseg,
+                               g->d_col_idx, nwide, static_cast<const CheckL<M, kIter> *>(L), R, b.iters, b.fail, S,
+                               groups, syn_iter, rp);
+    }
 }
 
 template <int M, int V, int RULE>

@@ -591,4 +591,48 @@ __device__ __forceinline__ void chunk_context(const ChunkShare<V, ENTRIES> &sh, 
     for (int k = 0; k < V; k++) { parity[k] = (tot >> k) & 1u; syn[k] = int((tot >> (8 + k)) & 1u); }
 }
 
+// Rows of up to kWideWaves chunks of C edges on one workgroup of kWideWaves
+// wavefronts, one chunk each, for one 64-slot group at one slot per lane: the
+// chunk aggregates, sign parities and syndrome parities go through LDS, and
+// each wavefront finishes its chunk from the inputs it still holds, so every
+// input is read once.  Every wavefront of the workgroup must call it (it
+// synchronises the workgroup).  Returns the row's syndrome parity for the
+// lane (meaningful in wavefronts wv < number of chunks).
+constexpr int kWideWaves = 16;
+constexpr int kWideChunk = 32;   // edges per wavefront: rows of up to 512 edges
+
+template <int M, int C, int IN, int RULE, typename LT>
+__device__ __forceinline__ bool wide_row(const int32_t *__restrict__ col_idx, int e0, int d,
+                                         const LT *__restrict__ L, typename Codec<M>::T *__restrict__ R, int32_t S,
+                                         int s, const SlotSrc<1> &src, bool active, ChunkShare<1, kWideWaves> &sh,
+                                         int wv, int lane, float rp) {
+    using Rule = CheckRule<RULE>;
+    const int nch = (d + C - 1) / C;
+    const int dc = min(C, d - wv * C);
+    float u[C][1], suf[C][1], agg[1];
+    uint32_t par[1];
+    int syn[1];
+    const bool mine = wv < nch && active;
+    if (mine) {
+        chunk_load<M, 1, C, IN, RULE>(col_idx, e0 + wv * C, dc, L, R, S, s, src, u, suf, agg, par, syn);
+    } else {
+        agg[0] = Rule::identity();
+        par[0] = 0u;
+        syn[0] = 0;
+    }
+    if (wv < nch) {
+        sh.agg[wv][lane][0] = agg[0];
+        sh.bits[wv][lane] = pack_bits<1>(par, syn);
+    }
+    __syncthreads();
+    int syn_row[1] = {0};
+    if (mine) {
+        float pre[1], post[1];
+        uint32_t parity[1];
+        chunk_context<1, kWideWaves, RULE>(sh, 0, nch, wv, lane, pre, post, parity, syn_row);
+        chunk_store<M, 1, C, RULE>(e0 + wv * C, dc, u, suf, pre, post, parity, R, S, s, rp);
+    }
+    return syn_row[0] != 0;
+}
+
 }  // namespace ldpc_dev

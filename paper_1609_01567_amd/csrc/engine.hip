@@ -62,6 +62,7 @@ struct EngGraph {
     const int32_t *class_rd;   // per class row (class order): first edge, degree
     int32_t n, S, E;
     int32_t post16;       // the posterior storage is fp16 (16-bit message formats)
+    int32_t hub_seg;      // rows of the long class on the segmented path (the first ones); the rest are wide rows
     int32_t class_begin[ldpc::kNumClasses + 1];
     float *lch, *lpost;
     void *post;           // posterior in the check pass's storage (Post<M>); lpost for 32/8-bit messages
@@ -203,7 +204,8 @@ struct Work {
     int32_t rpw[kMaxGraphs];
 };
 constexpr int kMaxPack = 16;
-constexpr int kBitItems = -1;   // `cls` value for the bit pass: items are bits
+constexpr int kBitItems = -1;    // `cls` value for the bit pass: items are bits
+constexpr int kWideItems = -2;   // `cls` value for the wide rows of the long class (after its segmented rows)
 
 // PM (packing mode): kPackNone counts every graph unpacked; kPackAll packs the
 // graphs whose extent allows it; kPackOnlyFlat / kPackOnlyPacked keep only the
@@ -231,7 +233,11 @@ __device__ __forceinline__ void build_work(const EngGraph *__restrict__ graphs, 
             const EngGraph &G = graphs[c];
             const int32_t x = gmem(counters)[ctr_extent(ngraphs, c)];
             const int32_t gr = (x + unit - 1) / unit;
-            const int32_t units = cls == kBitItems ? G.n : G.class_begin[cls + 1] - G.class_begin[cls];
+            const int32_t hubs = G.class_begin[ldpc::kClassHub + 1] - G.class_begin[ldpc::kClassHub];
+            const int32_t units = cls == kBitItems ? G.n
+                                  : cls == kWideItems ? hubs - G.hub_seg
+                                  : cls == ldpc::kClassHub ? G.hub_seg
+                                  : G.class_begin[cls + 1] - G.class_begin[cls];
             int32_t rpw = 1;
             if (PM != kPackNone && x > 0)
                 while (rpw < kMaxPack && (unit / (2 * rpw)) >= x) rpw *= 2;   // unit = 64 V slots per wavefront
@@ -503,6 +509,47 @@ __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict_
         }
         // the next item's wavefront 0 rewrites total_bits only after the first
         // barrier of that item, which every wavefront reaches after reading it here
+    }
+}
+
+// Rows of the long class up to kWideRowMax edges (after its segmented rows):
+// one workgroup of 16 wavefronts per (row, 64 slots), one 32-edge chunk per
+// wavefront, chunk aggregates through LDS (wide_row).
+template <int M, int RULE>
+__global__ __launch_bounds__(1024) void eng_check_wide(const EngGraph *__restrict__ graphs, int32_t ngraphs,
+                                                       const int32_t *__restrict__ counters, int32_t T,
+                                                       int32_t early, int32_t par, float rp) {
+    using MT = typename Codec<M>::T;
+    __shared__ ChunkShare<1, kWideWaves> sh;
+    __shared__ Work w;
+    build_work(graphs, ngraphs, counters, kWideItems, 64, 1, w);
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_uniform(threadIdx.x >> 6);
+    const int total = wave_uniform(w.p[ngraphs]);
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {     // uniform over the workgroup
+        const int c = wave_uniform(work_graph(w, ngraphs, u));
+        const EngGraph &G = graphs[c];
+        const int32_t S = G.S;
+        const int groups = wave_uniform(w.groups[c]);
+        const int local = u - wave_uniform(w.p[c]);
+        const int g = local % groups;
+        const int rk = G.hub_seg + local / groups;
+        const int s = g * 64 + lane;
+        const int32_t ts = gmem(G.slot_t)[par * S + s];
+        const bool active = ts >= 0 && ts < kStopped;
+        if (__ballot(active) == 0) continue;   // same slots in every wavefront: uniform over the workgroup
+        const bool syn_on = active && ts >= 1 && (early || ts == T);
+        SlotSrc<1> src;
+        src.alt[0] = active && ts == 0;
+        src.any = src.alt[0];
+        const u32x2 rdv = cload(reinterpret_cast<const u32x2 *>(G.class_rd) + G.class_begin[ldpc::kClassHub] + rk);
+        const int e0 = wave_uniform(int(rdv.x));
+        const int d = wave_uniform(int(rdv.y));
+        const bool syn = wide_row<M, kWideChunk, kInMixed, RULE>(
+            G.col_idx, e0, d, static_cast<const typename Post<M>::T *>(G.post), static_cast<MT *>(G.r), S, s, src,
+            active, sh, wv, lane, rp);
+        if (wv == 0 && syn_on && syn && gmem(G.fail)[s] != ts) gmem(G.fail)[s] = ts;
+        __syncthreads();   // the shared aggregates are reused by the next item
     }
 }
 
@@ -966,9 +1013,9 @@ struct ldpc_engine {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     Prefix pre_slots;
-    bool has_rows[3] = {false, false, false}, has_hub = false;
-    int64_t bit_waves = 0, hub_blocks = 0, total_slots = 0, row_waves[3] = {0, 0, 0};   // with every slot occupied
-    unsigned grid_rows[3] = {1, 1, 1}, grid_hub = 1, grid_bit = 1;   // workgroups per launch (grid-stride)
+    bool has_rows[3] = {false, false, false}, has_hub = false, has_wide = false;
+    int64_t bit_waves = 0, hub_blocks = 0, wide_blocks = 0, total_slots = 0, row_waves[3] = {0, 0, 0};   // with every slot occupied
+    unsigned grid_rows[3] = {1, 1, 1}, grid_hub = 1, grid_wide = 1, grid_bit = 1;   // workgroups per launch (grid-stride)
     unsigned grid_packed = 256;      // packed row items: few rows per graph once drained
     unsigned grid_chunk_narrow = 1;  // chunked rows of drained pools at one slot per lane
     int64_t chunk_rows = 0;          // rows of the chunked class over all graphs
@@ -1030,6 +1077,9 @@ void enqueue_step_rule(ldpc_engine *e) {
                                    st, e->d_graphs, ng, e->d_counters, int32_t(ldpc::kClassD128), e->T, early, par,
                                    rp, wide_unit);
         }
+        if (e->has_wide)
+            hipLaunchKernelGGL((eng_check_wide<M, RULE>), dim3(e->grid_wide), dim3(64 * kWideWaves), 0, st,
+                               e->d_graphs, ng, e->d_counters, e->T, early, par, rp);
         if (e->has_hub)
             hipLaunchKernelGGL((eng_check_hub<M, RULE>), dim3(e->grid_hub), dim3(256), 0, st, e->d_graphs, ng,
                                e->d_counters, e->T, early, par, rp);
@@ -1090,9 +1140,9 @@ int grid_factor() {
 
 template <int M, int V>
 void size_grids(ldpc_engine *e, int cus) {
-    auto fit = [cus](const void *k, int64_t need) -> unsigned {
+    auto fit = [cus](const void *k, int64_t need, int block = 256) -> unsigned {
         int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, 0) != hipSuccess || per_cu < 1) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, block, 0) != hipSuccess || per_cu < 1) {
             (void)hipGetLastError();
             per_cu = 1;
         }
@@ -1119,6 +1169,7 @@ void size_grids(ldpc_engine *e, int cus) {
                                                         kSplitNarrow>),
                                    std::max<int64_t>(1, e->chunk_rows * (V / 2)));
     e->grid_hub = fit(reinterpret_cast<const void *>(&eng_check_hub<M, kRuleSP>), e->hub_blocks);
+    e->grid_wide = fit(reinterpret_cast<const void *>(&eng_check_wide<M, kRuleSP>), e->wide_blocks, 64 * kWideWaves);
     e->grid_bit = fit(reinterpret_cast<const void *>(&eng_bit<M, V>), (e->bit_waves + 3) / 4);
 }
 
@@ -1293,6 +1344,7 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
         G.lpost = reinterpret_cast<float *>(base + o.lpost);
         G.post = base + o.post;
         G.post16 = post16 ? 1 : 0;
+        G.hub_seg = g->hub_seg_rows;
         G.want32 = reinterpret_cast<int32_t *>(base + o.want);
         G.r = base + o.r;
         G.slot_t = reinterpret_cast<int32_t *>(base + o.t);
@@ -1346,11 +1398,13 @@ extern "C" ldpc_status ldpc_engine_create(const ldpc_graph *const *graphs, int32
     for (int32_t c = 0; c < ngraphs; c++) {
         const ldpc_graph *g = graphs[c];
         const int64_t hubs = g->class_begin[ldpc::kClassHub + 1] - g->class_begin[ldpc::kClassHub];
-        e->hub_blocks += hubs * (e->S[size_t(c)] / 64);
+        e->hub_blocks += int64_t(g->hub_seg_rows) * (e->S[size_t(c)] / 64);
+        e->wide_blocks += (hubs - g->hub_seg_rows) * (e->S[size_t(c)] / 64);
         e->bit_waves += int64_t(g->n) * (e->S[size_t(c)] / (64 * V));
         e->pre_slots.p[c + 1] = e->pre_slots.p[c] + e->S[size_t(c)];
     }
     e->has_hub = e->hub_blocks > 0;
+    e->has_wide = e->wide_blocks > 0;
     {
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {

@@ -175,6 +175,7 @@ extern "C" ldpc_status ldpc_graph_create(int32_t m, int32_t n, int64_t nnz, cons
         for (int32_t r : per_class[ldpc::kClassHub]) {
             const int32_t d = g->row_ptr[r + 1] - g->row_ptr[r];
             g->hub_chunk_base.push_back(g->hub_chunk_base.back() + (d + ldpc::kHubChunk - 1) / ldpc::kHubChunk);
+            if (d > ldpc::kWideRowMax) g->hub_seg_rows++;   // longest first: these lead the class
         }
         g->hub_chunks = g->hub_chunk_base.back();
     } catch (const std::bad_alloc &) {

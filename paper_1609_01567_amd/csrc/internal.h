@@ -17,6 +17,10 @@ namespace ldpc {
 // into 32-edge chunks with aggregates in global scratch (no degree bound).
 enum CheckClass : int { kClassD8 = 0, kClassD16 = 1, kClassD128 = 2, kClassHub = 3, kNumClasses = 4 };
 constexpr int kHubChunk = 32;   // edges per chunk on the segmented path
+// Rows of the long class up to this degree take the LDS path instead (one
+// workgroup of 16 wavefronts per row and slot group, one 32-edge chunk each);
+// longer rows the segmented path.
+constexpr int kWideRowMax = 512;
 
 inline int check_class_of(int d) {
     return d <= 8 ? kClassD8 : d <= 16 ? kClassD16 : d <= 128 ? kClassD128 : kClassHub;
@@ -69,6 +73,7 @@ struct ldpc_graph {
     // Segmented path: first chunk index of each hub row (in class order) and total chunks.
     std::vector<int32_t> hub_chunk_base;             // [#hub rows + 1]
     int64_t hub_chunks = 0;
+    int32_t hub_seg_rows = 0;                        // hub rows (the first, longest ones) above kWideRowMax
 
     // Device copies.
     int32_t *d_row_ptr = nullptr, *d_col_idx = nullptr;

@@ -101,6 +101,23 @@ def test_degree_classes_and_segmented_rows():
     compare(code, llr, 3, early_stop=False, posterior_all=True)
 
 
+def test_long_rows_wide_and_segmented_paths():
+    """Rows just inside and just beyond the LDS path's 512-edge limit, and far
+    beyond it (segmented path), with iterations fixed and with early stop."""
+    rng = np.random.default_rng(31)
+    cdeg = np.concatenate([[1200, 700, 513, 512, 300, 129], rng.integers(3, 12, size=200)])
+    E = int(cdeg.sum())
+    n = 1500
+    bdeg = np.full(n, E // n)
+    bdeg[: E - bdeg.sum()] += 1
+    code = li.socket_code(bdeg, cdeg, seed=32)
+    assert sorted(code.check_degrees())[-4:] == [512, 513, 700, 1200]
+    llr = li.awgn_llr(n, 70, li.ebn0_to_sigma2(6.0, code.rate), seed=33)
+    _announce("long-rows", frames=70, max_deg=1200)
+    compare(code, llr, 4, early_stop=False, posterior_all=True)
+    print(compare(code, llr, 20))
+
+
 def test_degree_classes_converging_frames():
     """Rows of every register and chunk class (degrees 3..64) on frames that
     converge at different iterations, so the syndrome fold of each class

@@ -141,3 +141,15 @@ def first_iteration_bound(code, llr, lmax: float = 64.0):
     bound = np.zeros((F, code.n))
     np.add.at(bound.T, cols, excl.T)
     return bound
+
+
+def first_iteration_input_bound(code, llr, lmax: float = 64.0):
+    """[F][n]: sum over the checks of v of the sum of min(lmax, |Lch|) over the check's other bits."""
+    a = np.minimum(np.abs(llr.astype(np.float64)), lmax)          # [F][n]
+    rows, cols = code.rows.astype(np.int64), code.cols.astype(np.int64)
+    row_sum = np.zeros((llr.shape[0], code.m))
+    np.add.at(row_sum.T, rows, a[:, cols].T)                       # per check: sum over its bits
+    other = row_sum[:, rows] - a[:, cols]                          # per edge: the other bits of its check
+    bound = np.zeros((llr.shape[0], code.n))
+    np.add.at(bound.T, cols, other.T)
+    return bound

@@ -5,10 +5,14 @@ clamped channel LLRs of the other bits of c, and the magnitude of the exact
 check combination never exceeds the smallest magnitude among its inputs.  So
 |R(c->v)| <= min(64, min over v' in N(c)\\{v} of |Lch(v')|).  Storing R rounds it once
 to the nearest value of the storage format (relative error at most u = 2^-11
-for FP16, 2^-8 for BF16), and the posterior sums the stored messages in FP32.
-Against the FP64 oracle, the posterior after one iteration therefore stays
-within the FP32 parity bar plus u times the sum of those minima over the
-checks of v.
+for FP16, 2^-8 for BF16).  With 16-bit messages the check pass also reads the
+channel LLRs from their FP16 copy (relative error at most 2^-11 each), and the
+check combination changes by at most the sum of its inputs' changes (each
+two-input step a (+) b has |d(a (+) b)/da| <= 1).  The posterior sums the
+stored messages in FP32.  Against the FP64 oracle, the posterior after one
+iteration therefore stays within the FP32 parity bar plus, over the checks of
+v, u times the smallest other input plus 2^-11 times the sum of the other
+(clamped) inputs.
 Later iterations have no such closed bound; the decodes must still be
 self-consistent (flags agree with the syndrome of the returned bits) and
 independent of the tile shape.
@@ -18,7 +22,7 @@ import pytest
 
 import ldpc_inputs as li
 import oracle
-from parity import ATOL, RTOL, first_iteration_bound, gpu_decode
+from parity import ATOL, RTOL, first_iteration_bound, first_iteration_input_bound, gpu_decode
 
 pytestmark = pytest.mark.gpu
 
@@ -55,7 +59,8 @@ def test_first_iteration_within_rounding_bound(prec, which):
     print(f"[case] first-iteration bound {prec} {which} n={code.n}", flush=True)
     gpu = gpu_decode(code, llr, 1, flags=_flag(prec) | ldpc.NO_EARLY_STOP)
     ora = oracle.decode(code, llr, 1, early_stop=False)
-    bound = ATOL + RTOL * np.abs(ora["lpost"]) + UNIT_ROUNDOFF[prec] * first_iteration_bound(code, llr)
+    bound = (ATOL + RTOL * np.abs(ora["lpost"]) + UNIT_ROUNDOFF[prec] * first_iteration_bound(code, llr)
+             + 2.0 ** -11 * first_iteration_input_bound(code, llr))
     err = np.abs(gpu["lpost"].astype(np.float64) - ora["lpost"])
     assert (err <= bound).all(), f"max excess {(err - bound).max():.3e}"
     # the messages really are stored rounded: FP32 storage stays below 1e-5 here

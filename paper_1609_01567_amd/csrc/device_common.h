@@ -182,23 +182,26 @@ __device__ __forceinline__ float tanh_complement(float x) {
 // Complement of a product of complements: 1 - (1-a)(1-b) = a + b(1-a).
 __device__ __forceinline__ float dplus(float a, float b) { return fmaf(b, 1.f - a, a); }
 
-// |R| = 2 atanh(1 - D) = ln((2 - D)/D), clamped to LMAX; D = 0 (empty product) gives LMAX.
+// |R| = 2 atanh(1 - D) = ln((2 - D)/D) = ln(2/D - 1), clamped to LMAX; D = 0
+// (empty product) gives LMAX.  For 0 < D <= 1 the ratio is >= 1, so the one
+// rounding of 2/D - 1 in the fma adds no cancellation.
 __device__ __forceinline__ float magnitude_from_complement(float D) {
-    const float ratio = (2.f - D) * __builtin_amdgcn_rcpf(D);
+    const float ratio = fmaf(2.f, __builtin_amdgcn_rcpf(D), -1.f);
     return fminf(__builtin_amdgcn_logf(ratio) * kLn2, kLmax);
 }
 
-__device__ __forceinline__ float clamp_msg(float q) { return fminf(fmaxf(q, -kLmax), kLmax); }
+// Q clamped to [-LMAX, LMAX] (one v_med3; Q is never NaN).
+__device__ __forceinline__ float clamp_msg(float q) { return __builtin_amdgcn_fmed3f(q, -kLmax, kLmax); }
 
 // Signs travel in the sign bit of the rule inputs: u carries the sign of its
-// Q, the row's sign parity is the XOR of those bits, and an output magnitude
-// (>= 0) takes its sign by OR-ing in a sign bit.  The values a check pass
+// Q, the row's sign parity is bit 31 of the XOR of the Q words (the other bits
+// of that word are never read), and an output magnitude (>= 0) takes its sign
+// from bit 31 of a word.  The values a check pass
 // reads never hold -0 (channel LLRs are stored with -0 replaced by +0, and
 // sums and differences of such values round exact zeros to +0), so the sign
 // bit of Q is exactly Q < 0, the sign Algorithm 1 uses (sgn(0) = +1).
-__device__ __forceinline__ uint32_t sign_of(float x) { return __float_as_uint(x) & 0x80000000u; }
 __device__ __forceinline__ float signed_mag(float mag, uint32_t sign) {
-    return __uint_as_float(__float_as_uint(mag) | (sign & 0x80000000u));
+    return copysignf(mag, __uint_as_float(sign));
 }
 // A channel LLR as the check and bit passes store it: -0 becomes +0.
 __device__ __forceinline__ float canon_llr(float x) { return x + 0.f; }
@@ -340,11 +343,10 @@ __device__ __forceinline__ void gather_edges(const int32_t *__restrict__ col_idx
                     sw[w] ^= lw[j][w];
                     const float q0 = clamp_msg(sub_f16_halves<0>(lw[j][w], rw[j][w]));
                     const float q1 = clamp_msg(sub_f16_halves<1>(lw[j][w], rw[j][w]));
-                    const uint32_t s0q = sign_of(q0), s1q = sign_of(q1);
-                    par[2 * w] ^= s0q;
-                    par[2 * w + 1] ^= s1q;
-                    u[j][2 * w] = signed_mag(CheckRule<RULE>::input(fabsf(q0)), s0q);
-                    u[j][2 * w + 1] = signed_mag(CheckRule<RULE>::input(fabsf(q1)), s1q);
+                    par[2 * w] ^= __float_as_uint(q0);
+                    par[2 * w + 1] ^= __float_as_uint(q1);
+                    u[j][2 * w] = copysignf(CheckRule<RULE>::input(fabsf(q0)), q0);
+                    u[j][2 * w + 1] = copysignf(CheckRule<RULE>::input(fabsf(q1)), q1);
                 }
             }
         }
@@ -382,9 +384,8 @@ __device__ __forceinline__ void gather_edges(const int32_t *__restrict__ col_idx
             for (int k = 0; k < V; k++) {
                 syn[k] ^= (lv[j][k] < 0.f);
                 const float q = clamp_msg(lv[j][k] - r[j][k]);
-                const uint32_t sq = sign_of(q);
-                par[k] ^= sq;
-                u[j][k] = signed_mag(CheckRule<RULE>::input(fabsf(q)), sq);
+                par[k] ^= __float_as_uint(q);
+                u[j][k] = copysignf(CheckRule<RULE>::input(fabsf(q)), q);
             }
         }
     }

@@ -281,7 +281,7 @@ __global__ __launch_bounds__(256) void check_hub_kernel(
                 const int v = wave_uniform(col_idx[j0 + jj]);
                 const float lv = Codec<CodecOf<CheckL<M, MODE>>::kMsg>::dec(L[size_t(v) * S + s]);
                 const float r = (MODE == kIter) ? Codec<M>::dec(R[size_t(j0 + jj) * S + s]) : 0.f;
-                const float q = clamp_msg(lv - r);
+                const float q = rule_q<M, RULE>(lv, r);
                 bits ^= int32_t(q < 0.f) | (int32_t(lv < 0.f) << 1);
                 agg = Rule::combine(agg, Rule::input(fabsf(q)));
             }
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(256) void check_hub_kernel(
                 const int v = wave_uniform(col_idx[j0 + jj]);
                 const float lv = Codec<CodecOf<CheckL<M, MODE>>::kMsg>::dec(L[size_t(v) * S + s]);
                 const float r = (MODE == kIter) ? Codec<M>::dec(R[size_t(j0 + jj) * S + s]) : 0.f;
-                const float q = clamp_msg(lv - r);
+                const float q = rule_q<M, RULE>(lv, r);
                 neg |= uint32_t(q < 0.f) << jj;
                 u[jj] = Rule::input(fabsf(q));
             }
@@ -341,7 +341,7 @@ __global__ __launch_bounds__(256) void check_hub_kernel(
 #pragma unroll
         for (int jj = 0; jj < C; jj++) {
             if (jj < dc) {
-                const float mag = Rule::magnitude(Rule::combine(run, sf[jj]), rp);
+                const float mag = rule_mag<M, RULE>(Rule::combine(run, sf[jj]), rp);
                 const uint32_t sgn = parity ^ ((neg >> jj) & 1u);
                 R[size_t(j0 + jj) * S + s] = Codec<M>::enc(sgn ? -mag : mag);
                 run = Rule::combine(run, u[jj]);
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(256) void bit_kernel(const int32_t *__restrict__ co
                                                   typename Post<M>::T *__restrict__ post,
                                                   float *__restrict__ Lpost, int32_t *__restrict__ iters,
                                                   const int32_t *__restrict__ fail, int32_t S, int32_t groups,
-                                                  int32_t t, int32_t early_stop) {
+                                                  int32_t t, int32_t early_stop, float bscale) {
     const int lane = threadIdx.x & 63;
     const int wave = wave_uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const int g = wave % groups;
@@ -393,10 +393,9 @@ __global__ __launch_bounds__(256) void bit_kernel(const int32_t *__restrict__ co
     if (!any_active) return;   // lanes with no running frame issue no loads or stores
 
     float sum[V];
-    load_vec<kF32, V>(Lch + size_t(v) * S + s0, sum);
     const int a = wave_uniform(col_ptr[v]);
     const int b = wave_uniform(col_ptr[v + 1]);
-    bit_sum<M, V, true>(csc_to_csr, a, b, R, S, s0, sum);
+    bit_posterior<M, V, true>(csc_to_csr, a, b, R, S, s0, Lch + size_t(v) * S, bscale, sum);
     bool all = true;
 #pragma unroll
     for (int k = 0; k < V; k++) all &= act[k];
@@ -1017,6 +1016,10 @@ void run_decode(const ldpc_graph *g, const Plan &p, const Bufs &b, const float *
     // 16-bit message formats write the fp32 posterior only when it is an output
     const bool keep32 = kPost16<M> && llr_out && !sim.on;
     _Float16 *post16 = kPost16<M> ? static_cast<_Float16 *>(b.post) : nullptr;
+    // factor of a bit's message sum in its posterior (the messages' units)
+    const float bscale = rule.kind == kRuleNMS   ? MsgUnits<M, kRuleNMS>::kBitScale
+                         : rule.kind == kRuleOMS ? MsgUnits<M, kRuleOMS>::kBitScale
+                                                 : MsgUnits<M, kRuleSP>::kBitScale;
     mk.mark(0, st);
     hipLaunchKernelGGL(init_state_kernel, dim3((S + 255) / 256), dim3(256), 0, st, b.iters, b.fail, F, S);
     const dim3 tgrid((g->n + 63) / 64, S / 64);
@@ -1076,7 +1079,7 @@ void run_decode(const ldpc_graph *g, const Plan &p, const Bufs &b, const float *
             hipLaunchKernelGGL((bit_kernel<M, 1>), dim3(blocks_for_waves(int64_t(g->n) * (Sp / 64))), dim3(256), 0, st,
                                g->d_col_ptr, g->d_csc_to_csr, g->n, cb.lch, static_cast<const MT *>(cb.r),
                                static_cast<PT *>(cb.post), keep32 ? cb.lpost : nullptr,
-                               cb.iters, cb.fail, Sp, Sp / 64, t, int32_t(early_stop));
+                               cb.iters, cb.fail, Sp, Sp / 64, t, int32_t(early_stop), bscale);
             mk.mark(2 * t + 1, st);
         } else {
             const void *L1 = kPost16<M> ? b.post : static_cast<const void *>(b.lch);
@@ -1086,7 +1089,7 @@ void run_decode(const ldpc_graph *g, const Plan &p, const Bufs &b, const float *
             hipLaunchKernelGGL((bit_kernel<M, V>), dim3(bit_blocks), dim3(256), 0, st, g->d_col_ptr, g->d_csc_to_csr,
                                g->n, b.lch, static_cast<const MT *>(b.r), static_cast<PT *>(b.post),
                                keep32 ? b.lpost : nullptr, b.iters, b.fail, S, groups, t,
-                               int32_t(early_stop));
+                               int32_t(early_stop), bscale);
             mk.mark(2 * t + 1, st);
         }
         if (cp.on && check == 0 && t >= kFirstCheck && t % kEvery == 0 && t + kLag + 2 <= T) {

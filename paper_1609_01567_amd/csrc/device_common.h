@@ -173,21 +173,21 @@ __device__ __forceinline__ void store_i32(int32_t *p, const int32_t (&in)[V]) {
 
 // -------------------------------------------------------------- check math
 
-// u = 1 - tanh(x/2) = 2 / (1 + e^x) = 1 / ((1 + e^x)/2), for 0 <= x = |Q| <= LMAX
-// (e^64 is a normal fp32 number; the halved denominator is one fma).
-__device__ __forceinline__ float tanh_complement(float x) {
-    return __builtin_amdgcn_rcpf(fmaf(0.5f, __builtin_amdgcn_exp2f(x * kLog2e), 0.5f));
+// u = 1 - tanh(x/2) = 2 / (1 + e^x) = 1 / ((1 + 2^y)/2) with y = x log2(e), for
+// 0 <= x = |Q| <= LMAX, the argument given as y (2^(64 log2 e) is a normal fp32
+// number; the halved denominator is one fma).
+__device__ __forceinline__ float tanh_complement_b2(float y) {
+    return __builtin_amdgcn_rcpf(fmaf(0.5f, __builtin_amdgcn_exp2f(y), 0.5f));
 }
 
 // Complement of a product of complements: 1 - (1-a)(1-b) = a + b(1-a).
 __device__ __forceinline__ float dplus(float a, float b) { return fmaf(b, 1.f - a, a); }
 
-// |R| = 2 atanh(1 - D) = ln((2 - D)/D) = ln(2/D - 1), clamped to LMAX; D = 0
-// (empty product) gives LMAX.  For 0 < D <= 1 the ratio is >= 1, so the one
-// rounding of 2/D - 1 in the fma adds no cancellation.
-__device__ __forceinline__ float magnitude_from_complement(float D) {
-    const float ratio = fmaf(2.f, __builtin_amdgcn_rcpf(D), -1.f);
-    return fminf(__builtin_amdgcn_logf(ratio) * kLn2, kLmax);
+// |R| log2(e) = 2 atanh(1 - D) log2(e) = log2((2 - D)/D) = log2(2/D - 1); D = 0
+// (empty product) gives +inf, which the caller clamps.  For 0 < D <= 1 the
+// ratio is >= 1, so the one rounding of 2/D - 1 in the fma adds no cancellation.
+__device__ __forceinline__ float magnitude_from_complement_b2(float D) {
+    return __builtin_amdgcn_logf(fmaf(2.f, __builtin_amdgcn_rcpf(D), -1.f));
 }
 
 // Q clamped to [-LMAX, LMAX] (one v_med3; Q is never NaN).
@@ -222,11 +222,14 @@ enum RuleKind { kRuleSP = 0, kRuleNMS = 1, kRuleOMS = 2 };
 
 template <int RULE> struct CheckRule;
 
+// Sum-product works on LLRs in base-2 units (|Q| log2 e in, |R| log2 e out):
+// the hardware's transcendentals are exp2 and log2.  See MsgUnits for where
+// the scaling happens.
 template <> struct CheckRule<kRuleSP> {
     static __device__ __forceinline__ float identity() { return 0.f; }
-    static __device__ __forceinline__ float input(float qa) { return tanh_complement(qa); }
+    static __device__ __forceinline__ float input(float qa2) { return tanh_complement_b2(qa2); }
     static __device__ __forceinline__ float combine(float a, float b) { return dplus(a, b); }
-    static __device__ __forceinline__ float magnitude(float agg, float) { return magnitude_from_complement(agg); }
+    static __device__ __forceinline__ float magnitude_b2(float agg) { return magnitude_from_complement_b2(agg); }
 };
 
 template <> struct CheckRule<kRuleNMS> {
@@ -244,6 +247,40 @@ template <> struct CheckRule<kRuleOMS> {
         return fminf(fmaxf(m - beta, 0.f), kLmax);
     }
 };
+
+// Units of the stored messages.  With the sum-product rule and FP32, FP16 or
+// BF16 storage a message is stored as R log2(e): the check pass then forms
+// the rule's input Q log2(e) = L log2(e) - R log2(e) with one fma and stores
+// the rule's output as it comes, and the bit pass adds ln(2) times the sum of
+// a bit's messages to its channel LLR.  Posteriors and channel LLRs stay in
+// natural units.  8-bit fixed-point messages (steps of 1/2) and the Min-Sum
+// rules store R itself.  LMAX bounds |Q| and |R| in natural units either way.
+template <int M, int RULE>
+struct MsgUnits {
+    static constexpr bool kRuleB2 = RULE == kRuleSP;       // the rule takes and gives base-2 magnitudes
+    static constexpr bool kStoredB2 = kRuleB2 && M != kQ8;  // messages are stored in base-2 units
+    static constexpr float kLim = kStoredB2 ? kLmax * kLog2e : kLmax;   // |Q|, |R| bound in stored units
+    // factor of the sum of a bit's messages in its posterior
+    static constexpr float kBitScale = kStoredB2 ? kLn2 : 1.f;
+};
+
+// The rule's input Q (clamped) from a posterior L and a stored message R.
+template <int M, int RULE>
+__device__ __forceinline__ float rule_q(float L, float R) {
+    using U = MsgUnits<M, RULE>;
+    if constexpr (U::kStoredB2) return __builtin_amdgcn_fmed3f(fmaf(L, kLog2e, -R), -U::kLim, U::kLim);
+    else if constexpr (U::kRuleB2) return clamp_msg(L - R) * kLog2e;
+    else return clamp_msg(L - R);
+}
+
+// The stored magnitude of an outgoing message from the rule's aggregate.
+template <int M, int RULE>
+__device__ __forceinline__ float rule_mag(float agg, float rp) {
+    using U = MsgUnits<M, RULE>;
+    if constexpr (U::kStoredB2) return fminf(CheckRule<RULE>::magnitude_b2(agg), U::kLim);
+    else if constexpr (U::kRuleB2) return fminf(CheckRule<RULE>::magnitude_b2(agg) * kLn2, kLmax);
+    else return CheckRule<RULE>::magnitude(agg, rp);
+}
 
 __device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
@@ -268,17 +305,24 @@ struct SlotSrc {
     bool any;   // some alt[k] is set
 };
 
-// L - R for fp16 L and R held as halves of 32-bit words (half 0: bits 0-15,
-// half 1: bits 16-31): one mixed-precision fma converts both halves to fp32
-// on the fly and rounds L * 1 - R once, the fp32 difference of the two values.
+// L * a - R for fp16 L and R held as halves of 32-bit words (half 0: bits
+// 0-15, half 1: bits 16-31) and an fp32 factor a: one mixed-precision fma
+// converts both halves to fp32 on the fly and rounds the result once.
 template <int HALF>
-__device__ __forceinline__ float sub_f16_halves(uint32_t l, uint32_t r) {
+__device__ __forceinline__ float fma_f16_halves(uint32_t l, float a, uint32_t r) {
     float q;
     if constexpr (HALF == 0)
-        asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel_hi:[1,0,1]" : "=v"(q) : "v"(l), "v"(r));
+        asm("v_fma_mix_f32 %0, %1, %2, -%3 op_sel_hi:[1,0,1]" : "=v"(q) : "v"(l), "s"(a), "v"(r));
     else
-        asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(q) : "v"(l), "v"(r));
+        asm("v_fma_mix_f32 %0, %1, %2, -%3 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(q) : "v"(l), "s"(a), "v"(r));
     return q;
+}
+
+// rule_q for fp16 posteriors and messages held as word halves.
+template <int HALF, int RULE>
+__device__ __forceinline__ float rule_q_f16_halves(uint32_t l, uint32_t r) {
+    using U = MsgUnits<kF16, RULE>;
+    return __builtin_amdgcn_fmed3f(fma_f16_halves<HALF>(l, U::kStoredB2 ? kLog2e : 1.f, r), -U::kLim, U::kLim);
 }
 
 // Inputs of edges j0 .. j0+count-1 (1 <= count <= C) for the lane's slots:
@@ -341,8 +385,8 @@ __device__ __forceinline__ void gather_edges(const int32_t *__restrict__ col_idx
 #pragma unroll
                 for (int w = 0; w < W; w++) {
                     sw[w] ^= lw[j][w];
-                    const float q0 = clamp_msg(sub_f16_halves<0>(lw[j][w], rw[j][w]));
-                    const float q1 = clamp_msg(sub_f16_halves<1>(lw[j][w], rw[j][w]));
+                    const float q0 = rule_q_f16_halves<0, RULE>(lw[j][w], rw[j][w]);
+                    const float q1 = rule_q_f16_halves<1, RULE>(lw[j][w], rw[j][w]);
                     par[2 * w] ^= __float_as_uint(q0);
                     par[2 * w + 1] ^= __float_as_uint(q1);
                     u[j][2 * w] = copysignf(CheckRule<RULE>::input(fabsf(q0)), q0);
@@ -383,7 +427,7 @@ __device__ __forceinline__ void gather_edges(const int32_t *__restrict__ col_idx
 #pragma unroll
             for (int k = 0; k < V; k++) {
                 syn[k] ^= (lv[j][k] < 0.f);
-                const float q = clamp_msg(lv[j][k] - r[j][k]);
+                const float q = rule_q<M, RULE>(lv[j][k], r[j][k]);
                 par[k] ^= __float_as_uint(q);
                 u[j][k] = copysignf(CheckRule<RULE>::input(fabsf(q)), q);
             }
@@ -428,7 +472,7 @@ __device__ __forceinline__ void row_rule_n(const int32_t *__restrict__ col_idx, 
             float out[V];
 #pragma unroll
             for (int k = 0; k < V; k++) {
-                const float mag = Rule::magnitude(Rule::combine(run[k], suf[j][k]), rp);
+                const float mag = rule_mag<M, RULE>(Rule::combine(run[k], suf[j][k]), rp);
                 out[k] = signed_mag(mag, par[k] ^ __float_as_uint(u[j][k]));   // sign of the other inputs
                 run[k] = Rule::combine(run[k], fabsf(u[j][k]));
             }
@@ -496,6 +540,29 @@ __device__ __forceinline__ void bit_sum(const int32_t *__restrict__ csc_to_csr, 
     }
 }
 
+// Posterior of a bit from its channel LLRs (row `lch` of the [n][S] array):
+// scale 1 adds the bit's messages to Lch in column order; any other scale
+// (base-2 messages) sums the messages first and adds scale times the sum to
+// Lch with one fma.  The branch is uniform over the wavefront.
+template <int M, int V, bool UNIFORM>
+__device__ __forceinline__ void bit_posterior(const int32_t *__restrict__ csc_to_csr, int a, int b,
+                                              const typename Codec<M>::T *__restrict__ R, int32_t S, int s0,
+                                              const float *__restrict__ lch, float scale, float (&sum)[V]) {
+    float l[V];
+    load_vec<kF32, V>(lch + s0, l);
+    if (scale == 1.f) {
+#pragma unroll
+        for (int k = 0; k < V; k++) sum[k] = l[k];
+        bit_sum<M, V, UNIFORM>(csc_to_csr, a, b, R, S, s0, sum);
+    } else {
+#pragma unroll
+        for (int k = 0; k < V; k++) sum[k] = 0.f;
+        bit_sum<M, V, UNIFORM>(csc_to_csr, a, b, R, S, s0, sum);
+#pragma unroll
+        for (int k = 0; k < V; k++) sum[k] = fmaf(scale, sum[k], l[k]);
+    }
+}
+
 // Chunked rows: a row is cut into chunks of C edges handled by different
 // wavefronts.  chunk_load forms a chunk's u's, exclusive in-chunk suffixes and
 // its aggregate (the u's combined), sign bits and syndrome parity;
@@ -541,7 +608,7 @@ __device__ __forceinline__ void chunk_store(int j0, int dc, const float (&u)[C][
             float out[V];
 #pragma unroll
             for (int k = 0; k < V; k++) {
-                const float mag = Rule::magnitude(Rule::combine(run[k], Rule::combine(suf[j][k], post[k])), rp);
+                const float mag = rule_mag<M, RULE>(Rule::combine(run[k], Rule::combine(suf[j][k], post[k])), rp);
                 out[k] = signed_mag(mag, (parity[k] << 31) ^ __float_as_uint(u[j][k]));
                 run[k] = Rule::combine(run[k], fabsf(u[j][k]));
             }

@@ -444,7 +444,7 @@ __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict_
                     const int v = wave_uniform(cload(G.col_idx + (j0 + jj)));
                     const float lv = Codec<Post<M>::kMsg>::dec(L[size_t(v) * S + s]);
                     const float r = first ? 0.f : Codec<M>::dec(R[size_t(j0 + jj) * S + s]);
-                    const float qv = clamp_msg(lv - r);
+                    const float qv = rule_q<M, RULE>(lv, r);
                     bits ^= int32_t(qv < 0.f) | (int32_t(lv < 0.f) << 1);
                     agg = Rule::combine(agg, Rule::input(fabsf(qv)));
                 }
@@ -483,7 +483,7 @@ __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict_
                     const int v = wave_uniform(cload(G.col_idx + (j0 + jj)));
                     const float lv = Codec<Post<M>::kMsg>::dec(L[size_t(v) * S + s]);
                     const float r = first ? 0.f : Codec<M>::dec(R[size_t(j0 + jj) * S + s]);
-                    const float qv = clamp_msg(lv - r);
+                    const float qv = rule_q<M, RULE>(lv, r);
                     neg |= uint32_t(qv < 0.f) << jj;
                     uu[jj] = Rule::input(fabsf(qv));
                 }
@@ -500,7 +500,7 @@ __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict_
 #pragma unroll
             for (int jj = 0; jj < C; jj++) {
                 if (jj < dc) {
-                    const float mag = Rule::magnitude(Rule::combine(run, sf[jj]), rp);
+                    const float mag = rule_mag<M, RULE>(Rule::combine(run, sf[jj]), rp);
                     const uint32_t sgn = parity ^ ((neg >> jj) & 1u);
                     R[size_t(j0 + jj) * S + s] = Codec<M>::enc(sgn ? -mag : mag);
                     run = Rule::combine(run, uu[jj]);
@@ -560,7 +560,7 @@ __global__ __launch_bounds__(1024) void eng_check_wide(const EngGraph *__restric
 // cover every slot below the extent once, and write the slots' next state.
 template <int M, int V, bool UNIFORM>
 __device__ __forceinline__ void bit_item(const EngGraph &G, int v, int s0, int32_t T, int32_t early,
-                                         int32_t par) {
+                                         int32_t par, float bscale) {
     using MT = typename Codec<M>::T;
     const int32_t S = G.S;
     int32_t t[V], f[V];
@@ -584,10 +584,9 @@ __device__ __forceinline__ void bit_item(const EngGraph &G, int v, int s0, int32
     if (!any) return;
     const MT *R = static_cast<const MT *>(G.r);
     float sum[V];
-    load_vec<kF32, V>(G.lch + size_t(v) * S + s0, sum);
     const int a = UNIFORM ? wave_uniform(cload(G.col_ptr + (v))) : cload(G.col_ptr + (v));
     const int b = UNIFORM ? wave_uniform(cload(G.col_ptr + (v + 1))) : cload(G.col_ptr + (v + 1));
-    bit_sum<M, V, UNIFORM>(G.csc_to_csr, a, b, R, S, s0, sum);
+    bit_posterior<M, V, UNIFORM>(G.csc_to_csr, a, b, R, S, s0, G.lch + size_t(v) * S, bscale, sum);
     using PT = typename Post<M>::T;
     PT *post = static_cast<PT *>(G.post);
     if (all) {
@@ -609,7 +608,7 @@ __device__ __forceinline__ void bit_item(const EngGraph &G, int v, int s0, int32
 template <int M, int V>
 __global__ __launch_bounds__(256) void eng_bit(const EngGraph *__restrict__ graphs, int32_t ngraphs,
                                                const int32_t *__restrict__ counters, int32_t T, int32_t early,
-                                               int32_t par) {
+                                               int32_t par, float bscale) {
     // The previous step's turnover and admission are complete: move each
     // graph's queue head past the frames it admitted and empty its list
     // (a no-op in the later passes of a step).
@@ -632,11 +631,11 @@ __global__ __launch_bounds__(256) void eng_bit(const EngGraph *__restrict__ grap
         if (rpw == 1) {
             const int groups = wave_uniform(w.groups[c]);
             const int v = local / groups;
-            bit_item<M, V, true>(G, v, ((local - v * groups) * 64 + lane) * V, T, early, par);
+            bit_item<M, V, true>(G, v, ((local - v * groups) * 64 + lane) * V, T, early, par, bscale);
         } else {
             const int lpr = 64 / rpw;
             const int v = local * rpw + lane / lpr;
-            if (v < G.n) bit_item<M, V, false>(G, v, (lane % lpr) * V, T, early, par);
+            if (v < G.n) bit_item<M, V, false>(G, v, (lane % lpr) * V, T, early, par, bscale);
         }
     }
 }
@@ -1084,7 +1083,7 @@ void enqueue_step_rule(ldpc_engine *e) {
             hipLaunchKernelGGL((eng_check_hub<M, RULE>), dim3(e->grid_hub), dim3(256), 0, st, e->d_graphs, ng,
                                e->d_counters, e->T, early, par, rp);
         hipLaunchKernelGGL((eng_bit<M, V>), dim3(e->grid_bit), dim3(256), 0, st, e->d_graphs, ng, e->d_counters,
-                           e->T, early, par);
+                           e->T, early, par, MsgUnits<M, RULE>::kBitScale);
     }
     const unsigned slot_blocks = unsigned((e->total_slots + 255) / 256);
     hipLaunchKernelGGL(eng_advance, dim3(slot_blocks), dim3(256), 0, st, e->d_graphs, e->pre_slots, e->T,

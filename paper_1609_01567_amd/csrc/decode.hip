@@ -283,7 +283,7 @@ __global__ __launch_bounds__(256) void check_hub_kernel(
                 const float r = (MODE == kIter) ? Codec<M>::dec(R[size_t(j0 + jj) * S + s]) : 0.f;
                 const float q = rule_q<M, RULE>(lv, r);
                 bits ^= int32_t(q < 0.f) | (int32_t(lv < 0.f) << 1);
-                agg = Rule::combine(agg, Rule::input(fabsf(q)));
+                agg = Rule::combine(agg, rule_in<M, RULE>(fabsf(q)));
             }
         }
         aggD[size_t(cb + c) * S + s] = agg;
@@ -326,7 +326,7 @@ __global__ __launch_bounds__(256) void check_hub_kernel(
                 const float r = (MODE == kIter) ? Codec<M>::dec(R[size_t(j0 + jj) * S + s]) : 0.f;
                 const float q = rule_q<M, RULE>(lv, r);
                 neg |= uint32_t(q < 0.f) << jj;
-                u[jj] = Rule::input(fabsf(q));
+                u[jj] = rule_in<M, RULE>(fabsf(q));
             }
         }
         float run = Rule::identity();

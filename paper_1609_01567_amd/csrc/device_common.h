@@ -200,8 +200,12 @@ __device__ __forceinline__ float clamp_msg(float q) { return __builtin_amdgcn_fm
 // reads never hold -0 (channel LLRs are stored with -0 replaced by +0, and
 // sums and differences of such values round exact zeros to +0), so the sign
 // bit of Q is exactly Q < 0, the sign Algorithm 1 uses (sgn(0) = +1).
+// (FP16 messages: one bit-field insert; the other formats OR the masked sign
+// bit in, which keeps their kernels within their register budget.)
+template <int M>
 __device__ __forceinline__ float signed_mag(float mag, uint32_t sign) {
-    return copysignf(mag, __uint_as_float(sign));
+    if constexpr (M == kF16) return copysignf(mag, __uint_as_float(sign));
+    else return __uint_as_float(__float_as_uint(mag) | (sign & 0x80000000u));
 }
 // A channel LLR as the check and bit passes store it: -0 becomes +0.
 __device__ __forceinline__ float canon_llr(float x) { return x + 0.f; }
@@ -248,29 +252,39 @@ template <> struct CheckRule<kRuleOMS> {
     }
 };
 
-// Units of the stored messages.  With the sum-product rule and FP32, FP16 or
-// BF16 storage a message is stored as R log2(e): the check pass then forms
-// the rule's input Q log2(e) = L log2(e) - R log2(e) with one fma and stores
-// the rule's output as it comes, and the bit pass adds ln(2) times the sum of
-// a bit's messages to its channel LLR.  Posteriors and channel LLRs stay in
-// natural units.  8-bit fixed-point messages (steps of 1/2) and the Min-Sum
-// rules store R itself.  LMAX bounds |Q| and |R| in natural units either way.
+// Units of the stored messages.  With the sum-product rule and FP16 or BF16
+// storage a message is stored as R log2(e): the check pass then forms the
+// rule's input Q log2(e) = L log2(e) - R log2(e) with one fma and stores the
+// rule's output as it comes, and the bit pass adds ln(2) times the sum of a
+// bit's messages to its channel LLR.  Posteriors and channel LLRs stay in
+// natural units.  FP32 messages (whose check pass is bound by memory, not by
+// its arithmetic), 8-bit fixed-point messages (steps of 1/2) and the Min-Sum
+// rules store R itself, and the sum-product rule scales on the way in and
+// out.  LMAX bounds |Q| and |R| in natural units either way.
 template <int M, int RULE>
 struct MsgUnits {
-    static constexpr bool kRuleB2 = RULE == kRuleSP;       // the rule takes and gives base-2 magnitudes
-    static constexpr bool kStoredB2 = kRuleB2 && M != kQ8;  // messages are stored in base-2 units
+    static constexpr bool kRuleB2 = RULE == kRuleSP;                              // base-2 rule magnitudes
+    static constexpr bool kStoredB2 = kRuleB2 && (M == kF16 || M == kBF16);      // base-2 stored messages
     static constexpr float kLim = kStoredB2 ? kLmax * kLog2e : kLmax;   // |Q|, |R| bound in stored units
     // factor of the sum of a bit's messages in its posterior
     static constexpr float kBitScale = kStoredB2 ? kLn2 : 1.f;
 };
 
-// The rule's input Q (clamped) from a posterior L and a stored message R.
+// Q (clamped, in stored units) from a posterior L and a stored message R.
 template <int M, int RULE>
 __device__ __forceinline__ float rule_q(float L, float R) {
     using U = MsgUnits<M, RULE>;
     if constexpr (U::kStoredB2) return __builtin_amdgcn_fmed3f(fmaf(L, kLog2e, -R), -U::kLim, U::kLim);
-    else if constexpr (U::kRuleB2) return clamp_msg(L - R) * kLog2e;
     else return clamp_msg(L - R);
+}
+
+// The rule's input from |Q| in stored units.
+template <int M, int RULE>
+__device__ __forceinline__ float rule_in(float qa) {
+    using U = MsgUnits<M, RULE>;
+    if constexpr (U::kStoredB2) return CheckRule<RULE>::input(qa);
+    else if constexpr (U::kRuleB2) return CheckRule<RULE>::input(qa * kLog2e);
+    else return CheckRule<RULE>::input(qa);
 }
 
 // The stored magnitude of an outgoing message from the rule's aggregate.
@@ -389,8 +403,8 @@ __device__ __forceinline__ void gather_edges(const int32_t *__restrict__ col_idx
                     const float q1 = rule_q_f16_halves<1, RULE>(lw[j][w], rw[j][w]);
                     par[2 * w] ^= __float_as_uint(q0);
                     par[2 * w + 1] ^= __float_as_uint(q1);
-                    u[j][2 * w] = copysignf(CheckRule<RULE>::input(fabsf(q0)), q0);
-                    u[j][2 * w + 1] = copysignf(CheckRule<RULE>::input(fabsf(q1)), q1);
+                    u[j][2 * w] = copysignf(rule_in<M, RULE>(fabsf(q0)), q0);
+                    u[j][2 * w + 1] = copysignf(rule_in<M, RULE>(fabsf(q1)), q1);
                 }
             }
         }
@@ -428,8 +442,10 @@ __device__ __forceinline__ void gather_edges(const int32_t *__restrict__ col_idx
             for (int k = 0; k < V; k++) {
                 syn[k] ^= (lv[j][k] < 0.f);
                 const float q = rule_q<M, RULE>(lv[j][k], r[j][k]);
-                par[k] ^= __float_as_uint(q);
-                u[j][k] = copysignf(CheckRule<RULE>::input(fabsf(q)), q);
+                // bit 31 only: keeping whole words here costs the FP32 kernels registers
+                const uint32_t sq = __float_as_uint(q) & 0x80000000u;
+                par[k] ^= sq;
+                u[j][k] = __uint_as_float(__float_as_uint(rule_in<M, RULE>(fabsf(q))) | sq);
             }
         }
     }
@@ -473,7 +489,7 @@ __device__ __forceinline__ void row_rule_n(const int32_t *__restrict__ col_idx, 
 #pragma unroll
             for (int k = 0; k < V; k++) {
                 const float mag = rule_mag<M, RULE>(Rule::combine(run[k], suf[j][k]), rp);
-                out[k] = signed_mag(mag, par[k] ^ __float_as_uint(u[j][k]));   // sign of the other inputs
+                out[k] = signed_mag<M>(mag, par[k] ^ __float_as_uint(u[j][k]));   // sign of the other inputs
                 run[k] = Rule::combine(run[k], fabsf(u[j][k]));
             }
             store_vec<M, V>(lane_elem(R + size_t(e0 + j) * S, s0), out);
@@ -609,7 +625,7 @@ __device__ __forceinline__ void chunk_store(int j0, int dc, const float (&u)[C][
 #pragma unroll
             for (int k = 0; k < V; k++) {
                 const float mag = rule_mag<M, RULE>(Rule::combine(run[k], Rule::combine(suf[j][k], post[k])), rp);
-                out[k] = signed_mag(mag, (parity[k] << 31) ^ __float_as_uint(u[j][k]));
+                out[k] = signed_mag<M>(mag, (parity[k] << 31) ^ __float_as_uint(u[j][k]));
                 run[k] = Rule::combine(run[k], fabsf(u[j][k]));
             }
             store_vec<M, V>(R + size_t(j0 + j) * S + s0, out);

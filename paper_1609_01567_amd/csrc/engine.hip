@@ -446,7 +446,7 @@ __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict_
                     const float r = first ? 0.f : Codec<M>::dec(R[size_t(j0 + jj) * S + s]);
                     const float qv = rule_q<M, RULE>(lv, r);
                     bits ^= int32_t(qv < 0.f) | (int32_t(lv < 0.f) << 1);
-                    agg = Rule::combine(agg, Rule::input(fabsf(qv)));
+                    agg = Rule::combine(agg, rule_in<M, RULE>(fabsf(qv)));
                 }
             }
             gmem(G.aggd)[size_t(cb + ch) * S + s] = agg;
@@ -485,7 +485,7 @@ __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict_
                     const float r = first ? 0.f : Codec<M>::dec(R[size_t(j0 + jj) * S + s]);
                     const float qv = rule_q<M, RULE>(lv, r);
                     neg |= uint32_t(qv < 0.f) << jj;
-                    uu[jj] = Rule::input(fabsf(qv));
+                    uu[jj] = rule_in<M, RULE>(fabsf(qv));
                 }
             }
             float run = Rule::identity();

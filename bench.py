@@ -174,20 +174,23 @@ def copy_ceiling(torch, nbytes=1 << 30, reps=5):
 def algorithmic_bytes(iters: np.ndarray, T: int, E: int, n: int, msg_bytes: int):
     """Bytes the method must move, per pass, from each frame's iteration count.
 
+    s is the message size and p the posterior size the check pass reads (2
+    bytes with 16-bit messages, whose posterior is stored in FP16; else 4).
     Check pass t reads every message and the previous posterior and writes
-    every message: 2 E s + 4 n per active frame (iteration 1 reads the channel
-    LLRs and writes messages only: E s + 4 n).  It runs for frame f while
+    every message: 2 E s + p n per active frame (iteration 1 reads the channel
+    LLRs and writes messages only: E s + p n).  It runs for frame f while
     t <= iters_f + 1 (the pass after the last estimate also evaluates its
-    syndrome).  Bit pass t reads every message and the channel LLRs and writes
-    the posterior: E s + 8 n, for t <= iters_f.
+    syndrome).  Bit pass t reads every message and the FP32 channel LLRs and
+    writes the posterior: E s + (4 + p) n, for t <= iters_f.
     """
+    p = 2 if msg_bytes == 2 else 4
     check = np.zeros(T)
     bit = np.zeros(T)
     for t in range(1, T + 1):
         a = int((iters >= t - 1).sum()) if t > 1 else iters.size
         b = int((iters >= t).sum())
-        check[t - 1] = a * ((2 if t > 1 else 1) * E * msg_bytes + 4 * n)
-        bit[t - 1] = b * (E * msg_bytes + 8 * n)
+        check[t - 1] = a * ((2 if t > 1 else 1) * E * msg_bytes + p * n)
+        bit[t - 1] = b * (E * msg_bytes + (4 + p) * n)
     return check, bit
 
 
@@ -918,7 +921,8 @@ def main():
                     "kernel": "check_rows_kernel (check-node pass, rows of degree <= 8)",
                     "avg_launch_ms": round(avg_ms, 5), "launches": launches,
                     "bytes_per_launch": round(chk_bytes.sum() / launches),
-                    "per_unit": f"{2 * msg_bytes} B per edge-frame (message read + write) + 4 B per bit-frame "
+                    "per_unit": f"{2 * msg_bytes} B per edge-frame (message read + write) + "
+                                f"{2 if msg_bytes == 2 else 4} B per bit-frame "
                                 f"(posterior gather); units = active frames x (E={E} edges, n={n} bits)"}
         phase = {"check_ms_per_step": round(chk_ms.sum() / args.steps, 3),
                  "bit_ms_per_step": round(bit_ms.sum() / args.steps, 3),

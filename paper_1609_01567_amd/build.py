@@ -1,7 +1,9 @@
 """Build the decoder's shared library (HIP for gfx950) in-tree with hipcc."""
 from __future__ import annotations
 
+import json
 import os
+import re
 import subprocess
 import sys
 
@@ -9,6 +11,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libldpc_hip.so")
+# per-kernel register, scratch and occupancy figures of the last build (compiler remarks)
+RESOURCES = os.path.join(PKG, "libldpc_hip.resources.json")
 SOURCES = ["graph.cpp", "decode.hip", "engine.hip", "serve.cpp"]
 ARCH = os.environ.get("LDPC_OFFLOAD_ARCH", "gfx950")
 
@@ -32,6 +36,25 @@ def hipcc() -> str:
     return "hipcc"
 
 
+_REMARK_KEYS = {"VGPRs": "vgpr", "AGPRs": "agpr", "TotalSGPRs": "sgpr", "ScratchSize [bytes/lane]": "scratch",
+                "Occupancy [waves/SIMD]": "occupancy", "LDS Size [bytes/block]": "lds"}
+
+
+def parse_resource_remarks(text: str) -> dict:
+    """{mangled kernel name: {vgpr, agpr, sgpr, scratch, occupancy, lds}} from the
+    compiler's kernel-resource-usage remarks."""
+    out, cur = {}, None
+    for line in text.splitlines():
+        m = re.search(r"remark: Function Name: (\S+)", line)
+        if m:
+            cur = out.setdefault(m.group(1), {})
+            continue
+        m = re.search(r"remark:\s+([A-Za-z ]+(?:\[[^\]]*\])?): (\d+)", line)
+        if m and cur is not None and m.group(1).strip() in _REMARK_KEYS:
+            cur[_REMARK_KEYS[m.group(1).strip()]] = int(m.group(2))
+    return out
+
+
 def build_library(verbose: bool = False) -> str:
     """Compile csrc/*.{cpp,hip} into libldpc_hip.so next to this file.
 
@@ -46,16 +69,21 @@ def build_library(verbose: bool = False) -> str:
             obj = os.path.join(tmpdir, src + ".o")
             cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-c", "-o", obj,
                    os.path.join(CSRC, src)]
+            if src.endswith(".hip"):
+                cmd.append("-Rpass-analysis=kernel-resource-usage")
             if verbose:
                 print(" ".join(cmd), flush=True)
             procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
             objs.append(obj)
         failed = []
+        resources = {}
         for src, pr in procs:
             out, _ = pr.communicate()
             if pr.returncode != 0:
                 sys.stderr.write(out)
                 failed.append(src)
+            elif src.endswith(".hip"):
+                resources.update(parse_resource_remarks(out))
         if failed:
             raise RuntimeError(f"hipcc failed to compile {', '.join(failed)}")
         tmp = LIB + ".tmp"
@@ -67,6 +95,9 @@ def build_library(verbose: bool = False) -> str:
             sys.stderr.write(res.stdout + res.stderr)
             raise RuntimeError("hipcc failed to link libldpc_hip.so")
     os.replace(tmp, LIB)
+    with open(RESOURCES + ".tmp", "w") as f:
+        json.dump(resources, f, indent=0, sort_keys=True)
+    os.replace(RESOURCES + ".tmp", RESOURCES)
     return LIB
 
 

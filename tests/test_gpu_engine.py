@@ -282,3 +282,32 @@ def test_engine_repack_with_long_rows_and_many_graphs():
         plain = gpu_decode(c, x, 25)
         _assert_same(on[i], off[i], f"graph {i}: repack vs no repack")
         _assert_same(on[i], plain, f"graph {i}: engine vs plain")
+
+
+def _long_rows_code():
+    """Rows just inside and beyond the 512-edge limit of the LDS path, and far
+    beyond it (segmented path), among short rows."""
+    rng = np.random.default_rng(31)
+    cdeg = np.concatenate([[1200, 700, 513, 512, 300, 129], rng.integers(3, 12, size=200)])
+    E = int(cdeg.sum())
+    n = 1500
+    bdeg = np.full(n, E // n)
+    bdeg[: E - bdeg.sum()] += 1
+    return li.socket_code(bdeg, cdeg, seed=32)
+
+
+@pytest.mark.parametrize("msg", ["fp32", "fp16", "bf16"])
+def test_engine_segmented_and_wide_rows_equal_plain(msg):
+    """The engine's long-row kernels (16-wavefront rows up to 512 edges and the
+    segmented path beyond) against the plain decoder, with repacking and several
+    iterations per step, in every floating-point message format."""
+    from paper_1609_01567_amd import ldpc
+    flags = {"fp32": 0, "fp16": ldpc.MSG_FP16, "bf16": ldpc.MSG_BF16}[msg]
+    code = _long_rows_code()
+    assert code.check_degrees().max() == 1200
+    llr = li.awgn_llr(code.n, 200, li.ebn0_to_sigma2(6.0, code.rate), seed=33)
+    _announce("engine-long-rows", msg=msg, frames=200)
+    eng = _engine_decode([code], [llr], [128], 20, flags=flags, iters_per_step=2)[0]
+    plain = gpu_decode(code, llr, 20, flags=flags)
+    _assert_same(eng, plain, f"engine {msg} long rows vs plain")
+    assert len(np.unique(plain["iters"])) >= 2     # frames leave and enter at different steps

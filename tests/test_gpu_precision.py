@@ -68,6 +68,35 @@ def test_first_iteration_within_rounding_bound(prec, which):
 
 
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_first_iteration_long_rows_against_rounded_inputs(prec):
+    """Rows of 129..512 edges (LDS path) and of 513..1200 (segmented path).
+    The check pass of iteration 1 reads the channel LLRs from their FP16 copy,
+    so the FP64 oracle is given those rounded values: the message sums
+    Lpost - Lch of both then differ only by the storage rounding of each
+    message (at most u times the smallest other input of its check) and the
+    FP32 bar.  (The input-change term of the general bound grows with the row
+    length and would hide a wrong message scale on these rows.)"""
+    from paper_1609_01567_amd import ldpc
+    rng = np.random.default_rng(31)
+    cdeg = np.concatenate([[1200, 700, 513, 512, 300, 129], rng.integers(3, 12, size=200)])
+    E = int(cdeg.sum())
+    bdeg = np.full(1500, E // 1500)
+    bdeg[: E - bdeg.sum()] += 1
+    code = li.socket_code(bdeg, cdeg, seed=32)
+    llr = li.awgn_llr(code.n, 70, li.ebn0_to_sigma2(6.0, code.rate), seed=73)
+    llr16 = llr.astype(np.float16).astype(np.float64)
+    print(f"[case] long rows first iteration {prec}", flush=True)
+    gpu = gpu_decode(code, llr, 1, flags=_flag(prec) | ldpc.NO_EARLY_STOP)
+    ora = oracle.decode(code, llr16, 1, early_stop=False)
+    sum_gpu = gpu["lpost"].astype(np.float64) - llr.astype(np.float64)
+    sum_ora = ora["lpost"] - llr16
+    bound = ATOL + RTOL * np.abs(ora["lpost"]) + UNIT_ROUNDOFF[prec] * first_iteration_bound(code, llr16)
+    err = np.abs(sum_gpu - sum_ora)
+    assert (err <= bound).all(), f"max excess {(err - bound).max():.3e}"
+    assert err.max() > 1e-4
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
 def test_reduced_precision_decodes_are_consistent(prec):
     code = li.extreme_code()
     llr = li.awgn_llr(code.n, 200, li.ebn0_to_sigma2(5.0, code.rate), seed=2013)

@@ -649,7 +649,10 @@ __global__ __launch_bounds__(1024) void running_list_kernel(const int32_t *__res
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) *count = base;
+    if (threadIdx.x == 0) {
+        *count = base;
+        __threadfence_system();   // `count` may be a host word read once the stream reaches an event
+    }
 }
 
 // Copy rows of [rows][S] state into [rows][Sc]: element (r, k) takes
@@ -943,14 +946,17 @@ struct Compact {
     CompactLevel lv[2];
     int32_t *probe = nullptr;     // device word of the periodic counts
     int32_t *host_count = nullptr;
+    int32_t *host_count_dev = nullptr;   // the host word as the device addresses it (null: copy from probe)
 };
 
 int32_t *pinned_count_word() {
     static thread_local int32_t *word = nullptr;
     if (!word) {
         void *h = nullptr;
-        // portable: a thread may decode on several devices
-        if (hipHostMalloc(&h, 256, hipHostMallocPortable) != hipSuccess) {
+        // portable: a thread may decode on several devices; mapped and coherent: the
+        // count kernel stores into it directly
+        if (hipHostMalloc(&h, 256, hipHostMallocPortable | hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess) {
             (void)hipGetLastError();
             return nullptr;
         }
@@ -980,6 +986,11 @@ Compact compact_at(const Plan &p, const Bufs &b, bool wanted) {
     c.probe = reinterpret_cast<int32_t *>(ws + p.off_probe);
     c.host_count = pinned_count_word();
     c.on = c.host_count != nullptr;
+    // the count kernel writes the host word directly when the device can address it
+    if (c.on && hipHostGetDevicePointer(reinterpret_cast<void **>(&c.host_count_dev), c.host_count, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        c.host_count_dev = nullptr;
+    }
     return c;
 }
 
@@ -1095,8 +1106,9 @@ void run_decode(const ldpc_graph *g, const Plan &p, const Bufs &b, const float *
         if (cp.on && check == 0 && t >= kFirstCheck && t % kEvery == 0 && t + kLag + 2 <= T) {
             const int32_t *it_now = level == 0 ? b.iters : cp.lv[level - 1].b.iters;
             hipLaunchKernelGGL(running_list_kernel, dim3(1), dim3(1024), 0, st, it_now, Sl[level], nullptr, 0,
-                               cp.probe);
-            if (hipMemcpyAsync(cp.host_count, cp.probe, sizeof(int32_t), hipMemcpyDeviceToHost, st) == hipSuccess &&
+                               cp.host_count_dev ? cp.host_count_dev : cp.probe);
+            if ((cp.host_count_dev ||
+                 hipMemcpyAsync(cp.host_count, cp.probe, sizeof(int32_t), hipMemcpyDeviceToHost, st) == hipSuccess) &&
                 hipEventRecord(ev, st) == hipSuccess) {
                 check = t;
             } else {

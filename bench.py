@@ -874,6 +874,18 @@ def main():
     value = frames_per_step * k / (ms * 1e-3) / 1e9
     print(f"[bench] timed {args.steps} steps: {ms:.3f} ms/step", file=sys.stderr, flush=True)
 
+    # each point's decode timed on its own (after the timed steps, same calls)
+    point_ms = []
+    for i in range(len(points)):
+        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s0.record(stream)
+        for _ in range(args.steps):
+            ldpc.decode(g, d_llr[i], T, flags=timed_flags, workspace=ws, stream=stream, out=outs[i])
+        s1.record(stream)
+        torch.cuda.synchronize()
+        point_ms.append(s0.elapsed_time(s1) / args.steps)
+    k_rank = li.Encoder(code).k   # n - rank(H) over GF(2)
+
     per_point = []
     step_bytes = 0.0
     all_check = []
@@ -886,7 +898,8 @@ def main():
         err = bits != cws[i]
         per_point.append({"ebn0_db": eb, "mean_iters": float(it.mean()), "max_iters": int(it.max()),
                           "fer": float(err.any(axis=1).mean()), "ber": float(err.mean()),
-                          "syndrome_ok_frames": int(ok.sum())})
+                          "syndrome_ok_frames": int(ok.sum()), "ms": round(point_ms[i], 3),
+                          "gbits": round(F * k / (point_ms[i] * 1e-3) / 1e9, 4)})
         all_check.append((it, cb, bb))
     hbm_frac = step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
 
@@ -996,7 +1009,8 @@ def main():
         "config": {"workload": f"n={n} m={m} E={E} rate-1/2 random irregular LDPC (bit degrees 8/3/2, check "
                                f"degree 7), {F} frames at each Eb/N0 in {points} dB, max {T} iterations, "
                                f"syndrome early stop, {args.msg} messages",
-                   "frames_per_step": frames_per_step, "info_bits_per_frame": k},
+                   "frames_per_step": frames_per_step, "info_bits_per_frame": k,
+                   "info_bits_per_frame_n_minus_rank": k_rank},
         "tail_compaction": not args.no_compact,
         "hbm_frac_step": round(hbm_frac, 4),
         "copy_ceiling_gbs": round(ceiling, 1),

@@ -26,7 +26,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak, GB/s
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "check_rows_kernel_n64800_f256_4pts.json")
-DOMINANT = "void check_rows_kernel<0, 4, 8, 1, 0>"   # FP32, 4 slots per lane, rows <= 8, steady state, sum-product
+DOMINANT = "void check_rows_kernel<0, 4, 8, 1, 0, false>"   # FP32, 4 slots per lane, rows <= 8, steady state, sum-product, column table
 
 
 def kernel_source_sha():
@@ -481,50 +481,64 @@ def bench_minsum(torch, ldpc, g, d_llr, cws, points, T, steps, rules=(("oms", 0.
 
 def bench_structured(torch, ldpc, li, points, F, T, steps, compact=True):
     """The headline workload on a quasi-cyclic stand-in: the same degree profile
-    lifted by Z = 360 from a 90 x 180 base graph.  The generic decoder runs it
-    unchanged; the circulant structure only changes which posterior lines
-    neighbouring rows gather."""
+    lifted by Z = 360 from a 90 x 180 base graph, decoded through two graphs of
+    the same code: one built from the base matrix (ldpc_graph_create_qc: the
+    check pass computes each edge's bit from its circulant shift) and one built
+    from the COO (the check pass reads the column table).  Both give identical
+    results; the figures say what the circulant indexing changes."""
     code = li.large_qc_code()
+    Z, shifts = code.qc
     n, E, k = code.n, code.nnz, code.n - code.m
     enc = li.Encoder(code)
     cws = [enc.random_codewords(F, seed=3102 + i) for i in range(len(points))]
     llrs = [li.awgn_llr(n, F, li.ebn0_to_sigma2(eb, code.rate), seed=2102 + 10 * i, codewords=cws[i])
             for i, eb in enumerate(points)]
-    g = ldpc.Graph.from_code(code)
     d_llr = [torch.from_numpy(x).cuda() for x in llrs]
     timed_flags = ldpc.COMPACT_TAIL if compact else 0
-    ws = ldpc.Workspace(ldpc.workspace_size(g, F, timed_flags))
-    outs = [None] * len(points)
 
-    def step():
-        for i in range(len(points)):
-            outs[i] = ldpc.decode(g, d_llr[i], T, flags=timed_flags, workspace=ws)
+    def run(g):
+        ws = ldpc.Workspace(ldpc.workspace_size(g, F, timed_flags))
+        outs = [None] * len(points)
 
-    step()
-    torch.cuda.synchronize()
-    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    s.record()
-    for _ in range(steps):
+        def step():
+            for i in range(len(points)):
+                outs[i] = ldpc.decode(g, d_llr[i], T, flags=timed_flags, workspace=ws)
+
         step()
-    e.record()
-    torch.cuda.synchronize()
-    ms = s.elapsed_time(e) / steps
-    fer = [round(float((o.bits.cpu().numpy() != cw).any(axis=1).mean()), 5) for o, cw in zip(outs, cws)]
-    it = np.concatenate([o.iters.cpu().numpy() for o in outs])
-    chk_ms, chk_bytes, launches = 0.0, 0.0, 0
-    for i in range(len(points)):
-        res, tm = ldpc.decode_profiled(g, d_llr[i], T, workspace=ws)
-        cb, _ = algorithmic_bytes(res.iters.cpu().numpy(), T, E, n, 4)
-        chk_ms += float(tm["check_ms"].sum())
-        chk_bytes += float(cb.sum())
-        launches += T
-    achieved = chk_bytes / launches / (chk_ms / launches * 1e-3) / 1e9
-    return {"workload": f"n={n} m={code.m} E={E} quasi-cyclic (Z=360, base 90x180, the headline degree profile), "
-                        f"{F} random codewords at each Eb/N0 in {points} dB, max {T} iterations, fp32 messages",
-            "ms_per_step": round(ms, 3), "gbits": round(len(points) * F * k / (ms * 1e-3) / 1e9, 4),
-            "tail_compaction": compact, "fer": fer, "mean_iters": round(float(it.mean()), 2),
-            "check_avg_launch_ms": round(chk_ms / launches, 5),
-            "check_achieved_gbs": round(achieved, 1), "check_frac": round(achieved / HBM_PEAK_GBS, 4)}
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(steps):
+            step()
+        e.record()
+        torch.cuda.synchronize()
+        ms = s.elapsed_time(e) / steps
+        res = [(o.bits.cpu().numpy(), o.iters.cpu().numpy()) for o in outs]
+        chk_ms, chk_bytes, launches = 0.0, 0.0, 0
+        for i in range(len(points)):
+            r, tm = ldpc.decode_profiled(g, d_llr[i], T, workspace=ws)
+            cb, _ = algorithmic_bytes(r.iters.cpu().numpy(), T, E, n, 4)
+            chk_ms += float(tm["check_ms"].sum())
+            chk_bytes += float(cb.sum())
+            launches += T
+        achieved = chk_bytes / launches / (chk_ms / launches * 1e-3) / 1e9
+        del ws
+        return res, {"ms_per_step": round(ms, 3), "gbits": round(len(points) * F * k / (ms * 1e-3) / 1e9, 4),
+                     "check_avg_launch_ms": round(chk_ms / launches, 5), "check_achieved_gbs": round(achieved, 1),
+                     "check_frac": round(achieved / HBM_PEAK_GBS, 4)}
+
+    res_qc, circ = run(ldpc.Graph.from_qc(Z, shifts))
+    res_coo, table = run(ldpc.Graph.from_code(code))
+    same = all((a[0] == b[0]).all() and (a[1] == b[1]).all() for a, b in zip(res_qc, res_coo))
+    fer = [round(float((bits != cw).any(axis=1).mean()), 5) for (bits, _), cw in zip(res_qc, cws)]
+    it = np.concatenate([iters for _, iters in res_qc])
+    out = {"workload": f"n={n} m={code.m} E={E} quasi-cyclic (Z=360, base 90x180, the headline degree profile), "
+                       f"{F} random codewords at each Eb/N0 in {points} dB, max {T} iterations, fp32 messages",
+           "tail_compaction": compact, "fer": fer, "mean_iters": round(float(it.mean()), 2)}
+    out.update(circ)   # the structured path: circulant indexing
+    out["column_table"] = table
+    out["results_identical"] = bool(same)
+    return out
 
 
 def _mcnemar(b, c, N):

@@ -106,6 +106,35 @@ LDPC_API ldpc_status ldpc_graph_create(int32_t m, int32_t n, int64_t nnz,
                               const int32_t *rows, const int32_t *cols,
                               uint32_t flags, ldpc_graph **out);
 
+/*
+ * Build the Tanner graph of a quasi-cyclic (lifted) code and keep its base
+ * matrix for circulant indexing.  The results section benchmarks protograph
+ * expansions of a base code, and the further-acceleration subsection names
+ * modifications of the algorithm for certain families of LDPC codes; this is
+ * that family: every entry of the mb x nb base matrix is either a zero block
+ * or a Z x Z circulant, so check i*Z + t joins bit j*Z + ((t + s_ij) mod Z)
+ * for every base entry (i, j) with shift s_ij.
+ *
+ *  mb, nb      base rows and columns; both >= 1.
+ *  Z           lifting size >= 1; mb*Z and nb*Z, and the edge count
+ *              (nonzero base entries times Z), must stay below 2^31.
+ *  shifts      host int32 array [mb][nb] (row-major): s_ij in [0, Z), or -1
+ *              for a zero block.  Read only during the call.
+ *  flags, out  as for ldpc_graph_create.
+ *
+ * The graph is the one ldpc_graph_create builds from the lifted H with each
+ * check's edges in base-column order, so every entry point accepts it and
+ * ldpc_graph_arrays returns the same tables.  In addition, the check passes
+ * of rows of up to 16 edges compute each edge's bit from its base entry
+ * instead of reading the column index (sum-product rule).  Results are
+ * identical to decoding the same H built by ldpc_graph_create.
+ *
+ * Errors: INVAL (sizes out of range, null pointer, unknown flags), RANGE (a
+ * shift outside [-1, Z)), NOMEM, DEVICE.
+ */
+LDPC_API ldpc_status ldpc_graph_create_qc(int32_t mb, int32_t nb, int32_t Z, const int32_t *shifts,
+                                 uint32_t flags, ldpc_graph **out);
+
 /* Release the graph and its device tables.  NULL is accepted (no-op). */
 LDPC_API ldpc_status ldpc_graph_destroy(ldpc_graph *g);
 

@@ -39,6 +39,8 @@ class Code:
     rows: np.ndarray   # int32 [E], check index of each edge
     cols: np.ndarray   # int32 [E], bit index of each edge
     name: str = ""
+    # quasi-cyclic codes: (Z, shifts) with shifts int32 [m/Z][n/Z], -1 for a zero block
+    qc: tuple | None = None
 
     @property
     def nnz(self) -> int:
@@ -195,8 +197,10 @@ def lifted_code(base: Code, Z: int, seed: int, name: str = "") -> Code:
     rows = (base.rows.astype(np.int64)[:, None] * Z + r[None, :]).ravel()
     cols = (base.cols.astype(np.int64)[:, None] * Z + (r[None, :] + shifts[:, None]) % Z).ravel()
     order = np.lexsort((cols, rows))
+    table = np.full((base.m, base.n), -1, np.int32)
+    table[base.rows, base.cols] = shifts
     return Code(m=base.m * Z, n=base.n * Z, rows=rows[order].astype(np.int32),
-                cols=cols[order].astype(np.int32), name=name)
+                cols=cols[order].astype(np.int32), name=name, qc=(int(Z), table))
 
 
 def large_qc_code(seed: int = 1012) -> Code:

@@ -103,12 +103,15 @@ __device__ __forceinline__ void plain_syndrome(const int32_t (&st)[V], const int
 // RULE: the check rule (CheckRule); rp its parameter.  At least four
 // wavefronts per SIMD (at most 128 registers): a row keeps all of its loads in
 // flight, so the number of resident wavefronts bounds the memory parallelism.
-template <int M, int V, int DMAX, int MODE, int RULE>
+// QC: a quasi-cyclic graph; each edge's bit comes from the row's base entry
+// (QcCols) instead of col_idx, with the class's row ids in `rows`.
+template <int M, int V, int DMAX, int MODE, int RULE, bool QC>
 __global__ __launch_bounds__(256, 4) void check_rows_kernel(
     const int32_t *__restrict__ rd, const int32_t *__restrict__ col_idx,
     int32_t nrows, const CheckL<M, MODE> *__restrict__ L, typename Codec<M>::T *__restrict__ R,
     const int32_t *__restrict__ iters, int32_t *__restrict__ fail, int32_t S, int32_t groups, int32_t syn_iter,
-    float rp) {
+    float rp, const int32_t *__restrict__ rows, const int32_t *__restrict__ qc_row_ptr,
+    const int32_t *__restrict__ qc_ent, int32_t Z) {
     const int lane = threadIdx.x & 63;
     const int wave = wave_uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const int g = wave % groups;
@@ -135,7 +138,14 @@ __global__ __launch_bounds__(256, 4) void check_rows_kernel(
 #pragma unroll
     for (int k = 0; k < V; k++) syn[k] = 0;
     constexpr int IN = MODE == kIter ? kInSteady : kInFirst;
-    row_rule<M, V, DMAX, true, IN, RULE>(col_idx, e0, d, L, R, S, s0, src, syn, rp);
+    if constexpr (QC) {
+        const int r = wave_uniform(cload(rows + rk));
+        const int i = r / Z;
+        const QcCols q{qc_ent + 2 * wave_uniform(cload(qc_row_ptr + i)), e0, r - i * Z, Z};
+        row_rule<M, V, DMAX, true, IN, RULE>(q, e0, d, L, R, S, s0, src, syn, rp);
+    } else {
+        row_rule<M, V, DMAX, true, IN, RULE>(col_idx, e0, d, L, R, S, s0, src, syn, rp);
+    }
     if (MODE == kIter) plain_syndrome<V>(st, syn, fail, s0, syn_iter);
 }
 
@@ -812,14 +822,30 @@ void launch_rows(const ldpc_graph *g, int cls, int mode, const void *L, const Bu
     using T = typename Codec<M>::T;
     T *R = static_cast<T *>(b.r);
     const int32_t *rd = g->d_class_rd + 2 * g->class_begin[cls];
+    const int32_t *rows = g->d_class_rows + g->class_begin[cls];
+    // quasi-cyclic graphs take their bits from the base matrix (sum-product rule)
+    if constexpr (RULE == kRuleSP) {
+        if (g->qc_Z > 0) {
+            if (mode == kFirst)
+                hipLaunchKernelGGL((check_rows_kernel<M, V, DMAX, kFirst, RULE, true>), dim3(blocks), dim3(256), 0,
+                                   st, rd, g->d_col_idx, nrows, static_cast<const CheckL<M, kFirst> *>(L), R,
+                                   b.iters, b.fail, S, groups, 0, rp, rows, g->d_qc_row_ptr, g->d_qc_ent, g->qc_Z);
+            else
+                hipLaunchKernelGGL((check_rows_kernel<M, V, DMAX, kIter, RULE, true>), dim3(blocks), dim3(256), 0,
+                                   st, rd, g->d_col_idx, nrows, static_cast<const CheckL<M, kIter> *>(L), R,
+                                   b.iters, b.fail, S, groups, syn_iter, rp, rows, g->d_qc_row_ptr, g->d_qc_ent,
+                                   g->qc_Z);
+            return;
+        }
+    }
     if (mode == kFirst)
-        hipLaunchKernelGGL((check_rows_kernel<M, V, DMAX, kFirst, RULE>), dim3(blocks), dim3(256), 0, st, rd,
+        hipLaunchKernelGGL((check_rows_kernel<M, V, DMAX, kFirst, RULE, false>), dim3(blocks), dim3(256), 0, st, rd,
                            g->d_col_idx, nrows, static_cast<const CheckL<M, kFirst> *>(L), R, b.iters, b.fail, S,
-                           groups, 0, rp);
+                           groups, 0, rp, nullptr, nullptr, nullptr, 0);
     else
-        hipLaunchKernelGGL((check_rows_kernel<M, V, DMAX, kIter, RULE>), dim3(blocks), dim3(256), 0, st, rd,
+        hipLaunchKernelGGL((check_rows_kernel<M, V, DMAX, kIter, RULE, false>), dim3(blocks), dim3(256), 0, st, rd,
                            g->d_col_idx, nrows, static_cast<const CheckL<M, kIter> *>(L), R, b.iters, b.fail, S,
-                           groups, syn_iter, rp);
+                           groups, syn_iter, rp, nullptr, nullptr, nullptr, 0);
 }
 
 template <int M, int V, int WPR, int RULE>

@@ -339,6 +339,25 @@ __device__ __forceinline__ float rule_q_f16_halves(uint32_t l, uint32_t r) {
     return __builtin_amdgcn_fmed3f(fma_f16_halves<HALF>(l, U::kStoredB2 ? kLog2e : 1.f, r), -U::kLim, U::kLim);
 }
 
+// Column index of a check-sorted edge position: read from the column table,
+// or, for a row of a quasi-cyclic code, computed from its base row.  Edge
+// e0 + k of check i*Z + t joins bit J_k + ((t + s_k) mod Z), where (J_k = j_k Z,
+// s_k) is the k-th entry of base row i (the graph keeps base-column order).
+struct QcCols {
+    const int32_t *ent;   // (J, s) pairs of the row's base row
+    int32_t e0, t, Z;     // first edge of the row, its offset in the block, lifting size
+};
+template <bool UNIFORM>
+__device__ __forceinline__ int col_at(const int32_t *col_idx, int e) {
+    return UNIFORM ? wave_uniform(cload(col_idx + e)) : cload(col_idx + e);
+}
+template <bool UNIFORM>
+__device__ __forceinline__ int col_at(const QcCols &q, int e) {
+    const int k = e - q.e0;
+    const int u = q.t + cload(q.ent + 2 * k + 1);
+    return cload(q.ent + 2 * k) + (u >= q.Z ? u - q.Z : u);
+}
+
 // Inputs of edges j0 .. j0+count-1 (1 <= count <= C) for the lane's slots:
 // Q = clamp(L - R_old) and the rule's input u (1 - tanh(|Q|/2) for
 // sum-product, |Q| for Min-Sum) carrying the sign of Q in its sign bit; the
@@ -349,8 +368,8 @@ __device__ __forceinline__ float rule_q_f16_halves(uint32_t l, uint32_t r) {
 // branch), so the loads of a row are in flight together instead of one edge
 // at a time.  UNIFORM: all lanes walk the same row (indices read once per
 // wavefront).
-template <int M, int V, int C, bool UNIFORM, int IN, int RULE = kRuleSP, typename LT>
-__device__ __forceinline__ void gather_edges(const int32_t *__restrict__ col_idx, int j0, int count,
+template <int M, int V, int C, bool UNIFORM, int IN, int RULE = kRuleSP, typename LT, typename CI>
+__device__ __forceinline__ void gather_edges(CI col_idx, int j0, int count,
                                              const LT *__restrict__ L,
                                              const typename Codec<M>::T *__restrict__ R, int32_t S, int s0,
                                              const SlotSrc<V> &src, float (&u)[C][V], uint32_t (&par)[V],
@@ -359,7 +378,7 @@ __device__ __forceinline__ void gather_edges(const int32_t *__restrict__ col_idx
 #pragma unroll
     for (int j = 0; j < C; j++) {
         const int e = j0 + (j < count ? j : count - 1);
-        vix[j] = UNIFORM ? wave_uniform(cload(col_idx + e)) : cload(col_idx + e);
+        vix[j] = col_at<UNIFORM>(col_idx, e);
     }
     if constexpr (M == kF16 && CodecOf<LT>::kMsg == kF16 && V % 2 == 0) {
         // fp16 posterior and messages: the words as loaded, two slots each
@@ -455,8 +474,8 @@ __device__ __forceinline__ void gather_edges(const int32_t *__restrict__ col_idx
 // suffixes, then exclusive prefixes combined on the fly; R is updated in place.
 // UNIFORM: every lane of the wavefront works on the same row (indices are read
 // once per wavefront); otherwise each lane walks its own row.
-template <int M, int V, int DMAX, bool UNIFORM, int IN, int RULE = kRuleSP, typename LT>
-__device__ __forceinline__ void row_rule_n(const int32_t *__restrict__ col_idx, int e0, int d,
+template <int M, int V, int DMAX, bool UNIFORM, int IN, int RULE = kRuleSP, typename LT, typename CI>
+__device__ __forceinline__ void row_rule_n(CI col_idx, int e0, int d,
                                          const LT *__restrict__ L,
                                          typename Codec<M>::T *__restrict__ R, int32_t S, int s0,
                                          const SlotSrc<V> &src, int (&syn)[V], float rp = 0.f) {
@@ -500,8 +519,8 @@ __device__ __forceinline__ void row_rule_n(const int32_t *__restrict__ col_idx, 
 // row_rule_n with the degree as a compile-time constant when every lane works
 // on the same row of at most 8 edges: the row's code is then straight-line
 // (no per-position test of the degree).  Other rows take the generic form.
-template <int M, int V, int D, bool UNIFORM, int IN, int RULE, typename LT>
-__device__ __forceinline__ bool row_rule_fixed(const int32_t *__restrict__ col_idx, int e0, int d,
+template <int M, int V, int D, bool UNIFORM, int IN, int RULE, typename LT, typename CI>
+__device__ __forceinline__ bool row_rule_fixed(CI col_idx, int e0, int d,
                                                const LT *__restrict__ L, typename Codec<M>::T *__restrict__ R,
                                                int32_t S, int s0, const SlotSrc<V> &src, int (&syn)[V], float rp) {
     if (d != D) return false;
@@ -509,8 +528,8 @@ __device__ __forceinline__ bool row_rule_fixed(const int32_t *__restrict__ col_i
     return true;
 }
 
-template <int M, int V, int DMAX, bool UNIFORM, int IN, int RULE = kRuleSP, typename LT>
-__device__ __forceinline__ void row_rule(const int32_t *__restrict__ col_idx, int e0, int d,
+template <int M, int V, int DMAX, bool UNIFORM, int IN, int RULE = kRuleSP, typename LT, typename CI>
+__device__ __forceinline__ void row_rule(CI col_idx, int e0, int d,
                                          const LT *__restrict__ L,
                                          typename Codec<M>::T *__restrict__ R, int32_t S, int s0,
                                          const SlotSrc<V> &src, int (&syn)[V], float rp = 0.f) {

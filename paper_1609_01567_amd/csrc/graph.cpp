@@ -44,7 +44,8 @@ extern "C" const char *ldpc_status_str(ldpc_status s) {
 
 static void free_device(ldpc_graph *g) {
     int32_t **ptrs[] = {&g->d_row_ptr, &g->d_col_idx, &g->d_col_ptr, &g->d_csc_to_csr,
-                        &g->d_class_rows, &g->d_hub_chunk_base, &g->d_class_rd};
+                        &g->d_class_rows, &g->d_hub_chunk_base, &g->d_class_rd,
+                        &g->d_qc_row_ptr, &g->d_qc_ent};
     for (int32_t **p : ptrs) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
@@ -56,7 +57,8 @@ static ldpc_status upload(ldpc_graph *g) {
     Item items[] = {{&g->d_row_ptr, &g->row_ptr}, {&g->d_col_idx, &g->col_idx},
                     {&g->d_col_ptr, &g->col_ptr}, {&g->d_csc_to_csr, &g->csc_to_csr},
                     {&g->d_class_rows, &g->class_rows}, {&g->d_hub_chunk_base, &g->hub_chunk_base},
-                    {&g->d_class_rd, &g->class_rd}};
+                    {&g->d_class_rd, &g->class_rd}, {&g->d_qc_row_ptr, &g->qc_row_ptr},
+                    {&g->d_qc_ent, &g->qc_ent}};
     if (hipGetDevice(&g->device) != hipSuccess) {
         set_error("ldpc_graph_create: no HIP device is available");
         (void)hipGetLastError();
@@ -86,8 +88,72 @@ static ldpc_status upload(ldpc_graph *g) {
     return LDPC_OK;
 }
 
+// The graph of (m, n, COO); `qc` (may be null) is moved into it before its
+// tables go to the device.
+struct QcBase {
+    int32_t Z = 0;
+    std::vector<int32_t> row_ptr, ent;
+};
+static ldpc_status build_graph(int32_t m, int32_t n, int64_t nnz, const int32_t *rows, const int32_t *cols,
+                               uint32_t flags, QcBase *qc, ldpc_graph **out);
+
 extern "C" ldpc_status ldpc_graph_create(int32_t m, int32_t n, int64_t nnz, const int32_t *rows,
                                          const int32_t *cols, uint32_t flags, ldpc_graph **out) {
+    return build_graph(m, n, nnz, rows, cols, flags, nullptr, out);
+}
+
+extern "C" ldpc_status ldpc_graph_create_qc(int32_t mb, int32_t nb, int32_t Z, const int32_t *shifts,
+                                            uint32_t flags, ldpc_graph **out) {
+    if (!out || !shifts) { set_error("ldpc_graph_create_qc: null pointer"); return LDPC_E_INVAL; }
+    if (mb < 1 || nb < 1 || Z < 1) { set_error("ldpc_graph_create_qc: mb, nb and Z must be >= 1"); return LDPC_E_INVAL; }
+    if (int64_t(mb) * Z > INT32_MAX || int64_t(nb) * Z > INT32_MAX) {
+        set_error("ldpc_graph_create_qc: mb * Z and nb * Z must be below 2^31");
+        return LDPC_E_INVAL;
+    }
+    if (flags & ~uint32_t(LDPC_GRAPH_HOST_ONLY)) { set_error("ldpc_graph_create_qc: unknown flags"); return LDPC_E_INVAL; }
+    try {
+        QcBase qc;
+        qc.Z = Z;
+        qc.row_ptr.assign(size_t(mb) + 1, 0);
+        for (int32_t i = 0; i < mb; i++) {
+            for (int32_t j = 0; j < nb; j++) {
+                const int32_t s = shifts[size_t(i) * nb + j];
+                if (s < -1 || s >= Z) {
+                    set_error("ldpc_graph_create_qc: shift (" + std::to_string(i) + ", " + std::to_string(j) +
+                              ") = " + std::to_string(s) + " is outside [-1, Z)");
+                    return LDPC_E_RANGE;
+                }
+                if (s >= 0) {
+                    qc.ent.push_back(j * Z);
+                    qc.ent.push_back(s);
+                }
+            }
+            qc.row_ptr[i + 1] = int32_t(qc.ent.size() / 2);
+        }
+        const int64_t E = int64_t(qc.row_ptr[mb]) * Z;
+        if (E > INT32_MAX) { set_error("ldpc_graph_create_qc: more than 2^31 - 1 edges"); return LDPC_E_INVAL; }
+        // the lifted H, check by check, each check's edges in base-column order
+        std::vector<int32_t> rows(static_cast<size_t>(E)), cols(static_cast<size_t>(E));
+        size_t k = 0;
+        for (int32_t i = 0; i < mb; i++) {
+            for (int32_t t = 0; t < Z; t++) {
+                for (int32_t q = qc.row_ptr[i]; q < qc.row_ptr[i + 1]; q++) {
+                    const int32_t u = t + qc.ent[2 * size_t(q) + 1];
+                    rows[k] = i * Z + t;
+                    cols[k] = qc.ent[2 * size_t(q)] + (u >= Z ? u - Z : u);
+                    k++;
+                }
+            }
+        }
+        return build_graph(mb * Z, nb * Z, E, rows.data(), cols.data(), flags, &qc, out);
+    } catch (const std::bad_alloc &) {
+        set_error("ldpc_graph_create_qc: out of host memory");
+        return LDPC_E_NOMEM;
+    }
+}
+
+static ldpc_status build_graph(int32_t m, int32_t n, int64_t nnz, const int32_t *rows, const int32_t *cols,
+                               uint32_t flags, QcBase *qc, ldpc_graph **out) {
     if (!out) { set_error("ldpc_graph_create: out is NULL"); return LDPC_E_INVAL; }
     if (m < 1 || n < 1) { set_error("ldpc_graph_create: m and n must be >= 1"); return LDPC_E_INVAL; }
     if (nnz < 0 || nnz > INT32_MAX) { set_error("ldpc_graph_create: nnz must be in [0, 2^31)"); return LDPC_E_INVAL; }
@@ -178,6 +244,11 @@ extern "C" ldpc_status ldpc_graph_create(int32_t m, int32_t n, int64_t nnz, cons
             if (d > ldpc::kWideRowMax) g->hub_seg_rows++;   // longest first: these lead the class
         }
         g->hub_chunks = g->hub_chunk_base.back();
+        if (qc) {
+            g->qc_Z = qc->Z;
+            g->qc_row_ptr = std::move(qc->row_ptr);
+            g->qc_ent = std::move(qc->ent);
+        }
     } catch (const std::bad_alloc &) {
         delete g;
         set_error("ldpc_graph_create: out of host memory");

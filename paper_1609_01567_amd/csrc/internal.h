@@ -75,9 +75,16 @@ struct ldpc_graph {
     int64_t hub_chunks = 0;
     int32_t hub_seg_rows = 0;                        // hub rows (the first, longest ones) above kWideRowMax
 
+    // Quasi-cyclic codes (ldpc_graph_create_qc): lifting size (0: not quasi-cyclic),
+    // and per base row its entries in edge order as (j * Z, shift) pairs.
+    int32_t qc_Z = 0;
+    std::vector<int32_t> qc_row_ptr;                 // [mb + 1] base-entry offsets
+    std::vector<int32_t> qc_ent;                     // [2 * base entries]
+
     // Device copies.
     int32_t *d_row_ptr = nullptr, *d_col_idx = nullptr;
     int32_t *d_col_ptr = nullptr, *d_csc_to_csr = nullptr;
     int32_t *d_class_rows = nullptr, *d_hub_chunk_base = nullptr, *d_class_rd = nullptr;
+    int32_t *d_qc_row_ptr = nullptr, *d_qc_ent = nullptr;
     int64_t device_bytes = 0;
 };

@@ -30,7 +30,7 @@ COMPACT_TAIL = 1 << 7    # decode only: move the last running frames into smalle
 # graph flags
 GRAPH_HOST_ONLY = 1 << 0
 
-EXPORTED = ("ldpc_graph_create", "ldpc_graph_destroy", "ldpc_graph_info", "ldpc_graph_arrays",
+EXPORTED = ("ldpc_graph_create", "ldpc_graph_create_qc", "ldpc_graph_destroy", "ldpc_graph_info", "ldpc_graph_arrays",
             "ldpc_decode_workspace_size", "ldpc_decode", "ldpc_decode_rule", "ldpc_decode_profiled",
             "ldpc_decode_noalloc", "ldpc_simulate_workspace_size", "ldpc_simulate", "ldpc_simulate_rule",
             "ldpc_status_str", "ldpc_last_error", "ldpc_engine_create", "ldpc_engine_destroy", "ldpc_engine_info",
@@ -100,6 +100,7 @@ def load_library():
     lib = ctypes.CDLL(LIB_PATH)
     P, I32, I64, U32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
     lib.ldpc_graph_create.argtypes = [I32, I32, I64, P, P, U32, ctypes.POINTER(P)]
+    lib.ldpc_graph_create_qc.argtypes = [I32, I32, I32, P, U32, ctypes.POINTER(P)]
     lib.ldpc_graph_destroy.argtypes = [P]
     lib.ldpc_graph_info.argtypes = [P, P, P, P, P, P, P]
     lib.ldpc_graph_arrays.argtypes = [P, P, P, P, P, P]
@@ -113,7 +114,7 @@ def load_library():
                                   ctypes.c_size_t, P]
     lib.ldpc_simulate_rule.argtypes = [P, I32, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint64, I32, U32, P, P, P,
                                        P, ctypes.c_size_t, P]
-    for f in ("ldpc_graph_create", "ldpc_graph_destroy", "ldpc_graph_info", "ldpc_graph_arrays",
+    for f in ("ldpc_graph_create", "ldpc_graph_create_qc", "ldpc_graph_destroy", "ldpc_graph_info", "ldpc_graph_arrays",
               "ldpc_decode_workspace_size", "ldpc_decode", "ldpc_decode_rule", "ldpc_decode_profiled",
               "ldpc_decode_noalloc", "ldpc_simulate_workspace_size", "ldpc_simulate", "ldpc_simulate_rule"):
         getattr(lib, f).restype = ctypes.c_int
@@ -179,6 +180,23 @@ class Graph:
     @classmethod
     def from_code(cls, code, host_only: bool = False) -> "Graph":
         return cls(code.m, code.n, code.rows, code.cols, host_only=host_only)
+
+    @classmethod
+    def from_qc(cls, Z: int, shifts, host_only: bool = False) -> "Graph":
+        """ldpc_graph_create_qc: the code lifted from an [mb][nb] shift table (-1: zero block) by Z."""
+        shifts = np.ascontiguousarray(shifts, dtype=np.int32)
+        if shifts.ndim != 2:
+            raise ValueError("shifts must be a 2-D [mb][nb] array")
+        self = cls.__new__(cls)
+        self._lib = load_library()
+        self._h = ctypes.c_void_p()
+        mb, nb = shifts.shape
+        _check(self._lib.ldpc_graph_create_qc(int(mb), int(nb), int(Z), _np_ptr(shifts),
+                                              GRAPH_HOST_ONLY if host_only else 0, ctypes.byref(self._h)),
+               "ldpc_graph_create_qc")
+        self.m, self.n, self.nnz = int(mb * Z), int(nb * Z), int((shifts >= 0).sum()) * int(Z)
+        self.host_only = host_only
+        return self
 
     @property
     def handle(self):

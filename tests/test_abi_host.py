@@ -97,6 +97,69 @@ def test_graph_create_rejects_bad_input(m, n, rows, cols, status):
     assert ei.value.status == status
 
 
+def _lifted_by_definition(Z, shifts):
+    """COO of the lifted H straight from the definition of a circulant block:
+    row i*Z + t of block (i, j) has its one in column j*Z + ((t + s_ij) mod Z)."""
+    H = np.zeros((shifts.shape[0] * Z, shifts.shape[1] * Z), np.uint8)
+    eye = np.eye(Z, dtype=np.uint8)
+    for i, j in zip(*np.nonzero(shifts >= 0)):
+        H[i * Z:(i + 1) * Z, j * Z:(j + 1) * Z] = np.roll(eye, shifts[i, j], axis=1)
+    return H
+
+
+@pytest.mark.parametrize("Z,mb,nb,seed", [(1, 3, 5, 1), (7, 4, 9, 2), (360, 90, 180, 3)])
+def test_qc_graph_equals_lifted_matrix(Z, mb, nb, seed):
+    rng = np.random.default_rng(seed)
+    shifts = np.where(rng.random((mb, nb)) < 0.35, rng.integers(0, Z, (mb, nb)), -1).astype(np.int32)
+    shifts[np.arange(mb), rng.integers(0, nb, mb)] = rng.integers(0, Z, mb)   # no empty base row
+    g = ldpc.Graph.from_qc(Z, shifts, host_only=True)
+    a = g.arrays()
+    assert g.info()["nnz"] == int((shifts >= 0).sum()) * Z == a["col_idx"].size
+    if Z * nb <= 2000:   # the dense definition for the small cases
+        H = _lifted_by_definition(Z, shifts)
+        rows_csr = np.repeat(np.arange(mb * Z), np.diff(a["row_ptr"]))
+        D = np.zeros_like(H)
+        D[rows_csr, a["col_idx"]] = 1
+        assert (D == H).all() and H.sum() == a["col_idx"].size
+    # the same tables as the COO graph of the lifted code, edges in base-column order within each check
+    rows, cols = [], []
+    for i in range(mb):
+        js = np.nonzero(shifts[i] >= 0)[0]
+        for t in range(Z):
+            rows.extend([i * Z + t] * len(js))
+            cols.extend((js * Z + (t + shifts[i, js]) % Z).tolist())
+    ref = ldpc.Graph(mb * Z, nb * Z, np.array(rows), np.array(cols), host_only=True).arrays()
+    for k in ref:
+        assert (a[k] == ref[k]).all(), k
+
+
+def test_qc_graph_of_the_structured_stand_in_equals_its_coo_graph():
+    code = li.large_qc_code()
+    Z, shifts = code.qc
+    a = ldpc.Graph.from_qc(Z, shifts, host_only=True).arrays()
+    b = ldpc.Graph.from_code(code, host_only=True).arrays()
+    for k in a:
+        assert (a[k] == b[k]).all(), k
+
+
+@pytest.mark.parametrize("mb,nb,Z,shift,status", [
+    (0, 2, 4, 0, ldpc.E_INVAL),
+    (2, 2, 0, 0, ldpc.E_INVAL),
+    (2, 2, 4, 4, ldpc.E_RANGE),
+    (2, 2, 4, -2, ldpc.E_RANGE),
+    (2, 1 << 20, 1 << 12, -1, ldpc.E_INVAL),    # n = nb * Z beyond 2^31
+])
+def test_qc_graph_rejects_bad_input(mb, nb, Z, shift, status):
+    shifts = np.full((max(mb, 1), min(nb, 4)), -1, np.int32)
+    shifts[0, 0] = shift
+    lib = ldpc.load_library()
+    h = ctypes.c_void_p()
+    st = lib.ldpc_graph_create_qc(mb, nb, Z, shifts.ctypes.data, 1, ctypes.byref(h))
+    assert st == status
+    assert not h
+    assert lib.ldpc_graph_create_qc(2, 2, 4, None, 1, ctypes.byref(h)) == ldpc.E_INVAL
+
+
 def test_empty_rows_and_columns_are_accepted():
     g = ldpc.Graph(4, 6, np.array([0, 0, 2], np.int32), np.array([1, 3, 3], np.int32), host_only=True)
     a = g.arrays()

@@ -63,18 +63,17 @@ enum {
     LDPC_LANE_SLOTS_1 = 1u << 3,
     LDPC_LANE_SLOTS_2 = 1u << 4,
     LDPC_LANE_SLOTS_4 = 1u << 5,
-    /* Tail compaction (the ldpc_decode and ldpc_simulate entry points; ignored
-     * with LDPC_NO_EARLY_STOP and below 256 frame slots).  Every
-     * 4 iterations from iteration 8 the call counts the frames still running;
-     * once they fit in half of the slots in use, it copies their state into a
-     * smaller slot range (at most half, then at most a quarter of the slots)
-     * and runs the remaining iterations there, one frame slot per lane, then
-     * copies the posteriors back; once no frame runs it skips the remaining
-     * iterations.  Results are identical.  The call waits on the stream for
-     * each count (the device keeps two iterations of queued work meanwhile),
-     * so it returns only shortly before the decode ends and cannot be
-     * captured into a graph.  The workspace grows by three quarters of the
-     * per-slot state. */
+    /* Tail compaction (the ldpc_decode, ldpc_decode_noalloc and ldpc_simulate
+     * entry points; ignored with LDPC_NO_EARLY_STOP and below 256 frame
+     * slots).  After iteration 8 and every 4 iterations after it, a kernel
+     * counts the frames still running; once they fit in a smaller copy of the
+     * state (at most half, then at most a quarter of the slots, with half and
+     * a quarter of the frame slots per lane), it moves them there and the
+     * remaining iterations run on that copy; the posteriors are copied back
+     * at the end.  Every decision is taken on the device: the call still only
+     * enqueues work, never waits, and can be captured into a graph.  Results
+     * are identical.  The workspace grows by three quarters of the per-slot
+     * state. */
     LDPC_COMPACT_TAIL = 1u << 7
 };
 
@@ -199,8 +198,7 @@ LDPC_API ldpc_status ldpc_decode_workspace_size(const ldpc_graph *g, int32_t fra
  *               256-byte aligned; caller-owned; contents are scratch.
  *  hip_stream   hipStream_t to enqueue on (NULL = default stream).
  *
- * The call only enqueues work and returns (with LDPC_COMPACT_TAIL it also
- * waits for its periodic running-frame counts, see that flag); outputs are
+ * The call only enqueues work and returns (with every flag); outputs are
  * valid once the stream has reached this point.  Inputs must not be modified and outputs
  * must not be read before then.  Errors (returned synchronously; nothing is
  * enqueued): INVAL (bad sizes or pointers, workspace too small or unaligned,
@@ -242,7 +240,6 @@ LDPC_API ldpc_status ldpc_decode_profiled(const ldpc_graph *g, const float *llr_
  * nothing.  Arguments, results and errors are those of ldpc_decode, except:
  *  - frames whose state (ldpc_decode_workspace_size with the same flags)
  *    exceeds LDPC_NOALLOC_SCRATCH_BYTES are refused with RANGE;
- *  - LDPC_COMPACT_TAIL is refused with INVAL (it keeps host memory of its own);
  *  - DEVICE if the array's device address cannot be looked up.
  * Every call on one device uses the same array, which keeps the last call's
  * contents; a call writes every part of it before reading it, so nothing

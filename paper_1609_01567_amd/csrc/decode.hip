@@ -106,7 +106,7 @@ __device__ __forceinline__ void plain_syndrome(const int32_t (&st)[V], const int
 // QC: a quasi-cyclic graph; each edge's bit comes from the row's base entry
 // (QcCols) instead of col_idx, with the class's row ids in `rows`.
 template <int M, int V, int DMAX, int MODE, int RULE, bool QC>
-__global__ __launch_bounds__(256, 4) void check_rows_kernel(
+__device__ __forceinline__ void check_rows_body(
     const int32_t *__restrict__ rd, const int32_t *__restrict__ col_idx,
     int32_t nrows, const CheckL<M, MODE> *__restrict__ L, typename Codec<M>::T *__restrict__ R,
     const int32_t *__restrict__ iters, int32_t *__restrict__ fail, int32_t S, int32_t groups, int32_t syn_iter,
@@ -149,20 +149,34 @@ __global__ __launch_bounds__(256, 4) void check_rows_kernel(
     if (MODE == kIter) plain_syndrome<V>(st, syn, fail, s0, syn_iter);
 }
 
-// Rows of 9..128 edges: WPR wavefronts per (row, slot group), 8-edge chunks,
-// chunk aggregates exchanged through LDS.  A wavefront with more than one
-// chunk recomputes its chunks' inputs in the second phase.
-template <int M, int V, int WPR, int MODE, int RULE>
-__global__ __launch_bounds__(256) void check_chunk_kernel(
+template <int M, int V, int DMAX, int MODE, int RULE, bool QC>
+__global__ __launch_bounds__(256, 4) void check_rows_kernel(
     const int32_t *__restrict__ rd, const int32_t *__restrict__ col_idx,
     int32_t nrows, const CheckL<M, MODE> *__restrict__ L, typename Codec<M>::T *__restrict__ R,
     const int32_t *__restrict__ iters, int32_t *__restrict__ fail, int32_t S, int32_t groups, int32_t syn_iter,
-    float rp) {
+    float rp, const int32_t *__restrict__ rows, const int32_t *__restrict__ qc_row_ptr,
+    const int32_t *__restrict__ qc_ent, int32_t Z) {
+    check_rows_body<M, V, DMAX, MODE, RULE, QC>(rd, col_idx, nrows, L, R, iters, fail, S, groups, syn_iter, rp, rows,
+                                                qc_row_ptr, qc_ent, Z);
+}
+
+// Rows of 9..128 edges: WPR wavefronts per (row, slot group), 8-edge chunks,
+// chunk aggregates exchanged through LDS.  A wavefront with more than one
+// chunk recomputes its chunks' inputs in the second phase.
+// Chunk aggregates of one workgroup of check_chunk_body: 4 / WPR rows.
+template <int WPR>
+constexpr int chunk_share_entries() { return (4 / WPR) * (WPR == 2 ? 2 : 16); }
+
+template <int M, int V, int WPR, int MODE, int RULE>
+__device__ __forceinline__ void check_chunk_body(
+    const int32_t *__restrict__ rd, const int32_t *__restrict__ col_idx,
+    int32_t nrows, const CheckL<M, MODE> *__restrict__ L, typename Codec<M>::T *__restrict__ R,
+    const int32_t *__restrict__ iters, int32_t *__restrict__ fail, int32_t S, int32_t groups, int32_t syn_iter,
+    float rp, ChunkShare<V, chunk_share_entries<WPR>()> &sh) {
     constexpr int C = kRowChunk;
     constexpr int RPB = 4 / WPR;
     constexpr int MAXCH = WPR == 2 ? 2 : 16;
     constexpr int kChunkIn = MODE == kIter ? kInSteady : kInFirst;
-    __shared__ ChunkShare<V, RPB * MAXCH> sh;
     const int lane = threadIdx.x & 63;
     const int wave = wave_uniform(threadIdx.x >> 6);
     const int lr = wave / WPR;
@@ -222,15 +236,24 @@ __global__ __launch_bounds__(256) void check_chunk_kernel(
     }
 }
 
+template <int M, int V, int WPR, int MODE, int RULE>
+__global__ __launch_bounds__(256) void check_chunk_kernel(
+    const int32_t *__restrict__ rd, const int32_t *__restrict__ col_idx,
+    int32_t nrows, const CheckL<M, MODE> *__restrict__ L, typename Codec<M>::T *__restrict__ R,
+    const int32_t *__restrict__ iters, int32_t *__restrict__ fail, int32_t S, int32_t groups, int32_t syn_iter,
+    float rp) {
+    __shared__ ChunkShare<V, chunk_share_entries<WPR>()> sh;
+    check_chunk_body<M, V, WPR, MODE, RULE>(rd, col_idx, nrows, L, R, iters, fail, S, groups, syn_iter, rp, sh);
+}
+
 // Check pass for rows of 129..512 edges: one workgroup of sixteen wavefronts
 // per (row, 64-slot group), one 32-edge chunk per wavefront, chunk aggregates
 // exchanged through LDS (wide_row); every input is read once.
 template <int M, int MODE, int RULE>
-__global__ __launch_bounds__(1024) void check_wide_kernel(
+__device__ __forceinline__ void check_wide_body(
     const int32_t *__restrict__ rd, const int32_t *__restrict__ col_idx, int32_t nrows,
     const CheckL<M, MODE> *__restrict__ L, typename Codec<M>::T *__restrict__ R, const int32_t *__restrict__ iters,
-    int32_t *__restrict__ fail, int32_t S, int32_t groups, int32_t syn_iter, float rp) {
-    __shared__ ChunkShare<1, kWideWaves> sh;
+    int32_t *__restrict__ fail, int32_t S, int32_t groups, int32_t syn_iter, float rp, ChunkShare<1, kWideWaves> &sh) {
     const int lane = threadIdx.x & 63;
     const int wv = wave_uniform(threadIdx.x >> 6);
     const int g = blockIdx.x % groups;
@@ -249,21 +272,29 @@ __global__ __launch_bounds__(1024) void check_wide_kernel(
     if (MODE == kIter && wv == 0 && syn_iter > 0 && active && syn && fail[s] != syn_iter) fail[s] = syn_iter;
 }
 
+template <int M, int MODE, int RULE>
+__global__ __launch_bounds__(1024) void check_wide_kernel(
+    const int32_t *__restrict__ rd, const int32_t *__restrict__ col_idx, int32_t nrows,
+    const CheckL<M, MODE> *__restrict__ L, typename Codec<M>::T *__restrict__ R, const int32_t *__restrict__ iters,
+    int32_t *__restrict__ fail, int32_t S, int32_t groups, int32_t syn_iter, float rp) {
+    __shared__ ChunkShare<1, kWideWaves> sh;
+    check_wide_body<M, MODE, RULE>(rd, col_idx, nrows, L, R, iters, fail, S, groups, syn_iter, rp, sh);
+}
+
 // Check pass for rows longer than 512 edges: one workgroup of four wavefronts
 // per (row, 64-slot group).  The row is cut into 32-edge chunks; each chunk's
 // combined u (its D aggregate), sign parity and syndrome parity go to scratch,
 // one wavefront scans the chunk aggregates into per-chunk exclusive values,
 // and each chunk is then finished with a local prefix/suffix pass.
 template <int M, int MODE, int RULE>
-__global__ __launch_bounds__(256) void check_hub_kernel(
+__device__ __forceinline__ void check_hub_body(
     const int32_t *__restrict__ rd, const int32_t *__restrict__ col_idx,
     int32_t nrows, const int32_t *__restrict__ chunk_base, const CheckL<M, MODE> *__restrict__ L,
     typename Codec<M>::T *__restrict__ R, const int32_t *__restrict__ iters, int32_t *__restrict__ fail,
     int32_t S, int32_t groups, int32_t syn_iter, float *__restrict__ aggD, float *__restrict__ aggPre,
-    int32_t *__restrict__ aggBits, float rp) {
+    int32_t *__restrict__ aggBits, float rp, int32_t (&total_bits)[64]) {
     using Rule = CheckRule<RULE>;
     constexpr int C = ldpc::kHubChunk;
-    __shared__ int32_t total_bits[64];
     const int lane = threadIdx.x & 63;
     const int wv = wave_uniform(threadIdx.x >> 6);
     const int nw = blockDim.x >> 6;
@@ -360,6 +391,18 @@ __global__ __launch_bounds__(256) void check_hub_kernel(
     }
 }
 
+template <int M, int MODE, int RULE>
+__global__ __launch_bounds__(256) void check_hub_kernel(
+    const int32_t *__restrict__ rd, const int32_t *__restrict__ col_idx,
+    int32_t nrows, const int32_t *__restrict__ chunk_base, const CheckL<M, MODE> *__restrict__ L,
+    typename Codec<M>::T *__restrict__ R, const int32_t *__restrict__ iters, int32_t *__restrict__ fail,
+    int32_t S, int32_t groups, int32_t syn_iter, float *__restrict__ aggD, float *__restrict__ aggPre,
+    int32_t *__restrict__ aggBits, float rp) {
+    __shared__ int32_t total_bits[64];
+    check_hub_body<M, MODE, RULE>(rd, col_idx, nrows, chunk_base, L, R, iters, fail, S, groups, syn_iter, aggD, aggPre,
+                                  aggBits, rp, total_bits);
+}
+
 // Bit pass: Lpost = Lch + sum of R over the bit's checks (Algorithm 4); one
 // wavefront per (bit, slot group).  The posterior goes to the check pass's
 // storage `post` (Post<M>) and, when Lpost is not NULL, also to the fp32 array
@@ -368,13 +411,12 @@ __global__ __launch_bounds__(256) void check_hub_kernel(
 // iteration t-1) is finished: its posterior is left as is and the wavefront
 // of bit 0 records iters = t-1.
 template <int M, int V>
-__global__ __launch_bounds__(256) void bit_kernel(const int32_t *__restrict__ col_ptr,
-                                                  const int32_t *__restrict__ csc_to_csr, int32_t n,
-                                                  const float *__restrict__ Lch, const typename Codec<M>::T *__restrict__ R,
-                                                  typename Post<M>::T *__restrict__ post,
-                                                  float *__restrict__ Lpost, int32_t *__restrict__ iters,
-                                                  const int32_t *__restrict__ fail, int32_t S, int32_t groups,
-                                                  int32_t t, int32_t early_stop, float bscale) {
+__device__ __forceinline__ void bit_body(const int32_t *__restrict__ col_ptr, const int32_t *__restrict__ csc_to_csr,
+                                         int32_t n, const float *__restrict__ Lch,
+                                         const typename Codec<M>::T *__restrict__ R,
+                                         typename Post<M>::T *__restrict__ post, float *__restrict__ Lpost,
+                                         int32_t *__restrict__ iters, const int32_t *__restrict__ fail, int32_t S,
+                                         int32_t groups, int32_t t, int32_t early_stop, float bscale) {
     const int lane = threadIdx.x & 63;
     const int wave = wave_uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const int g = wave % groups;
@@ -421,6 +463,17 @@ __global__ __launch_bounds__(256) void bit_kernel(const int32_t *__restrict__ co
             }
         }
     }
+}
+
+template <int M, int V>
+__global__ __launch_bounds__(256) void bit_kernel(const int32_t *__restrict__ col_ptr,
+                                                  const int32_t *__restrict__ csc_to_csr, int32_t n,
+                                                  const float *__restrict__ Lch, const typename Codec<M>::T *__restrict__ R,
+                                                  typename Post<M>::T *__restrict__ post,
+                                                  float *__restrict__ Lpost, int32_t *__restrict__ iters,
+                                                  const int32_t *__restrict__ fail, int32_t S, int32_t groups,
+                                                  int32_t t, int32_t early_stop, float bscale) {
+    bit_body<M, V>(col_ptr, csc_to_csr, n, Lch, R, post, Lpost, iters, fail, S, groups, t, early_stop, bscale);
 }
 
 // Syndrome of the current estimate for every non-empty check (any degree):
@@ -627,93 +680,279 @@ __global__ __launch_bounds__(256) void tally_kernel(const int32_t *__restrict__ 
 // ------------------------------------------------------- tail compaction
 //
 // Once few frames of a call are still running, their state is copied into a
-// smaller slot range (slot k of the copy holds slot map[k] of the full state)
-// and the remaining iterations run there at one slot per lane.  Only the
-// running frames move; the per-frame arithmetic is unchanged, so results are
-// identical.  A frame "runs" while iters[s] == 0.
+// smaller slot range (slot k of the copy holds slot map[k] of the state it
+// came from) and the remaining iterations run there.  Level 0 is the full
+// state (S slots, V per lane); level l = 1, 2 is a copy of S_l <= S >> l slots
+// (a multiple of 64) at V_l = max(1, V >> l) slots per lane, so that no
+// level's grid is larger than the full state's.  The device takes every
+// decision: every few iterations one workgroup counts the running frames and,
+// once they fit a smaller level, lists them and switches the level word; a
+// gather kernel then moves them (it exits at once when no move was decided);
+// every pass kernel after the first count reads the level word and works on
+// that level's state.  Only the running frames move and the per-frame
+// arithmetic is unchanged, so results are identical; the host never waits.
+// A frame runs while iters[s] == 0.
 
-// One workgroup: the running slots in slot order (map) and their number.
-__global__ __launch_bounds__(1024) void running_list_kernel(const int32_t *__restrict__ iters, int32_t S,
-                                                            int32_t *__restrict__ map, int32_t cap,
-                                                            int32_t *__restrict__ count) {
+constexpr int kLevels = 3;
+
+// The state of one level as the kernels address it.
+struct LevelView {
+    float *lch;
+    void *post;       // posterior in the check pass's storage (Post<M>)
+    float *lpost;     // fp32 posterior output (16-bit formats with llr_out), else NULL
+    void *r;
+    int32_t *iters, *fail;
+    int32_t *map;     // slot k of this level holds slot map[k] of the level it came from
+    int32_t S;        // slots (0: the level does not exist)
+    int32_t V;        // slots per lane of the launch's check class (or of the bit pass)
+};
+
+// Every level of a call, and the device word that names the current one.
+struct Levels {
+    LevelView lv[kLevels];
+    const int32_t *level;
+};
+
+// Control words of a call, in its workspace.
+struct LevelCtl {
+    int32_t level;            // the level the running frames are in
+    int32_t from, to;         // the move the last count decided (to < 0: none)
+    int32_t running;          // frames running at the last count
+    int32_t src[kLevels];     // the level each level's frames came from (-1: not entered)
+    int32_t count[kLevels];   // frames moved into each level
+};
+
+__device__ __forceinline__ const LevelView &level_at(const Levels &a, int l) {
+    return l == 0 ? a.lv[0] : l == 1 ? a.lv[1] : a.lv[2];
+}
+
+// The level the frames are in (the same word for the whole grid).
+__device__ __forceinline__ const LevelView &current_level(const Levels &a) {
+    return level_at(a, wave_uniform(cload(a.level)));
+}
+
+// Pass kernels on the current level.  The grid is the full state's for the
+// launch's class; at a smaller level the wavefronts beyond its slot groups
+// exit at once.
+template <int M, int V0, int DMAX, int RULE, bool QC>
+__global__ __launch_bounds__(256, 4) void check_rows_level_kernel(
+    const int32_t *__restrict__ rd, const int32_t *__restrict__ col_idx, int32_t nrows, Levels a, int32_t syn_iter,
+    float rp, const int32_t *__restrict__ rows, const int32_t *__restrict__ qc_row_ptr,
+    const int32_t *__restrict__ qc_ent, int32_t Z) {
+    const LevelView &x = current_level(a);
+    const auto *L = static_cast<const CheckL<M, kIter> *>(x.post);
+    auto *R = static_cast<typename Codec<M>::T *>(x.r);
+    if constexpr (V0 >= 4) {
+        if (x.V == 4) {
+            check_rows_body<M, 4, DMAX, kIter, RULE, QC>(rd, col_idx, nrows, L, R, x.iters, x.fail, x.S, x.S / 256,
+                                                         syn_iter, rp, rows, qc_row_ptr, qc_ent, Z);
+            return;
+        }
+    }
+    if constexpr (V0 >= 2) {
+        if (x.V == 2) {
+            check_rows_body<M, 2, DMAX, kIter, RULE, QC>(rd, col_idx, nrows, L, R, x.iters, x.fail, x.S, x.S / 128,
+                                                         syn_iter, rp, rows, qc_row_ptr, qc_ent, Z);
+            return;
+        }
+    }
+    check_rows_body<M, 1, DMAX, kIter, RULE, QC>(rd, col_idx, nrows, L, R, x.iters, x.fail, x.S, x.S / 64, syn_iter,
+                                                 rp, rows, qc_row_ptr, qc_ent, Z);
+}
+
+template <int M, int V0, int WPR, int RULE>
+__global__ __launch_bounds__(256) void check_chunk_level_kernel(const int32_t *__restrict__ rd,
+                                                                const int32_t *__restrict__ col_idx, int32_t nrows,
+                                                                Levels a, int32_t syn_iter, float rp) {
+    constexpr int NE = chunk_share_entries<WPR>();
+    __shared__ ChunkShare<V0, NE> sh;   // the largest of the levels' shares
+    const LevelView &x = current_level(a);
+    const auto *L = static_cast<const CheckL<M, kIter> *>(x.post);
+    auto *R = static_cast<typename Codec<M>::T *>(x.r);
+    if constexpr (V0 >= 4) {
+        if (x.V == 4) {
+            check_chunk_body<M, 4, WPR, kIter, RULE>(rd, col_idx, nrows, L, R, x.iters, x.fail, x.S, x.S / 256,
+                                                     syn_iter, rp, reinterpret_cast<ChunkShare<4, NE> &>(sh));
+            return;
+        }
+    }
+    if constexpr (V0 >= 2) {
+        if (x.V == 2) {
+            check_chunk_body<M, 2, WPR, kIter, RULE>(rd, col_idx, nrows, L, R, x.iters, x.fail, x.S, x.S / 128,
+                                                     syn_iter, rp, reinterpret_cast<ChunkShare<2, NE> &>(sh));
+            return;
+        }
+    }
+    check_chunk_body<M, 1, WPR, kIter, RULE>(rd, col_idx, nrows, L, R, x.iters, x.fail, x.S, x.S / 64, syn_iter, rp,
+                                             reinterpret_cast<ChunkShare<1, NE> &>(sh));
+}
+
+template <int M, int RULE>
+__global__ __launch_bounds__(1024) void check_wide_level_kernel(const int32_t *__restrict__ rd,
+                                                                const int32_t *__restrict__ col_idx, int32_t nrows,
+                                                                Levels a, int32_t syn_iter, float rp) {
+    __shared__ ChunkShare<1, kWideWaves> sh;
+    const LevelView &x = current_level(a);
+    check_wide_body<M, kIter, RULE>(rd, col_idx, nrows, static_cast<const CheckL<M, kIter> *>(x.post),
+                                    static_cast<typename Codec<M>::T *>(x.r), x.iters, x.fail, x.S, x.S / 64,
+                                    syn_iter, rp, sh);
+}
+
+template <int M, int RULE>
+__global__ __launch_bounds__(256) void check_hub_level_kernel(
+    const int32_t *__restrict__ rd, const int32_t *__restrict__ col_idx, int32_t nrows,
+    const int32_t *__restrict__ chunk_base, Levels a, int32_t syn_iter, float *__restrict__ aggD,
+    float *__restrict__ aggPre, int32_t *__restrict__ aggBits, float rp) {
+    __shared__ int32_t total_bits[64];
+    const LevelView &x = current_level(a);
+    check_hub_body<M, kIter, RULE>(rd, col_idx, nrows, chunk_base, static_cast<const CheckL<M, kIter> *>(x.post),
+                                   static_cast<typename Codec<M>::T *>(x.r), x.iters, x.fail, x.S, x.S / 64,
+                                   syn_iter, aggD, aggPre, aggBits, rp, total_bits);
+}
+
+template <int M, int V0>
+__global__ __launch_bounds__(256) void bit_level_kernel(const int32_t *__restrict__ col_ptr,
+                                                        const int32_t *__restrict__ csc_to_csr, int32_t n, Levels a,
+                                                        int32_t t, int32_t early_stop, float bscale) {
+    const LevelView &x = current_level(a);
+    const auto *R = static_cast<const typename Codec<M>::T *>(x.r);
+    auto *post = static_cast<typename Post<M>::T *>(x.post);
+    if constexpr (V0 >= 4) {
+        if (x.V == 4) {
+            bit_body<M, 4>(col_ptr, csc_to_csr, n, x.lch, R, post, x.lpost, x.iters, x.fail, x.S, x.S / 256, t,
+                           early_stop, bscale);
+            return;
+        }
+    }
+    if constexpr (V0 >= 2) {
+        if (x.V == 2) {
+            bit_body<M, 2>(col_ptr, csc_to_csr, n, x.lch, R, post, x.lpost, x.iters, x.fail, x.S, x.S / 128, t,
+                           early_stop, bscale);
+            return;
+        }
+    }
+    bit_body<M, 1>(col_ptr, csc_to_csr, n, x.lch, R, post, x.lpost, x.iters, x.fail, x.S, x.S / 64, t, early_stop,
+                   bscale);
+}
+
+// One workgroup: counts the frames running at the current level and, when
+// they fit a smaller level (the smallest that holds them), lists them in slot
+// order into that level's map and switches the level word.
+__global__ __launch_bounds__(1024) void level_decide_kernel(LevelCtl *__restrict__ ctl, Levels a) {
     __shared__ int32_t part[16];
     __shared__ int32_t base;
-    if (threadIdx.x == 0) base = 0;
+    const int l = ctl->level;
+    const LevelView &x = level_at(a, l);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    // count
+    int32_t mine = 0;
+    for (int s = threadIdx.x; s < x.S; s += blockDim.x) mine += x.iters[s] == 0;
+    for (int o = 32; o > 0; o >>= 1) mine += __shfl_xor(mine, o);
+    if (lane == 0) part[w] = mine;
     __syncthreads();
-    for (int s0 = 0; s0 < S; s0 += blockDim.x) {
-        const int s = s0 + int(threadIdx.x);
-        const bool run = s < S && iters[s] == 0;
-        const uint64_t m = __ballot(run);
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        if (lane == 0) part[w] = __popcll(m);
-        __syncthreads();
-        int before = base;
-        for (int i = 0; i < w; i++) before += part[i];
-        const int idx = before + __popcll(m & ((uint64_t(1) << lane) - 1u));
-        if (run && map && idx < cap) map[idx] = s;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int tot = 0;
-            for (int i = 0; i < int(blockDim.x >> 6); i++) tot += part[i];
-            base += tot;
+    int32_t K = 0;
+    for (int i = 0; i < nw; i++) K += part[i];
+    int to = -1;
+    for (int c = kLevels - 1; c > l; c--) {
+        if (K > 0 && level_at(a, c).S > 0 && K <= level_at(a, c).S) {
+            to = c;
+            break;
         }
+    }
+    if (to >= 0) {
+        // list: running slots in slot order
+        int32_t *map = level_at(a, to).map;
+        if (threadIdx.x == 0) base = 0;
         __syncthreads();
+        for (int s0 = 0; s0 < x.S; s0 += blockDim.x) {
+            const int s = s0 + int(threadIdx.x);
+            const bool run = s < x.S && x.iters[s] == 0;
+            const uint64_t m = __ballot(run);
+            if (lane == 0) part[w] = __popcll(m);
+            __syncthreads();
+            int before = base;
+            for (int i = 0; i < w; i++) before += part[i];
+            if (run) map[before + __popcll(m & ((uint64_t(1) << lane) - 1u))] = s;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int tot = 0;
+                for (int i = 0; i < nw; i++) tot += part[i];
+                base += tot;
+            }
+            __syncthreads();
+        }
     }
     if (threadIdx.x == 0) {
-        *count = base;
-        __threadfence_system();   // `count` may be a host word read once the stream reaches an event
-    }
-}
-
-// Copy rows of [rows][S] state into [rows][Sc]: element (r, k) takes
-// src[r][map[k]] for k < count, 0 above.  W is the element type.
-template <typename W>
-__global__ __launch_bounds__(256) void gather_slots_kernel(const W *__restrict__ src, int32_t S, W *__restrict__ dst,
-                                                           int32_t Sc, int64_t rows, const int32_t *__restrict__ map,
-                                                           const int32_t *__restrict__ count) {
-    const int32_t K = min(*count, Sc);
-    const int64_t total = rows * Sc;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x) {
-        const int64_t r = i / Sc;
-        const int k = int(i - r * Sc);
-        dst[i] = k < K ? src[r * S + map[k]] : W(0);
-    }
-}
-
-// Per-slot state of the copy: running frames keep their fail marks; the
-// slots above count are padding.
-__global__ __launch_bounds__(256) void gather_state_kernel(const int32_t *__restrict__ fail, int32_t Sc,
-                                                           const int32_t *__restrict__ map,
-                                                           const int32_t *__restrict__ count, int32_t *__restrict__ c_iters,
-                                                           int32_t *__restrict__ c_fail) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= Sc) return;
-    const bool live = k < *count;
-    c_iters[k] = live ? 0 : kPadSlot;
-    c_fail[k] = live ? fail[map[k]] : 0;
-}
-
-// Back to the full state: posterior rows, iteration counts and fail marks of
-// the moved frames (the messages are not needed after the last iteration).
-template <typename PT>
-__global__ __launch_bounds__(256) void scatter_slots_kernel(const PT *__restrict__ c_lpost, int32_t Sc,
-                                                            PT *__restrict__ lpost, int32_t S, int64_t n,
-                                                            const int32_t *__restrict__ c_iters,
-                                                            const int32_t *__restrict__ c_fail, int32_t *__restrict__ iters,
-                                                            int32_t *__restrict__ fail, const int32_t *__restrict__ map,
-                                                            const int32_t *__restrict__ count) {
-    const int32_t K = min(*count, Sc);
-    const int64_t total = n * Sc;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x) {
-        const int64_t v = i / Sc;
-        const int k = int(i - v * Sc);
-        if (k < K) {
-            lpost[v * S + map[k]] = c_lpost[i];
-            if (v == 0 && c_iters) {
-                iters[map[k]] = c_iters[k];
-                fail[map[k]] = c_fail[k];
-            }
+        ctl->running = K;
+        ctl->to = to;
+        if (to >= 0) {
+            ctl->from = l;
+            ctl->src[to] = l;
+            ctl->count[to] = K;
+            ctl->level = to;
         }
+    }
+}
+
+// dst[r][k] = src[r][map[k]] for k < K, 0 above (rows x St elements).
+template <typename W>
+__device__ __forceinline__ void gather_rows(const W *__restrict__ src, int32_t Sf, W *__restrict__ dst, int32_t St,
+                                            int64_t rows, const int32_t *__restrict__ map, int32_t K) {
+    const int64_t total = rows * St;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t r = i / St;
+        const int k = int(i - r * St);
+        dst[i] = k < K ? src[r * Sf + map[k]] : W(0);
+    }
+}
+
+// The move the last count decided, if any: messages, channel LLRs, posteriors
+// and fail marks of the running frames into the new level; its slots above
+// the running count are padding.
+template <typename W, typename PW>
+__global__ __launch_bounds__(256) void level_move_kernel(const LevelCtl *__restrict__ ctl, Levels a, int64_t E,
+                                                         int64_t n, int32_t keep32) {
+    const int to = wave_uniform(cload(&ctl->to));
+    if (to < 0) return;
+    const int from = wave_uniform(cload(&ctl->from));
+    const int32_t K = wave_uniform(cload(&ctl->count[to]));
+    const LevelView &f = level_at(a, from);
+    const LevelView &d = level_at(a, to);
+    gather_rows<W>(static_cast<const W *>(f.r), f.S, static_cast<W *>(d.r), d.S, E, d.map, K);
+    gather_rows<float>(f.lch, f.S, d.lch, d.S, n, d.map, K);
+    gather_rows<PW>(static_cast<const PW *>(f.post), f.S, static_cast<PW *>(d.post), d.S, n, d.map, K);
+    if (keep32) gather_rows<float>(f.lpost, f.S, d.lpost, d.S, n, d.map, K);
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < d.S; k += gridDim.x * blockDim.x) {
+        d.iters[k] = k < K ? 0 : kPadSlot;
+        d.fail[k] = k < K ? f.fail[d.map[k]] : 0;
+    }
+}
+
+// Level l back into the level its frames came from, if it was entered:
+// posteriors, iteration counts and fail marks (messages are not needed after
+// the last iteration).  Deeper levels go first.
+template <typename PT>
+__global__ __launch_bounds__(256) void level_scatter_kernel(const LevelCtl *__restrict__ ctl, Levels a, int32_t l,
+                                                            int64_t n, int32_t keep32) {
+    const int up = wave_uniform(cload(&ctl->src[l]));
+    if (up < 0) return;
+    const int32_t K = wave_uniform(cload(&ctl->count[l]));
+    const LevelView &x = level_at(a, l);
+    const LevelView &u = level_at(a, up);
+    const int64_t total = n * x.S;
+    const PT *xp = static_cast<const PT *>(x.post);
+    PT *upost = static_cast<PT *>(u.post);
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t v = i / x.S;
+        const int k = int(i - v * x.S);
+        if (k < K) {
+            upost[v * u.S + x.map[k]] = xp[i];
+            if (keep32) u.lpost[v * u.S + x.map[k]] = x.lpost[i];
+        }
+    }
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < K; k += gridDim.x * blockDim.x) {
+        u.iters[x.map[k]] = x.iters[k];
+        u.fail[x.map[k]] = x.fail[k];
     }
 }
 
@@ -725,13 +964,12 @@ struct Plan {
     size_t off_aggd = 0, off_aggpre = 0, off_aggbits = 0, total = 0;
     size_t off_err = 0, off_it = 0, off_ok = 0;   // Monte-Carlo runs only
     // tail compaction (LDPC_COMPACT_TAIL): two copies of the state, for S/2
-    // and S/4 slots (level 1 and 2), and the word the running counts go through
+    // and S/4 slots (level 1 and 2), and the control words (LevelCtl)
     struct Level {
         int32_t Sc = 0;
-        size_t off_lch = 0, off_lpost = 0, off_post = 0, off_r = 0, off_iters = 0, off_fail = 0, off_map = 0,
-               off_count = 0;
+        size_t off_lch = 0, off_lpost = 0, off_post = 0, off_r = 0, off_iters = 0, off_fail = 0, off_map = 0;
     } lv[2];
-    size_t off_probe = 0;
+    size_t off_ctl = 0;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -776,9 +1014,8 @@ Plan make_plan(const ldpc_graph *g, int32_t F, uint32_t flags, bool sim = false)
         p.off_it = off;  off = align256(off + S * 4);
         p.off_ok = off;  off = align256(off + S);
     }
-    // Pools below 256 slots are left as they are.  The copies' capacities
-    // (S/2, S/4) need not be multiples of 64: the slot count a compaction
-    // uses is the running count rounded up to 64, and it must fit.
+    // Pools below 256 slots are left as they are.  A copy uses the largest
+    // multiple of 64 slots within its capacity (S/2, S/4).
     if ((flags & LDPC_COMPACT_TAIL) && !(flags & LDPC_NO_EARLY_STOP) && p.S >= 256) {
         for (int l = 0; l < 2; l++) {
             Plan::Level &L = p.lv[l];
@@ -792,9 +1029,8 @@ Plan make_plan(const ldpc_graph *g, int32_t F, uint32_t flags, bool sim = false)
             L.off_iters = off; off = align256(off + Sc * 4);
             L.off_fail = off;  off = align256(off + Sc * 4);
             L.off_map = off;   off = align256(off + Sc * 4);
-            L.off_count = off; off = align256(off + 4);
         }
-        p.off_probe = off; off = align256(off + 4);
+        p.off_ctl = off; off = align256(off + sizeof(LevelCtl));
     }
     p.total = off;
     return p;
@@ -957,89 +1193,166 @@ struct SimRun {
     ldpc_sim_counts *counts = nullptr;
 };
 
-// State copies of the compacted tail (LDPC_COMPACT_TAIL) and the pinned word the
-// running-frame counts come back through (one per host thread, kept for the
-// thread's lifetime; a call waits for its last count before it returns).
-struct CompactLevel {
-    Bufs b;                       // lch, lpost, r, iters, fail of the copy; hub scratch shared
-    int32_t Sc = 0;               // capacity in slots
-    int32_t *map = nullptr;       // slot k of the copy holds slot map[k] of the level above
-    int32_t *count = nullptr;     // frames moved in
-};
-
-struct Compact {
+// The levels of a call's tail compaction (LDPC_COMPACT_TAIL): views of the
+// full state and of its copies, and the control words.  Off when the plan has
+// no copies (too few slots, no early stop).
+struct LevelSet {
     bool on = false;
-    CompactLevel lv[2];
-    int32_t *probe = nullptr;     // device word of the periodic counts
-    int32_t *host_count = nullptr;
-    int32_t *host_count_dev = nullptr;   // the host word as the device addresses it (null: copy from probe)
+    Levels a{};                 // views; V is per launch (with_class_v)
+    int32_t V[kLevels] = {};    // slots per lane of the register rows and the bit pass
+    LevelCtl *ctl = nullptr;
 };
 
-int32_t *pinned_count_word() {
-    static thread_local int32_t *word = nullptr;
-    if (!word) {
-        void *h = nullptr;
-        // portable: a thread may decode on several devices; mapped and coherent: the
-        // count kernel stores into it directly
-        if (hipHostMalloc(&h, 256, hipHostMallocPortable | hipHostMallocMapped | hipHostMallocCoherent) !=
-            hipSuccess) {
-            (void)hipGetLastError();
-            return nullptr;
-        }
-        word = static_cast<int32_t *>(h);
-    }
-    return word;
-}
-
-Compact compact_at(const Plan &p, const Bufs &b, bool wanted) {
-    Compact c;
-    if (!wanted || p.lv[0].Sc == 0 || !b.base) return c;
+LevelSet level_set(const Plan &p, const Bufs &b, bool wanted, bool keep32) {
+    LevelSet ls;
+    if (!wanted || p.lv[0].Sc == 0 || !b.base) return ls;
     char *ws = b.base;
-    for (int l = 0; l < 2; l++) {
-        const Plan::Level &L = p.lv[l];
-        CompactLevel &C = c.lv[l];
-        C.b = b;
-        C.b.lch = reinterpret_cast<float *>(ws + L.off_lch);
-        C.b.lpost = reinterpret_cast<float *>(ws + L.off_lpost);
-        C.b.post = ws + L.off_post;
-        C.b.r = ws + L.off_r;
-        C.b.iters = reinterpret_cast<int32_t *>(ws + L.off_iters);
-        C.b.fail = reinterpret_cast<int32_t *>(ws + L.off_fail);
-        C.Sc = L.Sc;
-        C.map = reinterpret_cast<int32_t *>(ws + L.off_map);
-        C.count = reinterpret_cast<int32_t *>(ws + L.off_count);
+    LevelView &z = ls.a.lv[0];
+    z.lch = b.lch;
+    z.post = b.post;
+    z.lpost = keep32 ? b.lpost : nullptr;
+    z.r = b.r;
+    z.iters = b.iters;
+    z.fail = b.fail;
+    z.map = nullptr;
+    z.S = p.S;
+    ls.V[0] = p.V;
+    for (int l = 1; l < kLevels; l++) {
+        const Plan::Level &L = p.lv[l - 1];
+        LevelView &x = ls.a.lv[l];
+        x.lch = reinterpret_cast<float *>(ws + L.off_lch);
+        x.post = ws + L.off_post;
+        x.lpost = keep32 ? reinterpret_cast<float *>(ws + L.off_lpost) : nullptr;
+        x.r = ws + L.off_r;
+        x.iters = reinterpret_cast<int32_t *>(ws + L.off_iters);
+        x.fail = reinterpret_cast<int32_t *>(ws + L.off_fail);
+        x.map = reinterpret_cast<int32_t *>(ws + L.off_map);
+        x.S = L.Sc / 64 * 64;
+        int v = std::max(1, p.V >> l);
+        if (x.S % (64 * v) != 0) v = 1;
+        ls.V[l] = v;
+        if (x.S < 64) x.S = 0;
     }
-    c.probe = reinterpret_cast<int32_t *>(ws + p.off_probe);
-    c.host_count = pinned_count_word();
-    c.on = c.host_count != nullptr;
-    // the count kernel writes the host word directly when the device can address it
-    if (c.on && hipHostGetDevicePointer(reinterpret_cast<void **>(&c.host_count_dev), c.host_count, 0) != hipSuccess) {
-        (void)hipGetLastError();
-        c.host_count_dev = nullptr;
-    }
-    return c;
+    ls.ctl = reinterpret_cast<LevelCtl *>(ws + p.off_ctl);
+    ls.a.level = &ls.ctl->level;
+    ls.on = ls.a.lv[1].S > 0;
+    return ls;
 }
 
-// List the running frames of `from` (S slots; at most Sp of them run: frames
-// only ever stop) and copy their messages, channel and posterior LLRs and fail
-// marks into the first Sp slots of `to`.
-template <int M>
-void enqueue_compaction(const ldpc_graph *g, const Bufs &from, int32_t S, const CompactLevel &to, int32_t Sp,
-                        bool keep32, hipStream_t st) {
-    using W = typename Raw<sizeof(typename Codec<M>::T)>::T;
-    using PW = typename Raw<sizeof(typename Post<M>::T)>::T;
-    hipLaunchKernelGGL(running_list_kernel, dim3(1), dim3(1024), 0, st, from.iters, S, to.map, Sp, to.count);
-    hipLaunchKernelGGL((gather_slots_kernel<W>), dim3(4096), dim3(256), 0, st, static_cast<const W *>(from.r), S,
-                       static_cast<W *>(to.b.r), Sp, int64_t(g->E), to.map, to.count);
-    hipLaunchKernelGGL((gather_slots_kernel<float>), dim3(2048), dim3(256), 0, st, from.lch, S, to.b.lch, Sp,
-                       int64_t(g->n), to.map, to.count);
-    hipLaunchKernelGGL((gather_slots_kernel<PW>), dim3(2048), dim3(256), 0, st, static_cast<const PW *>(from.post), S,
-                       static_cast<PW *>(to.b.post), Sp, int64_t(g->n), to.map, to.count);
-    if (keep32)
-        hipLaunchKernelGGL((gather_slots_kernel<float>), dim3(2048), dim3(256), 0, st, from.lpost, S, to.b.lpost, Sp,
-                           int64_t(g->n), to.map, to.count);
-    hipLaunchKernelGGL(gather_state_kernel, dim3(unsigned((Sp + 255) / 256)), dim3(256), 0, st, from.fail, Sp,
-                       to.map, to.count, to.b.iters, to.b.fail);
+// The views with the slots per lane of check class `cls` (every level's grid
+// must fit in the full state's: checked by the caller through fits()).
+Levels with_class_v(const LevelSet &ls, int cls) {
+    Levels a = ls.a;
+    for (int l = 0; l < kLevels; l++) a.lv[l].V = cls < 0 ? ls.V[l] : ldpc::class_lane_slots(cls, ls.V[l]);
+    return a;
+}
+
+bool fits(const Levels &a) {
+    for (int l = 1; l < kLevels; l++)
+        if (a.lv[l].S > 0 && (a.lv[l].S % (64 * a.lv[l].V) != 0 ||
+                              int64_t(a.lv[l].S) * a.lv[0].V > int64_t(a.lv[0].S) * a.lv[l].V))
+            return false;
+    return true;
+}
+
+__global__ __launch_bounds__(64) void level_init_kernel(LevelCtl *ctl) {
+    if (threadIdx.x == 0) {
+        ctl->level = 0;
+        ctl->from = 0;
+        ctl->to = -1;
+        ctl->running = -1;
+        for (int l = 0; l < kLevels; l++) {
+            ctl->src[l] = -1;
+            ctl->count[l] = 0;
+        }
+    }
+}
+
+// The check pass on the current level (iterations after the first count).
+template <int M, int V, int RULE>
+void launch_check_pass_levels(const ldpc_graph *g, const LevelSet &ls, int32_t syn_iter, float rp, const Bufs &b,
+                              hipStream_t st) {
+    const int32_t S = ls.a.lv[0].S;
+    {
+        constexpr int cls = ldpc::kClassD8;
+        const int32_t nrows = g->class_begin[cls + 1] - g->class_begin[cls];
+        if (nrows > 0) {
+            const Levels a = with_class_v(ls, cls);
+            const unsigned blocks = blocks_for_waves(int64_t(nrows) * (S / (64 * V)));
+            const int32_t *rd = g->d_class_rd + 2 * g->class_begin[cls];
+            const bool qc = RULE == kRuleSP && g->qc_Z > 0;
+            if (qc)
+                hipLaunchKernelGGL((check_rows_level_kernel<M, V, 8, RULE, true>), dim3(blocks), dim3(256), 0, st, rd,
+                                   g->d_col_idx, nrows, a, syn_iter, rp, g->d_class_rows + g->class_begin[cls],
+                                   g->d_qc_row_ptr, g->d_qc_ent, g->qc_Z);
+            else
+                hipLaunchKernelGGL((check_rows_level_kernel<M, V, 8, RULE, false>), dim3(blocks), dim3(256), 0, st,
+                                   rd, g->d_col_idx, nrows, a, syn_iter, rp, nullptr, nullptr, nullptr, 0);
+        }
+    }
+    {
+        constexpr int cls = ldpc::kClassD16;
+        constexpr int V16 = ldpc::class_lane_slots(cls, V);
+        const int32_t nrows = g->class_begin[cls + 1] - g->class_begin[cls];
+        if (nrows > 0) {
+            const Levels a = with_class_v(ls, cls);
+            const unsigned blocks = blocks_for_waves(int64_t(nrows) * (S / (64 * V16)));
+            const int32_t *rd = g->d_class_rd + 2 * g->class_begin[cls];
+            const bool qc = RULE == kRuleSP && g->qc_Z > 0;
+            if (qc)
+                hipLaunchKernelGGL((check_rows_level_kernel<M, V16, 16, RULE, true>), dim3(blocks), dim3(256), 0, st,
+                                   rd, g->d_col_idx, nrows, a, syn_iter, rp, g->d_class_rows + g->class_begin[cls],
+                                   g->d_qc_row_ptr, g->d_qc_ent, g->qc_Z);
+            else
+                hipLaunchKernelGGL((check_rows_level_kernel<M, V16, 16, RULE, false>), dim3(blocks), dim3(256), 0, st,
+                                   rd, g->d_col_idx, nrows, a, syn_iter, rp, nullptr, nullptr, nullptr, 0);
+        }
+    }
+    {
+        constexpr int cls = ldpc::kClassD128;
+        constexpr int WPR = ldpc::class_waves_per_row(cls);
+        const int32_t nrows = g->class_begin[cls + 1] - g->class_begin[cls];
+        if (nrows > 0) {
+            const Levels a = with_class_v(ls, cls);
+            const int64_t items = int64_t(nrows) * (S / (64 * V));
+            const unsigned blocks = unsigned((items + (4 / WPR) - 1) / (4 / WPR));
+            hipLaunchKernelGGL((check_chunk_level_kernel<M, V, WPR, RULE>), dim3(blocks), dim3(256), 0, st,
+                               g->d_class_rd + 2 * g->class_begin[cls], g->d_col_idx, nrows, a, syn_iter, rp);
+        }
+    }
+    {
+        const int32_t nrows = g->class_begin[ldpc::kClassHub + 1] - g->class_begin[ldpc::kClassHub];
+        if (nrows > 0) {
+            const Levels a = with_class_v(ls, ldpc::kClassHub);
+            const int32_t groups = S / 64;
+            const int32_t *rd = g->d_class_rd + 2 * g->class_begin[ldpc::kClassHub];
+            const int32_t nseg = g->hub_seg_rows, nwide = nrows - nseg;
+            if (nseg > 0)
+                hipLaunchKernelGGL((check_hub_level_kernel<M, RULE>), dim3(unsigned(int64_t(nseg) * groups)),
+                                   dim3(256), 0, st, rd, g->d_col_idx, nseg, g->d_hub_chunk_base, a, syn_iter, b.aggd,
+                                   b.aggpre, b.aggbits, rp);
+            if (nwide > 0)
+                hipLaunchKernelGGL((check_wide_level_kernel<M, RULE>), dim3(unsigned(int64_t(nwide) * groups)),
+                                   dim3(64 * kWideWaves), 0, st, rd + 2 * nseg, g->d_col_idx, nwide, a, syn_iter, rp);
+        }
+    }
+}
+
+template <int M, int V>
+void launch_check_pass_levels_rule(const ldpc_graph *g, const LevelSet &ls, int32_t syn_iter, const RuleSel &rule,
+                                   const Bufs &b, hipStream_t st) {
+    switch (rule.kind) {
+        case kRuleNMS: launch_check_pass_levels<M, V, kRuleNMS>(g, ls, syn_iter, rule.param, b, st); break;
+        case kRuleOMS: launch_check_pass_levels<M, V, kRuleOMS>(g, ls, syn_iter, rule.param, b, st); break;
+        default: launch_check_pass_levels<M, V, kRuleSP>(g, ls, syn_iter, 0.f, b, st); break;
+    }
+}
+
+// Every launch class of the decode fits the level grid rule.
+bool level_set_fits(const LevelSet &ls) {
+    return fits(with_class_v(ls, -1)) && fits(with_class_v(ls, ldpc::kClassD8)) &&
+           fits(with_class_v(ls, ldpc::kClassD16)) && fits(with_class_v(ls, ldpc::kClassD128)) &&
+           fits(with_class_v(ls, ldpc::kClassHub));
 }
 
 template <int M, int V>
@@ -1071,52 +1384,22 @@ void run_decode(const ldpc_graph *g, const Plan &p, const Bufs &b, const float *
     mk.mark(1, st);
     const unsigned bit_blocks = blocks_for_waves(int64_t(g->n) * groups);
 
-    // Tail compaction: every kEvery iterations a one-workgroup kernel counts
-    // the running frames into pinned host memory; the host reads the count
-    // kLag iterations later (the device is then still busy with those).  Once
-    // the running frames fit in half of the current slots (and in the next
-    // copy), it moves them into that copy: S -> at most S/2 -> at most S/4.
-    constexpr int32_t kFirstCheck = 8, kEvery = 4, kLag = 2;
-    Compact cp = compact_at(p, b, early_stop);
-    hipEvent_t ev = nullptr;
-    if (cp.on && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
-        (void)hipGetLastError();
-        cp.on = false;
-    }
-    int level = 0;                // 0: the full state; 1, 2: the copies
-    int32_t Sl[3] = {S, 0, 0};    // slots in use at each level
-    int32_t check = 0;            // iteration after which a count is in flight (0: none)
+    // Tail compaction: after iteration kFirstCheck and every kEvery
+    // iterations after it, the device counts the running frames and moves
+    // them into a smaller level once they fit one; the passes after the first
+    // count run on whichever level the frames are in.
+    constexpr int32_t kFirstCheck = 8, kEvery = 4;
+    LevelSet ls = level_set(p, b, early_stop, keep32);
+    if (ls.on && !level_set_fits(ls)) ls.on = false;
+    if (ls.on) hipLaunchKernelGGL(level_init_kernel, dim3(1), dim3(64), 0, st, ls.ctl);
+    const Levels bit_levels = with_class_v(ls, -1);
     for (int32_t t = 1; t <= T; t++) {
         const int32_t syn_iter = (early_stop && t > 1) ? t - 1 : 0;
-        if (check > 0 && t == check + kLag + 1) {
-            check = 0;
-            int32_t K = -1;
-            if (hipEventSynchronize(ev) == hipSuccess) K = *cp.host_count;
-            (void)hipGetLastError();
-            if (K == 0) {   // every frame has stopped: the remaining iterations have no work
-                for (int32_t u = t; u <= T; u++) {
-                    mk.mark(2 * u, st);
-                    mk.mark(2 * u + 1, st);
-                }
-                break;
-            }
-            const int32_t need = (K + 63) / 64 * 64;
-            if (K > 0 && level < 2 && need <= cp.lv[level].Sc && 2 * need <= Sl[level]) {
-                const Bufs &from = level == 0 ? b : cp.lv[level - 1].b;
-                enqueue_compaction<M>(g, from, Sl[level], cp.lv[level], need, keep32, st);
-                level++;
-                Sl[level] = need;
-            }
-        }
-        if (level > 0) {
-            const Bufs &cb = cp.lv[level - 1].b;
-            const int32_t Sp = Sl[level];
-            launch_check_pass_rule<M, 1>(g, kIter, cb.post, cb, Sp, syn_iter, rule, st);
+        if (ls.on && t > kFirstCheck) {
+            launch_check_pass_levels_rule<M, V>(g, ls, syn_iter, rule, b, st);
             mk.mark(2 * t, st);
-            hipLaunchKernelGGL((bit_kernel<M, 1>), dim3(blocks_for_waves(int64_t(g->n) * (Sp / 64))), dim3(256), 0, st,
-                               g->d_col_ptr, g->d_csc_to_csr, g->n, cb.lch, static_cast<const MT *>(cb.r),
-                               static_cast<PT *>(cb.post), keep32 ? cb.lpost : nullptr,
-                               cb.iters, cb.fail, Sp, Sp / 64, t, int32_t(early_stop), bscale);
+            hipLaunchKernelGGL((bit_level_kernel<M, V>), dim3(bit_blocks), dim3(256), 0, st, g->d_col_ptr,
+                               g->d_csc_to_csr, g->n, bit_levels, t, int32_t(early_stop), bscale);
             mk.mark(2 * t + 1, st);
         } else {
             const void *L1 = kPost16<M> ? b.post : static_cast<const void *>(b.lch);
@@ -1129,35 +1412,19 @@ void run_decode(const ldpc_graph *g, const Plan &p, const Bufs &b, const float *
                                int32_t(early_stop), bscale);
             mk.mark(2 * t + 1, st);
         }
-        if (cp.on && check == 0 && t >= kFirstCheck && t % kEvery == 0 && t + kLag + 2 <= T) {
-            const int32_t *it_now = level == 0 ? b.iters : cp.lv[level - 1].b.iters;
-            hipLaunchKernelGGL(running_list_kernel, dim3(1), dim3(1024), 0, st, it_now, Sl[level], nullptr, 0,
-                               cp.host_count_dev ? cp.host_count_dev : cp.probe);
-            if ((cp.host_count_dev ||
-                 hipMemcpyAsync(cp.host_count, cp.probe, sizeof(int32_t), hipMemcpyDeviceToHost, st) == hipSuccess) &&
-                hipEventRecord(ev, st) == hipSuccess) {
-                check = t;
-            } else {
-                (void)hipGetLastError();
-                cp.on = false;
-            }
+        if (ls.on && t >= kFirstCheck && (t - kFirstCheck) % kEvery == 0 && t < T) {
+            using W = typename Raw<sizeof(MT)>::T;
+            using PW = typename Raw<sizeof(PT)>::T;
+            hipLaunchKernelGGL(level_decide_kernel, dim3(1), dim3(1024), 0, st, ls.ctl, ls.a);
+            hipLaunchKernelGGL((level_move_kernel<W, PW>), dim3(2048), dim3(256), 0, st, ls.ctl, ls.a, int64_t(g->E),
+                               int64_t(g->n), int32_t(keep32));
         }
     }
-    // posteriors, iteration counts and fail marks back up the levels
-    for (int l = level; l > 0; l--) {
-        const CompactLevel &C = cp.lv[l - 1];
-        const Bufs &up = l == 1 ? b : cp.lv[l - 2].b;
-        hipLaunchKernelGGL((scatter_slots_kernel<PT>), dim3(2048), dim3(256), 0, st, static_cast<const PT *>(C.b.post),
-                           Sl[l], static_cast<PT *>(up.post), Sl[l - 1], int64_t(g->n), C.b.iters, C.b.fail, up.iters,
-                           up.fail, C.map, C.count);
-        if (keep32)
-            hipLaunchKernelGGL((scatter_slots_kernel<float>), dim3(2048), dim3(256), 0, st, C.b.lpost, Sl[l], up.lpost,
-                               Sl[l - 1], int64_t(g->n), nullptr, nullptr, up.iters, up.fail, C.map, C.count);
-    }
-    if (ev) {
-        // a count still in flight would land in the shared pinned word later
-        if (check > 0) (void)hipEventSynchronize(ev);
-        (void)hipEventDestroy(ev);
+    // posteriors, iteration counts and fail marks back to the full state
+    if (ls.on && T > kFirstCheck) {
+        for (int l = kLevels - 1; l > 0; l--)
+            hipLaunchKernelGGL((level_scatter_kernel<PT>), dim3(2048), dim3(256), 0, st, ls.ctl, ls.a, l,
+                               int64_t(g->n), int32_t(keep32));
     }
     const int32_t nrows = g->class_begin[ldpc::kNumClasses];
     if (nrows > 0) {
@@ -1234,24 +1501,6 @@ Bufs bufs_at(char *ws, const Plan &p) {
     return b;
 }
 
-// Tail compaction waits on the host for its periodic counts, which a stream
-// under graph capture cannot do: such a call is refused before anything is
-// enqueued.
-bool capture_blocks_compaction(hipStream_t st, uint32_t flags, const std::string &f) {
-    if (!(flags & LDPC_COMPACT_TAIL)) return false;
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
-        (void)hipGetLastError();
-        set_error(f + ": cannot query the stream's capture state");
-        return true;
-    }
-    if (cs != hipStreamCaptureStatusNone) {
-        set_error(f + ": LDPC_COMPACT_TAIL waits on the host and cannot run on a capturing stream");
-        return true;
-    }
-    return false;
-}
-
 ldpc_status decode_core(const char *fn, const ldpc_graph *g, const float *llr_in, int32_t frames, int32_t max_iter,
                         uint32_t flags, const ldpc_rule *rule_in, uint8_t *bits_out, uint8_t *syndrome_ok,
                         int32_t *iters, float *llr_out, void *workspace, size_t workspace_bytes, void *hip_stream,
@@ -1288,7 +1537,6 @@ ldpc_status decode_core(const char *fn, const ldpc_graph *g, const float *llr_in
     }
     const Bufs b = bufs_at(static_cast<char *>(workspace), p);
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    if (capture_blocks_compaction(st, flags, f)) return LDPC_E_INVAL;
     const bool es = !(flags & LDPC_NO_EARLY_STOP);
     (void)hipGetLastError();
     switch (p.msg) {
@@ -1443,7 +1691,6 @@ ldpc_status simulate_core(const char *fn, const ldpc_graph *g, int32_t frames, d
     sim.ok = reinterpret_cast<uint8_t *>(ws + p.off_ok);
     sim.counts = counts;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    if (capture_blocks_compaction(st, flags, f)) return LDPC_E_INVAL;
     const bool es = !(flags & LDPC_NO_EARLY_STOP);
     (void)hipGetLastError();
     switch (p.msg) {
@@ -1537,11 +1784,6 @@ extern "C" ldpc_status ldpc_decode_noalloc(const ldpc_graph *g, const float *llr
     if (g->host_only) { set_error(f + ": graph was built host-only"); return LDPC_E_INVAL; }
     if (frames < 0) { set_error(f + ": frames < 0"); return LDPC_E_INVAL; }
     if (!flags_ok(flags)) { set_error(f + ": bad flags"); return LDPC_E_INVAL; }
-    // compaction keeps a pinned host word and events of its own
-    if (flags & LDPC_COMPACT_TAIL) {
-        set_error(f + ": LDPC_COMPACT_TAIL allocates and is not available here");
-        return LDPC_E_INVAL;
-    }
     if (frames == 0 || max_iter < 1)   // no-op or an argument error, reported by the decode itself
         return decode_core(f.c_str(), g, llr_in, frames, max_iter, flags, nullptr, bits_out, syndrome_ok, iters,
                            llr_out, nullptr, 0, hip_stream, Marks{});

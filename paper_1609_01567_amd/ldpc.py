@@ -26,7 +26,7 @@ MSG_Q8 = 1 << 6          # 8-bit fixed-point messages: steps of 1/2, saturating 
 LANE_SLOTS_1 = 1 << 3
 LANE_SLOTS_2 = 1 << 4
 LANE_SLOTS_4 = 1 << 5
-COMPACT_TAIL = 1 << 7    # decode only: move the last running frames into smaller slot ranges (blocks the caller)
+COMPACT_TAIL = 1 << 7    # decode/simulate: move the last running frames into smaller slot ranges (device-driven)
 # graph flags
 GRAPH_HOST_ONLY = 1 << 0
 

@@ -17,8 +17,12 @@ from paper_1609_01567_amd import build
 
 # Kernels allowed to spill, with the most scratch bytes per lane they may use:
 # the sum-product rows of 129..512 edges hold 32 edges per lane (u's and
-# suffixes) in a 1024-thread workgroup, whose register budget is 128.
-ALLOWED_SPILL = {r"check_wide_kernel": 32}
+# suffixes) in a 1024-thread workgroup, whose register budget is 128; the
+# compacted-tail form of the fp32 sum-product register rows (all three lane
+# widths in one kernel) keeps one message address in scratch between its load
+# and its store (8 bytes, once per wavefront; the headline decode that runs it
+# measured no slower than with the plain kernels).
+ALLOWED_SPILL = {r"check_wide_(level_)?kernel": 32, r"check_rows_level_kernelILi0ELi4ELi8ELi0E": 12}
 
 
 @pytest.fixture(scope="module")
@@ -34,6 +38,7 @@ def resources():
 def test_record_covers_the_kernels(resources):
     names = " ".join(resources)
     for k in ("check_rows_kernel", "check_chunk_kernel", "check_wide_kernel", "check_hub_kernel", "bit_kernel",
+              "check_rows_level_kernel", "bit_level_kernel", "level_decide_kernel", "level_move_kernel",
               "eng_check_rows", "eng_check_chunk", "eng_bit", "ingest_kernel", "egress_kernel"):
         assert k in names, k
     for name, r in resources.items():
@@ -53,7 +58,7 @@ def test_hot_check_kernels_keep_four_waves_per_simd(resources):
     # the register-row check kernels of the plain and engine paths: at most 128
     # registers, so that four wavefronts per SIMD hide the gathers' latency
     hot = {n: r for n, r in resources.items()
-           if re.search(r"check_rows_kernelILi\dELi4ELi8E|eng_check_rowsILi\dELi4ELi8E", n)}
+           if re.search(r"check_rows_(level_)?kernelILi\dELi4ELi8E|eng_check_rowsILi\dELi4ELi8E", n)}
     assert hot
     low = {n: (r["vgpr"], r["occupancy"]) for n, r in hot.items() if r["occupancy"] < 4}
     assert not low, low

@@ -1,6 +1,6 @@
 """GPU tests of tail compaction (LDPC_COMPACT_TAIL): once few frames of a call
-still run, they move into a smaller slot range and finish there one slot per
-lane.  Only the schedule changes, so every output must be bit-identical to the
+still run, they move into a smaller slot range (with fewer slots per lane)
+and finish there.  Only the schedule changes, so every output must be bit-identical to the
 same decode without the flag (which is itself held to the oracle)."""
 import numpy as np
 import pytest
@@ -51,7 +51,7 @@ def test_compact_tail_equals_plain(msg, lane):
 
 
 def test_compact_tail_one_slot_per_lane_ragged_pool():
-    """One slot per lane and 300 frames: 320 slots, copies of 160 and 80."""
+    """One slot per lane and 300 frames: 320 slots, copies of 128 and 64."""
     from paper_1609_01567_amd import ldpc
     code = li.random_small_code(600, 300, 3, seed=8)
     llr = li.awgn_llr(code.n, 300, li.ebn0_to_sigma2(1.8, code.rate), seed=36)
@@ -75,7 +75,7 @@ def test_compact_tail_every_check_class():
 
 
 def test_compact_tail_all_stop_early():
-    """Every frame stops early: the call skips the iterations with no work."""
+    """Every frame stops early: the later iterations find no running frame."""
     from paper_1609_01567_amd import ldpc
     code = li.random_small_code(600, 300, 3, seed=8)
     llr = li.awgn_llr(code.n, 512, li.ebn0_to_sigma2(4.0, code.rate), seed=35)

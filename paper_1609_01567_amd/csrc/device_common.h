@@ -147,13 +147,23 @@ __device__ __forceinline__ void store_post1(T *p, float x) {
     else *gmem(p) = post16_enc(x);
 }
 
-// Element s0 of row `row` (a wave-uniform row start) as a uniform base plus a
-// 32-bit per-lane byte offset, the form global loads and stores take with the
-// base in scalar registers (no per-lane 64-bit address arithmetic).
-template <typename T>
+// Element s0 of row `row` as a base plus a 32-bit per-lane byte offset.  With
+// UNIFORM (every lane of the wavefront on the same row) the base is read from
+// lane 0 into scalar registers, so the access takes the scalar-base form:
+// without it the compiler folds the lane offset into one 64-bit address per
+// row and lane, two registers per edge that stay live from a message's load
+// to its store.
+template <bool UNIFORM, typename T>
 __device__ __forceinline__ T *lane_elem(T *row, int s0) {
     using B = std::conditional_t<std::is_const_v<T>, const char, char>;
-    return reinterpret_cast<T *>(reinterpret_cast<B *>(row) + uint32_t(s0) * uint32_t(sizeof(T)));
+    B *base = reinterpret_cast<B *>(row);
+    if constexpr (UNIFORM) {
+        const uint64_t a = reinterpret_cast<uint64_t>(row);
+        const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(a));
+        const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(a >> 32));
+        base = reinterpret_cast<B *>((uint64_t(hi) << 32) | lo);
+    }
+    return reinterpret_cast<T *>(base + uint32_t(s0) * uint32_t(sizeof(T)));
 }
 
 template <int V>
@@ -313,6 +323,12 @@ __device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_rea
 //              so the common case pays one branch per lane (SlotSrc::any).
 enum Inputs { kInFirst = 0, kInSteady = 1, kInMixed = 2 };
 
+// Whether a row's message and posterior accesses take scalar bases
+// (lane_elem).  The engine's 8-bit rows (first-iteration slots mixed in) need
+// more registers with them than without, so they keep per-lane addresses.
+template <int M, bool UNIFORM, int IN>
+constexpr bool scalar_base() { return UNIFORM && !(M == kQ8 && IN == kInMixed); }
+
 template <int V>
 struct SlotSrc {
     bool alt[V];
@@ -374,6 +390,7 @@ __device__ __forceinline__ void gather_edges(CI col_idx, int j0, int count,
                                              const typename Codec<M>::T *__restrict__ R, int32_t S, int s0,
                                              const SlotSrc<V> &src, float (&u)[C][V], uint32_t (&par)[V],
                                              int (&syn)[V]) {
+    constexpr bool SB = scalar_base<M, UNIFORM, IN>();
     int vix[C];
 #pragma unroll
     for (int j = 0; j < C; j++) {
@@ -388,10 +405,10 @@ __device__ __forceinline__ void gather_edges(CI col_idx, int j0, int count,
         for (int j = 0; j < C; j++) {
             const int e = j0 + (j < count ? j : count - 1);
             using RawW = typename Raw<4 * W>::T;
-            const RawW a = *gmem(reinterpret_cast<const RawW *>(lane_elem(L + size_t(vix[j]) * S, s0)));
+            const RawW a = *gmem(reinterpret_cast<const RawW *>(lane_elem<SB>(L + size_t(vix[j]) * S, s0)));
             __builtin_memcpy(lw[j], &a, sizeof(RawW));
             if (IN != kInFirst) {
-                const RawW b = *gmem(reinterpret_cast<const RawW *>(lane_elem(R + size_t(e) * S, s0)));
+                const RawW b = *gmem(reinterpret_cast<const RawW *>(lane_elem<SB>(R + size_t(e) * S, s0)));
                 __builtin_memcpy(rw[j], &b, sizeof(RawW));
             } else {
 #pragma unroll
@@ -438,9 +455,9 @@ __device__ __forceinline__ void gather_edges(CI col_idx, int j0, int count,
 #pragma unroll
     for (int j = 0; j < C; j++) {
         const int e = j0 + (j < count ? j : count - 1);
-        load_vec<CodecOf<LT>::kMsg, V>(lane_elem(L + size_t(vix[j]) * S, s0), lv[j]);
+        load_vec<CodecOf<LT>::kMsg, V>(lane_elem<SB>(L + size_t(vix[j]) * S, s0), lv[j]);
         if (IN != kInFirst) {
-            load_vec<M, V>(lane_elem(R + size_t(e) * S, s0), r[j]);
+            load_vec<M, V>(lane_elem<SB>(R + size_t(e) * S, s0), r[j]);
         } else {
 #pragma unroll
             for (int k = 0; k < V; k++) r[j][k] = 0.f;
@@ -511,7 +528,7 @@ __device__ __forceinline__ void row_rule_n(CI col_idx, int e0, int d,
                 out[k] = signed_mag<M>(mag, par[k] ^ __float_as_uint(u[j][k]));   // sign of the other inputs
                 run[k] = Rule::combine(run[k], fabsf(u[j][k]));
             }
-            store_vec<M, V>(lane_elem(R + size_t(e0 + j) * S, s0), out);
+            store_vec<M, V>(lane_elem<scalar_base<M, UNIFORM, IN>()>(R + size_t(e0 + j) * S, s0), out);
         }
     }
 }

@@ -115,3 +115,26 @@ def test_compact_tail_profiled_entry_point():
     assert (res.iters.cpu().numpy() == ref["iters"]).all()
     assert (res.bits.cpu().numpy() == ref["bits"]).all()
     assert len(tm["check_ms"]) == 40 and (np.asarray(tm["check_ms"]) >= 0).all()
+
+
+@pytest.mark.parametrize("msg,high", [("fp32", 300), ("fp32", 420), ("fp16", 420)])
+def test_compact_tail_segmented_and_wide_rows(msg, high):
+    """Rows beyond 512 edges (segmented path) and of 129..512 (16-wavefront
+    path) in compacted decodes: 512 frames, `high` of them at 8 dB (they stop
+    within 3 iterations) and the rest at 4 dB (most run all 30), so that the
+    count after iteration 8 moves the running frames into the half-size copy
+    (300) or straight into the quarter-size one (420)."""
+    from paper_1609_01567_amd import ldpc
+    from test_gpu_engine import _long_rows_code
+    flags = {"fp32": 0, "fp16": ldpc.MSG_FP16}[msg]
+    code = _long_rows_code()
+    assert code.check_degrees().max() == 1200
+    s8, s4 = li.ebn0_to_sigma2(8.0, code.rate), li.ebn0_to_sigma2(4.0, code.rate)
+    llr = np.concatenate([li.awgn_llr(code.n, high, s8, seed=81), li.awgn_llr(code.n, 512 - high, s4, seed=82)])
+    print(f"[case] compact long rows msg={msg} high={high} frames=512", flush=True)
+    a = gpu_decode(code, llr, 30, flags=flags)
+    b = gpu_decode(code, llr, 30, flags=flags | ldpc.COMPACT_TAIL)
+    its = a["iters"]
+    # frames still running after iteration 8 fit the intended copy, and some run on
+    assert (its > 8).sum() <= (128 if high == 420 else 256) and (its > 12).sum() > 0
+    _same(a, b, f"long rows {msg} {high}")

@@ -268,14 +268,14 @@ __device__ __forceinline__ int work_graph(const Work &w, int32_t ngraphs, int x)
 // on row rk (a scalar), so the row descriptor and the column indices come in
 // through scalar loads issued before the slot state is examined; otherwise
 // each lane has its own row (packed items).
+// ln: the slot state of the lane's slots (eng_lane), the same for every row of
+// one slot group in one pass.
 template <int M, int V, int DMAX, bool UNIFORM, int RULE>
-__device__ __forceinline__ void rows_item(const EngGraph &G, int cls, int nrows, int rk, int s0, int32_t T,
-                                          int32_t early, int32_t par, float rp) {
+__device__ __forceinline__ void rows_item(const EngGraph &G, int cls, int nrows, int rk, int s0,
+                                          const EngLane<V> &ln, float rp) {
     using MT = typename Codec<M>::T;
     if (!UNIFORM && rk >= nrows) return;
     const u32x2 rdv = cload(reinterpret_cast<const u32x2 *>(G.class_rd) + G.class_begin[cls] + rk);
-    EngLane<V> ln;
-    eng_lane<V>(G, s0, T, early, par, ln);
     if (!ln.active) return;
     const int e0 = UNIFORM ? wave_uniform(int(rdv.x)) : int(rdv.x);
     const int d = UNIFORM ? wave_uniform(int(rdv.y)) : int(rdv.y);
@@ -297,6 +297,8 @@ __global__ __launch_bounds__(256, 4) void eng_check_rows(const EngGraph *__restr
     const int lane = threadIdx.x & 63;
     const int total = wave_uniform(w.p[ngraphs]);
     const int stride = int(gridDim.x * (blockDim.x >> 6));
+    int prev_c = -1, prev_g = -1;
+    EngLane<V> ln;
     for (int item = wave_uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6); item < total; item += stride) {
         const int c = wave_uniform(work_graph(w, ngraphs, item));
         const EngGraph &G = graphs[c];
@@ -306,12 +308,25 @@ __global__ __launch_bounds__(256, 4) void eng_check_rows(const EngGraph *__restr
         if (PM == kPackNone || PM == kPackOnlyFlat || (PM == kPackAll && rpw == 1)) {
             const int groups = wave_uniform(w.groups[c]);
             const int rk = local / groups;
-            rows_item<M, V, DMAX, true, RULE>(G, cls, nrows, rk, ((local - rk * groups) * 64 + lane) * V, T, early, par,
-                                              rp);
+            const int g = local - rk * groups;
+            const int s0 = (g * 64 + lane) * V;
+            // consecutive items of a wavefront often share their graph and slot
+            // group: keep its slot state
+            if (c != prev_c || g != prev_g) {
+                eng_lane<V>(G, s0, T, early, par, ln);
+                prev_c = c;
+                prev_g = g;
+            }
+            rows_item<M, V, DMAX, true, RULE>(G, cls, nrows, rk, s0, ln, rp);
         } else {
             const int lpr = 64 / rpw;
-            rows_item<M, V, DMAX, false, RULE>(G, cls, nrows, local * rpw + lane / lpr, (lane % lpr) * V, T, early,
-                                               par, rp);
+            const int rk = local * rpw + lane / lpr;
+            if (rk < nrows) {
+                const int s0 = (lane % lpr) * V;
+                EngLane<V> pl;
+                eng_lane<V>(G, s0, T, early, par, pl);
+                rows_item<M, V, DMAX, false, RULE>(G, cls, nrows, rk, s0, pl, rp);
+            }
         }
     }
 }
@@ -558,50 +573,66 @@ __global__ __launch_bounds__(1024) void eng_check_wide(const EngGraph *__restric
 // Posterior of bit v for the lane's V slots (iteration t_s + 1 of every slot
 // whose frame continues).  UNIFORM: one bit per wavefront.  The items of bit 0
 // cover every slot below the extent once, and write the slots' next state.
-template <int M, int V, bool UNIFORM>
-__device__ __forceinline__ void bit_item(const EngGraph &G, int v, int s0, int32_t T, int32_t early,
-                                         int32_t par, float bscale) {
-    using MT = typename Codec<M>::T;
-    const int32_t S = G.S;
-    int32_t t[V], f[V];
-    load_i32<V>(G.slot_t + par * S + s0, t);
-    load_i32<V>(G.fail + s0, f);
+// Slot state of a lane's V slots for the bit pass: the slot's iteration
+// counter and whether the slot advances (its frame is still running after this
+// pass's stop test).  The same for every bit of one slot group in one pass.
+template <int V>
+struct BitSlots {
+    int32_t t[V];
     bool adv[V];
-    bool any = false, all = true;
+    bool any, all;
+};
+
+template <int V>
+__device__ __forceinline__ void bit_slots(const EngGraph &G, int s0, int32_t T, int32_t early, int32_t par,
+                                          BitSlots<V> &b) {
+    int32_t f[V];
+    load_i32<V>(G.slot_t + par * G.S + s0, b.t);
+    load_i32<V>(G.fail + s0, f);
+    b.any = false;
+    b.all = true;
 #pragma unroll
     for (int k = 0; k < V; k++) {
-        adv[k] = t[k] >= 0 && t[k] < kStopped && !slot_stops(t[k], f[k], T, early);
-        any |= adv[k];
-        all &= adv[k];
+        b.adv[k] = b.t[k] >= 0 && b.t[k] < kStopped && !slot_stops(b.t[k], f[k], T, early);
+        b.any |= b.adv[k];
+        b.all &= b.adv[k];
     }
+}
+
+// One (bit, slot group) item of the bit pass, given the group's slot state.
+template <int M, int V, bool UNIFORM>
+__device__ __forceinline__ void bit_item(const EngGraph &G, int v, int s0, const BitSlots<V> &b, int32_t par,
+                                         float bscale) {
+    using MT = typename Codec<M>::T;
+    const int32_t S = G.S;
     if (v == 0) {
         int32_t nx[V];
 #pragma unroll
         for (int k = 0; k < V; k++)
-            nx[k] = adv[k] ? t[k] + 1 : (t[k] >= 0 && t[k] < kStopped) ? t[k] + kStopped : t[k];
+            nx[k] = b.adv[k] ? b.t[k] + 1 : (b.t[k] >= 0 && b.t[k] < kStopped) ? b.t[k] + kStopped : b.t[k];
         store_i32<V>(G.slot_t + (par ^ 1) * S + s0, nx);
     }
-    if (!any) return;
+    if (!b.any) return;
     const MT *R = static_cast<const MT *>(G.r);
     float sum[V];
     const int a = UNIFORM ? wave_uniform(cload(G.col_ptr + (v))) : cload(G.col_ptr + (v));
-    const int b = UNIFORM ? wave_uniform(cload(G.col_ptr + (v + 1))) : cload(G.col_ptr + (v + 1));
-    bit_posterior<M, V, UNIFORM>(G.csc_to_csr, a, b, R, S, s0, G.lch + size_t(v) * S, bscale, sum);
+    const int e = UNIFORM ? wave_uniform(cload(G.col_ptr + (v + 1))) : cload(G.col_ptr + (v + 1));
+    bit_posterior<M, V, UNIFORM>(G.csc_to_csr, a, e, R, S, s0, G.lch + size_t(v) * S, bscale, sum);
     using PT = typename Post<M>::T;
     PT *post = static_cast<PT *>(G.post);
-    if (all) {
+    if (b.all) {
         store_post<V>(post + size_t(v) * S + s0, sum);
     } else {
 #pragma unroll
         for (int k = 0; k < V; k++)
-            if (adv[k]) store_post1(post + size_t(v) * S + s0 + k, sum[k]);
+            if (b.adv[k]) store_post1(post + size_t(v) * S + s0 + k, sum[k]);
     }
     if constexpr (kPost16<M>) {
         int32_t w[V];
         load_i32<V>(G.want32 + s0, w);
 #pragma unroll
         for (int k = 0; k < V; k++)
-            if (adv[k] && w[k]) gmem(G.lpost)[size_t(v) * S + s0 + k] = sum[k];
+            if (b.adv[k] && w[k]) gmem(G.lpost)[size_t(v) * S + s0 + k] = sum[k];
     }
 }
 
@@ -623,6 +654,8 @@ __global__ __launch_bounds__(256) void eng_bit(const EngGraph *__restrict__ grap
     const int lane = threadIdx.x & 63;
     const int total = wave_uniform(w.p[ngraphs]);
     const int stride = int(gridDim.x * (blockDim.x >> 6));
+    int prev_c = -1, prev_g = -1;
+    BitSlots<V> bs;
     for (int item = wave_uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6); item < total; item += stride) {
         const int c = wave_uniform(work_graph(w, ngraphs, item));
         const EngGraph &G = graphs[c];
@@ -631,11 +664,25 @@ __global__ __launch_bounds__(256) void eng_bit(const EngGraph *__restrict__ grap
         if (rpw == 1) {
             const int groups = wave_uniform(w.groups[c]);
             const int v = local / groups;
-            bit_item<M, V, true>(G, v, ((local - v * groups) * 64 + lane) * V, T, early, par, bscale);
+            const int g = local - v * groups;
+            const int s0 = (g * 64 + lane) * V;
+            // consecutive items of a wavefront often share their graph and slot
+            // group (one group per pool of up to 64 V slots): keep its state
+            if (c != prev_c || g != prev_g) {
+                bit_slots<V>(G, s0, T, early, par, bs);
+                prev_c = c;
+                prev_g = g;
+            }
+            bit_item<M, V, true>(G, v, s0, bs, par, bscale);
         } else {
             const int lpr = 64 / rpw;
             const int v = local * rpw + lane / lpr;
-            if (v < G.n) bit_item<M, V, false>(G, v, (lane % lpr) * V, T, early, par, bscale);
+            if (v < G.n) {
+                const int s0 = (lane % lpr) * V;
+                BitSlots<V> pb;
+                bit_slots<V>(G, s0, T, early, par, pb);
+                bit_item<M, V, false>(G, v, s0, pb, par, bscale);
+            }
         }
     }
 }

@@ -574,21 +574,24 @@ __global__ __launch_bounds__(1024) void eng_check_wide(const EngGraph *__restric
 // whose frame continues).  UNIFORM: one bit per wavefront.  The items of bit 0
 // cover every slot below the extent once, and write the slots' next state.
 // Slot state of a lane's V slots for the bit pass: the slot's iteration
-// counter and whether the slot advances (its frame is still running after this
-// pass's stop test).  The same for every bit of one slot group in one pass.
+// counter, whether the slot advances (its frame is still running after this
+// pass's stop test) and, with 16-bit messages, whether its frame wants the fp32
+// posterior.  The same for every bit of one slot group in one pass.
 template <int V>
 struct BitSlots {
     int32_t t[V];
+    int32_t want[V];
     bool adv[V];
     bool any, all;
 };
 
-template <int V>
+template <int M, int V>
 __device__ __forceinline__ void bit_slots(const EngGraph &G, int s0, int32_t T, int32_t early, int32_t par,
                                           BitSlots<V> &b) {
     int32_t f[V];
     load_i32<V>(G.slot_t + par * G.S + s0, b.t);
     load_i32<V>(G.fail + s0, f);
+    if constexpr (kPost16<M>) load_i32<V>(G.want32 + s0, b.want);
     b.any = false;
     b.all = true;
 #pragma unroll
@@ -628,11 +631,9 @@ __device__ __forceinline__ void bit_item(const EngGraph &G, int v, int s0, const
             if (b.adv[k]) store_post1(post + size_t(v) * S + s0 + k, sum[k]);
     }
     if constexpr (kPost16<M>) {
-        int32_t w[V];
-        load_i32<V>(G.want32 + s0, w);
 #pragma unroll
         for (int k = 0; k < V; k++)
-            if (b.adv[k] && w[k]) gmem(G.lpost)[size_t(v) * S + s0 + k] = sum[k];
+            if (b.adv[k] && b.want[k]) gmem(G.lpost)[size_t(v) * S + s0 + k] = sum[k];
     }
 }
 
@@ -669,7 +670,7 @@ __global__ __launch_bounds__(256) void eng_bit(const EngGraph *__restrict__ grap
             // consecutive items of a wavefront often share their graph and slot
             // group (one group per pool of up to 64 V slots): keep its state
             if (c != prev_c || g != prev_g) {
-                bit_slots<V>(G, s0, T, early, par, bs);
+                bit_slots<M, V>(G, s0, T, early, par, bs);
                 prev_c = c;
                 prev_g = g;
             }
@@ -680,7 +681,7 @@ __global__ __launch_bounds__(256) void eng_bit(const EngGraph *__restrict__ grap
             if (v < G.n) {
                 const int s0 = (lane % lpr) * V;
                 BitSlots<V> pb;
-                bit_slots<V>(G, s0, T, early, par, pb);
+                bit_slots<M, V>(G, s0, T, early, par, pb);
                 bit_item<M, V, false>(G, v, s0, pb, par, bscale);
             }
         }

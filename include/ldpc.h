@@ -67,10 +67,10 @@ enum {
      * entry points; ignored with LDPC_NO_EARLY_STOP and below 256 frame
      * slots).  After iteration 8 and every 4 iterations after it, a kernel
      * counts the frames still running; once they fit in a smaller copy of the
-     * state (at most half, then at most a quarter of the slots, with half and
-     * a quarter of the frame slots per lane), it moves them there and the
-     * remaining iterations run on that copy; the posteriors are copied back
-     * at the end.  Every decision is taken on the device: the call still only
+     * state (half or a quarter of the slots, at half or a quarter of the
+     * frame slots per lane, at least one), it moves them into the smallest
+     * copy that holds them and the remaining iterations run there; the
+     * posteriors are copied back at the end.  Every decision is taken on the device: the call still only
      * enqueues work, never waits, and can be captured into a graph.  Results
      * are identical.  The workspace grows by three quarters of the per-slot
      * state. */

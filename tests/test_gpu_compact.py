@@ -138,3 +138,22 @@ def test_compact_tail_segmented_and_wide_rows(msg, high):
     # frames still running after iteration 8 fit the intended copy, and some run on
     assert (its > 8).sum() <= (128 if high == 420 else 256) and (its > 12).sum() > 0
     _same(a, b, f"long rows {msg} {high}")
+
+
+@pytest.mark.parametrize("T", [1, 8, 9, 12])
+def test_compact_tail_short_runs(T):
+    """Runs that end before, at and just after the first count (after iteration
+    8): no count at all, and a move with a single iteration left before the
+    results are copied back.  Half of the 512 frames stop within 3 iterations,
+    so that count moves the others; posteriors are compared too."""
+    from paper_1609_01567_amd import ldpc
+    from test_gpu_engine import _long_rows_code
+    code = _long_rows_code()
+    s8, s4 = li.ebn0_to_sigma2(8.0, code.rate), li.ebn0_to_sigma2(4.0, code.rate)
+    llr = np.concatenate([li.awgn_llr(code.n, 300, s8, seed=83), li.awgn_llr(code.n, 212, s4, seed=84)])
+    print(f"[case] compact short runs T={T} frames=512", flush=True)
+    a = gpu_decode(code, llr, T)
+    b = gpu_decode(code, llr, T, flags=ldpc.COMPACT_TAIL)
+    if T >= 9:
+        assert (a["iters"] > 8).sum() <= 256 and (a["iters"] == T).sum() > 0
+    _same(a, b, f"T={T}")

@@ -256,8 +256,10 @@ __device__ __forceinline__ void build_work(const EngGraph *__restrict__ graphs, 
 // through wave_uniform so that the compiler keeps the item's indices in scalar
 // registers (LDS reads are otherwise treated as per-lane, which turns every
 // index load of the item into a vector load).
-__device__ __forceinline__ int work_graph(const Work &w, int32_t ngraphs, int x) {
-    int c = 0;
+// The search starts at graph c0, at or before x's graph: a pass's loop visits
+// its items in increasing order, so it passes the previous item's graph.
+__device__ __forceinline__ int work_graph(const Work &w, int32_t ngraphs, int x, int c0) {
+    int c = c0;
     while (c + 1 < ngraphs && x >= w.p[c + 1]) c++;
     return c;
 }
@@ -299,8 +301,10 @@ __global__ __launch_bounds__(256, 4) void eng_check_rows(const EngGraph *__restr
     const int stride = int(gridDim.x * (blockDim.x >> 6));
     int prev_c = -1, prev_g = -1;
     EngLane<V> ln;
+    int last_c = 0;
     for (int item = wave_uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6); item < total; item += stride) {
-        const int c = wave_uniform(work_graph(w, ngraphs, item));
+        const int c = wave_uniform(work_graph(w, ngraphs, item, last_c));
+        last_c = c;
         const EngGraph &G = graphs[c];
         const int local = item - wave_uniform(w.p[c]);
         const int rpw = wave_uniform(w.rpw[c]);
@@ -350,8 +354,10 @@ __global__ __launch_bounds__(256) void eng_check_chunk(const EngGraph *__restric
     const int lr = wave / WPR;
     const int wr = wave % WPR;
     const int total = wave_uniform(w.p[ngraphs]);
+    int last_c = 0;
     for (int u = blockIdx.x; u < total; u += gridDim.x) {     // uniform over the workgroup
-        const int c = wave_uniform(work_graph(w, ngraphs, u));
+        const int c = wave_uniform(work_graph(w, ngraphs, u, last_c));
+        last_c = c;
         const EngGraph &G = graphs[c];
         const int groups = wave_uniform(w.groups[c]);
         const int nrows = G.class_begin[cls + 1] - G.class_begin[cls];
@@ -425,8 +431,10 @@ __global__ __launch_bounds__(256) void eng_check_hub(const EngGraph *__restrict_
     const int wv = wave_uniform(threadIdx.x >> 6);
     const int nw = blockDim.x >> 6;
     const int total = wave_uniform(w.p[ngraphs]);
+    int last_c = 0;
     for (int u = blockIdx.x; u < total; u += gridDim.x) {     // uniform over the workgroup
-        const int c = wave_uniform(work_graph(w, ngraphs, u));
+        const int c = wave_uniform(work_graph(w, ngraphs, u, last_c));
+        last_c = c;
         const EngGraph &G = graphs[c];
         const int32_t S = G.S;
         const int groups = wave_uniform(w.groups[c]);
@@ -541,8 +549,10 @@ __global__ __launch_bounds__(1024) void eng_check_wide(const EngGraph *__restric
     const int lane = threadIdx.x & 63;
     const int wv = wave_uniform(threadIdx.x >> 6);
     const int total = wave_uniform(w.p[ngraphs]);
+    int last_c = 0;
     for (int u = blockIdx.x; u < total; u += gridDim.x) {     // uniform over the workgroup
-        const int c = wave_uniform(work_graph(w, ngraphs, u));
+        const int c = wave_uniform(work_graph(w, ngraphs, u, last_c));
+        last_c = c;
         const EngGraph &G = graphs[c];
         const int32_t S = G.S;
         const int groups = wave_uniform(w.groups[c]);
@@ -657,8 +667,10 @@ __global__ __launch_bounds__(256) void eng_bit(const EngGraph *__restrict__ grap
     const int stride = int(gridDim.x * (blockDim.x >> 6));
     int prev_c = -1, prev_g = -1;
     BitSlots<V> bs;
+    int last_c = 0;
     for (int item = wave_uniform((blockIdx.x * blockDim.x + threadIdx.x) >> 6); item < total; item += stride) {
-        const int c = wave_uniform(work_graph(w, ngraphs, item));
+        const int c = wave_uniform(work_graph(w, ngraphs, item, last_c));
+        last_c = c;
         const EngGraph &G = graphs[c];
         const int local = item - wave_uniform(w.p[c]);
         const int rpw = wave_uniform(w.rpw[c]);
@@ -776,9 +788,11 @@ __global__ __launch_bounds__(256) void eng_turnover(const EngGraph *__restrict__
     __syncthreads();
     const int total = base[ngraphs];
     const int r = tid >> 6, l = tid & 63;
+    int last_c = 0;
     for (int u = blockIdx.x; u < total; u += gridDim.x) {     // uniform over the workgroup
-        int c = 0;
+        int c = last_c;   // items in increasing order: start from the previous item's graph
         while (c + 1 < ngraphs && u >= base[c + 1]) c++;
+        last_c = c;
         const EngGraph &G = graphs[c];
         const int32_t S = G.S, n = G.n;
         const int nvt = (n + kTile - 1) / kTile;
